@@ -1,0 +1,358 @@
+/*
+ * fdtd_oracle.c -- plain FP64 CPU oracle of the differentiable FDTD step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links or calls
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.  It shares no source with the HIP path.
+ *
+ * It is written for a reader holding the paper (TorchFDTD, arXiv 2609.30039):
+ *   - Yee leapfrog, Eq. (1) of Section 2.1: E += S eps^-1 C^-(H) + s,
+ *     then H -= S C^+(E).  Unit mesh, c = 1, so dt = S.
+ *   - Convolutional PML (Section 2.2): one memory variable per transverse
+ *     derivative inside each absorbing face; forward form psi <- b psi + c D,
+ *     Dt = D / kappa + psi (the form whose transpose Section 3.1 prints).
+ *   - PEC faces (Section 2.2): tangential E held at zero on the low boundary
+ *     node; the high boundary node is not stored (ghost zero).
+ *   - One-pole Lorentz medium by the trapezoidal auxiliary differential
+ *     equation (Section 2.3): Ampere at n+1/2 with the trapezoidal average of
+ *     the polarisation current, the pole ODE by central differences at n.
+ *   - Discrete adjoint, Eq. (3) of Section 3.1, with the transposes of
+ *     Section 3.1 (opposite-direction differences, the absorber transpose,
+ *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl).
+ *
+ * Arrays are [nz][ny][nx], x fastest, one full-grid array per quantity.
+ * Every loop is a plain loop over the grid; OpenMP splits the outer z loop
+ * only where the iterations write disjoint nodes.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int n[3];                    /* cells along x, y, z (absorbing cells included) */
+    double S;                    /* Courant number c dt / h */
+    /* absorber tables along each axis a, indexed by the node index along a.
+       E-update derivatives are sampled at integer positions, H-update
+       derivatives at half-integer positions. slab[a][i] = 1 inside a face. */
+    const double *bE[3], *cE[3], *kiE[3];
+    const double *bH[3], *cH[3], *kiH[3];
+    const unsigned char *slab[3];
+    const double *eps[3];        /* permittivity at each E node, per component */
+    const unsigned char *lor;    /* 1 where the cell is a Lorentz cell, or NULL */
+    double lor_deps, lor_w0dt, lor_gdt;   /* delta eps, omega0 dt, gamma dt */
+} orc_params;
+
+typedef struct {
+    double *F[6];                /* Ex Ey Ez Hx Hy Hz */
+    double *psiE[3][3];          /* [E component][derivative axis], diagonal unused */
+    double *psiH[3][3];          /* [H component][derivative axis] */
+    double *Eold[3], *W[3], *Wold[3];   /* Lorentz history: E^{n-1}, W^n, W^{n-1} */
+} orc_state;
+
+#define IDX(P, i, j, k) (((size_t)(k) * (size_t)(P)->n[1] + (size_t)(j)) * (size_t)(P)->n[0] + (size_t)(i))
+
+static size_t stride_of(const orc_params *P, int a) {
+    return a == 0 ? 1 : (a == 1 ? (size_t)P->n[0] : (size_t)P->n[0] * (size_t)P->n[1]);
+}
+
+/* PEC: E component c is tangential to the low faces normal to the other two
+   axes; those boundary nodes are held at zero and are not degrees of freedom. */
+static int e_masked(int c, const int x[3]) {
+    return x[(c + 1) % 3] == 0 || x[(c + 2) % 3] == 0;
+}
+
+static int is_lorentz(const orc_params *P, size_t p) { return P->lor && P->lor[p]; }
+
+/* Pole recursion constants of the trapezoidal ADE with W = dt J:
+   W^{n+1} = al W^n + xi W^{n-1} + (g/2)(E^{n+1} - E^{n-1}). */
+static void lorentz_consts(const orc_params *P, double *al, double *xi, double *g) {
+    double q = 1.0 + 0.5 * P->lor_gdt;
+    *al = (2.0 - P->lor_w0dt * P->lor_w0dt) / q;
+    *xi = (0.5 * P->lor_gdt - 1.0) / q;
+    *g = P->lor_deps * P->lor_w0dt * P->lor_w0dt / q;
+}
+
+/* Stretched backward-difference curl of H at E node p (component c):
+   (C^- H)_c = d-_{c+1} H_{c+2} - d-_{c+2} H_{c+1}.
+   With write_psi the updated absorber memories are stored (forward step);
+   without, they are only used to form the value (gradient recomputation). */
+static double curl_minus(const orc_params *P, const orc_state *U, int c, const int x[3], size_t p,
+                         int write_psi) {
+    double acc = 0.0;
+    for (int t = 0; t < 2; ++t) {
+        int a = (c + 1 + t) % 3;
+        int h = t == 0 ? (c + 2) % 3 : (c + 1) % 3;
+        double sgn = t == 0 ? 1.0 : -1.0;
+        const double *H = U->F[3 + h];
+        double D = H[p] - (x[a] > 0 ? H[p - stride_of(P, a)] : 0.0);
+        double Dt = D;
+        if (P->slab[a][x[a]]) {
+            double *psi = U->psiE[c][a];
+            double pn = P->bE[a][x[a]] * psi[p] + P->cE[a][x[a]] * D;
+            if (write_psi) psi[p] = pn;
+            Dt = P->kiE[a][x[a]] * D + pn;
+        }
+        acc += sgn * Dt;
+    }
+    return acc;
+}
+
+/* Stretched forward-difference curl of E at H node p (component c):
+   (C^+ E)_c = d+_{c+1} E_{c+2} - d+_{c+2} E_{c+1}; updates the H memories. */
+static double curl_plus(const orc_params *P, orc_state *U, int c, const int x[3], size_t p) {
+    double acc = 0.0;
+    for (int t = 0; t < 2; ++t) {
+        int a = (c + 1 + t) % 3;
+        int e = t == 0 ? (c + 2) % 3 : (c + 1) % 3;
+        double sgn = t == 0 ? 1.0 : -1.0;
+        const double *E = U->F[e];
+        double D = (x[a] < P->n[a] - 1 ? E[p + stride_of(P, a)] : 0.0) - E[p];
+        double Dt = D;
+        if (P->slab[a][x[a]]) {
+            double *psi = U->psiH[c][a];
+            psi[p] = P->bH[a][x[a]] * psi[p] + P->cH[a][x[a]] * D;
+            Dt = P->kiH[a][x[a]] * D + psi[p];
+        }
+        acc += sgn * Dt;
+    }
+    return acc;
+}
+
+/* E^{n+1} before the source, from u^n, at one unmasked node. */
+static double e_pre(const orc_params *P, const orc_state *U, int c, size_t p, double curl) {
+    double ep = P->eps[c][p];
+    if (is_lorentz(P, p)) {
+        double al, xi, g;
+        lorentz_consts(P, &al, &xi, &g);
+        double den = ep + 0.25 * g;
+        return (ep * U->F[c][p] + 0.25 * g * U->Eold[c][p] + P->S * curl
+                - 0.5 * ((1.0 + al) * U->W[c][p] + xi * U->Wold[c][p])) / den;
+    }
+    return U->F[c][p] + P->S * curl / ep;
+}
+
+/*
+ * One forward step u^n -> u^{n+1}, in the order
+ *   1. E (or Lorentz-ADE) update with the absorber memories, PEC nodes kept,
+ *   2. soft electric sources s^{n+1} (PEC nodes skipped),
+ *   3. Lorentz history roll with the post-source E^{n+1},
+ *   4. H update with its absorber memories.
+ * src_*: the increments of this step.  work: three full-grid scratch arrays.
+ */
+void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, const long long *src_idx,
+              const double *src_amp, double *work) {
+    const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    const size_t N = (size_t)nx * ny * nz;
+    for (int c = 0; c < 3; ++c) {
+        double *En = work + (size_t)c * N;      /* E^n of Lorentz nodes, for the roll */
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int x[3] = {i, j, k};
+                    if (e_masked(c, x)) continue;
+                    size_t p = IDX(P, i, j, k);
+                    double curl = curl_minus(P, U, c, x, p, 1);
+                    double en1 = e_pre(P, U, c, p, curl);
+                    En[p] = U->F[c][p];
+                    U->F[c][p] = en1;
+                }
+    }
+    for (int s = 0; s < nsrc; ++s) {
+        size_t p = (size_t)src_idx[s];
+        int c = src_comp[s];
+        int x[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / ((size_t)nx * ny))};
+        if (e_masked(c, x)) continue;
+        U->F[c][p] += src_amp[s];
+    }
+    if (P->lor) {
+        double al, xi, g;
+        lorentz_consts(P, &al, &xi, &g);
+        for (int c = 0; c < 3; ++c) {
+            const double *En = work + (size_t)c * N;
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        if (!P->lor[p] || e_masked(c, x)) continue;
+                        double wn1 = al * U->W[c][p] + xi * U->Wold[c][p]
+                                     + 0.5 * g * (U->F[c][p] - U->Eold[c][p]);
+                        U->Wold[c][p] = U->W[c][p];
+                        U->W[c][p] = wn1;
+                        U->Eold[c][p] = En[p];
+                    }
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int x[3] = {i, j, k};
+                    size_t p = IDX(P, i, j, k);
+                    U->F[3 + c][p] -= P->S * curl_plus(P, U, c, x, p);
+                }
+    }
+}
+
+/* Absorber transpose (Section 3.1): given the cotangent ybar of the stretched
+   derivative and the cotangent of the stored memory, return the cotangent of
+   the raw difference and leave the cotangent of the previous memory. */
+static double cpml_T(double ybar, double *psibar, double b, double c, double ki) {
+    double mem = *psibar + ybar;
+    double Dbar = ki * ybar + c * mem;
+    *psibar = b * mem;
+    return Dbar;
+}
+
+/*
+ * One adjoint step ubar^{n+1} -> (dF_n/du)^T ubar^{n+1}, in place in A, and
+ * accumulation of the permittivity gradient dJ/deps_c into g[c] (when g is
+ * non-null) from the forward state U = u^n.  The seeds dJ/du^n are added by
+ * the caller.  The order is the reverse of orc_step: H transpose, Lorentz
+ * history transpose, E transpose.  work: four full-grid scratch arrays.
+ */
+void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, double **g, double *work) {
+    const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    const size_t N = (size_t)nx * ny * nz;
+    double *Dbar = work;
+    double *Epb[3] = {work + N, work + 2 * N, work + 3 * N};   /* cotangent of E^{n+1} before the source */
+
+    /* ---- H transpose: H_c -= S * sgn * Dt(d+_a E_e) ---- */
+    for (int c = 0; c < 3; ++c)
+        for (int t = 0; t < 2; ++t) {
+            int a = (c + 1 + t) % 3;
+            int e = t == 0 ? (c + 2) % 3 : (c + 1) % 3;
+            double sgn = t == 0 ? 1.0 : -1.0;
+            size_t sa = stride_of(P, a);
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        double ybar = -P->S * sgn * A->F[3 + c][p];
+                        if (P->slab[a][x[a]])
+                            Dbar[p] = cpml_T(ybar, &A->psiH[c][a][p], P->bH[a][x[a]], P->cH[a][x[a]],
+                                             P->kiH[a][x[a]]);
+                        else
+                            Dbar[p] = ybar;
+                    }
+            /* D[i] = E[i+1] - E[i] (E beyond the grid is zero)  =>  Ebar[i] += Dbar[i-1] - Dbar[i] */
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        A->F[e][p] += (x[a] > 0 ? Dbar[p - sa] : 0.0) - Dbar[p];
+                    }
+        }
+
+    /* ---- Lorentz history and E-update transposes, pointwise ---- */
+    double al = 0, xi = 0, gg = 0;
+    if (P->lor) lorentz_consts(P, &al, &xi, &gg);
+    for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int x[3] = {i, j, k};
+                    size_t p = IDX(P, i, j, k);
+                    if (e_masked(c, x)) {
+                        A->F[c][p] = 0.0;
+                        Epb[c][p] = 0.0;
+                        continue;
+                    }
+                    if (is_lorentz(P, p)) {
+                        double ep = P->eps[c][p];
+                        double den = ep + 0.25 * gg;
+                        /* roll: W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1}),
+                           Wold <- W^n, Eold <- E^n */
+                        double Wb = A->W[c][p], Wob = A->Wold[c][p], Eob = A->Eold[c][p];
+                        double Et = A->F[c][p] + 0.5 * gg * Wb;      /* cotangent of E^{n+1} */
+                        double Wn = al * Wb + Wob;                    /* cotangent of W^n */
+                        double Wnm1 = xi * Wb;                        /* cotangent of W^{n-1} */
+                        double Enm1 = -0.5 * gg * Wb;                 /* cotangent of E^{n-1} */
+                        double En = Eob;                              /* cotangent of E^n */
+                        /* E^{n+1}_pre = [eps E^n + g/4 E^{n-1} + S curl - ((1+al) W^n + xi W^{n-1})/2] / den */
+                        double Ep = Et;
+                        En += ep / den * Ep;
+                        Enm1 += 0.25 * gg / den * Ep;
+                        Wn += -0.5 * (1.0 + al) / den * Ep;
+                        Wnm1 += -0.5 * xi / den * Ep;
+                        Epb[c][p] = Ep;
+                        A->F[c][p] = En;
+                        A->Eold[c][p] = Enm1;
+                        A->W[c][p] = Wn;
+                        A->Wold[c][p] = Wnm1;
+                    } else {
+                        Epb[c][p] = A->F[c][p];   /* E^{n+1} = E^n + ... : identity on E^n */
+                    }
+                }
+    }
+
+    /* ---- gradient: dJ/deps_c accumulates dE_pre/deps_c * Ebar_pre ---- */
+    if (g) {
+        for (int c = 0; c < 3; ++c) {
+            if (!g[c]) continue;
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        if (e_masked(c, x)) continue;
+                        size_t p = IDX(P, i, j, k);
+                        double curl = curl_minus(P, U, c, x, p, 0);
+                        double ep = P->eps[c][p];
+                        if (is_lorentz(P, p)) {
+                            double den = ep + 0.25 * gg;
+                            double epre = e_pre(P, U, c, p, curl);
+                            g[c][p] += Epb[c][p] * (U->F[c][p] - epre) / den;
+                        } else {
+                            g[c][p] += -Epb[c][p] * P->S * curl / (ep * ep);
+                        }
+                    }
+        }
+    }
+
+    /* ---- E transpose: E_c += S * coef * sgn * Dt(d-_a H_h) ---- */
+    for (int c = 0; c < 3; ++c)
+        for (int t = 0; t < 2; ++t) {
+            int a = (c + 1 + t) % 3;
+            int h = t == 0 ? (c + 2) % 3 : (c + 1) % 3;
+            double sgn = t == 0 ? 1.0 : -1.0;
+            size_t sa = stride_of(P, a);
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        if (e_masked(c, x)) {
+                            Dbar[p] = 0.0;
+                            continue;
+                        }
+                        double ep = P->eps[c][p];
+                        double coef = is_lorentz(P, p) ? 1.0 / (ep + 0.25 * gg) : 1.0 / ep;
+                        double ybar = P->S * coef * sgn * Epb[c][p];
+                        if (P->slab[a][x[a]])
+                            Dbar[p] = cpml_T(ybar, &A->psiE[c][a][p], P->bE[a][x[a]], P->cE[a][x[a]],
+                                             P->kiE[a][x[a]]);
+                        else
+                            Dbar[p] = ybar;
+                    }
+            /* D[i] = H[i] - H[i-1] (H below the grid is zero)  =>  Hbar[i] += Dbar[i] - Dbar[i+1] */
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        A->F[3 + h][p] += Dbar[p] - (x[a] < P->n[a] - 1 ? Dbar[p + sa] : 0.0);
+                    }
+        }
+}

@@ -1,0 +1,279 @@
+"""Seeded synthetic workloads for the FDTD hot path.
+
+This module only *describes* problems: grid sizes, absorbing-layer depths and
+grading constants, permittivity arrays drawn from seeded generators, dispersive
+boxes, source waveforms, monitor placements and frequencies.  It performs none
+of the method's arithmetic (no curls, no absorber coefficients, no dispersion
+coefficients, no transforms), so that the CPU oracle and the HIP library can
+both consume the same inputs without sharing any numerical code.
+
+Index conventions (used by both consumers):
+  * every field-like array is ``[nz][ny][nx]`` (x fastest);
+  * ``lo``/``hi`` boxes are half-open ``[lo, hi)`` triples ``(i, j, k)``;
+  * component codes: 0,1,2 = Ex,Ey,Ez ; 3,4,5 = Hx,Hy,Hz.
+
+The workloads follow the shapes of the paper's scenes (Section 6-7: dielectric
+scatterers in absorbing boxes, dispersive slabs, plane monitors); no dataset
+is read.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+Box = Tuple[Tuple[int, int, int], Tuple[int, int, int]]
+
+EX, EY, EZ, HX, HY, HZ = range(6)
+COMP_NAMES = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+
+@dataclass
+class LorentzSpec:
+    """One-pole Lorentz medium on a box; eps_inf is the cell's permittivity."""
+    lo: Tuple[int, int, int]
+    hi: Tuple[int, int, int]
+    delta_eps: float
+    omega0_dt: float
+    gamma_dt: float
+
+
+@dataclass
+class SourceSpec:
+    """Soft electric source.  ``kind`` is 'point' or 'plane_z' (whole z-plane).
+
+    ``waveform[t]`` is the increment added at forward step t (the step that
+    produces E at time (t+1)*dt); steps past the end add nothing.
+    """
+    kind: str
+    comp: int
+    pos: Tuple[int, int, int]
+    waveform: np.ndarray
+
+
+@dataclass
+class MonitorSpec:
+    """Observation.
+
+    kind 'probe'   : comp at pos, one sample per forward step.
+    kind 'flux_z'  : z-plane pos[2], rectangle rect=(i0,i1,j0,j1); records
+                     Ex, Ey and Hx, Hy averaged over planes k and k-1.
+    kind 'patch_z' : one component comp on z-plane pos[2], rectangle rect.
+    """
+    kind: str
+    comp: int = 0
+    pos: Tuple[int, int, int] = (0, 0, 0)
+    rect: Tuple[int, int, int, int] = (0, 0, 0, 0)
+    omega_dt: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+
+@dataclass
+class DomainSpec:
+    shape: Tuple[int, int, int]                 # (nx, ny, nz), absorbing cells included
+    courant: float                              # S = c dt / h
+    pml: Tuple[int, int, int, int, int, int] = (0, 0, 0, 0, 0, 0)   # xlo,xhi,ylo,yhi,zlo,zhi
+    pml_m: float = 3.0
+    pml_kappa_max: float = 5.0
+    pml_sigma_max: float = 3.2
+    pml_alpha_max: float = 0.05
+    eps_kind: str = "iso"                       # 'iso' or 'diag'
+    eps_box: Optional[Box] = None               # where ``eps`` is given; eps_bg outside
+    eps: Optional[np.ndarray] = None            # [ncomp][bz][by][bx]
+    eps_bg: float = 1.0
+    lorentz: List[LorentzSpec] = field(default_factory=list)
+    sources: List[SourceSpec] = field(default_factory=list)
+    monitors: List[MonitorSpec] = field(default_factory=list)
+    grad_box: Optional[Box] = None
+    n_steps: int = 0
+
+    @property
+    def ncells(self) -> int:
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+    def eps_full(self) -> np.ndarray:
+        """Dense per-component permittivity [3][nz][ny][nx] (float64)."""
+        nx, ny, nz = self.shape
+        out = np.full((3, nz, ny, nx), float(self.eps_bg))
+        if self.eps is not None:
+            (i0, j0, k0), (i1, j1, k1) = self.eps_box
+            e = self.eps
+            for c in range(3):
+                out[c, k0:k1, j0:j1, i0:i1] = e[0] if e.shape[0] == 1 else e[c]
+        return out
+
+
+# --------------------------------------------------------------------------
+# waveforms and frequency grids (inputs, not method arithmetic)
+# --------------------------------------------------------------------------
+
+def gaussian_sine(n_steps: int, omega_c_dt: float, tau: float, n0: float) -> np.ndarray:
+    """s(n) = sin(w_c dt (n-n0)) exp(-((n-n0)/tau)^2 / 2), sampled at n=1..n_steps.
+
+    Entry t of the result is s(t+1), the increment of forward step t."""
+    n = np.arange(1, n_steps + 1, dtype=np.float64)
+    x = n - n0
+    return np.sin(omega_c_dt * x) * np.exp(-0.5 * (x / tau) ** 2)
+
+
+def freq_grid(n_f: int, lo: float = 0.10, hi: float = 0.20) -> np.ndarray:
+    return np.linspace(lo, hi, n_f)
+
+
+def courant_3d(eta: float = 0.99) -> float:
+    """Uniform-mesh Courant number S = eta / sqrt(3)."""
+    return eta / math.sqrt(3.0)
+
+
+def _centered_box(n: Sequence[int], size: Sequence[int]) -> Box:
+    lo = tuple((n[a] - size[a]) // 2 for a in range(3))
+    hi = tuple(lo[a] + size[a] for a in range(3))
+    return lo, hi
+
+
+# --------------------------------------------------------------------------
+# the five workloads and their reduced parity-size relatives
+# --------------------------------------------------------------------------
+
+def pec_cavity(n: int = 32, n_steps: int = 200, seed: int = 1001, src=None, probe=None) -> DomainSpec:
+    """3D Yee FP64 PEC box with per-cell eps in [1,4], Ez point dipole, Ez probe."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps = 1.0 + 3.0 * rng.random((n, n, n))
+    c = n // 2
+    src = src or (c, c, c)
+    probe = probe or (min(n - 2, c + n // 4), c, c)
+    return DomainSpec(
+        shape=(n, n, n), courant=courant_3d(), eps_kind="iso",
+        eps_box=((0, 0, 0), (n, n, n)), eps=eps[None], eps_bg=1.0,
+        sources=[SourceSpec("point", EZ, src, gaussian_sine(n_steps, 0.2 * math.pi, 20.0, 80.0))],
+        monitors=[MonitorSpec("probe", comp=EZ, pos=probe)],
+        n_steps=n_steps,
+    )
+
+
+def lorentz_flux(interior: int = 128, pml: int = 10, lorentz: int = 48, n_steps: int = 1000,
+                 n_f: int = 16, shape: Optional[Tuple[int, int, int]] = None) -> DomainSpec:
+    """FP32 forward: interior^3 + CPML, central Lorentz block, z-sheet source, far flux plane."""
+    if shape is None:
+        shape = (interior + 2 * pml,) * 3
+    nx, ny, nz = shape
+    lo, hi = _centered_box(shape, (lorentz,) * 3)
+    eps = np.full((1, lorentz, lorentz, lorentz), 2.0)
+    ks = pml + 5
+    kf = nz - pml - 6
+    return DomainSpec(
+        shape=shape, courant=courant_3d(), pml=(pml,) * 6, eps_kind="iso",
+        eps_box=(lo, hi), eps=eps, eps_bg=1.0,
+        lorentz=[LorentzSpec(lo, hi, 1.5, 0.15, 0.01)],
+        sources=[SourceSpec("plane_z", EX, (0, 0, ks), gaussian_sine(n_steps, 0.15, 30.0, 120.0))],
+        monitors=[MonitorSpec("flux_z", pos=(0, 0, kf), rect=(0, nx, 0, ny), omega_dt=freq_grid(n_f))],
+        n_steps=n_steps,
+    )
+
+
+def design_patch(interior: int = 192, pml: int = 10, design: int = 64, patch: int = 32,
+                 n_steps: int = 2000, n_f: int = 8, seed: int = 1003, n_fd: int = 20,
+                 shape: Optional[Tuple[int, int, int]] = None):
+    """FP32 adjoint: random eps_r in [1,6] on a centred design box; |DFT Ez|^2 on a patch.
+
+    Returns (spec, fd_cells) where fd_cells are (i,j,k) inside the design box
+    drawn from the same generator after eps."""
+    if shape is None:
+        shape = (interior + 2 * pml,) * 3
+    nx, ny, nz = shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = _centered_box(shape, (design,) * 3)
+    eps = 1.0 + 5.0 * rng.random((design, design, design))
+    cells = rng.integers(0, design, size=(n_fd, 3))
+    fd_cells = [tuple(int(lo[a] + cells[m, a]) for a in range(3)) for m in range(n_fd)]
+    kp = nz - pml - 10
+    p0 = ((nx - patch) // 2, (ny - patch) // 2)
+    spec = DomainSpec(
+        shape=shape, courant=courant_3d(), pml=(pml,) * 6, eps_kind="iso",
+        eps_box=(lo, hi), eps=eps[None], eps_bg=1.0,
+        sources=[SourceSpec("plane_z", EX, (0, 0, pml + 5), gaussian_sine(n_steps, 0.15, 30.0, 120.0))],
+        monitors=[MonitorSpec("patch_z", comp=EZ, pos=(0, 0, kp),
+                              rect=(p0[0], p0[0] + patch, p0[1], p0[1] + patch), omega_dt=freq_grid(n_f))],
+        grad_box=(lo, hi), n_steps=n_steps,
+    )
+    return spec, fd_cells
+
+
+def batch_domains(n_domains: int = 48, sizes: Sequence[int] = (48, 64, 96, 128, 160), pml: int = 10,
+                  n_steps: int = 800, n_f: int = 4, seed: int = 1004) -> List[DomainSpec]:
+    """Ragged ensemble: per-axis interior sizes drawn from ``sizes`` (Cartesian product)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    picks = rng.integers(0, len(sizes), size=(n_domains, 3))
+    out = []
+    for d in range(n_domains):
+        inner = tuple(int(sizes[picks[d, a]]) for a in range(3))
+        shape = tuple(inner[a] + 2 * pml for a in range(3))
+        nx, ny, nz = shape
+        eps = 1.0 + 3.0 * rng.random((inner[2], inner[1], inner[0]))
+        lo = (pml, pml, pml)
+        hi = (nx - pml, ny - pml, nz - pml)
+        c = (nx // 2, ny // 2, nz // 2)
+        kf = nz - pml - 3
+        out.append(DomainSpec(
+            shape=shape, courant=courant_3d(), pml=(pml,) * 6, eps_kind="iso",
+            eps_box=(lo, hi), eps=eps[None], eps_bg=1.0,
+            sources=[SourceSpec("point", EZ, c, gaussian_sine(n_steps, 0.15, 30.0, 120.0))],
+            monitors=[MonitorSpec("flux_z", pos=(0, 0, kf), rect=(0, nx, 0, ny), omega_dt=freq_grid(n_f))],
+            grad_box=(lo, hi) if d % 2 == 0 else None, n_steps=n_steps,
+        ))
+    return out
+
+
+def anisotropic_lorentz(interior: int = 512, pml: int = 12, lorentz: int = 128, patch: int = 64,
+                        n_steps: int = 4000, n_f: int = 8, seed: int = 1005,
+                        shape: Optional[Tuple[int, int, int]] = None) -> DomainSpec:
+    """FP32 adjoint: diagonal eps (each in [1,5]) on the interior, central Lorentz box."""
+    if shape is None:
+        shape = (interior + 2 * pml,) * 3
+    nx, ny, nz = shape
+    inner = (nx - 2 * pml, ny - 2 * pml, nz - 2 * pml)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps = np.empty((3, inner[2], inner[1], inner[0]))
+    for c in range(3):
+        eps[c] = 1.0 + 4.0 * rng.random((inner[2], inner[1], inner[0]))
+    lo = (pml, pml, pml)
+    hi = (nx - pml, ny - pml, nz - pml)
+    llo, lhi = _centered_box(shape, (lorentz,) * 3)
+    kp = nz - pml - 5
+    p0 = ((nx - patch) // 2, (ny - patch) // 2)
+    return DomainSpec(
+        shape=shape, courant=courant_3d(), pml=(pml,) * 6, eps_kind="diag",
+        eps_box=(lo, hi), eps=eps, eps_bg=1.0,
+        lorentz=[LorentzSpec(llo, lhi, 1.5, 0.15, 0.01)],
+        sources=[SourceSpec("plane_z", EX, (0, 0, pml + 5), gaussian_sine(n_steps, 0.15, 30.0, 120.0))],
+        monitors=[MonitorSpec("patch_z", comp=EX, pos=(0, 0, kp),
+                              rect=(p0[0], p0[0] + patch, p0[1], p0[1] + patch), omega_dt=freq_grid(n_f))],
+        grad_box=(lo, hi), n_steps=n_steps,
+    )
+
+
+def random_state_like(spec: DomainSpec, seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# Named configurations (full size), for bench and sampled full-size parity.
+def c1():
+    return pec_cavity(32, 200)
+
+
+def c2():
+    return lorentz_flux()
+
+
+def c3():
+    return design_patch()
+
+
+def c4():
+    return batch_domains()
+
+
+def c5():
+    return anisotropic_lorentz()
