@@ -1,0 +1,208 @@
+/*
+ * fdtd.h -- C-ABI of libfdtd, the MI355X (gfx950) hot path of a
+ * differentiable FDTD solver (TorchFDTD, arXiv 2609.30039).
+ *
+ * The library advances one or more independent 3-D Yee domains
+ *   E^{n+1} = E^n + S eps^-1 C^-(H^{n+1/2}) + s^{n+1},
+ *   H^{n+3/2} = H^{n+1/2} - S C^+(E^{n+1})            (Section 2.1, Eq. 1)
+ * with convolutional PML memories in absorbing faces and PEC outer walls
+ * (Section 2.2), per-node real or diagonal permittivity and a one-pole
+ * Lorentz box integrated by the trapezoidal ADE (Section 2.3), soft electric
+ * sources and point / plane-spectrum monitors (Section 2.4), and runs the
+ * discrete adjoint of that step (Section 3.1, Eq. 3) with accumulation of
+ * dJ/deps.  Checkpoint slots serve the binomial replay of Section 3.2.
+ *
+ * Conventions shared by every call:
+ *   - unit mesh (h = 1), c = 1: dt = S, frequencies are given as omega*dt;
+ *   - field arrays are [nz][ny][nx], x fastest; boxes are half-open [lo, hi)
+ *     in cell indices (i, j, k);
+ *   - Ex[k][j][i] sits at (i+1/2, j, k), Ey at (i, j+1/2, k), Ez at
+ *     (i, j, k+1/2), Hx at (i, j+1/2, k+1/2), Hy at (i+1/2, j, k+1/2),
+ *     Hz at (i+1/2, j+1/2, k); E at index N_a is a zero ghost, H at -1 too;
+ *     E tangential to a low face (index 0 along another axis) is held at 0;
+ *   - forward step t (t = 0, 1, ...) maps u^t -> u^{t+1}; E^{t+1} is sampled
+ *     at time (t+1) dt and H^{t+3/2} at (t+3/2) dt; plane spectra are
+ *     X(w) = sum_n x^n exp(-i w t_n) with that half-step offset kept.
+ *
+ * Ownership: the handle owns all device memory (hipMalloc); every host array
+ * passed in is copied during the call and never retained.  All device work is
+ * enqueued on the stream given at create; only calls returning host data
+ * synchronise (that stream only).  A handle is not thread-safe; distinct
+ * handles are independent.
+ *
+ * Errors: every call returns an int status, never aborts or throws.
+ *   FDTD_E_INVALID, FDTD_E_STATE, FDTD_E_RANGE leave the handle usable;
+ *   FDTD_E_DEVICE (a HIP error) poisons it: every later call except
+ *   fdtd_destroy and fdtd_last_error returns FDTD_E_DEVICE.
+ */
+#ifndef FDTD_H_
+#define FDTD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FDTD_OK = 0,
+    FDTD_E_INVALID = -1,   /* bad argument or descriptor */
+    FDTD_E_UNSTABLE = -2,  /* CFL eta > 0.99 (Eq. 2), non-finite or non-positive eps,
+                              anisotropic eps inside an absorbing face violating the
+                              principal-axis rule of Section 2.3 */
+    FDTD_E_NOMEM = -3,     /* device memory request above budget, refused before allocating */
+    FDTD_E_DEVICE = -4,    /* HIP runtime error; handle poisoned */
+    FDTD_E_STATE = -5,     /* wrong step index for an adjoint step, empty or corrupt slot */
+    FDTD_E_RANGE = -6      /* index out of range (domain, component, slot, monitor, buffer size) */
+};
+
+enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_BF16 = 2 };
+enum { FDTD_EPS_ISO = 0, FDTD_EPS_DIAG = 1 };
+enum { FDTD_SRC_POINT = 0, FDTD_SRC_PLANE_Z = 1 };
+enum { FDTD_MON_PROBE = 0, FDTD_MON_FLUX_Z = 1, FDTD_MON_PATCH_Z = 2 };
+/* field components for get/set: 0..5 = Ex..Hz of the forward state,
+   6..11 = the adjoint (cotangent) Ex..Hz */
+enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ, FDTD_ADJ = 6 };
+/* step_forward flags */
+enum { FDTD_RECORD = 1u, FDTD_REPLAY = 2u };
+/* monitor ops */
+enum { FDTD_MON_GET = 0, FDTD_MON_FLUX = 1, FDTD_MON_SET_COTANGENT = 2, FDTD_MON_RESET = 3 };
+/* kernel selection (for tests of tile invariance; FDTD_KERNEL_AUTO in production) */
+enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
+
+#define FDTD_MAX_SOURCES 4
+#define FDTD_MAX_MONITORS 8
+
+typedef struct {
+    int32_t lo[3], hi[3];          /* cell box; eps_inf of each cell is its permittivity */
+    double delta_eps;              /* pole strength */
+    double omega0_dt;              /* resonance omega_0 * dt */
+    double gamma_dt;               /* damping gamma * dt (full rate) */
+} fdtd_lorentz_desc;
+
+typedef struct {
+    int32_t kind;                  /* FDTD_SRC_POINT | FDTD_SRC_PLANE_Z */
+    int32_t comp;                  /* 0..2: Ex, Ey, Ez */
+    int32_t pos[3];                /* point (i,j,k); plane uses pos[2] = k, whole plane */
+    const double *waveform;        /* host; waveform[t] is added at forward step t */
+    int32_t n_waveform;            /* steps beyond the end add nothing */
+} fdtd_source_desc;
+
+typedef struct {
+    int32_t kind;                  /* FDTD_MON_PROBE | FDTD_MON_FLUX_Z | FDTD_MON_PATCH_Z */
+    int32_t comp;                  /* probe / patch component 0..5 */
+    int32_t pos[3];                /* probe (i,j,k); planes use pos[2] = k */
+    int32_t rect[4];               /* plane rectangle i0, i1, j0, j1 */
+    const double *omega_dt;        /* host; n_freq frequencies omega*dt */
+    int32_t n_freq;
+} fdtd_monitor_desc;
+
+typedef struct {
+    int32_t n[3];                  /* nx, ny, nz cells, absorbing cells included */
+    double courant;                /* S = c dt / h; S*sqrt(3) must be <= 0.99 */
+    int32_t pml[6];                /* absorbing cells at xlo, xhi, ylo, yhi, zlo, zhi */
+    double pml_m, pml_kappa_max, pml_sigma_max, pml_alpha_max;   /* grading */
+    int32_t eps_kind;              /* FDTD_EPS_ISO | FDTD_EPS_DIAG */
+    int32_t eps_lo[3], eps_hi[3];  /* box where eps is given */
+    const double *eps;             /* host [ncomp][bz][by][bx], ncomp 1 (ISO) or 3 (DIAG) */
+    double eps_bg;                 /* permittivity outside the box */
+    int32_t n_lorentz;             /* 0 or 1 */
+    fdtd_lorentz_desc lorentz;
+    int32_t n_sources;             /* <= FDTD_MAX_SOURCES */
+    fdtd_source_desc sources[FDTD_MAX_SOURCES];
+    int32_t n_monitors;            /* <= FDTD_MAX_MONITORS */
+    fdtd_monitor_desc monitors[FDTD_MAX_MONITORS];
+    int32_t grad;                  /* 1: this domain takes part in the adjoint */
+    int32_t grad_lo[3], grad_hi[3];/* box where dJ/deps accumulates */
+} fdtd_domain_desc;
+
+typedef struct {
+    int32_t dtype;                 /* FDTD_F32 | FDTD_F64: field and coefficient arithmetic */
+    int32_t n_ckpt;                /* checkpoint slots */
+    int32_t ckpt_storage;          /* FDTD_F32 (= dtype width) | FDTD_BF16 (per-array scale) */
+    int32_t ckpt_checksum;         /* 1: store a checksum per slot, verify on restore */
+    int32_t max_steps;             /* length of probe traces and adjoint seed range */
+    int32_t kernel;                /* FDTD_KERNEL_* */
+    int32_t dft_block;             /* time samples buffered before a DFT flush (0: default) */
+    int32_t graph_chunk;           /* steps per captured hipGraph (0: no graph) */
+    void *stream;                  /* hipStream_t; NULL = default stream */
+    double mem_budget_bytes;       /* refuse with FDTD_E_NOMEM above this (0: device free memory) */
+} fdtd_options;
+
+typedef struct fdtd_s *fdtd_t;
+
+/* Create a handle advancing n_domains independent domains together
+   (n_domains > 1: one launch covers all of them through a tile table).
+   Validates the CFL bound (Eq. 2), eps positivity and the absorbing-face
+   tensor rule, estimates device memory and refuses above budget, then
+   allocates and uploads.  State starts at zero with forward step 0. */
+int fdtd_create(const fdtd_domain_desc *domains, int32_t n_domains, const fdtd_options *opt, fdtd_t *out);
+
+/* Release all device memory of the handle (after draining its stream). */
+int fdtd_destroy(fdtd_t h);
+
+/* Advance every domain n_steps forward steps (Eq. 1 with absorbers,
+   dispersion, sources).  FDTD_RECORD accumulates monitors; FDTD_REPLAY
+   leaves them untouched (checkpoint replay must not double count). */
+int fdtd_step_forward(fdtd_t h, int32_t n_steps, uint32_t flags);
+
+/* Start the reverse sweep at m = n_total: zero the cotangent state and the
+   gradient accumulators and inject dJ/du^{n_total} from the cotangents set
+   with FDTD_MON_SET_COTANGENT. */
+int fdtd_adjoint_begin(fdtd_t h, int32_t n_total);
+
+/* n_steps adjoint steps of Eq. 3.  Each step m -> m-1 requires the forward
+   state u^{m-1} (forward step index == m-1, else FDTD_E_STATE; so n_steps
+   is 1 unless the caller replays in between), applies the transposes of
+   Section 3.1 in reverse order, accumulates dJ/deps from u^{m-1} inside the
+   gradient box, and adds dJ/du^{m-1}. */
+int fdtd_step_adjoint(fdtd_t h, int32_t n_steps);
+
+/* Copy the full forward state u^n (fields, absorber memories, Lorentz
+   history) and n into slot (Section 3.2).  BF16 storage scales each array by
+   its max-abs value. */
+int fdtd_checkpoint_save(fdtd_t h, int32_t slot);
+
+/* Make the slot's state current: u := slot, forward step := slot's n.
+   FDTD_E_STATE for an empty slot or (with checksums) a mismatch. */
+int fdtd_checkpoint_restore(fdtd_t h, int32_t slot);
+
+/* Plane-spectrum monitor access for domain `domain`, monitor `monitor`:
+   GET            host_buf <- complex128 [n_freq][ncomp][j1-j0][i1-i0]
+                  (flux: ncomp 4 = Ex, Ey, Hx, Hy with H averaged over planes
+                  k and k-1; patch: ncomp 1); probes: double [n_recorded].
+   FLUX           host_buf <- double [n_freq], Re sum (Ex Hy* - Ey Hx*).
+   SET_COTANGENT  host_buf -> same layout as GET: dJ/dRe X + i dJ/dIm X
+                  (probes: dJ/dsample, double [max_steps]).
+   RESET          zero the spectra / trace (host_buf unused). */
+int fdtd_monitor_dft(fdtd_t h, int32_t domain, int32_t monitor, int32_t op, void *host_buf, size_t bytes);
+
+/* Copy one component (FDTD_EX..FDTD_HZ, + FDTD_ADJ for the cotangent) of one
+   domain to/from a host array of nx*ny*nz elements of the handle's dtype. */
+int fdtd_get_field(fdtd_t h, int32_t domain, int32_t comp, void *host_buf, size_t bytes);
+int fdtd_set_field(fdtd_t h, int32_t domain, int32_t comp, const void *host_buf, size_t bytes);
+
+/* dJ/deps over the gradient box: double [ncomp][gz][gy][gx]. */
+int fdtd_get_grad(fdtd_t h, int32_t domain, double *host_buf, size_t bytes);
+
+/* Replace the permittivity of a domain (same layout as the descriptor). */
+int fdtd_set_eps(fdtd_t h, int32_t domain, const double *eps, size_t bytes);
+
+/* Zero the forward state and monitors, forward step := 0. */
+int fdtd_reset(fdtd_t h);
+
+/* Current forward step n and adjoint index m (-1 before fdtd_adjoint_begin). */
+int fdtd_get_step(fdtd_t h, int32_t *fwd_n, int32_t *adj_m);
+
+/* Bytes of device memory held by the handle. */
+int fdtd_get_memory(fdtd_t h, double *bytes);
+
+/* Message of the last failing call on this handle (or of the last failing
+   create when h is NULL); valid until the next call. */
+const char *fdtd_last_error(fdtd_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_H_ */

@@ -1,0 +1,43 @@
+// fdtd_launch.h -- host-visible launch interface between the runtime and the
+// kernels of libfdtd (internal; not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fdtd {
+
+constexpr int kMaxDftBlock = 64;   // buffered time samples per DFT flush
+
+// One monitor as the kernels see it.
+struct MonDev {
+    int dom, kind, comp, ncomp, nf;   // kind 0 probe, 1 flux (Ex, Ey, <Hx>, <Hy>), 2 patch
+    int i0, i1, j0, j1, k;            // plane rectangle and plane index
+    int pi, pj;                       // probe (pi, pj, k)
+    const double* omega;              // [nf] omega * dt
+    void* samples;                    // ring buffer [block][ncomp][npts] of the field type
+    double* acc;                      // spectra [nf][ncomp][npts] (re, im)
+    double* cot;                      // cotangents, same layout (probe: [max_steps])
+    double* trace;                    // probe samples [max_steps]
+};
+
+template <typename T>
+void launch_fwd_split(const void* doms, const int* bs, int ndom, int nblocks, int kz, int p, int t, hipStream_t s);
+template <typename T>
+void launch_adj_split(const void* doms, const int* bs, int ndom, int nblocks, int kz, int p, int fp, hipStream_t s);
+template <typename T>
+void launch_sample(const void* doms, const MonDev& m, int p, int slot, hipStream_t s);
+template <typename T>
+void launch_dft(const MonDev& m, int n0, int count, hipStream_t s);
+template <typename T>
+void launch_probe(const void* doms, const MonDev& m, int p, int n, hipStream_t s);
+template <typename T>
+void launch_seed(const void* doms, const MonDev& m, int p, int n, hipStream_t s);
+
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_maxabs_f32(const float* x, long long n, unsigned int* out, hipStream_t s);
+void launch_pack_bf16(const float* x, long long n, const unsigned int* scale, uint16_t* y, hipStream_t s);
+void launch_unpack_bf16(const uint16_t* y, long long n, const unsigned int* scale, float* x, hipStream_t s);
+void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s);
+
+}  // namespace fdtd

@@ -1,0 +1,1062 @@
+// fdtd_runtime.cpp -- host runtime and C-ABI of libfdtd.
+//
+// Owns the device memory of a handle (one pooled hipMalloc planned and
+// admitted before allocation), the absorber and dispersion coefficient tables,
+// the monitor ring buffers, the checkpoint slots, and the step bookkeeping of
+// the forward sweep and of the reverse (adjoint) sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "fdtd.h"
+#include "fdtd_dev.h"
+#include "fdtd_launch.h"
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Err {
+    int code;
+    std::string msg;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- CPML tables
+// Roden-Gedney recursive convolution along one axis (Section 2.2).  Node i is
+// at x = i for E-update derivatives and x = i + 1/2 for H-update derivatives;
+// depth d in [0,1] from the interface (0) to the outer wall (1);
+// sigma = smax d^m, kappa = 1 + (kmax-1) d^m, alpha = amax (1-d);
+// b = exp(-(sigma/kappa + alpha) dt), c = sigma (b-1) / (sigma kappa + kappa^2 alpha).
+void cpml_tables(int n, int l0, int l1, double S, double m, double kmax, double smax, double amax,
+                 std::vector<double>& out /* 6*n: bE cE kiE bH cH kiH */) {
+    out.assign(6 * (size_t)n, 0.0);
+    for (int half = 0; half < 2; ++half) {
+        double* b = out.data() + (size_t)(3 * half + 0) * n;
+        double* c = out.data() + (size_t)(3 * half + 1) * n;
+        double* ki = out.data() + (size_t)(3 * half + 2) * n;
+        for (int i = 0; i < n; ++i) {
+            b[i] = 1.0;
+            c[i] = 0.0;
+            ki[i] = 1.0;
+            double x = i + (half ? 0.5 : 0.0);
+            double d;
+            if (l0 > 0 && i < l0) d = std::max(0.0, (l0 - x) / l0);
+            else if (l1 > 0 && i >= n - l1) d = std::max(0.0, (x - (n - l1)) / l1);
+            else continue;
+            double dm = std::pow(d, m);
+            double sig = smax * dm, kap = 1.0 + (kmax - 1.0) * dm, alp = amax * (1.0 - d);
+            b[i] = std::exp(-(sig / kap + alp) * S);
+            c[i] = sig > 0 ? sig * (b[i] - 1.0) / (sig * kap + kap * kap * alp) : 0.0;
+            ki[i] = 1.0 / kap;
+        }
+    }
+}
+
+struct MonHost {
+    MonDev dev{};
+    int npts = 0;
+    size_t acc_elems = 0;   // doubles in acc (and cot)
+    int pending = 0, n0 = 0;
+    bool cot_set = false;
+    std::vector<double> omega;
+};
+
+struct DomHost {
+    fdtd_domain_desc desc{};
+    std::vector<double> eps;                 // host copy
+    std::vector<std::vector<double>> waves;
+    std::vector<MonHost> mons;
+    int ncomp_eps = 1;
+    size_t nfield = 0;                       // elements per field array (pitch*ny*nz)
+    int gncomp = 0;
+    size_t gelems = 0;                       // per component
+};
+
+struct StateArr {
+    void* p[2];
+    size_t n;                                // elements
+};
+
+struct Slot {
+    bool valid = false;
+    int step = 0;
+    unsigned long long sum = 0;
+};
+
+struct Base {
+    virtual ~Base() = default;
+    std::string err;
+    bool poisoned = false;
+    virtual int step_forward(int n, unsigned flags) = 0;
+    virtual int adjoint_begin(int n) = 0;
+    virtual int step_adjoint(int n) = 0;
+    virtual int ckpt_save(int slot) = 0;
+    virtual int ckpt_restore(int slot) = 0;
+    virtual int monitor(int dom, int mon, int op, void* buf, size_t bytes) = 0;
+    virtual int get_field(int dom, int comp, void* buf, size_t bytes, bool set) = 0;
+    virtual int get_grad(int dom, double* buf, size_t bytes) = 0;
+    virtual int set_eps(int dom, const double* eps, size_t bytes) = 0;
+    virtual int reset() = 0;
+    virtual void steps(int* n, int* m) = 0;
+    virtual double memory() = 0;
+};
+
+template <typename T>
+struct Handle : Base {
+    hipStream_t st = nullptr;
+    fdtd_options opt{};
+    int ndom = 0;
+    std::vector<DomHost> dh;
+    std::vector<DomDev<T>> dd;
+    DomDev<T>* d_doms = nullptr;
+    int* d_bs = nullptr;
+    int nblk = 0, kz = 8;
+    char* pool = nullptr;
+    size_t pool_bytes = 0;
+    char* ckpool = nullptr;
+    size_t slot_bytes = 0;
+    std::vector<Slot> slots;
+    unsigned int* d_scales = nullptr;         // [n_ckpt][n_state] BF16 scales
+    unsigned long long* d_sum = nullptr;      // checksum scratch
+    std::vector<StateArr> fwd, adj;           // state arrays (per set)
+    std::vector<std::pair<void*, size_t>> adj_flat;   // every adjoint/gradient buffer, for zeroing
+    int fp = 0, ap = 0, t = 0, m = -1;
+    int dft_block = 32;
+    bool bf16 = false;
+
+    ~Handle() override {
+        if (!pool && !ckpool) return;   // nothing was allocated (e.g. refused at admission)
+        if (st) (void)hipStreamSynchronize(st);
+        else (void)hipDeviceSynchronize();
+        if (pool) (void)hipFree(pool);
+        if (ckpool) (void)hipFree(ckpool);
+    }
+
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        if (code == FDTD_E_DEVICE) poisoned = true;
+        return code;
+    }
+
+    int check(const char* what) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(FDTD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+        return FDTD_OK;
+    }
+
+    int sync(const char* what) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(FDTD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+        return check(what);
+    }
+
+    // ------------------------------------------------------------ create
+    int create(const fdtd_domain_desc* doms, int n, const fdtd_options* o) {
+        opt = *o;
+        st = (hipStream_t)o->stream;
+        ndom = n;
+        dft_block = o->dft_block > 0 ? std::min(o->dft_block, kMaxDftBlock) : 32;
+        bf16 = o->ckpt_storage == FDTD_BF16;
+        if (bf16 && sizeof(T) != 4) return fail(FDTD_E_INVALID, "BF16 checkpoints need FP32 fields");
+        if (o->n_ckpt < 0 || o->max_steps < 0) return fail(FDTD_E_INVALID, "negative n_ckpt or max_steps");
+        dh.resize(n);
+        dd.assign(n, DomDev<T>{});
+        for (int q = 0; q < n; ++q) {
+            int rc = validate(doms[q], dh[q]);
+            if (rc) return rc;
+        }
+        // ---- plan the pool (offsets stored as pointer values + 1, fixed up after allocation)
+        size_t off = 0;
+        auto take = [&](size_t bytes) -> size_t {
+            off = align256(off);
+            size_t at = off;
+            off += std::max<size_t>(bytes, 1);
+            return at + 1;
+        };
+        size_t ts = sizeof(T);
+        for (int q = 0; q < n; ++q) {
+            DomHost& h = dh[q];
+            DomDev<T>& d = dd[q];
+            const fdtd_domain_desc& s = h.desc;
+            int nx = s.n[0], ny = s.n[1], nz = s.n[2];
+            int align = 128 / (int)ts;
+            d.n[0] = nx;
+            d.n[1] = ny;
+            d.n[2] = nz;
+            d.pitch = (nx + align - 1) / align * align;
+            d.plane = (long long)d.pitch * ny;
+            h.nfield = (size_t)d.plane * nz;
+            d.S = (T)s.courant;
+            for (int st2 = 0; st2 < 2; ++st2)
+                for (int c = 0; c < 3; ++c) {
+                    d.E[st2][c] = (T*)take(h.nfield * ts);
+                    d.H[st2][c] = (T*)take(h.nfield * ts);
+                }
+            for (int a = 0; a < 3; ++a) {
+                d.L[a][0] = s.pml[2 * a];
+                d.L[a][1] = s.pml[2 * a + 1];
+                d.tab[a] = (const T*)take(6 * (size_t)s.n[a] * ts);
+            }
+            auto slab_elems = [&](int a, int side) -> size_t {
+                size_t L = (size_t)d.L[a][side];
+                if (a == 0) return L * ny * nz;
+                if (a == 1) return L * nx * nz;
+                return L * nx * ny;
+            };
+            bool g = s.grad != 0;
+            d.grad = g ? 1 : 0;
+            for (int st2 = 0; st2 < 2; ++st2)
+                for (int a = 0; a < 3; ++a)
+                    for (int side = 0; side < 2; ++side)
+                        for (int r = 0; r < 2; ++r) {
+                            size_t ne = slab_elems(a, side);
+                            d.psiE[st2][a][side][r] = ne ? (T*)take(ne * ts) : nullptr;
+                            d.psiH[st2][a][side][r] = ne ? (T*)take(ne * ts) : nullptr;
+                            d.psiEa[st2][a][side][r] = (ne && g) ? (T*)take(ne * ts) : nullptr;
+                            d.psiHa[st2][a][side][r] = (ne && g) ? (T*)take(ne * ts) : nullptr;
+                        }
+            d.eps_diag = s.eps_kind == FDTD_EPS_DIAG;
+            size_t ebox = 1;
+            for (int a = 0; a < 3; ++a) {
+                d.elo[a] = s.eps_lo[a];
+                d.ehi[a] = s.eps_hi[a];
+                ebox *= (size_t)(s.eps_hi[a] - s.eps_lo[a]);
+            }
+            d.epsinv_bg = (T)(1.0 / s.eps_bg);
+            if (ebox && s.eps) {
+                for (int c = 0; c < h.ncomp_eps; ++c) d.epsinv[c] = (const T*)take(ebox * ts);
+                for (int c = h.ncomp_eps; c < 3; ++c) d.epsinv[c] = d.epsinv[0];
+            } else {
+                for (int a = 0; a < 3; ++a) d.elo[a] = d.ehi[a] = 0;
+            }
+            d.has_lor = s.n_lorentz > 0;
+            if (d.has_lor) {
+                const fdtd_lorentz_desc& L = s.lorentz;
+                size_t lbox = 1;
+                for (int a = 0; a < 3; ++a) {
+                    d.llo[a] = L.lo[a];
+                    d.lhi[a] = L.hi[a];
+                    lbox *= (size_t)(L.hi[a] - L.lo[a]);
+                }
+                // trapezoidal ADE with W = dt J: W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1})
+                double qq = 1.0 + 0.5 * L.gamma_dt;
+                d.lal = (T)((2.0 - L.omega0_dt * L.omega0_dt) / qq);
+                d.lxi = (T)((0.5 * L.gamma_dt - 1.0) / qq);
+                d.lg = (T)(L.delta_eps * L.omega0_dt * L.omega0_dt / qq);
+                for (int st2 = 0; st2 < 2; ++st2)
+                    for (int w = 0; w < 3; ++w)
+                        for (int c = 0; c < 3; ++c) {
+                            d.lor[st2][w][c] = (T*)take(lbox * ts);
+                            d.lora[st2][w][c] = g ? (T*)take(lbox * ts) : nullptr;
+                        }
+            }
+            d.nsrc = s.n_sources;
+            for (int k = 0; k < s.n_sources; ++k) {
+                const fdtd_source_desc& sr = s.sources[k];
+                SrcDev<T>& sd = d.src[k];
+                sd.kind = sr.kind;
+                sd.comp = sr.comp;
+                sd.i = sr.pos[0];
+                sd.j = sr.pos[1];
+                sd.k = sr.pos[2];
+                sd.nwave = sr.n_waveform;
+                sd.wave = (const T*)take((size_t)std::max(1, sr.n_waveform) * ts);
+            }
+            if (g) {
+                for (int st2 = 0; st2 < 2; ++st2)
+                    for (int c = 0; c < 3; ++c) {
+                        d.Ea[st2][c] = (T*)take(h.nfield * ts);
+                        d.Ha[st2][c] = (T*)take(h.nfield * ts);
+                    }
+                for (int c = 0; c < 3; ++c) d.Et[c] = (T*)take(h.nfield * ts);
+                h.gelems = 1;
+                for (int a = 0; a < 3; ++a) {
+                    d.glo[a] = s.grad_lo[a];
+                    d.ghi[a] = s.grad_hi[a];
+                    h.gelems *= (size_t)(s.grad_hi[a] - s.grad_lo[a]);
+                }
+                h.gncomp = d.eps_diag ? 3 : 1;
+                for (int c = 0; c < h.gncomp; ++c) d.gacc[c] = (double*)take(std::max<size_t>(h.gelems, 1) * 8);
+            }
+            // monitors
+            for (size_t k = 0; k < h.mons.size(); ++k) {
+                MonHost& mh = h.mons[k];
+                MonDev& md = mh.dev;
+                md.omega = (const double*)take(std::max(1, md.nf) * 8);
+                if (md.kind == 0) {
+                    md.trace = (double*)take(std::max(1, o->max_steps) * 8);
+                    md.cot = (double*)take(std::max(1, o->max_steps) * 8);
+                } else {
+                    md.samples = (void*)take((size_t)dft_block * md.ncomp * mh.npts * ts);
+                    mh.acc_elems = (size_t)md.nf * md.ncomp * mh.npts * 2;
+                    md.acc = (double*)take(mh.acc_elems * 8);
+                    md.cot = (double*)take(mh.acc_elems * 8);
+                }
+            }
+        }
+        size_t doms_off = take(sizeof(DomDev<T>) * n);
+        // tile table of the split kernels: 64 x 4 columns, kz-plane chunks
+        kz = 8;
+        std::vector<int> bs(n + 1, 0);
+        for (int q = 0; q < n; ++q) {
+            const fdtd_domain_desc& s = dh[q].desc;
+            int nb = ((s.n[0] + 63) / 64) * ((s.n[1] + 3) / 4) * ((s.n[2] + kz - 1) / kz);
+            bs[q + 1] = bs[q] + nb;
+        }
+        nblk = bs[n];
+        size_t bs_off = take(sizeof(int) * (n + 1));
+        // count state arrays for the checkpoint layout
+        size_t nstate = 0;
+        slot_bytes = 0;
+        for (int q = 0; q < n; ++q) collect_state(q, nstate, slot_bytes, /*fill=*/false);
+        size_t scales_off = take(std::max<size_t>(1, (size_t)o->n_ckpt * nstate) * 4);
+        size_t sum_off = take(8);
+        pool_bytes = align256(off);
+        double total = (double)pool_bytes + (double)slot_bytes * o->n_ckpt;
+        double budget = o->mem_budget_bytes;
+        if (budget <= 0) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(FDTD_E_DEVICE, "hipMemGetInfo failed");
+            budget = (double)fr - 256.0 * 1024 * 1024;
+        }
+        if (total > budget) {
+            char b[160];
+            snprintf(b, sizeof b, "device memory request %.3e B exceeds budget %.3e B", total, budget);
+            return fail(FDTD_E_NOMEM, b);
+        }
+        if (hipMalloc((void**)&pool, pool_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            pool = nullptr;
+            return fail(FDTD_E_NOMEM, "hipMalloc of the state pool failed");
+        }
+        if (o->n_ckpt > 0 && slot_bytes > 0) {
+            if (hipMalloc((void**)&ckpool, slot_bytes * o->n_ckpt) != hipSuccess) {
+                (void)hipGetLastError();
+                ckpool = nullptr;
+                return fail(FDTD_E_NOMEM, "hipMalloc of the checkpoint slots failed");
+            }
+        }
+        slots.assign(o->n_ckpt, Slot{});
+        // ---- fix up pointers
+        for (int q = 0; q < n; ++q) fixup(dd[q], dh[q]);
+        d_doms = (DomDev<T>*)(pool + doms_off - 1);
+        d_bs = (int*)(pool + bs_off - 1);
+        d_scales = (unsigned int*)(pool + scales_off - 1);
+        d_sum = (unsigned long long*)(pool + sum_off - 1);
+        fwd.clear();
+        adj.clear();
+        size_t dummy_n = 0, dummy_b = 0;
+        for (int q = 0; q < n; ++q) collect_state(q, dummy_n, dummy_b, /*fill=*/true);
+        // ---- initialise: zero everything, upload tables and inputs
+        launch_zero(pool, pool_bytes, st);
+        int rc = check("zero pool");
+        if (rc) return rc;
+        std::vector<T> tmp;
+        auto up = [&](const void* dst, const std::vector<double>& src) -> int {
+            tmp.assign(src.begin(), src.end());
+            if (hipMemcpyAsync((void*)dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return fail(FDTD_E_DEVICE, "upload failed");
+            return hipStreamSynchronize(st) == hipSuccess ? 0 : fail(FDTD_E_DEVICE, "upload sync failed");
+        };
+        for (int q = 0; q < n; ++q) {
+            DomHost& h = dh[q];
+            DomDev<T>& d = dd[q];
+            const fdtd_domain_desc& s = h.desc;
+            std::vector<double> tb;
+            for (int a = 0; a < 3; ++a) {
+                cpml_tables(s.n[a], s.pml[2 * a], s.pml[2 * a + 1], s.courant, s.pml_m, s.pml_kappa_max,
+                            s.pml_sigma_max, s.pml_alpha_max, tb);
+                if ((rc = up(d.tab[a], tb))) return rc;
+            }
+            if ((rc = upload_eps(q))) return rc;
+            for (int k = 0; k < s.n_sources; ++k)
+                if (s.sources[k].n_waveform > 0 && (rc = up(d.src[k].wave, h.waves[k]))) return rc;
+            for (auto& mh : h.mons) {
+                if (hipMemcpyAsync((void*)mh.dev.omega, mh.omega.data(), mh.omega.size() * 8, hipMemcpyHostToDevice,
+                                   st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "upload omega failed");
+            }
+        }
+        if (hipMemcpyAsync(d_doms, dd.data(), sizeof(DomDev<T>) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(d_bs, bs.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+            return fail(FDTD_E_DEVICE, "upload descriptors failed");
+        return sync("create");
+    }
+
+    int upload_eps(int q) {
+        DomHost& h = dh[q];
+        DomDev<T>& d = dd[q];
+        if (!d.epsinv[0]) return FDTD_OK;
+        size_t ebox = 1;
+        for (int a = 0; a < 3; ++a) ebox *= (size_t)(d.ehi[a] - d.elo[a]);
+        std::vector<T> v(ebox);
+        for (int c = 0; c < h.ncomp_eps; ++c) {
+            for (size_t e = 0; e < ebox; ++e) v[e] = (T)(1.0 / h.eps[c * ebox + e]);
+            if (hipMemcpyAsync((void*)d.epsinv[c], v.data(), ebox * sizeof(T), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return fail(FDTD_E_DEVICE, "upload eps failed");
+            if (hipStreamSynchronize(st) != hipSuccess) return fail(FDTD_E_DEVICE, "upload eps sync failed");
+        }
+        return FDTD_OK;
+    }
+
+    template <typename P>
+    void fix(P*& p) {
+        if (p) p = (P*)(pool + (uintptr_t)p - 1);
+    }
+
+    void fixup(DomDev<T>& d, DomHost& h) {
+        for (int s = 0; s < 2; ++s)
+            for (int c = 0; c < 3; ++c) {
+                fix(d.E[s][c]);
+                fix(d.H[s][c]);
+                fix(d.Ea[s][c]);
+                fix(d.Ha[s][c]);
+            }
+        for (int c = 0; c < 3; ++c) fix(d.Et[c]);
+        for (int a = 0; a < 3; ++a) fix(d.tab[a]);
+        for (int s = 0; s < 2; ++s)
+            for (int a = 0; a < 3; ++a)
+                for (int side = 0; side < 2; ++side)
+                    for (int r = 0; r < 2; ++r) {
+                        fix(d.psiE[s][a][side][r]);
+                        fix(d.psiH[s][a][side][r]);
+                        fix(d.psiEa[s][a][side][r]);
+                        fix(d.psiHa[s][a][side][r]);
+                    }
+        // isotropic eps: the three component pointers alias one array
+        const T* e0 = d.epsinv[0];
+        fix(d.epsinv[0]);
+        for (int c = 1; c < 3; ++c) {
+            if (d.epsinv[c] == e0) d.epsinv[c] = d.epsinv[0];
+            else fix(d.epsinv[c]);
+        }
+        for (int s = 0; s < 2; ++s)
+            for (int w = 0; w < 3; ++w)
+                for (int c = 0; c < 3; ++c) {
+                    fix(d.lor[s][w][c]);
+                    fix(d.lora[s][w][c]);
+                }
+        for (int k = 0; k < d.nsrc; ++k) fix(d.src[k].wave);
+        for (int c = 0; c < 3; ++c) fix(d.gacc[c]);
+        for (auto& mh : h.mons) {
+            fix(mh.dev.omega);
+            fix(mh.dev.trace);
+            fix(mh.dev.cot);
+            fix(mh.dev.samples);
+            fix(mh.dev.acc);
+        }
+    }
+
+    // state arrays of domain q: forward (checkpointed) and adjoint (zeroed at begin)
+    void collect_state(int q, size_t& nstate, size_t& bytes, bool fill) {
+        DomDev<T>& d = dd[q];
+        DomHost& h = dh[q];
+        size_t es = bf16 ? 2 : sizeof(T);
+        auto addf = [&](void* a, void* b, size_t ne) {
+            if (!a) return;
+            nstate++;
+            bytes += align256(ne * es);
+            if (fill) fwd.push_back(StateArr{{a, b}, ne});
+        };
+        auto adda = [&](void* a, void* b, size_t ne) {
+            if (!a || !fill) return;
+            adj.push_back(StateArr{{a, b}, ne});
+        };
+        const fdtd_domain_desc& s = h.desc;
+        int nx = s.n[0], ny = s.n[1], nz = s.n[2];
+        for (int c = 0; c < 3; ++c) {
+            addf(d.E[0][c], d.E[1][c], h.nfield);
+            addf(d.H[0][c], d.H[1][c], h.nfield);
+            adda(d.Ea[0][c], d.Ea[1][c], h.nfield);
+            adda(d.Ha[0][c], d.Ha[1][c], h.nfield);
+            adda(d.Et[c], d.Et[c], h.nfield);
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int side = 0; side < 2; ++side) {
+                size_t L = (size_t)d.L[a][side];
+                size_t ne = a == 0 ? L * ny * nz : (a == 1 ? L * nx * nz : L * nx * ny);
+                for (int r = 0; r < 2; ++r) {
+                    addf(d.psiE[0][a][side][r], d.psiE[1][a][side][r], ne);
+                    addf(d.psiH[0][a][side][r], d.psiH[1][a][side][r], ne);
+                    adda(d.psiEa[0][a][side][r], d.psiEa[1][a][side][r], ne);
+                    adda(d.psiHa[0][a][side][r], d.psiHa[1][a][side][r], ne);
+                }
+            }
+        if (d.has_lor) {
+            size_t lbox = 1;
+            for (int a = 0; a < 3; ++a) lbox *= (size_t)(d.lhi[a] - d.llo[a]);
+            for (int w = 0; w < 3; ++w)
+                for (int c = 0; c < 3; ++c) {
+                    addf(d.lor[0][w][c], d.lor[1][w][c], lbox);
+                    adda(d.lora[0][w][c], d.lora[1][w][c], lbox);
+                }
+        }
+        if (fill && d.grad)
+            for (int c = 0; c < h.gncomp; ++c) adj_flat.push_back({d.gacc[c], std::max<size_t>(h.gelems, 1) * 8});
+    }
+
+    // ------------------------------------------------------------ validation
+    int validate(const fdtd_domain_desc& s, DomHost& h) {
+        h.desc = s;
+        for (int a = 0; a < 3; ++a)
+            if (s.n[a] < 1 || s.n[a] > (1 << 20)) return fail(FDTD_E_INVALID, "grid size out of range");
+        if (!(s.courant > 0) || !std::isfinite(s.courant))
+            return fail(FDTD_E_UNSTABLE, "Courant number must be positive and finite");
+        if (s.courant * std::sqrt(3.0) > 0.99 + 1e-12)
+            return fail(FDTD_E_UNSTABLE, "CFL: S*sqrt(3) exceeds 0.99 (Eq. 2)");
+        for (int a = 0; a < 3; ++a) {
+            int l0 = s.pml[2 * a], l1 = s.pml[2 * a + 1];
+            if (l0 < 0 || l1 < 0 || l0 + l1 > s.n[a]) return fail(FDTD_E_INVALID, "absorbing depth out of range");
+        }
+        if (!(s.eps_bg > 0) || !std::isfinite(s.eps_bg))
+            return fail(FDTD_E_UNSTABLE, "background permittivity must be positive and finite");
+        if (s.eps_kind != FDTD_EPS_ISO && s.eps_kind != FDTD_EPS_DIAG) return fail(FDTD_E_INVALID, "eps_kind");
+        h.ncomp_eps = s.eps_kind == FDTD_EPS_DIAG ? 3 : 1;
+        size_t ebox = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (s.eps_lo[a] < 0 || s.eps_hi[a] > s.n[a] || s.eps_lo[a] > s.eps_hi[a])
+                return fail(FDTD_E_INVALID, "eps box out of range");
+            ebox *= (size_t)(s.eps_hi[a] - s.eps_lo[a]);
+        }
+        if (ebox && !s.eps) return fail(FDTD_E_INVALID, "eps array missing");
+        if (ebox) {
+            h.eps.assign(s.eps, s.eps + ebox * h.ncomp_eps);
+            for (double e : h.eps)
+                if (!(e > 0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be positive and finite");
+            if (h.ncomp_eps == 3) {
+                // Section 2.3: a tensor inside an absorbing face needs the face normal to be a
+                // principal axis whose eigenvalue is not the intermediate one.
+                int bx = s.eps_hi[0] - s.eps_lo[0], by = s.eps_hi[1] - s.eps_lo[1];
+                for (size_t e = 0; e < ebox; ++e) {
+                    int i = s.eps_lo[0] + (int)(e % bx), j = s.eps_lo[1] + (int)((e / bx) % by),
+                        k = s.eps_lo[2] + (int)(e / ((size_t)bx * by));
+                    int x[3] = {i, j, k};
+                    double v[3] = {h.eps[e], h.eps[ebox + e], h.eps[2 * ebox + e]};
+                    for (int a = 0; a < 3; ++a) {
+                        bool inface = x[a] < s.pml[2 * a] || x[a] >= s.n[a] - s.pml[2 * a + 1];
+                        if (!inface) continue;
+                        double o1 = v[(a + 1) % 3], o2 = v[(a + 2) % 3];
+                        bool mid = (v[a] > std::min(o1, o2) && v[a] < std::max(o1, o2));
+                        if (mid) return fail(FDTD_E_UNSTABLE, "anisotropic eps with intermediate normal eigenvalue in an absorbing face");
+                    }
+                }
+            }
+        }
+        if (s.n_lorentz < 0 || s.n_lorentz > 1) return fail(FDTD_E_INVALID, "at most one Lorentz box per domain");
+        if (s.n_lorentz) {
+            const fdtd_lorentz_desc& L = s.lorentz;
+            for (int a = 0; a < 3; ++a)
+                if (L.lo[a] < 0 || L.hi[a] > s.n[a] || L.lo[a] >= L.hi[a]) return fail(FDTD_E_INVALID, "Lorentz box");
+            if (!(L.delta_eps >= 0) || !(L.omega0_dt > 0) || !(L.gamma_dt >= 0) || !std::isfinite(L.delta_eps) ||
+                !std::isfinite(L.omega0_dt) || !std::isfinite(L.gamma_dt))
+                return fail(FDTD_E_UNSTABLE, "Lorentz parameters must be finite with delta_eps >= 0, omega0 > 0, gamma >= 0");
+        }
+        if (s.n_sources < 0 || s.n_sources > FDTD_MAX_SOURCES) return fail(FDTD_E_INVALID, "too many sources");
+        h.waves.resize(s.n_sources);
+        for (int k = 0; k < s.n_sources; ++k) {
+            const fdtd_source_desc& sr = s.sources[k];
+            if (sr.comp < 0 || sr.comp > 2) return fail(FDTD_E_RANGE, "source component must be Ex, Ey or Ez");
+            if (sr.kind == FDTD_SRC_POINT) {
+                for (int a = 0; a < 3; ++a)
+                    if (sr.pos[a] < 0 || sr.pos[a] >= s.n[a]) return fail(FDTD_E_RANGE, "source position");
+            } else if (sr.kind == FDTD_SRC_PLANE_Z) {
+                if (sr.pos[2] < 0 || sr.pos[2] >= s.n[2]) return fail(FDTD_E_RANGE, "source plane");
+            } else {
+                return fail(FDTD_E_INVALID, "source kind");
+            }
+            if (sr.n_waveform < 0 || (sr.n_waveform > 0 && !sr.waveform)) return fail(FDTD_E_INVALID, "waveform");
+            h.waves[k].assign(sr.waveform, sr.waveform + sr.n_waveform);
+            for (double w : h.waves[k])
+                if (!std::isfinite(w)) return fail(FDTD_E_UNSTABLE, "non-finite waveform sample");
+        }
+        if (s.n_monitors < 0 || s.n_monitors > FDTD_MAX_MONITORS) return fail(FDTD_E_INVALID, "too many monitors");
+        h.mons.resize(s.n_monitors);
+        int dom_index = (int)(&h - dh.data());
+        for (int k = 0; k < s.n_monitors; ++k) {
+            const fdtd_monitor_desc& md = s.monitors[k];
+            MonHost& mh = h.mons[k];
+            MonDev& m = mh.dev;
+            m.dom = dom_index;
+            m.kind = md.kind == FDTD_MON_PROBE ? 0 : (md.kind == FDTD_MON_FLUX_Z ? 1 : 2);
+            if (md.kind < 0 || md.kind > 2) return fail(FDTD_E_INVALID, "monitor kind");
+            m.comp = md.comp;
+            m.k = md.pos[2];
+            if (m.k < 0 || m.k >= s.n[2]) return fail(FDTD_E_RANGE, "monitor plane");
+            if (md.kind == FDTD_MON_PROBE) {
+                if (md.comp < 0 || md.comp > 5) return fail(FDTD_E_RANGE, "probe component");
+                m.pi = md.pos[0];
+                m.pj = md.pos[1];
+                if (m.pi < 0 || m.pi >= s.n[0] || m.pj < 0 || m.pj >= s.n[1]) return fail(FDTD_E_RANGE, "probe position");
+                m.ncomp = 1;
+                m.nf = 0;
+                continue;
+            }
+            m.i0 = md.rect[0];
+            m.i1 = md.rect[1];
+            m.j0 = md.rect[2];
+            m.j1 = md.rect[3];
+            if (m.i0 < 0 || m.i1 > s.n[0] || m.i0 >= m.i1 || m.j0 < 0 || m.j1 > s.n[1] || m.j0 >= m.j1)
+                return fail(FDTD_E_RANGE, "monitor rectangle");
+            if (md.kind == FDTD_MON_PATCH_Z && (md.comp < 0 || md.comp > 5))
+                return fail(FDTD_E_RANGE, "patch component");
+            if (md.n_freq < 1 || md.n_freq > 4096 || !md.omega_dt) return fail(FDTD_E_INVALID, "monitor frequencies");
+            m.nf = md.n_freq;
+            m.ncomp = md.kind == FDTD_MON_FLUX_Z ? 4 : 1;
+            mh.npts = (m.i1 - m.i0) * (m.j1 - m.j0);
+            mh.omega.assign(md.omega_dt, md.omega_dt + md.n_freq);
+        }
+        if (s.grad) {
+            for (int a = 0; a < 3; ++a)
+                if (s.grad_lo[a] < 0 || s.grad_hi[a] > s.n[a] || s.grad_lo[a] > s.grad_hi[a])
+                    return fail(FDTD_E_INVALID, "gradient box out of range");
+        }
+        return FDTD_OK;
+    }
+
+    // ------------------------------------------------------------ stepping
+    void flush(MonHost& mh) {
+        if (mh.dev.kind == 0 || mh.pending == 0) return;
+        launch_dft<T>(mh.dev, mh.n0, mh.pending, st);
+        mh.pending = 0;
+    }
+
+    void record() {
+        int n = t;   // the state now holds E^n, H^{n+1/2}
+        for (auto& h : dh)
+            for (auto& mh : h.mons) {
+                if (mh.dev.kind == 0) {
+                    if (n - 1 < opt.max_steps) launch_probe<T>(d_doms, mh.dev, fp, n - 1, st);
+                    continue;
+                }
+                if (mh.pending == 0) mh.n0 = n;
+                launch_sample<T>(d_doms, mh.dev, fp, mh.pending, st);
+                if (++mh.pending == dft_block) flush(mh);
+            }
+    }
+
+    int step_forward(int n, unsigned flags) override {
+        if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
+        bool rec = (flags & FDTD_RECORD) && !(flags & FDTD_REPLAY);
+        for (int s = 0; s < n; ++s) {
+            launch_fwd_split<T>(d_doms, d_bs, ndom, nblk, kz, fp, t, st);
+            fp ^= 1;
+            ++t;
+            if (rec) record();
+        }
+        return check("step_forward");
+    }
+
+    int seed(int n) {
+        for (auto& h : dh) {
+            if (!h.desc.grad) continue;
+            for (auto& mh : h.mons) {
+                if (!mh.cot_set) continue;
+                if (mh.dev.kind == 0 && (n - 1 >= opt.max_steps || n < 1)) continue;
+                launch_seed<T>(d_doms, mh.dev, ap, n, st);
+            }
+        }
+        return check("seed");
+    }
+
+    int adjoint_begin(int n) override {
+        if (n < 0) return fail(FDTD_E_INVALID, "negative n_total");
+        for (auto& a : adj)
+            for (int s = 0; s < 2; ++s) launch_zero(a.p[s], a.n * sizeof(T), st);
+        for (auto& a : adj_flat) launch_zero(a.first, a.second, st);
+        ap = 0;
+        m = n;
+        if (n >= 1) return seed(n);
+        return check("adjoint_begin");
+    }
+
+    int step_adjoint(int n) override {
+        if (m < 0) return fail(FDTD_E_STATE, "fdtd_adjoint_begin has not been called");
+        for (int s = 0; s < n; ++s) {
+            if (m < 1) return fail(FDTD_E_STATE, "adjoint sweep already at step 0");
+            if (t != m - 1) {
+                char b[128];
+                snprintf(b, sizeof b, "adjoint step %d needs forward state u^%d, forward is at %d", m, m - 1, t);
+                return fail(FDTD_E_STATE, b);
+            }
+            launch_adj_split<T>(d_doms, d_bs, ndom, nblk, kz, ap, fp, st);
+            ap ^= 1;
+            --m;
+            if (m >= 1) {
+                int rc = seed(m);
+                if (rc) return rc;
+            }
+        }
+        return check("step_adjoint");
+    }
+
+    // ------------------------------------------------------------ checkpoints
+    int ckpt_save(int slot) override {
+        if (slot < 0 || slot >= (int)slots.size()) return fail(FDTD_E_RANGE, "checkpoint slot");
+        char* base = ckpool + (size_t)slot * slot_bytes;
+        size_t off = 0;
+        for (size_t q = 0; q < fwd.size(); ++q) {
+            StateArr& a = fwd[q];
+            if (bf16) {
+                unsigned int* sc = d_scales + (size_t)slot * fwd.size() + q;
+                launch_zero(sc, 4, st);
+                launch_maxabs_f32((const float*)a.p[fp], (long long)a.n, sc, st);
+                launch_pack_bf16((const float*)a.p[fp], (long long)a.n, sc, (uint16_t*)(base + off), st);
+                off += align256(a.n * 2);
+            } else {
+                if (hipMemcpyAsync(base + off, a.p[fp], a.n * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "checkpoint copy failed");
+                off += align256(a.n * sizeof(T));
+            }
+        }
+        slots[slot].valid = true;
+        slots[slot].step = t;
+        if (opt.ckpt_checksum) {
+            int rc = slot_sum(slot, &slots[slot].sum);
+            if (rc) return rc;
+        }
+        return check("checkpoint_save");
+    }
+
+    int slot_sum(int slot, unsigned long long* out) {
+        launch_zero(d_sum, 8, st);
+        launch_checksum(ckpool + (size_t)slot * slot_bytes, slot_bytes, d_sum, st);
+        if (hipMemcpyAsync(out, d_sum, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+            return fail(FDTD_E_DEVICE, "checksum copy failed");
+        return sync("checksum");
+    }
+
+    int ckpt_restore(int slot) override {
+        if (slot < 0 || slot >= (int)slots.size()) return fail(FDTD_E_RANGE, "checkpoint slot");
+        if (!slots[slot].valid) return fail(FDTD_E_STATE, "checkpoint slot is empty");
+        if (opt.ckpt_checksum) {
+            unsigned long long s2 = 0;
+            int rc = slot_sum(slot, &s2);
+            if (rc) return rc;
+            if (s2 != slots[slot].sum) return fail(FDTD_E_STATE, "checkpoint checksum mismatch");
+        }
+        char* base = ckpool + (size_t)slot * slot_bytes;
+        size_t off = 0;
+        for (size_t q = 0; q < fwd.size(); ++q) {
+            StateArr& a = fwd[q];
+            if (bf16) {
+                const unsigned int* sc = d_scales + (size_t)slot * fwd.size() + q;
+                launch_unpack_bf16((const uint16_t*)(base + off), (long long)a.n, sc, (float*)a.p[fp], st);
+                off += align256(a.n * 2);
+            } else {
+                if (hipMemcpyAsync(a.p[fp], base + off, a.n * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "checkpoint restore copy failed");
+                off += align256(a.n * sizeof(T));
+            }
+        }
+        t = slots[slot].step;
+        return check("checkpoint_restore");
+    }
+
+    // ------------------------------------------------------------ monitors
+    int monitor(int dom, int mon, int op, void* buf, size_t bytes) override {
+        if (dom < 0 || dom >= ndom) return fail(FDTD_E_RANGE, "domain index");
+        DomHost& h = dh[dom];
+        if (mon < 0 || mon >= (int)h.mons.size()) return fail(FDTD_E_RANGE, "monitor index");
+        MonHost& mh = h.mons[mon];
+        MonDev& m = mh.dev;
+        size_t ms = (size_t)std::max(1, opt.max_steps);
+        if (op == FDTD_MON_RESET) {
+            if (m.kind == 0) launch_zero(m.trace, ms * 8, st);
+            else launch_zero(m.acc, mh.acc_elems * 8, st);
+            mh.pending = 0;
+            return check("monitor reset");
+        }
+        if (op == FDTD_MON_GET || op == FDTD_MON_FLUX) {
+            flush(mh);
+            if (m.kind == 0) {
+                if (op != FDTD_MON_GET) return fail(FDTD_E_INVALID, "flux of a probe");
+                size_t nb = std::min(bytes / 8, ms) * 8;
+                if (hipMemcpyAsync(buf, m.trace, nb, hipMemcpyDeviceToHost, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "probe copy failed");
+                return sync("probe get");
+            }
+            std::vector<double> acc(mh.acc_elems);
+            if (hipMemcpyAsync(acc.data(), m.acc, mh.acc_elems * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "spectra copy failed");
+            int rc = sync("spectra get");
+            if (rc) return rc;
+            if (op == FDTD_MON_GET) {
+                if (bytes < mh.acc_elems * 8) return fail(FDTD_E_RANGE, "buffer too small for spectra");
+                std::memcpy(buf, acc.data(), mh.acc_elems * 8);
+                return FDTD_OK;
+            }
+            if (m.kind != 1) return fail(FDTD_E_INVALID, "flux needs a flux monitor");
+            if (bytes < (size_t)m.nf * 8) return fail(FDTD_E_RANGE, "buffer too small for flux");
+            // F(w) = Re sum (Ex Hy* - Ey Hx*), components (Ex, Ey, Hx, Hy)
+            double* out = (double*)buf;
+            size_t np = mh.npts;
+            for (int f = 0; f < m.nf; ++f) {
+                const double* a = acc.data() + (size_t)f * 4 * np * 2;
+                double s = 0;
+                for (size_t q = 0; q < np; ++q) {
+                    double exr = a[(0 * np + q) * 2], exi = a[(0 * np + q) * 2 + 1];
+                    double eyr = a[(1 * np + q) * 2], eyi = a[(1 * np + q) * 2 + 1];
+                    double hxr = a[(2 * np + q) * 2], hxi = a[(2 * np + q) * 2 + 1];
+                    double hyr = a[(3 * np + q) * 2], hyi = a[(3 * np + q) * 2 + 1];
+                    s += (exr * hyr + exi * hyi) - (eyr * hxr + eyi * hxi);
+                }
+                out[f] = s;
+            }
+            return FDTD_OK;
+        }
+        if (op == FDTD_MON_SET_COTANGENT) {
+            if (m.kind == 0) {
+                std::vector<double> g(ms, 0.0);
+                std::memcpy(g.data(), buf, std::min(bytes / 8, ms) * 8);
+                if (hipMemcpyAsync(m.cot, g.data(), ms * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "cotangent copy failed");
+            } else {
+                if (bytes < mh.acc_elems * 8) return fail(FDTD_E_RANGE, "buffer too small for cotangents");
+                if (hipMemcpyAsync(m.cot, buf, mh.acc_elems * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "cotangent copy failed");
+            }
+            mh.cot_set = true;
+            return sync("set cotangent");
+        }
+        return fail(FDTD_E_INVALID, "monitor op");
+    }
+
+    // ------------------------------------------------------------ fields
+    int get_field(int dom, int comp, void* buf, size_t bytes, bool set) override {
+        if (dom < 0 || dom >= ndom) return fail(FDTD_E_RANGE, "domain index");
+        if (comp < 0 || comp > 11) return fail(FDTD_E_RANGE, "component");
+        DomDev<T>& d = dd[dom];
+        bool adjc = comp >= 6;
+        int c = comp % 6;
+        if (adjc && !d.grad) return fail(FDTD_E_RANGE, "domain has no adjoint state");
+        int sset = adjc ? ap : fp;
+        T* p = adjc ? (c < 3 ? d.Ea[sset][c] : d.Ha[sset][c - 3]) : (c < 3 ? d.E[sset][c] : d.H[sset][c - 3]);
+        size_t nx = d.n[0], ny = d.n[1], nz = d.n[2];
+        if (bytes < nx * ny * nz * sizeof(T)) return fail(FDTD_E_RANGE, "buffer too small for field");
+        hipError_t e;
+        if (set)
+            e = hipMemcpy2DAsync(p, d.pitch * sizeof(T), buf, nx * sizeof(T), nx * sizeof(T), ny * nz,
+                                 hipMemcpyHostToDevice, st);
+        else
+            e = hipMemcpy2DAsync(buf, nx * sizeof(T), p, d.pitch * sizeof(T), nx * sizeof(T), ny * nz,
+                                 hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return fail(FDTD_E_DEVICE, "field copy failed");
+        return sync("field copy");
+    }
+
+    int get_grad(int dom, double* buf, size_t bytes) override {
+        if (dom < 0 || dom >= ndom) return fail(FDTD_E_RANGE, "domain index");
+        DomHost& h = dh[dom];
+        DomDev<T>& d = dd[dom];
+        if (!d.grad) return fail(FDTD_E_RANGE, "domain has no gradient");
+        if (bytes < h.gelems * h.gncomp * 8) return fail(FDTD_E_RANGE, "buffer too small for gradient");
+        for (int c = 0; c < h.gncomp; ++c)
+            if (hipMemcpyAsync(buf + c * h.gelems, d.gacc[c], h.gelems * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "gradient copy failed");
+        return sync("gradient copy");
+    }
+
+    int set_eps(int dom, const double* eps, size_t bytes) override {
+        if (dom < 0 || dom >= ndom) return fail(FDTD_E_RANGE, "domain index");
+        DomHost& h = dh[dom];
+        if (bytes < h.eps.size() * 8) return fail(FDTD_E_RANGE, "buffer too small for eps");
+        int rc = validate_eps_only(h.desc, h, eps);
+        if (rc) return rc;
+        return upload_eps(dom);
+    }
+
+    int validate_eps_only(const fdtd_domain_desc& s, DomHost& h, const double* eps) {
+        std::vector<double> v(eps, eps + h.eps.size());
+        for (double e : v)
+            if (!(e > 0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be positive and finite");
+        if (h.ncomp_eps == 3) {
+            size_t ebox = h.eps.size() / 3;
+            int bx = s.eps_hi[0] - s.eps_lo[0], by = s.eps_hi[1] - s.eps_lo[1];
+            for (size_t e = 0; e < ebox; ++e) {
+                int x[3] = {s.eps_lo[0] + (int)(e % bx), s.eps_lo[1] + (int)((e / bx) % by),
+                            s.eps_lo[2] + (int)(e / ((size_t)bx * by))};
+                double w[3] = {v[e], v[ebox + e], v[2 * ebox + e]};
+                for (int a = 0; a < 3; ++a) {
+                    bool inface = x[a] < s.pml[2 * a] || x[a] >= s.n[a] - s.pml[2 * a + 1];
+                    if (!inface) continue;
+                    double o1 = w[(a + 1) % 3], o2 = w[(a + 2) % 3];
+                    if (w[a] > std::min(o1, o2) && w[a] < std::max(o1, o2))
+                        return fail(FDTD_E_UNSTABLE, "anisotropic eps with intermediate normal eigenvalue in an absorbing face");
+                }
+            }
+        }
+        h.eps = v;
+        return FDTD_OK;
+    }
+
+    int reset() override {
+        for (auto& a : fwd)
+            for (int s = 0; s < 2; ++s) launch_zero(a.p[s], a.n * sizeof(T), st);
+        for (auto& h : dh)
+            for (auto& mh : h.mons) {
+                if (mh.dev.kind == 0) launch_zero(mh.dev.trace, std::max(1, opt.max_steps) * 8, st);
+                else launch_zero(mh.dev.acc, mh.acc_elems * 8, st);
+                mh.pending = 0;
+            }
+        fp = 0;
+        t = 0;
+        m = -1;
+        return sync("reset");
+    }
+
+    void steps(int* n, int* mm) override {
+        if (n) *n = t;
+        if (mm) *mm = m;
+    }
+
+    double memory() override { return (double)pool_bytes + (double)slot_bytes * slots.size(); }
+};
+
+int guard(fdtd_t h);
+
+}  // namespace
+
+struct fdtd_s {
+    std::unique_ptr<Base> impl;
+};
+
+namespace {
+int guard(fdtd_t h) {
+    if (!h || !h->impl) return FDTD_E_INVALID;
+    if (h->impl->poisoned) return FDTD_E_DEVICE;
+    return FDTD_OK;
+}
+}  // namespace
+
+#define GUARD(h)                \
+    do {                        \
+        int _g = guard(h);      \
+        if (_g) return _g;      \
+    } while (0)
+
+extern "C" {
+
+int fdtd_create(const fdtd_domain_desc* domains, int32_t n_domains, const fdtd_options* opt, fdtd_t* out) {
+    if (!out) return FDTD_E_INVALID;
+    *out = nullptr;
+    if (!domains || n_domains < 1 || !opt) {
+        g_create_error = "null descriptor or n_domains < 1";
+        return FDTD_E_INVALID;
+    }
+    if (opt->dtype != FDTD_F32 && opt->dtype != FDTD_F64) {
+        g_create_error = "dtype must be FDTD_F32 or FDTD_F64";
+        return FDTD_E_INVALID;
+    }
+    std::unique_ptr<fdtd_s> h(new fdtd_s);
+    if (opt->dtype == FDTD_F32) h->impl.reset(new Handle<float>());
+    else h->impl.reset(new Handle<double>());
+    int rc;
+    if (opt->dtype == FDTD_F32) rc = static_cast<Handle<float>*>(h->impl.get())->create(domains, n_domains, opt);
+    else rc = static_cast<Handle<double>*>(h->impl.get())->create(domains, n_domains, opt);
+    if (rc) {
+        g_create_error = h->impl->err;
+        return rc;
+    }
+    *out = h.release();
+    return FDTD_OK;
+}
+
+int fdtd_destroy(fdtd_t h) {
+    if (!h) return FDTD_E_INVALID;
+    delete h;
+    return FDTD_OK;
+}
+
+int fdtd_step_forward(fdtd_t h, int32_t n_steps, uint32_t flags) {
+    GUARD(h);
+    return h->impl->step_forward(n_steps, flags);
+}
+
+int fdtd_adjoint_begin(fdtd_t h, int32_t n_total) {
+    GUARD(h);
+    return h->impl->adjoint_begin(n_total);
+}
+
+int fdtd_step_adjoint(fdtd_t h, int32_t n_steps) {
+    GUARD(h);
+    return h->impl->step_adjoint(n_steps);
+}
+
+int fdtd_checkpoint_save(fdtd_t h, int32_t slot) {
+    GUARD(h);
+    return h->impl->ckpt_save(slot);
+}
+
+int fdtd_checkpoint_restore(fdtd_t h, int32_t slot) {
+    GUARD(h);
+    return h->impl->ckpt_restore(slot);
+}
+
+int fdtd_monitor_dft(fdtd_t h, int32_t domain, int32_t monitor, int32_t op, void* host_buf, size_t bytes) {
+    GUARD(h);
+    if (!host_buf && op != FDTD_MON_RESET) return FDTD_E_INVALID;
+    return h->impl->monitor(domain, monitor, op, host_buf, bytes);
+}
+
+int fdtd_get_field(fdtd_t h, int32_t domain, int32_t comp, void* host_buf, size_t bytes) {
+    GUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->get_field(domain, comp, host_buf, bytes, false);
+}
+
+int fdtd_set_field(fdtd_t h, int32_t domain, int32_t comp, const void* host_buf, size_t bytes) {
+    GUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->get_field(domain, comp, (void*)host_buf, bytes, true);
+}
+
+int fdtd_get_grad(fdtd_t h, int32_t domain, double* host_buf, size_t bytes) {
+    GUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->get_grad(domain, host_buf, bytes);
+}
+
+int fdtd_set_eps(fdtd_t h, int32_t domain, const double* eps, size_t bytes) {
+    GUARD(h);
+    if (!eps) return FDTD_E_INVALID;
+    return h->impl->set_eps(domain, eps, bytes);
+}
+
+int fdtd_reset(fdtd_t h) {
+    GUARD(h);
+    return h->impl->reset();
+}
+
+int fdtd_get_step(fdtd_t h, int32_t* fwd_n, int32_t* adj_m) {
+    GUARD(h);
+    int n = 0, m = 0;
+    h->impl->steps(&n, &m);
+    if (fwd_n) *fwd_n = n;
+    if (adj_m) *adj_m = m;
+    return FDTD_OK;
+}
+
+int fdtd_get_memory(fdtd_t h, double* bytes) {
+    GUARD(h);
+    if (bytes) *bytes = h->impl->memory();
+    return FDTD_OK;
+}
+
+const char* fdtd_last_error(fdtd_t h) {
+    if (!h || !h->impl) return g_create_error.c_str();
+    return h->impl->err.c_str();
+}
+
+}  // extern "C"

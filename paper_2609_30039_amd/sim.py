@@ -1,0 +1,128 @@
+"""Convenience layer over the C-ABI handle: numpy in, numpy out."""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import binding as B
+
+
+class Simulation:
+    """Owns one libfdtd handle advancing ``specs`` (one or more domains)."""
+
+    def __init__(self, specs, dtype: str = "f32", n_ckpt: int = 0, ckpt_storage: Optional[str] = None,
+                 ckpt_checksum: bool = False, max_steps: Optional[int] = None, kernel: str = "auto",
+                 dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
+                 mem_budget_bytes: float = 0.0):
+        if not isinstance(specs, (list, tuple)):
+            specs = [specs]
+        self.specs = list(specs)
+        self.dtype = np.float32 if dtype == "f32" else np.float64
+        dt = B.FDTD_F32 if dtype == "f32" else B.FDTD_F64
+        storage = {None: dt, "f32": B.FDTD_F32, "f64": B.FDTD_F64, "bf16": B.FDTD_BF16}[ckpt_storage]
+        kern = {"auto": B.FDTD_KERNEL_AUTO, "split": B.FDTD_KERNEL_SPLIT, "fused": B.FDTD_KERNEL_FUSED}[kernel]
+        if max_steps is None:
+            max_steps = max(max(s.n_steps for s in self.specs), 1)
+        self.max_steps = max_steps
+        self.h = B.fdtd_create(self.specs, dt, n_ckpt, storage, ckpt_checksum, max_steps, kern, dft_block,
+                               graph_chunk, stream, mem_budget_bytes)
+
+    def close(self):
+        if self.h is not None:
+            B.fdtd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------- stepping ----------------
+    def step(self, n: int = 1, record: bool = True):
+        B.fdtd_step_forward(self.h, n, B.FDTD_RECORD if record else B.FDTD_REPLAY)
+
+    def adjoint_begin(self, n_total: int):
+        B.fdtd_adjoint_begin(self.h, n_total)
+
+    def step_adjoint(self, n: int = 1):
+        B.fdtd_step_adjoint(self.h, n)
+
+    def save(self, slot: int):
+        B.fdtd_checkpoint_save(self.h, slot)
+
+    def restore(self, slot: int):
+        B.fdtd_checkpoint_restore(self.h, slot)
+
+    def reset(self):
+        B.fdtd_reset(self.h)
+
+    @property
+    def steps(self):
+        return B.fdtd_get_step(self.h)
+
+    # ---------------- data ----------------
+    def field(self, comp: int, domain: int = 0, adjoint: bool = False) -> np.ndarray:
+        nx, ny, nz = self.specs[domain].shape
+        out = np.empty((nz, ny, nx), dtype=self.dtype)
+        B.fdtd_get_field(self.h, domain, comp + (B.FDTD_ADJ if adjoint else 0), out)
+        return out
+
+    def set_field(self, comp: int, values: np.ndarray, domain: int = 0, adjoint: bool = False):
+        B.fdtd_set_field(self.h, domain, comp + (B.FDTD_ADJ if adjoint else 0),
+                         np.ascontiguousarray(values, dtype=self.dtype))
+
+    def _mon_shape(self, domain: int, monitor: int):
+        m = self.specs[domain].monitors[monitor]
+        i0, i1, j0, j1 = m.rect
+        nc = 4 if m.kind == "flux_z" else 1
+        return (len(m.omega_dt), nc, j1 - j0, i1 - i0)
+
+    def spectra(self, monitor: int, domain: int = 0) -> np.ndarray:
+        m = self.specs[domain].monitors[monitor]
+        if m.kind == "probe":
+            out = np.zeros(self.max_steps)
+            B.fdtd_monitor_dft(self.h, domain, monitor, B.FDTD_MON_GET, out)
+            return out
+        buf = np.zeros(self._mon_shape(domain, monitor) + (2,))
+        B.fdtd_monitor_dft(self.h, domain, monitor, B.FDTD_MON_GET, buf)
+        return buf[..., 0] + 1j * buf[..., 1]
+
+    def probe(self, monitor: int, domain: int = 0, n: Optional[int] = None) -> np.ndarray:
+        tr = self.spectra(monitor, domain)
+        return tr if n is None else tr[:n]
+
+    def flux(self, monitor: int, domain: int = 0) -> np.ndarray:
+        nf = len(self.specs[domain].monitors[monitor].omega_dt)
+        out = np.zeros(nf)
+        B.fdtd_monitor_dft(self.h, domain, monitor, B.FDTD_MON_FLUX, out)
+        return out
+
+    def set_cotangent(self, monitor: int, g: np.ndarray, domain: int = 0):
+        m = self.specs[domain].monitors[monitor]
+        if m.kind == "probe":
+            buf = np.zeros(self.max_steps)
+            g = np.asarray(g, dtype=np.float64).ravel()
+            buf[:len(g)] = g[:self.max_steps]
+        else:
+            g = np.asarray(g, dtype=np.complex128).reshape(self._mon_shape(domain, monitor))
+            buf = np.ascontiguousarray(np.stack([g.real, g.imag], axis=-1))
+        B.fdtd_monitor_dft(self.h, domain, monitor, B.FDTD_MON_SET_COTANGENT, buf)
+
+    def reset_monitor(self, monitor: int, domain: int = 0):
+        B.fdtd_monitor_dft(self.h, domain, monitor, B.FDTD_MON_RESET, None)
+
+    def grad(self, domain: int = 0) -> np.ndarray:
+        s = self.specs[domain]
+        lo, hi = s.grad_box
+        nc = 3 if s.eps_kind == "diag" else 1
+        out = np.zeros((nc, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]))
+        B.fdtd_get_grad(self.h, domain, out)
+        return out
+
+    def set_eps(self, eps: np.ndarray, domain: int = 0):
+        B.fdtd_set_eps(self.h, domain, eps)
+
+    def memory_bytes(self) -> float:
+        return B.fdtd_get_memory(self.h)

@@ -1,0 +1,98 @@
+"""The C-ABI library loads, exports every entry point of include/fdtd.h, and
+refuses bad descriptors on the host before touching the device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2609_30039_amd import binding as B
+from paper_2609_30039_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = B.lib()
+    names = _header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+def _spec(**kw):
+    s = W.pec_cavity(8, 10)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _refused(spec, code, **kw):
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([spec], B.FDTD_F32, mem_budget_bytes=1e12, **kw)
+    assert e.value.code == code, str(e.value)
+
+
+def test_cfl_bound_refused():
+    _refused(_spec(courant=0.995 / np.sqrt(3.0)), B.FDTD_E_UNSTABLE)
+
+
+def test_nonpositive_eps_refused():
+    s = _spec()
+    s.eps = s.eps.copy()
+    s.eps[0, 1, 2, 3] = -1.0
+    _refused(s, B.FDTD_E_UNSTABLE)
+    s.eps[0, 1, 2, 3] = np.nan
+    _refused(s, B.FDTD_E_UNSTABLE)
+
+
+def test_tensor_rule_in_absorbing_face():
+    """Diagonal eps inside an absorbing face whose normal eigenvalue is the
+    intermediate one is refused (Section 2.3); a non-intermediate one passes
+    validation (and is then refused only by the tiny memory budget)."""
+    n = 10
+    eps = np.ones((3, n, n, n))
+    eps[0, 5, 5, 0] = 2.0      # eps_xx = 2 at x = 0 (x face), eps_yy = 1, eps_zz = 3 -> intermediate
+    eps[2, 5, 5, 0] = 3.0
+    s = W.DomainSpec(shape=(n, n, n), courant=W.courant_3d(), pml=(3, 3, 0, 0, 0, 0), eps_kind="diag",
+                     eps_box=((0, 0, 0), (n, n, n)), eps=eps)
+    _refused(s, B.FDTD_E_UNSTABLE)
+    eps[0, 5, 5, 0] = 4.0      # largest eigenvalue along the normal: admitted
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([s], B.FDTD_F32, mem_budget_bytes=1.0)
+    assert e.value.code == B.FDTD_E_NOMEM
+
+
+def test_memory_budget_refused_before_allocation():
+    _refused_small = _spec()
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([_refused_small], B.FDTD_F32, mem_budget_bytes=1024.0)
+    assert e.value.code == B.FDTD_E_NOMEM
+    assert "budget" in str(e.value)
+
+
+def test_bad_positions_refused():
+    s = _spec()
+    s.sources[0].pos = (8, 1, 1)
+    _refused(s, B.FDTD_E_RANGE)
+    s = _spec()
+    s.monitors[0].comp = 7
+    _refused(s, B.FDTD_E_RANGE)
+    s = _spec()
+    s.monitors.append(W.MonitorSpec("flux_z", pos=(0, 0, 3), rect=(0, 9, 0, 8), omega_dt=np.array([0.1])))
+    _refused(s, B.FDTD_E_RANGE)
+    s = _spec(pml=(5, 5, 0, 0, 0, 0))
+    _refused(s, B.FDTD_E_INVALID)
+
+
+def test_bf16_needs_fp32():
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([_spec()], B.FDTD_F64, ckpt_storage=B.FDTD_BF16, mem_budget_bytes=1e12)
+    assert e.value.code == B.FDTD_E_INVALID
