@@ -126,6 +126,8 @@ typedef struct {
     int32_t kernel;                /* FDTD_KERNEL_* */
     int32_t dft_block;             /* time samples buffered before a DFT flush (0: default) */
     int32_t graph_chunk;           /* steps per captured hipGraph (0: no graph) */
+    int32_t tile_rows;             /* fused kernel: rows per wave, 2 | 4 | 8 (0: 4) */
+    int32_t tile_kz;               /* z planes per block (0: default) */
     void *stream;                  /* hipStream_t; NULL = default stream */
     double mem_budget_bytes;       /* refuse with FDTD_E_NOMEM above this (0: device free memory) */
 } fdtd_options;
@@ -197,6 +199,16 @@ int fdtd_get_step(fdtd_t h, int32_t *fwd_n, int32_t *adj_m);
 
 /* Bytes of device memory held by the handle. */
 int fdtd_get_memory(fdtd_t h, double *bytes);
+
+/* Timing of the stepping kernels with HIP events recorded on the handle's
+   stream around every forward/adjoint stepping launch:
+   op 1 = enable and clear, 0 = disable, 2 = synchronise and return the
+   summed kernel time (ms) and the number of timed launches since enable. */
+int fdtd_kernel_timing(fdtd_t h, int32_t op, double *total_ms, int64_t *launches);
+
+/* Failure injection for tests of checksum validation: overwrite 32-bit word
+   `word` of checkpoint slot `slot` with `value`. */
+int fdtd_checkpoint_corrupt(fdtd_t h, int32_t slot, size_t word, uint32_t value);
 
 /* Message of the last failing call on this handle (or of the last failing
    create when h is NULL); valid until the next call. */

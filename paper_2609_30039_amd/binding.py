@@ -32,7 +32,7 @@ ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_E_INVALID", -2: "FDTD_E_UNSTABLE", -3: "F
 EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_begin", "fdtd_step_adjoint",
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
-            "fdtd_get_memory", "fdtd_last_error"]
+            "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_checkpoint_corrupt", "fdtd_last_error"]
 
 
 class FdtdError(RuntimeError):
@@ -70,7 +70,8 @@ class DomainDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("n_ckpt", C.c_int32), ("ckpt_storage", C.c_int32),
                 ("ckpt_checksum", C.c_int32), ("max_steps", C.c_int32), ("kernel", C.c_int32),
-                ("dft_block", C.c_int32), ("graph_chunk", C.c_int32), ("stream", C.c_void_p),
+                ("dft_block", C.c_int32), ("graph_chunk", C.c_int32), ("tile_rows", C.c_int32),
+                ("tile_kz", C.c_int32), ("stream", C.c_void_p),
                 ("mem_budget_bytes", C.c_double)]
 
 
@@ -100,6 +101,8 @@ def lib():
         L.fdtd_reset.argtypes = [vp]
         L.fdtd_get_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.fdtd_get_memory.argtypes = [vp, C.POINTER(C.c_double)]
+        L.fdtd_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.fdtd_checkpoint_corrupt.argtypes = [vp, i32, sz, u32]
         L.fdtd_last_error.argtypes = [vp]
         L.fdtd_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -181,7 +184,7 @@ def domain_desc(spec, keep: list) -> DomainDesc:
 def fdtd_create(specs: Sequence, dtype: int = FDTD_F32, n_ckpt: int = 0, ckpt_storage: Optional[int] = None,
                 ckpt_checksum: bool = False, max_steps: int = 0, kernel: int = FDTD_KERNEL_AUTO,
                 dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
-                mem_budget_bytes: float = 0.0):
+                mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0):
     keep: list = []
     arr = (DomainDesc * len(specs))()
     for q, s in enumerate(specs):
@@ -195,6 +198,8 @@ def fdtd_create(specs: Sequence, dtype: int = FDTD_F32, n_ckpt: int = 0, ckpt_st
     o.kernel = kernel
     o.dft_block = dft_block
     o.graph_chunk = graph_chunk
+    o.tile_rows = tile_rows
+    o.tile_kz = tile_kz
     o.stream = stream
     o.mem_budget_bytes = mem_budget_bytes
     h = C.c_void_p()
@@ -264,6 +269,16 @@ def fdtd_get_memory(h) -> float:
     b = C.c_double()
     _chk(lib().fdtd_get_memory(h, C.byref(b)), h)
     return b.value
+
+
+def fdtd_kernel_timing(h, op: int):
+    ms, n = C.c_double(), C.c_int64()
+    _chk(lib().fdtd_kernel_timing(h, op, C.byref(ms), C.byref(n)), h)
+    return ms.value, n.value
+
+
+def fdtd_checkpoint_corrupt(h, slot: int, word: int, value: int):
+    return _chk(lib().fdtd_checkpoint_corrupt(h, slot, word, value), h)
 
 
 def fdtd_last_error(h=None) -> str:

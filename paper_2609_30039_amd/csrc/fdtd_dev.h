@@ -1,17 +1,20 @@
 // fdtd_dev.h -- device-side data layout and per-node arithmetic of libfdtd.
 //
 // Layout (per domain):
-//   fields         E[set][c], H[set][c]: [nz][ny][pitch], x fastest, pitch a
-//                  multiple of 128 B so every row starts on a cache line;
+//   fields         E[c], H[c]: [nz][ny][pitch], x fastest, pitch a multiple of
+//                  128 B so every row starts on a cache line;
 //   absorbers      psi slabs per face (axis a, side s) for the two components
 //                  that take a-derivatives; x faces [nz][ny][L], y faces
 //                  [nz][L][nx], z faces [L][ny][nx];
 //   material       eps^-1 over a box (one array for isotropic media, three for
 //                  diagonal tensors), a scalar outside;
 //   Lorentz        E^{n-1}, W^n, W^{n-1} per component over the Lorentz box.
-// Every quantity that a neighbouring tile may read during a step is kept in
-// two sets (ping-pong): a step reads set p and writes set 1-p, so tiles can
-// recompute halos without ordering constraints between workgroups.
+// The forward state of all domains forms one "state set"; state sets are
+// laid out at a fixed stride fs (elements), so the pointers stored here are
+// those of set 0 and set q lives at +q*fs.  Sets 0 and 1 are working sets; a
+// step reads one set and writes another, so tiles can recompute halos without
+// ordering between workgroups, and checkpoint slots are further sets that a
+// step can read directly.  The adjoint state has its own two sets (stride as).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,13 +35,14 @@ struct DomDev {
     int pitch;                 // row pitch of field arrays
     long long plane;           // pitch * ny
     T S;
-    // ---- forward state ----
-    T* E[2][3];
-    T* H[2][3];
+    long long fs, as;          // forward / adjoint state-set strides (elements)
+    // ---- forward state (set 0) ----
+    T* E[3];
+    T* H[3];
     int L[3][2];               // absorbing depth per axis and side
     const T* tab[3];           // per axis 6 tables of n[a]: bE cE kiE bH cH kiH
-    T* psiE[2][3][2][2];       // [set][axis][side][r], r = 0 -> component (a+2)%3, 1 -> (a+1)%3
-    T* psiH[2][3][2][2];
+    T* psiE[3][2][2];          // [axis][side][r], r = 0 -> component (a+2)%3, 1 -> (a+1)%3
+    T* psiH[3][2][2];
     int eps_diag;
     int elo[3], ehi[3];
     T epsinv_bg;
@@ -46,17 +50,17 @@ struct DomDev {
     int has_lor;
     int llo[3], lhi[3];
     T lal, lxi, lg;            // pole recursion constants
-    T* lor[2][3][3];           // [set][0 Eold | 1 W | 2 Wold][component] over the Lorentz box
+    T* lor[3][3];              // [0 Eold | 1 W | 2 Wold][component] over the Lorentz box
     int nsrc;
     SrcDev<T> src[kMaxSrc];
-    // ---- adjoint state ----
+    // ---- adjoint state (set 0) ----
     int grad;                  // domain takes part in the adjoint
-    T* Ea[2][3];
-    T* Ha[2][3];
+    T* Ea[3];
+    T* Ha[3];
     T* Et[3];                  // split transpose: cotangent of E^{n+1} after the H transpose
-    T* psiEa[2][3][2][2];
-    T* psiHa[2][3][2][2];
-    T* lora[2][3][3];
+    T* psiEa[3][2][2];
+    T* psiHa[3][2][2];
+    T* lora[3][3];
     int glo[3], ghi[3];
     double* gacc[3];           // dJ/deps accumulators over the gradient box (isotropic: [0] only)
 };
@@ -66,6 +70,8 @@ template <typename T>
 __device__ __forceinline__ long long fidx(const DomDev<T>& d, int i, int j, int k) {
     return (long long)k * d.plane + (long long)j * d.pitch + i;
 }
+
+__device__ __forceinline__ int coord(int a, int i, int j, int k) { return a == 0 ? i : (a == 1 ? j : k); }
 
 // side of the absorbing slab containing index x along axis a: 0 low, 1 high, -1 none
 template <typename T>
@@ -91,8 +97,13 @@ __device__ __forceinline__ long long pidx(const DomDev<T>& d, int a, int s, int 
 }
 
 template <typename T>
+__device__ __forceinline__ bool in_box(const int lo[3], const int hi[3], int i, int j, int k) {
+    return i >= lo[0] && i < hi[0] && j >= lo[1] && j < hi[1] && k >= lo[2] && k < hi[2];
+}
+
+template <typename T>
 __device__ __forceinline__ T epsinv_at(const DomDev<T>& d, int c, int i, int j, int k) {
-    if (i >= d.elo[0] && i < d.ehi[0] && j >= d.elo[1] && j < d.ehi[1] && k >= d.elo[2] && k < d.ehi[2]) {
+    if (in_box<T>(d.elo, d.ehi, i, j, k)) {
         long long q = ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) * (d.ehi[0] - d.elo[0]) +
                       (i - d.elo[0]);
         return d.epsinv[c][q];
@@ -102,8 +113,7 @@ __device__ __forceinline__ T epsinv_at(const DomDev<T>& d, int c, int i, int j, 
 
 template <typename T>
 __device__ __forceinline__ bool in_lor(const DomDev<T>& d, int i, int j, int k) {
-    return d.has_lor && i >= d.llo[0] && i < d.lhi[0] && j >= d.llo[1] && j < d.lhi[1] && k >= d.llo[2] &&
-           k < d.lhi[2];
+    return d.has_lor && in_box<T>(d.llo, d.lhi, i, j, k);
 }
 
 template <typename T>
@@ -112,62 +122,63 @@ __device__ __forceinline__ long long lidx(const DomDev<T>& d, int i, int j, int 
            (i - d.llo[0]);
 }
 
-__device__ __forceinline__ int coord(int a, int i, int j, int k) { return a == 0 ? i : (a == 1 ? j : k); }
-
 // PEC: E_c is held at zero where the index along c+1 or c+2 is 0
 __device__ __forceinline__ bool e_masked(int c, int i, int j, int k) {
     return coord((c + 1) % 3, i, j, k) == 0 || coord((c + 2) % 3, i, j, k) == 0;
 }
 
 // ---------------------------------------------------------- forward pieces
-// Stretched difference for one curl term: D raw difference along axis a at
-// node (i,j,k), r the slab component slot.  tab offset 0 (E side) or 3 (H side).
-template <typename T, bool WRITE>
-__device__ __forceinline__ T stretch(const DomDev<T>& d, T* const (&psi)[2][3][2][2], int p, int a, int r, int toff,
-                                     int i, int j, int k, T D) {
+// Stretched difference of one curl term: D is the raw difference along axis
+// a at node (i,j,k), r the slab slot, toff 0 (E side) or 3 (H side) in the
+// tables.  psi_new = b psi + c D, returns D / kappa + psi_new; the owner
+// stores psi_new into set ws.
+template <typename T>
+__device__ __forceinline__ T stretch(const DomDev<T>& d, T* const (&psi)[3][2][2], long long stride, int rs, int ws,
+                                     bool own, int a, int r, int toff, int i, int j, int k, T D) {
     int x = coord(a, i, j, k);
     int s = slab_side(d, a, x);
     if (s < 0) return D;
     const T* tb = d.tab[a];
     int n = d.n[a];
     T b = tb[(toff + 0) * n + x], c = tb[(toff + 1) * n + x], ki = tb[(toff + 2) * n + x];
-    long long q = pidx(d, a, s, i, j, k);
-    T pn = fma(b, psi[p][a][s][r][q], c * D);
-    if (WRITE) psi[1 - p][a][s][r][q] = pn;
+    T* base = psi[a][s][r] + pidx(d, a, s, i, j, k);
+    T pn = fma(b, base[rs * stride], c * D);
+    if (own) base[ws * stride] = pn;
     return fma(ki, D, pn);
 }
 
-// New E_c at node (i,j,k) from H^{n+1/2} (set p): h0 = H_{c+2} at the node and
-// h0m one step back along a0 = c+1; h1 = H_{c+1} and h1m back along a1 = c+2.
-// With WRITE the absorber memories and Lorentz history of set 1-p are
-// written (the owning tile); without, the value is only recomputed (halo).
-template <typename T, bool WRITE>
+// E^{n+1}_c at an unmasked or masked node (i,j,k) from H^{n+1/2} of set rs:
+// h0 = H_{c+2} at the node and h0m one step back along a0 = c+1; h1 = H_{c+1}
+// and h1m back along a1 = c+2.  The owner writes the absorber memories and
+// the Lorentz history into set ws; other callers only recompute the value.
+template <typename T>
 __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m,
-                                      T h1, T h1m, int p, int t) {
+                                      T h1, T h1m, int rs, int ws, bool own, int t) {
     const bool lorc = in_lor(d, i, j, k);
+    const long long fs = d.fs;
     if (e_masked(c, i, j, k)) {
-        if (WRITE && lorc) {
-            long long q = lidx(d, i, j, k);
-            d.lor[1 - p][0][c][q] = T(0);
-            d.lor[1 - p][1][c][q] = T(0);
-            d.lor[1 - p][2][c][q] = T(0);
+        if (own && lorc) {
+            long long q = lidx(d, i, j, k) + ws * fs;
+            d.lor[0][c][q] = T(0);
+            d.lor[1][c][q] = T(0);
+            d.lor[2][c][q] = T(0);
         }
         return T(0);
     }
     const int a0 = (c + 1) % 3, a1 = (c + 2) % 3;
-    T D0 = stretch<T, WRITE>(d, d.psiE, p, a0, 0, 0, i, j, k, h0 - h0m);
-    T D1 = stretch<T, WRITE>(d, d.psiE, p, a1, 1, 0, i, j, k, h1 - h1m);
+    T D0 = stretch(d, d.psiE, fs, rs, ws, own, a0, 0, 0, i, j, k, h0 - h0m);
+    T D1 = stretch(d, d.psiE, fs, rs, ws, own, a1, 1, 0, i, j, k, h1 - h1m);
     T curl = D0 - D1;
     T einv = epsinv_at(d, c, i, j, k);
-    T e = d.E[p][c][f];
+    T e = d.E[c][f + rs * fs];
     T en;
     long long q = 0;
     T eold = 0, w = 0, wold = 0;
     if (lorc) {
         q = lidx(d, i, j, k);
-        eold = d.lor[p][0][c][q];
-        w = d.lor[p][1][c][q];
-        wold = d.lor[p][2][c][q];
+        eold = d.lor[0][c][q + rs * fs];
+        w = d.lor[1][c][q + rs * fs];
+        wold = d.lor[2][c][q + rs * fs];
         T einf = T(1) / einv;
         T invden = T(1) / (einf + T(0.25) * d.lg);
         T num = fma(einf, e, T(0.25) * d.lg * eold);
@@ -181,35 +192,49 @@ __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, i
         const SrcDev<T>& sr = d.src[s];
         if (sr.comp == c && t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) en += sr.wave[t];
     }
-    if (WRITE && lorc) {
+    if (own && lorc) {
         T wn = fma(d.lal, w, d.lxi * wold);
         wn = fma(T(0.5) * d.lg, en - eold, wn);
-        d.lor[1 - p][0][c][q] = e;
-        d.lor[1 - p][1][c][q] = wn;
-        d.lor[1 - p][2][c][q] = w;
+        d.lor[0][c][q + ws * fs] = e;
+        d.lor[1][c][q + ws * fs] = wn;
+        d.lor[2][c][q + ws * fs] = w;
     }
     return en;
 }
 
-// New H_c at node (i,j,k) from E^{n+1}: e0p/e0 = E_{c+2} one step forward along
-// a0 = c+1 and at the node; e1p/e1 = E_{c+1} forward along a1 = c+2.
+// Bulk E update (no absorber, no mask, no Lorentz, no source at the node).
 template <typename T>
-__device__ __forceinline__ T h_update(const DomDev<T>& d, int c, int i, int j, int k, long long f, T e0p, T e0,
-                                      T e1p, T e1, int p) {
-    const int a0 = (c + 1) % 3, a1 = (c + 2) % 3;
-    T D0 = stretch<T, true>(d, d.psiH, p, a0, 0, 3, i, j, k, e0p - e0);
-    T D1 = stretch<T, true>(d, d.psiH, p, a1, 1, 3, i, j, k, e1p - e1);
-    return fma(-d.S, D0 - D1, d.H[p][c][f]);
+__device__ __forceinline__ T e_bulk(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m, T h1,
+                                    T h1m, int rs) {
+    T curl = (h0 - h0m) - (h1 - h1m);
+    return fma(d.S * epsinv_at(d, c, i, j, k), curl, d.E[c][f + rs * d.fs]);
 }
 
-// Stretched backward-difference curl of the forward H (set p) at E node,
-// read-only (the gradient needs it from u^n without touching the state).
+// H^{n+3/2}_c at node (i,j,k) from E^{n+1}: e0p/e0 = E_{c+2} one step forward
+// along a0 = c+1 and at the node; e1p/e1 = E_{c+1} forward along a1 = c+2.
+// hold is H^{n+1/2}_c at the node.
+template <typename T>
+__device__ __forceinline__ T h_update(const DomDev<T>& d, int c, int i, int j, int k, T hold, T e0p, T e0, T e1p,
+                                      T e1, int rs, int ws, bool own) {
+    const int a0 = (c + 1) % 3, a1 = (c + 2) % 3;
+    T D0 = stretch(d, d.psiH, d.fs, rs, ws, own, a0, 0, 3, i, j, k, e0p - e0);
+    T D1 = stretch(d, d.psiH, d.fs, rs, ws, own, a1, 1, 3, i, j, k, e1p - e1);
+    return fma(-d.S, D0 - D1, hold);
+}
+
+template <typename T>
+__device__ __forceinline__ T h_bulk(const DomDev<T>& d, T hold, T e0p, T e0, T e1p, T e1) {
+    return fma(-d.S, (e0p - e0) - (e1p - e1), hold);
+}
+
+// Stretched backward-difference curl of the forward H (set rs) at an E node,
+// read only (the gradient needs it from u^n without touching the state).
 template <typename T>
 __device__ __forceinline__ T curl_minus_ro(const DomDev<T>& d, int c, int i, int j, int k, T h0, T h0m, T h1, T h1m,
-                                           int p) {
+                                           int rs) {
     const int a0 = (c + 1) % 3, a1 = (c + 2) % 3;
-    T D0 = stretch<T, false>(d, d.psiE, p, a0, 0, 0, i, j, k, h0 - h0m);
-    T D1 = stretch<T, false>(d, d.psiE, p, a1, 1, 0, i, j, k, h1 - h1m);
+    T D0 = stretch(d, d.psiE, d.fs, rs, rs, false, a0, 0, 0, i, j, k, h0 - h0m);
+    T D1 = stretch(d, d.psiE, d.fs, rs, rs, false, a1, 1, 0, i, j, k, h1 - h1m);
     return D0 - D1;
 }
 
@@ -217,91 +242,67 @@ __device__ __forceinline__ T curl_minus_ro(const DomDev<T>& d, int c, int i, int
 // Transposed absorber recursion (Section 3.1): from the cotangent ybar of the
 // stretched derivative and the memory cotangent psibar, the cotangent of the
 // raw difference is ki*ybar + c*(psibar + ybar) and the memory cotangent
-// becomes b*(psibar + ybar).
-template <typename T, bool WRITE>
-__device__ __forceinline__ T stretch_T(const DomDev<T>& d, T* const (&psi)[2][3][2][2], int p, int a, int r,
-                                       int toff, int i, int j, int k, T ybar) {
+// becomes b*(psibar + ybar) (stored by the owner into set ws).
+template <typename T>
+__device__ __forceinline__ T stretch_T(const DomDev<T>& d, T* const (&psi)[3][2][2], int rs, int ws, bool own, int a,
+                                       int r, int toff, int i, int j, int k, T ybar) {
     int x = coord(a, i, j, k);
     int s = slab_side(d, a, x);
     if (s < 0) return ybar;
     const T* tb = d.tab[a];
     int n = d.n[a];
     T b = tb[(toff + 0) * n + x], c = tb[(toff + 1) * n + x], ki = tb[(toff + 2) * n + x];
-    long long q = pidx(d, a, s, i, j, k);
-    T mem = psi[p][a][s][r][q] + ybar;
-    if (WRITE) psi[1 - p][a][s][r][q] = b * mem;
+    T* base = psi[a][s][r] + pidx(d, a, s, i, j, k);
+    T mem = base[rs * d.as] + ybar;
+    if (own) base[ws * d.as] = b * mem;
     return fma(ki, ybar, c * mem);
 }
 
 // Cotangent of the raw forward difference d+_a E of the H_h update term
 // (a, sign, r) at H node (i,j,k): ybar = -S sign Hbar_h.
-template <typename T, bool WRITE>
-__device__ __forceinline__ T hT_dbar(const DomDev<T>& d, int a, int r, T sgn, int i, int j, int k, T hbar, int p) {
-    return stretch_T<T, WRITE>(d, d.psiHa, p, a, r, 3, i, j, k, -d.S * sgn * hbar);
-}
-
-// H transpose at E node: Ebar_e after adding (d+)^T of the two H terms that
-// differentiate E_e.  Term 1: H_{e+1} along e+2, sign +, slot r=0;
-// term 2: H_{e+2} along e+1, sign -, slot r=1.  hb1/hb1m: H_{e+1} cotangent at
-// the node and one step back along e+2; hb2/hb2m likewise along e+1.
 template <typename T>
-__device__ __forceinline__ T ht_update(const DomDev<T>& d, int e, int i, int j, int k, long long f, T hb1, T hb1m,
-                                       T hb2, T hb2m, int p) {
-    if (e_masked(e, i, j, k)) return T(0);
-    const int a1 = (e + 2) % 3, a2 = (e + 1) % 3;
-    T acc = d.Ea[p][e][f];
-    T t1 = hT_dbar<T, false>(d, a1, 0, T(1), i, j, k, hb1, p);
-    T t1m = coord(a1, i, j, k) > 0
-                ? hT_dbar<T, false>(d, a1, 0, T(1), i - (a1 == 0), j - (a1 == 1), k - (a1 == 2), hb1m, p)
-                : T(0);
-    T t2 = hT_dbar<T, false>(d, a2, 1, T(-1), i, j, k, hb2, p);
-    T t2m = coord(a2, i, j, k) > 0
-                ? hT_dbar<T, false>(d, a2, 1, T(-1), i - (a2 == 0), j - (a2 == 1), k - (a2 == 2), hb2m, p)
-                : T(0);
-    acc += t1m - t1;
-    acc += t2m - t2;
-    return acc;
+__device__ __forceinline__ T hT_dbar(const DomDev<T>& d, int a, int r, T sgn, int i, int j, int k, T hbar, int rs,
+                                     int ws, bool own) {
+    return stretch_T(d, d.psiHa, rs, ws, own, a, r, 3, i, j, k, -d.S * sgn * hbar);
 }
 
 // E-update transpose at E node c.  From etot (cotangent of E^{n+1} after the
-// H transpose) returns the cotangent of E^{n+1} before the source, epre, and
-// the coefficient that multiplies the curl (eps^-1 or 1/den).  With OWNER the
-// Lorentz history transpose is applied to set 1-p, the new cotangent of E^n
-// is returned in en, and the gradient contribution in dg (needs the forward
-// state: curl of H^{n+1/2} and, for Lorentz nodes, E^n, E^{n-1}, W^n, W^{n-1}
-// of set fp).
+// H transpose) returns the cotangent of E^{n+1} before the source (epre) and
+// the coefficient of the curl (eps^-1 or 1/den).  The owner applies the
+// Lorentz history transpose into set ws and gets the new cotangent of E^n.
 template <typename T>
 struct AdjE {
     T epre, coef, en;
 };
 
-template <typename T, bool OWNER>
-__device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int j, int k, long long f, T etot,
-                                           int p) {
+template <typename T>
+__device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int j, int k, T etot, int rs, int ws,
+                                           bool own) {
     AdjE<T> r;
     r.epre = T(0);
     r.coef = T(0);
     r.en = T(0);
+    const long long as = d.as;
     if (e_masked(c, i, j, k)) {
-        if (OWNER && in_lor(d, i, j, k)) {
-            long long q = lidx(d, i, j, k);
-            d.lora[1 - p][0][c][q] = T(0);
-            d.lora[1 - p][1][c][q] = T(0);
-            d.lora[1 - p][2][c][q] = T(0);
+        if (own && in_lor(d, i, j, k)) {
+            long long q = lidx(d, i, j, k) + ws * as;
+            d.lora[0][c][q] = T(0);
+            d.lora[1][c][q] = T(0);
+            d.lora[2][c][q] = T(0);
         }
         return r;
     }
     T einv = epsinv_at(d, c, i, j, k);
     if (in_lor(d, i, j, k)) {
         long long q = lidx(d, i, j, k);
-        T wb = d.lora[p][1][c][q];
+        T wb = d.lora[1][c][q + rs * as];
         T einf = T(1) / einv;
         T invden = T(1) / (einf + T(0.25) * d.lg);
         T ep = fma(T(0.5) * d.lg, wb, etot);      // W^{n+1} roll feeds E^{n+1}
         r.epre = ep;
         r.coef = invden;
-        if (OWNER) {
-            T wob = d.lora[p][2][c][q], eob = d.lora[p][0][c][q];
+        if (own) {
+            T wob = d.lora[2][c][q + rs * as], eob = d.lora[0][c][q + rs * as];
             T wn = fma(d.lal, wb, wob);
             T wnm1 = d.lxi * wb;
             T enm1 = -T(0.5) * d.lg * wb;
@@ -310,9 +311,9 @@ __device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int
             enm1 = fma(T(0.25) * d.lg, s, enm1);
             wn = fma(-T(0.5) * (T(1) + d.lal), s, wn);
             wnm1 = fma(-T(0.5) * d.lxi, s, wnm1);
-            d.lora[1 - p][0][c][q] = enm1;
-            d.lora[1 - p][1][c][q] = wn;
-            d.lora[1 - p][2][c][q] = wnm1;
+            d.lora[0][c][q + ws * as] = enm1;
+            d.lora[1][c][q + ws * as] = wn;
+            d.lora[2][c][q + ws * as] = wnm1;
         }
     } else {
         r.epre = etot;
@@ -324,10 +325,50 @@ __device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int
 
 // Cotangent of the raw backward difference d-_a H of the E_c update term
 // (a, sign, r) at E node: ybar = S coef sign Ebar_pre.
-template <typename T, bool WRITE>
+template <typename T>
 __device__ __forceinline__ T et_dbar(const DomDev<T>& d, int a, int r, T sgn, int i, int j, int k, T epre, T coef,
-                                     int p) {
-    return stretch_T<T, WRITE>(d, d.psiEa, p, a, r, 0, i, j, k, d.S * coef * sgn * epre);
+                                     int rs, int ws, bool own) {
+    return stretch_T(d, d.psiEa, rs, ws, own, a, r, 0, i, j, k, d.S * coef * sgn * epre);
+}
+
+// dJ/deps_c contribution of one E node from the forward state u^n (set fsr):
+// -S eps^-2 Ebar_pre curl (dielectric), Ebar_pre (E^n - E^{n+1}_pre)/den (Lorentz).
+template <typename T>
+__device__ __forceinline__ double grad_term(const DomDev<T>& d, int c, int i, int j, int k, long long f, T epre,
+                                            T h0, T h0m, T h1, T h1m, int fsr) {
+    T curl = curl_minus_ro(d, c, i, j, k, h0, h0m, h1, h1m, fsr);
+    T einv = epsinv_at(d, c, i, j, k);
+    if (in_lor(d, i, j, k)) {
+        long long q = lidx(d, i, j, k) + fsr * d.fs;
+        T e = d.E[c][f + fsr * d.fs];
+        T eold = d.lor[0][c][q], w = d.lor[1][c][q], wold = d.lor[2][c][q];
+        T einf = T(1) / einv;
+        T invden = T(1) / (einf + T(0.25) * d.lg);
+        T num = fma(einf, e, T(0.25) * d.lg * eold);
+        num = fma(d.S, curl, num);
+        num -= T(0.5) * fma(T(1) + d.lal, w, d.lxi * wold);
+        T epre_f = num * invden;
+        return (double)epre * (double)((e - epre_f) * invden);
+    }
+    return -(double)epre * (double)(d.S * einv * einv * curl);
+}
+
+template <typename T>
+__device__ __forceinline__ bool in_gbox(const DomDev<T>& d, int i, int j, int k) {
+    return d.grad && in_box<T>(d.glo, d.ghi, i, j, k);
+}
+
+template <typename T>
+__device__ __forceinline__ void grad_store(const DomDev<T>& d, int i, int j, int k, const double g[3]) {
+    long long q = ((long long)(k - d.glo[2]) * (d.ghi[1] - d.glo[1]) + (j - d.glo[1])) * (d.ghi[0] - d.glo[0]) +
+                  (i - d.glo[0]);
+    if (d.eps_diag) {
+        d.gacc[0][q] += g[0];
+        d.gacc[1][q] += g[1];
+        d.gacc[2][q] += g[2];
+    } else {
+        d.gacc[0][q] += (g[0] + g[1]) + g[2];
+    }
 }
 
 }  // namespace fdtd

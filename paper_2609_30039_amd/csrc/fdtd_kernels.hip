@@ -1,9 +1,20 @@
 // fdtd_kernels.hip -- HIP kernels of libfdtd for gfx950 (MI355X).
 //
 // The Yee step is memory bound (~1 flop per byte against a machine balance of
-// ~20), so there is no matrix-core work here: kernels are organised around
+// ~20 flop/B), so there is no matrix-core work: kernels are built around
 // coalesced x-fastest rows, z-marching columns that keep the previous plane in
-// registers, XCD-aware block placement and ping-ponged state.
+// registers, XCD-aware block placement and state sets that a step reads and
+// writes separately.
+//
+// Two kernel families compute bitwise-identical results (same per-node
+// functions, no implicit contraction):
+//   split  one launch for the E update and one for the H update (their
+//          transposes for the adjoint); the simple reference path;
+//   fused  a single pass per step: a block of 4 waves covers 64 x-columns by
+//          4R rows, marches z, computes E^{n+1} on its tile plus a one-cell
+//          halo and H^{n+3/2} on the 62 x (4R-2) interior it owns; x
+//          neighbours travel by lane shuffles, y neighbours across waves by a
+//          double-buffered LDS row, z neighbours stay in registers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,19 +44,19 @@ __device__ __forceinline__ int find_domain(const int* __restrict__ bs, int ndom,
 }
 
 struct Col {
-    int dom, i, j, k0, k1;
+    int i, j, k0, k1;
     bool ok;
 };
 
-// 256 threads = 64 (x) x 4 (y) columns; each marches a z chunk of length kz.
+// split kernels: 256 threads = 64 (x) x 4 (y) columns, z chunk of length kz
 template <typename T>
 __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int ndom, int kz, const DomDev<T>*& dp) {
     Col c;
     int b = xcd_remap(blockIdx.x, gridDim.x);
-    c.dom = find_domain(bs, ndom, b);
-    dp = doms + c.dom;
+    int dom = find_domain(bs, ndom, b);
+    dp = doms + dom;
     const DomDev<T>& d = *dp;
-    int lb = b - bs[c.dom];
+    int lb = b - bs[dom];
     int nbx = (d.n[0] + 63) >> 6, nby = (d.n[1] + 3) >> 2;
     int bx = lb % nbx;
     int r = lb / nbx;
@@ -61,15 +72,16 @@ __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int 
 // ============================================================ forward, split
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               int ndom, int kz, int p, int t) {
+                                               int ndom, int kz, int rs, int ws, int t) {
     const DomDev<T>* dp;
     Col c = column(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
-    const T* Hx = d.H[p][0];
-    const T* Hy = d.H[p][1];
-    const T* Hz = d.H[p][2];
+    const long long ro = rs * d.fs, wo = ws * d.fs;
+    const T* Hx = d.H[0] + ro;
+    const T* Hy = d.H[1] + ro;
+    const T* Hz = d.H[2] + ro;
     T hxm = 0, hym = 0;   // Hx, Hy one plane below
     if (c.k0 > 0) {
         long long f = fidx(d, i, j, c.k0 - 1);
@@ -82,29 +94,30 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
         T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
         T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
         // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
-        T ex = e_update<T, true>(d, 0, i, j, k, f, hz, hz_ym, hy, hym, p, t);
-        T ey = e_update<T, true>(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, p, t);
-        T ez = e_update<T, true>(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, p, t);
-        d.E[1 - p][0][f] = ex;
-        d.E[1 - p][1][f] = ey;
-        d.E[1 - p][2][f] = ez;
+        T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
+        T ey = e_update(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, rs, ws, true, t);
+        T ez = e_update(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, rs, ws, true, t);
+        d.E[0][f + wo] = ex;
+        d.E[1][f + wo] = ey;
+        d.E[2][f + wo] = ez;
         hxm = hx;
         hym = hy;
     }
 }
 
-// reads E^{n+1} from set 1-p (written by k_fwd_e), H^{n+1/2} from set p
+// reads E^{n+1} from set ws (written by k_fwd_e), H^{n+1/2} from set rs
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               int ndom, int kz, int p) {
+                                               int ndom, int kz, int rs, int ws) {
     const DomDev<T>* dp;
     Col c = column(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j, nx = d.n[0], ny = d.n[1], nz = d.n[2];
-    const T* Ex = d.E[1 - p][0];
-    const T* Ey = d.E[1 - p][1];
-    const T* Ez = d.E[1 - p][2];
+    const long long ro = rs * d.fs, wo = ws * d.fs;
+    const T* Ex = d.E[0] + wo;
+    const T* Ey = d.E[1] + wo;
+    const T* Ez = d.E[2] + wo;
     long long f0 = fidx(d, i, j, c.k0);
     T ex = Ex[f0], ey = Ey[f0], ez = Ez[f0];
     for (int k = c.k0; k < c.k1; ++k) {
@@ -118,9 +131,9 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
         T ey_xp = i + 1 < nx ? Ey[f + 1] : T(0), ez_xp = i + 1 < nx ? Ez[f + 1] : T(0);
         T ex_yp = j + 1 < ny ? Ex[f + d.pitch] : T(0), ez_yp = j + 1 < ny ? Ez[f + d.pitch] : T(0);
         // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
-        d.H[1 - p][0][f] = h_update(d, 0, i, j, k, f, ez_yp, ez, ey1, ey, p);
-        d.H[1 - p][1][f] = h_update(d, 1, i, j, k, f, ex1, ex, ez_xp, ez, p);
-        d.H[1 - p][2][f] = h_update(d, 2, i, j, k, f, ey_xp, ey, ex_yp, ex, p);
+        d.H[0][f + wo] = h_update(d, 0, i, j, k, d.H[0][f + ro], ez_yp, ez, ey1, ey, rs, ws, true);
+        d.H[1][f + wo] = h_update(d, 1, i, j, k, d.H[1][f + ro], ex1, ex, ez_xp, ez, rs, ws, true);
+        d.H[2][f + wo] = h_update(d, 2, i, j, k, d.H[2][f + ro], ey_xp, ey, ex_yp, ex, rs, ws, true);
         ex = ex1;
         ey = ey1;
         ez = ez1;
@@ -128,19 +141,40 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
 }
 
 // ============================================================ adjoint, split
-// H transpose: Et = Ebar + (d+)^T of the H-update terms, from Hbar (set p).
+// H transpose: Et = Ebar + (d+)^T of the H-update terms, from Hbar (set rs).
+template <typename T>
+__device__ __forceinline__ T ht_update(const DomDev<T>& d, int e, int i, int j, int k, long long f, T hb1, T hb1m,
+                                       T hb2, T hb2m, int rs) {
+    if (e_masked(e, i, j, k)) return T(0);
+    // term 1: H_{e+1} along e+2 (+, slot 0); term 2: H_{e+2} along e+1 (-, slot 1)
+    const int a1 = (e + 2) % 3, a2 = (e + 1) % 3;
+    T acc = d.Ea[e][f + rs * d.as];
+    T t1 = hT_dbar(d, a1, 0, T(1), i, j, k, hb1, rs, rs, false);
+    T t1m = coord(a1, i, j, k) > 0
+                ? hT_dbar(d, a1, 0, T(1), i - (a1 == 0), j - (a1 == 1), k - (a1 == 2), hb1m, rs, rs, false)
+                : T(0);
+    T t2 = hT_dbar(d, a2, 1, T(-1), i, j, k, hb2, rs, rs, false);
+    T t2m = coord(a2, i, j, k) > 0
+                ? hT_dbar(d, a2, 1, T(-1), i - (a2 == 0), j - (a2 == 1), k - (a2 == 2), hb2m, rs, rs, false)
+                : T(0);
+    acc += t1m - t1;
+    acc += t2m - t2;
+    return acc;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                int ndom, int kz, int p) {
+                                                int ndom, int kz, int rs) {
     const DomDev<T>* dp;
     Col c = column(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
     const int i = c.i, j = c.j;
-    const T* Hx = d.Ha[p][0];
-    const T* Hy = d.Ha[p][1];
-    const T* Hz = d.Ha[p][2];
+    const long long ro = rs * d.as;
+    const T* Hx = d.Ha[0] + ro;
+    const T* Hy = d.Ha[1] + ro;
+    const T* Hz = d.Ha[2] + ro;
     T hxm = 0, hym = 0;
     if (c.k0 > 0) {
         long long f = fidx(d, i, j, c.k0 - 1);
@@ -152,186 +186,480 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
         T hx = Hx[f], hy = Hy[f], hz = Hz[f];
         T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
         T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
-        // Ebar_e: term 1 H_{e+1} along e+2 (+), term 2 H_{e+2} along e+1 (-)
         // Ex: Hy along z, Hz along y ; Ey: Hz along x, Hx along z ; Ez: Hx along y, Hy along x
-        d.Et[0][f] = ht_update(d, 0, i, j, k, f, hy, hym, hz, hz_ym, p);
-        d.Et[1][f] = ht_update(d, 1, i, j, k, f, hz, hz_xm, hx, hxm, p);
-        d.Et[2][f] = ht_update(d, 2, i, j, k, f, hx, hx_ym, hy, hy_xm, p);
+        d.Et[0][f] = ht_update(d, 0, i, j, k, f, hy, hym, hz, hz_ym, rs);
+        d.Et[1][f] = ht_update(d, 1, i, j, k, f, hz, hz_xm, hx, hxm, rs);
+        d.Et[2][f] = ht_update(d, 2, i, j, k, f, hx, hx_ym, hy, hy_xm, rs);
         hxm = hx;
         hym = hy;
     }
 }
 
-// Owner work at E node (i,j,k): E-update transposes of the three components,
-// new cotangents of E^n and the memories, gradient from the forward state
-// u^n (set fp), and the six raw-difference cotangents of the curl terms.
+// Raw-difference cotangents of the six curl terms at one E node.
 template <typename T>
 struct Dbar6 {
-    T x0, x1, y0, y1, z0, z1;   // component (x,y,z) term (0: along c+1, +; 1: along c+2, -)
+    T x0, x1, y0, y1, z0, z1;   // component (x,y,z), term 0 (along c+1, +) or 1 (along c+2, -)
 };
 
+// Owner work at E node (i,j,k) from the cotangents etot[3]: E-update
+// transposes, new cotangents of E^n (returned in en[3]), the six
+// raw-difference cotangents, and dJ/deps from the forward state (set fsr).
 template <typename T>
-__device__ __forceinline__ Dbar6<T> et_owner(const DomDev<T>& d, int i, int j, int k, int p, int fp, bool in_g,
-                                             double* gsum, double gc[3]) {
+__device__ __forceinline__ Dbar6<T> et_cell(const DomDev<T>& d, int i, int j, int k, const T etot[3], int rs, int ws,
+                                            bool own, int fsr, T en[3]) {
     long long f = fidx(d, i, j, k);
     Dbar6<T> o;
     T* dd[3][2] = {{&o.x0, &o.x1}, {&o.y0, &o.y1}, {&o.z0, &o.z1}};
-    T H[3], Hm[3][3];   // forward H at the node and one step back along x, y, z
-    if (in_g) {
-        for (int q = 0; q < 3; ++q) H[q] = d.H[fp][q][f];
+    bool ing = own && in_gbox(d, i, j, k);
+    T H[3] = {0, 0, 0}, Hm[3][3];   // forward H at the node and one step back along x, y, z
+    if (ing) {
+        const long long fo = fsr * d.fs;
+        for (int q = 0; q < 3; ++q) H[q] = d.H[q][f + fo];
         for (int q = 0; q < 3; ++q) {
-            Hm[0][q] = i > 0 ? d.H[fp][q][f - 1] : T(0);
-            Hm[1][q] = j > 0 ? d.H[fp][q][f - d.pitch] : T(0);
-            Hm[2][q] = k > 0 ? d.H[fp][q][f - d.plane] : T(0);
+            Hm[0][q] = i > 0 ? d.H[q][f + fo - 1] : T(0);
+            Hm[1][q] = j > 0 ? d.H[q][f + fo - d.pitch] : T(0);
+            Hm[2][q] = k > 0 ? d.H[q][f + fo - d.plane] : T(0);
         }
     }
+    double g[3] = {0, 0, 0};
     for (int cc = 0; cc < 3; ++cc) {
-        T et = d.Et[cc][f];
-        AdjE<T> r = et_node<T, true>(d, cc, i, j, k, f, et, p);
-        d.Ea[1 - p][cc][f] = r.en;
+        AdjE<T> r = et_node(d, cc, i, j, k, etot[cc], rs, ws, own);
+        en[cc] = r.en;
         const int a0 = (cc + 1) % 3, a1 = (cc + 2) % 3;
         if (e_masked(cc, i, j, k)) {
             *dd[cc][0] = T(0);
             *dd[cc][1] = T(0);
             continue;
         }
-        *dd[cc][0] = et_dbar<T, true>(d, a0, 0, T(1), i, j, k, r.epre, r.coef, p);
-        *dd[cc][1] = et_dbar<T, true>(d, a1, 1, T(-1), i, j, k, r.epre, r.coef, p);
-        if (in_g) {
+        *dd[cc][0] = et_dbar(d, a0, 0, T(1), i, j, k, r.epre, r.coef, rs, ws, own);
+        *dd[cc][1] = et_dbar(d, a1, 1, T(-1), i, j, k, r.epre, r.coef, rs, ws, own);
+        if (ing) {
             const int h0 = (cc + 2) % 3, h1 = (cc + 1) % 3;
-            T curl = curl_minus_ro(d, cc, i, j, k, H[h0], Hm[a0][h0], H[h1], Hm[a1][h1], fp);
-            T einv = epsinv_at(d, cc, i, j, k);
-            double g;
-            if (in_lor(d, i, j, k)) {
-                long long q = lidx(d, i, j, k);
-                T e = d.E[fp][cc][f];
-                T eold = d.lor[fp][0][cc][q], w = d.lor[fp][1][cc][q], wold = d.lor[fp][2][cc][q];
-                T einf = T(1) / einv;
-                T invden = T(1) / (einf + T(0.25) * d.lg);
-                T num = fma(einf, e, T(0.25) * d.lg * eold);
-                num = fma(d.S, curl, num);
-                num -= T(0.5) * fma(T(1) + d.lal, w, d.lxi * wold);
-                T epre_f = num * invden;
-                g = (double)r.epre * (double)((e - epre_f) * invden);
-            } else {
-                g = -(double)r.epre * (double)(d.S * einv * einv * curl);
-            }
-            gc[cc] = g;
-            *gsum += g;
+            g[cc] = grad_term(d, cc, i, j, k, f, r.epre, H[h0], Hm[a0][h0], H[h1], Hm[a1][h1], fsr);
         }
     }
+    if (ing) grad_store(d, i, j, k, g);
     return o;
-}
-
-template <typename T>
-__device__ __forceinline__ bool in_gbox(const DomDev<T>& d, int i, int j, int k) {
-    return i >= d.glo[0] && i < d.ghi[0] && j >= d.glo[1] && j < d.ghi[1] && k >= d.glo[2] && k < d.ghi[2];
-}
-
-template <typename T>
-__device__ __forceinline__ void grad_store(const DomDev<T>& d, int i, int j, int k, double gsum, const double gc[3]) {
-    long long q = ((long long)(k - d.glo[2]) * (d.ghi[1] - d.glo[1]) + (j - d.glo[1])) * (d.ghi[0] - d.glo[0]) +
-                  (i - d.glo[0]);
-    if (d.eps_diag) {
-        d.gacc[0][q] += gc[0];
-        d.gacc[1][q] += gc[1];
-        d.gacc[2][q] += gc[2];
-    } else {
-        d.gacc[0][q] += gsum;
-    }
 }
 
 // Raw-difference cotangent of one curl term at a neighbouring E node, read only.
 template <typename T>
-__device__ __forceinline__ T et_dbar_at(const DomDev<T>& d, int cc, int term, int i, int j, int k, int p) {
+__device__ __forceinline__ T et_dbar_at(const DomDev<T>& d, int cc, int term, int i, int j, int k, int rs) {
     if (e_masked(cc, i, j, k)) return T(0);
     long long f = fidx(d, i, j, k);
-    AdjE<T> r = et_node<T, false>(d, cc, i, j, k, f, d.Et[cc][f], p);
+    AdjE<T> r = et_node(d, cc, i, j, k, d.Et[cc][f], rs, rs, false);
     int a = term == 0 ? (cc + 1) % 3 : (cc + 2) % 3;
-    return et_dbar<T, false>(d, a, term, term == 0 ? T(1) : T(-1), i, j, k, r.epre, r.coef, p);
+    return et_dbar(d, a, term, term == 0 ? T(1) : T(-1), i, j, k, r.epre, r.coef, rs, rs, false);
 }
 
 // E transpose: Hbar += (d-)^T of the E-update terms; owner updates at E nodes.
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                int ndom, int kz, int p, int fp) {
+                                                int ndom, int kz, int rs, int ws, int fsr) {
     const DomDev<T>* dp;
     Col c = column(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
     const int i = c.i, j = c.j, nx = d.n[0], ny = d.n[1], nz = d.n[2];
-    double gsum = 0, gc[3] = {0, 0, 0};
-    bool ing = in_gbox(d, i, j, c.k0);
-    Dbar6<T> cur = et_owner(d, i, j, c.k0, p, fp, ing, &gsum, gc);
-    if (ing) grad_store(d, i, j, c.k0, gsum, gc);
+    const long long ro = rs * d.as, wo = ws * d.as;
+    auto owner = [&](int k) -> Dbar6<T> {
+        long long f = fidx(d, i, j, k);
+        T et[3] = {d.Et[0][f], d.Et[1][f], d.Et[2][f]};
+        T en[3];
+        Dbar6<T> o = et_cell(d, i, j, k, et, rs, ws, true, fsr, en);
+        d.Ea[0][f + wo] = en[0];
+        d.Ea[1][f + wo] = en[1];
+        d.Ea[2][f + wo] = en[2];
+        return o;
+    };
+    Dbar6<T> cur = owner(c.k0);
     for (int k = c.k0; k < c.k1; ++k) {
         long long f = fidx(d, i, j, k);
         // z-terms one plane up: Ey term 0 (along z), Ex term 1 (along z)
         Dbar6<T> nxt{};
         T up_y0 = 0, up_x1 = 0;
         if (k + 1 < c.k1) {
-            gsum = 0;
-            gc[0] = gc[1] = gc[2] = 0;
-            ing = in_gbox(d, i, j, k + 1);
-            nxt = et_owner(d, i, j, k + 1, p, fp, ing, &gsum, gc);
-            if (ing) grad_store(d, i, j, k + 1, gsum, gc);
+            nxt = owner(k + 1);
             up_y0 = nxt.y0;
             up_x1 = nxt.x1;
         } else if (k + 1 < nz) {
-            up_y0 = et_dbar_at(d, 1, 0, i, j, k + 1, p);
-            up_x1 = et_dbar_at(d, 0, 1, i, j, k + 1, p);
+            up_y0 = et_dbar_at(d, 1, 0, i, j, k + 1, rs);
+            up_x1 = et_dbar_at(d, 0, 1, i, j, k + 1, rs);
         }
         // x neighbour: Ez term 0 and Ey term 1 (along x); y neighbour: Ez term 1, Ex term 0 (along y)
         T xp_z0 = 0, xp_y1 = 0, yp_z1 = 0, yp_x0 = 0;
         if (i + 1 < nx) {
-            xp_z0 = et_dbar_at(d, 2, 0, i + 1, j, k, p);
-            xp_y1 = et_dbar_at(d, 1, 1, i + 1, j, k, p);
+            xp_z0 = et_dbar_at(d, 2, 0, i + 1, j, k, rs);
+            xp_y1 = et_dbar_at(d, 1, 1, i + 1, j, k, rs);
         }
         if (j + 1 < ny) {
-            yp_z1 = et_dbar_at(d, 2, 1, i, j + 1, k, p);
-            yp_x0 = et_dbar_at(d, 0, 0, i, j + 1, k, p);
+            yp_z1 = et_dbar_at(d, 2, 1, i, j + 1, k, rs);
+            yp_x0 = et_dbar_at(d, 0, 0, i, j + 1, k, rs);
         }
-        T hbx = d.Ha[p][0][f], hby = d.Ha[p][1][f], hbz = d.Ha[p][2][f];
+        T hbx = d.Ha[0][f + ro], hby = d.Ha[1][f + ro], hbz = d.Ha[2][f + ro];
         // memory cotangents of the H update at this node (input Hbar)
-        hT_dbar<T, true>(d, 1, 0, T(1), i, j, k, hbx, p);   // Hx term 0 along y
-        hT_dbar<T, true>(d, 2, 1, T(-1), i, j, k, hbx, p);  // Hx term 1 along z
-        hT_dbar<T, true>(d, 2, 0, T(1), i, j, k, hby, p);   // Hy term 0 along z
-        hT_dbar<T, true>(d, 0, 1, T(-1), i, j, k, hby, p);  // Hy term 1 along x
-        hT_dbar<T, true>(d, 0, 0, T(1), i, j, k, hbz, p);   // Hz term 0 along x
-        hT_dbar<T, true>(d, 1, 1, T(-1), i, j, k, hbz, p);  // Hz term 1 along y
+        hT_dbar(d, 1, 0, T(1), i, j, k, hbx, rs, ws, true);    // Hx term 0 along y
+        hT_dbar(d, 2, 1, T(-1), i, j, k, hbx, rs, ws, true);   // Hx term 1 along z
+        hT_dbar(d, 2, 0, T(1), i, j, k, hby, rs, ws, true);    // Hy term 0 along z
+        hT_dbar(d, 0, 1, T(-1), i, j, k, hby, rs, ws, true);   // Hy term 1 along x
+        hT_dbar(d, 0, 0, T(1), i, j, k, hbz, rs, ws, true);    // Hz term 0 along x
+        hT_dbar(d, 1, 1, T(-1), i, j, k, hbz, rs, ws, true);   // Hz term 1 along y
         hbx += (cur.y0 - up_y0) + (cur.z1 - yp_z1);
         hby += (cur.z0 - xp_z0) + (cur.x1 - up_x1);
         hbz += (cur.x0 - yp_x0) + (cur.y1 - xp_y1);
-        d.Ha[1 - p][0][f] = hbx;
-        d.Ha[1 - p][1][f] = hby;
-        d.Ha[1 - p][2][f] = hbz;
+        d.Ha[0][f + wo] = hbx;
+        d.Ha[1][f + wo] = hby;
+        d.Ha[2][f + wo] = hbz;
         cur = nxt;
     }
 }
 
+// ============================================================ fused tiles
+constexpr int kWaves = 4;
+
+struct Tile {
+    int X0, Y0, k0, k1, lane, w;
+    bool gen;   // tile touches absorbers, PEC faces, the Lorentz box or a source
+};
+
+template <typename T, int R>
+__device__ __forceinline__ Tile fused_tile(const DomDev<T>& d, int lb, int kz) {
+    Tile tl;
+    const int TXo = 62, TYo = kWaves * R - 2;
+    int nbx = (d.n[0] + TXo - 1) / TXo, nby = (d.n[1] + TYo - 1) / TYo;
+    int bx = lb % nbx, r = lb / nbx;
+    int by = r % nby, bz = r / nby;
+    tl.X0 = bx * TXo - 1;
+    tl.Y0 = by * TYo - 1;
+    tl.k0 = bz * kz;
+    tl.k1 = min(tl.k0 + kz, d.n[2]);
+    tl.lane = threadIdx.x & 63;
+    tl.w = threadIdx.x >> 6;
+    // block-uniform classification
+    int xlo = tl.X0, xhi = tl.X0 + 63, ylo = tl.Y0, yhi = tl.Y0 + kWaves * R - 1, zlo = tl.k0 - 1, zhi = tl.k1;
+    bool g = xlo <= 0 || ylo <= 0 || zlo <= 0;
+    int lo[3] = {xlo, ylo, zlo}, hi[3] = {xhi, yhi, zhi};
+    for (int a = 0; a < 3; ++a) {
+        if (d.L[a][0] > 0 && lo[a] < d.L[a][0]) g = true;
+        if (d.L[a][1] > 0 && hi[a] >= d.n[a] - d.L[a][1]) g = true;
+    }
+    if (d.has_lor && hi[0] >= d.llo[0] && lo[0] < d.lhi[0] && hi[1] >= d.llo[1] && lo[1] < d.lhi[1] &&
+        hi[2] >= d.llo[2] && lo[2] < d.lhi[2])
+        g = true;
+    for (int s = 0; s < d.nsrc; ++s) {
+        const SrcDev<T>& sr = d.src[s];
+        if (sr.k >= lo[2] && sr.k <= hi[2] &&
+            (sr.kind == 1 || (sr.i >= lo[0] && sr.i <= hi[0] && sr.j >= lo[1] && sr.j <= hi[1])))
+            g = true;
+    }
+    tl.gen = g;
+    return tl;
+}
+
+// ============================================================ forward, fused
+template <typename T, int R, bool GEN>
+__device__ __forceinline__ void fwd_fused_body(const DomDev<T>& d, const Tile& tl, int rs, int ws, int t) {
+    __shared__ T sH[2][kWaves][2][64];   // row R-1 of each wave: Hx, Hz of the newest H plane
+    __shared__ T sE[2][kWaves][2][64];   // row 0 of each wave: Ex, Ez of the newest E^{n+1} plane
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const int lane = tl.lane, w = tl.w;
+    const int i = tl.X0 + lane;
+    const bool ix = i >= 0 && i < nx;
+    const long long ro = rs * d.fs, wo = ws * d.fs;
+    int jr[R];
+    bool vr[R], ecomp[R], own[R];
+    for (int r = 0; r < R; ++r) {
+        int row = w * R + r;
+        jr[r] = tl.Y0 + row;
+        vr[r] = ix && jr[r] >= 0 && jr[r] < ny;
+        ecomp[r] = vr[r] && lane >= 1 && row >= 1;
+        own[r] = vr[r] && lane >= 1 && lane <= 62 && row >= 1 && row <= kWaves * R - 2;
+    }
+    T Hk[R][3], Ek[R][3];     // H^{n+1/2} and E^{n+1} at plane k
+    for (int r = 0; r < R; ++r)
+        for (int q = 0; q < 3; ++q) {
+            Hk[r][q] = T(0);
+            Ek[r][q] = T(0);
+        }
+    if (tl.k0 > 0)
+        for (int r = 0; r < R; ++r)
+            if (vr[r]) {
+                long long f = fidx(d, i, jr[r], tl.k0 - 1) + ro;
+                Hk[r][0] = d.H[0][f];
+                Hk[r][1] = d.H[1][f];
+            }
+    for (int k = tl.k0 - 1; k < tl.k1; ++k) {
+        const int kn = k + 1;             // plane of the E update
+        const bool have_n = kn < nz;
+        T Hn[R][3], En[R][3];
+        for (int r = 0; r < R; ++r) {
+            Hn[r][0] = Hn[r][1] = Hn[r][2] = T(0);
+            if (vr[r] && have_n) {
+                long long f = fidx(d, i, jr[r], kn) + ro;
+                Hn[r][0] = d.H[0][f];
+                Hn[r][1] = d.H[1][f];
+                Hn[r][2] = d.H[2][f];
+            }
+        }
+        const int pb = kn & 1;
+        sH[pb][w][0][lane] = Hn[R - 1][0];
+        sH[pb][w][1][lane] = Hn[R - 1][2];
+        __syncthreads();
+        T hx_ym0 = w > 0 ? sH[pb][w - 1][0][lane] : T(0);
+        T hz_ym0 = w > 0 ? sH[pb][w - 1][1][lane] : T(0);
+        // ---- E^{n+1} at plane kn
+        for (int r = 0; r < R; ++r) {
+            T hy_xm = __shfl_up(Hn[r][1], 1);
+            T hz_xm = __shfl_up(Hn[r][2], 1);
+            T hx_ym = r > 0 ? Hn[r - 1][0] : hx_ym0;
+            T hz_ym = r > 0 ? Hn[r - 1][2] : hz_ym0;
+            En[r][0] = En[r][1] = En[r][2] = T(0);
+            if (ecomp[r] && have_n) {
+                const int j = jr[r];
+                long long f = fidx(d, i, j, kn);
+                bool o = own[r] && kn >= tl.k0 && kn < tl.k1;
+                if (GEN) {
+                    En[r][0] = e_update(d, 0, i, j, kn, f, Hn[r][2], hz_ym, Hn[r][1], Hk[r][1], rs, ws, o, t);
+                    En[r][1] = e_update(d, 1, i, j, kn, f, Hn[r][0], Hk[r][0], Hn[r][2], hz_xm, rs, ws, o, t);
+                    En[r][2] = e_update(d, 2, i, j, kn, f, Hn[r][1], hy_xm, Hn[r][0], hx_ym, rs, ws, o, t);
+                } else {
+                    En[r][0] = e_bulk(d, 0, i, j, kn, f, Hn[r][2], hz_ym, Hn[r][1], Hk[r][1], rs);
+                    En[r][1] = e_bulk(d, 1, i, j, kn, f, Hn[r][0], Hk[r][0], Hn[r][2], hz_xm, rs);
+                    En[r][2] = e_bulk(d, 2, i, j, kn, f, Hn[r][1], hy_xm, Hn[r][0], hx_ym, rs);
+                }
+                if (o) {
+                    d.E[0][f + wo] = En[r][0];
+                    d.E[1][f + wo] = En[r][1];
+                    d.E[2][f + wo] = En[r][2];
+                }
+            }
+        }
+        // ---- H^{n+3/2} at plane k (uses E^{n+1} at k from the previous pass)
+        if (k >= tl.k0) {
+            const int pk = k & 1;
+            T ex_yp3 = w + 1 < kWaves ? sE[pk][w + 1][0][lane] : T(0);
+            T ez_yp3 = w + 1 < kWaves ? sE[pk][w + 1][1][lane] : T(0);
+            for (int r = 0; r < R; ++r) {
+                T ey_xp = __shfl_down(Ek[r][1], 1);
+                T ez_xp = __shfl_down(Ek[r][2], 1);
+                T ex_yp = r + 1 < R ? Ek[r + 1][0] : ex_yp3;
+                T ez_yp = r + 1 < R ? Ek[r + 1][2] : ez_yp3;
+                if (own[r]) {
+                    const int j = jr[r];
+                    long long f = fidx(d, i, j, k);
+                    T hx, hy, hz;
+                    if (GEN) {
+                        hx = h_update(d, 0, i, j, k, Hk[r][0], ez_yp, Ek[r][2], En[r][1], Ek[r][1], rs, ws, true);
+                        hy = h_update(d, 1, i, j, k, Hk[r][1], En[r][0], Ek[r][0], ez_xp, Ek[r][2], rs, ws, true);
+                        hz = h_update(d, 2, i, j, k, Hk[r][2], ey_xp, Ek[r][1], ex_yp, Ek[r][0], rs, ws, true);
+                    } else {
+                        hx = h_bulk(d, Hk[r][0], ez_yp, Ek[r][2], En[r][1], Ek[r][1]);
+                        hy = h_bulk(d, Hk[r][1], En[r][0], Ek[r][0], ez_xp, Ek[r][2]);
+                        hz = h_bulk(d, Hk[r][2], ey_xp, Ek[r][1], ex_yp, Ek[r][0]);
+                    }
+                    d.H[0][f + wo] = hx;
+                    d.H[1][f + wo] = hy;
+                    d.H[2][f + wo] = hz;
+                }
+            }
+        }
+        sE[pb][w][0][lane] = En[0][0];
+        sE[pb][w][1][lane] = En[0][2];
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hk[r][q] = Hn[r][q];
+                Ek[r][q] = En[r][q];
+            }
+    }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_fwd_fused(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
+                                                   int ndom, int kz, int rs, int ws, int t) {
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    int dom = find_domain(bs, ndom, b);
+    const DomDev<T>& d = doms[dom];
+    Tile tl = fused_tile<T, R>(d, b - bs[dom], kz);
+    if (tl.gen) fwd_fused_body<T, R, true>(d, tl, rs, ws, t);
+    else fwd_fused_body<T, R, false>(d, tl, rs, ws, t);
+}
+
+// ============================================================ adjoint, fused
+// Same tiling; the E-like pass forms the cotangent of E^{n+1} (H transpose)
+// and applies the E-update transpose at E nodes, the H-like pass applies the
+// transposed backward differences to Hbar.  Exchanged between nodes are the
+// raw-difference cotangents (absorber transpose already applied at their
+// source node).
+template <typename T, int R>
+__device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& tl, int rs, int ws, int fsr) {
+    __shared__ T sH[2][kWaves][2][64];   // row R-1: Hz term 1 (along y), Hx term 0 (along y)
+    __shared__ T sE[2][kWaves][2][64];   // row 0: Ez term 1 (along y), Ex term 0 (along y)
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const int lane = tl.lane, w = tl.w;
+    const int i = tl.X0 + lane;
+    const bool ix = i >= 0 && i < nx;
+    const long long ro = rs * d.as, wo = ws * d.as;
+    int jr[R];
+    bool vr[R], ecomp[R], own[R];
+    for (int r = 0; r < R; ++r) {
+        int row = w * R + r;
+        jr[r] = tl.Y0 + row;
+        vr[r] = ix && jr[r] >= 0 && jr[r] < ny;
+        ecomp[r] = vr[r] && lane >= 1 && row >= 1;
+        own[r] = vr[r] && lane >= 1 && lane <= 62 && row >= 1 && row <= kWaves * R - 2;
+    }
+    // plane-k registers: Hbar input, H-term cotangents along z, E-term cotangents
+    T Hbk[R][3], dHyz_k[R], dHxz_k[R];
+    Dbar6<T> Dk[R];
+    for (int r = 0; r < R; ++r) {
+        Hbk[r][0] = Hbk[r][1] = Hbk[r][2] = T(0);
+        dHyz_k[r] = dHxz_k[r] = T(0);
+        Dk[r] = Dbar6<T>{};
+    }
+    if (tl.k0 > 0)
+        for (int r = 0; r < R; ++r)
+            if (vr[r]) {
+                const int kk = tl.k0 - 1;
+                long long f = fidx(d, i, jr[r], kk) + ro;
+                dHyz_k[r] = hT_dbar(d, 2, 0, T(1), i, jr[r], kk, d.Ha[1][f], rs, rs, false);
+                dHxz_k[r] = hT_dbar(d, 2, 1, T(-1), i, jr[r], kk, d.Ha[0][f], rs, rs, false);
+            }
+    for (int k = tl.k0 - 1; k < tl.k1; ++k) {
+        const int kn = k + 1;
+        const bool have_n = kn < nz;
+        const bool hown_n = kn >= tl.k0 && kn < tl.k1;   // H nodes of plane kn belong to this chunk
+        T Hbn[R][3];
+        T dHxy[R], dHxz[R], dHyz[R], dHyx[R], dHzx[R], dHzy[R];
+        for (int r = 0; r < R; ++r) {
+            Hbn[r][0] = Hbn[r][1] = Hbn[r][2] = T(0);
+            dHxy[r] = dHxz[r] = dHyz[r] = dHyx[r] = dHzx[r] = dHzy[r] = T(0);
+            if (vr[r] && have_n) {
+                const int j = jr[r];
+                long long f = fidx(d, i, j, kn) + ro;
+                Hbn[r][0] = d.Ha[0][f];
+                Hbn[r][1] = d.Ha[1][f];
+                Hbn[r][2] = d.Ha[2][f];
+                bool o = own[r] && hown_n;
+                dHxy[r] = hT_dbar(d, 1, 0, T(1), i, j, kn, Hbn[r][0], rs, ws, o);
+                dHxz[r] = hT_dbar(d, 2, 1, T(-1), i, j, kn, Hbn[r][0], rs, ws, o);
+                dHyz[r] = hT_dbar(d, 2, 0, T(1), i, j, kn, Hbn[r][1], rs, ws, o);
+                dHyx[r] = hT_dbar(d, 0, 1, T(-1), i, j, kn, Hbn[r][1], rs, ws, o);
+                dHzx[r] = hT_dbar(d, 0, 0, T(1), i, j, kn, Hbn[r][2], rs, ws, o);
+                dHzy[r] = hT_dbar(d, 1, 1, T(-1), i, j, kn, Hbn[r][2], rs, ws, o);
+            }
+        }
+        const int pb = kn & 1;
+        sH[pb][w][0][lane] = dHzy[R - 1];
+        sH[pb][w][1][lane] = dHxy[R - 1];
+        __syncthreads();
+        T dHzy_m0 = w > 0 ? sH[pb][w - 1][0][lane] : T(0);
+        T dHxy_m0 = w > 0 ? sH[pb][w - 1][1][lane] : T(0);
+        // ---- E-like pass at plane kn
+        Dbar6<T> Dn[R];
+        for (int r = 0; r < R; ++r) {
+            T dHzx_m = __shfl_up(dHzx[r], 1);
+            T dHyx_m = __shfl_up(dHyx[r], 1);
+            T dHzy_m = r > 0 ? dHzy[r - 1] : dHzy_m0;
+            T dHxy_m = r > 0 ? dHxy[r - 1] : dHxy_m0;
+            Dn[r] = Dbar6<T>{};
+            if (ecomp[r] && have_n) {
+                const int j = jr[r];
+                long long f = fidx(d, i, j, kn);
+                bool o = own[r] && kn >= tl.k0 && kn < tl.k1;
+                T et[3];
+                // Ebar_e += [t1(p - e_a1) - t1(p)] + [t2(p - e_a2) - t2(p)]
+                // Ex: t1 = Hy along z, t2 = Hz along y; Ey: t1 = Hz along x, t2 = Hx along z;
+                // Ez: t1 = Hx along y, t2 = Hy along x
+                T t1[3] = {dHyz[r], dHzx[r], dHxy[r]}, t1m[3] = {dHyz_k[r], dHzx_m, dHxy_m};
+                T t2[3] = {dHzy[r], dHxz[r], dHyx[r]}, t2m[3] = {dHzy_m, dHxz_k[r], dHyx_m};
+                for (int e = 0; e < 3; ++e) {
+                    if (e_masked(e, i, j, kn)) {
+                        et[e] = T(0);
+                        continue;
+                    }
+                    T acc = d.Ea[e][f + ro];
+                    acc += t1m[e] - t1[e];
+                    acc += t2m[e] - t2[e];
+                    et[e] = acc;
+                }
+                T en[3];
+                Dn[r] = et_cell(d, i, j, kn, et, rs, ws, o, fsr, en);
+                if (o) {
+                    d.Ea[0][f + wo] = en[0];
+                    d.Ea[1][f + wo] = en[1];
+                    d.Ea[2][f + wo] = en[2];
+                }
+            }
+        }
+        // ---- H-like pass at plane k
+        if (k >= tl.k0) {
+            const int pk = k & 1;
+            T z1_yp3 = w + 1 < kWaves ? sE[pk][w + 1][0][lane] : T(0);
+            T x0_yp3 = w + 1 < kWaves ? sE[pk][w + 1][1][lane] : T(0);
+            for (int r = 0; r < R; ++r) {
+                T z0_xp = __shfl_down(Dk[r].z0, 1);
+                T y1_xp = __shfl_down(Dk[r].y1, 1);
+                T z1_yp = r + 1 < R ? Dk[r + 1].z1 : z1_yp3;
+                T x0_yp = r + 1 < R ? Dk[r + 1].x0 : x0_yp3;
+                if (own[r]) {
+                    long long f = fidx(d, i, jr[r], k);
+                    T hbx = Hbk[r][0], hby = Hbk[r][1], hbz = Hbk[r][2];
+                    hbx += (Dk[r].y0 - Dn[r].y0) + (Dk[r].z1 - z1_yp);
+                    hby += (Dk[r].z0 - z0_xp) + (Dk[r].x1 - Dn[r].x1);
+                    hbz += (Dk[r].x0 - x0_yp) + (Dk[r].y1 - y1_xp);
+                    d.Ha[0][f + wo] = hbx;
+                    d.Ha[1][f + wo] = hby;
+                    d.Ha[2][f + wo] = hbz;
+                }
+            }
+        }
+        sE[pb][w][0][lane] = Dn[0].z1;
+        sE[pb][w][1][lane] = Dn[0].x0;
+        for (int r = 0; r < R; ++r) {
+            Hbk[r][0] = Hbn[r][0];
+            Hbk[r][1] = Hbn[r][1];
+            Hbk[r][2] = Hbn[r][2];
+            dHyz_k[r] = dHyz[r];
+            dHxz_k[r] = dHxz[r];
+            Dk[r] = Dn[r];
+        }
+    }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_adj_fused(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
+                                                   int ndom, int kz, int rs, int ws, int fsr) {
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    int dom = find_domain(bs, ndom, b);
+    const DomDev<T>& d = doms[dom];
+    if (!d.grad) return;
+    Tile tl = fused_tile<T, R>(d, b - bs[dom], kz);
+    adj_fused_body<T, R>(d, tl, rs, ws, fsr);
+}
+
 // ============================================================ monitors
-// Sample one plane monitor into slot `slot` of its ring buffer
+// Sample one plane monitor (state set cs) into slot `slot` of its ring buffer
 // [block][ncomp][npts] (E at time n, H at n + 1/2; flux H averaged over
 // planes k and k-1).
 template <typename T>
-__global__ void k_sample(const DomDev<T>* __restrict__ doms, MonDev m, int p, int slot) {
+__global__ void k_sample(const DomDev<T>* __restrict__ doms, MonDev m, int cs, int slot) {
     const DomDev<T>& d = doms[m.dom];
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     int ni = m.i1 - m.i0, npts = ni * (m.j1 - m.j0);
     if (q >= npts) return;
     int i = m.i0 + q % ni, j = m.j0 + q / ni, k = m.k;
-    long long f = fidx(d, i, j, k);
+    long long f = fidx(d, i, j, k) + cs * d.fs;
     T* buf = (T*)m.samples + (long long)slot * m.ncomp * npts;
     if (m.kind == 1) {
-        T hxm = k > 0 ? d.H[p][0][f - d.plane] : T(0);
-        T hym = k > 0 ? d.H[p][1][f - d.plane] : T(0);
-        buf[q] = d.E[p][0][f];
-        buf[npts + q] = d.E[p][1][f];
-        buf[2 * npts + q] = T(0.5) * (d.H[p][0][f] + hxm);
-        buf[3 * npts + q] = T(0.5) * (d.H[p][1][f] + hym);
+        T hxm = k > 0 ? d.H[0][f - d.plane] : T(0);
+        T hym = k > 0 ? d.H[1][f - d.plane] : T(0);
+        buf[q] = d.E[0][f];
+        buf[npts + q] = d.E[1][f];
+        buf[2 * npts + q] = T(0.5) * (d.H[0][f] + hxm);
+        buf[3 * npts + q] = T(0.5) * (d.H[1][f] + hym);
     } else {
-        buf[q] = m.comp < 3 ? d.E[p][m.comp][f] : d.H[p][m.comp - 3][f];
+        buf[q] = m.comp < 3 ? d.E[m.comp][f] : d.H[m.comp - 3][f];
     }
 }
 
@@ -373,25 +701,25 @@ __global__ void k_dft(MonDev m, int n0, int count) {
 }
 
 template <typename T>
-__global__ void k_probe(const DomDev<T>* __restrict__ doms, MonDev m, int p, int n) {
+__global__ void k_probe(const DomDev<T>* __restrict__ doms, MonDev m, int cs, int n) {
     const DomDev<T>& d = doms[m.dom];
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        long long f = fidx(d, m.pi, m.pj, m.k);
-        m.trace[n] = (double)(m.comp < 3 ? d.E[p][m.comp][f] : d.H[p][m.comp - 3][f]);
+        long long f = fidx(d, m.pi, m.pj, m.k) + cs * d.fs;
+        m.trace[n] = (double)(m.comp < 3 ? d.E[m.comp][f] : d.H[m.comp - 3][f]);
     }
 }
 
-// Seeds dJ/du^n of one plane monitor into the cotangent state (set p):
+// Seeds dJ/du^n of one plane monitor into the cotangent state (set as_):
 // Re sum_f G_f exp(+i w t), t = n (E) or n + 1/2 (H).
 template <typename T>
-__global__ void k_seed(const DomDev<T>* __restrict__ doms, MonDev m, int p, int n) {
+__global__ void k_seed(const DomDev<T>* __restrict__ doms, MonDev m, int as_, int n) {
     const DomDev<T>& d = doms[m.dom];
     int npts = (m.i1 - m.i0) * (m.j1 - m.j0);
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npts) return;
     int ni = m.i1 - m.i0;
     int i = m.i0 + q % ni, j = m.j0 + q / ni, k = m.k;
-    long long f = fidx(d, i, j, k);
+    long long f = fidx(d, i, j, k) + as_ * d.as;
     for (int cq = 0; cq < m.ncomp; ++cq) {
         int comp = m.kind == 1 ? (cq < 2 ? cq : cq + 1) : m.comp;   // flux: Ex, Ey, Hx, Hy
         int ish = comp >= 3;
@@ -404,25 +732,25 @@ __global__ void k_seed(const DomDev<T>* __restrict__ doms, MonDev m, int p, int 
             s += g[0] * cs - g[1] * sn;
         }
         if (m.kind == 1 && ish) {
-            T* H = d.Ha[p][comp - 3];
+            T* H = d.Ha[comp - 3];
             H[f] += (T)(0.5 * s);
             if (k > 0) H[f - d.plane] += (T)(0.5 * s);
         } else if (ish) {
-            d.Ha[p][comp - 3][f] += (T)s;
+            d.Ha[comp - 3][f] += (T)s;
         } else {
-            d.Ea[p][comp][f] += (T)s;
+            d.Ea[comp][f] += (T)s;
         }
     }
 }
 
 template <typename T>
-__global__ void k_probe_seed(const DomDev<T>* __restrict__ doms, MonDev m, int p, int n) {
+__global__ void k_probe_seed(const DomDev<T>* __restrict__ doms, MonDev m, int as_, int n) {
     const DomDev<T>& d = doms[m.dom];
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        long long f = fidx(d, m.pi, m.pj, m.k);
+        long long f = fidx(d, m.pi, m.pj, m.k) + as_ * d.as;
         double g = m.cot[n - 1];
-        if (m.comp < 3) d.Ea[p][m.comp][f] += (T)g;
-        else d.Ha[p][m.comp - 3][f] += (T)g;
+        if (m.comp < 3) d.Ea[m.comp][f] += (T)g;
+        else d.Ha[m.comp - 3][f] += (T)g;
     }
 }
 
@@ -431,6 +759,12 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, long long n_words) {
     long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long stride = (long long)gridDim.x * blockDim.x;
     for (; q < n_words; q += stride) p[q] = 0u;
+}
+
+__global__ void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, long long n_words) {
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; q < n_words; q += stride) dst[q] = src[q];
 }
 
 // max |x| of an FP32 array into *out (as ordered bits; out pre-zeroed)
@@ -463,7 +797,7 @@ __global__ void k_unpack_bf16(const uint16_t* __restrict__ y, long long n, const
         x[q] = __uint_as_float(((uint32_t)y[q]) << 16) * s;
 }
 
-// 64-bit wrap-around sum of 32-bit words (slot checksum)
+// 64-bit wrap-around weighted sum of 32-bit words (slot checksum)
 __global__ void k_checksum(const uint32_t* __restrict__ w, long long n, unsigned long long* out) {
     unsigned long long s = 0;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
@@ -480,21 +814,39 @@ static inline int blocks_1d(long long n, int bs, int cap = 65536) {
 }
 
 template <typename T>
-void launch_fwd_split(const void* doms, const int* bs, int ndom, int nblocks, int kz, int p, int t, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwd_e<T>, dim3(nblocks), dim3(256), 0, s, (const DomDev<T>*)doms, bs, ndom, kz, p, t);
-    hipLaunchKernelGGL(k_fwd_h<T>, dim3(nblocks), dim3(256), 0, s, (const DomDev<T>*)doms, bs, ndom, kz, p);
+void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s) {
+    const DomDev<T>* dd = (const DomDev<T>*)doms;
+    if (c.kernel == 1) {
+        hipLaunchKernelGGL(k_fwd_e<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t);
+        hipLaunchKernelGGL(k_fwd_h<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
+        return;
+    }
+    switch (c.rows) {
+        case 2: hipLaunchKernelGGL((k_fwd_fused<T, 2>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t); break;
+        case 8: hipLaunchKernelGGL((k_fwd_fused<T, 8>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t); break;
+        default: hipLaunchKernelGGL((k_fwd_fused<T, 4>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t); break;
+    }
 }
 
 template <typename T>
-void launch_adj_split(const void* doms, const int* bs, int ndom, int nblocks, int kz, int p, int fp, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_ht<T>, dim3(nblocks), dim3(256), 0, s, (const DomDev<T>*)doms, bs, ndom, kz, p);
-    hipLaunchKernelGGL(k_adj_et<T>, dim3(nblocks), dim3(256), 0, s, (const DomDev<T>*)doms, bs, ndom, kz, p, fp);
+void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s) {
+    const DomDev<T>* dd = (const DomDev<T>*)doms;
+    if (c.kernel == 1) {
+        hipLaunchKernelGGL(k_adj_ht<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs);
+        hipLaunchKernelGGL(k_adj_et<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr);
+        return;
+    }
+    switch (c.rows) {
+        case 2: hipLaunchKernelGGL((k_adj_fused<T, 2>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr); break;
+        case 8: hipLaunchKernelGGL((k_adj_fused<T, 8>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr); break;
+        default: hipLaunchKernelGGL((k_adj_fused<T, 4>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr); break;
+    }
 }
 
 template <typename T>
-void launch_sample(const void* doms, const MonDev& m, int p, int slot, hipStream_t s) {
+void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s) {
     int npts = (m.i1 - m.i0) * (m.j1 - m.j0);
-    hipLaunchKernelGGL(k_sample<T>, dim3((npts + 255) / 256), dim3(256), 0, s, (const DomDev<T>*)doms, m, p, slot);
+    hipLaunchKernelGGL(k_sample<T>, dim3((npts + 255) / 256), dim3(256), 0, s, (const DomDev<T>*)doms, m, cs, slot);
 }
 
 template <typename T>
@@ -504,24 +856,31 @@ void launch_dft(const MonDev& m, int n0, int count, hipStream_t s) {
 }
 
 template <typename T>
-void launch_probe(const void* doms, const MonDev& m, int p, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_probe<T>, dim3(1), dim3(64), 0, s, (const DomDev<T>*)doms, m, p, n);
+void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe<T>, dim3(1), dim3(64), 0, s, (const DomDev<T>*)doms, m, cs, n);
 }
 
 template <typename T>
-void launch_seed(const void* doms, const MonDev& m, int p, int n, hipStream_t s) {
+void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t s) {
     if (m.kind == 0) {
-        hipLaunchKernelGGL(k_probe_seed<T>, dim3(1), dim3(64), 0, s, (const DomDev<T>*)doms, m, p, n);
+        hipLaunchKernelGGL(k_probe_seed<T>, dim3(1), dim3(64), 0, s, (const DomDev<T>*)doms, m, as_, n);
         return;
     }
     int npts = (m.i1 - m.i0) * (m.j1 - m.j0);
-    hipLaunchKernelGGL(k_seed<T>, dim3((npts + 255) / 256), dim3(256), 0, s, (const DomDev<T>*)doms, m, p, n);
+    hipLaunchKernelGGL(k_seed<T>, dim3((npts + 255) / 256), dim3(256), 0, s, (const DomDev<T>*)doms, m, as_, n);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
     long long nw = (long long)(bytes / 4);
     if (nw == 0) return;
     hipLaunchKernelGGL(k_fill_zero, dim3(blocks_1d(nw, 256, 8192)), dim3(256), 0, s, (uint32_t*)p, nw);
+}
+
+void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    long long nw = (long long)(bytes / 4);
+    if (nw == 0) return;
+    hipLaunchKernelGGL(k_copy_words, dim3(blocks_1d(nw, 256, 8192)), dim3(256), 0, s, (const uint32_t*)src,
+                       (uint32_t*)dst, nw);
 }
 
 void launch_maxabs_f32(const float* x, long long n, unsigned int* out, hipStream_t s) {
@@ -542,12 +901,19 @@ void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipSt
     hipLaunchKernelGGL(k_checksum, dim3(blocks_1d(nw, 256, 4096)), dim3(256), 0, s, (const uint32_t*)p, nw, out);
 }
 
-#define FDTD_INSTANTIATE(T)                                                                                      \
-    template void launch_fwd_split<T>(const void*, const int*, int, int, int, int, int, hipStream_t);            \
-    template void launch_adj_split<T>(const void*, const int*, int, int, int, int, int, hipStream_t);            \
-    template void launch_sample<T>(const void*, const MonDev&, int, int, hipStream_t);                           \
-    template void launch_dft<T>(const MonDev&, int, int, hipStream_t);                                           \
-    template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t);                            \
+int fused_blocks(int nx, int ny, int nz, int rows, int kz) {
+    int TYo = kWaves * rows - 2;
+    return ((nx + 61) / 62) * ((ny + TYo - 1) / TYo) * ((nz + kz - 1) / kz);
+}
+
+int split_blocks(int nx, int ny, int nz, int kz) { return ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + kz - 1) / kz); }
+
+#define FDTD_INSTANTIATE(T)                                                                   \
+    template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t);   \
+    template void launch_adj<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t);   \
+    template void launch_sample<T>(const void*, const MonDev&, int, int, hipStream_t);        \
+    template void launch_dft<T>(const MonDev&, int, int, hipStream_t);                        \
+    template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t);         \
     template void launch_seed<T>(const void*, const MonDev&, int, int, hipStream_t);
 FDTD_INSTANTIATE(float)
 FDTD_INSTANTIATE(double)

@@ -21,20 +21,32 @@ struct MonDev {
     double* trace;                    // probe samples [max_steps]
 };
 
+// One stepping launch over all domains: kernel 1 = split, 2 = fused; rows =
+// register-blocked rows per wave of the fused kernel; kz = z chunk; bs =
+// device prefix sums of blocks per domain (ndom + 1 entries).
+struct LaunchCfg {
+    int kernel, rows, kz, nblk, ndom;
+    const int* bs;
+};
+
 template <typename T>
-void launch_fwd_split(const void* doms, const int* bs, int ndom, int nblocks, int kz, int p, int t, hipStream_t s);
+void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s);
 template <typename T>
-void launch_adj_split(const void* doms, const int* bs, int ndom, int nblocks, int kz, int p, int fp, hipStream_t s);
+void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s);
 template <typename T>
-void launch_sample(const void* doms, const MonDev& m, int p, int slot, hipStream_t s);
+void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s);
 template <typename T>
 void launch_dft(const MonDev& m, int n0, int count, hipStream_t s);
 template <typename T>
-void launch_probe(const void* doms, const MonDev& m, int p, int n, hipStream_t s);
+void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t s);
 template <typename T>
-void launch_seed(const void* doms, const MonDev& m, int p, int n, hipStream_t s);
+void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t s);
+
+int fused_blocks(int nx, int ny, int nz, int rows, int kz);
+int split_blocks(int nx, int ny, int nz, int kz);
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 void launch_maxabs_f32(const float* x, long long n, unsigned int* out, hipStream_t s);
 void launch_pack_bf16(const float* x, long long n, const unsigned int* scale, uint16_t* y, hipStream_t s);
 void launch_unpack_bf16(const uint16_t* y, long long n, const unsigned int* scale, float* x, hipStream_t s);

@@ -83,7 +83,7 @@ struct DomHost {
 };
 
 struct StateArr {
-    void* p[2];
+    void* p;                                 // set-0 address
     size_t n;                                // elements
 };
 
@@ -109,6 +109,21 @@ struct Base {
     virtual int reset() = 0;
     virtual void steps(int* n, int* m) = 0;
     virtual double memory() = 0;
+    virtual int timing(int op, double* ms, long long* n) = 0;
+    virtual int poke_slot(int slot, size_t word, unsigned int value) = 0;
+};
+
+// Bump allocator over one arena of the pool; with assign=false it only sizes.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    bool assign = false;
+    template <typename P>
+    void take(P*& p, size_t bytes) {
+        off = align256(off);
+        if (assign) p = (P*)(base + off);
+        off += std::max<size_t>(bytes, 1);
+    }
 };
 
 template <typename T>
@@ -120,26 +135,36 @@ struct Handle : Base {
     std::vector<DomDev<T>> dd;
     DomDev<T>* d_doms = nullptr;
     int* d_bs = nullptr;
-    int nblk = 0, kz = 8;
+    LaunchCfg cfg{};
+    std::vector<int> bs_host;
+    // pool: [misc][forward sets x nsets][adjoint sets x 2][split scratch][bf16 slots]
     char* pool = nullptr;
-    size_t pool_bytes = 0;
-    char* ckpool = nullptr;
-    size_t slot_bytes = 0;
+    size_t pool_bytes = 0, misc_bytes = 0, fstride = 0, astride = 0, et_bytes = 0, bfslot = 0;
+    int nsets = 2;
+    char *fbase = nullptr, *abase = nullptr, *etbase = nullptr, *bfbase = nullptr;
     std::vector<Slot> slots;
     unsigned int* d_scales = nullptr;         // [n_ckpt][n_state] BF16 scales
     unsigned long long* d_sum = nullptr;      // checksum scratch
-    std::vector<StateArr> fwd, adj;           // state arrays (per set)
-    std::vector<std::pair<void*, size_t>> adj_flat;   // every adjoint/gradient buffer, for zeroing
-    int fp = 0, ap = 0, t = 0, m = -1;
+    std::vector<StateArr> fwd, adj;           // state arrays (set-0 addresses)
+    std::vector<std::pair<void*, size_t>> adj_flat;   // gradient accumulators, for zeroing
+    // physical forward sets: two working sets and one per full-precision slot
+    int wset[2] = {0, 1};
+    std::vector<int> slotset;
+    int cur = 0;                               // set holding the current forward state
+    int ap = 0, t = 0, m = -1;
     int dft_block = 32;
     bool bf16 = false;
+    // kernel timing
+    bool timing_on = false;
+    std::vector<hipEvent_t> evs;
+    size_t nev = 0;
 
     ~Handle() override {
-        if (!pool && !ckpool) return;   // nothing was allocated (e.g. refused at admission)
+        if (!pool) return;   // nothing was allocated (e.g. refused at admission)
         if (st) (void)hipStreamSynchronize(st);
         else (void)hipDeviceSynchronize();
-        if (pool) (void)hipFree(pool);
-        if (ckpool) (void)hipFree(ckpool);
+        for (auto e : evs) (void)hipEventDestroy(e);
+        (void)hipFree(pool);
     }
 
     int fail(int code, const std::string& msg) {
@@ -160,6 +185,106 @@ struct Handle : Base {
         return check(what);
     }
 
+    char* set_ptr(int q) { return fbase + (size_t)q * fstride; }
+
+    // ------------------------------------------------------------ layout
+    // Places every array in its arena.  Forward state arrays of all domains form
+    // one set (stride fstride), adjoint arrays one adjoint set (astride).
+    void layout(Arena& M, Arena& F, Arena& A, Arena& X) {
+        const bool asg = M.assign;
+        if (asg) {
+            fwd.clear();
+            adj.clear();
+            adj_flat.clear();
+        }
+        bfslot = 0;
+        size_t nstate = 0;
+        const size_t ts = sizeof(T);
+        for (int q = 0; q < ndom; ++q) {
+            DomHost& h = dh[q];
+            DomDev<T>& d = dd[q];
+            const fdtd_domain_desc& s = h.desc;
+            const int nx = s.n[0], ny = s.n[1], nz = s.n[2];
+            const bool g = s.grad != 0;
+            auto fst = [&](T*& p, size_t n) {
+                F.take(p, n * ts);
+                bfslot += align256(n * 2);
+                nstate++;
+                if (asg) fwd.push_back(StateArr{p, n});
+            };
+            auto ast = [&](T*& p, size_t n) {
+                A.take(p, n * ts);
+                if (asg) adj.push_back(StateArr{p, n});
+            };
+            for (int c = 0; c < 3; ++c) {
+                fst(d.E[c], h.nfield);
+                fst(d.H[c], h.nfield);
+            }
+            for (int a = 0; a < 3; ++a) M.take(d.tab[a], 6 * (size_t)s.n[a] * ts);
+            for (int a = 0; a < 3; ++a)
+                for (int side = 0; side < 2; ++side) {
+                    size_t L = (size_t)s.pml[2 * a + side];
+                    size_t ne = a == 0 ? L * ny * nz : (a == 1 ? L * nx * nz : L * nx * ny);
+                    for (int r = 0; r < 2; ++r) {
+                        if (!ne) continue;
+                        fst(d.psiE[a][side][r], ne);
+                        fst(d.psiH[a][side][r], ne);
+                        if (g) {
+                            ast(d.psiEa[a][side][r], ne);
+                            ast(d.psiHa[a][side][r], ne);
+                        }
+                    }
+                }
+            size_t ebox = 1;
+            for (int a = 0; a < 3; ++a) ebox *= (size_t)(d.ehi[a] - d.elo[a]);
+            if (ebox && s.eps) {
+                for (int c = 0; c < h.ncomp_eps; ++c) M.take(d.epsinv[c], ebox * ts);
+                if (asg)
+                    for (int c = h.ncomp_eps; c < 3; ++c) d.epsinv[c] = d.epsinv[0];
+            }
+            if (d.has_lor) {
+                size_t lbox = 1;
+                for (int a = 0; a < 3; ++a) lbox *= (size_t)(d.lhi[a] - d.llo[a]);
+                for (int w = 0; w < 3; ++w)
+                    for (int c = 0; c < 3; ++c) {
+                        fst(d.lor[w][c], lbox);
+                        if (g) ast(d.lora[w][c], lbox);
+                    }
+            }
+            for (int k = 0; k < s.n_sources; ++k)
+                M.take(d.src[k].wave, (size_t)std::max(1, s.sources[k].n_waveform) * ts);
+            if (g) {
+                for (int c = 0; c < 3; ++c) {
+                    ast(d.Ea[c], h.nfield);
+                    ast(d.Ha[c], h.nfield);
+                }
+                if (cfg.kernel == 1)
+                    for (int c = 0; c < 3; ++c) X.take(d.Et[c], h.nfield * ts);
+                for (int c = 0; c < h.gncomp; ++c) {
+                    size_t nb = std::max<size_t>(h.gelems, 1) * 8;
+                    M.take(d.gacc[c], nb);
+                    if (asg) adj_flat.push_back({d.gacc[c], nb});
+                }
+            }
+            for (auto& mh : h.mons) {
+                MonDev& md = mh.dev;
+                M.take(md.omega, std::max(1, md.nf) * 8);
+                if (md.kind == 0) {
+                    M.take(md.trace, std::max(1, opt.max_steps) * 8);
+                    M.take(md.cot, std::max(1, opt.max_steps) * 8);
+                } else {
+                    M.take(md.samples, (size_t)dft_block * md.ncomp * mh.npts * ts);
+                    M.take(md.acc, mh.acc_elems * 8);
+                    M.take(md.cot, mh.acc_elems * 8);
+                }
+            }
+        }
+        M.take(d_doms, sizeof(DomDev<T>) * ndom);
+        M.take(d_bs, sizeof(int) * (ndom + 1));
+        M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
+        M.take(d_sum, 8);
+    }
+
     // ------------------------------------------------------------ create
     int create(const fdtd_domain_desc* doms, int n, const fdtd_options* o) {
         opt = *o;
@@ -169,194 +294,78 @@ struct Handle : Base {
         bf16 = o->ckpt_storage == FDTD_BF16;
         if (bf16 && sizeof(T) != 4) return fail(FDTD_E_INVALID, "BF16 checkpoints need FP32 fields");
         if (o->n_ckpt < 0 || o->max_steps < 0) return fail(FDTD_E_INVALID, "negative n_ckpt or max_steps");
+        if (o->kernel < 0 || o->kernel > 2) return fail(FDTD_E_INVALID, "kernel selector");
+        if (o->tile_rows != 0 && o->tile_rows != 2 && o->tile_rows != 4 && o->tile_rows != 8)
+            return fail(FDTD_E_INVALID, "tile_rows must be 2, 4 or 8");
+        if (o->tile_kz < 0) return fail(FDTD_E_INVALID, "tile_kz");
+        cfg.kernel = o->kernel == FDTD_KERNEL_SPLIT ? 1 : 2;
+        cfg.rows = o->tile_rows ? o->tile_rows : 4;
+        cfg.kz = o->tile_kz ? o->tile_kz : (cfg.kernel == 1 ? 8 : 16);
+        cfg.ndom = n;
         dh.resize(n);
         dd.assign(n, DomDev<T>{});
         for (int q = 0; q < n; ++q) {
-            int rc = validate(doms[q], dh[q]);
+            int rc = validate(doms[q], dh[q], q);
             if (rc) return rc;
+            init_scalars(q);
         }
-        // ---- plan the pool (offsets stored as pointer values + 1, fixed up after allocation)
-        size_t off = 0;
-        auto take = [&](size_t bytes) -> size_t {
-            off = align256(off);
-            size_t at = off;
-            off += std::max<size_t>(bytes, 1);
-            return at + 1;
-        };
-        size_t ts = sizeof(T);
-        for (int q = 0; q < n; ++q) {
-            DomHost& h = dh[q];
-            DomDev<T>& d = dd[q];
-            const fdtd_domain_desc& s = h.desc;
-            int nx = s.n[0], ny = s.n[1], nz = s.n[2];
-            int align = 128 / (int)ts;
-            d.n[0] = nx;
-            d.n[1] = ny;
-            d.n[2] = nz;
-            d.pitch = (nx + align - 1) / align * align;
-            d.plane = (long long)d.pitch * ny;
-            h.nfield = (size_t)d.plane * nz;
-            d.S = (T)s.courant;
-            for (int st2 = 0; st2 < 2; ++st2)
-                for (int c = 0; c < 3; ++c) {
-                    d.E[st2][c] = (T*)take(h.nfield * ts);
-                    d.H[st2][c] = (T*)take(h.nfield * ts);
-                }
-            for (int a = 0; a < 3; ++a) {
-                d.L[a][0] = s.pml[2 * a];
-                d.L[a][1] = s.pml[2 * a + 1];
-                d.tab[a] = (const T*)take(6 * (size_t)s.n[a] * ts);
-            }
-            auto slab_elems = [&](int a, int side) -> size_t {
-                size_t L = (size_t)d.L[a][side];
-                if (a == 0) return L * ny * nz;
-                if (a == 1) return L * nx * nz;
-                return L * nx * ny;
-            };
-            bool g = s.grad != 0;
-            d.grad = g ? 1 : 0;
-            for (int st2 = 0; st2 < 2; ++st2)
-                for (int a = 0; a < 3; ++a)
-                    for (int side = 0; side < 2; ++side)
-                        for (int r = 0; r < 2; ++r) {
-                            size_t ne = slab_elems(a, side);
-                            d.psiE[st2][a][side][r] = ne ? (T*)take(ne * ts) : nullptr;
-                            d.psiH[st2][a][side][r] = ne ? (T*)take(ne * ts) : nullptr;
-                            d.psiEa[st2][a][side][r] = (ne && g) ? (T*)take(ne * ts) : nullptr;
-                            d.psiHa[st2][a][side][r] = (ne && g) ? (T*)take(ne * ts) : nullptr;
-                        }
-            d.eps_diag = s.eps_kind == FDTD_EPS_DIAG;
-            size_t ebox = 1;
-            for (int a = 0; a < 3; ++a) {
-                d.elo[a] = s.eps_lo[a];
-                d.ehi[a] = s.eps_hi[a];
-                ebox *= (size_t)(s.eps_hi[a] - s.eps_lo[a]);
-            }
-            d.epsinv_bg = (T)(1.0 / s.eps_bg);
-            if (ebox && s.eps) {
-                for (int c = 0; c < h.ncomp_eps; ++c) d.epsinv[c] = (const T*)take(ebox * ts);
-                for (int c = h.ncomp_eps; c < 3; ++c) d.epsinv[c] = d.epsinv[0];
-            } else {
-                for (int a = 0; a < 3; ++a) d.elo[a] = d.ehi[a] = 0;
-            }
-            d.has_lor = s.n_lorentz > 0;
-            if (d.has_lor) {
-                const fdtd_lorentz_desc& L = s.lorentz;
-                size_t lbox = 1;
-                for (int a = 0; a < 3; ++a) {
-                    d.llo[a] = L.lo[a];
-                    d.lhi[a] = L.hi[a];
-                    lbox *= (size_t)(L.hi[a] - L.lo[a]);
-                }
-                // trapezoidal ADE with W = dt J: W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1})
-                double qq = 1.0 + 0.5 * L.gamma_dt;
-                d.lal = (T)((2.0 - L.omega0_dt * L.omega0_dt) / qq);
-                d.lxi = (T)((0.5 * L.gamma_dt - 1.0) / qq);
-                d.lg = (T)(L.delta_eps * L.omega0_dt * L.omega0_dt / qq);
-                for (int st2 = 0; st2 < 2; ++st2)
-                    for (int w = 0; w < 3; ++w)
-                        for (int c = 0; c < 3; ++c) {
-                            d.lor[st2][w][c] = (T*)take(lbox * ts);
-                            d.lora[st2][w][c] = g ? (T*)take(lbox * ts) : nullptr;
-                        }
-            }
-            d.nsrc = s.n_sources;
-            for (int k = 0; k < s.n_sources; ++k) {
-                const fdtd_source_desc& sr = s.sources[k];
-                SrcDev<T>& sd = d.src[k];
-                sd.kind = sr.kind;
-                sd.comp = sr.comp;
-                sd.i = sr.pos[0];
-                sd.j = sr.pos[1];
-                sd.k = sr.pos[2];
-                sd.nwave = sr.n_waveform;
-                sd.wave = (const T*)take((size_t)std::max(1, sr.n_waveform) * ts);
-            }
-            if (g) {
-                for (int st2 = 0; st2 < 2; ++st2)
-                    for (int c = 0; c < 3; ++c) {
-                        d.Ea[st2][c] = (T*)take(h.nfield * ts);
-                        d.Ha[st2][c] = (T*)take(h.nfield * ts);
-                    }
-                for (int c = 0; c < 3; ++c) d.Et[c] = (T*)take(h.nfield * ts);
-                h.gelems = 1;
-                for (int a = 0; a < 3; ++a) {
-                    d.glo[a] = s.grad_lo[a];
-                    d.ghi[a] = s.grad_hi[a];
-                    h.gelems *= (size_t)(s.grad_hi[a] - s.grad_lo[a]);
-                }
-                h.gncomp = d.eps_diag ? 3 : 1;
-                for (int c = 0; c < h.gncomp; ++c) d.gacc[c] = (double*)take(std::max<size_t>(h.gelems, 1) * 8);
-            }
-            // monitors
-            for (size_t k = 0; k < h.mons.size(); ++k) {
-                MonHost& mh = h.mons[k];
-                MonDev& md = mh.dev;
-                md.omega = (const double*)take(std::max(1, md.nf) * 8);
-                if (md.kind == 0) {
-                    md.trace = (double*)take(std::max(1, o->max_steps) * 8);
-                    md.cot = (double*)take(std::max(1, o->max_steps) * 8);
-                } else {
-                    md.samples = (void*)take((size_t)dft_block * md.ncomp * mh.npts * ts);
-                    mh.acc_elems = (size_t)md.nf * md.ncomp * mh.npts * 2;
-                    md.acc = (double*)take(mh.acc_elems * 8);
-                    md.cot = (double*)take(mh.acc_elems * 8);
-                }
-            }
-        }
-        size_t doms_off = take(sizeof(DomDev<T>) * n);
-        // tile table of the split kernels: 64 x 4 columns, kz-plane chunks
-        kz = 8;
-        std::vector<int> bs(n + 1, 0);
-        for (int q = 0; q < n; ++q) {
-            const fdtd_domain_desc& s = dh[q].desc;
-            int nb = ((s.n[0] + 63) / 64) * ((s.n[1] + 3) / 4) * ((s.n[2] + kz - 1) / kz);
-            bs[q + 1] = bs[q] + nb;
-        }
-        nblk = bs[n];
-        size_t bs_off = take(sizeof(int) * (n + 1));
-        // count state arrays for the checkpoint layout
-        size_t nstate = 0;
-        slot_bytes = 0;
-        for (int q = 0; q < n; ++q) collect_state(q, nstate, slot_bytes, /*fill=*/false);
-        size_t scales_off = take(std::max<size_t>(1, (size_t)o->n_ckpt * nstate) * 4);
-        size_t sum_off = take(8);
-        pool_bytes = align256(off);
-        double total = (double)pool_bytes + (double)slot_bytes * o->n_ckpt;
+        nsets = 2 + (bf16 ? 0 : o->n_ckpt);
+        // ---- size the arenas
+        Arena M, F, A, X;
+        layout(M, F, A, X);
+        misc_bytes = align256(M.off);
+        fstride = align256(F.off);
+        astride = align256(A.off);
+        et_bytes = align256(X.off);
+        size_t bf_total = bf16 ? align256(bfslot) * o->n_ckpt : 0;
+        pool_bytes = misc_bytes + fstride * nsets + astride * 2 + et_bytes + bf_total;
         double budget = o->mem_budget_bytes;
         if (budget <= 0) {
             size_t fr = 0, tot = 0;
             if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(FDTD_E_DEVICE, "hipMemGetInfo failed");
             budget = (double)fr - 256.0 * 1024 * 1024;
         }
-        if (total > budget) {
+        if ((double)pool_bytes > budget) {
             char b[160];
-            snprintf(b, sizeof b, "device memory request %.3e B exceeds budget %.3e B", total, budget);
+            snprintf(b, sizeof b, "device memory request %.3e B exceeds budget %.3e B", (double)pool_bytes, budget);
             return fail(FDTD_E_NOMEM, b);
         }
         if (hipMalloc((void**)&pool, pool_bytes) != hipSuccess) {
             (void)hipGetLastError();
             pool = nullptr;
-            return fail(FDTD_E_NOMEM, "hipMalloc of the state pool failed");
+            return fail(FDTD_E_NOMEM, "hipMalloc of the device pool failed");
         }
-        if (o->n_ckpt > 0 && slot_bytes > 0) {
-            if (hipMalloc((void**)&ckpool, slot_bytes * o->n_ckpt) != hipSuccess) {
-                (void)hipGetLastError();
-                ckpool = nullptr;
-                return fail(FDTD_E_NOMEM, "hipMalloc of the checkpoint slots failed");
-            }
+        fbase = pool + misc_bytes;
+        abase = fbase + fstride * nsets;
+        etbase = abase + astride * 2;
+        bfbase = etbase + et_bytes;
+        Arena M2, F2, A2, X2;
+        M2.base = pool;
+        F2.base = fbase;
+        A2.base = abase;
+        X2.base = etbase;
+        M2.assign = F2.assign = A2.assign = X2.assign = true;
+        layout(M2, F2, A2, X2);
+        for (int q = 0; q < n; ++q) {
+            dd[q].fs = (long long)(fstride / sizeof(T));
+            dd[q].as = (long long)(astride / sizeof(T));
         }
         slots.assign(o->n_ckpt, Slot{});
-        // ---- fix up pointers
-        for (int q = 0; q < n; ++q) fixup(dd[q], dh[q]);
-        d_doms = (DomDev<T>*)(pool + doms_off - 1);
-        d_bs = (int*)(pool + bs_off - 1);
-        d_scales = (unsigned int*)(pool + scales_off - 1);
-        d_sum = (unsigned long long*)(pool + sum_off - 1);
-        fwd.clear();
-        adj.clear();
-        size_t dummy_n = 0, dummy_b = 0;
-        for (int q = 0; q < n; ++q) collect_state(q, dummy_n, dummy_b, /*fill=*/true);
+        slotset.resize(o->n_ckpt);
+        for (int k = 0; k < o->n_ckpt; ++k) slotset[k] = bf16 ? -1 : 2 + k;
+        wset[0] = 0;
+        wset[1] = 1;
+        cur = 0;
+        // tile table
+        bs_host.assign(n + 1, 0);
+        for (int q = 0; q < n; ++q) {
+            const fdtd_domain_desc& s = dh[q].desc;
+            int nb = cfg.kernel == 1 ? split_blocks(s.n[0], s.n[1], s.n[2], cfg.kz)
+                                     : fused_blocks(s.n[0], s.n[1], s.n[2], cfg.rows, cfg.kz);
+            bs_host[q + 1] = bs_host[q] + nb;
+        }
+        cfg.nblk = bs_host[n];
+        cfg.bs = d_bs;
         // ---- initialise: zero everything, upload tables and inputs
         launch_zero(pool, pool_bytes, st);
         int rc = check("zero pool");
@@ -389,9 +398,73 @@ struct Handle : Base {
             }
         }
         if (hipMemcpyAsync(d_doms, dd.data(), sizeof(DomDev<T>) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(d_bs, bs.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+            hipMemcpyAsync(d_bs, bs_host.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
             return fail(FDTD_E_DEVICE, "upload descriptors failed");
         return sync("create");
+    }
+
+    // scalar (non-pointer) fields of the device descriptor
+    void init_scalars(int q) {
+        DomHost& h = dh[q];
+        DomDev<T>& d = dd[q];
+        const fdtd_domain_desc& s = h.desc;
+        const int align = 128 / (int)sizeof(T);
+        for (int a = 0; a < 3; ++a) d.n[a] = s.n[a];
+        d.pitch = (s.n[0] + align - 1) / align * align;
+        d.plane = (long long)d.pitch * s.n[1];
+        h.nfield = (size_t)d.plane * s.n[2];
+        d.S = (T)s.courant;
+        for (int a = 0; a < 3; ++a) {
+            d.L[a][0] = s.pml[2 * a];
+            d.L[a][1] = s.pml[2 * a + 1];
+        }
+        d.eps_diag = s.eps_kind == FDTD_EPS_DIAG;
+        size_t ebox = 1;
+        for (int a = 0; a < 3; ++a) {
+            d.elo[a] = s.eps_lo[a];
+            d.ehi[a] = s.eps_hi[a];
+            ebox *= (size_t)(s.eps_hi[a] - s.eps_lo[a]);
+        }
+        if (!(ebox && s.eps))
+            for (int a = 0; a < 3; ++a) d.elo[a] = d.ehi[a] = 0;
+        d.epsinv_bg = (T)(1.0 / s.eps_bg);
+        d.has_lor = s.n_lorentz > 0;
+        if (d.has_lor) {
+            const fdtd_lorentz_desc& L = s.lorentz;
+            for (int a = 0; a < 3; ++a) {
+                d.llo[a] = L.lo[a];
+                d.lhi[a] = L.hi[a];
+            }
+            // trapezoidal ADE with W = dt J: W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1})
+            double qq = 1.0 + 0.5 * L.gamma_dt;
+            d.lal = (T)((2.0 - L.omega0_dt * L.omega0_dt) / qq);
+            d.lxi = (T)((0.5 * L.gamma_dt - 1.0) / qq);
+            d.lg = (T)(L.delta_eps * L.omega0_dt * L.omega0_dt / qq);
+        }
+        d.nsrc = s.n_sources;
+        for (int k = 0; k < s.n_sources; ++k) {
+            const fdtd_source_desc& sr = s.sources[k];
+            SrcDev<T>& sd = d.src[k];
+            sd.kind = sr.kind;
+            sd.comp = sr.comp;
+            sd.i = sr.pos[0];
+            sd.j = sr.pos[1];
+            sd.k = sr.pos[2];
+            sd.nwave = sr.n_waveform;
+        }
+        d.grad = s.grad ? 1 : 0;
+        if (s.grad) {
+            h.gelems = 1;
+            for (int a = 0; a < 3; ++a) {
+                d.glo[a] = s.grad_lo[a];
+                d.ghi[a] = s.grad_hi[a];
+                h.gelems *= (size_t)(s.grad_hi[a] - s.grad_lo[a]);
+            }
+            h.gncomp = d.eps_diag ? 3 : 1;
+        }
+        for (auto& mh : h.mons) {
+            if (mh.dev.kind != 0) mh.acc_elems = (size_t)mh.dev.nf * mh.dev.ncomp * mh.npts * 2;
+        }
     }
 
     int upload_eps(int q) {
@@ -411,104 +484,8 @@ struct Handle : Base {
         return FDTD_OK;
     }
 
-    template <typename P>
-    void fix(P*& p) {
-        if (p) p = (P*)(pool + (uintptr_t)p - 1);
-    }
-
-    void fixup(DomDev<T>& d, DomHost& h) {
-        for (int s = 0; s < 2; ++s)
-            for (int c = 0; c < 3; ++c) {
-                fix(d.E[s][c]);
-                fix(d.H[s][c]);
-                fix(d.Ea[s][c]);
-                fix(d.Ha[s][c]);
-            }
-        for (int c = 0; c < 3; ++c) fix(d.Et[c]);
-        for (int a = 0; a < 3; ++a) fix(d.tab[a]);
-        for (int s = 0; s < 2; ++s)
-            for (int a = 0; a < 3; ++a)
-                for (int side = 0; side < 2; ++side)
-                    for (int r = 0; r < 2; ++r) {
-                        fix(d.psiE[s][a][side][r]);
-                        fix(d.psiH[s][a][side][r]);
-                        fix(d.psiEa[s][a][side][r]);
-                        fix(d.psiHa[s][a][side][r]);
-                    }
-        // isotropic eps: the three component pointers alias one array
-        const T* e0 = d.epsinv[0];
-        fix(d.epsinv[0]);
-        for (int c = 1; c < 3; ++c) {
-            if (d.epsinv[c] == e0) d.epsinv[c] = d.epsinv[0];
-            else fix(d.epsinv[c]);
-        }
-        for (int s = 0; s < 2; ++s)
-            for (int w = 0; w < 3; ++w)
-                for (int c = 0; c < 3; ++c) {
-                    fix(d.lor[s][w][c]);
-                    fix(d.lora[s][w][c]);
-                }
-        for (int k = 0; k < d.nsrc; ++k) fix(d.src[k].wave);
-        for (int c = 0; c < 3; ++c) fix(d.gacc[c]);
-        for (auto& mh : h.mons) {
-            fix(mh.dev.omega);
-            fix(mh.dev.trace);
-            fix(mh.dev.cot);
-            fix(mh.dev.samples);
-            fix(mh.dev.acc);
-        }
-    }
-
-    // state arrays of domain q: forward (checkpointed) and adjoint (zeroed at begin)
-    void collect_state(int q, size_t& nstate, size_t& bytes, bool fill) {
-        DomDev<T>& d = dd[q];
-        DomHost& h = dh[q];
-        size_t es = bf16 ? 2 : sizeof(T);
-        auto addf = [&](void* a, void* b, size_t ne) {
-            if (!a) return;
-            nstate++;
-            bytes += align256(ne * es);
-            if (fill) fwd.push_back(StateArr{{a, b}, ne});
-        };
-        auto adda = [&](void* a, void* b, size_t ne) {
-            if (!a || !fill) return;
-            adj.push_back(StateArr{{a, b}, ne});
-        };
-        const fdtd_domain_desc& s = h.desc;
-        int nx = s.n[0], ny = s.n[1], nz = s.n[2];
-        for (int c = 0; c < 3; ++c) {
-            addf(d.E[0][c], d.E[1][c], h.nfield);
-            addf(d.H[0][c], d.H[1][c], h.nfield);
-            adda(d.Ea[0][c], d.Ea[1][c], h.nfield);
-            adda(d.Ha[0][c], d.Ha[1][c], h.nfield);
-            adda(d.Et[c], d.Et[c], h.nfield);
-        }
-        for (int a = 0; a < 3; ++a)
-            for (int side = 0; side < 2; ++side) {
-                size_t L = (size_t)d.L[a][side];
-                size_t ne = a == 0 ? L * ny * nz : (a == 1 ? L * nx * nz : L * nx * ny);
-                for (int r = 0; r < 2; ++r) {
-                    addf(d.psiE[0][a][side][r], d.psiE[1][a][side][r], ne);
-                    addf(d.psiH[0][a][side][r], d.psiH[1][a][side][r], ne);
-                    adda(d.psiEa[0][a][side][r], d.psiEa[1][a][side][r], ne);
-                    adda(d.psiHa[0][a][side][r], d.psiHa[1][a][side][r], ne);
-                }
-            }
-        if (d.has_lor) {
-            size_t lbox = 1;
-            for (int a = 0; a < 3; ++a) lbox *= (size_t)(d.lhi[a] - d.llo[a]);
-            for (int w = 0; w < 3; ++w)
-                for (int c = 0; c < 3; ++c) {
-                    addf(d.lor[0][w][c], d.lor[1][w][c], lbox);
-                    adda(d.lora[0][w][c], d.lora[1][w][c], lbox);
-                }
-        }
-        if (fill && d.grad)
-            for (int c = 0; c < h.gncomp; ++c) adj_flat.push_back({d.gacc[c], std::max<size_t>(h.gelems, 1) * 8});
-    }
-
     // ------------------------------------------------------------ validation
-    int validate(const fdtd_domain_desc& s, DomHost& h) {
+    int validate(const fdtd_domain_desc& s, DomHost& h, int dom_index) {
         h.desc = s;
         for (int a = 0; a < 3; ++a)
             if (s.n[a] < 1 || s.n[a] > (1 << 20)) return fail(FDTD_E_INVALID, "grid size out of range");
@@ -583,7 +560,6 @@ struct Handle : Base {
         }
         if (s.n_monitors < 0 || s.n_monitors > FDTD_MAX_MONITORS) return fail(FDTD_E_INVALID, "too many monitors");
         h.mons.resize(s.n_monitors);
-        int dom_index = (int)(&h - dh.data());
         for (int k = 0; k < s.n_monitors; ++k) {
             const fdtd_monitor_desc& md = s.monitors[k];
             MonHost& mh = h.mons[k];
@@ -633,25 +609,42 @@ struct Handle : Base {
     }
 
     void record() {
-        int n = t;   // the state now holds E^n, H^{n+1/2}
+        int n = t;   // the current set holds E^n, H^{n+1/2}
         for (auto& h : dh)
             for (auto& mh : h.mons) {
                 if (mh.dev.kind == 0) {
-                    if (n - 1 < opt.max_steps) launch_probe<T>(d_doms, mh.dev, fp, n - 1, st);
+                    if (n - 1 < opt.max_steps) launch_probe<T>(d_doms, mh.dev, cur, n - 1, st);
                     continue;
                 }
                 if (mh.pending == 0) mh.n0 = n;
-                launch_sample<T>(d_doms, mh.dev, fp, mh.pending, st);
+                launch_sample<T>(d_doms, mh.dev, cur, mh.pending, st);
                 if (++mh.pending == dft_block) flush(mh);
             }
     }
+
+    void ev_mark() {
+        if (nev == evs.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                return;
+            }
+            evs.push_back(e);
+        }
+        (void)hipEventRecord(evs[nev++], st);
+    }
+
+    int write_set() const { return wset[0] != cur ? wset[0] : wset[1]; }
 
     int step_forward(int n, unsigned flags) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
         bool rec = (flags & FDTD_RECORD) && !(flags & FDTD_REPLAY);
         for (int s = 0; s < n; ++s) {
-            launch_fwd_split<T>(d_doms, d_bs, ndom, nblk, kz, fp, t, st);
-            fp ^= 1;
+            int ws = write_set();
+            if (timing_on) ev_mark();
+            launch_fwd<T>(cfg, d_doms, cur, ws, t, st);
+            if (timing_on) ev_mark();
+            cur = ws;
             ++t;
             if (rec) record();
         }
@@ -672,8 +665,7 @@ struct Handle : Base {
 
     int adjoint_begin(int n) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative n_total");
-        for (auto& a : adj)
-            for (int s = 0; s < 2; ++s) launch_zero(a.p[s], a.n * sizeof(T), st);
+        if (astride) launch_zero(abase, astride * 2, st);
         for (auto& a : adj_flat) launch_zero(a.first, a.second, st);
         ap = 0;
         m = n;
@@ -690,7 +682,9 @@ struct Handle : Base {
                 snprintf(b, sizeof b, "adjoint step %d needs forward state u^%d, forward is at %d", m, m - 1, t);
                 return fail(FDTD_E_STATE, b);
             }
-            launch_adj_split<T>(d_doms, d_bs, ndom, nblk, kz, ap, fp, st);
+            if (timing_on) ev_mark();
+            launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st);
+            if (timing_on) ev_mark();
             ap ^= 1;
             --m;
             if (m >= 1) {
@@ -701,24 +695,55 @@ struct Handle : Base {
         return check("step_adjoint");
     }
 
+    int timing(int op, double* ms, long long* cnt) override {
+        if (op == 1 || op == 0) {
+            if (sync("timing")) return FDTD_E_DEVICE;
+            timing_on = op == 1;
+            nev = 0;
+            return FDTD_OK;
+        }
+        if (op != 2) return fail(FDTD_E_INVALID, "timing op");
+        int rc = sync("timing");
+        if (rc) return rc;
+        double tot = 0;
+        for (size_t q = 0; q + 1 < nev; q += 2) {
+            float e = 0;
+            if (hipEventElapsedTime(&e, evs[q], evs[q + 1]) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(FDTD_E_DEVICE, "hipEventElapsedTime failed");
+            }
+            tot += e;
+        }
+        if (ms) *ms = tot;
+        if (cnt) *cnt = (long long)(nev / 2);
+        return FDTD_OK;
+    }
+
     // ------------------------------------------------------------ checkpoints
+    // Full-precision slots are forward state sets.  Saving hands the current
+    // working set to the slot and takes the slot's old set as the new working
+    // set (no copy); restoring points the next step at the slot's set (no copy).
     int ckpt_save(int slot) override {
         if (slot < 0 || slot >= (int)slots.size()) return fail(FDTD_E_RANGE, "checkpoint slot");
-        char* base = ckpool + (size_t)slot * slot_bytes;
-        size_t off = 0;
-        for (size_t q = 0; q < fwd.size(); ++q) {
-            StateArr& a = fwd[q];
-            if (bf16) {
+        if (bf16) {
+            char* base = bfbase + (size_t)slot * align256(bfslot);
+            size_t off = 0;
+            for (size_t q = 0; q < fwd.size(); ++q) {
+                StateArr& a = fwd[q];
+                const float* src = (const float*)((char*)a.p + (size_t)cur * fstride);
                 unsigned int* sc = d_scales + (size_t)slot * fwd.size() + q;
                 launch_zero(sc, 4, st);
-                launch_maxabs_f32((const float*)a.p[fp], (long long)a.n, sc, st);
-                launch_pack_bf16((const float*)a.p[fp], (long long)a.n, sc, (uint16_t*)(base + off), st);
+                launch_maxabs_f32(src, (long long)a.n, sc, st);
+                launch_pack_bf16(src, (long long)a.n, sc, (uint16_t*)(base + off), st);
                 off += align256(a.n * 2);
-            } else {
-                if (hipMemcpyAsync(base + off, a.p[fp], a.n * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
-                    return fail(FDTD_E_DEVICE, "checkpoint copy failed");
-                off += align256(a.n * sizeof(T));
             }
+        } else if (cur == wset[0] || cur == wset[1]) {
+            int wi = cur == wset[0] ? 0 : 1;
+            int old = slotset[slot];
+            slotset[slot] = cur;
+            wset[wi] = old;
+        } else if (cur != slotset[slot]) {
+            launch_copy(set_ptr(cur), set_ptr(slotset[slot]), fstride, st);
         }
         slots[slot].valid = true;
         slots[slot].step = t;
@@ -731,7 +756,8 @@ struct Handle : Base {
 
     int slot_sum(int slot, unsigned long long* out) {
         launch_zero(d_sum, 8, st);
-        launch_checksum(ckpool + (size_t)slot * slot_bytes, slot_bytes, d_sum, st);
+        if (bf16) launch_checksum(bfbase + (size_t)slot * align256(bfslot), bfslot, d_sum, st);
+        else launch_checksum(set_ptr(slotset[slot]), fstride, d_sum, st);
         if (hipMemcpyAsync(out, d_sum, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
             return fail(FDTD_E_DEVICE, "checksum copy failed");
         return sync("checksum");
@@ -746,22 +772,34 @@ struct Handle : Base {
             if (rc) return rc;
             if (s2 != slots[slot].sum) return fail(FDTD_E_STATE, "checkpoint checksum mismatch");
         }
-        char* base = ckpool + (size_t)slot * slot_bytes;
-        size_t off = 0;
-        for (size_t q = 0; q < fwd.size(); ++q) {
-            StateArr& a = fwd[q];
-            if (bf16) {
+        if (bf16) {
+            int ws = write_set();
+            char* base = bfbase + (size_t)slot * align256(bfslot);
+            size_t off = 0;
+            for (size_t q = 0; q < fwd.size(); ++q) {
+                StateArr& a = fwd[q];
                 const unsigned int* sc = d_scales + (size_t)slot * fwd.size() + q;
-                launch_unpack_bf16((const uint16_t*)(base + off), (long long)a.n, sc, (float*)a.p[fp], st);
+                launch_unpack_bf16((const uint16_t*)(base + off), (long long)a.n, sc,
+                                   (float*)((char*)a.p + (size_t)ws * fstride), st);
                 off += align256(a.n * 2);
-            } else {
-                if (hipMemcpyAsync(a.p[fp], base + off, a.n * sizeof(T), hipMemcpyDeviceToDevice, st) != hipSuccess)
-                    return fail(FDTD_E_DEVICE, "checkpoint restore copy failed");
-                off += align256(a.n * sizeof(T));
             }
+            cur = ws;
+        } else {
+            cur = slotset[slot];
         }
         t = slots[slot].step;
         return check("checkpoint_restore");
+    }
+
+    // Corrupt one word of a slot (failure-path tests of checksum validation).
+    int poke_slot(int slot, size_t word, unsigned int value) override {
+        if (slot < 0 || slot >= (int)slots.size()) return fail(FDTD_E_RANGE, "checkpoint slot");
+        char* base = bf16 ? bfbase + (size_t)slot * align256(bfslot) : set_ptr(slotset[slot]);
+        size_t bytes = bf16 ? bfslot : fstride;
+        if ((word + 1) * 4 > bytes) return fail(FDTD_E_RANGE, "word index");
+        if (hipMemcpyAsync(base + word * 4, &value, 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            return fail(FDTD_E_DEVICE, "poke failed");
+        return sync("poke");
     }
 
     // ------------------------------------------------------------ monitors
@@ -841,8 +879,14 @@ struct Handle : Base {
         bool adjc = comp >= 6;
         int c = comp % 6;
         if (adjc && !d.grad) return fail(FDTD_E_RANGE, "domain has no adjoint state");
-        int sset = adjc ? ap : fp;
-        T* p = adjc ? (c < 3 ? d.Ea[sset][c] : d.Ha[sset][c - 3]) : (c < 3 ? d.E[sset][c] : d.H[sset][c - 3]);
+        if (set && !adjc && cur != wset[0] && cur != wset[1]) {
+            // never write into a checkpoint slot: continue from a working copy
+            int ws = write_set();
+            launch_copy(set_ptr(cur), set_ptr(ws), fstride, st);
+            cur = ws;
+        }
+        T* p = adjc ? (c < 3 ? d.Ea[c] : d.Ha[c - 3]) + (size_t)ap * d.as
+                    : (c < 3 ? d.E[c] : d.H[c - 3]) + (size_t)cur * d.fs;
         size_t nx = d.n[0], ny = d.n[1], nz = d.n[2];
         if (bytes < nx * ny * nz * sizeof(T)) return fail(FDTD_E_RANGE, "buffer too small for field");
         hipError_t e;
@@ -902,15 +946,15 @@ struct Handle : Base {
     }
 
     int reset() override {
-        for (auto& a : fwd)
-            for (int s = 0; s < 2; ++s) launch_zero(a.p[s], a.n * sizeof(T), st);
+        cur = wset[0];
+        launch_zero(set_ptr(cur), fstride, st);
+        for (auto& sl : slots) sl.valid = false;
         for (auto& h : dh)
             for (auto& mh : h.mons) {
                 if (mh.dev.kind == 0) launch_zero(mh.dev.trace, std::max(1, opt.max_steps) * 8, st);
                 else launch_zero(mh.dev.acc, mh.acc_elems * 8, st);
                 mh.pending = 0;
             }
-        fp = 0;
         t = 0;
         m = -1;
         return sync("reset");
@@ -921,7 +965,7 @@ struct Handle : Base {
         if (mm) *mm = m;
     }
 
-    double memory() override { return (double)pool_bytes + (double)slot_bytes * slots.size(); }
+    double memory() override { return (double)pool_bytes; }
 };
 
 int guard(fdtd_t h);
@@ -1052,6 +1096,19 @@ int fdtd_get_memory(fdtd_t h, double* bytes) {
     GUARD(h);
     if (bytes) *bytes = h->impl->memory();
     return FDTD_OK;
+}
+
+int fdtd_checkpoint_corrupt(fdtd_t h, int32_t slot, size_t word, uint32_t value) {
+    GUARD(h);
+    return h->impl->poke_slot(slot, word, value);
+}
+
+int fdtd_kernel_timing(fdtd_t h, int32_t op, double* total_ms, int64_t* launches) {
+    GUARD(h);
+    long long n = 0;
+    int rc = h->impl->timing(op, total_ms, &n);
+    if (launches) *launches = n;
+    return rc;
 }
 
 const char* fdtd_last_error(fdtd_t h) {

@@ -14,7 +14,7 @@ class Simulation:
     def __init__(self, specs, dtype: str = "f32", n_ckpt: int = 0, ckpt_storage: Optional[str] = None,
                  ckpt_checksum: bool = False, max_steps: Optional[int] = None, kernel: str = "auto",
                  dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
-                 mem_budget_bytes: float = 0.0):
+                 mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0):
         if not isinstance(specs, (list, tuple)):
             specs = [specs]
         self.specs = list(specs)
@@ -26,7 +26,7 @@ class Simulation:
             max_steps = max(max(s.n_steps for s in self.specs), 1)
         self.max_steps = max_steps
         self.h = B.fdtd_create(self.specs, dt, n_ckpt, storage, ckpt_checksum, max_steps, kern, dft_block,
-                               graph_chunk, stream, mem_budget_bytes)
+                               graph_chunk, stream, mem_budget_bytes, tile_rows, tile_kz)
 
     def close(self):
         if self.h is not None:
@@ -123,6 +123,10 @@ class Simulation:
 
     def set_eps(self, eps: np.ndarray, domain: int = 0):
         B.fdtd_set_eps(self.h, domain, eps)
+
+    def timing(self, op: int):
+        """1: enable and clear, 0: disable, 2: (total kernel ms, launches)."""
+        return B.fdtd_kernel_timing(self.h, op)
 
     def memory_bytes(self) -> float:
         return B.fdtd_get_memory(self.h)

@@ -1,0 +1,182 @@
+"""Engine properties on the GPU that need no oracle: bitwise invariance of the
+results under kernel family, tile shape, checkpoint schedule and batching
+(every node is computed by the same arithmetic whatever the launch), exact
+replay from checkpoints, and the failure paths of the slots."""
+import numpy as np
+import pytest
+
+from paper_2609_30039_amd import binding as B
+from paper_2609_30039_amd import workloads as W
+from paper_2609_30039_amd import adjoint as A
+from paper_2609_30039_amd.sim import Simulation
+from tests.gpu_util import patch_objective, flux_objective, gpu_gradient_store_all
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n_steps=160):
+    spec = W.lorentz_flux(pml=6, lorentz=10, n_steps=n_steps, n_f=6, shape=(133, 37, 45))
+    nx, ny, nz = spec.shape
+    spec.monitors.append(W.MonitorSpec("patch_z", comp=2, pos=(0, 0, nz - 12), rect=(20, 90, 5, 30),
+                                       omega_dt=W.freq_grid(4)))
+    spec.grad_box = ((6, 6, 6), (nx - 6, ny - 6, nz - 6))
+    return spec
+
+
+def _fields(sim):
+    return [sim.field(q) for q in range(6)]
+
+
+def _cot(mi, m, sp):
+    if m.kind == "patch_z":
+        return patch_objective(sp)[1]
+    if m.kind == "flux_z":
+        return flux_objective(sp)[1]
+    return 2.0 * np.asarray(sp)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_equals_split_forward(dtype):
+    spec = _case()
+    runs = []
+    for kern, rows, kz in (("split", 0, 0), ("fused", 4, 16), ("fused", 2, 7), ("fused", 8, 32)):
+        sim = Simulation(spec, dtype=dtype, kernel=kern, tile_rows=rows, tile_kz=kz)
+        sim.step(spec.n_steps)
+        runs.append((_fields(sim), sim.spectra(0), sim.spectra(1)))
+    for other in runs[1:]:
+        for q in range(6):
+            assert np.array_equal(runs[0][0][q], other[0][q]), W.COMP_NAMES[q]
+        assert np.array_equal(runs[0][1], other[1])
+        assert np.array_equal(runs[0][2], other[2])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_equals_split_adjoint(dtype):
+    spec = _case(n_steps=60)
+    g = {}
+    for kern in ("split", "fused"):
+        N = spec.n_steps
+        sim = Simulation(spec, dtype=dtype, kernel=kern, n_ckpt=N + 1)
+        sim.save(0)
+        for t in range(N):
+            sim.step(1)
+            sim.save(t + 1)
+        for mi, m in enumerate(spec.monitors):
+            sim.set_cotangent(mi, _cot(mi, m, sim.spectra(mi)))
+        sim.adjoint_begin(N)
+        for m_ in range(N, 0, -1):
+            sim.restore(m_ - 1)
+            sim.step_adjoint(1)
+        g[kern] = (sim.grad(), [sim.field(q, adjoint=True) for q in range(6)])
+    assert np.array_equal(g["split"][0], g["fused"][0])
+    for q in range(6):
+        assert np.array_equal(g["split"][1][q], g["fused"][1][q])
+
+
+@pytest.mark.parametrize("slots", [2, 5, 16])
+def test_revolve_gradient_is_schedule_independent(slots):
+    """Binomial replay gives the bitwise gradient of storing every state."""
+    spec = _case(n_steps=64)
+    N = spec.n_steps
+    _, g_all, _ = gpu_gradient_store_all(spec, "f32", _cot)
+    sim = Simulation(spec, dtype="f32", n_ckpt=slots)
+    cot = lambda s: {(0, mi): _cot(mi, m, s.spectra(mi)) for mi, m in enumerate(spec.monitors)}
+    g = A.gradient(sim, N, slots, cot)[0]
+    assert np.array_equal(g, g_all)
+
+
+def test_checkpoint_replay_is_exact():
+    spec = _case(n_steps=120)
+    sim = Simulation(spec, dtype="f32", n_ckpt=2)
+    sim.step(50)
+    sim.save(1)
+    sim.step(70)
+    ref = _fields(sim)
+    sim.restore(1)
+    assert sim.steps[0] == 50
+    sim.step(70, record=False)
+    for a, b in zip(ref, _fields(sim)):
+        assert np.array_equal(a, b)
+    # the slot survives stepping from it: restore again, replay again
+    sim.restore(1)
+    sim.step(70, record=False)
+    for a, b in zip(ref, _fields(sim)):
+        assert np.array_equal(a, b)
+
+
+def test_bf16_checkpoints_report_error():
+    """BF16 snapshots perturb the replayed trajectory (~2^-9); the gradient
+    stays within a few percent (reported, not a parity claim)."""
+    spec = _case(n_steps=64)
+    cot = lambda s: {(0, mi): _cot(mi, m, s.spectra(mi)) for mi, m in enumerate(spec.monitors)}
+    g32 = A.gradient(Simulation(spec, dtype="f32", n_ckpt=6), 64, 6, cot)[0]
+    g16 = A.gradient(Simulation(spec, dtype="f32", n_ckpt=6, ckpt_storage="bf16"), 64, 6, cot)[0]
+    err = np.linalg.norm(g16 - g32) / np.linalg.norm(g32)
+    assert 0 < err < 5e-2, err
+
+
+def test_checksum_detects_corruption_and_empty_slot():
+    spec = _case(n_steps=20)
+    sim = Simulation(spec, dtype="f32", n_ckpt=3, ckpt_checksum=True)
+    with pytest.raises(B.FdtdError) as e:
+        sim.restore(2)
+    assert e.value.code == B.FDTD_E_STATE
+    sim.step(10)
+    sim.save(1)
+    sim.step(5)
+    sim.restore(1)                 # intact: accepted
+    B.fdtd_checkpoint_corrupt(sim.h, 1, 1000, 0x3f800000)
+    with pytest.raises(B.FdtdError) as e:
+        sim.restore(1)
+    assert e.value.code == B.FDTD_E_STATE
+
+
+def test_adjoint_step_index_checked():
+    spec = _case(n_steps=10)
+    sim = Simulation(spec, dtype="f32", n_ckpt=1)
+    sim.step(10)
+    sim.adjoint_begin(10)
+    with pytest.raises(B.FdtdError) as e:
+        sim.step_adjoint(1)        # forward is at 10, step 10 needs u^9
+    assert e.value.code == B.FDTD_E_STATE
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_batched_domains_equal_solo_runs(kernel):
+    """Ragged batch in one launch: every domain is bitwise its solo run (fields,
+    spectra and gradient)."""
+    specs = W.batch_domains(n_domains=3, sizes=(12, 20, 33), pml=5, n_steps=40, n_f=3, seed=7)
+    batch = Simulation(specs, dtype="f32", kernel=kernel, n_ckpt=41)
+    N = 40
+    batch.save(0)
+    for t in range(N):
+        batch.step(1)
+        batch.save(t + 1)
+    for d, s in enumerate(specs):
+        solo = Simulation(s, dtype="f32", kernel=kernel)
+        solo.step(N)
+        for q in range(6):
+            assert np.array_equal(batch.field(q, domain=d), solo.field(q)), (d, q)
+        assert np.array_equal(batch.spectra(0, domain=d), solo.spectra(0))
+    # gradients of the even domains
+    for d, s in enumerate(specs):
+        if s.grad_box is not None:
+            batch.set_cotangent(0, flux_objective(batch.spectra(0, domain=d))[1], domain=d)
+    batch.adjoint_begin(N)
+    for m_ in range(N, 0, -1):
+        batch.restore(m_ - 1)
+        batch.step_adjoint(1)
+    for d, s in enumerate(specs):
+        if s.grad_box is None:
+            continue
+        _, g_solo, _ = gpu_gradient_store_all(s, "f32", lambda mi, m, sp: flux_objective(sp)[1])
+        assert np.array_equal(batch.grad(d), g_solo), d
+
+
+def test_kernel_timing_counts_launches():
+    spec = _case(n_steps=30)
+    sim = Simulation(spec, dtype="f32")
+    sim.timing(1)
+    sim.step(30)
+    ms, n = sim.timing(2)
+    assert n == 30 and ms > 0
