@@ -1,0 +1,251 @@
+#!/usr/bin/env python
+"""Benchmark of the FDTD hot path on one MI355X.
+
+Headline (value): FP32 forward throughput in Mcell-updates/s on the 128^3 +
+10-cell CPML workload with a 48^3 Lorentz block, a z-sheet source and a
+16-frequency flux plane, 1000 time steps (one "step" of this benchmark = one
+complete 1000-time-step solve from rest, monitors included).  Alongside: the
+dominant kernel against the HBM roofline (HIP events on the library stream),
+the FP64 oracle on the host cores, the FP64 GPU path, the adjoint sweep with
+binomial replay on the 192^3 + CPML design-patch workload, and a 512^3 + CPML
+forward whose working set is far beyond the on-die cache.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fdtd_kernels.hip", "fdtd_dev.h"):
+        with open(os.path.join(ROOT, "paper_2609_30039_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_hash):
+    """HBM bytes per launch of the dominant kernel from committed PMC summaries,
+    only if they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "fwd_fused_c2_pmc.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_forward(spec, dtype, stream, K, Wm, tile=None):
+    from paper_2609_30039_amd.sim import Simulation
+    import torch
+    kw = tile or {}
+    sim = Simulation(spec, dtype=dtype, stream=stream, **kw)
+
+    def solve():
+        sim.reset()
+        sim.step(spec.n_steps, record=True)
+
+    for _ in range(Wm):
+        solve()
+    torch.cuda.synchronize()
+    sim.timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms, nl = sim.timing(2)
+    sim.timing(0)
+    return sim, el, kms, nl
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the path is single-GPU (no collectives); --gpus {args.gpus} is not "
+              f"supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs the GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import roofline as RL
+    from paper_2609_30039_amd.sim import Simulation
+    from paper_2609_30039_amd import adjoint as A
+
+    stream = torch.cuda.current_stream().cuda_stream
+    K, Wm = args.steps, args.warmup
+    khash = kernel_source_hash()
+
+    # ---------------------------------------------------------------- headline
+    spec = W.c2()
+    ncell = spec.ncells
+    log(f"c2 FP32 forward: {spec.shape} x {spec.n_steps} steps, warmup {Wm}, timed {K}")
+    sim32, el, kms, nl = run_forward(spec, "f32", stream, K, Wm)
+    mcups = ncell * spec.n_steps * K / el / 1e6
+    avg_ms = kms / nl
+    bytes_launch = RL.forward_bytes(spec, 4)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    log(f"c2 FP32: {el / K * 1e3:.2f} ms/solve, {mcups:.0f} Mcell-upd/s, kernel {avg_ms * 1e3:.1f} us/launch, "
+        f"{achieved:.0f} GB/s algorithmic")
+    traffic = traffic_from_profiles(khash)
+    out = {
+        "metric": "Mcell-updates/s fwd & adjoint (FP32 vs FP64), % HBM roofline, grad rel. err",
+        "value": round(mcups, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(el / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "148^3 cells (128^3 + 10-cell CPML, m=3, kappa_max=5), 48^3 one-pole Lorentz "
+                               "block, Ex sheet source, 16-frequency flux plane, 1000 time steps per step",
+                   "cells": ncell, "time_steps_per_step": spec.n_steps, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
+                     "kernel": "k_fwd_fused (one launch per time step)",
+                     "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_launch,
+                     "kernel_source_hash": khash},
+    }
+
+    # ---------------------------------------------------------------- CPU oracle
+    if not args.no_cpu:
+        from oracle import oracle as O
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        osim = O.OracleSim(spec)
+        t0 = time.perf_counter()
+        osim.step(2)
+        per = (time.perf_counter() - t0) / 2
+        nsteps = int(max(2, min(spec.n_steps - 2, args.cpu_seconds / max(per, 1e-6))))
+        log(f"oracle: {per * 1e3:.0f} ms/step on {cores} threads, running {nsteps} more steps")
+        t0 = time.perf_counter()
+        osim.step(nsteps)
+        cel = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(ncell * nsteps / cel / 1e6, 2), "unit": "Mcell-updates/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"FP64 C oracle, same workload, time steps 3..{nsteps + 2} of 1000 "
+                                         f"({cel:.1f} s), monitors recorded"}
+        # FP32 GPU fields against the oracle at the same step
+        n_cmp = nsteps + 2
+        cmp_sim = Simulation(spec, dtype="f32", stream=stream)
+        cmp_sim.step(n_cmp)
+        errs = {W.COMP_NAMES[q]: float(np.linalg.norm(cmp_sim.field(q) - osim.field(q)) /
+                                       max(np.linalg.norm(osim.field(q)), 1e-300)) for q in range(6)}
+        out["accuracy_vs_oracle"] = {"fp32_field_rel_l2_at_step": n_cmp, **{k: float(f"{v:.3e}") for k, v in
+                                                                           errs.items()}}
+        del cmp_sim, osim
+
+    if not args.no_extra:
+        # ------------------------------------------------------------ FP64 path and FP32 accuracy at 1000 steps
+        log("c2 FP64 forward")
+        sim64, el64, kms64, nl64 = run_forward(spec, "f64", stream, 1, 1)
+        out["fp64"] = {"value": round(ncell * spec.n_steps / el64 / 1e6, 1), "unit": "Mcell-updates/s",
+                       "ms_per_solve": round(el64 * 1e3, 2),
+                       "achieved_GBs": round(RL.forward_bytes(spec, 8) / (kms64 / nl64 * 1e-3) / 1e9, 1)}
+        f32e = {}
+        for q in range(6):
+            a, b = sim32.field(q).astype(np.float64), sim64.field(q)
+            f32e[W.COMP_NAMES[q]] = float(f"{np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300):.3e}")
+        fl32, fl64 = sim32.flux(0), sim64.flux(0)
+        f32e["flux_max_rel"] = float(f"{np.max(np.abs(fl32 - fl64) / np.abs(fl64)):.3e}")
+        out["fp32_vs_fp64_gpu_at_1000"] = f32e
+        del sim64
+
+        # ------------------------------------------------------------ adjoint (192^3 + CPML, 2000 steps, 24 slots)
+        spec3, fd_cells = W.c3()
+        log(f"c3 adjoint: {spec3.shape} x {spec3.n_steps}, 24 checkpoint slots")
+
+        def cot(s):
+            sp = s.spectra(0)
+            return {(0, 0): 2.0 * sp}
+
+        grads = {}
+        for dt in ("f32", "f64"):
+            sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream)
+            plan = A.RevolvePlan(spec3.n_steps, 24)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            last = A.forward_record(sim3, plan)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sim3.set_cotangent(0, 2.0 * sim3.spectra(0))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            sim3.timing(1)
+            A.reverse_sweep(sim3, plan, *last)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            akms, anl = sim3.timing(2)
+            grads[dt] = sim3.grad(0)[0]
+            tf, tr = t1 - t0, t3 - t2
+            n3 = spec3.ncells
+            if dt == "f32":
+                out["adjoint"] = {
+                    "workload": "212^3 (192^3 + 10-cell CPML), 64^3 design box eps in [1,6], |DFT Ez|^2 on a "
+                                "32x32 patch, 8 frequencies, 2000 steps, 24 checkpoints (binomial)",
+                    "forward_s": round(tf, 4), "reverse_s": round(tr, 4),
+                    "reverse_over_forward": round(tr / tf, 3),
+                    "adjoint_mcups": round(n3 * spec3.n_steps / tr / 1e6, 1),
+                    "forward_mcups": round(n3 * spec3.n_steps / tf / 1e6, 1),
+                    "forward_evaluations": plan.forward_evals + 1,
+                    "stepping_kernel_ms": round(akms, 2), "stepping_launches": anl}
+            else:
+                out["adjoint"]["fp64_reverse_s"] = round(tr, 4)
+                out["adjoint"]["fp64_forward_s"] = round(tf, 4)
+            log(f"c3 {dt}: forward {tf:.3f} s, reverse {tr:.3f} s")
+            del sim3
+        g32, g64 = grads["f32"], grads["f64"]
+        out["adjoint"]["grad_rel_l2_fp32_vs_fp64"] = float(f"{np.linalg.norm(g32 - g64) / np.linalg.norm(g64):.3e}")
+
+        # ------------------------------------------------------------ large forward (cache-free roofline)
+        spec5 = W.c5()
+        spec5.n_steps = 200
+        for s_ in spec5.sources:
+            s_.waveform = s_.waveform[:200]
+        log(f"c5-shape forward: {spec5.shape} x 200 steps")
+        sim5, el5, kms5, nl5 = run_forward(spec5, "f32", stream, 1, 1)
+        b5 = RL.forward_bytes(spec5, 4)
+        out["large_forward"] = {
+            "workload": "536^3 (512^3 + 12-cell CPML), diagonal eps, 128^3 Lorentz box, Ex sheet, Ex patch "
+                        "monitor, 200 steps FP32",
+            "mcups": round(spec5.ncells * 200 / el5 / 1e6, 1),
+            "avg_launch_us": round(kms5 / nl5 * 1e3, 1),
+            "achieved_GBs": round(b5 / (kms5 / nl5 * 1e-3) / 1e9, 1),
+            "frac_hbm": round(b5 / (kms5 / nl5 * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4)}
+        del sim5
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

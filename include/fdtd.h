@@ -206,6 +206,12 @@ int fdtd_get_memory(fdtd_t h, double *bytes);
    summed kernel time (ms) and the number of timed launches since enable. */
 int fdtd_kernel_timing(fdtd_t h, int32_t op, double *total_ms, int64_t *launches);
 
+/* Bandwidth calibration: copy `bytes` (a multiple of 4) between two device
+   buffers allocated for the call, `reps` times, on the default stream, and
+   return the mean kernel time per copy in ms (HIP events).  Used to scale
+   hardware byte counters against a plain copy of known size. */
+int fdtd_copy_probe(size_t bytes, int32_t reps, double *ms_per_copy);
+
 /* Failure injection for tests of checksum validation: overwrite 32-bit word
    `word` of checkpoint slot `slot` with `value`. */
 int fdtd_checkpoint_corrupt(fdtd_t h, int32_t slot, size_t word, uint32_t value);

@@ -32,7 +32,8 @@ ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_E_INVALID", -2: "FDTD_E_UNSTABLE", -3: "F
 EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_begin", "fdtd_step_adjoint",
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
-            "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_checkpoint_corrupt", "fdtd_last_error"]
+            "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
+            "fdtd_last_error"]
 
 
 class FdtdError(RuntimeError):
@@ -103,6 +104,7 @@ def lib():
         L.fdtd_get_memory.argtypes = [vp, C.POINTER(C.c_double)]
         L.fdtd_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.fdtd_checkpoint_corrupt.argtypes = [vp, i32, sz, u32]
+        L.fdtd_copy_probe.argtypes = [sz, i32, C.POINTER(C.c_double)]
         L.fdtd_last_error.argtypes = [vp]
         L.fdtd_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -275,6 +277,12 @@ def fdtd_kernel_timing(h, op: int):
     ms, n = C.c_double(), C.c_int64()
     _chk(lib().fdtd_kernel_timing(h, op, C.byref(ms), C.byref(n)), h)
     return ms.value, n.value
+
+
+def fdtd_copy_probe(nbytes: int, reps: int) -> float:
+    ms = C.c_double()
+    _chk(lib().fdtd_copy_probe(nbytes, reps, C.byref(ms)), None)
+    return ms.value
 
 
 def fdtd_checkpoint_corrupt(h, slot: int, word: int, value: int):

@@ -23,6 +23,26 @@ namespace fdtd {
 
 constexpr int kMaxSrc = 4;
 
+// Global-address-space views of device pointers.  Pointers read out of a
+// descriptor are generic to the compiler, which would emit flat memory
+// instructions; flat loads also count against the LDS wait counter, so a
+// barrier's LDS wait would drain every prefetched global load.
+#define FDTD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ FDTD_GLOBAL T* gp(T* p) {
+    return (FDTD_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const FDTD_GLOBAL T* gp(const T* p) {
+    return (const FDTD_GLOBAL T*)p;
+}
+
+// streaming store: the written field is not read again by this launch
+template <typename T>
+__device__ __forceinline__ void st_nt(FDTD_GLOBAL T* p, int off, T v) {
+    __builtin_nontemporal_store(v, p + off);
+}
+
 template <typename T>
 struct SrcDev {
     int kind, comp, i, j, k, nwave;

@@ -323,16 +323,14 @@ struct Tile {
     bool gen;   // tile touches absorbers, PEC faces, the Lorentz box or a source
 };
 
+// Tile-table entry: (domain, X0, Y0, k0); the block covers x in [X0, X0+64),
+// rows [Y0, Y0 + 4R) and planes [k0, k1) (+ one halo plane on each side).
 template <typename T, int R>
-__device__ __forceinline__ Tile fused_tile(const DomDev<T>& d, int lb, int kz) {
+__device__ __forceinline__ Tile fused_tile(const DomDev<T>& d, int4 e, int kz) {
     Tile tl;
-    const int TXo = 62, TYo = kWaves * R - 2;
-    int nbx = (d.n[0] + TXo - 1) / TXo, nby = (d.n[1] + TYo - 1) / TYo;
-    int bx = lb % nbx, r = lb / nbx;
-    int by = r % nby, bz = r / nby;
-    tl.X0 = bx * TXo - 1;
-    tl.Y0 = by * TYo - 1;
-    tl.k0 = bz * kz;
+    tl.X0 = e.y;
+    tl.Y0 = e.z;
+    tl.k0 = e.w;
     tl.k1 = min(tl.k0 + kz, d.n[2]);
     tl.lane = threadIdx.x & 63;
     tl.w = threadIdx.x >> 6;
@@ -475,14 +473,12 @@ __device__ __forceinline__ void fwd_fused_body(const DomDev<T>& d, const Tile& t
 }
 
 template <typename T, int R>
-__global__ void __launch_bounds__(256) k_fwd_fused(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                   int ndom, int kz, int rs, int ws, int t) {
-    int b = xcd_remap(blockIdx.x, gridDim.x);
-    int dom = find_domain(bs, ndom, b);
-    const DomDev<T>& d = doms[dom];
-    Tile tl = fused_tile<T, R>(d, b - bs[dom], kz);
-    if (tl.gen) fwd_fused_body<T, R, true>(d, tl, rs, ws, t);
-    else fwd_fused_body<T, R, false>(d, tl, rs, ws, t);
+__global__ void __launch_bounds__(256) k_fwd_fused(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                   int kz, int rs, int ws, int t) {
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DomDev<T>& d = doms[e.x];
+    Tile tl = fused_tile<T, R>(d, e, kz);
+    fwd_fused_body<T, R, true>(d, tl, rs, ws, t);
 }
 
 // ============================================================ adjoint, fused
@@ -628,14 +624,715 @@ __device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& t
 }
 
 template <typename T, int R>
-__global__ void __launch_bounds__(256) k_adj_fused(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                   int ndom, int kz, int rs, int ws, int fsr) {
-    int b = xcd_remap(blockIdx.x, gridDim.x);
-    int dom = find_domain(bs, ndom, b);
-    const DomDev<T>& d = doms[dom];
+__global__ void __launch_bounds__(256) k_adj_fused(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                   int kz, int rs, int ws, int fsr) {
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DomDev<T>& d = doms[e.x];
     if (!d.grad) return;
-    Tile tl = fused_tile<T, R>(d, b - bs[dom], kz);
+    Tile tl = fused_tile<T, R>(d, e, kz);
     adj_fused_body<T, R>(d, tl, rs, ws, fsr);
+}
+
+// ============================================================ bulk tiles
+// Tiles that lie inside the domain (no ghost nodes, no PEC nodes) and touch
+// no absorber, Lorentz cell or source: plain Yee arithmetic, 32-bit offsets,
+// the next plane's loads issued before the current plane is processed.
+// Results equal the general path bitwise (same operations in the same order).
+template <typename T>
+struct EpsView {
+    int mode;                   // 0 background everywhere, 1 inside the eps box, 2 partial
+    int diag;
+    const FDTD_GLOBAL T* p[3];
+    int lo[3], hi[3], ex, ey;
+    T bg;
+};
+
+template <typename T>
+__device__ __forceinline__ EpsView<T> eps_view(const DomDev<T>& d, int X0, int Y0, int NR, int klo, int khi) {
+    EpsView<T> v;
+    v.diag = d.eps_diag;
+    v.bg = d.epsinv_bg;
+    for (int c = 0; c < 3; ++c) v.p[c] = gp(d.epsinv[c]);
+    for (int a = 0; a < 3; ++a) {
+        v.lo[a] = d.elo[a];
+        v.hi[a] = d.ehi[a];
+    }
+    v.ex = d.ehi[0] - d.elo[0];
+    v.ey = d.ehi[1] - d.elo[1];
+    int lo[3] = {X0, Y0, klo}, hi[3] = {X0 + 63, Y0 + NR - 1, khi};
+    bool inside = true, outside = false;
+    for (int a = 0; a < 3; ++a) {
+        if (lo[a] < d.elo[a] || hi[a] >= d.ehi[a]) inside = false;
+        if (hi[a] < d.elo[a] || lo[a] >= d.ehi[a]) outside = true;
+    }
+    v.mode = outside ? 0 : (inside ? 1 : 2);
+    return v;
+}
+
+// eps^-1 of the three components at (i, j, k)
+template <typename T>
+__device__ __forceinline__ void eps_at(const EpsView<T>& v, int i, int j, int k, T out[3]) {
+    bool in = v.mode == 1 || (v.mode == 2 && i >= v.lo[0] && i < v.hi[0] && j >= v.lo[1] && j < v.hi[1] &&
+                              k >= v.lo[2] && k < v.hi[2]);
+    if (!in) {
+        out[0] = out[1] = out[2] = v.bg;
+        return;
+    }
+    int q = ((k - v.lo[2]) * v.ey + (j - v.lo[1])) * v.ex + (i - v.lo[0]);
+    out[0] = v.p[0][q];
+    if (v.diag) {
+        out[1] = v.p[1][q];
+        out[2] = v.p[2][q];
+    } else {
+        out[1] = out[2] = out[0];
+    }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_fwd_bulk(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                  int kz, int rs, int ws) {
+    __shared__ T sH[2][kWaves][2][64];
+    __shared__ T sE[2][kWaves][2][64];
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DomDev<T>& d = doms[e.x];
+    const int X0 = e.y, Y0 = e.z, k0 = e.w, k1 = min(k0 + kz, d.n[2]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = X0 + lane;
+    const int pitch = d.pitch, plane = (int)d.plane;
+    const T S = d.S;
+    const FDTD_GLOBAL T* __restrict__ rH0 = gp(d.H[0] + rs * d.fs);
+    const FDTD_GLOBAL T* __restrict__ rH1 = gp(d.H[1] + rs * d.fs);
+    const FDTD_GLOBAL T* __restrict__ rH2 = gp(d.H[2] + rs * d.fs);
+    const FDTD_GLOBAL T* __restrict__ rE0 = gp(d.E[0] + rs * d.fs);
+    const FDTD_GLOBAL T* __restrict__ rE1 = gp(d.E[1] + rs * d.fs);
+    const FDTD_GLOBAL T* __restrict__ rE2 = gp(d.E[2] + rs * d.fs);
+    FDTD_GLOBAL T* __restrict__ wH0 = gp(d.H[0] + ws * d.fs);
+    FDTD_GLOBAL T* __restrict__ wH1 = gp(d.H[1] + ws * d.fs);
+    FDTD_GLOBAL T* __restrict__ wH2 = gp(d.H[2] + ws * d.fs);
+    FDTD_GLOBAL T* __restrict__ wE0 = gp(d.E[0] + ws * d.fs);
+    FDTD_GLOBAL T* __restrict__ wE1 = gp(d.E[1] + ws * d.fs);
+    FDTD_GLOBAL T* __restrict__ wE2 = gp(d.E[2] + ws * d.fs);
+    const EpsView<T> ev = eps_view(d, X0, Y0, kWaves * R, k0 - 1, k1);
+    int ro[R];
+    bool own[R], ecomp[R];
+    for (int r = 0; r < R; ++r) {
+        int row = w * R + r;
+        ro[r] = (Y0 + row) * pitch + i;
+        ecomp[r] = lane >= 1 && row >= 1;
+        own[r] = lane >= 1 && lane <= 62 && row >= 1 && row <= kWaves * R - 2;
+    }
+    T Hk[R][3], Ek[R][3], Hp[R][3], Ep[R][3];
+    for (int r = 0; r < R; ++r) {
+        int f = (k0 - 1) * plane + ro[r];
+        Hk[r][0] = rH0[f];
+        Hk[r][1] = rH1[f];
+        Hk[r][2] = T(0);
+        Ek[r][0] = Ek[r][1] = Ek[r][2] = T(0);
+        f += plane;
+        Hp[r][0] = rH0[f];
+        Hp[r][1] = rH1[f];
+        Hp[r][2] = rH2[f];
+        Ep[r][0] = rE0[f];
+        Ep[r][1] = rE1[f];
+        Ep[r][2] = rE2[f];
+    }
+    for (int k = k0 - 1; k < k1; ++k) {
+        const int kn = k + 1;
+        T Hn[R][3], Eo[R][3];
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hn[r][q] = Hp[r][q];
+                Eo[r][q] = Ep[r][q];
+            }
+        if (kn < k1) {   // prefetch plane kn + 1 (<= k1 <= nz - 1)
+            for (int r = 0; r < R; ++r) {
+                int f = (kn + 1) * plane + ro[r];
+                Hp[r][0] = rH0[f];
+                Hp[r][1] = rH1[f];
+                Hp[r][2] = rH2[f];
+                Ep[r][0] = rE0[f];
+                Ep[r][1] = rE1[f];
+                Ep[r][2] = rE2[f];
+            }
+        }
+        const int pb = kn & 1;
+        sH[pb][w][0][lane] = Hn[R - 1][0];
+        sH[pb][w][1][lane] = Hn[R - 1][2];
+        __syncthreads();
+        T hx_ym0 = w > 0 ? sH[pb][w - 1][0][lane] : T(0);
+        T hz_ym0 = w > 0 ? sH[pb][w - 1][1][lane] : T(0);
+        const bool kin = kn >= k0 && kn < k1;
+        T En[R][3];
+        for (int r = 0; r < R; ++r) {
+            T hy_xm = __shfl_up(Hn[r][1], 1);
+            T hz_xm = __shfl_up(Hn[r][2], 1);
+            T hx_ym = r > 0 ? Hn[r - 1][0] : hx_ym0;
+            T hz_ym = r > 0 ? Hn[r - 1][2] : hz_ym0;
+            En[r][0] = En[r][1] = En[r][2] = T(0);
+            if (ecomp[r]) {
+                T ei[3];
+                eps_at(ev, i, Y0 + w * R + r, kn, ei);
+                // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
+                En[r][0] = fma(S * ei[0], (Hn[r][2] - hz_ym) - (Hn[r][1] - Hk[r][1]), Eo[r][0]);
+                En[r][1] = fma(S * ei[1], (Hn[r][0] - Hk[r][0]) - (Hn[r][2] - hz_xm), Eo[r][1]);
+                En[r][2] = fma(S * ei[2], (Hn[r][1] - hy_xm) - (Hn[r][0] - hx_ym), Eo[r][2]);
+                if (own[r] && kin) {
+                    int f = kn * plane + ro[r];
+                    st_nt(wE0, f, En[r][0]);
+                    st_nt(wE1, f, En[r][1]);
+                    st_nt(wE2, f, En[r][2]);
+                }
+            }
+        }
+        if (k >= k0) {
+            const int pk = k & 1;
+            T ex_yp3 = w + 1 < kWaves ? sE[pk][w + 1][0][lane] : T(0);
+            T ez_yp3 = w + 1 < kWaves ? sE[pk][w + 1][1][lane] : T(0);
+            for (int r = 0; r < R; ++r) {
+                T ey_xp = __shfl_down(Ek[r][1], 1);
+                T ez_xp = __shfl_down(Ek[r][2], 1);
+                T ex_yp = r + 1 < R ? Ek[r + 1][0] : ex_yp3;
+                T ez_yp = r + 1 < R ? Ek[r + 1][2] : ez_yp3;
+                if (own[r]) {
+                    int f = k * plane + ro[r];
+                    // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
+                    st_nt(wH0, f, fma(-S, (ez_yp - Ek[r][2]) - (En[r][1] - Ek[r][1]), Hk[r][0]));
+                    st_nt(wH1, f, fma(-S, (En[r][0] - Ek[r][0]) - (ez_xp - Ek[r][2]), Hk[r][1]));
+                    st_nt(wH2, f, fma(-S, (ey_xp - Ek[r][1]) - (ex_yp - Ek[r][0]), Hk[r][2]));
+                }
+            }
+        }
+        sE[pb][w][0][lane] = En[0][0];
+        sE[pb][w][1][lane] = En[0][2];
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hk[r][q] = Hn[r][q];
+                Ek[r][q] = En[r][q];
+            }
+    }
+}
+
+// ============================================================ plain tiles
+// Every tile without Lorentz cells: ghost lanes and rows (outside the domain)
+// read zero and write nothing, PEC nodes stay zero, soft sources are added,
+// and with CP the absorber recursion is applied per term.  Absorber
+// coefficients are loaded once per lane (x), per row (y) and per plane (z).
+// The arithmetic of every node is that of e_update / h_update.
+template <typename T>
+struct Cpml1 {
+    int side;                  // -1 outside the slabs
+    int idx;                   // index along the axis
+    T bE, cE, kE, bH, cH, kH;
+};
+
+template <typename T>
+__device__ __forceinline__ Cpml1<T> cpml_at(const DomDev<T>& d, int a, int x) {
+    Cpml1<T> c;
+    c.idx = x;
+    c.side = (x >= 0 && x < d.n[a]) ? slab_side(d, a, x) : -1;
+    c.bE = c.cE = c.kE = c.bH = c.cH = c.kH = T(0);
+    if (c.side >= 0) {
+        const FDTD_GLOBAL T* tb = gp(d.tab[a]);
+        int n = d.n[a];
+        c.bE = tb[x];
+        c.cE = tb[n + x];
+        c.kE = tb[2 * n + x];
+        c.bH = tb[3 * n + x];
+        c.cH = tb[4 * n + x];
+        c.kH = tb[5 * n + x];
+    }
+    return c;
+}
+
+// psi slab offset of node (i,j,k) on axis a, side s (32-bit)
+template <typename T>
+__device__ __forceinline__ int poff(const DomDev<T>& d, int a, int s, int i, int j, int k) {
+    int L = d.L[a][s];
+    if (a == 0) return (k * d.n[1] + j) * L + (s ? i - (d.n[0] - L) : i);
+    if (a == 1) return (k * L + (s ? j - (d.n[1] - L) : j)) * d.n[0] + i;
+    return ((s ? k - (d.n[2] - L) : k) * d.n[1] + j) * d.n[0] + i;
+}
+
+// one stretched term: psi_new = b psi + c D; D/kappa + psi_new (as stretch())
+template <typename T>
+__device__ __forceinline__ T st_term(T* base, long long rso, long long wso, bool own, T b, T c, T ki, T D) {
+    FDTD_GLOBAL T* g = gp(base);
+    T pn = fma(b, g[rso], c * D);
+    if (own) g[wso] = pn;
+    return fma(ki, D, pn);
+}
+
+// psi memories of the six terms of one node, slots ordered
+// 0: y-slab term of Ex (E) / Hx (H), 1: y-slab term of Ez / Hz,
+// 2: z-slab term of Ey / Hy, 3: z-slab term of Ex / Hx,
+// 4: x-slab term of Ez / Hz, 5: x-slab term of Ey / Hy.
+// (E side: Ex t0, Ez t1, Ey t0, Ex t1, Ez t0, Ey t1; H side: Hx t0, Hz t1,
+// Hy t0, Hx t1, Hz t0, Hy t1.)
+template <typename T>
+__device__ __forceinline__ void psi_load(const DomDev<T>& d, T* const (&psi)[3][2][2], long long so, bool v,
+                                         const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cz, int i, int j, int k,
+                                         T out[6]) {
+    for (int q = 0; q < 6; ++q) out[q] = T(0);
+    if (!v) return;
+    if (cy.side >= 0) {
+        int o = poff(d, 1, cy.side, i, j, k);
+        out[0] = gp(psi[1][cy.side][0] + so)[o];
+        out[1] = gp(psi[1][cy.side][1] + so)[o];
+    }
+    if (cz.side >= 0) {
+        int o = poff(d, 2, cz.side, i, j, k);
+        out[2] = gp(psi[2][cz.side][0] + so)[o];
+        out[3] = gp(psi[2][cz.side][1] + so)[o];
+    }
+    if (cx.side >= 0) {
+        int o = poff(d, 0, cx.side, i, j, k);
+        out[4] = gp(psi[0][cx.side][0] + so)[o];
+        out[5] = gp(psi[0][cx.side][1] + so)[o];
+    }
+}
+
+// stretched term from a prefetched memory: psi_new = b psi + c D (stored by
+// the owner), returns D/kappa + psi_new (the arithmetic of stretch())
+template <typename T>
+__device__ __forceinline__ T st_pref(T* base, long long wso, int off, bool own, T b, T c, T ki, T psi, T D) {
+    T pn = fma(b, psi, c * D);
+    if (own) gp(base + wso)[off] = pn;
+    return fma(ki, D, pn);
+}
+
+template <typename T, int R, bool CP>
+__device__ __forceinline__ void fwd_plain_body(const DomDev<T>& d, int X0, int Y0, int k0, int k1, int rs, int ws,
+                                               int t) {
+    __shared__ T sH[2][kWaves][2][64];
+    __shared__ T sE[2][kWaves][2][64];
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = X0 + lane;
+    const bool ix = i >= 0 && i < nx;
+    const int pitch = d.pitch, plane = (int)d.plane;
+    const T S = d.S;
+    const long long fso = (long long)rs * d.fs, fwo = (long long)ws * d.fs;
+    const FDTD_GLOBAL T* __restrict__ rH0 = gp(d.H[0] + fso);
+    const FDTD_GLOBAL T* __restrict__ rH1 = gp(d.H[1] + fso);
+    const FDTD_GLOBAL T* __restrict__ rH2 = gp(d.H[2] + fso);
+    const FDTD_GLOBAL T* __restrict__ rE0 = gp(d.E[0] + fso);
+    const FDTD_GLOBAL T* __restrict__ rE1 = gp(d.E[1] + fso);
+    const FDTD_GLOBAL T* __restrict__ rE2 = gp(d.E[2] + fso);
+    FDTD_GLOBAL T* __restrict__ wH0 = gp(d.H[0] + fwo);
+    FDTD_GLOBAL T* __restrict__ wH1 = gp(d.H[1] + fwo);
+    FDTD_GLOBAL T* __restrict__ wH2 = gp(d.H[2] + fwo);
+    FDTD_GLOBAL T* __restrict__ wE0 = gp(d.E[0] + fwo);
+    FDTD_GLOBAL T* __restrict__ wE1 = gp(d.E[1] + fwo);
+    FDTD_GLOBAL T* __restrict__ wE2 = gp(d.E[2] + fwo);
+    const EpsView<T> ev = eps_view(d, X0, Y0, kWaves * R, k0 - 1, k1);
+    int jr[R], ro[R];
+    bool vr[R], own[R], ecomp[R];
+    Cpml1<T> cy[R];
+    for (int r = 0; r < R; ++r) {
+        int row = w * R + r;
+        jr[r] = Y0 + row;
+        vr[r] = ix && jr[r] >= 0 && jr[r] < ny;
+        ro[r] = vr[r] ? jr[r] * pitch + i : 0;
+        ecomp[r] = vr[r] && lane >= 1 && row >= 1;
+        own[r] = vr[r] && lane >= 1 && lane <= 62 && row >= 1 && row <= kWaves * R - 2;
+        if (CP) cy[r] = cpml_at(d, 1, jr[r]);
+    }
+    Cpml1<T> cx;
+    if (CP) cx = cpml_at(d, 0, i);
+    T Hk[R][3], Ek[R][3], Hp[R][3], Ep[R][3];
+    T pEp[CP ? R : 1][6], pHp[CP ? R : 1][6];   // prefetched memories: E side at kn, H side at k
+    for (int r = 0; r < R; ++r)
+        for (int q = 0; q < 3; ++q) {
+            Hk[r][q] = Ek[r][q] = Hp[r][q] = Ep[r][q] = T(0);
+        }
+    if (CP) {
+        Cpml1<T> cz0 = cpml_at(d, 2, k0);
+        for (int r = 0; r < R; ++r) psi_load(d, d.psiE, fso, vr[r], cx, cy[r], cz0, i, jr[r], k0, pEp[CP ? r : 0]);
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 6; ++q) pHp[CP ? r : 0][q] = T(0);
+    }
+    for (int r = 0; r < R; ++r) {
+        if (!vr[r]) continue;
+        if (k0 > 0) {
+            int f = (k0 - 1) * plane + ro[r];
+            Hk[r][0] = rH0[f];
+            Hk[r][1] = rH1[f];
+        }
+        int f = k0 * plane + ro[r];
+        Hp[r][0] = rH0[f];
+        Hp[r][1] = rH1[f];
+        Hp[r][2] = rH2[f];
+        Ep[r][0] = rE0[f];
+        Ep[r][1] = rE1[f];
+        Ep[r][2] = rE2[f];
+    }
+    for (int k = k0 - 1; k < k1; ++k) {
+        const int kn = k + 1;
+        const bool have_n = kn < nz;
+        T Hn[R][3], Eo[R][3];
+        T pE[CP ? R : 1][6], pH[CP ? R : 1][6];
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hn[r][q] = Hp[r][q];
+                Eo[r][q] = Ep[r][q];
+            }
+        if (CP)
+            for (int r = 0; r < R; ++r)
+                for (int q = 0; q < 6; ++q) {
+                    pE[CP ? r : 0][q] = pEp[CP ? r : 0][q];
+                    pH[CP ? r : 0][q] = pHp[CP ? r : 0][q];
+                }
+        const bool pf = kn < k1 && kn + 1 < nz;
+        if (pf) {
+            for (int r = 0; r < R; ++r) {
+                if (!vr[r]) continue;
+                int f = (kn + 1) * plane + ro[r];
+                Hp[r][0] = rH0[f];
+                Hp[r][1] = rH1[f];
+                Hp[r][2] = rH2[f];
+                Ep[r][0] = rE0[f];
+                Ep[r][1] = rE1[f];
+                Ep[r][2] = rE2[f];
+            }
+        } else {
+            for (int r = 0; r < R; ++r)
+                for (int q = 0; q < 3; ++q) Hp[r][q] = Ep[r][q] = T(0);
+        }
+        if (CP) {
+            // memories of the next E pass (plane kn+1) and of the next H pass (plane kn)
+            Cpml1<T> czp = cpml_at(d, 2, kn + 1), czh = cpml_at(d, 2, kn);
+            for (int r = 0; r < R; ++r) {
+                psi_load(d, d.psiE, fso, vr[r] && pf, cx, cy[r], czp, i, jr[r], kn + 1, pEp[CP ? r : 0]);
+                psi_load(d, d.psiH, fso, vr[r] && kn < k1, cx, cy[r], czh, i, jr[r], kn, pHp[CP ? r : 0]);
+            }
+        }
+        const int pb = kn & 1;
+        sH[pb][w][0][lane] = Hn[R - 1][0];
+        sH[pb][w][1][lane] = Hn[R - 1][2];
+        __syncthreads();
+        T hx_ym0 = w > 0 ? sH[pb][w - 1][0][lane] : T(0);
+        T hz_ym0 = w > 0 ? sH[pb][w - 1][1][lane] : T(0);
+        const bool kin = kn >= k0 && kn < k1;
+        Cpml1<T> czn;
+        if (CP) czn = cpml_at(d, 2, kn);
+        T En[R][3];
+        for (int r = 0; r < R; ++r) {
+            T hy_xm = __shfl_up(Hn[r][1], 1);
+            T hz_xm = __shfl_up(Hn[r][2], 1);
+            T hx_ym = r > 0 ? Hn[r - 1][0] : hx_ym0;
+            T hz_ym = r > 0 ? Hn[r - 1][2] : hz_ym0;
+            En[r][0] = En[r][1] = En[r][2] = T(0);
+            if (ecomp[r] && have_n) {
+                const int j = jr[r];
+                const bool o = own[r] && kin;
+                T ei[3];
+                eps_at(ev, i, j, kn, ei);
+                // raw differences of the six terms
+                T Dx0 = Hn[r][2] - hz_ym, Dx1 = Hn[r][1] - Hk[r][1];   // Ex: Hz along y, Hy along z
+                T Dy0 = Hn[r][0] - Hk[r][0], Dy1 = Hn[r][2] - hz_xm;   // Ey: Hx along z, Hz along x
+                T Dz0 = Hn[r][1] - hy_xm, Dz1 = Hn[r][0] - hx_ym;      // Ez: Hy along x, Hx along y
+                if (CP) {
+                    const T* pe = pE[CP ? r : 0];
+                    if (cy[r].side >= 0) {
+                        int q = poff(d, 1, cy[r].side, i, j, kn);
+                        Dx0 = st_pref(d.psiE[1][cy[r].side][0], fwo, q, o && j > 0 && kn > 0, cy[r].bE, cy[r].cE,
+                                      cy[r].kE, pe[0], Dx0);
+                        Dz1 = st_pref(d.psiE[1][cy[r].side][1], fwo, q, o && i > 0 && j > 0, cy[r].bE, cy[r].cE,
+                                      cy[r].kE, pe[1], Dz1);
+                    }
+                    if (czn.side >= 0) {
+                        int q = poff(d, 2, czn.side, i, j, kn);
+                        Dy0 = st_pref(d.psiE[2][czn.side][0], fwo, q, o && i > 0 && kn > 0, czn.bE, czn.cE, czn.kE,
+                                      pe[2], Dy0);
+                        Dx1 = st_pref(d.psiE[2][czn.side][1], fwo, q, o && j > 0 && kn > 0, czn.bE, czn.cE, czn.kE,
+                                      pe[3], Dx1);
+                    }
+                    if (cx.side >= 0) {
+                        int q = poff(d, 0, cx.side, i, j, kn);
+                        Dz0 = st_pref(d.psiE[0][cx.side][0], fwo, q, o && i > 0 && j > 0, cx.bE, cx.cE, cx.kE,
+                                      pe[4], Dz0);
+                        Dy1 = st_pref(d.psiE[0][cx.side][1], fwo, q, o && i > 0 && kn > 0, cx.bE, cx.cE, cx.kE,
+                                      pe[5], Dy1);
+                    }
+                }
+                T ex = fma(S * ei[0], Dx0 - Dx1, Eo[r][0]);
+                T ey = fma(S * ei[1], Dy0 - Dy1, Eo[r][1]);
+                T ez = fma(S * ei[2], Dz0 - Dz1, Eo[r][2]);
+                for (int q = 0; q < d.nsrc; ++q) {
+                    const SrcDev<T>& sr = d.src[q];
+                    if (t < sr.nwave && kn == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) {
+                        T v = gp(sr.wave)[t];
+                        if (sr.comp == 0) ex += v;
+                        else if (sr.comp == 1) ey += v;
+                        else ez += v;
+                    }
+                }
+                // PEC: E_c is zero where the index along c+1 or c+2 is 0
+                if (j == 0 || kn == 0) ex = T(0);
+                if (i == 0 || kn == 0) ey = T(0);
+                if (i == 0 || j == 0) ez = T(0);
+                En[r][0] = ex;
+                En[r][1] = ey;
+                En[r][2] = ez;
+                if (o) {
+                    int f = kn * plane + ro[r];
+                    wE0[f] = ex;
+                    wE1[f] = ey;
+                    wE2[f] = ez;
+                }
+            }
+        }
+        if (k >= k0) {
+            const int pk = k & 1;
+            Cpml1<T> czk;
+            if (CP) czk = cpml_at(d, 2, k);
+            T ex_yp3 = w + 1 < kWaves ? sE[pk][w + 1][0][lane] : T(0);
+            T ez_yp3 = w + 1 < kWaves ? sE[pk][w + 1][1][lane] : T(0);
+            for (int r = 0; r < R; ++r) {
+                T ey_xp = __shfl_down(Ek[r][1], 1);
+                T ez_xp = __shfl_down(Ek[r][2], 1);
+                T ex_yp = r + 1 < R ? Ek[r + 1][0] : ex_yp3;
+                T ez_yp = r + 1 < R ? Ek[r + 1][2] : ez_yp3;
+                if (own[r]) {
+                    const int j = jr[r];
+                    T Ax0 = ez_yp - Ek[r][2], Ax1 = En[r][1] - Ek[r][1];   // Hx: Ez along y, Ey along z
+                    T Ay0 = En[r][0] - Ek[r][0], Ay1 = ez_xp - Ek[r][2];   // Hy: Ex along z, Ez along x
+                    T Az0 = ey_xp - Ek[r][1], Az1 = ex_yp - Ek[r][0];      // Hz: Ey along x, Ex along y
+                    if (CP) {
+                        const T* ph = pH[CP ? r : 0];
+                        if (cy[r].side >= 0) {
+                            int q = poff(d, 1, cy[r].side, i, j, k);
+                            Ax0 = st_pref(d.psiH[1][cy[r].side][0], fwo, q, true, cy[r].bH, cy[r].cH, cy[r].kH, ph[0],
+                                          Ax0);
+                            Az1 = st_pref(d.psiH[1][cy[r].side][1], fwo, q, true, cy[r].bH, cy[r].cH, cy[r].kH, ph[1],
+                                          Az1);
+                        }
+                        if (czk.side >= 0) {
+                            int q = poff(d, 2, czk.side, i, j, k);
+                            Ay0 = st_pref(d.psiH[2][czk.side][0], fwo, q, true, czk.bH, czk.cH, czk.kH, ph[2], Ay0);
+                            Ax1 = st_pref(d.psiH[2][czk.side][1], fwo, q, true, czk.bH, czk.cH, czk.kH, ph[3], Ax1);
+                        }
+                        if (cx.side >= 0) {
+                            int q = poff(d, 0, cx.side, i, j, k);
+                            Az0 = st_pref(d.psiH[0][cx.side][0], fwo, q, true, cx.bH, cx.cH, cx.kH, ph[4], Az0);
+                            Ay1 = st_pref(d.psiH[0][cx.side][1], fwo, q, true, cx.bH, cx.cH, cx.kH, ph[5], Ay1);
+                        }
+                    }
+                    int f = k * plane + ro[r];
+                    wH0[f] = fma(-S, Ax0 - Ax1, Hk[r][0]);
+                    wH1[f] = fma(-S, Ay0 - Ay1, Hk[r][1]);
+                    wH2[f] = fma(-S, Az0 - Az1, Hk[r][2]);
+                }
+            }
+        }
+        sE[pb][w][0][lane] = En[0][0];
+        sE[pb][w][1][lane] = En[0][2];
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hk[r][q] = Hn[r][q];
+                Ek[r][q] = En[r][q];
+            }
+    }
+}
+
+// Adjoint of a bulk tile.  Hbar and Ebar (set rs) -> set ws; dJ/deps inside
+// the gradient box from the forward H (set fsr).  GRAD: the tile meets the
+// gradient box.
+template <typename T, int R, bool GRAD>
+__device__ __forceinline__ void adj_bulk_body(const DomDev<T>& d, int X0, int Y0, int k0, int k1, int rs, int ws,
+                                              int fsr) {
+    __shared__ T sH[2][kWaves][4][64];   // row R-1: Hbar z, Hbar x, forward Hx, forward Hz
+    __shared__ T sE[2][kWaves][2][64];   // row 0: Ez term 1, Ex term 0
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = X0 + lane;
+    const int pitch = d.pitch, plane = (int)d.plane;
+    const T S = d.S, mS = -d.S;          // -S*sgn for sgn = +1 and sgn = -1 (exact)
+    const FDTD_GLOBAL T* __restrict__ rH0 = gp(d.Ha[0] + rs * d.as);
+    const FDTD_GLOBAL T* __restrict__ rH1 = gp(d.Ha[1] + rs * d.as);
+    const FDTD_GLOBAL T* __restrict__ rH2 = gp(d.Ha[2] + rs * d.as);
+    const FDTD_GLOBAL T* __restrict__ rE0 = gp(d.Ea[0] + rs * d.as);
+    const FDTD_GLOBAL T* __restrict__ rE1 = gp(d.Ea[1] + rs * d.as);
+    const FDTD_GLOBAL T* __restrict__ rE2 = gp(d.Ea[2] + rs * d.as);
+    FDTD_GLOBAL T* __restrict__ wH0 = gp(d.Ha[0] + ws * d.as);
+    FDTD_GLOBAL T* __restrict__ wH1 = gp(d.Ha[1] + ws * d.as);
+    FDTD_GLOBAL T* __restrict__ wH2 = gp(d.Ha[2] + ws * d.as);
+    FDTD_GLOBAL T* __restrict__ wE0 = gp(d.Ea[0] + ws * d.as);
+    FDTD_GLOBAL T* __restrict__ wE1 = gp(d.Ea[1] + ws * d.as);
+    FDTD_GLOBAL T* __restrict__ wE2 = gp(d.Ea[2] + ws * d.as);
+    const FDTD_GLOBAL T* __restrict__ fH0 = gp(d.H[0] + fsr * d.fs);
+    const FDTD_GLOBAL T* __restrict__ fH1 = gp(d.H[1] + fsr * d.fs);
+    const FDTD_GLOBAL T* __restrict__ fH2 = gp(d.H[2] + fsr * d.fs);
+    const EpsView<T> ev = eps_view(d, X0, Y0, kWaves * R, k0 - 1, k1);
+    int ro[R], jr[R];
+    bool own[R], ecomp[R];
+    for (int r = 0; r < R; ++r) {
+        int row = w * R + r;
+        jr[r] = Y0 + row;
+        ro[r] = jr[r] * pitch + i;
+        ecomp[r] = lane >= 1 && row >= 1;
+        own[r] = lane >= 1 && lane <= 62 && row >= 1 && row <= kWaves * R - 2;
+    }
+    // plane-k registers: Hbar at k; forward Hx, Hy at k (gradient z-differences)
+    T Hb[R][3], Fk[R][2];
+    Dbar6<T> Dk[R];
+    T Hbp[R][3], Ebp[R][3], Fp[R][3];   // prefetched plane
+    for (int r = 0; r < R; ++r) {
+        int f = (k0 - 1) * plane + ro[r];
+        Hb[r][0] = rH0[f];
+        Hb[r][1] = rH1[f];
+        Hb[r][2] = T(0);
+        Fk[r][0] = GRAD ? fH0[f] : T(0);
+        Fk[r][1] = GRAD ? fH1[f] : T(0);
+        Dk[r] = Dbar6<T>{};
+        f += plane;
+        Hbp[r][0] = rH0[f];
+        Hbp[r][1] = rH1[f];
+        Hbp[r][2] = rH2[f];
+        Ebp[r][0] = rE0[f];
+        Ebp[r][1] = rE1[f];
+        Ebp[r][2] = rE2[f];
+        if (GRAD) {
+            Fp[r][0] = fH0[f];
+            Fp[r][1] = fH1[f];
+            Fp[r][2] = fH2[f];
+        } else {
+            Fp[r][0] = Fp[r][1] = Fp[r][2] = T(0);
+        }
+    }
+    for (int k = k0 - 1; k < k1; ++k) {
+        const int kn = k + 1;
+        T Hn[R][3], Eo[R][3], Fn[R][3];
+        for (int r = 0; r < R; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hn[r][q] = Hbp[r][q];
+                Eo[r][q] = Ebp[r][q];
+                Fn[r][q] = Fp[r][q];
+            }
+        if (kn < k1) {
+            for (int r = 0; r < R; ++r) {
+                int f = (kn + 1) * plane + ro[r];
+                Hbp[r][0] = rH0[f];
+                Hbp[r][1] = rH1[f];
+                Hbp[r][2] = rH2[f];
+                Ebp[r][0] = rE0[f];
+                Ebp[r][1] = rE1[f];
+                Ebp[r][2] = rE2[f];
+                if (GRAD) {
+                    Fp[r][0] = fH0[f];
+                    Fp[r][1] = fH1[f];
+                    Fp[r][2] = fH2[f];
+                }
+            }
+        }
+        const int pb = kn & 1;
+        sH[pb][w][0][lane] = Hn[R - 1][2];
+        sH[pb][w][1][lane] = Hn[R - 1][0];
+        if (GRAD) {
+            sH[pb][w][2][lane] = Fn[R - 1][0];
+            sH[pb][w][3][lane] = Fn[R - 1][2];
+        }
+        __syncthreads();
+        T hz_m0 = w > 0 ? sH[pb][w - 1][0][lane] : T(0);
+        T hx_m0 = w > 0 ? sH[pb][w - 1][1][lane] : T(0);
+        T fx_m0 = (GRAD && w > 0) ? sH[pb][w - 1][2][lane] : T(0);
+        T fz_m0 = (GRAD && w > 0) ? sH[pb][w - 1][3][lane] : T(0);
+        const bool kin = kn >= k0 && kn < k1;
+        Dbar6<T> Dn[R];
+        for (int r = 0; r < R; ++r) {
+            // raw-difference cotangents of the H terms at the node: -S sgn Hbar
+            T dHxy = mS * Hn[r][0], dHxz = S * Hn[r][0];
+            T dHyz = mS * Hn[r][1], dHyx = S * Hn[r][1];
+            T dHzx = mS * Hn[r][2], dHzy = S * Hn[r][2];
+            T hz_xm = __shfl_up(Hn[r][2], 1), hy_xm = __shfl_up(Hn[r][1], 1);
+            T dHzx_m = mS * hz_xm, dHyx_m = S * hy_xm;
+            T dHzy_m = S * (r > 0 ? Hn[r - 1][2] : hz_m0);
+            T dHxy_m = mS * (r > 0 ? Hn[r - 1][0] : hx_m0);
+            T dHyz_k = mS * Hb[r][1], dHxz_k = S * Hb[r][0];
+            T fy_xm = GRAD ? __shfl_up(Fn[r][1], 1) : T(0), fz_xm = GRAD ? __shfl_up(Fn[r][2], 1) : T(0);
+            Dn[r] = Dbar6<T>{};
+            if (ecomp[r]) {
+                const int j = jr[r];
+                T et0 = Eo[r][0], et1 = Eo[r][1], et2 = Eo[r][2];
+                et0 += dHyz_k - dHyz;
+                et0 += dHzy_m - dHzy;
+                et1 += dHzx_m - dHzx;
+                et1 += dHxz_k - dHxz;
+                et2 += dHxy_m - dHxy;
+                et2 += dHyx_m - dHyx;
+                T ei[3];
+                eps_at(ev, i, j, kn, ei);
+                T c0 = S * ei[0], c1 = S * ei[1], c2 = S * ei[2];
+                Dn[r].x0 = c0 * et0;
+                Dn[r].x1 = -c0 * et0;
+                Dn[r].y0 = c1 * et1;
+                Dn[r].y1 = -c1 * et1;
+                Dn[r].z0 = c2 * et2;
+                Dn[r].z1 = -c2 * et2;
+                if (own[r] && kin) {
+                    int f = kn * plane + ro[r];
+                    st_nt(wE0, f, et0);
+                    st_nt(wE1, f, et1);
+                    st_nt(wE2, f, et2);
+                    if (GRAD && in_gbox(d, i, j, kn)) {
+                        T fx_ym = r > 0 ? Fn[r - 1][0] : fx_m0, fz_ym = r > 0 ? Fn[r - 1][2] : fz_m0;
+                        // forward curls: Ex (Hz along y, Hy along z), Ey (Hx along z, Hz along x), Ez (Hy along x, Hx along y)
+                        T cx = (Fn[r][2] - fz_ym) - (Fn[r][1] - Fk[r][1]);
+                        T cy = (Fn[r][0] - Fk[r][0]) - (Fn[r][2] - fz_xm);
+                        T cz = (Fn[r][1] - fy_xm) - (Fn[r][0] - fx_ym);
+                        double g[3];
+                        g[0] = -(double)et0 * (double)(S * ei[0] * ei[0] * cx);
+                        g[1] = -(double)et1 * (double)(S * ei[1] * ei[1] * cy);
+                        g[2] = -(double)et2 * (double)(S * ei[2] * ei[2] * cz);
+                        grad_store(d, i, j, kn, g);
+                    }
+                }
+            }
+        }
+        if (k >= k0) {
+            const int pk = k & 1;
+            T z1_yp3 = w + 1 < kWaves ? sE[pk][w + 1][0][lane] : T(0);
+            T x0_yp3 = w + 1 < kWaves ? sE[pk][w + 1][1][lane] : T(0);
+            for (int r = 0; r < R; ++r) {
+                T z0_xp = __shfl_down(Dk[r].z0, 1);
+                T y1_xp = __shfl_down(Dk[r].y1, 1);
+                T z1_yp = r + 1 < R ? Dk[r + 1].z1 : z1_yp3;
+                T x0_yp = r + 1 < R ? Dk[r + 1].x0 : x0_yp3;
+                if (own[r]) {
+                    int f = k * plane + ro[r];
+                    T hbx = Hb[r][0], hby = Hb[r][1], hbz = Hb[r][2];
+                    hbx += (Dk[r].y0 - Dn[r].y0) + (Dk[r].z1 - z1_yp);
+                    hby += (Dk[r].z0 - z0_xp) + (Dk[r].x1 - Dn[r].x1);
+                    hbz += (Dk[r].x0 - x0_yp) + (Dk[r].y1 - y1_xp);
+                    st_nt(wH0, f, hbx);
+                    st_nt(wH1, f, hby);
+                    st_nt(wH2, f, hbz);
+                }
+            }
+        }
+        sE[pb][w][0][lane] = Dn[0].z1;
+        sE[pb][w][1][lane] = Dn[0].x0;
+        for (int r = 0; r < R; ++r) {
+            Hb[r][0] = Hn[r][0];
+            Hb[r][1] = Hn[r][1];
+            Hb[r][2] = Hn[r][2];
+            Fk[r][0] = Fn[r][0];
+            Fk[r][1] = Fn[r][1];
+            Dk[r] = Dn[r];
+        }
+    }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_adj_bulk(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                  int kz, int rs, int ws, int fsr) {
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DomDev<T>& d = doms[e.x];
+    if (!d.grad) return;
+    const int k1 = min(e.w + kz, d.n[2]);
+    bool g = d.grad && e.y + 63 >= d.glo[0] && e.y < d.ghi[0] && e.z + kWaves * R - 1 >= d.glo[1] &&
+             e.z < d.ghi[1] && k1 - 1 >= d.glo[2] && e.w < d.ghi[2];
+    if (g) adj_bulk_body<T, R, true>(d, e.y, e.z, e.w, k1, rs, ws, fsr);
+    else adj_bulk_body<T, R, false>(d, e.y, e.z, e.w, k1, rs, ws, fsr);
 }
 
 // ============================================================ monitors
@@ -813,6 +1510,29 @@ static inline int blocks_1d(long long n, int bs, int cap = 65536) {
     return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_fwd_plain_cp(const DomDev<T>* __restrict__ doms,
+                                                      const int4* __restrict__ tiles, int kz, int rs, int ws, int t) {
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DomDev<T>& d = doms[e.x];
+    fwd_plain_body<T, R, true>(d, e.y, e.z, e.w, min(e.w + kz, d.n[2]), rs, ws, t);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_fwd_plain_nc(const DomDev<T>* __restrict__ doms,
+                                                      const int4* __restrict__ tiles, int kz, int rs, int ws, int t) {
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    const DomDev<T>& d = doms[e.x];
+    fwd_plain_body<T, R, false>(d, e.y, e.z, e.w, min(e.w + kz, d.n[2]), rs, ws, t);
+}
+
+#define FDTD_ROWS_SWITCH(KER, R, ...)                                                              \
+    switch (R) {                                                                                  \
+        case 2: hipLaunchKernelGGL((KER<T, 2>), __VA_ARGS__); break;                              \
+        case 8: hipLaunchKernelGGL((KER<T, 8>), __VA_ARGS__); break;                              \
+        default: hipLaunchKernelGGL((KER<T, 4>), __VA_ARGS__); break;                             \
+    }
+
 template <typename T>
 void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
@@ -821,11 +1541,10 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
         hipLaunchKernelGGL(k_fwd_h<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
         return;
     }
-    switch (c.rows) {
-        case 2: hipLaunchKernelGGL((k_fwd_fused<T, 2>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t); break;
-        case 8: hipLaunchKernelGGL((k_fwd_fused<T, 8>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t); break;
-        default: hipLaunchKernelGGL((k_fwd_fused<T, 4>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t); break;
-    }
+    if (c.nfgen) FDTD_ROWS_SWITCH(k_fwd_fused, c.rows, dim3(c.nfgen), dim3(256), 0, s, dd, c.tfgen, c.kz, rs, ws, t)
+    if (c.nfcp) FDTD_ROWS_SWITCH(k_fwd_plain_cp, c.rows, dim3(c.nfcp), dim3(256), 0, s, dd, c.tfcp, c.kz, rs, ws, t)
+    if (c.nfplain)
+        FDTD_ROWS_SWITCH(k_fwd_plain_nc, c.rows, dim3(c.nfplain), dim3(256), 0, s, dd, c.tfplain, c.kz, rs, ws, t)
 }
 
 template <typename T>
@@ -836,11 +1555,8 @@ void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, h
         hipLaunchKernelGGL(k_adj_et<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr);
         return;
     }
-    switch (c.rows) {
-        case 2: hipLaunchKernelGGL((k_adj_fused<T, 2>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr); break;
-        case 8: hipLaunchKernelGGL((k_adj_fused<T, 8>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr); break;
-        default: hipLaunchKernelGGL((k_adj_fused<T, 4>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr); break;
-    }
+    if (c.ngen) FDTD_ROWS_SWITCH(k_adj_fused, c.rows, dim3(c.ngen), dim3(256), 0, s, dd, c.tgen, c.kz, rs, ws, fsr)
+    if (c.nbulk) FDTD_ROWS_SWITCH(k_adj_bulk, c.rows, dim3(c.nbulk), dim3(256), 0, s, dd, c.tbulk, c.kz, rs, ws, fsr)
 }
 
 template <typename T>
@@ -899,11 +1615,6 @@ void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipSt
     long long nw = (long long)(bytes / 4);
     if (nw == 0) return;
     hipLaunchKernelGGL(k_checksum, dim3(blocks_1d(nw, 256, 4096)), dim3(256), 0, s, (const uint32_t*)p, nw, out);
-}
-
-int fused_blocks(int nx, int ny, int nz, int rows, int kz) {
-    int TYo = kWaves * rows - 2;
-    return ((nx + 61) / 62) * ((ny + TYo - 1) / TYo) * ((nz + kz - 1) / kz);
 }
 
 int split_blocks(int nx, int ny, int nz, int kz) { return ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + kz - 1) / kz); }

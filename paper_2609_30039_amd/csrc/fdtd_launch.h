@@ -22,12 +22,22 @@ struct MonDev {
 };
 
 // One stepping launch over all domains: kernel 1 = split, 2 = fused; rows =
-// register-blocked rows per wave of the fused kernel; kz = z chunk; bs =
-// device prefix sums of blocks per domain (ndom + 1 entries).
+// register-blocked rows per wave of the fused kernels; kz = z chunk.
+// Split: bs = device prefix sums of blocks per domain (ndom + 1 entries).
+// Fused: tile tables (domain, X0, Y0, k0) of general and bulk tiles.
 struct LaunchCfg {
     int kernel, rows, kz, nblk, ndom;
     const int* bs;
+    int ngen, nbulk;           // adjoint: general tiles, interior (bulk) tiles
+    const int4* tgen;
+    const int4* tbulk;
+    int nfgen, nfcp, nfplain;  // forward: Lorentz tiles, absorber tiles, all other tiles
+    const int4* tfgen;
+    const int4* tfcp;
+    const int4* tfplain;
 };
+
+constexpr int kFusedWaves = 4;
 
 template <typename T>
 void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s);
@@ -42,7 +52,6 @@ void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t 
 template <typename T>
 void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t s);
 
-int fused_blocks(int nx, int ny, int nz, int rows, int kz);
 int split_blocks(int nx, int ny, int nz, int kz);
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -137,6 +137,8 @@ struct Handle : Base {
     int* d_bs = nullptr;
     LaunchCfg cfg{};
     std::vector<int> bs_host;
+    std::vector<int4> tiles_gen, tiles_bulk, tiles_fgen, tiles_fcp, tiles_fplain;
+    int4* d_tiles = nullptr;
     // pool: [misc][forward sets x nsets][adjoint sets x 2][split scratch][bf16 slots]
     char* pool = nullptr;
     size_t pool_bytes = 0, misc_bytes = 0, fstride = 0, astride = 0, et_bytes = 0, bfslot = 0;
@@ -186,6 +188,72 @@ struct Handle : Base {
     }
 
     char* set_ptr(int q) { return fbase + (size_t)q * fstride; }
+
+    // ------------------------------------------------------------ tiles
+    // Split kernels: prefix sums of 64 x 4 column blocks per domain.  Fused
+    // kernels: tiles of 64 x-columns (62 owned) by 4R rows (4R - 2 owned) by
+    // kz planes, listed as bulk when they lie inside the domain away from
+    // PEC nodes, absorbers, the Lorentz box and sources, general otherwise.
+    void build_tiles() {
+        bs_host.assign(ndom + 1, 0);
+        tiles_gen.clear();
+        tiles_bulk.clear();
+        tiles_fgen.clear();
+        tiles_fcp.clear();
+        tiles_fplain.clear();
+        const int R = cfg.rows, NR = kFusedWaves * R, TYo = NR - 2, kz = cfg.kz;
+        for (int q = 0; q < ndom; ++q) {
+            const fdtd_domain_desc& s = dh[q].desc;
+            const int nx = s.n[0], ny = s.n[1], nz = s.n[2];
+            bs_host[q + 1] = bs_host[q] + split_blocks(nx, ny, nz, kz);
+            if (cfg.kernel == 1) continue;
+            for (int bz = 0; bz * kz < nz; ++bz)
+                for (int by = 0; by * TYo < ny; ++by)
+                    for (int bx = 0; bx * 62 < nx; ++bx) {
+                        int X0 = bx * 62 - 1, Y0 = by * TYo - 1, k0 = bz * kz, k1 = std::min(k0 + kz, nz);
+                        int lo[3] = {X0, Y0, k0 - 1}, hi[3] = {X0 + 63, Y0 + NR - 1, k1};
+                        bool lor = false;
+                        if (s.n_lorentz) {
+                            const fdtd_lorentz_desc& L = s.lorentz;
+                            lor = true;
+                            for (int a = 0; a < 3; ++a)
+                                if (hi[a] < L.lo[a] || lo[a] >= L.hi[a]) lor = false;
+                        }
+                        bool cp = false;
+                        for (int a = 0; a < 3; ++a)
+                            if ((s.pml[2 * a] > 0 && lo[a] < s.pml[2 * a]) ||
+                                (s.pml[2 * a + 1] > 0 && hi[a] >= s.n[a] - s.pml[2 * a + 1]))
+                                cp = true;
+                        (lor ? tiles_fgen : (cp ? tiles_fcp : tiles_fplain)).push_back(make_int4(q, X0, Y0, k0));
+                        bool bulk = X0 >= 1 && hi[0] <= nx - 1 && Y0 >= 1 && hi[1] <= ny - 1 && k0 >= 1 &&
+                                    k1 <= nz - 1;
+                        for (int a = 0; a < 3 && bulk; ++a)
+                            if (lo[a] < s.pml[2 * a] || hi[a] >= s.n[a] - s.pml[2 * a + 1]) bulk = false;
+                        if (bulk && s.n_lorentz) {
+                            const fdtd_lorentz_desc& L = s.lorentz;
+                            bool meet = true;
+                            for (int a = 0; a < 3; ++a)
+                                if (hi[a] < L.lo[a] || lo[a] >= L.hi[a]) meet = false;
+                            if (meet) bulk = false;
+                        }
+                        for (int k = 0; k < s.n_sources && bulk; ++k) {
+                            const fdtd_source_desc& sr = s.sources[k];
+                            bool zin = sr.pos[2] >= lo[2] && sr.pos[2] <= hi[2];
+                            bool xyin = sr.kind == FDTD_SRC_PLANE_Z ||
+                                        (sr.pos[0] >= lo[0] && sr.pos[0] <= hi[0] && sr.pos[1] >= lo[1] &&
+                                         sr.pos[1] <= hi[1]);
+                            if (zin && xyin) bulk = false;
+                        }
+                        (bulk ? tiles_bulk : tiles_gen).push_back(make_int4(q, X0, Y0, k0));
+                    }
+        }
+        cfg.nblk = bs_host[ndom];
+        cfg.ngen = (int)tiles_gen.size();
+        cfg.nbulk = (int)tiles_bulk.size();
+        cfg.nfgen = (int)tiles_fgen.size();
+        cfg.nfcp = (int)tiles_fcp.size();
+        cfg.nfplain = (int)tiles_fplain.size();
+    }
 
     // ------------------------------------------------------------ layout
     // Places every array in its arena.  Forward state arrays of all domains form
@@ -281,6 +349,8 @@ struct Handle : Base {
         }
         M.take(d_doms, sizeof(DomDev<T>) * ndom);
         M.take(d_bs, sizeof(int) * (ndom + 1));
+        M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
+                                                               tiles_fcp.size() + tiles_fplain.size()));
         M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
         M.take(d_sum, 8);
     }
@@ -310,6 +380,7 @@ struct Handle : Base {
             init_scalars(q);
         }
         nsets = 2 + (bf16 ? 0 : o->n_ckpt);
+        build_tiles();
         // ---- size the arenas
         Arena M, F, A, X;
         layout(M, F, A, X);
@@ -356,16 +427,12 @@ struct Handle : Base {
         wset[0] = 0;
         wset[1] = 1;
         cur = 0;
-        // tile table
-        bs_host.assign(n + 1, 0);
-        for (int q = 0; q < n; ++q) {
-            const fdtd_domain_desc& s = dh[q].desc;
-            int nb = cfg.kernel == 1 ? split_blocks(s.n[0], s.n[1], s.n[2], cfg.kz)
-                                     : fused_blocks(s.n[0], s.n[1], s.n[2], cfg.rows, cfg.kz);
-            bs_host[q + 1] = bs_host[q] + nb;
-        }
-        cfg.nblk = bs_host[n];
         cfg.bs = d_bs;
+        cfg.tgen = d_tiles;
+        cfg.tbulk = cfg.tgen + tiles_gen.size();
+        cfg.tfgen = cfg.tbulk + tiles_bulk.size();
+        cfg.tfcp = cfg.tfgen + tiles_fgen.size();
+        cfg.tfplain = cfg.tfcp + tiles_fcp.size();
         // ---- initialise: zero everything, upload tables and inputs
         launch_zero(pool, pool_bytes, st);
         int rc = check("zero pool");
@@ -400,6 +467,16 @@ struct Handle : Base {
         if (hipMemcpyAsync(d_doms, dd.data(), sizeof(DomDev<T>) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(d_bs, bs_host.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
             return fail(FDTD_E_DEVICE, "upload descriptors failed");
+        {
+            std::vector<int4> all(tiles_gen);
+            all.insert(all.end(), tiles_bulk.begin(), tiles_bulk.end());
+            all.insert(all.end(), tiles_fgen.begin(), tiles_fgen.end());
+            all.insert(all.end(), tiles_fcp.begin(), tiles_fcp.end());
+            all.insert(all.end(), tiles_fplain.begin(), tiles_fplain.end());
+            if (!all.empty() && hipMemcpyAsync(d_tiles, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice,
+                                               st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "upload tile tables failed");
+        }
         return sync("create");
     }
 
@@ -1108,6 +1185,39 @@ int fdtd_kernel_timing(fdtd_t h, int32_t op, double* total_ms, int64_t* launches
     long long n = 0;
     int rc = h->impl->timing(op, total_ms, &n);
     if (launches) *launches = n;
+    return rc;
+}
+
+int fdtd_copy_probe(size_t bytes, int32_t reps, double* ms_per_copy) {
+    if (bytes == 0 || bytes % 4 || reps < 1 || !ms_per_copy) return FDTD_E_INVALID;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return FDTD_E_NOMEM;
+    }
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(a);
+        return FDTD_E_NOMEM;
+    }
+    hipEvent_t e0, e1;
+    int rc = FDTD_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = FDTD_E_DEVICE;
+    if (!rc) {
+        launch_zero(a, bytes, nullptr);
+        launch_copy(a, b, bytes, nullptr);   // warm-up
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; ++r) launch_copy(a, b, bytes, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+        float ms = 0;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = FDTD_E_DEVICE;
+        *ms_per_copy = ms / reps;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    (void)hipFree(a);
+    (void)hipFree(b);
     return rc;
 }
 

@@ -15,11 +15,24 @@ pytestmark = pytest.mark.gpu
 
 
 def _case(n_steps=160):
-    spec = W.lorentz_flux(pml=6, lorentz=10, n_steps=n_steps, n_f=6, shape=(133, 37, 45))
+    """CPML, a Lorentz box off to one side, sheet source, flux and patch monitors;
+    large enough to hold bulk tiles for every tile shape tested."""
+    spec = W.lorentz_flux(pml=6, lorentz=8, n_steps=n_steps, n_f=6, shape=(190, 62, 58))
     nx, ny, nz = spec.shape
+    lo, hi = (9, 8, 40), (17, 16, 48)
+    spec.lorentz[0].lo, spec.lorentz[0].hi = lo, hi
+    spec.eps_box = (lo, hi)
     spec.monitors.append(W.MonitorSpec("patch_z", comp=2, pos=(0, 0, nz - 12), rect=(20, 90, 5, 30),
                                        omega_dt=W.freq_grid(4)))
     spec.grad_box = ((6, 6, 6), (nx - 6, ny - 6, nz - 6))
+    return spec
+
+
+def _case_design(n_steps=100):
+    """Random eps design box partly covering interior tiles, no Lorentz."""
+    spec, _ = W.design_patch(pml=6, design=40, patch=20, n_steps=n_steps, n_f=4, shape=(190, 62, 58))
+    nx, ny, nz = spec.shape
+    spec.grad_box = ((30, 10, 12), (150, 50, 40))
     return spec
 
 
@@ -35,28 +48,30 @@ def _cot(mi, m, sp):
     return 2.0 * np.asarray(sp)
 
 
+@pytest.mark.parametrize("case", ["lorentz", "design"])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_fused_equals_split_forward(dtype):
-    spec = _case()
+def test_fused_equals_split_forward(dtype, case):
+    spec = _case() if case == "lorentz" else _case_design()
     runs = []
     for kern, rows, kz in (("split", 0, 0), ("fused", 4, 16), ("fused", 2, 7), ("fused", 8, 32)):
         sim = Simulation(spec, dtype=dtype, kernel=kern, tile_rows=rows, tile_kz=kz)
         sim.step(spec.n_steps)
-        runs.append((_fields(sim), sim.spectra(0), sim.spectra(1)))
+        runs.append((_fields(sim), [sim.spectra(mi) for mi in range(len(spec.monitors))]))
     for other in runs[1:]:
         for q in range(6):
             assert np.array_equal(runs[0][0][q], other[0][q]), W.COMP_NAMES[q]
-        assert np.array_equal(runs[0][1], other[1])
-        assert np.array_equal(runs[0][2], other[2])
+        for a, b in zip(runs[0][1], other[1]):
+            assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("case", ["lorentz", "design"])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_fused_equals_split_adjoint(dtype):
-    spec = _case(n_steps=60)
+def test_fused_equals_split_adjoint(dtype, case):
+    spec = _case(n_steps=60) if case == "lorentz" else _case_design(n_steps=60)
     g = {}
-    for kern in ("split", "fused"):
+    for kern, rows in (("split", 0), ("fused", 2), ("fused", 4)):
         N = spec.n_steps
-        sim = Simulation(spec, dtype=dtype, kernel=kern, n_ckpt=N + 1)
+        sim = Simulation(spec, dtype=dtype, kernel=kern, n_ckpt=N + 1, tile_rows=rows)
         sim.save(0)
         for t in range(N):
             sim.step(1)
@@ -67,10 +82,12 @@ def test_fused_equals_split_adjoint(dtype):
         for m_ in range(N, 0, -1):
             sim.restore(m_ - 1)
             sim.step_adjoint(1)
-        g[kern] = (sim.grad(), [sim.field(q, adjoint=True) for q in range(6)])
-    assert np.array_equal(g["split"][0], g["fused"][0])
-    for q in range(6):
-        assert np.array_equal(g["split"][1][q], g["fused"][1][q])
+        g[(kern, rows)] = (sim.grad(), [sim.field(q, adjoint=True) for q in range(6)])
+    ref = g[("split", 0)]
+    for key, val in g.items():
+        assert np.array_equal(ref[0], val[0]), key
+        for q in range(6):
+            assert np.array_equal(ref[1][q], val[1][q]), (key, q)
 
 
 @pytest.mark.parametrize("slots", [2, 5, 16])
