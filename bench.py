@@ -10,7 +10,7 @@ the FP64 oracle on the host cores, the FP64 GPU path, the adjoint sweep with
 binomial replay on the 192^3 + CPML design-patch workload, and a 512^3 + CPML
 forward whose working set is far beyond the on-die cache.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--shape K,R,Z]
 """
 import argparse
 import hashlib
@@ -40,7 +40,7 @@ def kernel_source_hash():
 def traffic_from_profiles(kernel_hash):
     """HBM bytes per launch of the dominant kernel from committed PMC summaries,
     only if they were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "fwd_fused_c2_pmc.json")
+    p = os.path.join(ROOT, "profiles", "fwd_lorentz_flux_f32_pmc.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--shape", default=None,
+                    help="launch shape KERNEL,ROWS,KZ for the headline (skips the autotuner), e.g. split,0,8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path is single-GPU (no collectives); --gpus {args.gpus} is not "
@@ -102,16 +104,23 @@ def main():
     K, Wm = args.steps, args.warmup
     khash = kernel_source_hash()
 
+    from paper_2609_30039_amd import autotune as AT
+
     # ---------------------------------------------------------------- headline
-    spec = W.c2()
+    spec = W.lorentz_flux()
     ncell = spec.ncells
-    log(f"c2 FP32 forward: {spec.shape} x {spec.n_steps} steps, warmup {Wm}, timed {K}")
-    sim32, el, kms, nl = run_forward(spec, "f32", stream, K, Wm)
+    if args.shape:
+        kk, rr, zz = args.shape.split(",")
+        tile = {"kernel": kk, "tile_rows": int(rr), "tile_kz": int(zz)}
+    else:
+        tile = AT.tune(spec, "f32", stream=stream, log=log)
+    log(f"lorentz_flux FP32 forward: {spec.shape} x {spec.n_steps} steps, warmup {Wm}, timed {K}, launch shape {tile}")
+    sim32, el, kms, nl = run_forward(spec, "f32", stream, K, Wm, tile)
     mcups = ncell * spec.n_steps * K / el / 1e6
     avg_ms = kms / nl
     bytes_launch = RL.forward_bytes(spec, 4)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    log(f"c2 FP32: {el / K * 1e3:.2f} ms/solve, {mcups:.0f} Mcell-upd/s, kernel {avg_ms * 1e3:.1f} us/launch, "
+    log(f"lorentz_flux FP32: {el / K * 1e3:.2f} ms/solve, {mcups:.0f} Mcell-upd/s, kernel {avg_ms * 1e3:.1f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic")
     traffic = traffic_from_profiles(khash)
     out = {
@@ -133,7 +142,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
-                     "kernel": "k_fwd_fused (one launch per time step)",
+                     "kernel": ("k_fwd_e + k_fwd_h (split)" if tile["kernel"] == "split" else
+                                "fused single-pass tile kernels") + " per time step",
+                     "launch_shape": tile,
                      "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_source_hash": khash},
     }
@@ -167,8 +178,9 @@ def main():
 
     if not args.no_extra:
         # ------------------------------------------------------------ FP64 path and FP32 accuracy at 1000 steps
-        log("c2 FP64 forward")
-        sim64, el64, kms64, nl64 = run_forward(spec, "f64", stream, 1, 1)
+        tile64 = AT.tune(spec, "f64", stream=stream, log=log)
+        log(f"lorentz_flux FP64 forward, launch shape {tile64}")
+        sim64, el64, kms64, nl64 = run_forward(spec, "f64", stream, 1, 1, tile64)
         out["fp64"] = {"value": round(ncell * spec.n_steps / el64 / 1e6, 1), "unit": "Mcell-updates/s",
                        "ms_per_solve": round(el64 * 1e3, 2),
                        "achieved_GBs": round(RL.forward_bytes(spec, 8) / (kms64 / nl64 * 1e-3) / 1e9, 1)}
@@ -182,8 +194,8 @@ def main():
         del sim64
 
         # ------------------------------------------------------------ adjoint (192^3 + CPML, 2000 steps, 24 slots)
-        spec3, fd_cells = W.c3()
-        log(f"c3 adjoint: {spec3.shape} x {spec3.n_steps}, 24 checkpoint slots")
+        spec3, fd_cells = W.design_patch()
+        log(f"design_patch adjoint: {spec3.shape} x {spec3.n_steps}, 24 checkpoint slots")
 
         def cot(s):
             sp = s.spectra(0)
@@ -191,7 +203,8 @@ def main():
 
         grads = {}
         for dt in ("f32", "f64"):
-            sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream)
+            tile3 = AT.tune(spec3, dt, adjoint=True, stream=stream, log=log)
+            sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream, **tile3)
             plan = A.RevolvePlan(spec3.n_steps, 24)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -217,23 +230,24 @@ def main():
                     "reverse_over_forward": round(tr / tf, 3),
                     "adjoint_mcups": round(n3 * spec3.n_steps / tr / 1e6, 1),
                     "forward_mcups": round(n3 * spec3.n_steps / tf / 1e6, 1),
-                    "forward_evaluations": plan.forward_evals + 1,
+                    "forward_evaluations": plan.forward_evals + 1, "launch_shape": tile3,
                     "stepping_kernel_ms": round(akms, 2), "stepping_launches": anl}
             else:
                 out["adjoint"]["fp64_reverse_s"] = round(tr, 4)
                 out["adjoint"]["fp64_forward_s"] = round(tf, 4)
-            log(f"c3 {dt}: forward {tf:.3f} s, reverse {tr:.3f} s")
+            log(f"design_patch {dt}: forward {tf:.3f} s, reverse {tr:.3f} s")
             del sim3
         g32, g64 = grads["f32"], grads["f64"]
         out["adjoint"]["grad_rel_l2_fp32_vs_fp64"] = float(f"{np.linalg.norm(g32 - g64) / np.linalg.norm(g64):.3e}")
 
         # ------------------------------------------------------------ large forward (cache-free roofline)
-        spec5 = W.c5()
+        spec5 = W.anisotropic_lorentz()
         spec5.n_steps = 200
         for s_ in spec5.sources:
             s_.waveform = s_.waveform[:200]
-        log(f"c5-shape forward: {spec5.shape} x 200 steps")
-        sim5, el5, kms5, nl5 = run_forward(spec5, "f32", stream, 1, 1)
+        tile5 = AT.tune(spec5, "f32", stream=stream, log=log, steps=3)
+        log(f"anisotropic_lorentz forward: {spec5.shape} x 200 steps, launch shape {tile5}")
+        sim5, el5, kms5, nl5 = run_forward(spec5, "f32", stream, 1, 1, tile5)
         b5 = RL.forward_bytes(spec5, 4)
         out["large_forward"] = {
             "workload": "536^3 (512^3 + 12-cell CPML), diagonal eps, 128^3 Lorentz box, Ex sheet, Ex patch "
@@ -241,7 +255,7 @@ def main():
             "mcups": round(spec5.ncells * 200 / el5 / 1e6, 1),
             "avg_launch_us": round(kms5 / nl5 * 1e3, 1),
             "achieved_GBs": round(b5 / (kms5 / nl5 * 1e-3) / 1e9, 1),
-            "frac_hbm": round(b5 / (kms5 / nl5 * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4)}
+            "frac_hbm": round(b5 / (kms5 / nl5 * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4), "launch_shape": tile5}
         del sim5
 
     print(json.dumps(out), flush=True)

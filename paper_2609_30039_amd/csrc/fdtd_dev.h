@@ -126,7 +126,7 @@ __device__ __forceinline__ T epsinv_at(const DomDev<T>& d, int c, int i, int j, 
     if (in_box<T>(d.elo, d.ehi, i, j, k)) {
         long long q = ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) * (d.ehi[0] - d.elo[0]) +
                       (i - d.elo[0]);
-        return d.epsinv[c][q];
+        return gp(d.epsinv[c])[q];
     }
     return d.epsinv_bg;
 }
@@ -158,10 +158,10 @@ __device__ __forceinline__ T stretch(const DomDev<T>& d, T* const (&psi)[3][2][2
     int x = coord(a, i, j, k);
     int s = slab_side(d, a, x);
     if (s < 0) return D;
-    const T* tb = d.tab[a];
+    const FDTD_GLOBAL T* tb = gp(d.tab[a]);
     int n = d.n[a];
     T b = tb[(toff + 0) * n + x], c = tb[(toff + 1) * n + x], ki = tb[(toff + 2) * n + x];
-    T* base = psi[a][s][r] + pidx(d, a, s, i, j, k);
+    FDTD_GLOBAL T* base = gp(psi[a][s][r]) + pidx(d, a, s, i, j, k);
     T pn = fma(b, base[rs * stride], c * D);
     if (own) base[ws * stride] = pn;
     return fma(ki, D, pn);
@@ -179,9 +179,9 @@ __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, i
     if (e_masked(c, i, j, k)) {
         if (own && lorc) {
             long long q = lidx(d, i, j, k) + ws * fs;
-            d.lor[0][c][q] = T(0);
-            d.lor[1][c][q] = T(0);
-            d.lor[2][c][q] = T(0);
+            gp(d.lor[0][c])[q] = T(0);
+            gp(d.lor[1][c])[q] = T(0);
+            gp(d.lor[2][c])[q] = T(0);
         }
         return T(0);
     }
@@ -190,15 +190,15 @@ __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, i
     T D1 = stretch(d, d.psiE, fs, rs, ws, own, a1, 1, 0, i, j, k, h1 - h1m);
     T curl = D0 - D1;
     T einv = epsinv_at(d, c, i, j, k);
-    T e = d.E[c][f + rs * fs];
+    T e = gp(d.E[c])[f + rs * fs];
     T en;
     long long q = 0;
     T eold = 0, w = 0, wold = 0;
     if (lorc) {
         q = lidx(d, i, j, k);
-        eold = d.lor[0][c][q + rs * fs];
-        w = d.lor[1][c][q + rs * fs];
-        wold = d.lor[2][c][q + rs * fs];
+        eold = gp(d.lor[0][c])[q + rs * fs];
+        w = gp(d.lor[1][c])[q + rs * fs];
+        wold = gp(d.lor[2][c])[q + rs * fs];
         T einf = T(1) / einv;
         T invden = T(1) / (einf + T(0.25) * d.lg);
         T num = fma(einf, e, T(0.25) * d.lg * eold);
@@ -210,14 +210,14 @@ __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, i
     }
     for (int s = 0; s < d.nsrc; ++s) {
         const SrcDev<T>& sr = d.src[s];
-        if (sr.comp == c && t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) en += sr.wave[t];
+        if (sr.comp == c && t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) en += gp(sr.wave)[t];
     }
     if (own && lorc) {
         T wn = fma(d.lal, w, d.lxi * wold);
         wn = fma(T(0.5) * d.lg, en - eold, wn);
-        d.lor[0][c][q + ws * fs] = e;
-        d.lor[1][c][q + ws * fs] = wn;
-        d.lor[2][c][q + ws * fs] = w;
+        gp(d.lor[0][c])[q + ws * fs] = e;
+        gp(d.lor[1][c])[q + ws * fs] = wn;
+        gp(d.lor[2][c])[q + ws * fs] = w;
     }
     return en;
 }
@@ -227,7 +227,7 @@ template <typename T>
 __device__ __forceinline__ T e_bulk(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m, T h1,
                                     T h1m, int rs) {
     T curl = (h0 - h0m) - (h1 - h1m);
-    return fma(d.S * epsinv_at(d, c, i, j, k), curl, d.E[c][f + rs * d.fs]);
+    return fma(d.S * epsinv_at(d, c, i, j, k), curl, gp(d.E[c])[f + rs * d.fs]);
 }
 
 // H^{n+3/2}_c at node (i,j,k) from E^{n+1}: e0p/e0 = E_{c+2} one step forward
@@ -269,10 +269,10 @@ __device__ __forceinline__ T stretch_T(const DomDev<T>& d, T* const (&psi)[3][2]
     int x = coord(a, i, j, k);
     int s = slab_side(d, a, x);
     if (s < 0) return ybar;
-    const T* tb = d.tab[a];
+    const FDTD_GLOBAL T* tb = gp(d.tab[a]);
     int n = d.n[a];
     T b = tb[(toff + 0) * n + x], c = tb[(toff + 1) * n + x], ki = tb[(toff + 2) * n + x];
-    T* base = psi[a][s][r] + pidx(d, a, s, i, j, k);
+    FDTD_GLOBAL T* base = gp(psi[a][s][r]) + pidx(d, a, s, i, j, k);
     T mem = base[rs * d.as] + ybar;
     if (own) base[ws * d.as] = b * mem;
     return fma(ki, ybar, c * mem);
@@ -306,23 +306,23 @@ __device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int
     if (e_masked(c, i, j, k)) {
         if (own && in_lor(d, i, j, k)) {
             long long q = lidx(d, i, j, k) + ws * as;
-            d.lora[0][c][q] = T(0);
-            d.lora[1][c][q] = T(0);
-            d.lora[2][c][q] = T(0);
+            gp(d.lora[0][c])[q] = T(0);
+            gp(d.lora[1][c])[q] = T(0);
+            gp(d.lora[2][c])[q] = T(0);
         }
         return r;
     }
     T einv = epsinv_at(d, c, i, j, k);
     if (in_lor(d, i, j, k)) {
         long long q = lidx(d, i, j, k);
-        T wb = d.lora[1][c][q + rs * as];
+        T wb = gp(d.lora[1][c])[q + rs * as];
         T einf = T(1) / einv;
         T invden = T(1) / (einf + T(0.25) * d.lg);
         T ep = fma(T(0.5) * d.lg, wb, etot);      // W^{n+1} roll feeds E^{n+1}
         r.epre = ep;
         r.coef = invden;
         if (own) {
-            T wob = d.lora[2][c][q + rs * as], eob = d.lora[0][c][q + rs * as];
+            T wob = gp(d.lora[2][c])[q + rs * as], eob = gp(d.lora[0][c])[q + rs * as];
             T wn = fma(d.lal, wb, wob);
             T wnm1 = d.lxi * wb;
             T enm1 = -T(0.5) * d.lg * wb;
@@ -331,9 +331,9 @@ __device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int
             enm1 = fma(T(0.25) * d.lg, s, enm1);
             wn = fma(-T(0.5) * (T(1) + d.lal), s, wn);
             wnm1 = fma(-T(0.5) * d.lxi, s, wnm1);
-            d.lora[0][c][q + ws * as] = enm1;
-            d.lora[1][c][q + ws * as] = wn;
-            d.lora[2][c][q + ws * as] = wnm1;
+            gp(d.lora[0][c])[q + ws * as] = enm1;
+            gp(d.lora[1][c])[q + ws * as] = wn;
+            gp(d.lora[2][c])[q + ws * as] = wnm1;
         }
     } else {
         r.epre = etot;
@@ -360,8 +360,8 @@ __device__ __forceinline__ double grad_term(const DomDev<T>& d, int c, int i, in
     T einv = epsinv_at(d, c, i, j, k);
     if (in_lor(d, i, j, k)) {
         long long q = lidx(d, i, j, k) + fsr * d.fs;
-        T e = d.E[c][f + fsr * d.fs];
-        T eold = d.lor[0][c][q], w = d.lor[1][c][q], wold = d.lor[2][c][q];
+        T e = gp(d.E[c])[f + fsr * d.fs];
+        T eold = gp(d.lor[0][c])[q], w = gp(d.lor[1][c])[q], wold = gp(d.lor[2][c])[q];
         T einf = T(1) / einv;
         T invden = T(1) / (einf + T(0.25) * d.lg);
         T num = fma(einf, e, T(0.25) * d.lg * eold);
@@ -383,11 +383,11 @@ __device__ __forceinline__ void grad_store(const DomDev<T>& d, int i, int j, int
     long long q = ((long long)(k - d.glo[2]) * (d.ghi[1] - d.glo[1]) + (j - d.glo[1])) * (d.ghi[0] - d.glo[0]) +
                   (i - d.glo[0]);
     if (d.eps_diag) {
-        d.gacc[0][q] += g[0];
-        d.gacc[1][q] += g[1];
-        d.gacc[2][q] += g[2];
+        gp(d.gacc[0])[q] += g[0];
+        gp(d.gacc[1])[q] += g[1];
+        gp(d.gacc[2])[q] += g[2];
     } else {
-        d.gacc[0][q] += (g[0] + g[1]) + g[2];
+        gp(d.gacc[0])[q] += (g[0] + g[1]) + g[2];
     }
 }
 

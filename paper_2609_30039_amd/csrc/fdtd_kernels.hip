@@ -79,9 +79,9 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
     const long long ro = rs * d.fs, wo = ws * d.fs;
-    const T* Hx = d.H[0] + ro;
-    const T* Hy = d.H[1] + ro;
-    const T* Hz = d.H[2] + ro;
+    const FDTD_GLOBAL T* Hx = gp(d.H[0] + ro);
+    const FDTD_GLOBAL T* Hy = gp(d.H[1] + ro);
+    const FDTD_GLOBAL T* Hz = gp(d.H[2] + ro);
     T hxm = 0, hym = 0;   // Hx, Hy one plane below
     if (c.k0 > 0) {
         long long f = fidx(d, i, j, c.k0 - 1);
@@ -97,9 +97,9 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
         T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
         T ey = e_update(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, rs, ws, true, t);
         T ez = e_update(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, rs, ws, true, t);
-        d.E[0][f + wo] = ex;
-        d.E[1][f + wo] = ey;
-        d.E[2][f + wo] = ez;
+        gp(d.E[0])[f + wo] = ex;
+        gp(d.E[1])[f + wo] = ey;
+        gp(d.E[2])[f + wo] = ez;
         hxm = hx;
         hym = hy;
     }
@@ -115,9 +115,9 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j, nx = d.n[0], ny = d.n[1], nz = d.n[2];
     const long long ro = rs * d.fs, wo = ws * d.fs;
-    const T* Ex = d.E[0] + wo;
-    const T* Ey = d.E[1] + wo;
-    const T* Ez = d.E[2] + wo;
+    const FDTD_GLOBAL T* Ex = gp(d.E[0] + wo);
+    const FDTD_GLOBAL T* Ey = gp(d.E[1] + wo);
+    const FDTD_GLOBAL T* Ez = gp(d.E[2] + wo);
     long long f0 = fidx(d, i, j, c.k0);
     T ex = Ex[f0], ey = Ey[f0], ez = Ez[f0];
     for (int k = c.k0; k < c.k1; ++k) {
@@ -131,9 +131,9 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
         T ey_xp = i + 1 < nx ? Ey[f + 1] : T(0), ez_xp = i + 1 < nx ? Ez[f + 1] : T(0);
         T ex_yp = j + 1 < ny ? Ex[f + d.pitch] : T(0), ez_yp = j + 1 < ny ? Ez[f + d.pitch] : T(0);
         // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
-        d.H[0][f + wo] = h_update(d, 0, i, j, k, d.H[0][f + ro], ez_yp, ez, ey1, ey, rs, ws, true);
-        d.H[1][f + wo] = h_update(d, 1, i, j, k, d.H[1][f + ro], ex1, ex, ez_xp, ez, rs, ws, true);
-        d.H[2][f + wo] = h_update(d, 2, i, j, k, d.H[2][f + ro], ey_xp, ey, ex_yp, ex, rs, ws, true);
+        gp(d.H[0])[f + wo] = h_update(d, 0, i, j, k, gp(d.H[0])[f + ro], ez_yp, ez, ey1, ey, rs, ws, true);
+        gp(d.H[1])[f + wo] = h_update(d, 1, i, j, k, gp(d.H[1])[f + ro], ex1, ex, ez_xp, ez, rs, ws, true);
+        gp(d.H[2])[f + wo] = h_update(d, 2, i, j, k, gp(d.H[2])[f + ro], ey_xp, ey, ex_yp, ex, rs, ws, true);
         ex = ex1;
         ey = ey1;
         ez = ez1;
@@ -148,7 +148,7 @@ __device__ __forceinline__ T ht_update(const DomDev<T>& d, int e, int i, int j, 
     if (e_masked(e, i, j, k)) return T(0);
     // term 1: H_{e+1} along e+2 (+, slot 0); term 2: H_{e+2} along e+1 (-, slot 1)
     const int a1 = (e + 2) % 3, a2 = (e + 1) % 3;
-    T acc = d.Ea[e][f + rs * d.as];
+    T acc = gp(d.Ea[e])[f + rs * d.as];
     T t1 = hT_dbar(d, a1, 0, T(1), i, j, k, hb1, rs, rs, false);
     T t1m = coord(a1, i, j, k) > 0
                 ? hT_dbar(d, a1, 0, T(1), i - (a1 == 0), j - (a1 == 1), k - (a1 == 2), hb1m, rs, rs, false)
@@ -172,9 +172,9 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
     if (!d.grad) return;
     const int i = c.i, j = c.j;
     const long long ro = rs * d.as;
-    const T* Hx = d.Ha[0] + ro;
-    const T* Hy = d.Ha[1] + ro;
-    const T* Hz = d.Ha[2] + ro;
+    const FDTD_GLOBAL T* Hx = gp(d.Ha[0] + ro);
+    const FDTD_GLOBAL T* Hy = gp(d.Ha[1] + ro);
+    const FDTD_GLOBAL T* Hz = gp(d.Ha[2] + ro);
     T hxm = 0, hym = 0;
     if (c.k0 > 0) {
         long long f = fidx(d, i, j, c.k0 - 1);
@@ -187,9 +187,9 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
         T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
         T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
         // Ex: Hy along z, Hz along y ; Ey: Hz along x, Hx along z ; Ez: Hx along y, Hy along x
-        d.Et[0][f] = ht_update(d, 0, i, j, k, f, hy, hym, hz, hz_ym, rs);
-        d.Et[1][f] = ht_update(d, 1, i, j, k, f, hz, hz_xm, hx, hxm, rs);
-        d.Et[2][f] = ht_update(d, 2, i, j, k, f, hx, hx_ym, hy, hy_xm, rs);
+        gp(d.Et[0])[f] = ht_update(d, 0, i, j, k, f, hy, hym, hz, hz_ym, rs);
+        gp(d.Et[1])[f] = ht_update(d, 1, i, j, k, f, hz, hz_xm, hx, hxm, rs);
+        gp(d.Et[2])[f] = ht_update(d, 2, i, j, k, f, hx, hx_ym, hy, hy_xm, rs);
         hxm = hx;
         hym = hy;
     }
@@ -214,11 +214,11 @@ __device__ __forceinline__ Dbar6<T> et_cell(const DomDev<T>& d, int i, int j, in
     T H[3] = {0, 0, 0}, Hm[3][3];   // forward H at the node and one step back along x, y, z
     if (ing) {
         const long long fo = fsr * d.fs;
-        for (int q = 0; q < 3; ++q) H[q] = d.H[q][f + fo];
+        for (int q = 0; q < 3; ++q) H[q] = gp(d.H[q])[f + fo];
         for (int q = 0; q < 3; ++q) {
-            Hm[0][q] = i > 0 ? d.H[q][f + fo - 1] : T(0);
-            Hm[1][q] = j > 0 ? d.H[q][f + fo - d.pitch] : T(0);
-            Hm[2][q] = k > 0 ? d.H[q][f + fo - d.plane] : T(0);
+            Hm[0][q] = i > 0 ? gp(d.H[q])[f + fo - 1] : T(0);
+            Hm[1][q] = j > 0 ? gp(d.H[q])[f + fo - d.pitch] : T(0);
+            Hm[2][q] = k > 0 ? gp(d.H[q])[f + fo - d.plane] : T(0);
         }
     }
     double g[3] = {0, 0, 0};
@@ -247,7 +247,7 @@ template <typename T>
 __device__ __forceinline__ T et_dbar_at(const DomDev<T>& d, int cc, int term, int i, int j, int k, int rs) {
     if (e_masked(cc, i, j, k)) return T(0);
     long long f = fidx(d, i, j, k);
-    AdjE<T> r = et_node(d, cc, i, j, k, d.Et[cc][f], rs, rs, false);
+    AdjE<T> r = et_node(d, cc, i, j, k, gp(d.Et[cc])[f], rs, rs, false);
     int a = term == 0 ? (cc + 1) % 3 : (cc + 2) % 3;
     return et_dbar(d, a, term, term == 0 ? T(1) : T(-1), i, j, k, r.epre, r.coef, rs, rs, false);
 }
@@ -265,12 +265,12 @@ __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ do
     const long long ro = rs * d.as, wo = ws * d.as;
     auto owner = [&](int k) -> Dbar6<T> {
         long long f = fidx(d, i, j, k);
-        T et[3] = {d.Et[0][f], d.Et[1][f], d.Et[2][f]};
+        T et[3] = {gp(d.Et[0])[f], gp(d.Et[1])[f], gp(d.Et[2])[f]};
         T en[3];
         Dbar6<T> o = et_cell(d, i, j, k, et, rs, ws, true, fsr, en);
-        d.Ea[0][f + wo] = en[0];
-        d.Ea[1][f + wo] = en[1];
-        d.Ea[2][f + wo] = en[2];
+        gp(d.Ea[0])[f + wo] = en[0];
+        gp(d.Ea[1])[f + wo] = en[1];
+        gp(d.Ea[2])[f + wo] = en[2];
         return o;
     };
     Dbar6<T> cur = owner(c.k0);
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ do
             yp_z1 = et_dbar_at(d, 2, 1, i, j + 1, k, rs);
             yp_x0 = et_dbar_at(d, 0, 0, i, j + 1, k, rs);
         }
-        T hbx = d.Ha[0][f + ro], hby = d.Ha[1][f + ro], hbz = d.Ha[2][f + ro];
+        T hbx = gp(d.Ha[0])[f + ro], hby = gp(d.Ha[1])[f + ro], hbz = gp(d.Ha[2])[f + ro];
         // memory cotangents of the H update at this node (input Hbar)
         hT_dbar(d, 1, 0, T(1), i, j, k, hbx, rs, ws, true);    // Hx term 0 along y
         hT_dbar(d, 2, 1, T(-1), i, j, k, hbx, rs, ws, true);   // Hx term 1 along z
@@ -308,9 +308,9 @@ __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ do
         hbx += (cur.y0 - up_y0) + (cur.z1 - yp_z1);
         hby += (cur.z0 - xp_z0) + (cur.x1 - up_x1);
         hbz += (cur.x0 - yp_x0) + (cur.y1 - xp_y1);
-        d.Ha[0][f + wo] = hbx;
-        d.Ha[1][f + wo] = hby;
-        d.Ha[2][f + wo] = hbz;
+        gp(d.Ha[0])[f + wo] = hbx;
+        gp(d.Ha[1])[f + wo] = hby;
+        gp(d.Ha[2])[f + wo] = hbz;
         cur = nxt;
     }
 }
@@ -384,8 +384,8 @@ __device__ __forceinline__ void fwd_fused_body(const DomDev<T>& d, const Tile& t
         for (int r = 0; r < R; ++r)
             if (vr[r]) {
                 long long f = fidx(d, i, jr[r], tl.k0 - 1) + ro;
-                Hk[r][0] = d.H[0][f];
-                Hk[r][1] = d.H[1][f];
+                Hk[r][0] = gp(d.H[0])[f];
+                Hk[r][1] = gp(d.H[1])[f];
             }
     for (int k = tl.k0 - 1; k < tl.k1; ++k) {
         const int kn = k + 1;             // plane of the E update
@@ -395,9 +395,9 @@ __device__ __forceinline__ void fwd_fused_body(const DomDev<T>& d, const Tile& t
             Hn[r][0] = Hn[r][1] = Hn[r][2] = T(0);
             if (vr[r] && have_n) {
                 long long f = fidx(d, i, jr[r], kn) + ro;
-                Hn[r][0] = d.H[0][f];
-                Hn[r][1] = d.H[1][f];
-                Hn[r][2] = d.H[2][f];
+                Hn[r][0] = gp(d.H[0])[f];
+                Hn[r][1] = gp(d.H[1])[f];
+                Hn[r][2] = gp(d.H[2])[f];
             }
         }
         const int pb = kn & 1;
@@ -427,9 +427,9 @@ __device__ __forceinline__ void fwd_fused_body(const DomDev<T>& d, const Tile& t
                     En[r][2] = e_bulk(d, 2, i, j, kn, f, Hn[r][1], hy_xm, Hn[r][0], hx_ym, rs);
                 }
                 if (o) {
-                    d.E[0][f + wo] = En[r][0];
-                    d.E[1][f + wo] = En[r][1];
-                    d.E[2][f + wo] = En[r][2];
+                    gp(d.E[0])[f + wo] = En[r][0];
+                    gp(d.E[1])[f + wo] = En[r][1];
+                    gp(d.E[2])[f + wo] = En[r][2];
                 }
             }
         }
@@ -456,9 +456,9 @@ __device__ __forceinline__ void fwd_fused_body(const DomDev<T>& d, const Tile& t
                         hy = h_bulk(d, Hk[r][1], En[r][0], Ek[r][0], ez_xp, Ek[r][2]);
                         hz = h_bulk(d, Hk[r][2], ey_xp, Ek[r][1], ex_yp, Ek[r][0]);
                     }
-                    d.H[0][f + wo] = hx;
-                    d.H[1][f + wo] = hy;
-                    d.H[2][f + wo] = hz;
+                    gp(d.H[0])[f + wo] = hx;
+                    gp(d.H[1])[f + wo] = hy;
+                    gp(d.H[2])[f + wo] = hz;
                 }
             }
         }
@@ -518,8 +518,8 @@ __device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& t
             if (vr[r]) {
                 const int kk = tl.k0 - 1;
                 long long f = fidx(d, i, jr[r], kk) + ro;
-                dHyz_k[r] = hT_dbar(d, 2, 0, T(1), i, jr[r], kk, d.Ha[1][f], rs, rs, false);
-                dHxz_k[r] = hT_dbar(d, 2, 1, T(-1), i, jr[r], kk, d.Ha[0][f], rs, rs, false);
+                dHyz_k[r] = hT_dbar(d, 2, 0, T(1), i, jr[r], kk, gp(d.Ha[1])[f], rs, rs, false);
+                dHxz_k[r] = hT_dbar(d, 2, 1, T(-1), i, jr[r], kk, gp(d.Ha[0])[f], rs, rs, false);
             }
     for (int k = tl.k0 - 1; k < tl.k1; ++k) {
         const int kn = k + 1;
@@ -533,9 +533,9 @@ __device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& t
             if (vr[r] && have_n) {
                 const int j = jr[r];
                 long long f = fidx(d, i, j, kn) + ro;
-                Hbn[r][0] = d.Ha[0][f];
-                Hbn[r][1] = d.Ha[1][f];
-                Hbn[r][2] = d.Ha[2][f];
+                Hbn[r][0] = gp(d.Ha[0])[f];
+                Hbn[r][1] = gp(d.Ha[1])[f];
+                Hbn[r][2] = gp(d.Ha[2])[f];
                 bool o = own[r] && hown_n;
                 dHxy[r] = hT_dbar(d, 1, 0, T(1), i, j, kn, Hbn[r][0], rs, ws, o);
                 dHxz[r] = hT_dbar(d, 2, 1, T(-1), i, j, kn, Hbn[r][0], rs, ws, o);
@@ -574,7 +574,7 @@ __device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& t
                         et[e] = T(0);
                         continue;
                     }
-                    T acc = d.Ea[e][f + ro];
+                    T acc = gp(d.Ea[e])[f + ro];
                     acc += t1m[e] - t1[e];
                     acc += t2m[e] - t2[e];
                     et[e] = acc;
@@ -582,9 +582,9 @@ __device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& t
                 T en[3];
                 Dn[r] = et_cell(d, i, j, kn, et, rs, ws, o, fsr, en);
                 if (o) {
-                    d.Ea[0][f + wo] = en[0];
-                    d.Ea[1][f + wo] = en[1];
-                    d.Ea[2][f + wo] = en[2];
+                    gp(d.Ea[0])[f + wo] = en[0];
+                    gp(d.Ea[1])[f + wo] = en[1];
+                    gp(d.Ea[2])[f + wo] = en[2];
                 }
             }
         }
@@ -604,9 +604,9 @@ __device__ __forceinline__ void adj_fused_body(const DomDev<T>& d, const Tile& t
                     hbx += (Dk[r].y0 - Dn[r].y0) + (Dk[r].z1 - z1_yp);
                     hby += (Dk[r].z0 - z0_xp) + (Dk[r].x1 - Dn[r].x1);
                     hbz += (Dk[r].x0 - x0_yp) + (Dk[r].y1 - y1_xp);
-                    d.Ha[0][f + wo] = hbx;
-                    d.Ha[1][f + wo] = hby;
-                    d.Ha[2][f + wo] = hbz;
+                    gp(d.Ha[0])[f + wo] = hbx;
+                    gp(d.Ha[1])[f + wo] = hby;
+                    gp(d.Ha[2])[f + wo] = hbz;
                 }
             }
         }
@@ -1347,16 +1347,18 @@ __global__ void k_sample(const DomDev<T>* __restrict__ doms, MonDev m, int cs, i
     if (q >= npts) return;
     int i = m.i0 + q % ni, j = m.j0 + q / ni, k = m.k;
     long long f = fidx(d, i, j, k) + cs * d.fs;
-    T* buf = (T*)m.samples + (long long)slot * m.ncomp * npts;
+    FDTD_GLOBAL T* buf = gp((T*)m.samples) + (long long)slot * m.ncomp * npts;
+    const FDTD_GLOBAL T* Hx = gp(d.H[0]);
+    const FDTD_GLOBAL T* Hy = gp(d.H[1]);
     if (m.kind == 1) {
-        T hxm = k > 0 ? d.H[0][f - d.plane] : T(0);
-        T hym = k > 0 ? d.H[1][f - d.plane] : T(0);
-        buf[q] = d.E[0][f];
-        buf[npts + q] = d.E[1][f];
-        buf[2 * npts + q] = T(0.5) * (d.H[0][f] + hxm);
-        buf[3 * npts + q] = T(0.5) * (d.H[1][f] + hym);
+        T hxm = k > 0 ? Hx[f - d.plane] : T(0);
+        T hym = k > 0 ? Hy[f - d.plane] : T(0);
+        buf[q] = gp(d.E[0])[f];
+        buf[npts + q] = gp(d.E[1])[f];
+        buf[2 * npts + q] = T(0.5) * (Hx[f] + hxm);
+        buf[3 * npts + q] = T(0.5) * (Hy[f] + hym);
     } else {
-        buf[q] = m.comp < 3 ? d.E[m.comp][f] : d.H[m.comp - 3][f];
+        buf[q] = m.comp < 3 ? gp(d.E[m.comp])[f] : gp(d.H[m.comp - 3])[f];
     }
 }
 

@@ -258,22 +258,12 @@ def random_state_like(spec: DomainSpec, seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
-# Named configurations (full size), for bench and sampled full-size parity.
-def c1():
-    return pec_cavity(32, 200)
-
-
-def c2():
-    return lorentz_flux()
-
-
-def c3():
-    return design_patch()
-
-
-def c4():
-    return batch_domains()
-
-
-def c5():
-    return anisotropic_lorentz()
+# Full-size named workloads, for the benchmark, profiling and sampled
+# full-size parity.
+WORKLOADS = {
+    "pec_cavity": lambda: pec_cavity(32, 200),
+    "lorentz_flux": lambda: lorentz_flux(),
+    "design_patch": lambda: design_patch()[0],
+    "batch_domains": lambda: batch_domains(),
+    "anisotropic_lorentz": lambda: anisotropic_lorentz(),
+}
