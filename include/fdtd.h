@@ -68,7 +68,10 @@ enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ, FDTD_ADJ = 6 };
 enum { FDTD_RECORD = 1u, FDTD_REPLAY = 2u };
 /* monitor ops */
 enum { FDTD_MON_GET = 0, FDTD_MON_FLUX = 1, FDTD_MON_SET_COTANGENT = 2, FDTD_MON_RESET = 3 };
-/* kernel selection (for tests of tile invariance; FDTD_KERNEL_AUTO in production) */
+/* kernel family.  AUTO and SPLIT: one E launch and one H launch per step,
+   updating the state in place; FUSED: one pass per step over tiles, writing
+   the other state set.  Results are bitwise identical; the speed depends on
+   the geometry (the package's autotuner picks per workload). */
 enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
 
 #define FDTD_MAX_SOURCES 4
@@ -126,7 +129,7 @@ typedef struct {
     int32_t kernel;                /* FDTD_KERNEL_* */
     int32_t dft_block;             /* time samples buffered before a DFT flush (0: default) */
     int32_t graph_chunk;           /* steps per captured hipGraph (0: no graph) */
-    int32_t tile_rows;             /* fused kernel: rows per wave, 2 | 4 | 8 (0: 4) */
+    int32_t tile_rows;             /* fused kernel: rows per wave, 2 | 4 | 8 (0: 2) */
     int32_t tile_kz;               /* z planes per block (0: default) */
     void *stream;                  /* hipStream_t; NULL = default stream */
     double mem_budget_bytes;       /* refuse with FDTD_E_NOMEM above this (0: device free memory) */

@@ -20,6 +20,7 @@ from typing import Dict, List, Optional, Sequence
 from .sim import Simulation
 
 CANDIDATES = [
+    {"kernel": "split", "tile_rows": 0, "tile_kz": 4},
     {"kernel": "split", "tile_rows": 0, "tile_kz": 8},
     {"kernel": "split", "tile_rows": 0, "tile_kz": 16},
     {"kernel": "fused", "tile_rows": 2, "tile_kz": 8},

@@ -171,9 +171,11 @@ __device__ __forceinline__ T stretch(const DomDev<T>& d, T* const (&psi)[3][2][2
 // h0 = H_{c+2} at the node and h0m one step back along a0 = c+1; h1 = H_{c+1}
 // and h1m back along a1 = c+2.  The owner writes the absorber memories and
 // the Lorentz history into set ws; other callers only recompute the value.
+// e_update_v takes E^n_c and eps^-1 at the node from the caller (which may
+// have fetched them ahead); e_update loads them itself.
 template <typename T>
-__device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m,
-                                      T h1, T h1m, int rs, int ws, bool own, int t) {
+__device__ __forceinline__ T e_update_v(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m,
+                                        T h1, T h1m, T e, T einv, int rs, int ws, bool own, int t) {
     const bool lorc = in_lor(d, i, j, k);
     const long long fs = d.fs;
     if (e_masked(c, i, j, k)) {
@@ -189,8 +191,6 @@ __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, i
     T D0 = stretch(d, d.psiE, fs, rs, ws, own, a0, 0, 0, i, j, k, h0 - h0m);
     T D1 = stretch(d, d.psiE, fs, rs, ws, own, a1, 1, 0, i, j, k, h1 - h1m);
     T curl = D0 - D1;
-    T einv = epsinv_at(d, c, i, j, k);
-    T e = gp(d.E[c])[f + rs * fs];
     T en;
     long long q = 0;
     T eold = 0, w = 0, wold = 0;
@@ -220,6 +220,14 @@ __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, i
         gp(d.lor[2][c])[q + ws * fs] = w;
     }
     return en;
+}
+
+template <typename T>
+__device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m,
+                                      T h1, T h1m, int rs, int ws, bool own, int t) {
+    T e = e_masked(c, i, j, k) ? T(0) : gp(d.E[c])[f + rs * d.fs];
+    T einv = e_masked(c, i, j, k) ? T(0) : epsinv_at(d, c, i, j, k);
+    return e_update_v(d, c, i, j, k, f, h0, h0m, h1, h1m, e, einv, rs, ws, own, t);
 }
 
 // Bulk E update (no absorber, no mask, no Lorentz, no source at the node).

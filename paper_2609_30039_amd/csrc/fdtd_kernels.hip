@@ -70,6 +70,36 @@ __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int 
 }
 
 // ============================================================ forward, split
+// Both kernels fetch the next plane's operands before computing and storing
+// the current one, so a wave keeps a plane of loads in flight while it works
+// (the compiler cannot hoist loads above the stores itself: it cannot tell
+// the state arrays apart).  With rs == ws they update in place: every value
+// a thread writes is read only by that thread.
+template <typename T>
+struct EPlane {
+    T hx, hy, hz, hy_xm, hz_xm, hx_ym, hz_ym;   // H^{n+1/2} at the node and one step back along x and y
+    T e[3], einv[3];                             // E^n and eps^-1 at the node
+};
+
+template <typename T>
+__device__ __forceinline__ void e_fetch(const DomDev<T>& d, EPlane<T>& p, const FDTD_GLOBAL T* Hx,
+                                        const FDTD_GLOBAL T* Hy, const FDTD_GLOBAL T* Hz, int i, int j, int k,
+                                        long long f, long long ro) {
+    p.hx = Hx[f];
+    p.hy = Hy[f];
+    p.hz = Hz[f];
+    p.hy_xm = i > 0 ? Hy[f - 1] : T(0);
+    p.hz_xm = i > 0 ? Hz[f - 1] : T(0);
+    p.hx_ym = j > 0 ? Hx[f - d.pitch] : T(0);
+    p.hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        bool m = e_masked(c, i, j, k);
+        p.e[c] = m ? T(0) : gp(d.E[c])[f + ro];
+        p.einv[c] = m ? T(0) : epsinv_at(d, c, i, j, k);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                int ndom, int kz, int rs, int ws, int t) {
@@ -88,24 +118,50 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
         hxm = Hx[f];
         hym = Hy[f];
     }
+    EPlane<T> cur, nxt;
+    e_fetch(d, cur, Hx, Hy, Hz, i, j, c.k0, fidx(d, i, j, c.k0), ro);
     for (int k = c.k0; k < c.k1; ++k) {
         long long f = fidx(d, i, j, k);
-        T hx = Hx[f], hy = Hy[f], hz = Hz[f];
-        T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
-        T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
+        if (k + 1 < c.k1) e_fetch(d, nxt, Hx, Hy, Hz, i, j, k + 1, f + d.plane, ro);
         // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
-        T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
-        T ey = e_update(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, rs, ws, true, t);
-        T ez = e_update(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, rs, ws, true, t);
+        T ex = e_update_v(d, 0, i, j, k, f, cur.hz, cur.hz_ym, cur.hy, hym, cur.e[0], cur.einv[0], rs, ws, true, t);
+        T ey = e_update_v(d, 1, i, j, k, f, cur.hx, hxm, cur.hz, cur.hz_xm, cur.e[1], cur.einv[1], rs, ws, true, t);
+        T ez = e_update_v(d, 2, i, j, k, f, cur.hy, cur.hy_xm, cur.hx, cur.hx_ym, cur.e[2], cur.einv[2], rs, ws, true,
+                          t);
         gp(d.E[0])[f + wo] = ex;
         gp(d.E[1])[f + wo] = ey;
         gp(d.E[2])[f + wo] = ez;
-        hxm = hx;
-        hym = hy;
+        hxm = cur.hx;
+        hym = cur.hy;
+        cur = nxt;
     }
 }
 
 // reads E^{n+1} from set ws (written by k_fwd_e), H^{n+1/2} from set rs
+template <typename T>
+struct HPlane {
+    T e1[3];                          // E^{n+1} one plane up
+    T ey_xp, ez_xp, ex_yp, ez_yp;     // E^{n+1} one step forward along x and y, this plane
+    T h[3];                           // H^{n+1/2} at the node
+};
+
+template <typename T>
+__device__ __forceinline__ void h_fetch(const DomDev<T>& d, HPlane<T>& p, const FDTD_GLOBAL T* Ex,
+                                        const FDTD_GLOBAL T* Ey, const FDTD_GLOBAL T* Ez, int i, int j, int k,
+                                        long long f, long long ro) {
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    bool up = k + 1 < nz;
+    p.e1[0] = up ? Ex[f + d.plane] : T(0);
+    p.e1[1] = up ? Ey[f + d.plane] : T(0);
+    p.e1[2] = up ? Ez[f + d.plane] : T(0);
+    p.ey_xp = i + 1 < nx ? Ey[f + 1] : T(0);
+    p.ez_xp = i + 1 < nx ? Ez[f + 1] : T(0);
+    p.ex_yp = j + 1 < ny ? Ex[f + d.pitch] : T(0);
+    p.ez_yp = j + 1 < ny ? Ez[f + d.pitch] : T(0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) p.h[q] = gp(d.H[q])[f + ro];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                int ndom, int kz, int rs, int ws) {
@@ -113,30 +169,29 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
     Col c = column(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
-    const int i = c.i, j = c.j, nx = d.n[0], ny = d.n[1], nz = d.n[2];
+    const int i = c.i, j = c.j;
     const long long ro = rs * d.fs, wo = ws * d.fs;
     const FDTD_GLOBAL T* Ex = gp(d.E[0] + wo);
     const FDTD_GLOBAL T* Ey = gp(d.E[1] + wo);
     const FDTD_GLOBAL T* Ez = gp(d.E[2] + wo);
     long long f0 = fidx(d, i, j, c.k0);
     T ex = Ex[f0], ey = Ey[f0], ez = Ez[f0];
+    HPlane<T> cur, nxt;
+    h_fetch(d, cur, Ex, Ey, Ez, i, j, c.k0, f0, ro);
     for (int k = c.k0; k < c.k1; ++k) {
         long long f = fidx(d, i, j, k);
-        T ex1 = 0, ey1 = 0, ez1 = 0;
-        if (k + 1 < nz) {
-            ex1 = Ex[f + d.plane];
-            ey1 = Ey[f + d.plane];
-            ez1 = Ez[f + d.plane];
-        }
-        T ey_xp = i + 1 < nx ? Ey[f + 1] : T(0), ez_xp = i + 1 < nx ? Ez[f + 1] : T(0);
-        T ex_yp = j + 1 < ny ? Ex[f + d.pitch] : T(0), ez_yp = j + 1 < ny ? Ez[f + d.pitch] : T(0);
+        if (k + 1 < c.k1) h_fetch(d, nxt, Ex, Ey, Ez, i, j, k + 1, f + d.plane, ro);
         // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
-        gp(d.H[0])[f + wo] = h_update(d, 0, i, j, k, gp(d.H[0])[f + ro], ez_yp, ez, ey1, ey, rs, ws, true);
-        gp(d.H[1])[f + wo] = h_update(d, 1, i, j, k, gp(d.H[1])[f + ro], ex1, ex, ez_xp, ez, rs, ws, true);
-        gp(d.H[2])[f + wo] = h_update(d, 2, i, j, k, gp(d.H[2])[f + ro], ey_xp, ey, ex_yp, ex, rs, ws, true);
-        ex = ex1;
-        ey = ey1;
-        ez = ez1;
+        T hx = h_update(d, 0, i, j, k, cur.h[0], cur.ez_yp, ez, cur.e1[1], ey, rs, ws, true);
+        T hy = h_update(d, 1, i, j, k, cur.h[1], cur.e1[0], ex, cur.ez_xp, ez, rs, ws, true);
+        T hz = h_update(d, 2, i, j, k, cur.h[2], cur.ey_xp, ey, cur.ex_yp, ex, rs, ws, true);
+        gp(d.H[0])[f + wo] = hx;
+        gp(d.H[1])[f + wo] = hy;
+        gp(d.H[2])[f + wo] = hz;
+        ex = cur.e1[0];
+        ey = cur.e1[1];
+        ez = cur.e1[2];
+        cur = nxt;
     }
 }
 

@@ -368,8 +368,8 @@ struct Handle : Base {
         if (o->tile_rows != 0 && o->tile_rows != 2 && o->tile_rows != 4 && o->tile_rows != 8)
             return fail(FDTD_E_INVALID, "tile_rows must be 2, 4 or 8");
         if (o->tile_kz < 0) return fail(FDTD_E_INVALID, "tile_kz");
-        cfg.kernel = o->kernel == FDTD_KERNEL_SPLIT ? 1 : 2;
-        cfg.rows = o->tile_rows ? o->tile_rows : 4;
+        cfg.kernel = o->kernel == FDTD_KERNEL_FUSED ? 2 : 1;
+        cfg.rows = o->tile_rows ? o->tile_rows : 2;
         cfg.kz = o->tile_kz ? o->tile_kz : (cfg.kernel == 1 ? 8 : 16);
         cfg.ndom = n;
         dh.resize(n);
@@ -716,8 +716,12 @@ struct Handle : Base {
     int step_forward(int n, unsigned flags) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
         bool rec = (flags & FDTD_RECORD) && !(flags & FDTD_REPLAY);
+        // The split kernels update a working set in place; the fused pass
+        // reads neighbours' old values after they are overwritten, so it
+        // writes the other set.  A restored slot is never written.
+        const bool inplace = cfg.kernel == 1;
         for (int s = 0; s < n; ++s) {
-            int ws = write_set();
+            int ws = inplace && (cur == wset[0] || cur == wset[1]) ? cur : write_set();
             if (timing_on) ev_mark();
             launch_fwd<T>(cfg, d_doms, cur, ws, t, st);
             if (timing_on) ev_mark();
