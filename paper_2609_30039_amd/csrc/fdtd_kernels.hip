@@ -69,35 +69,193 @@ __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int 
     return c;
 }
 
-// ============================================================ forward, split
-// Both kernels fetch the next plane's operands before computing and storing
-// the current one, so a wave keeps a plane of loads in flight while it works
-// (the compiler cannot hoist loads above the stores itself: it cannot tell
-// the state arrays apart).  With rs == ws they update in place: every value
-// a thread writes is read only by that thread.
+// ------------------------------------------------------------ per-axis views
+// Absorber coefficients of one index along an axis, eps^-1 over a block, and
+// absorber memories fetched ahead: shared by the split and the plain tile
+// kernels, whose node arithmetic is that of e_update / h_update.
 template <typename T>
-struct EPlane {
-    T hx, hy, hz, hy_xm, hz_xm, hx_ym, hz_ym;   // H^{n+1/2} at the node and one step back along x and y
-    T e[3], einv[3];                             // E^n and eps^-1 at the node
+struct EpsView {
+    int mode;                   // 0 background everywhere, 1 inside the eps box, 2 partial
+    int diag;
+    const FDTD_GLOBAL T* p[3];
+    int lo[3], hi[3], ex, ey;
+    T bg;
 };
 
 template <typename T>
-__device__ __forceinline__ void e_fetch(const DomDev<T>& d, EPlane<T>& p, const FDTD_GLOBAL T* Hx,
-                                        const FDTD_GLOBAL T* Hy, const FDTD_GLOBAL T* Hz, int i, int j, int k,
-                                        long long f, long long ro) {
-    p.hx = Hx[f];
-    p.hy = Hy[f];
-    p.hz = Hz[f];
-    p.hy_xm = i > 0 ? Hy[f - 1] : T(0);
-    p.hz_xm = i > 0 ? Hz[f - 1] : T(0);
-    p.hx_ym = j > 0 ? Hx[f - d.pitch] : T(0);
-    p.hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        bool m = e_masked(c, i, j, k);
-        p.e[c] = m ? T(0) : gp(d.E[c])[f + ro];
-        p.einv[c] = m ? T(0) : epsinv_at(d, c, i, j, k);
+__device__ __forceinline__ EpsView<T> eps_view(const DomDev<T>& d, int X0, int Y0, int NR, int klo, int khi) {
+    EpsView<T> v;
+    v.diag = d.eps_diag;
+    v.bg = d.epsinv_bg;
+    for (int c = 0; c < 3; ++c) v.p[c] = gp(d.epsinv[c]);
+    for (int a = 0; a < 3; ++a) {
+        v.lo[a] = d.elo[a];
+        v.hi[a] = d.ehi[a];
     }
+    v.ex = d.ehi[0] - d.elo[0];
+    v.ey = d.ehi[1] - d.elo[1];
+    int lo[3] = {X0, Y0, klo}, hi[3] = {X0 + 63, Y0 + NR - 1, khi};
+    bool inside = true, outside = false;
+    for (int a = 0; a < 3; ++a) {
+        if (lo[a] < d.elo[a] || hi[a] >= d.ehi[a]) inside = false;
+        if (hi[a] < d.elo[a] || lo[a] >= d.ehi[a]) outside = true;
+    }
+    v.mode = outside ? 0 : (inside ? 1 : 2);
+    return v;
+}
+
+// eps^-1 of the three components at (i, j, k)
+template <typename T>
+__device__ __forceinline__ void eps_at(const EpsView<T>& v, int i, int j, int k, T out[3]) {
+    bool in = v.mode == 1 || (v.mode == 2 && i >= v.lo[0] && i < v.hi[0] && j >= v.lo[1] && j < v.hi[1] &&
+                              k >= v.lo[2] && k < v.hi[2]);
+    if (!in) {
+        out[0] = out[1] = out[2] = v.bg;
+        return;
+    }
+    int q = ((k - v.lo[2]) * v.ey + (j - v.lo[1])) * v.ex + (i - v.lo[0]);
+    out[0] = v.p[0][q];
+    if (v.diag) {
+        out[1] = v.p[1][q];
+        out[2] = v.p[2][q];
+    } else {
+        out[1] = out[2] = out[0];
+    }
+}
+
+template <typename T>
+struct Cpml1 {
+    int side;                  // -1 outside the slabs
+    int idx;                   // index along the axis
+    T bE, cE, kE, bH, cH, kH;
+};
+
+template <typename T>
+__device__ __forceinline__ Cpml1<T> cpml_at(const DomDev<T>& d, int a, int x) {
+    Cpml1<T> c;
+    c.idx = x;
+    c.side = (x >= 0 && x < d.n[a]) ? slab_side(d, a, x) : -1;
+    c.bE = c.cE = c.kE = c.bH = c.cH = c.kH = T(0);
+    if (c.side >= 0) {
+        const FDTD_GLOBAL T* tb = gp(d.tab[a]);
+        int n = d.n[a];
+        c.bE = tb[x];
+        c.cE = tb[n + x];
+        c.kE = tb[2 * n + x];
+        c.bH = tb[3 * n + x];
+        c.cH = tb[4 * n + x];
+        c.kH = tb[5 * n + x];
+    }
+    return c;
+}
+
+// psi slab offset of node (i,j,k) on axis a, side s (32-bit)
+template <typename T>
+__device__ __forceinline__ int poff(const DomDev<T>& d, int a, int s, int i, int j, int k) {
+    int L = d.L[a][s];
+    if (a == 0) return (k * d.n[1] + j) * L + (s ? i - (d.n[0] - L) : i);
+    if (a == 1) return (k * L + (s ? j - (d.n[1] - L) : j)) * d.n[0] + i;
+    return ((s ? k - (d.n[2] - L) : k) * d.n[1] + j) * d.n[0] + i;
+}
+
+// one stretched term: psi_new = b psi + c D; D/kappa + psi_new (as stretch())
+template <typename T>
+__device__ __forceinline__ T st_term(T* base, long long rso, long long wso, bool own, T b, T c, T ki, T D) {
+    FDTD_GLOBAL T* g = gp(base);
+    T pn = fma(b, g[rso], c * D);
+    if (own) g[wso] = pn;
+    return fma(ki, D, pn);
+}
+
+// psi memories of the six terms of one node, slots ordered
+// 0: y-slab term of Ex (E) / Hx (H), 1: y-slab term of Ez / Hz,
+// 2: z-slab term of Ey / Hy, 3: z-slab term of Ex / Hx,
+// 4: x-slab term of Ez / Hz, 5: x-slab term of Ey / Hy.
+// (E side: Ex t0, Ez t1, Ey t0, Ex t1, Ez t0, Ey t1; H side: Hx t0, Hz t1,
+// Hy t0, Hx t1, Hz t0, Hy t1.)
+template <typename T>
+__device__ __forceinline__ void psi_load(const DomDev<T>& d, T* const (&psi)[3][2][2], long long so, bool v,
+                                         const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cz, int i, int j, int k,
+                                         T out[6]) {
+    for (int q = 0; q < 6; ++q) out[q] = T(0);
+    if (!v) return;
+    if (cy.side >= 0) {
+        int o = poff(d, 1, cy.side, i, j, k);
+        out[0] = gp(psi[1][cy.side][0] + so)[o];
+        out[1] = gp(psi[1][cy.side][1] + so)[o];
+    }
+    if (cz.side >= 0) {
+        int o = poff(d, 2, cz.side, i, j, k);
+        out[2] = gp(psi[2][cz.side][0] + so)[o];
+        out[3] = gp(psi[2][cz.side][1] + so)[o];
+    }
+    if (cx.side >= 0) {
+        int o = poff(d, 0, cx.side, i, j, k);
+        out[4] = gp(psi[0][cx.side][0] + so)[o];
+        out[5] = gp(psi[0][cx.side][1] + so)[o];
+    }
+}
+
+// stretched term from a prefetched memory: psi_new = b psi + c D (stored by
+// the owner), returns D/kappa + psi_new (the arithmetic of stretch())
+template <typename T>
+__device__ __forceinline__ T st_pref(T* base, long long wso, int off, bool own, T b, T c, T ki, T psi, T D) {
+    T pn = fma(b, psi, c * D);
+    if (own) gp(base + wso)[off] = pn;
+    return fma(ki, D, pn);
+}
+
+// ============================================================ forward, split
+// One thread per (i, j) column marching its z chunk, one launch for E and one
+// for H.  Absorber coefficients are loaded once per column (x, y) and per
+// plane (z, block-uniform); the next plane's operands, absorber memories
+// included, are fetched before the current plane is computed and stored, so
+// a wave keeps a plane of loads in flight while it works (the compiler cannot
+// hoist loads above the stores: it cannot tell the state arrays apart).
+// Blocks that touch no absorber slab skip the memories; Lorentz cells take
+// the general e_update_v.  With rs == ws the kernels update in place: every
+// value a thread writes is read only by that thread.
+struct BlkFlags {
+    bool cp, lor;
+};
+
+template <typename T>
+__device__ __forceinline__ BlkFlags blk_flags(const DomDev<T>& d, int x0, int y0, int k0, int k1) {
+    int lo[3] = {x0, y0, k0}, hi[3] = {min(x0 + 63, d.n[0] - 1), min(y0 + 3, d.n[1] - 1), k1 - 1};
+    BlkFlags f;
+    f.cp = false;
+    for (int a = 0; a < 3; ++a)
+        if (lo[a] < d.L[a][0] || hi[a] >= d.n[a] - d.L[a][1]) f.cp = true;
+    f.lor = d.has_lor;
+    for (int a = 0; a < 3; ++a)
+        if (hi[a] < d.llo[a] || lo[a] >= d.lhi[a]) f.lor = false;
+    return f;
+}
+
+template <typename T>
+struct ColE {
+    T hx, hy, hz, hy_xm, hz_xm, hx_ym, hz_ym;   // H^{n+1/2} at the node and one step back along x and y
+    T e[3], ei[3];                               // E^n and eps^-1 at the node
+    T ps[6];                                     // E-side absorber memories (psi_load order)
+};
+
+template <typename T>
+__device__ __forceinline__ void cole_fetch(const DomDev<T>& d, ColE<T>& p, const FDTD_GLOBAL T* const (&h)[3],
+                                           const FDTD_GLOBAL T* const (&e)[3], long long f, const EpsView<T>& ev,
+                                           bool cp, const Cpml1<T>& cx, const Cpml1<T>& cy, long long so, int i,
+                                           int j, int k) {
+    p.hx = h[0][f];
+    p.hy = h[1][f];
+    p.hz = h[2][f];
+    p.hy_xm = i > 0 ? h[1][f - 1] : T(0);
+    p.hz_xm = i > 0 ? h[2][f - 1] : T(0);
+    p.hx_ym = j > 0 ? h[0][f - d.pitch] : T(0);
+    p.hz_ym = j > 0 ? h[2][f - d.pitch] : T(0);
+    p.e[0] = e[0][f];
+    p.e[1] = e[1][f];
+    p.e[2] = e[2][f];
+    eps_at(ev, i, j, k, p.ei);
+    if (cp) psi_load(d, d.psiE, so, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ps);
 }
 
 template <typename T>
@@ -108,58 +266,131 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
-    const long long ro = rs * d.fs, wo = ws * d.fs;
-    const FDTD_GLOBAL T* Hx = gp(d.H[0] + ro);
-    const FDTD_GLOBAL T* Hy = gp(d.H[1] + ro);
-    const FDTD_GLOBAL T* Hz = gp(d.H[2] + ro);
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
+    const FDTD_GLOBAL T* h[3] = {gp(d.H[0] + so), gp(d.H[1] + so), gp(d.H[2] + so)};
+    const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + so), gp(d.E[1] + so), gp(d.E[2] + so)};
+    FDTD_GLOBAL T* ew[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
+    const BlkFlags bf = blk_flags(d, i & ~63, j & ~3, c.k0, c.k1);
+    const EpsView<T> ev = eps_view(d, i & ~63, j & ~3, 4, c.k0, c.k1 - 1);
+    const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j);
+    const T S = d.S;
+    long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
     T hxm = 0, hym = 0;   // Hx, Hy one plane below
     if (c.k0 > 0) {
-        long long f = fidx(d, i, j, c.k0 - 1);
-        hxm = Hx[f];
-        hym = Hy[f];
+        hxm = h[0][f - pl];
+        hym = h[1][f - pl];
     }
-    EPlane<T> cur, nxt;
-    e_fetch(d, cur, Hx, Hy, Hz, i, j, c.k0, fidx(d, i, j, c.k0), ro);
-    for (int k = c.k0; k < c.k1; ++k) {
-        long long f = fidx(d, i, j, k);
-        if (k + 1 < c.k1) e_fetch(d, nxt, Hx, Hy, Hz, i, j, k + 1, f + d.plane, ro);
-        // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
-        T ex = e_update_v(d, 0, i, j, k, f, cur.hz, cur.hz_ym, cur.hy, hym, cur.e[0], cur.einv[0], rs, ws, true, t);
-        T ey = e_update_v(d, 1, i, j, k, f, cur.hx, hxm, cur.hz, cur.hz_xm, cur.e[1], cur.einv[1], rs, ws, true, t);
-        T ez = e_update_v(d, 2, i, j, k, f, cur.hy, cur.hy_xm, cur.hx, cur.hx_ym, cur.e[2], cur.einv[2], rs, ws, true,
-                          t);
-        gp(d.E[0])[f + wo] = ex;
-        gp(d.E[1])[f + wo] = ey;
-        gp(d.E[2])[f + wo] = ez;
-        hxm = cur.hx;
-        hym = cur.hy;
-        cur = nxt;
+    ColE<T> cu, nx;
+    cole_fetch(d, cu, h, e, f, ev, bf.cp, cx, cy, so, i, j, c.k0);
+    for (int k = c.k0; k < c.k1; ++k, f += pl) {
+        if (k + 1 < c.k1) cole_fetch(d, nx, h, e, f + pl, ev, bf.cp, cx, cy, so, i, j, k + 1);
+        if (!(bf.lor && in_lor(d, i, j, k))) {   // Lorentz cells: k_fwd_e_lor
+            T ex, ey, ez;
+            T Dx0 = cu.hz - cu.hz_ym, Dx1 = cu.hy - hym;    // Ex: Hz along y, Hy along z
+            T Dy0 = cu.hx - hxm, Dy1 = cu.hz - cu.hz_xm;    // Ey: Hx along z, Hz along x
+            T Dz0 = cu.hy - cu.hy_xm, Dz1 = cu.hx - cu.hx_ym;   // Ez: Hy along x, Hx along y
+            if (bf.cp) {
+                const Cpml1<T> cz = cpml_at(d, 2, k);
+                const T* pe = cu.ps;
+                if (cy.side >= 0) {
+                    int q = poff(d, 1, cy.side, i, j, k);
+                    Dx0 = st_pref(d.psiE[1][cy.side][0], wo, q, j > 0 && k > 0, cy.bE, cy.cE, cy.kE, pe[0], Dx0);
+                    Dz1 = st_pref(d.psiE[1][cy.side][1], wo, q, i > 0 && j > 0, cy.bE, cy.cE, cy.kE, pe[1], Dz1);
+                }
+                if (cz.side >= 0) {
+                    int q = poff(d, 2, cz.side, i, j, k);
+                    Dy0 = st_pref(d.psiE[2][cz.side][0], wo, q, i > 0 && k > 0, cz.bE, cz.cE, cz.kE, pe[2], Dy0);
+                    Dx1 = st_pref(d.psiE[2][cz.side][1], wo, q, j > 0 && k > 0, cz.bE, cz.cE, cz.kE, pe[3], Dx1);
+                }
+                if (cx.side >= 0) {
+                    int q = poff(d, 0, cx.side, i, j, k);
+                    Dz0 = st_pref(d.psiE[0][cx.side][0], wo, q, i > 0 && j > 0, cx.bE, cx.cE, cx.kE, pe[4], Dz0);
+                    Dy1 = st_pref(d.psiE[0][cx.side][1], wo, q, i > 0 && k > 0, cx.bE, cx.cE, cx.kE, pe[5], Dy1);
+                }
+            }
+            ex = fma(S * cu.ei[0], Dx0 - Dx1, cu.e[0]);
+            ey = fma(S * cu.ei[1], Dy0 - Dy1, cu.e[1]);
+            ez = fma(S * cu.ei[2], Dz0 - Dz1, cu.e[2]);
+            for (int q = 0; q < d.nsrc; ++q) {
+                const SrcDev<T>& sr = d.src[q];
+                if (t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) {
+                    T v = gp(sr.wave)[t];
+                    if (sr.comp == 0) ex += v;
+                    else if (sr.comp == 1) ey += v;
+                    else ez += v;
+                }
+            }
+            // PEC: E_c is zero where the index along c+1 or c+2 is 0
+            if (j == 0 || k == 0) ex = T(0);
+            if (i == 0 || k == 0) ey = T(0);
+            if (i == 0 || j == 0) ez = T(0);
+            ew[0][f] = ex;
+            ew[1][f] = ey;
+            ew[2][f] = ez;
+        }
+        hxm = cu.hx;
+        hym = cu.hy;
+        cu = nx;
     }
+}
+
+// E update of the Lorentz boxes (one thread per box cell, x fastest): the
+// general per-node path with the auxiliary-differential-equation history.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fwd_e_lor(const DomDev<T>* __restrict__ doms, const int* __restrict__ lbs,
+                                                   int ndom, int rs, int ws, int t) {
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    int dom = find_domain(lbs, ndom, b);
+    const DomDev<T>& d = doms[dom];
+    const int bx = d.lhi[0] - d.llo[0], by = d.lhi[1] - d.llo[1], bzn = d.lhi[2] - d.llo[2];
+    long long q = (long long)(b - lbs[dom]) * 256 + threadIdx.x;
+    if (!d.has_lor || q >= (long long)bx * by * bzn) return;
+    const int i = d.llo[0] + (int)(q % bx), j = d.llo[1] + (int)((q / bx) % by), k = d.llo[2] + (int)(q / ((long long)bx * by));
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
+    const long long f = (long long)k * pl + (long long)j * d.pitch + i;
+    const FDTD_GLOBAL T* Hx = gp(d.H[0] + so);
+    const FDTD_GLOBAL T* Hy = gp(d.H[1] + so);
+    const FDTD_GLOBAL T* Hz = gp(d.H[2] + so);
+    T hx = Hx[f], hy = Hy[f], hz = Hz[f];
+    T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
+    T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
+    T hxm = k > 0 ? Hx[f - pl] : T(0), hym = k > 0 ? Hy[f - pl] : T(0);
+    // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
+    T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
+    T ey = e_update(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, rs, ws, true, t);
+    T ez = e_update(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, rs, ws, true, t);
+    gp(d.E[0] + wo)[f] = ex;
+    gp(d.E[1] + wo)[f] = ey;
+    gp(d.E[2] + wo)[f] = ez;
 }
 
 // reads E^{n+1} from set ws (written by k_fwd_e), H^{n+1/2} from set rs
 template <typename T>
-struct HPlane {
+struct ColH {
     T e1[3];                          // E^{n+1} one plane up
-    T ey_xp, ez_xp, ex_yp, ez_yp;     // E^{n+1} one step forward along x and y, this plane
+    T ey_xp, ez_xp, ex_yp, ez_yp;     // E^{n+1} one step forward along x and y
     T h[3];                           // H^{n+1/2} at the node
+    T ps[6];                          // H-side absorber memories (psi_load order)
 };
 
 template <typename T>
-__device__ __forceinline__ void h_fetch(const DomDev<T>& d, HPlane<T>& p, const FDTD_GLOBAL T* Ex,
-                                        const FDTD_GLOBAL T* Ey, const FDTD_GLOBAL T* Ez, int i, int j, int k,
-                                        long long f, long long ro) {
-    const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
-    bool up = k + 1 < nz;
-    p.e1[0] = up ? Ex[f + d.plane] : T(0);
-    p.e1[1] = up ? Ey[f + d.plane] : T(0);
-    p.e1[2] = up ? Ez[f + d.plane] : T(0);
-    p.ey_xp = i + 1 < nx ? Ey[f + 1] : T(0);
-    p.ez_xp = i + 1 < nx ? Ez[f + 1] : T(0);
-    p.ex_yp = j + 1 < ny ? Ex[f + d.pitch] : T(0);
-    p.ez_yp = j + 1 < ny ? Ez[f + d.pitch] : T(0);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) p.h[q] = gp(d.H[q])[f + ro];
+__device__ __forceinline__ void colh_fetch(const DomDev<T>& d, ColH<T>& p, const FDTD_GLOBAL T* const (&e)[3],
+                                           const FDTD_GLOBAL T* const (&h)[3], long long f, bool cp,
+                                           const Cpml1<T>& cx, const Cpml1<T>& cy, long long so, int i, int j,
+                                           int k) {
+    const bool up = k + 1 < d.n[2];
+    const long long pl = d.plane;
+    p.e1[0] = up ? e[0][f + pl] : T(0);
+    p.e1[1] = up ? e[1][f + pl] : T(0);
+    p.e1[2] = up ? e[2][f + pl] : T(0);
+    p.ey_xp = i + 1 < d.n[0] ? e[1][f + 1] : T(0);
+    p.ez_xp = i + 1 < d.n[0] ? e[2][f + 1] : T(0);
+    p.ex_yp = j + 1 < d.n[1] ? e[0][f + d.pitch] : T(0);
+    p.ez_yp = j + 1 < d.n[1] ? e[2][f + d.pitch] : T(0);
+    p.h[0] = h[0][f];
+    p.h[1] = h[1][f];
+    p.h[2] = h[2][f];
+    if (cp) psi_load(d, d.psiH, so, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ps);
 }
 
 template <typename T>
@@ -170,28 +401,49 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
-    const long long ro = rs * d.fs, wo = ws * d.fs;
-    const FDTD_GLOBAL T* Ex = gp(d.E[0] + wo);
-    const FDTD_GLOBAL T* Ey = gp(d.E[1] + wo);
-    const FDTD_GLOBAL T* Ez = gp(d.E[2] + wo);
-    long long f0 = fidx(d, i, j, c.k0);
-    T ex = Ex[f0], ey = Ey[f0], ez = Ez[f0];
-    HPlane<T> cur, nxt;
-    h_fetch(d, cur, Ex, Ey, Ez, i, j, c.k0, f0, ro);
-    for (int k = c.k0; k < c.k1; ++k) {
-        long long f = fidx(d, i, j, k);
-        if (k + 1 < c.k1) h_fetch(d, nxt, Ex, Ey, Ez, i, j, k + 1, f + d.plane, ro);
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
+    const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
+    const FDTD_GLOBAL T* h[3] = {gp(d.H[0] + so), gp(d.H[1] + so), gp(d.H[2] + so)};
+    FDTD_GLOBAL T* hw[3] = {gp(d.H[0] + wo), gp(d.H[1] + wo), gp(d.H[2] + wo)};
+    const BlkFlags bf = blk_flags(d, i & ~63, j & ~3, c.k0, c.k1);
+    const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j);
+    const T S = d.S;
+    long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
+    T ex = e[0][f], ey = e[1][f], ez = e[2][f];
+    ColH<T> cu, nx;
+    colh_fetch(d, cu, e, h, f, bf.cp, cx, cy, so, i, j, c.k0);
+    for (int k = c.k0; k < c.k1; ++k, f += pl) {
+        if (k + 1 < c.k1) colh_fetch(d, nx, e, h, f + pl, bf.cp, cx, cy, so, i, j, k + 1);
         // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
-        T hx = h_update(d, 0, i, j, k, cur.h[0], cur.ez_yp, ez, cur.e1[1], ey, rs, ws, true);
-        T hy = h_update(d, 1, i, j, k, cur.h[1], cur.e1[0], ex, cur.ez_xp, ez, rs, ws, true);
-        T hz = h_update(d, 2, i, j, k, cur.h[2], cur.ey_xp, ey, cur.ex_yp, ex, rs, ws, true);
-        gp(d.H[0])[f + wo] = hx;
-        gp(d.H[1])[f + wo] = hy;
-        gp(d.H[2])[f + wo] = hz;
-        ex = cur.e1[0];
-        ey = cur.e1[1];
-        ez = cur.e1[2];
-        cur = nxt;
+        T Dx0 = cu.ez_yp - ez, Dx1 = cu.e1[1] - ey;
+        T Dy0 = cu.e1[0] - ex, Dy1 = cu.ez_xp - ez;
+        T Dz0 = cu.ey_xp - ey, Dz1 = cu.ex_yp - ex;
+        if (bf.cp) {
+            const Cpml1<T> cz = cpml_at(d, 2, k);
+            const T* ph = cu.ps;
+            if (cy.side >= 0) {
+                int q = poff(d, 1, cy.side, i, j, k);
+                Dx0 = st_pref(d.psiH[1][cy.side][0], wo, q, true, cy.bH, cy.cH, cy.kH, ph[0], Dx0);
+                Dz1 = st_pref(d.psiH[1][cy.side][1], wo, q, true, cy.bH, cy.cH, cy.kH, ph[1], Dz1);
+            }
+            if (cz.side >= 0) {
+                int q = poff(d, 2, cz.side, i, j, k);
+                Dy0 = st_pref(d.psiH[2][cz.side][0], wo, q, true, cz.bH, cz.cH, cz.kH, ph[2], Dy0);
+                Dx1 = st_pref(d.psiH[2][cz.side][1], wo, q, true, cz.bH, cz.cH, cz.kH, ph[3], Dx1);
+            }
+            if (cx.side >= 0) {
+                int q = poff(d, 0, cx.side, i, j, k);
+                Dz0 = st_pref(d.psiH[0][cx.side][0], wo, q, true, cx.bH, cx.cH, cx.kH, ph[4], Dz0);
+                Dy1 = st_pref(d.psiH[0][cx.side][1], wo, q, true, cx.bH, cx.cH, cx.kH, ph[5], Dy1);
+            }
+        }
+        hw[0][f] = fma(-S, Dx0 - Dx1, cu.h[0]);
+        hw[1][f] = fma(-S, Dy0 - Dy1, cu.h[1]);
+        hw[2][f] = fma(-S, Dz0 - Dz1, cu.h[2]);
+        ex = cu.e1[0];
+        ey = cu.e1[1];
+        ez = cu.e1[2];
+        cu = nx;
     }
 }
 
@@ -688,272 +940,12 @@ __global__ void __launch_bounds__(256) k_adj_fused(const DomDev<T>* __restrict__
     adj_fused_body<T, R>(d, tl, rs, ws, fsr);
 }
 
-// ============================================================ bulk tiles
-// Tiles that lie inside the domain (no ghost nodes, no PEC nodes) and touch
-// no absorber, Lorentz cell or source: plain Yee arithmetic, 32-bit offsets,
-// the next plane's loads issued before the current plane is processed.
-// Results equal the general path bitwise (same operations in the same order).
-template <typename T>
-struct EpsView {
-    int mode;                   // 0 background everywhere, 1 inside the eps box, 2 partial
-    int diag;
-    const FDTD_GLOBAL T* p[3];
-    int lo[3], hi[3], ex, ey;
-    T bg;
-};
-
-template <typename T>
-__device__ __forceinline__ EpsView<T> eps_view(const DomDev<T>& d, int X0, int Y0, int NR, int klo, int khi) {
-    EpsView<T> v;
-    v.diag = d.eps_diag;
-    v.bg = d.epsinv_bg;
-    for (int c = 0; c < 3; ++c) v.p[c] = gp(d.epsinv[c]);
-    for (int a = 0; a < 3; ++a) {
-        v.lo[a] = d.elo[a];
-        v.hi[a] = d.ehi[a];
-    }
-    v.ex = d.ehi[0] - d.elo[0];
-    v.ey = d.ehi[1] - d.elo[1];
-    int lo[3] = {X0, Y0, klo}, hi[3] = {X0 + 63, Y0 + NR - 1, khi};
-    bool inside = true, outside = false;
-    for (int a = 0; a < 3; ++a) {
-        if (lo[a] < d.elo[a] || hi[a] >= d.ehi[a]) inside = false;
-        if (hi[a] < d.elo[a] || lo[a] >= d.ehi[a]) outside = true;
-    }
-    v.mode = outside ? 0 : (inside ? 1 : 2);
-    return v;
-}
-
-// eps^-1 of the three components at (i, j, k)
-template <typename T>
-__device__ __forceinline__ void eps_at(const EpsView<T>& v, int i, int j, int k, T out[3]) {
-    bool in = v.mode == 1 || (v.mode == 2 && i >= v.lo[0] && i < v.hi[0] && j >= v.lo[1] && j < v.hi[1] &&
-                              k >= v.lo[2] && k < v.hi[2]);
-    if (!in) {
-        out[0] = out[1] = out[2] = v.bg;
-        return;
-    }
-    int q = ((k - v.lo[2]) * v.ey + (j - v.lo[1])) * v.ex + (i - v.lo[0]);
-    out[0] = v.p[0][q];
-    if (v.diag) {
-        out[1] = v.p[1][q];
-        out[2] = v.p[2][q];
-    } else {
-        out[1] = out[2] = out[0];
-    }
-}
-
-template <typename T, int R>
-__global__ void __launch_bounds__(256) k_fwd_bulk(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
-                                                  int kz, int rs, int ws) {
-    __shared__ T sH[2][kWaves][2][64];
-    __shared__ T sE[2][kWaves][2][64];
-    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    const DomDev<T>& d = doms[e.x];
-    const int X0 = e.y, Y0 = e.z, k0 = e.w, k1 = min(k0 + kz, d.n[2]);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = X0 + lane;
-    const int pitch = d.pitch, plane = (int)d.plane;
-    const T S = d.S;
-    const FDTD_GLOBAL T* __restrict__ rH0 = gp(d.H[0] + rs * d.fs);
-    const FDTD_GLOBAL T* __restrict__ rH1 = gp(d.H[1] + rs * d.fs);
-    const FDTD_GLOBAL T* __restrict__ rH2 = gp(d.H[2] + rs * d.fs);
-    const FDTD_GLOBAL T* __restrict__ rE0 = gp(d.E[0] + rs * d.fs);
-    const FDTD_GLOBAL T* __restrict__ rE1 = gp(d.E[1] + rs * d.fs);
-    const FDTD_GLOBAL T* __restrict__ rE2 = gp(d.E[2] + rs * d.fs);
-    FDTD_GLOBAL T* __restrict__ wH0 = gp(d.H[0] + ws * d.fs);
-    FDTD_GLOBAL T* __restrict__ wH1 = gp(d.H[1] + ws * d.fs);
-    FDTD_GLOBAL T* __restrict__ wH2 = gp(d.H[2] + ws * d.fs);
-    FDTD_GLOBAL T* __restrict__ wE0 = gp(d.E[0] + ws * d.fs);
-    FDTD_GLOBAL T* __restrict__ wE1 = gp(d.E[1] + ws * d.fs);
-    FDTD_GLOBAL T* __restrict__ wE2 = gp(d.E[2] + ws * d.fs);
-    const EpsView<T> ev = eps_view(d, X0, Y0, kWaves * R, k0 - 1, k1);
-    int ro[R];
-    bool own[R], ecomp[R];
-    for (int r = 0; r < R; ++r) {
-        int row = w * R + r;
-        ro[r] = (Y0 + row) * pitch + i;
-        ecomp[r] = lane >= 1 && row >= 1;
-        own[r] = lane >= 1 && lane <= 62 && row >= 1 && row <= kWaves * R - 2;
-    }
-    T Hk[R][3], Ek[R][3], Hp[R][3], Ep[R][3];
-    for (int r = 0; r < R; ++r) {
-        int f = (k0 - 1) * plane + ro[r];
-        Hk[r][0] = rH0[f];
-        Hk[r][1] = rH1[f];
-        Hk[r][2] = T(0);
-        Ek[r][0] = Ek[r][1] = Ek[r][2] = T(0);
-        f += plane;
-        Hp[r][0] = rH0[f];
-        Hp[r][1] = rH1[f];
-        Hp[r][2] = rH2[f];
-        Ep[r][0] = rE0[f];
-        Ep[r][1] = rE1[f];
-        Ep[r][2] = rE2[f];
-    }
-    for (int k = k0 - 1; k < k1; ++k) {
-        const int kn = k + 1;
-        T Hn[R][3], Eo[R][3];
-        for (int r = 0; r < R; ++r)
-            for (int q = 0; q < 3; ++q) {
-                Hn[r][q] = Hp[r][q];
-                Eo[r][q] = Ep[r][q];
-            }
-        if (kn < k1) {   // prefetch plane kn + 1 (<= k1 <= nz - 1)
-            for (int r = 0; r < R; ++r) {
-                int f = (kn + 1) * plane + ro[r];
-                Hp[r][0] = rH0[f];
-                Hp[r][1] = rH1[f];
-                Hp[r][2] = rH2[f];
-                Ep[r][0] = rE0[f];
-                Ep[r][1] = rE1[f];
-                Ep[r][2] = rE2[f];
-            }
-        }
-        const int pb = kn & 1;
-        sH[pb][w][0][lane] = Hn[R - 1][0];
-        sH[pb][w][1][lane] = Hn[R - 1][2];
-        __syncthreads();
-        T hx_ym0 = w > 0 ? sH[pb][w - 1][0][lane] : T(0);
-        T hz_ym0 = w > 0 ? sH[pb][w - 1][1][lane] : T(0);
-        const bool kin = kn >= k0 && kn < k1;
-        T En[R][3];
-        for (int r = 0; r < R; ++r) {
-            T hy_xm = __shfl_up(Hn[r][1], 1);
-            T hz_xm = __shfl_up(Hn[r][2], 1);
-            T hx_ym = r > 0 ? Hn[r - 1][0] : hx_ym0;
-            T hz_ym = r > 0 ? Hn[r - 1][2] : hz_ym0;
-            En[r][0] = En[r][1] = En[r][2] = T(0);
-            if (ecomp[r]) {
-                T ei[3];
-                eps_at(ev, i, Y0 + w * R + r, kn, ei);
-                // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
-                En[r][0] = fma(S * ei[0], (Hn[r][2] - hz_ym) - (Hn[r][1] - Hk[r][1]), Eo[r][0]);
-                En[r][1] = fma(S * ei[1], (Hn[r][0] - Hk[r][0]) - (Hn[r][2] - hz_xm), Eo[r][1]);
-                En[r][2] = fma(S * ei[2], (Hn[r][1] - hy_xm) - (Hn[r][0] - hx_ym), Eo[r][2]);
-                if (own[r] && kin) {
-                    int f = kn * plane + ro[r];
-                    st_nt(wE0, f, En[r][0]);
-                    st_nt(wE1, f, En[r][1]);
-                    st_nt(wE2, f, En[r][2]);
-                }
-            }
-        }
-        if (k >= k0) {
-            const int pk = k & 1;
-            T ex_yp3 = w + 1 < kWaves ? sE[pk][w + 1][0][lane] : T(0);
-            T ez_yp3 = w + 1 < kWaves ? sE[pk][w + 1][1][lane] : T(0);
-            for (int r = 0; r < R; ++r) {
-                T ey_xp = __shfl_down(Ek[r][1], 1);
-                T ez_xp = __shfl_down(Ek[r][2], 1);
-                T ex_yp = r + 1 < R ? Ek[r + 1][0] : ex_yp3;
-                T ez_yp = r + 1 < R ? Ek[r + 1][2] : ez_yp3;
-                if (own[r]) {
-                    int f = k * plane + ro[r];
-                    // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
-                    st_nt(wH0, f, fma(-S, (ez_yp - Ek[r][2]) - (En[r][1] - Ek[r][1]), Hk[r][0]));
-                    st_nt(wH1, f, fma(-S, (En[r][0] - Ek[r][0]) - (ez_xp - Ek[r][2]), Hk[r][1]));
-                    st_nt(wH2, f, fma(-S, (ey_xp - Ek[r][1]) - (ex_yp - Ek[r][0]), Hk[r][2]));
-                }
-            }
-        }
-        sE[pb][w][0][lane] = En[0][0];
-        sE[pb][w][1][lane] = En[0][2];
-        for (int r = 0; r < R; ++r)
-            for (int q = 0; q < 3; ++q) {
-                Hk[r][q] = Hn[r][q];
-                Ek[r][q] = En[r][q];
-            }
-    }
-}
-
 // ============================================================ plain tiles
 // Every tile without Lorentz cells: ghost lanes and rows (outside the domain)
 // read zero and write nothing, PEC nodes stay zero, soft sources are added,
 // and with CP the absorber recursion is applied per term.  Absorber
 // coefficients are loaded once per lane (x), per row (y) and per plane (z).
 // The arithmetic of every node is that of e_update / h_update.
-template <typename T>
-struct Cpml1 {
-    int side;                  // -1 outside the slabs
-    int idx;                   // index along the axis
-    T bE, cE, kE, bH, cH, kH;
-};
-
-template <typename T>
-__device__ __forceinline__ Cpml1<T> cpml_at(const DomDev<T>& d, int a, int x) {
-    Cpml1<T> c;
-    c.idx = x;
-    c.side = (x >= 0 && x < d.n[a]) ? slab_side(d, a, x) : -1;
-    c.bE = c.cE = c.kE = c.bH = c.cH = c.kH = T(0);
-    if (c.side >= 0) {
-        const FDTD_GLOBAL T* tb = gp(d.tab[a]);
-        int n = d.n[a];
-        c.bE = tb[x];
-        c.cE = tb[n + x];
-        c.kE = tb[2 * n + x];
-        c.bH = tb[3 * n + x];
-        c.cH = tb[4 * n + x];
-        c.kH = tb[5 * n + x];
-    }
-    return c;
-}
-
-// psi slab offset of node (i,j,k) on axis a, side s (32-bit)
-template <typename T>
-__device__ __forceinline__ int poff(const DomDev<T>& d, int a, int s, int i, int j, int k) {
-    int L = d.L[a][s];
-    if (a == 0) return (k * d.n[1] + j) * L + (s ? i - (d.n[0] - L) : i);
-    if (a == 1) return (k * L + (s ? j - (d.n[1] - L) : j)) * d.n[0] + i;
-    return ((s ? k - (d.n[2] - L) : k) * d.n[1] + j) * d.n[0] + i;
-}
-
-// one stretched term: psi_new = b psi + c D; D/kappa + psi_new (as stretch())
-template <typename T>
-__device__ __forceinline__ T st_term(T* base, long long rso, long long wso, bool own, T b, T c, T ki, T D) {
-    FDTD_GLOBAL T* g = gp(base);
-    T pn = fma(b, g[rso], c * D);
-    if (own) g[wso] = pn;
-    return fma(ki, D, pn);
-}
-
-// psi memories of the six terms of one node, slots ordered
-// 0: y-slab term of Ex (E) / Hx (H), 1: y-slab term of Ez / Hz,
-// 2: z-slab term of Ey / Hy, 3: z-slab term of Ex / Hx,
-// 4: x-slab term of Ez / Hz, 5: x-slab term of Ey / Hy.
-// (E side: Ex t0, Ez t1, Ey t0, Ex t1, Ez t0, Ey t1; H side: Hx t0, Hz t1,
-// Hy t0, Hx t1, Hz t0, Hy t1.)
-template <typename T>
-__device__ __forceinline__ void psi_load(const DomDev<T>& d, T* const (&psi)[3][2][2], long long so, bool v,
-                                         const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cz, int i, int j, int k,
-                                         T out[6]) {
-    for (int q = 0; q < 6; ++q) out[q] = T(0);
-    if (!v) return;
-    if (cy.side >= 0) {
-        int o = poff(d, 1, cy.side, i, j, k);
-        out[0] = gp(psi[1][cy.side][0] + so)[o];
-        out[1] = gp(psi[1][cy.side][1] + so)[o];
-    }
-    if (cz.side >= 0) {
-        int o = poff(d, 2, cz.side, i, j, k);
-        out[2] = gp(psi[2][cz.side][0] + so)[o];
-        out[3] = gp(psi[2][cz.side][1] + so)[o];
-    }
-    if (cx.side >= 0) {
-        int o = poff(d, 0, cx.side, i, j, k);
-        out[4] = gp(psi[0][cx.side][0] + so)[o];
-        out[5] = gp(psi[0][cx.side][1] + so)[o];
-    }
-}
-
-// stretched term from a prefetched memory: psi_new = b psi + c D (stored by
-// the owner), returns D/kappa + psi_new (the arithmetic of stretch())
-template <typename T>
-__device__ __forceinline__ T st_pref(T* base, long long wso, int off, bool own, T b, T c, T ki, T psi, T D) {
-    T pn = fma(b, psi, c * D);
-    if (own) gp(base + wso)[off] = pn;
-    return fma(ki, D, pn);
-}
 
 template <typename T, int R, bool CP>
 __device__ __forceinline__ void fwd_plain_body(const DomDev<T>& d, int X0, int Y0, int k0, int k1, int rs, int ws,
@@ -1190,6 +1182,12 @@ __device__ __forceinline__ void fwd_plain_body(const DomDev<T>& d, int X0, int Y
     }
 }
 
+// ============================================================ adjoint, bulk tiles
+// Tiles that lie inside the domain (no ghost nodes, no PEC nodes) and touch
+// no absorber, Lorentz cell or source: plain transposed Yee arithmetic,
+// 32-bit offsets, the next plane's loads issued before the current plane is
+// processed.  Results equal the general path bitwise.
+//
 // Adjoint of a bulk tile.  Hbar and Ebar (set rs) -> set ws; dJ/deps inside
 // the gradient box from the forward H (set fsr).  GRAD: the tile meets the
 // gradient box.
@@ -1595,6 +1593,7 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
         hipLaunchKernelGGL(k_fwd_e<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t);
+        if (c.nlor) hipLaunchKernelGGL(k_fwd_e_lor<T>, dim3(c.nlor), dim3(256), 0, s, dd, c.lbs, c.ndom, rs, ws, t);
         hipLaunchKernelGGL(k_fwd_h<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
         return;
     }

@@ -27,7 +27,9 @@ struct MonDev {
 // Fused: tile tables (domain, X0, Y0, k0) of general and bulk tiles.
 struct LaunchCfg {
     int kernel, rows, kz, nblk, ndom;
-    const int* bs;
+    const int* bs;             // split blocks per domain (prefix sums)
+    const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
+    int nlor;
     int ngen, nbulk;           // adjoint: general tiles, interior (bulk) tiles
     const int4* tgen;
     const int4* tbulk;

@@ -136,7 +136,7 @@ struct Handle : Base {
     DomDev<T>* d_doms = nullptr;
     int* d_bs = nullptr;
     LaunchCfg cfg{};
-    std::vector<int> bs_host;
+    std::vector<int> bs_host;   // [0, ndom]: split blocks; [ndom+1, 2 ndom+1]: Lorentz-box blocks
     std::vector<int4> tiles_gen, tiles_bulk, tiles_fgen, tiles_fcp, tiles_fplain;
     int4* d_tiles = nullptr;
     // pool: [misc][forward sets x nsets][adjoint sets x 2][split scratch][bf16 slots]
@@ -195,7 +195,8 @@ struct Handle : Base {
     // kz planes, listed as bulk when they lie inside the domain away from
     // PEC nodes, absorbers, the Lorentz box and sources, general otherwise.
     void build_tiles() {
-        bs_host.assign(ndom + 1, 0);
+        bs_host.assign(2 * (ndom + 1), 0);
+        int* lbs = bs_host.data() + ndom + 1;
         tiles_gen.clear();
         tiles_bulk.clear();
         tiles_fgen.clear();
@@ -206,6 +207,12 @@ struct Handle : Base {
             const fdtd_domain_desc& s = dh[q].desc;
             const int nx = s.n[0], ny = s.n[1], nz = s.n[2];
             bs_host[q + 1] = bs_host[q] + split_blocks(nx, ny, nz, kz);
+            long long nl = 0;
+            if (s.n_lorentz) {
+                const fdtd_lorentz_desc& L = s.lorentz;
+                nl = (long long)(L.hi[0] - L.lo[0]) * (L.hi[1] - L.lo[1]) * (L.hi[2] - L.lo[2]);
+            }
+            lbs[q + 1] = lbs[q] + (int)((nl + 255) / 256);
             if (cfg.kernel == 1) continue;
             for (int bz = 0; bz * kz < nz; ++bz)
                 for (int by = 0; by * TYo < ny; ++by)
@@ -248,6 +255,7 @@ struct Handle : Base {
                     }
         }
         cfg.nblk = bs_host[ndom];
+        cfg.nlor = lbs[ndom];
         cfg.ngen = (int)tiles_gen.size();
         cfg.nbulk = (int)tiles_bulk.size();
         cfg.nfgen = (int)tiles_fgen.size();
@@ -348,7 +356,7 @@ struct Handle : Base {
             }
         }
         M.take(d_doms, sizeof(DomDev<T>) * ndom);
-        M.take(d_bs, sizeof(int) * (ndom + 1));
+        M.take(d_bs, sizeof(int) * 2 * (ndom + 1));
         M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
                                                                tiles_fcp.size() + tiles_fplain.size()));
         M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
@@ -428,6 +436,7 @@ struct Handle : Base {
         wset[1] = 1;
         cur = 0;
         cfg.bs = d_bs;
+        cfg.lbs = d_bs + ndom + 1;
         cfg.tgen = d_tiles;
         cfg.tbulk = cfg.tgen + tiles_gen.size();
         cfg.tfgen = cfg.tbulk + tiles_bulk.size();
@@ -465,7 +474,7 @@ struct Handle : Base {
             }
         }
         if (hipMemcpyAsync(d_doms, dd.data(), sizeof(DomDev<T>) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(d_bs, bs_host.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+            hipMemcpyAsync(d_bs, bs_host.data(), sizeof(int) * 2 * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
             return fail(FDTD_E_DEVICE, "upload descriptors failed");
         {
             std::vector<int4> all(tiles_gen);
