@@ -50,11 +50,16 @@ def traffic_from_profiles(kernel_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_forward(spec, dtype, stream, K, Wm, tile=None):
+def run_forward(spec, dtype, stream, K, Wm, tile=None, graph_chunk=32):
+    """K timed solves from rest (after Wm warm-up solves) with captured step
+    chunks, then one solve with per-step kernel timing (eager launches, HIP
+    events on the library stream) for the roofline."""
     from paper_2609_30039_amd.sim import Simulation
     import torch
-    kw = tile or {}
-    sim = Simulation(spec, dtype=dtype, stream=stream, **kw)
+    kw = dict(tile or {})
+    if kw.get("kernel") != "split":
+        graph_chunk = 0
+    sim = Simulation(spec, dtype=dtype, stream=stream, graph_chunk=graph_chunk, **kw)
 
     def solve():
         sim.reset()
@@ -63,13 +68,13 @@ def run_forward(spec, dtype, stream, K, Wm, tile=None):
     for _ in range(Wm):
         solve()
     torch.cuda.synchronize()
-    sim.timing(1)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(K):
         solve()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    sim.timing(1)
+    solve()
     kms, nl = sim.timing(2)
     sim.timing(0)
     return sim, el, kms, nl
@@ -142,8 +147,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
-                     "kernel": ("k_fwd_e + k_fwd_h (split)" if tile["kernel"] == "split" else
-                                "fused single-pass tile kernels") + " per time step",
+                     "kernel": ("split E and H kernels (k_fwd_e, k_fwd_e_lor, k_fwd_h; lean and general block "
+                                "classes)" if tile["kernel"] == "split" else "fused single-pass tile kernels")
+                               + ": all stepping launches of one time step",
                      "launch_shape": tile,
                      "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_source_hash": khash},
@@ -204,7 +210,8 @@ def main():
         grads = {}
         for dt in ("f32", "f64"):
             tile3 = AT.tune(spec3, dt, adjoint=True, stream=stream, log=log)
-            sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream, **tile3)
+            sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream,
+                              graph_chunk=32 if tile3["kernel"] == "split" else 0, **tile3)
             plan = A.RevolvePlan(spec3.n_steps, 24)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -239,6 +246,51 @@ def main():
             del sim3
         g32, g64 = grads["f32"], grads["f64"]
         out["adjoint"]["grad_rel_l2_fp32_vs_fp64"] = float(f"{np.linalg.norm(g32 - g64) / np.linalg.norm(g64):.3e}")
+
+        # ------------------------------------------------------------ ragged batch: 48 domains in every launch
+        specs4 = W.batch_domains()
+        cells4 = sum(s_.ncells for s_ in specs4)
+        n4 = specs4[0].n_steps
+        tile4 = AT.tune(specs4, "f32", stream=stream, log=log, steps=3)
+        log(f"batch_domains: {len(specs4)} domains, {cells4} cells, {n4} steps, launch shape {tile4}")
+        sim4 = Simulation(specs4, dtype="f32", n_ckpt=16, stream=stream,
+                          graph_chunk=32 if tile4["kernel"] == "split" else 0, **tile4)
+        sim4.step(4, record=False)
+        sim4.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim4.step(n4, record=True)
+        torch.cuda.synchronize()
+        el4 = time.perf_counter() - t0
+        # forward + adjoint of the flux objective on the even domains (binomial, 16 slots)
+        plan4 = A.RevolvePlan(n4, 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last4 = A.forward_record(sim4, plan4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for d_, s_ in enumerate(specs4):
+            if s_.grad_box is None:
+                continue
+            sp = sim4.spectra(0, domain=d_)
+            g = np.zeros_like(sp)     # J = sum_f Re sum (Ex Hy* - Ey Hx*)
+            g[:, 0], g[:, 3], g[:, 1], g[:, 2] = sp[:, 3], sp[:, 0], -sp[:, 2], -sp[:, 1]
+            sim4.set_cotangent(0, g, domain=d_)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        A.reverse_sweep(sim4, plan4, *last4)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out["batch"] = {
+            "workload": f"{len(specs4)} ragged domains (per-axis interior from {{48,64,96,128,160}} + 10-cell CPML), "
+                        f"eps in [1,4], Ez dipole, {n4} steps FP32; even domains forward+adjoint of a flux objective, "
+                        f"16 checkpoints",
+            "cells": cells4, "forward_mcups": round(cells4 * n4 / el4 / 1e6, 1),
+            "record_s": round(t1 - t0, 4), "reverse_s": round(t3 - t2, 4),
+            "reverse_over_forward": round((t3 - t2) / (t1 - t0), 3),
+            "forward_evaluations": plan4.forward_evals + 1, "launch_shape": tile4}
+        log(f"batch: forward {cells4 * n4 / el4 / 1e6:.0f} Mcell/s, reverse/forward {(t3 - t2) / (t1 - t0):.2f}")
+        del sim4
 
         # ------------------------------------------------------------ large forward (cache-free roofline)
         spec5 = W.anisotropic_lorentz()

@@ -129,10 +129,9 @@ class FDTDFunction:
                 spec = sim.specs[0]
                 for mi, g in zip(ctx.mons, grads):
                     if g is None:
-                        g = torch.zeros(1)
-                        sim.set_cotangent(mi, np.zeros(sim._mon_shape(0, mi), dtype=np.complex128))
-                        continue
-                    sim.set_cotangent(mi, g.detach().cpu().numpy().astype(np.complex128))
+                        sim.set_cotangent(mi, np.zeros_like(sim.spectra(mi)))
+                    else:
+                        sim.set_cotangent(mi, g.detach().cpu().numpy().astype(np.complex128))
                 reverse_sweep(sim, plan, *ctx.last)
                 gb = sim.grad(0)
                 full = np.zeros(ctx.eps_shape)

@@ -50,9 +50,11 @@ struct Col {
 
 // split kernels: 256 threads = 64 (x) x 4 (y) columns, z chunk of length kz
 template <typename T>
-__device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int ndom, int kz, const DomDev<T>*& dp) {
+__device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int ndom, int kz, const DomDev<T>*& dp,
+                                      const int* list = nullptr) {
     Col c;
     int b = xcd_remap(blockIdx.x, gridDim.x);
+    if (list) b = list[b];   // a class of blocks: logical block ids
     int dom = find_domain(bs, ndom, b);
     dp = doms + dom;
     const DomDev<T>& d = *dp;
@@ -260,10 +262,12 @@ __device__ __forceinline__ void cole_fetch(const DomDev<T>& d, ColE<T>& p, const
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               int ndom, int kz, int rs, int ws, int t) {
+                                               int ndom, int kz, int rs, int ws, int t,
+                                               const int* __restrict__ tdev) {
     const DomDev<T>* dp;
     Col c = column(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
+    if (tdev) t += *tdev;   // graph replays: step index held on the device
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
     const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
@@ -338,13 +342,14 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
 // general per-node path with the auxiliary-differential-equation history.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_e_lor(const DomDev<T>* __restrict__ doms, const int* __restrict__ lbs,
-                                                   int ndom, int rs, int ws, int t) {
+                                                   int ndom, int rs, int ws, int t, const int* __restrict__ tdev) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     int dom = find_domain(lbs, ndom, b);
     const DomDev<T>& d = doms[dom];
     const int bx = d.lhi[0] - d.llo[0], by = d.lhi[1] - d.llo[1], bzn = d.lhi[2] - d.llo[2];
     long long q = (long long)(b - lbs[dom]) * 256 + threadIdx.x;
     if (!d.has_lor || q >= (long long)bx * by * bzn) return;
+    if (tdev) t += *tdev;
     const int i = d.llo[0] + (int)(q % bx), j = d.llo[1] + (int)((q / bx) % by), k = d.llo[2] + (int)(q / ((long long)bx * by));
     const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
     const long long f = (long long)k * pl + (long long)j * d.pitch + i;
@@ -448,14 +453,26 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
 }
 
 // ============================================================ adjoint, split
-// H transpose: Et = Ebar + (d+)^T of the H-update terms, from Hbar (set rs).
+// Two launches per adjoint step, shaped like the forward pair:
+//   k_adj_ht  at E nodes (gathers Hbar from the node and one step back, like
+//             the E update): cotangent of E^{n+1} after the H transpose, the
+//             E-update transpose with the Lorentz history, the new Ebar^n
+//             (set ws), the scaled cotangent U = S coef Ebar_pre (into the
+//             scratch Et), the E-side absorber memory cotangents (set ws) and
+//             dJ/deps from the forward state (set fsr);
+//   k_adj_et  at H nodes (gathers U from the node and one step forward, like
+//             the H update): Hbar^n (set ws) and the H-side absorber memory
+//             cotangents (set ws).
+// Every node's E-side work is done once; the raw-difference cotangent of an
+// E term at a neighbour is rebuilt from its U and its old memory cotangent.
+
+// cotangent of E^{n+1}_e after the H transpose, from Ebar (given) and Hbar
+// (set rs): term 1 of H_{e+1} along e+2 (+), term 2 of H_{e+2} along e+1 (-)
 template <typename T>
-__device__ __forceinline__ T ht_update(const DomDev<T>& d, int e, int i, int j, int k, long long f, T hb1, T hb1m,
-                                       T hb2, T hb2m, int rs) {
+__device__ __forceinline__ T ht_update_v(const DomDev<T>& d, int e, int i, int j, int k, T acc, T hb1, T hb1m,
+                                         T hb2, T hb2m, int rs) {
     if (e_masked(e, i, j, k)) return T(0);
-    // term 1: H_{e+1} along e+2 (+, slot 0); term 2: H_{e+2} along e+1 (-, slot 1)
     const int a1 = (e + 2) % 3, a2 = (e + 1) % 3;
-    T acc = gp(d.Ea[e])[f + rs * d.as];
     T t1 = hT_dbar(d, a1, 0, T(1), i, j, k, hb1, rs, rs, false);
     T t1m = coord(a1, i, j, k) > 0
                 ? hT_dbar(d, a1, 0, T(1), i - (a1 == 0), j - (a1 == 1), k - (a1 == 2), hb1m, rs, rs, false)
@@ -469,36 +486,214 @@ __device__ __forceinline__ T ht_update(const DomDev<T>& d, int e, int i, int j, 
     return acc;
 }
 
+// Transposed absorber term with hoisted coefficients: ybar through
+// mem = psibar + ybar, returns ki ybar + c mem (stretch_T, read only).
 template <typename T>
+__device__ __forceinline__ T tr_term(bool slab, T ki, T c, T psi, T ybar) {
+    return slab ? fma(ki, ybar, c * (psi + ybar)) : ybar;
+}
+
+template <typename T>
+struct AdjColE {
+    T hx, hy, hz, hy_xm, hz_xm, hx_ym, hz_ym;   // Hbar at the node and one step back along x and y
+    T eb[3], ei[3];                              // Ebar and eps^-1 at the node
+    T ph[6];                                     // H-side memory cotangents at the node (psi_load order)
+    T phx[2], phy[2];                            // at (i-1): x-slab slots 4, 5; at (j-1): y-slab slots 0, 1
+    T pe[6];                                     // E-side memory cotangents at the node
+};
+
+template <typename T>
+__device__ __forceinline__ void adje_fetch(const DomDev<T>& d, AdjColE<T>& p, const FDTD_GLOBAL T* const (&h)[3],
+                                           const FDTD_GLOBAL T* const (&e)[3], long long f, const EpsView<T>& ev,
+                                           bool cp, const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cxm,
+                                           const Cpml1<T>& cym, long long ro, int i, int j, int k) {
+    p.hx = h[0][f];
+    p.hy = h[1][f];
+    p.hz = h[2][f];
+    p.hy_xm = i > 0 ? h[1][f - 1] : T(0);
+    p.hz_xm = i > 0 ? h[2][f - 1] : T(0);
+    p.hx_ym = j > 0 ? h[0][f - d.pitch] : T(0);
+    p.hz_ym = j > 0 ? h[2][f - d.pitch] : T(0);
+    p.eb[0] = e[0][f];
+    p.eb[1] = e[1][f];
+    p.eb[2] = e[2][f];
+    eps_at(ev, i, j, k, p.ei);
+    if (cp) {
+        const Cpml1<T> cz = cpml_at(d, 2, k);
+        psi_load(d, d.psiHa, ro, true, cx, cy, cz, i, j, k, p.ph);
+        psi_load(d, d.psiEa, ro, true, cx, cy, cz, i, j, k, p.pe);
+        p.phx[0] = p.phx[1] = p.phy[0] = p.phy[1] = T(0);
+        if (cxm.side >= 0) {
+            int o = poff(d, 0, cxm.side, i - 1, j, k);
+            p.phx[0] = gp(d.psiHa[0][cxm.side][0] + ro)[o];
+            p.phx[1] = gp(d.psiHa[0][cxm.side][1] + ro)[o];
+        }
+        if (cym.side >= 0) {
+            int o = poff(d, 1, cym.side, i, j - 1, k);
+            p.phy[0] = gp(d.psiHa[1][cym.side][0] + ro)[o];
+            p.phy[1] = gp(d.psiHa[1][cym.side][1] + ro)[o];
+        }
+    }
+}
+
+// GEN = false: blocks that meet no absorber slab (one step back included) and
+// no Lorentz cell; the arithmetic of those nodes without the general paths
+// and their registers.  GEN = true: every block.
+template <typename T, bool GEN>
 __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                int ndom, int kz, int rs) {
+                                                const int* __restrict__ list, int ndom, int kz, int rs, int ws,
+                                                int fsr) {
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp);
+    Col c = column(doms, bs, ndom, kz, dp, list);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
     const int i = c.i, j = c.j;
-    const long long ro = rs * d.as;
-    const FDTD_GLOBAL T* Hx = gp(d.Ha[0] + ro);
-    const FDTD_GLOBAL T* Hy = gp(d.Ha[1] + ro);
-    const FDTD_GLOBAL T* Hz = gp(d.Ha[2] + ro);
-    T hxm = 0, hym = 0;
+    const long long ro = (long long)rs * d.as, wo = (long long)ws * d.as, pl = d.plane;
+    const FDTD_GLOBAL T* h[3] = {gp(d.Ha[0] + ro), gp(d.Ha[1] + ro), gp(d.Ha[2] + ro)};
+    const FDTD_GLOBAL T* e[3] = {gp(d.Ea[0] + ro), gp(d.Ea[1] + ro), gp(d.Ea[2] + ro)};
+    FDTD_GLOBAL T* ew[3] = {gp(d.Ea[0] + wo), gp(d.Ea[1] + wo), gp(d.Ea[2] + wo)};
+    FDTD_GLOBAL T* uw[3] = {gp(d.Et[0]), gp(d.Et[1]), gp(d.Et[2])};
+    const int x0 = i & ~63, y0 = j & ~3;
+    BlkFlags bf = blk_flags(d, x0, y0, c.k0, c.k1);
+    // one step back along x, y or z can reach a low slab the block itself misses
+    bool cp = bf.cp || (x0 > 0 && x0 - 1 < d.L[0][0]) || (y0 > 0 && y0 - 1 < d.L[1][0]) ||
+              (c.k0 > 0 && c.k0 - 1 < d.L[2][0]);
+    if (!GEN) cp = bf.lor = false;
+    const EpsView<T> ev = eps_view(d, x0, y0, 4, c.k0, c.k1 - 1);
+    const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j), cxm = cpml_at(d, 0, i - 1), cym = cpml_at(d, 1, j - 1);
+    const T S = d.S, mS = -d.S;
+    long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
+    T hxm = 0, hym = 0;      // Hbar x, y one plane below
+    T pzm2 = 0, pzm3 = 0;    // H-side z-slab memory cotangents one plane below (slots 2, 3)
     if (c.k0 > 0) {
-        long long f = fidx(d, i, j, c.k0 - 1);
-        hxm = Hx[f];
-        hym = Hy[f];
+        hxm = h[0][f - pl];
+        hym = h[1][f - pl];
+        const Cpml1<T> czm = cpml_at(d, 2, c.k0 - 1);
+        if (cp && czm.side >= 0) {
+            int o = poff(d, 2, czm.side, i, j, c.k0 - 1);
+            pzm2 = gp(d.psiHa[2][czm.side][0] + ro)[o];
+            pzm3 = gp(d.psiHa[2][czm.side][1] + ro)[o];
+        }
     }
-    for (int k = c.k0; k < c.k1; ++k) {
-        long long f = fidx(d, i, j, k);
-        T hx = Hx[f], hy = Hy[f], hz = Hz[f];
-        T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
-        T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
-        // Ex: Hy along z, Hz along y ; Ey: Hz along x, Hx along z ; Ez: Hx along y, Hy along x
-        gp(d.Et[0])[f] = ht_update(d, 0, i, j, k, f, hy, hym, hz, hz_ym, rs);
-        gp(d.Et[1])[f] = ht_update(d, 1, i, j, k, f, hz, hz_xm, hx, hxm, rs);
-        gp(d.Et[2])[f] = ht_update(d, 2, i, j, k, f, hx, hx_ym, hy, hy_xm, rs);
-        hxm = hx;
-        hym = hy;
+    AdjColE<T> cu, nx;
+    adje_fetch(d, cu, h, e, f, ev, cp, cx, cy, cxm, cym, ro, i, j, c.k0);
+    for (int k = c.k0; k < c.k1; ++k, f += pl) {
+        if (k + 1 < c.k1) adje_fetch(d, nx, h, e, f + pl, ev, cp, cx, cy, cxm, cym, ro, i, j, k + 1);
+        const Cpml1<T> cz = cpml_at(d, 2, k), czm = cpml_at(d, 2, k - 1);
+        const bool sx = cp && cx.side >= 0, sy = cp && cy.side >= 0, sz = cp && cz.side >= 0;
+        const bool sxm = cp && cxm.side >= 0, sym = cp && cym.side >= 0, szm = cp && czm.side >= 0;
+        // H transposes (hT_dbar): ybar = -S sign Hbar; term 1 (+), term 2 (-)
+        T et[3];
+        {   // Ex: Hy term 0 along z (slot 2), Hz term 1 along y (slot 1)
+            T t1 = tr_term(sz, cz.kH, cz.cH, cu.ph[2], mS * cu.hy);
+            T t1m = k > 0 ? tr_term(szm, czm.kH, czm.cH, pzm2, mS * hym) : T(0);
+            T t2 = tr_term(sy, cy.kH, cy.cH, cu.ph[1], S * cu.hz);
+            T t2m = j > 0 ? tr_term(sym, cym.kH, cym.cH, cu.phy[1], S * cu.hz_ym) : T(0);
+            T acc = cu.eb[0];
+            acc += t1m - t1;
+            acc += t2m - t2;
+            et[0] = (j == 0 || k == 0) ? T(0) : acc;
+        }
+        {   // Ey: Hz term 0 along x (slot 4), Hx term 1 along z (slot 3)
+            T t1 = tr_term(sx, cx.kH, cx.cH, cu.ph[4], mS * cu.hz);
+            T t1m = i > 0 ? tr_term(sxm, cxm.kH, cxm.cH, cu.phx[0], mS * cu.hz_xm) : T(0);
+            T t2 = tr_term(sz, cz.kH, cz.cH, cu.ph[3], S * cu.hx);
+            T t2m = k > 0 ? tr_term(szm, czm.kH, czm.cH, pzm3, S * hxm) : T(0);
+            T acc = cu.eb[1];
+            acc += t1m - t1;
+            acc += t2m - t2;
+            et[1] = (i == 0 || k == 0) ? T(0) : acc;
+        }
+        {   // Ez: Hx term 0 along y (slot 0), Hy term 1 along x (slot 5)
+            T t1 = tr_term(sy, cy.kH, cy.cH, cu.ph[0], mS * cu.hx);
+            T t1m = j > 0 ? tr_term(sym, cym.kH, cym.cH, cu.phy[0], mS * cu.hx_ym) : T(0);
+            T t2 = tr_term(sx, cx.kH, cx.cH, cu.ph[5], S * cu.hy);
+            T t2m = i > 0 ? tr_term(sxm, cxm.kH, cxm.cH, cu.phx[1], S * cu.hy_xm) : T(0);
+            T acc = cu.eb[2];
+            acc += t1m - t1;
+            acc += t2m - t2;
+            et[2] = (i == 0 || j == 0) ? T(0) : acc;
+        }
+        // E-update transposes at the node
+        T u[3], en[3], epre[3];
+        if (GEN && bf.lor && in_lor(d, i, j, k)) {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                AdjE<T> r = et_node(d, cc, i, j, k, et[cc], rs, ws, true);
+                en[cc] = r.en;
+                epre[cc] = r.epre;
+                u[cc] = e_masked(cc, i, j, k) ? T(0) : S * r.coef * r.epre;
+            }
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                en[cc] = et[cc];
+                epre[cc] = et[cc];
+                u[cc] = e_masked(cc, i, j, k) ? T(0) : S * cu.ei[cc] * et[cc];
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            ew[cc][f] = en[cc];
+            uw[cc][f] = u[cc];
+        }
+        // E-side memory cotangents (owner): psibar <- b (psibar + ybar), ybar = +u (term 0), -u (term 1)
+        if (cp) {
+            if (cy.side >= 0) {
+                int q = poff(d, 1, cy.side, i, j, k);
+                if (j > 0 && k > 0) gp(d.psiEa[1][cy.side][0] + wo)[q] = cy.bE * (cu.pe[0] + u[0]);    // Ex t0
+                if (i > 0 && j > 0) gp(d.psiEa[1][cy.side][1] + wo)[q] = cy.bE * (cu.pe[1] + -u[2]);   // Ez t1
+            }
+            if (cz.side >= 0) {
+                int q = poff(d, 2, cz.side, i, j, k);
+                if (i > 0 && k > 0) gp(d.psiEa[2][cz.side][0] + wo)[q] = cz.bE * (cu.pe[2] + u[1]);    // Ey t0
+                if (j > 0 && k > 0) gp(d.psiEa[2][cz.side][1] + wo)[q] = cz.bE * (cu.pe[3] + -u[0]);   // Ex t1
+            }
+            if (cx.side >= 0) {
+                int q = poff(d, 0, cx.side, i, j, k);
+                if (i > 0 && j > 0) gp(d.psiEa[0][cx.side][0] + wo)[q] = cx.bE * (cu.pe[4] + u[2]);    // Ez t0
+                if (i > 0 && k > 0) gp(d.psiEa[0][cx.side][1] + wo)[q] = cx.bE * (cu.pe[5] + -u[1]);   // Ey t1
+            }
+        }
+        // dJ/deps from the forward state
+        if (!GEN && in_gbox(d, i, j, k)) {
+            // no absorber or Lorentz cell here: -S eps^-2 Ebar_pre curl with the plain curl
+            const long long fo = (long long)fsr * d.fs;
+            const FDTD_GLOBAL T* hf[3] = {gp(d.H[0] + fo), gp(d.H[1] + fo), gp(d.H[2] + fo)};
+            const T fx = hf[0][f], fy = hf[1][f], fz = hf[2][f];
+            const T fz_ym = j > 0 ? hf[2][f - d.pitch] : T(0), fx_ym = j > 0 ? hf[0][f - d.pitch] : T(0);
+            const T fz_xm = i > 0 ? hf[2][f - 1] : T(0), fy_xm = i > 0 ? hf[1][f - 1] : T(0);
+            const T fy_zm = k > 0 ? hf[1][f - pl] : T(0), fx_zm = k > 0 ? hf[0][f - pl] : T(0);
+            const T curl[3] = {(fz - fz_ym) - (fy - fy_zm), (fx - fx_zm) - (fz - fz_xm), (fy - fy_xm) - (fx - fx_ym)};
+            double g[3] = {0, 0, 0};
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+                if (!e_masked(cc, i, j, k))
+                    g[cc] = -(double)epre[cc] * (double)(S * cu.ei[cc] * cu.ei[cc] * curl[cc]);
+            grad_store(d, i, j, k, g);
+        } else if (GEN && in_gbox(d, i, j, k)) {
+            const long long fo = (long long)fsr * d.fs;
+            T H[3], Hm[3][3];
+            for (int q = 0; q < 3; ++q) H[q] = gp(d.H[q])[f + fo];
+            for (int q = 0; q < 3; ++q) {
+                Hm[0][q] = i > 0 ? gp(d.H[q])[f + fo - 1] : T(0);
+                Hm[1][q] = j > 0 ? gp(d.H[q])[f + fo - d.pitch] : T(0);
+                Hm[2][q] = k > 0 ? gp(d.H[q])[f + fo - pl] : T(0);
+            }
+            double g[3] = {0, 0, 0};
+            for (int cc = 0; cc < 3; ++cc) {
+                if (e_masked(cc, i, j, k)) continue;
+                const int a0 = (cc + 1) % 3, a1 = (cc + 2) % 3, h0 = (cc + 2) % 3, h1 = (cc + 1) % 3;
+                g[cc] = grad_term(d, cc, i, j, k, f, epre[cc], H[h0], Hm[a0][h0], H[h1], Hm[a1][h1], fsr);
+            }
+            grad_store(d, i, j, k, g);
+        }
+        hxm = cu.hx;
+        hym = cu.hy;
+        pzm2 = cu.ph[2];
+        pzm3 = cu.ph[3];
+        cu = nx;
     }
 }
 
@@ -549,76 +744,156 @@ __device__ __forceinline__ Dbar6<T> et_cell(const DomDev<T>& d, int i, int j, in
     return o;
 }
 
-// Raw-difference cotangent of one curl term at a neighbouring E node, read only.
+// Raw-difference cotangent of term r of E_c at node (i,j,k) from its scaled
+// cotangent u and the memory cotangent of set rs (read only): ybar = +u
+// (term 0) or -u (term 1) through the transposed absorber recursion.
 template <typename T>
-__device__ __forceinline__ T et_dbar_at(const DomDev<T>& d, int cc, int term, int i, int j, int k, int rs) {
-    if (e_masked(cc, i, j, k)) return T(0);
-    long long f = fidx(d, i, j, k);
-    AdjE<T> r = et_node(d, cc, i, j, k, gp(d.Et[cc])[f], rs, rs, false);
-    int a = term == 0 ? (cc + 1) % 3 : (cc + 2) % 3;
-    return et_dbar(d, a, term, term == 0 ? T(1) : T(-1), i, j, k, r.epre, r.coef, rs, rs, false);
+__device__ __forceinline__ T u_dbar(const DomDev<T>& d, int c, int r, int i, int j, int k, T u, int rs) {
+    if (e_masked(c, i, j, k)) return T(0);
+    const int a = r == 0 ? (c + 1) % 3 : (c + 2) % 3;
+    return stretch_T(d, d.psiEa, rs, rs, false, a, r, 0, i, j, k, r == 0 ? u : -u);
 }
 
-// E transpose: Hbar += (d-)^T of the E-update terms; owner updates at E nodes.
 template <typename T>
+struct AdjColH {
+    T u1[3];                          // U one plane up
+    T uy_xp, uz_xp, ux_yp, uz_yp;     // U one step forward along x and y
+    T hb[3];                          // Hbar at the node (set rs)
+    T ph[6];                          // H-side memory cotangents at the node (psi_load order)
+    T pe1[6];                         // E-side memory cotangents one plane up
+    T pex[2], pey[2];                 // at (i+1): x-slab slots 4, 5; at (j+1): y-slab slots 0, 1
+};
+
+template <typename T>
+__device__ __forceinline__ void adjh_fetch(const DomDev<T>& d, AdjColH<T>& p, const FDTD_GLOBAL T* const (&u)[3],
+                                           const FDTD_GLOBAL T* const (&h)[3], long long f, bool cp,
+                                           const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cxp,
+                                           const Cpml1<T>& cyp, long long ro, int i, int j, int k) {
+    const bool up = k + 1 < d.n[2];
+    const long long pl = d.plane;
+    p.u1[0] = up ? u[0][f + pl] : T(0);
+    p.u1[1] = up ? u[1][f + pl] : T(0);
+    p.u1[2] = up ? u[2][f + pl] : T(0);
+    p.uy_xp = i + 1 < d.n[0] ? u[1][f + 1] : T(0);
+    p.uz_xp = i + 1 < d.n[0] ? u[2][f + 1] : T(0);
+    p.ux_yp = j + 1 < d.n[1] ? u[0][f + d.pitch] : T(0);
+    p.uz_yp = j + 1 < d.n[1] ? u[2][f + d.pitch] : T(0);
+    p.hb[0] = h[0][f];
+    p.hb[1] = h[1][f];
+    p.hb[2] = h[2][f];
+    if (cp) {
+        psi_load(d, d.psiHa, ro, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ph);
+        psi_load(d, d.psiEa, ro, up, cx, cy, cpml_at(d, 2, k + 1), i, j, k + 1, p.pe1);
+        p.pex[0] = p.pex[1] = p.pey[0] = p.pey[1] = T(0);
+        if (cxp.side >= 0) {
+            int o = poff(d, 0, cxp.side, i + 1, j, k);
+            p.pex[0] = gp(d.psiEa[0][cxp.side][0] + ro)[o];
+            p.pex[1] = gp(d.psiEa[0][cxp.side][1] + ro)[o];
+        }
+        if (cyp.side >= 0) {
+            int o = poff(d, 1, cyp.side, i, j + 1, k);
+            p.pey[0] = gp(d.psiEa[1][cyp.side][0] + ro)[o];
+            p.pey[1] = gp(d.psiEa[1][cyp.side][1] + ro)[o];
+        }
+    }
+}
+
+// the six raw-difference cotangents of the E node (i,j,k) from its U and its
+// E-side memory cotangents pe (psi_load order); masked components give zero
+template <typename T>
+__device__ __forceinline__ Dbar6<T> dbar6(int i, int j, int k, T ux, T uy, T uz, const T pe[6], bool sx, bool sy,
+                                          bool sz, const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cz) {
+    Dbar6<T> o;
+    const bool mx = j == 0 || k == 0, my = i == 0 || k == 0, mz = i == 0 || j == 0;
+    o.x0 = mx ? T(0) : tr_term(sy, cy.kE, cy.cE, pe[0], ux);     // Ex term 0 along y
+    o.x1 = mx ? T(0) : tr_term(sz, cz.kE, cz.cE, pe[3], -ux);    // Ex term 1 along z
+    o.y0 = my ? T(0) : tr_term(sz, cz.kE, cz.cE, pe[2], uy);     // Ey term 0 along z
+    o.y1 = my ? T(0) : tr_term(sx, cx.kE, cx.cE, pe[5], -uy);    // Ey term 1 along x
+    o.z0 = mz ? T(0) : tr_term(sx, cx.kE, cx.cE, pe[4], uz);     // Ez term 0 along x
+    o.z1 = mz ? T(0) : tr_term(sy, cy.kE, cy.cE, pe[1], -uz);    // Ez term 1 along y
+    return o;
+}
+
+// GEN = false: blocks that meet no absorber slab (one step forward included).
+template <typename T, bool GEN>
 __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                int ndom, int kz, int rs, int ws, int fsr) {
+                                                const int* __restrict__ list, int ndom, int kz, int rs, int ws) {
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp);
+    Col c = column(doms, bs, ndom, kz, dp, list);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
     const int i = c.i, j = c.j, nx = d.n[0], ny = d.n[1], nz = d.n[2];
-    const long long ro = rs * d.as, wo = ws * d.as;
-    auto owner = [&](int k) -> Dbar6<T> {
-        long long f = fidx(d, i, j, k);
-        T et[3] = {gp(d.Et[0])[f], gp(d.Et[1])[f], gp(d.Et[2])[f]};
-        T en[3];
-        Dbar6<T> o = et_cell(d, i, j, k, et, rs, ws, true, fsr, en);
-        gp(d.Ea[0])[f + wo] = en[0];
-        gp(d.Ea[1])[f + wo] = en[1];
-        gp(d.Ea[2])[f + wo] = en[2];
-        return o;
-    };
-    Dbar6<T> cur = owner(c.k0);
-    for (int k = c.k0; k < c.k1; ++k) {
-        long long f = fidx(d, i, j, k);
-        // z-terms one plane up: Ey term 0 (along z), Ex term 1 (along z)
-        Dbar6<T> nxt{};
-        T up_y0 = 0, up_x1 = 0;
-        if (k + 1 < c.k1) {
-            nxt = owner(k + 1);
-            up_y0 = nxt.y0;
-            up_x1 = nxt.x1;
-        } else if (k + 1 < nz) {
-            up_y0 = et_dbar_at(d, 1, 0, i, j, k + 1, rs);
-            up_x1 = et_dbar_at(d, 0, 1, i, j, k + 1, rs);
-        }
-        // x neighbour: Ez term 0 and Ey term 1 (along x); y neighbour: Ez term 1, Ex term 0 (along y)
+    const long long ro = (long long)rs * d.as, wo = (long long)ws * d.as, pl = d.plane;
+    const FDTD_GLOBAL T* u[3] = {gp(d.Et[0]), gp(d.Et[1]), gp(d.Et[2])};
+    const FDTD_GLOBAL T* h[3] = {gp(d.Ha[0] + ro), gp(d.Ha[1] + ro), gp(d.Ha[2] + ro)};
+    FDTD_GLOBAL T* hw[3] = {gp(d.Ha[0] + wo), gp(d.Ha[1] + wo), gp(d.Ha[2] + wo)};
+    const int x0 = i & ~63, y0 = j & ~3;
+    const BlkFlags bf = blk_flags(d, x0, y0, c.k0, c.k1);
+    // one step forward along x, y or z can reach a high slab the block itself misses
+    const bool cp = GEN && (bf.cp || (min(x0 + 64, nx - 1) >= nx - d.L[0][1] && d.L[0][1] > 0) ||
+                            (min(y0 + 4, ny - 1) >= ny - d.L[1][1] && d.L[1][1] > 0) ||
+                            (c.k1 < nz && c.k1 >= nz - d.L[2][1] && d.L[2][1] > 0));
+    const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j), cxp = cpml_at(d, 0, i + 1), cyp = cpml_at(d, 1, j + 1);
+    const T S = d.S, mS = -d.S;
+    long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
+    Dbar6<T> cur;
+    {
+        T pe[6] = {0, 0, 0, 0, 0, 0};
+        const Cpml1<T> cz = cpml_at(d, 2, c.k0);
+        if (cp) psi_load(d, d.psiEa, ro, true, cx, cy, cz, i, j, c.k0, pe);
+        cur = dbar6(i, j, c.k0, u[0][f], u[1][f], u[2][f], pe, cp && cx.side >= 0, cp && cy.side >= 0,
+                    cp && cz.side >= 0, cx, cy, cz);
+    }
+    AdjColH<T> cu, nx_;
+    adjh_fetch(d, cu, u, h, f, cp, cx, cy, cxp, cyp, ro, i, j, c.k0);
+    for (int k = c.k0; k < c.k1; ++k, f += pl) {
+        if (k + 1 < c.k1) adjh_fetch(d, nx_, u, h, f + pl, cp, cx, cy, cxp, cyp, ro, i, j, k + 1);
+        const Cpml1<T> cz = cpml_at(d, 2, k), czp = cpml_at(d, 2, k + 1);
+        const bool sx = cp && cx.side >= 0, sy = cp && cy.side >= 0, sz = cp && cz.side >= 0;
+        // E terms of the plane above (all six: they are the next plane's own terms)
+        Dbar6<T> up{};
+        if (k + 1 < nz)
+            up = dbar6(i, j, k + 1, cu.u1[0], cu.u1[1], cu.u1[2], cu.pe1, sx, sy, cp && czp.side >= 0, cx, cy, czp);
+        // x neighbour: Ez term 0 and Ey term 1 (along x); y neighbour: Ez term 1 and Ex term 0 (along y)
         T xp_z0 = 0, xp_y1 = 0, yp_z1 = 0, yp_x0 = 0;
         if (i + 1 < nx) {
-            xp_z0 = et_dbar_at(d, 2, 0, i + 1, j, k, rs);
-            xp_y1 = et_dbar_at(d, 1, 1, i + 1, j, k, rs);
+            const bool s = cp && cxp.side >= 0;
+            if (j > 0) xp_z0 = tr_term(s, cxp.kE, cxp.cE, cu.pex[0], cu.uz_xp);
+            if (k > 0) xp_y1 = tr_term(s, cxp.kE, cxp.cE, cu.pex[1], -cu.uy_xp);
         }
         if (j + 1 < ny) {
-            yp_z1 = et_dbar_at(d, 2, 1, i, j + 1, k, rs);
-            yp_x0 = et_dbar_at(d, 0, 0, i, j + 1, k, rs);
+            const bool s = cp && cyp.side >= 0;
+            if (i > 0) yp_z1 = tr_term(s, cyp.kE, cyp.cE, cu.pey[1], -cu.uz_yp);
+            if (k > 0) yp_x0 = tr_term(s, cyp.kE, cyp.cE, cu.pey[0], cu.ux_yp);
         }
-        T hbx = gp(d.Ha[0])[f + ro], hby = gp(d.Ha[1])[f + ro], hbz = gp(d.Ha[2])[f + ro];
-        // memory cotangents of the H update at this node (input Hbar)
-        hT_dbar(d, 1, 0, T(1), i, j, k, hbx, rs, ws, true);    // Hx term 0 along y
-        hT_dbar(d, 2, 1, T(-1), i, j, k, hbx, rs, ws, true);   // Hx term 1 along z
-        hT_dbar(d, 2, 0, T(1), i, j, k, hby, rs, ws, true);    // Hy term 0 along z
-        hT_dbar(d, 0, 1, T(-1), i, j, k, hby, rs, ws, true);   // Hy term 1 along x
-        hT_dbar(d, 0, 0, T(1), i, j, k, hbz, rs, ws, true);    // Hz term 0 along x
-        hT_dbar(d, 1, 1, T(-1), i, j, k, hbz, rs, ws, true);   // Hz term 1 along y
-        hbx += (cur.y0 - up_y0) + (cur.z1 - yp_z1);
-        hby += (cur.z0 - xp_z0) + (cur.x1 - up_x1);
+        T hbx = cu.hb[0], hby = cu.hb[1], hbz = cu.hb[2];
+        // H-side memory cotangents of this node (owner): psibar <- b (psibar + ybar), ybar = -S sign Hbar
+        if (cp) {
+            if (cy.side >= 0) {
+                int q = poff(d, 1, cy.side, i, j, k);
+                gp(d.psiHa[1][cy.side][0] + wo)[q] = cy.bH * (cu.ph[0] + mS * hbx);   // Hx term 0 along y
+                gp(d.psiHa[1][cy.side][1] + wo)[q] = cy.bH * (cu.ph[1] + S * hbz);    // Hz term 1 along y
+            }
+            if (cz.side >= 0) {
+                int q = poff(d, 2, cz.side, i, j, k);
+                gp(d.psiHa[2][cz.side][0] + wo)[q] = cz.bH * (cu.ph[2] + mS * hby);   // Hy term 0 along z
+                gp(d.psiHa[2][cz.side][1] + wo)[q] = cz.bH * (cu.ph[3] + S * hbx);    // Hx term 1 along z
+            }
+            if (cx.side >= 0) {
+                int q = poff(d, 0, cx.side, i, j, k);
+                gp(d.psiHa[0][cx.side][0] + wo)[q] = cx.bH * (cu.ph[4] + mS * hbz);   // Hz term 0 along x
+                gp(d.psiHa[0][cx.side][1] + wo)[q] = cx.bH * (cu.ph[5] + S * hby);    // Hy term 1 along x
+            }
+        }
+        hbx += (cur.y0 - up.y0) + (cur.z1 - yp_z1);
+        hby += (cur.z0 - xp_z0) + (cur.x1 - up.x1);
         hbz += (cur.x0 - yp_x0) + (cur.y1 - xp_y1);
-        gp(d.Ha[0])[f + wo] = hbx;
-        gp(d.Ha[1])[f + wo] = hby;
-        gp(d.Ha[2])[f + wo] = hbz;
-        cur = nxt;
+        hw[0][f] = hbx;
+        hw[1][f] = hby;
+        hw[2][f] = hbz;
+        cur = up;
+        cu = nx_;
     }
 }
 
@@ -1419,8 +1694,9 @@ __global__ void k_sample(const DomDev<T>* __restrict__ doms, MonDev m, int cs, i
 // FP64 spectra acc[f][comp][pt] += x * exp(-i w t), t = n (E) or n + 1/2 (H).
 // grid.y = frequency; the block's twiddles sit in LDS.
 template <typename T>
-__global__ void k_dft(MonDev m, int n0, int count) {
+__global__ void k_dft(MonDev m, int n0, int count, const int* __restrict__ tdev) {
     __shared__ double tw[2][2][kMaxDftBlock];   // [E|H][cos|sin][sample]
+    if (tdev) n0 += *tdev;
     int f = blockIdx.y;
     double w = m.omega[f];
     for (int s = threadIdx.x; s < count; s += blockDim.x) {
@@ -1453,8 +1729,10 @@ __global__ void k_dft(MonDev m, int n0, int count) {
 }
 
 template <typename T>
-__global__ void k_probe(const DomDev<T>* __restrict__ doms, MonDev m, int cs, int n) {
+__global__ void k_probe(const DomDev<T>* __restrict__ doms, MonDev m, int cs, int n, const int* __restrict__ tdev) {
     const DomDev<T>& d = doms[m.dom];
+    if (tdev) n += *tdev;
+    if (n < 0 || n >= m.ntrace) return;
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         long long f = fidx(d, m.pi, m.pj, m.k) + cs * d.fs;
         m.trace[n] = (double)(m.comp < 3 ? d.E[m.comp][f] : d.H[m.comp - 3][f]);
@@ -1507,6 +1785,12 @@ __global__ void k_probe_seed(const DomDev<T>* __restrict__ doms, MonDev m, int a
 }
 
 // ============================================================ utilities
+// device-resident step index of graph replays: set, or advance by the steps
+// a replay has taken
+__global__ void k_step_counter(int* __restrict__ c, int value, int add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = add ? *c + value : value;
+}
+
 __global__ void k_fill_zero(uint32_t* __restrict__ p, long long n_words) {
     long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long stride = (long long)gridDim.x * blockDim.x;
@@ -1589,11 +1873,14 @@ __global__ void __launch_bounds__(256) k_fwd_plain_nc(const DomDev<T>* __restric
     }
 
 template <typename T>
-void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s) {
+void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
-        hipLaunchKernelGGL(k_fwd_e<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t);
-        if (c.nlor) hipLaunchKernelGGL(k_fwd_e_lor<T>, dim3(c.nlor), dim3(256), 0, s, dd, c.lbs, c.ndom, rs, ws, t);
+        // one launch per pass over all blocks: a second launch for the
+        // interior blocks costs more in its drain than its leaner registers win
+        hipLaunchKernelGGL(k_fwd_e<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t, tdev);
+        if (c.nlor)
+            hipLaunchKernelGGL(k_fwd_e_lor<T>, dim3(c.nlor), dim3(256), 0, s, dd, c.lbs, c.ndom, rs, ws, t, tdev);
         hipLaunchKernelGGL(k_fwd_h<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
         return;
     }
@@ -1607,8 +1894,18 @@ template <typename T>
 void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
-        hipLaunchKernelGGL(k_adj_ht<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs);
-        hipLaunchKernelGGL(k_adj_et<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, fsr);
+        if (c.na1[0])
+            hipLaunchKernelGGL((k_adj_ht<T, false>), dim3(c.na1[0]), dim3(256), 0, s, dd, c.bs, c.la1[0], c.ndom, c.kz,
+                               rs, ws, fsr);
+        if (c.na1[1])
+            hipLaunchKernelGGL((k_adj_ht<T, true>), dim3(c.na1[1]), dim3(256), 0, s, dd, c.bs, c.la1[1], c.ndom, c.kz,
+                               rs, ws, fsr);
+        if (c.na2[0])
+            hipLaunchKernelGGL((k_adj_et<T, false>), dim3(c.na2[0]), dim3(256), 0, s, dd, c.bs, c.la2[0], c.ndom, c.kz,
+                               rs, ws);
+        if (c.na2[1])
+            hipLaunchKernelGGL((k_adj_et<T, true>), dim3(c.na2[1]), dim3(256), 0, s, dd, c.bs, c.la2[1], c.ndom, c.kz,
+                               rs, ws);
         return;
     }
     if (c.ngen) FDTD_ROWS_SWITCH(k_adj_fused, c.rows, dim3(c.ngen), dim3(256), 0, s, dd, c.tgen, c.kz, rs, ws, fsr)
@@ -1622,14 +1919,14 @@ void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStrea
 }
 
 template <typename T>
-void launch_dft(const MonDev& m, int n0, int count, hipStream_t s) {
+void launch_dft(const MonDev& m, int n0, int count, hipStream_t s, const int* tdev) {
     int npts = (m.i1 - m.i0) * (m.j1 - m.j0);
-    hipLaunchKernelGGL(k_dft<T>, dim3((npts + 255) / 256, m.nf), dim3(256), 0, s, m, n0, count);
+    hipLaunchKernelGGL(k_dft<T>, dim3((npts + 255) / 256, m.nf), dim3(256), 0, s, m, n0, count, tdev);
 }
 
 template <typename T>
-void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_probe<T>, dim3(1), dim3(64), 0, s, (const DomDev<T>*)doms, m, cs, n);
+void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t s, const int* tdev) {
+    hipLaunchKernelGGL(k_probe<T>, dim3(1), dim3(64), 0, s, (const DomDev<T>*)doms, m, cs, n, tdev);
 }
 
 template <typename T>
@@ -1640,6 +1937,10 @@ void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t 
     }
     int npts = (m.i1 - m.i0) * (m.j1 - m.j0);
     hipLaunchKernelGGL(k_seed<T>, dim3((npts + 255) / 256), dim3(256), 0, s, (const DomDev<T>*)doms, m, as_, n);
+}
+
+void launch_step_counter(int* c, int value, bool add, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_counter, dim3(1), dim3(64), 0, s, c, value, add ? 1 : 0);
 }
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
@@ -1676,11 +1977,11 @@ void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipSt
 int split_blocks(int nx, int ny, int nz, int kz) { return ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + kz - 1) / kz); }
 
 #define FDTD_INSTANTIATE(T)                                                                   \
-    template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t);   \
+    template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, const int*); \
     template void launch_adj<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t);   \
     template void launch_sample<T>(const void*, const MonDev&, int, int, hipStream_t);        \
-    template void launch_dft<T>(const MonDev&, int, int, hipStream_t);                        \
-    template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t);         \
+    template void launch_dft<T>(const MonDev&, int, int, hipStream_t, const int*);            \
+    template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t, const int*); \
     template void launch_seed<T>(const void*, const MonDev&, int, int, hipStream_t);
 FDTD_INSTANTIATE(float)
 FDTD_INSTANTIATE(double)

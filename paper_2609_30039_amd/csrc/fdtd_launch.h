@@ -18,7 +18,8 @@ struct MonDev {
     void* samples;                    // ring buffer [block][ncomp][npts] of the field type
     double* acc;                      // spectra [nf][ncomp][npts] (re, im)
     double* cot;                      // cotangents, same layout (probe: [max_steps])
-    double* trace;                    // probe samples [max_steps]
+    double* trace;                    // probe samples [ntrace]
+    int ntrace;
 };
 
 // One stepping launch over all domains: kernel 1 = split, 2 = fused; rows =
@@ -30,6 +31,13 @@ struct LaunchCfg {
     const int* bs;             // split blocks per domain (prefix sums)
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
+    // split adjoint: block classes [0] lean (no absorber slab within one
+    // step, no Lorentz cell), [1] general; logical block ids, domains with a
+    // gradient only
+    int na1[2], na2[2];
+    const int* la1[2];
+    const int* la2[2];
+
     int ngen, nbulk;           // adjoint: general tiles, interior (bulk) tiles
     const int4* tgen;
     const int4* tbulk;
@@ -42,21 +50,23 @@ struct LaunchCfg {
 constexpr int kFusedWaves = 4;
 
 template <typename T>
-void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s);
+// tdev: when set, kernels add the device-held step index to t (graph replays)
+void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev = nullptr);
 template <typename T>
 void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s);
 template <typename T>
 void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s);
 template <typename T>
-void launch_dft(const MonDev& m, int n0, int count, hipStream_t s);
+void launch_dft(const MonDev& m, int n0, int count, hipStream_t s, const int* tdev = nullptr);
 template <typename T>
-void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t s);
+void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t s, const int* tdev = nullptr);
 template <typename T>
 void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t s);
 
 int split_blocks(int nx, int ny, int nz, int kz);
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+void launch_step_counter(int* c, int value, bool add, hipStream_t s);
 void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 void launch_maxabs_f32(const float* x, long long n, unsigned int* out, hipStream_t s);
 void launch_pack_bf16(const float* x, long long n, const unsigned int* scale, uint16_t* y, hipStream_t s);

@@ -139,6 +139,10 @@ struct Handle : Base {
     std::vector<int> bs_host;   // [0, ndom]: split blocks; [ndom+1, 2 ndom+1]: Lorentz-box blocks
     std::vector<int4> tiles_gen, tiles_bulk, tiles_fgen, tiles_fcp, tiles_fplain;
     int4* d_tiles = nullptr;
+    // split-family block classes of the adjoint passes (logical block ids):
+    // E-node pass lean / general, H-node pass lean / general
+    std::vector<int> blist[4];
+    int* d_blist = nullptr;
     // pool: [misc][forward sets x nsets][adjoint sets x 2][split scratch][bf16 slots]
     char* pool = nullptr;
     size_t pool_bytes = 0, misc_bytes = 0, fstride = 0, astride = 0, et_bytes = 0, bfslot = 0;
@@ -156,6 +160,17 @@ struct Handle : Base {
     int ap = 0, t = 0, m = -1;
     int dft_block = 32;
     bool bf16 = false;
+    // captured step chunks (graph_chunk > 0): the kernels read the step index
+    // from d_tstep, which the replay advances; keyed by (record, current set)
+    int* d_tstep = nullptr;
+    int tstep_val = -1;                        // value d_tstep holds after the queued work (-1: unknown)
+    hipStream_t cst = nullptr;                 // capture stream
+    struct GraphEx {
+        int key;
+        hipGraph_t g;
+        hipGraphExec_t ex;
+    };
+    std::vector<GraphEx> graphs;
     // kernel timing
     bool timing_on = false;
     std::vector<hipEvent_t> evs;
@@ -166,6 +181,11 @@ struct Handle : Base {
         if (st) (void)hipStreamSynchronize(st);
         else (void)hipDeviceSynchronize();
         for (auto e : evs) (void)hipEventDestroy(e);
+        for (auto& g : graphs) {
+            (void)hipGraphExecDestroy(g.ex);
+            (void)hipGraphDestroy(g.g);
+        }
+        if (cst) (void)hipStreamDestroy(cst);
         (void)hipFree(pool);
     }
 
@@ -256,11 +276,53 @@ struct Handle : Base {
         }
         cfg.nblk = bs_host[ndom];
         cfg.nlor = lbs[ndom];
+        classify_split_blocks();
         cfg.ngen = (int)tiles_gen.size();
         cfg.nbulk = (int)tiles_bulk.size();
         cfg.nfgen = (int)tiles_fgen.size();
         cfg.nfcp = (int)tiles_fcp.size();
         cfg.nfplain = (int)tiles_fplain.size();
+    }
+
+    // A block of the split family is "lean" for a pass when no node it
+    // updates, nor any node one step back (E-node pass) or forward (H-node
+    // pass) whose memory it reads, lies in an absorber slab, and (E-node
+    // pass) none is a Lorentz cell.  The kernels' lean variants rely on this.
+    void classify_split_blocks() {
+        for (auto& l : blist) l.clear();
+        const int kz = cfg.kz;
+        for (int q = 0; q < ndom; ++q) {
+            const fdtd_domain_desc& s = dh[q].desc;
+            if (!s.grad) continue;
+            const int n[3] = {s.n[0], s.n[1], s.n[2]};
+            const int nbx = (n[0] + 63) / 64, nby = (n[1] + 3) / 4;
+            for (int lb = 0; lb < bs_host[q + 1] - bs_host[q]; ++lb) {
+                const int bx = lb % nbx, r = lb / nbx, by = r % nby, bz = r / nby;
+                const int lo[3] = {bx * 64, by * 4, bz * kz};
+                const int hi[3] = {std::min(lo[0] + 63, n[0] - 1), std::min(lo[1] + 3, n[1] - 1),
+                                   std::min(lo[2] + kz, n[2]) - 1};
+                bool cp = false, cpm = false, cpp = false;
+                for (int a = 0; a < 3; ++a) {
+                    const int L0 = s.pml[2 * a], L1 = s.pml[2 * a + 1];
+                    if (lo[a] < L0 || hi[a] >= n[a] - L1) cp = true;
+                    if (lo[a] > 0 && lo[a] - 1 < L0) cpm = true;
+                    if (L1 > 0 && hi[a] + 1 < n[a] && hi[a] + 1 >= n[a] - L1) cpp = true;
+                }
+                bool lor = false;
+                if (s.n_lorentz) {
+                    lor = true;
+                    for (int a = 0; a < 3; ++a)
+                        if (hi[a] < s.lorentz.lo[a] || lo[a] >= s.lorentz.hi[a]) lor = false;
+                }
+                const int b = bs_host[q] + lb;
+                blist[(cp || cpm || lor) ? 1 : 0].push_back(b);
+                blist[(cp || cpp) ? 3 : 2].push_back(b);
+            }
+        }
+        for (int c = 0; c < 2; ++c) {
+            cfg.na1[c] = (int)blist[c].size();
+            cfg.na2[c] = (int)blist[2 + c].size();
+        }
     }
 
     // ------------------------------------------------------------ layout
@@ -347,6 +409,7 @@ struct Handle : Base {
                 M.take(md.omega, std::max(1, md.nf) * 8);
                 if (md.kind == 0) {
                     M.take(md.trace, std::max(1, opt.max_steps) * 8);
+                    md.ntrace = std::max(1, opt.max_steps);
                     M.take(md.cot, std::max(1, opt.max_steps) * 8);
                 } else {
                     M.take(md.samples, (size_t)dft_block * md.ncomp * mh.npts * ts);
@@ -357,6 +420,10 @@ struct Handle : Base {
         }
         M.take(d_doms, sizeof(DomDev<T>) * ndom);
         M.take(d_bs, sizeof(int) * 2 * (ndom + 1));
+        M.take(d_tstep, sizeof(int));
+        size_t nbl = 0;
+        for (auto& l : blist) nbl += l.size();
+        M.take(d_blist, sizeof(int) * std::max<size_t>(1, nbl));
         M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
                                                                tiles_fcp.size() + tiles_fplain.size()));
         M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
@@ -369,6 +436,10 @@ struct Handle : Base {
         st = (hipStream_t)o->stream;
         ndom = n;
         dft_block = o->dft_block > 0 ? std::min(o->dft_block, kMaxDftBlock) : 32;
+        if (o->graph_chunk < 0 || o->graph_chunk > kMaxDftBlock)
+            return fail(FDTD_E_INVALID, "graph_chunk must be in [0, 64]");
+        // a captured chunk ends with the spectrum update of its samples
+        if (o->graph_chunk > 0) dft_block = o->graph_chunk;
         bf16 = o->ckpt_storage == FDTD_BF16;
         if (bf16 && sizeof(T) != 4) return fail(FDTD_E_INVALID, "BF16 checkpoints need FP32 fields");
         if (o->n_ckpt < 0 || o->max_steps < 0) return fail(FDTD_E_INVALID, "negative n_ckpt or max_steps");
@@ -442,6 +513,14 @@ struct Handle : Base {
         cfg.tfgen = cfg.tbulk + tiles_bulk.size();
         cfg.tfcp = cfg.tfgen + tiles_fgen.size();
         cfg.tfplain = cfg.tfcp + tiles_fcp.size();
+        {
+            const int* p = d_blist;
+            const int** dst[4] = {&cfg.la1[0], &cfg.la1[1], &cfg.la2[0], &cfg.la2[1]};
+            for (int c = 0; c < 4; ++c) {
+                *dst[c] = p;
+                p += blist[c].size();
+            }
+        }
         // ---- initialise: zero everything, upload tables and inputs
         launch_zero(pool, pool_bytes, st);
         int rc = check("zero pool");
@@ -485,6 +564,11 @@ struct Handle : Base {
             if (!all.empty() && hipMemcpyAsync(d_tiles, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice,
                                                st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "upload tile tables failed");
+            std::vector<int> bl;
+            for (auto& l : blist) bl.insert(bl.end(), l.begin(), l.end());
+            if (!bl.empty() && hipMemcpyAsync(d_blist, bl.data(), sizeof(int) * bl.size(), hipMemcpyHostToDevice,
+                                              st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "upload block classes failed");
         }
         return sync("create");
     }
@@ -722,6 +806,53 @@ struct Handle : Base {
 
     int write_set() const { return wset[0] != cur ? wset[0] : wset[1]; }
 
+    bool monitors_flushed() const {
+        for (auto& h : dh)
+            for (auto& mh : h.mons)
+                if (mh.dev.kind != 0 && mh.pending != 0) return false;
+        return true;
+    }
+
+    // Capture graph_chunk in-place split steps (with or without monitor
+    // work) into a graph: the step index comes from d_tstep, which the last
+    // node advances, so one executable serves every chunk.
+    int graph_for(bool rec, GraphEx*& out) {
+        const int key = (rec ? 1 : 0) | (cur << 1), G = opt.graph_chunk;
+        for (auto& g : graphs)
+            if (g.key == key) {
+                out = &g;
+                return FDTD_OK;
+            }
+        if (!cst && hipStreamCreateWithFlags(&cst, hipStreamNonBlocking) != hipSuccess)
+            return fail(FDTD_E_DEVICE, "capture stream");
+        if (hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(FDTD_E_DEVICE, "hipStreamBeginCapture failed");
+        for (int s = 0; s < G; ++s) {
+            launch_fwd<T>(cfg, d_doms, cur, cur, s, cst, d_tstep);
+            if (!rec) continue;
+            for (auto& h : dh)
+                for (auto& mh : h.mons) {
+                    if (mh.dev.kind == 0) launch_probe<T>(d_doms, mh.dev, cur, s, cst, d_tstep);
+                    else launch_sample<T>(d_doms, mh.dev, cur, s, cst);
+                }
+        }
+        if (rec)
+            for (auto& h : dh)
+                for (auto& mh : h.mons)
+                    if (mh.dev.kind != 0) launch_dft<T>(mh.dev, 1, G, cst, d_tstep);
+        launch_step_counter(d_tstep, G, true, cst);
+        GraphEx ge{key, nullptr, nullptr};
+        if (hipStreamEndCapture(cst, &ge.g) != hipSuccess || !ge.g)
+            return fail(FDTD_E_DEVICE, "hipStreamEndCapture failed");
+        if (hipGraphInstantiate(&ge.ex, ge.g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(ge.g);
+            return fail(FDTD_E_DEVICE, "hipGraphInstantiate failed");
+        }
+        graphs.push_back(ge);
+        out = &graphs.back();
+        return FDTD_OK;
+    }
+
     int step_forward(int n, unsigned flags) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
         bool rec = (flags & FDTD_RECORD) && !(flags & FDTD_REPLAY);
@@ -729,14 +860,28 @@ struct Handle : Base {
         // reads neighbours' old values after they are overwritten, so it
         // writes the other set.  A restored slot is never written.
         const bool inplace = cfg.kernel == 1;
-        for (int s = 0; s < n; ++s) {
-            int ws = inplace && (cur == wset[0] || cur == wset[1]) ? cur : write_set();
+        const int G = opt.graph_chunk;
+        for (int s = 0; s < n;) {
+            const bool working = cur == wset[0] || cur == wset[1];
+            if (G > 0 && inplace && working && !timing_on && n - s >= G && (!rec || monitors_flushed())) {
+                GraphEx* g = nullptr;
+                int rc = graph_for(rec, g);
+                if (rc) return rc;
+                if (tstep_val != t) launch_step_counter(d_tstep, t, false, st);
+                if (hipGraphLaunch(g->ex, st) != hipSuccess) return fail(FDTD_E_DEVICE, "hipGraphLaunch failed");
+                t += G;
+                tstep_val = t;
+                s += G;
+                continue;
+            }
+            int ws = inplace && working ? cur : write_set();
             if (timing_on) ev_mark();
             launch_fwd<T>(cfg, d_doms, cur, ws, t, st);
             if (timing_on) ev_mark();
             cur = ws;
             ++t;
             if (rec) record();
+            ++s;
         }
         return check("step_forward");
     }

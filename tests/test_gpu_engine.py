@@ -197,3 +197,78 @@ def test_kernel_timing_counts_launches():
     sim.step(30)
     ms, n = sim.timing(2)
     assert n == 30 and ms > 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_graph_chunks_equal_eager_steps(dtype):
+    """Captured chunks of in-place steps (monitors included) give the eager
+    results bitwise; replays interleave with eager steps, host reads,
+    checkpoint swaps and restores, and every replay is checked."""
+    spec = _case(n_steps=120)
+    spec.monitors.append(W.MonitorSpec("probe", comp=2, pos=(30, 20, 30)))
+    G = 8
+    # same spectrum block length: the FP64 time sums are grouped per block
+    eager = Simulation(spec, dtype=dtype, n_ckpt=2, dft_block=G)
+    graph = Simulation(spec, dtype=dtype, n_ckpt=2, graph_chunk=G)
+    nmon = len(spec.monitors)
+
+    def same(tag):
+        assert eager.steps == graph.steps, tag
+        for q in range(6):
+            assert np.array_equal(eager.field(q), graph.field(q)), (tag, q)
+        for mi in range(nmon):
+            assert np.array_equal(eager.spectra(mi), graph.spectra(mi)), (tag, mi)
+
+    for sim in (eager, graph):
+        sim.step(2 * G)                    # two replays of the recording chunk
+    same("record x2")
+    for sim in (eager, graph):
+        sim.step(3)                        # eager steps leave monitors mid-block
+        sim.step(G + 5)                    # -> no recording chunk until flushed
+    same("unaligned")
+    for sim in (eager, graph):
+        sim.save(1)                        # role swap: the working set changes
+        sim.step(3 * G, record=False)      # replay chunks on the new set
+    same("replay after save")
+    for sim in (eager, graph):
+        sim.restore(1)                     # first step leaves the slot intact
+        sim.step(2 * G + 1, record=False)
+    same("after restore")
+    for sim in (eager, graph):
+        sim.reset()
+        sim.step(4 * G)
+    same("after reset")
+
+
+def test_split_block_classes_at_slab_edges():
+    """Absorber depth 8 with 4-row blocks and 4-plane chunks puts block edges
+    exactly on slab faces, so blocks whose neighbour one step back or forward
+    lies in a slab (and only that neighbour) occur on every face: the lean
+    and general block classes must still give the fused results bitwise."""
+    spec = W.lorentz_flux(pml=8, lorentz=8, n_steps=40, n_f=3, shape=(150, 68, 52))
+    nx, ny, nz = spec.shape
+    lo, hi = (70, 30, 20), (78, 38, 28)
+    spec.lorentz[0].lo, spec.lorentz[0].hi = lo, hi
+    spec.eps_box = (lo, hi)
+    spec.grad_box = ((4, 4, 4), (nx - 4, ny - 4, nz - 4))
+    N = spec.n_steps
+    res = {}
+    for kern, rows, kz in (("split", 0, 4), ("split", 0, 16), ("fused", 2, 8)):
+        sim = Simulation(spec, dtype="f32", kernel=kern, n_ckpt=N + 1, tile_rows=rows, tile_kz=kz)
+        sim.save(0)
+        for t in range(N):
+            sim.step(1)
+            sim.save(t + 1)
+        fields = _fields(sim)
+        sim.set_cotangent(0, flux_objective(sim.spectra(0))[1])
+        sim.adjoint_begin(N)
+        for m_ in range(N, 0, -1):
+            sim.restore(m_ - 1)
+            sim.step_adjoint(1)
+        res[(kern, kz)] = (fields, sim.grad(), [sim.field(q, adjoint=True) for q in range(6)])
+    ref = res[("fused", 8)]
+    for key, val in res.items():
+        for q in range(6):
+            assert np.array_equal(ref[0][q], val[0][q]), (key, "fwd", q)
+            assert np.array_equal(ref[2][q], val[2][q]), (key, "adj", q)
+        assert np.array_equal(ref[1], val[1]), (key, "grad")
