@@ -71,6 +71,35 @@ __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int 
     return c;
 }
 
+// Tile-table columns of the split adjoint.  A tile is (domain, x0 | xlen << 24,
+// y0, k0): W = 64, one row of 64 x-columns per wave (4 rows per block); W =
+// 16, 16 x-columns by 4 rows per wave (16 rows per block), for the narrow
+// x-slab zones.  Columns at or beyond x0 + xlen are idle.
+template <int W>
+struct TileCol {
+    int i, j, k0, k1, x0, y0;
+    bool ok;
+};
+
+template <typename T, int W>
+__device__ __forceinline__ TileCol<W> tile_column(const DomDev<T>* doms, const int4* tiles, int kz,
+                                                  const DomDev<T>*& dp) {
+    TileCol<W> c;
+    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+    dp = doms + e.x;
+    const DomDev<T>& d = *dp;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int xlen = e.y >> 24, lx = W == 64 ? lane : (lane & 15);
+    c.x0 = e.y & 0xFFFFFF;
+    c.y0 = e.z;
+    c.i = c.x0 + lx;
+    c.j = W == 64 ? e.z + w : e.z + 4 * w + (lane >> 4);
+    c.k0 = e.w;
+    c.k1 = min(e.w + kz, d.n[2]);
+    c.ok = lx < xlen && c.j < d.n[1];
+    return c;
+}
+
 // ------------------------------------------------------------ per-axis views
 // Absorber coefficients of one index along an axis, eps^-1 over a block, and
 // absorber memories fetched ahead: shared by the split and the plain tile
@@ -493,6 +522,26 @@ __device__ __forceinline__ T tr_term(bool slab, T ki, T c, T psi, T ybar) {
     return slab ? fma(ki, ybar, c * (psi + ybar)) : ybar;
 }
 
+// Variant masks of the adjoint passes: bit 0, 1, 2 = the block (or the
+// neighbour one step back / forward that it reads) meets the x, y, z absorber
+// slabs, so those memory cotangents are handled; bit 3 (E-node pass) = the
+// block holds Lorentz cells or gradient cells inside a slab, which take the
+// general per-node path.  The host sorts blocks into classes; each class is
+// a kernel of its own with only the registers it needs.
+constexpr int kAdjFull = 15;
+
+// the two memory slots (psi_load order) of axis a at node (i,j,k), if the
+// node lies in that axis' slab
+template <typename T>
+__device__ __forceinline__ void psi_axis(const DomDev<T>& d, T* const (&psi)[3][2][2], long long so, int a,
+                                         const Cpml1<T>& ca, int i, int j, int k, T& p0, T& p1) {
+    p0 = p1 = T(0);
+    if (ca.side < 0) return;
+    int o = poff(d, a, ca.side, i, j, k);
+    p0 = gp(psi[a][ca.side][0] + so)[o];
+    p1 = gp(psi[a][ca.side][1] + so)[o];
+}
+
 template <typename T>
 struct AdjColE {
     T hx, hy, hz, hy_xm, hz_xm, hx_ym, hz_ym;   // Hbar at the node and one step back along x and y
@@ -502,10 +551,10 @@ struct AdjColE {
     T pe[6];                                     // E-side memory cotangents at the node
 };
 
-template <typename T>
+template <typename T, int V>
 __device__ __forceinline__ void adje_fetch(const DomDev<T>& d, AdjColE<T>& p, const FDTD_GLOBAL T* const (&h)[3],
                                            const FDTD_GLOBAL T* const (&e)[3], long long f, const EpsView<T>& ev,
-                                           bool cp, const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cxm,
+                                           const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cxm,
                                            const Cpml1<T>& cym, long long ro, int i, int j, int k) {
     p.hx = h[0][f];
     p.hy = h[1][f];
@@ -518,33 +567,28 @@ __device__ __forceinline__ void adje_fetch(const DomDev<T>& d, AdjColE<T>& p, co
     p.eb[1] = e[1][f];
     p.eb[2] = e[2][f];
     eps_at(ev, i, j, k, p.ei);
-    if (cp) {
+    if (V & 1) {
+        psi_axis(d, d.psiHa, ro, 0, cx, i, j, k, p.ph[4], p.ph[5]);
+        psi_axis(d, d.psiEa, ro, 0, cx, i, j, k, p.pe[4], p.pe[5]);
+        psi_axis(d, d.psiHa, ro, 0, cxm, i - 1, j, k, p.phx[0], p.phx[1]);
+    }
+    if (V & 2) {
+        psi_axis(d, d.psiHa, ro, 1, cy, i, j, k, p.ph[0], p.ph[1]);
+        psi_axis(d, d.psiEa, ro, 1, cy, i, j, k, p.pe[0], p.pe[1]);
+        psi_axis(d, d.psiHa, ro, 1, cym, i, j - 1, k, p.phy[0], p.phy[1]);
+    }
+    if (V & 4) {
         const Cpml1<T> cz = cpml_at(d, 2, k);
-        psi_load(d, d.psiHa, ro, true, cx, cy, cz, i, j, k, p.ph);
-        psi_load(d, d.psiEa, ro, true, cx, cy, cz, i, j, k, p.pe);
-        p.phx[0] = p.phx[1] = p.phy[0] = p.phy[1] = T(0);
-        if (cxm.side >= 0) {
-            int o = poff(d, 0, cxm.side, i - 1, j, k);
-            p.phx[0] = gp(d.psiHa[0][cxm.side][0] + ro)[o];
-            p.phx[1] = gp(d.psiHa[0][cxm.side][1] + ro)[o];
-        }
-        if (cym.side >= 0) {
-            int o = poff(d, 1, cym.side, i, j - 1, k);
-            p.phy[0] = gp(d.psiHa[1][cym.side][0] + ro)[o];
-            p.phy[1] = gp(d.psiHa[1][cym.side][1] + ro)[o];
-        }
+        psi_axis(d, d.psiHa, ro, 2, cz, i, j, k, p.ph[2], p.ph[3]);
+        psi_axis(d, d.psiEa, ro, 2, cz, i, j, k, p.pe[2], p.pe[3]);
     }
 }
 
-// GEN = false: blocks that meet no absorber slab (one step back included) and
-// no Lorentz cell; the arithmetic of those nodes without the general paths
-// and their registers.  GEN = true: every block.
-template <typename T, bool GEN>
-__global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                const int* __restrict__ list, int ndom, int kz, int rs, int ws,
-                                                int fsr) {
+template <typename T, int V, int W>
+__global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                int kz, int rs, int ws, int fsr) {
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp, list);
+    const TileCol<W> c = tile_column<T, W>(doms, tiles, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
@@ -554,13 +598,9 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
     const FDTD_GLOBAL T* e[3] = {gp(d.Ea[0] + ro), gp(d.Ea[1] + ro), gp(d.Ea[2] + ro)};
     FDTD_GLOBAL T* ew[3] = {gp(d.Ea[0] + wo), gp(d.Ea[1] + wo), gp(d.Ea[2] + wo)};
     FDTD_GLOBAL T* uw[3] = {gp(d.Et[0]), gp(d.Et[1]), gp(d.Et[2])};
-    const int x0 = i & ~63, y0 = j & ~3;
-    BlkFlags bf = blk_flags(d, x0, y0, c.k0, c.k1);
-    // one step back along x, y or z can reach a low slab the block itself misses
-    bool cp = bf.cp || (x0 > 0 && x0 - 1 < d.L[0][0]) || (y0 > 0 && y0 - 1 < d.L[1][0]) ||
-              (c.k0 > 0 && c.k0 - 1 < d.L[2][0]);
-    if (!GEN) cp = bf.lor = false;
-    const EpsView<T> ev = eps_view(d, x0, y0, 4, c.k0, c.k1 - 1);
+    constexpr bool CX = V & 1, CY = V & 2, CZ = V & 4, FULL = V & 8;
+    constexpr int NR = W == 64 ? 4 : 16;   // rows per block
+    const EpsView<T> ev = eps_view(d, c.x0, c.y0, NR, c.k0, c.k1 - 1);
     const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j), cxm = cpml_at(d, 0, i - 1), cym = cpml_at(d, 1, j - 1);
     const T S = d.S, mS = -d.S;
     long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
@@ -569,20 +609,15 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
     if (c.k0 > 0) {
         hxm = h[0][f - pl];
         hym = h[1][f - pl];
-        const Cpml1<T> czm = cpml_at(d, 2, c.k0 - 1);
-        if (cp && czm.side >= 0) {
-            int o = poff(d, 2, czm.side, i, j, c.k0 - 1);
-            pzm2 = gp(d.psiHa[2][czm.side][0] + ro)[o];
-            pzm3 = gp(d.psiHa[2][czm.side][1] + ro)[o];
-        }
+        if (CZ) psi_axis(d, d.psiHa, ro, 2, cpml_at(d, 2, c.k0 - 1), i, j, c.k0 - 1, pzm2, pzm3);
     }
     AdjColE<T> cu, nx;
-    adje_fetch(d, cu, h, e, f, ev, cp, cx, cy, cxm, cym, ro, i, j, c.k0);
+    adje_fetch<T, V>(d, cu, h, e, f, ev, cx, cy, cxm, cym, ro, i, j, c.k0);
     for (int k = c.k0; k < c.k1; ++k, f += pl) {
-        if (k + 1 < c.k1) adje_fetch(d, nx, h, e, f + pl, ev, cp, cx, cy, cxm, cym, ro, i, j, k + 1);
+        if (k + 1 < c.k1) adje_fetch<T, V>(d, nx, h, e, f + pl, ev, cx, cy, cxm, cym, ro, i, j, k + 1);
         const Cpml1<T> cz = cpml_at(d, 2, k), czm = cpml_at(d, 2, k - 1);
-        const bool sx = cp && cx.side >= 0, sy = cp && cy.side >= 0, sz = cp && cz.side >= 0;
-        const bool sxm = cp && cxm.side >= 0, sym = cp && cym.side >= 0, szm = cp && czm.side >= 0;
+        const bool sx = CX && cx.side >= 0, sy = CY && cy.side >= 0, sz = CZ && cz.side >= 0;
+        const bool sxm = CX && cxm.side >= 0, sym = CY && cym.side >= 0, szm = CZ && czm.side >= 0;
         // H transposes (hT_dbar): ybar = -S sign Hbar; term 1 (+), term 2 (-)
         T et[3];
         {   // Ex: Hy term 0 along z (slot 2), Hz term 1 along y (slot 1)
@@ -617,7 +652,7 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
         }
         // E-update transposes at the node
         T u[3], en[3], epre[3];
-        if (GEN && bf.lor && in_lor(d, i, j, k)) {
+        if (FULL && in_lor(d, i, j, k)) {
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
                 AdjE<T> r = et_node(d, cc, i, j, k, et[cc], rs, ws, true);
@@ -639,25 +674,23 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
             uw[cc][f] = u[cc];
         }
         // E-side memory cotangents (owner): psibar <- b (psibar + ybar), ybar = +u (term 0), -u (term 1)
-        if (cp) {
-            if (cy.side >= 0) {
-                int q = poff(d, 1, cy.side, i, j, k);
-                if (j > 0 && k > 0) gp(d.psiEa[1][cy.side][0] + wo)[q] = cy.bE * (cu.pe[0] + u[0]);    // Ex t0
-                if (i > 0 && j > 0) gp(d.psiEa[1][cy.side][1] + wo)[q] = cy.bE * (cu.pe[1] + -u[2]);   // Ez t1
-            }
-            if (cz.side >= 0) {
-                int q = poff(d, 2, cz.side, i, j, k);
-                if (i > 0 && k > 0) gp(d.psiEa[2][cz.side][0] + wo)[q] = cz.bE * (cu.pe[2] + u[1]);    // Ey t0
-                if (j > 0 && k > 0) gp(d.psiEa[2][cz.side][1] + wo)[q] = cz.bE * (cu.pe[3] + -u[0]);   // Ex t1
-            }
-            if (cx.side >= 0) {
-                int q = poff(d, 0, cx.side, i, j, k);
-                if (i > 0 && j > 0) gp(d.psiEa[0][cx.side][0] + wo)[q] = cx.bE * (cu.pe[4] + u[2]);    // Ez t0
-                if (i > 0 && k > 0) gp(d.psiEa[0][cx.side][1] + wo)[q] = cx.bE * (cu.pe[5] + -u[1]);   // Ey t1
-            }
+        if (sy) {
+            int q = poff(d, 1, cy.side, i, j, k);
+            if (j > 0 && k > 0) gp(d.psiEa[1][cy.side][0] + wo)[q] = cy.bE * (cu.pe[0] + u[0]);    // Ex t0
+            if (i > 0 && j > 0) gp(d.psiEa[1][cy.side][1] + wo)[q] = cy.bE * (cu.pe[1] + -u[2]);   // Ez t1
+        }
+        if (sz) {
+            int q = poff(d, 2, cz.side, i, j, k);
+            if (i > 0 && k > 0) gp(d.psiEa[2][cz.side][0] + wo)[q] = cz.bE * (cu.pe[2] + u[1]);    // Ey t0
+            if (j > 0 && k > 0) gp(d.psiEa[2][cz.side][1] + wo)[q] = cz.bE * (cu.pe[3] + -u[0]);   // Ex t1
+        }
+        if (sx) {
+            int q = poff(d, 0, cx.side, i, j, k);
+            if (i > 0 && j > 0) gp(d.psiEa[0][cx.side][0] + wo)[q] = cx.bE * (cu.pe[4] + u[2]);    // Ez t0
+            if (i > 0 && k > 0) gp(d.psiEa[0][cx.side][1] + wo)[q] = cx.bE * (cu.pe[5] + -u[1]);   // Ey t1
         }
         // dJ/deps from the forward state
-        if (!GEN && in_gbox(d, i, j, k)) {
+        if (!FULL && in_gbox(d, i, j, k)) {
             // no absorber or Lorentz cell here: -S eps^-2 Ebar_pre curl with the plain curl
             const long long fo = (long long)fsr * d.fs;
             const FDTD_GLOBAL T* hf[3] = {gp(d.H[0] + fo), gp(d.H[1] + fo), gp(d.H[2] + fo)};
@@ -672,7 +705,7 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
                 if (!e_masked(cc, i, j, k))
                     g[cc] = -(double)epre[cc] * (double)(S * cu.ei[cc] * cu.ei[cc] * curl[cc]);
             grad_store(d, i, j, k, g);
-        } else if (GEN && in_gbox(d, i, j, k)) {
+        } else if (FULL && in_gbox(d, i, j, k)) {
             const long long fo = (long long)fsr * d.fs;
             T H[3], Hm[3][3];
             for (int q = 0; q < 3; ++q) H[q] = gp(d.H[q])[f + fo];
@@ -691,8 +724,10 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
         }
         hxm = cu.hx;
         hym = cu.hy;
-        pzm2 = cu.ph[2];
-        pzm3 = cu.ph[3];
+        if (CZ) {
+            pzm2 = cu.ph[2];
+            pzm3 = cu.ph[3];
+        }
         cu = nx;
     }
 }
@@ -764,11 +799,11 @@ struct AdjColH {
     T pex[2], pey[2];                 // at (i+1): x-slab slots 4, 5; at (j+1): y-slab slots 0, 1
 };
 
-template <typename T>
+template <typename T, int V>
 __device__ __forceinline__ void adjh_fetch(const DomDev<T>& d, AdjColH<T>& p, const FDTD_GLOBAL T* const (&u)[3],
-                                           const FDTD_GLOBAL T* const (&h)[3], long long f, bool cp,
-                                           const Cpml1<T>& cx, const Cpml1<T>& cy, const Cpml1<T>& cxp,
-                                           const Cpml1<T>& cyp, long long ro, int i, int j, int k) {
+                                           const FDTD_GLOBAL T* const (&h)[3], long long f, const Cpml1<T>& cx,
+                                           const Cpml1<T>& cy, const Cpml1<T>& cxp, const Cpml1<T>& cyp, long long ro,
+                                           int i, int j, int k) {
     const bool up = k + 1 < d.n[2];
     const long long pl = d.plane;
     p.u1[0] = up ? u[0][f + pl] : T(0);
@@ -781,20 +816,22 @@ __device__ __forceinline__ void adjh_fetch(const DomDev<T>& d, AdjColH<T>& p, co
     p.hb[0] = h[0][f];
     p.hb[1] = h[1][f];
     p.hb[2] = h[2][f];
-    if (cp) {
-        psi_load(d, d.psiHa, ro, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ph);
-        psi_load(d, d.psiEa, ro, up, cx, cy, cpml_at(d, 2, k + 1), i, j, k + 1, p.pe1);
-        p.pex[0] = p.pex[1] = p.pey[0] = p.pey[1] = T(0);
-        if (cxp.side >= 0) {
-            int o = poff(d, 0, cxp.side, i + 1, j, k);
-            p.pex[0] = gp(d.psiEa[0][cxp.side][0] + ro)[o];
-            p.pex[1] = gp(d.psiEa[0][cxp.side][1] + ro)[o];
-        }
-        if (cyp.side >= 0) {
-            int o = poff(d, 1, cyp.side, i, j + 1, k);
-            p.pey[0] = gp(d.psiEa[1][cyp.side][0] + ro)[o];
-            p.pey[1] = gp(d.psiEa[1][cyp.side][1] + ro)[o];
-        }
+    if (V & 1) {
+        psi_axis(d, d.psiHa, ro, 0, cx, i, j, k, p.ph[4], p.ph[5]);
+        p.pe1[4] = p.pe1[5] = T(0);
+        if (up) psi_axis(d, d.psiEa, ro, 0, cx, i, j, k + 1, p.pe1[4], p.pe1[5]);
+        psi_axis(d, d.psiEa, ro, 0, cxp, i + 1, j, k, p.pex[0], p.pex[1]);
+    }
+    if (V & 2) {
+        psi_axis(d, d.psiHa, ro, 1, cy, i, j, k, p.ph[0], p.ph[1]);
+        p.pe1[0] = p.pe1[1] = T(0);
+        if (up) psi_axis(d, d.psiEa, ro, 1, cy, i, j, k + 1, p.pe1[0], p.pe1[1]);
+        psi_axis(d, d.psiEa, ro, 1, cyp, i, j + 1, k, p.pey[0], p.pey[1]);
+    }
+    if (V & 4) {
+        psi_axis(d, d.psiHa, ro, 2, cpml_at(d, 2, k), i, j, k, p.ph[2], p.ph[3]);
+        p.pe1[2] = p.pe1[3] = T(0);
+        if (up) psi_axis(d, d.psiEa, ro, 2, cpml_at(d, 2, k + 1), i, j, k + 1, p.pe1[2], p.pe1[3]);
     }
 }
 
@@ -814,12 +851,11 @@ __device__ __forceinline__ Dbar6<T> dbar6(int i, int j, int k, T ux, T uy, T uz,
     return o;
 }
 
-// GEN = false: blocks that meet no absorber slab (one step forward included).
-template <typename T, bool GEN>
-__global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                                const int* __restrict__ list, int ndom, int kz, int rs, int ws) {
+template <typename T, int V, int W>
+__global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                int kz, int rs, int ws) {
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp, list);
+    const TileCol<W> c = tile_column<T, W>(doms, tiles, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
@@ -828,12 +864,7 @@ __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ do
     const FDTD_GLOBAL T* u[3] = {gp(d.Et[0]), gp(d.Et[1]), gp(d.Et[2])};
     const FDTD_GLOBAL T* h[3] = {gp(d.Ha[0] + ro), gp(d.Ha[1] + ro), gp(d.Ha[2] + ro)};
     FDTD_GLOBAL T* hw[3] = {gp(d.Ha[0] + wo), gp(d.Ha[1] + wo), gp(d.Ha[2] + wo)};
-    const int x0 = i & ~63, y0 = j & ~3;
-    const BlkFlags bf = blk_flags(d, x0, y0, c.k0, c.k1);
-    // one step forward along x, y or z can reach a high slab the block itself misses
-    const bool cp = GEN && (bf.cp || (min(x0 + 64, nx - 1) >= nx - d.L[0][1] && d.L[0][1] > 0) ||
-                            (min(y0 + 4, ny - 1) >= ny - d.L[1][1] && d.L[1][1] > 0) ||
-                            (c.k1 < nz && c.k1 >= nz - d.L[2][1] && d.L[2][1] > 0));
+    constexpr bool CX = V & 1, CY = V & 2, CZ = V & 4;
     const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j), cxp = cpml_at(d, 0, i + 1), cyp = cpml_at(d, 1, j + 1);
     const T S = d.S, mS = -d.S;
     long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
@@ -841,50 +872,50 @@ __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ do
     {
         T pe[6] = {0, 0, 0, 0, 0, 0};
         const Cpml1<T> cz = cpml_at(d, 2, c.k0);
-        if (cp) psi_load(d, d.psiEa, ro, true, cx, cy, cz, i, j, c.k0, pe);
-        cur = dbar6(i, j, c.k0, u[0][f], u[1][f], u[2][f], pe, cp && cx.side >= 0, cp && cy.side >= 0,
-                    cp && cz.side >= 0, cx, cy, cz);
+        if (CX) psi_axis(d, d.psiEa, ro, 0, cx, i, j, c.k0, pe[4], pe[5]);
+        if (CY) psi_axis(d, d.psiEa, ro, 1, cy, i, j, c.k0, pe[0], pe[1]);
+        if (CZ) psi_axis(d, d.psiEa, ro, 2, cz, i, j, c.k0, pe[2], pe[3]);
+        cur = dbar6(i, j, c.k0, u[0][f], u[1][f], u[2][f], pe, CX && cx.side >= 0, CY && cy.side >= 0,
+                    CZ && cz.side >= 0, cx, cy, cz);
     }
     AdjColH<T> cu, nx_;
-    adjh_fetch(d, cu, u, h, f, cp, cx, cy, cxp, cyp, ro, i, j, c.k0);
+    adjh_fetch<T, V>(d, cu, u, h, f, cx, cy, cxp, cyp, ro, i, j, c.k0);
     for (int k = c.k0; k < c.k1; ++k, f += pl) {
-        if (k + 1 < c.k1) adjh_fetch(d, nx_, u, h, f + pl, cp, cx, cy, cxp, cyp, ro, i, j, k + 1);
+        if (k + 1 < c.k1) adjh_fetch<T, V>(d, nx_, u, h, f + pl, cx, cy, cxp, cyp, ro, i, j, k + 1);
         const Cpml1<T> cz = cpml_at(d, 2, k), czp = cpml_at(d, 2, k + 1);
-        const bool sx = cp && cx.side >= 0, sy = cp && cy.side >= 0, sz = cp && cz.side >= 0;
+        const bool sx = CX && cx.side >= 0, sy = CY && cy.side >= 0, sz = CZ && cz.side >= 0;
         // E terms of the plane above (all six: they are the next plane's own terms)
         Dbar6<T> up{};
         if (k + 1 < nz)
-            up = dbar6(i, j, k + 1, cu.u1[0], cu.u1[1], cu.u1[2], cu.pe1, sx, sy, cp && czp.side >= 0, cx, cy, czp);
+            up = dbar6(i, j, k + 1, cu.u1[0], cu.u1[1], cu.u1[2], cu.pe1, sx, sy, CZ && czp.side >= 0, cx, cy, czp);
         // x neighbour: Ez term 0 and Ey term 1 (along x); y neighbour: Ez term 1 and Ex term 0 (along y)
         T xp_z0 = 0, xp_y1 = 0, yp_z1 = 0, yp_x0 = 0;
         if (i + 1 < nx) {
-            const bool s = cp && cxp.side >= 0;
+            const bool s = CX && cxp.side >= 0;
             if (j > 0) xp_z0 = tr_term(s, cxp.kE, cxp.cE, cu.pex[0], cu.uz_xp);
             if (k > 0) xp_y1 = tr_term(s, cxp.kE, cxp.cE, cu.pex[1], -cu.uy_xp);
         }
         if (j + 1 < ny) {
-            const bool s = cp && cyp.side >= 0;
+            const bool s = CY && cyp.side >= 0;
             if (i > 0) yp_z1 = tr_term(s, cyp.kE, cyp.cE, cu.pey[1], -cu.uz_yp);
             if (k > 0) yp_x0 = tr_term(s, cyp.kE, cyp.cE, cu.pey[0], cu.ux_yp);
         }
         T hbx = cu.hb[0], hby = cu.hb[1], hbz = cu.hb[2];
         // H-side memory cotangents of this node (owner): psibar <- b (psibar + ybar), ybar = -S sign Hbar
-        if (cp) {
-            if (cy.side >= 0) {
-                int q = poff(d, 1, cy.side, i, j, k);
-                gp(d.psiHa[1][cy.side][0] + wo)[q] = cy.bH * (cu.ph[0] + mS * hbx);   // Hx term 0 along y
-                gp(d.psiHa[1][cy.side][1] + wo)[q] = cy.bH * (cu.ph[1] + S * hbz);    // Hz term 1 along y
-            }
-            if (cz.side >= 0) {
-                int q = poff(d, 2, cz.side, i, j, k);
-                gp(d.psiHa[2][cz.side][0] + wo)[q] = cz.bH * (cu.ph[2] + mS * hby);   // Hy term 0 along z
-                gp(d.psiHa[2][cz.side][1] + wo)[q] = cz.bH * (cu.ph[3] + S * hbx);    // Hx term 1 along z
-            }
-            if (cx.side >= 0) {
-                int q = poff(d, 0, cx.side, i, j, k);
-                gp(d.psiHa[0][cx.side][0] + wo)[q] = cx.bH * (cu.ph[4] + mS * hbz);   // Hz term 0 along x
-                gp(d.psiHa[0][cx.side][1] + wo)[q] = cx.bH * (cu.ph[5] + S * hby);    // Hy term 1 along x
-            }
+        if (sy) {
+            int q = poff(d, 1, cy.side, i, j, k);
+            gp(d.psiHa[1][cy.side][0] + wo)[q] = cy.bH * (cu.ph[0] + mS * hbx);   // Hx term 0 along y
+            gp(d.psiHa[1][cy.side][1] + wo)[q] = cy.bH * (cu.ph[1] + S * hbz);    // Hz term 1 along y
+        }
+        if (sz) {
+            int q = poff(d, 2, cz.side, i, j, k);
+            gp(d.psiHa[2][cz.side][0] + wo)[q] = cz.bH * (cu.ph[2] + mS * hby);   // Hy term 0 along z
+            gp(d.psiHa[2][cz.side][1] + wo)[q] = cz.bH * (cu.ph[3] + S * hbx);    // Hx term 1 along z
+        }
+        if (sx) {
+            int q = poff(d, 0, cx.side, i, j, k);
+            gp(d.psiHa[0][cx.side][0] + wo)[q] = cx.bH * (cu.ph[4] + mS * hbz);   // Hz term 0 along x
+            gp(d.psiHa[0][cx.side][1] + wo)[q] = cx.bH * (cu.ph[5] + S * hby);    // Hy term 1 along x
         }
         hbx += (cur.y0 - up.y0) + (cur.z1 - yp_z1);
         hby += (cur.z0 - xp_z0) + (cur.x1 - up.x1);
@@ -1894,18 +1925,28 @@ template <typename T>
 void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
-        if (c.na1[0])
-            hipLaunchKernelGGL((k_adj_ht<T, false>), dim3(c.na1[0]), dim3(256), 0, s, dd, c.bs, c.la1[0], c.ndom, c.kz,
-                               rs, ws, fsr);
-        if (c.na1[1])
-            hipLaunchKernelGGL((k_adj_ht<T, true>), dim3(c.na1[1]), dim3(256), 0, s, dd, c.bs, c.la1[1], c.ndom, c.kz,
-                               rs, ws, fsr);
-        if (c.na2[0])
-            hipLaunchKernelGGL((k_adj_et<T, false>), dim3(c.na2[0]), dim3(256), 0, s, dd, c.bs, c.la2[0], c.ndom, c.kz,
-                               rs, ws);
-        if (c.na2[1])
-            hipLaunchKernelGGL((k_adj_et<T, true>), dim3(c.na2[1]), dim3(256), 0, s, dd, c.bs, c.la2[1], c.ndom, c.kz,
-                               rs, ws);
+        // one launch per tile class (see kAdjFull): only the registers each needs
+        static_assert(kAdjClasses1 == 7 && kAdjClasses2 == 6, "one launch per class below");
+#define FDTD_ADJ_HT(V, W, q)                                                                                          \
+    if (c.na1[q])                                                                                                     \
+        hipLaunchKernelGGL((k_adj_ht<T, V, W>), dim3(c.na1[q]), dim3(256), 0, s, dd, c.ta1[q], c.kz, rs, ws, fsr);
+#define FDTD_ADJ_ET(V, W, q)                                                                                          \
+    if (c.na2[q]) hipLaunchKernelGGL((k_adj_et<T, V, W>), dim3(c.na2[q]), dim3(256), 0, s, dd, c.ta2[q], c.kz, rs, ws);
+        FDTD_ADJ_HT(0, 64, 0)
+        FDTD_ADJ_HT(6, 64, 1)
+        FDTD_ADJ_HT(kAdjFull, 64, 2)
+        FDTD_ADJ_HT(1, 16, 3)
+        FDTD_ADJ_HT(7, 16, 4)
+        FDTD_ADJ_HT(kAdjFull, 16, 5)
+        FDTD_ADJ_HT(6, 16, 6)
+        FDTD_ADJ_ET(0, 64, 0)
+        FDTD_ADJ_ET(6, 64, 1)
+        FDTD_ADJ_ET(7, 64, 2)
+        FDTD_ADJ_ET(1, 16, 3)
+        FDTD_ADJ_ET(7, 16, 4)
+        FDTD_ADJ_ET(6, 16, 5)
+#undef FDTD_ADJ_HT
+#undef FDTD_ADJ_ET
         return;
     }
     if (c.ngen) FDTD_ROWS_SWITCH(k_adj_fused, c.rows, dim3(c.ngen), dim3(256), 0, s, dd, c.tgen, c.kz, rs, ws, fsr)

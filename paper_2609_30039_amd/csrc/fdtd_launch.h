@@ -26,17 +26,23 @@ struct MonDev {
 // register-blocked rows per wave of the fused kernels; kz = z chunk.
 // Split: bs = device prefix sums of blocks per domain (ndom + 1 entries).
 // Fused: tile tables (domain, X0, Y0, k0) of general and bulk tiles.
+constexpr int kAdjClasses1 = 7, kAdjClasses2 = 6;
+
 struct LaunchCfg {
     int kernel, rows, kz, nblk, ndom;
     const int* bs;             // split blocks per domain (prefix sums)
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
-    // split adjoint: block classes [0] lean (no absorber slab within one
-    // step, no Lorentz cell), [1] general; logical block ids, domains with a
-    // gradient only
-    int na1[2], na2[2];
-    const int* la1[2];
-    const int* la2[2];
+    // split adjoint: tile tables (domain, x0 | xlen << 24, y0, k0) per class,
+    // domains with a gradient only.  x is cut into the slab zones (narrow
+    // tiles, W = 16) and the interior zone (W = 64); a class names the slabs
+    // its tiles, or the neighbours they read, meet.  E-node pass kAdjClasses1
+    // classes [W64: none, y/z, general; W16: x, all, general, y/z], H-node
+    // pass kAdjClasses2 classes [W64: none, y/z, all; W16: x, all, y/z];
+    // general = Lorentz cells or gradient cells in a slab.
+    int na1[kAdjClasses1], na2[kAdjClasses2];
+    const int4* ta1[kAdjClasses1];
+    const int4* ta2[kAdjClasses2];
 
     int ngen, nbulk;           // adjoint: general tiles, interior (bulk) tiles
     const int4* tgen;

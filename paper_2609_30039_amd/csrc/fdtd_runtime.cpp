@@ -139,10 +139,10 @@ struct Handle : Base {
     std::vector<int> bs_host;   // [0, ndom]: split blocks; [ndom+1, 2 ndom+1]: Lorentz-box blocks
     std::vector<int4> tiles_gen, tiles_bulk, tiles_fgen, tiles_fcp, tiles_fplain;
     int4* d_tiles = nullptr;
-    // split-family block classes of the adjoint passes (logical block ids):
-    // E-node pass lean / general, H-node pass lean / general
-    std::vector<int> blist[4];
-    int* d_blist = nullptr;
+    // tile tables of the split adjoint: E-node pass 6 classes, H-node pass 5
+    // classes (LaunchCfg::ta1, ta2)
+    std::vector<int4> atiles[kAdjClasses1 + kAdjClasses2];
+    int4* d_atiles = nullptr;
     // pool: [misc][forward sets x nsets][adjoint sets x 2][split scratch][bf16 slots]
     char* pool = nullptr;
     size_t pool_bytes = 0, misc_bytes = 0, fstride = 0, astride = 0, et_bytes = 0, bfslot = 0;
@@ -276,7 +276,7 @@ struct Handle : Base {
         }
         cfg.nblk = bs_host[ndom];
         cfg.nlor = lbs[ndom];
-        classify_split_blocks();
+        build_adjoint_tiles();
         cfg.ngen = (int)tiles_gen.size();
         cfg.nbulk = (int)tiles_bulk.size();
         cfg.nfgen = (int)tiles_fgen.size();
@@ -284,45 +284,84 @@ struct Handle : Base {
         cfg.nfplain = (int)tiles_fplain.size();
     }
 
-    // A block of the split family is "lean" for a pass when no node it
-    // updates, nor any node one step back (E-node pass) or forward (H-node
-    // pass) whose memory it reads, lies in an absorber slab, and (E-node
-    // pass) none is a Lorentz cell.  The kernels' lean variants rely on this.
-    void classify_split_blocks() {
-        for (auto& l : blist) l.clear();
+    // Tiles of the split adjoint.  Along x each domain is cut into a low slab
+    // zone, an interior zone and a high slab zone; the E-node pass (which reads
+    // the memory one step back) widens the low zone by one column, the H-node
+    // pass (one step forward) the high zone.  Slab zones take narrow tiles (16
+    // columns by 16 rows), the interior zone wide ones (64 by 4) from its first
+    // 32-column boundary on (narrow tiles cover the columns before it).  Per axis a,
+    // a tile needs the a-slab memory cotangents if a node it updates, or the
+    // neighbour it reads along a, lies in an a-slab; it goes to the narrowest
+    // class whose mask covers that.  E-node tiles holding Lorentz cells or
+    // gradient cells inside a slab take the general class.  The kernels rely
+    // on this: a class only handles the slabs its mask names.
+    void build_adjoint_tiles() {
+        for (auto& l : atiles) l.clear();
         const int kz = cfg.kz;
         for (int q = 0; q < ndom; ++q) {
             const fdtd_domain_desc& s = dh[q].desc;
             if (!s.grad) continue;
             const int n[3] = {s.n[0], s.n[1], s.n[2]};
-            const int nbx = (n[0] + 63) / 64, nby = (n[1] + 3) / 4;
-            for (int lb = 0; lb < bs_host[q + 1] - bs_host[q]; ++lb) {
-                const int bx = lb % nbx, r = lb / nbx, by = r % nby, bz = r / nby;
-                const int lo[3] = {bx * 64, by * 4, bz * kz};
-                const int hi[3] = {std::min(lo[0] + 63, n[0] - 1), std::min(lo[1] + 3, n[1] - 1),
-                                   std::min(lo[2] + kz, n[2]) - 1};
-                bool cp = false, cpm = false, cpp = false;
-                for (int a = 0; a < 3; ++a) {
-                    const int L0 = s.pml[2 * a], L1 = s.pml[2 * a + 1];
-                    if (lo[a] < L0 || hi[a] >= n[a] - L1) cp = true;
-                    if (lo[a] > 0 && lo[a] - 1 < L0) cpm = true;
-                    if (L1 > 0 && hi[a] + 1 < n[a] && hi[a] + 1 >= n[a] - L1) cpp = true;
+            for (int pass = 0; pass < 2; ++pass) {
+                const int L0 = s.pml[0], L1 = s.pml[1];
+                const int xa = L0 > 0 ? std::min(L0 + (pass == 0 ? 1 : 0), n[0]) : 0;
+                const int xb = L1 > 0 ? std::max(n[0] - L1 - (pass == 1 ? 1 : 0), xa) : n[0];
+                // wide tiles start on a 32-column (128 B) boundary: a wave's row
+                // then spans two cache lines; narrow tiles take the columns before
+                const int wa = std::min((xa + 31) / 32 * 32, xb);
+                const int zlo[3] = {0, wa, xb}, zhi[3] = {wa, xb, n[0]};
+                for (int zone = 0; zone < 3; ++zone) {
+                    const bool wide = zone == 1;
+                    const int W = wide ? 64 : 16, rows = wide ? 4 : 16;
+                    for (int x0 = zlo[zone]; x0 < zhi[zone]; x0 += W)
+                        for (int y0 = 0; y0 < n[1]; y0 += rows)
+                            for (int k0 = 0; k0 < n[2]; k0 += kz) {
+                                const int xlen = std::min(W, zhi[zone] - x0);
+                                const int lo[3] = {x0, y0, k0};
+                                const int hi[3] = {x0 + xlen - 1, std::min(y0 + rows, n[1]) - 1,
+                                                   std::min(k0 + kz, n[2]) - 1};
+                                int mask = 0;
+                                for (int a = 0; a < 3; ++a) {
+                                    const int A0 = s.pml[2 * a], A1 = s.pml[2 * a + 1];
+                                    bool need = lo[a] < A0 || hi[a] >= n[a] - A1;
+                                    if (pass == 0 && lo[a] > 0 && lo[a] - 1 < A0) need = true;
+                                    if (pass == 1 && A1 > 0 && hi[a] + 1 < n[a] && hi[a] + 1 >= n[a] - A1) need = true;
+                                    if (need) mask |= 1 << a;
+                                }
+                                bool general = false;
+                                if (pass == 0) {
+                                    if (s.n_lorentz) {
+                                        bool meet = true;
+                                        for (int a = 0; a < 3; ++a)
+                                            if (hi[a] < s.lorentz.lo[a] || lo[a] >= s.lorentz.hi[a]) meet = false;
+                                        general = meet;
+                                    }
+                                    int glo[3], ghi[3];
+                                    bool meet = true;
+                                    for (int a = 0; a < 3; ++a) {
+                                        glo[a] = std::max(lo[a], s.grad_lo[a]);
+                                        ghi[a] = std::min(hi[a], s.grad_hi[a] - 1);
+                                        if (glo[a] > ghi[a]) meet = false;
+                                    }
+                                    for (int a = 0; a < 3 && meet; ++a)
+                                        if (glo[a] < s.pml[2 * a] || ghi[a] >= n[a] - s.pml[2 * a + 1]) general = true;
+                                }
+                                int cls;
+                                if (pass == 0) {
+                                    if (wide) cls = general || (mask & 1) ? 2 : mask ? 1 : 0;
+                                    else cls = general ? 5 : !(mask & 1) ? 6 : (mask & ~1) ? 4 : 3;
+                                } else {
+                                    if (wide) cls = (mask & 1) ? 2 : mask ? 1 : 0;
+                                    else cls = !(mask & 1) ? 5 : (mask & ~1) ? 4 : 3;
+                                    cls += kAdjClasses1;
+                                }
+                                atiles[cls].push_back(make_int4(q, x0 | (xlen << 24), y0, k0));
+                            }
                 }
-                bool lor = false;
-                if (s.n_lorentz) {
-                    lor = true;
-                    for (int a = 0; a < 3; ++a)
-                        if (hi[a] < s.lorentz.lo[a] || lo[a] >= s.lorentz.hi[a]) lor = false;
-                }
-                const int b = bs_host[q] + lb;
-                blist[(cp || cpm || lor) ? 1 : 0].push_back(b);
-                blist[(cp || cpp) ? 3 : 2].push_back(b);
             }
         }
-        for (int c = 0; c < 2; ++c) {
-            cfg.na1[c] = (int)blist[c].size();
-            cfg.na2[c] = (int)blist[2 + c].size();
-        }
+        for (int c = 0; c < kAdjClasses1; ++c) cfg.na1[c] = (int)atiles[c].size();
+        for (int c = 0; c < kAdjClasses2; ++c) cfg.na2[c] = (int)atiles[kAdjClasses1 + c].size();
     }
 
     // ------------------------------------------------------------ layout
@@ -421,9 +460,9 @@ struct Handle : Base {
         M.take(d_doms, sizeof(DomDev<T>) * ndom);
         M.take(d_bs, sizeof(int) * 2 * (ndom + 1));
         M.take(d_tstep, sizeof(int));
-        size_t nbl = 0;
-        for (auto& l : blist) nbl += l.size();
-        M.take(d_blist, sizeof(int) * std::max<size_t>(1, nbl));
+        size_t nat = 0;
+        for (auto& l : atiles) nat += l.size();
+        M.take(d_atiles, sizeof(int4) * std::max<size_t>(1, nat));
         M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
                                                                tiles_fcp.size() + tiles_fplain.size()));
         M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
@@ -514,11 +553,10 @@ struct Handle : Base {
         cfg.tfcp = cfg.tfgen + tiles_fgen.size();
         cfg.tfplain = cfg.tfcp + tiles_fcp.size();
         {
-            const int* p = d_blist;
-            const int** dst[4] = {&cfg.la1[0], &cfg.la1[1], &cfg.la2[0], &cfg.la2[1]};
-            for (int c = 0; c < 4; ++c) {
-                *dst[c] = p;
-                p += blist[c].size();
+            const int4* p = d_atiles;
+            for (int c = 0; c < kAdjClasses1 + kAdjClasses2; ++c) {
+                (c < kAdjClasses1 ? cfg.ta1[c] : cfg.ta2[c - kAdjClasses1]) = p;
+                p += atiles[c].size();
             }
         }
         // ---- initialise: zero everything, upload tables and inputs
@@ -564,11 +602,11 @@ struct Handle : Base {
             if (!all.empty() && hipMemcpyAsync(d_tiles, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice,
                                                st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "upload tile tables failed");
-            std::vector<int> bl;
-            for (auto& l : blist) bl.insert(bl.end(), l.begin(), l.end());
-            if (!bl.empty() && hipMemcpyAsync(d_blist, bl.data(), sizeof(int) * bl.size(), hipMemcpyHostToDevice,
+            std::vector<int4> at;
+            for (auto& l : atiles) at.insert(at.end(), l.begin(), l.end());
+            if (!at.empty() && hipMemcpyAsync(d_atiles, at.data(), sizeof(int4) * at.size(), hipMemcpyHostToDevice,
                                               st) != hipSuccess)
-                return fail(FDTD_E_DEVICE, "upload block classes failed");
+                return fail(FDTD_E_DEVICE, "upload adjoint tiles failed");
         }
         return sync("create");
     }
