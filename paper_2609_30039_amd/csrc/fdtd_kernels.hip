@@ -51,9 +51,9 @@ struct Col {
 // split kernels: 256 threads = 64 (x) x 4 (y) columns, z chunk of length kz
 template <typename T>
 __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int ndom, int kz, const DomDev<T>*& dp,
-                                      const int* list = nullptr) {
+                                      const int* list = nullptr, int braw = -1, int nb = 0) {
     Col c;
-    int b = xcd_remap(blockIdx.x, gridDim.x);
+    int b = braw < 0 ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(braw, nb);
     if (list) b = list[b];   // a class of blocks: logical block ids
     int dom = find_domain(bs, ndom, b);
     dp = doms + dom;
@@ -289,12 +289,50 @@ __device__ __forceinline__ void cole_fetch(const DomDev<T>& d, ColE<T>& p, const
     if (cp) psi_load(d, d.psiE, so, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ps);
 }
 
+// E update of the Lorentz boxes (one thread per box cell, x fastest): the
+// general per-node path with the auxiliary-differential-equation history.
+template <typename T>
+__device__ __forceinline__ void e_lor_block(const DomDev<T>* __restrict__ doms, const int* __restrict__ lbs, int ndom,
+                                           int b, int rs, int ws, int t, const int* __restrict__ tdev) {
+    if (b >= lbs[ndom]) return;
+    int dom = find_domain(lbs, ndom, b);
+    const DomDev<T>& d = doms[dom];
+    const int bx = d.lhi[0] - d.llo[0], by = d.lhi[1] - d.llo[1], bzn = d.lhi[2] - d.llo[2];
+    long long q = (long long)(b - lbs[dom]) * 256 + threadIdx.x;
+    if (!d.has_lor || q >= (long long)bx * by * bzn) return;
+    if (tdev) t += *tdev;
+    const int i = d.llo[0] + (int)(q % bx), j = d.llo[1] + (int)((q / bx) % by), k = d.llo[2] + (int)(q / ((long long)bx * by));
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
+    const long long f = (long long)k * pl + (long long)j * d.pitch + i;
+    const FDTD_GLOBAL T* Hx = gp(d.H[0] + so);
+    const FDTD_GLOBAL T* Hy = gp(d.H[1] + so);
+    const FDTD_GLOBAL T* Hz = gp(d.H[2] + so);
+    T hx = Hx[f], hy = Hy[f], hz = Hz[f];
+    T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
+    T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
+    T hxm = k > 0 ? Hx[f - pl] : T(0), hym = k > 0 ? Hy[f - pl] : T(0);
+    // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
+    T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
+    T ey = e_update(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, rs, ws, true, t);
+    T ez = e_update(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, rs, ws, true, t);
+    gp(d.E[0] + wo)[f] = ex;
+    gp(d.E[1] + wo)[f] = ey;
+    gp(d.E[2] + wo)[f] = ez;
+}
+
+// Blocks [0, nlb) update the Lorentz boxes (e_lor_block; nlb is a multiple
+// of 8 so that the column blocks keep their XCD placement), the rest the
+// columns.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               int ndom, int kz, int rs, int ws, int t,
-                                               const int* __restrict__ tdev) {
+                                               const int* __restrict__ lbs, int nlb, int ndom, int kz, int rs, int ws,
+                                               int t, const int* __restrict__ tdev) {
+    if ((int)blockIdx.x < nlb) {
+        e_lor_block(doms, lbs, ndom, xcd_remap(blockIdx.x, nlb), rs, ws, t, tdev);
+        return;
+    }
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp);
+    Col c = column(doms, bs, ndom, kz, dp, nullptr, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
     if (!c.ok) return;
     if (tdev) t += *tdev;   // graph replays: step index held on the device
     const DomDev<T>& d = *dp;
@@ -317,7 +355,7 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     cole_fetch(d, cu, h, e, f, ev, bf.cp, cx, cy, so, i, j, c.k0);
     for (int k = c.k0; k < c.k1; ++k, f += pl) {
         if (k + 1 < c.k1) cole_fetch(d, nx, h, e, f + pl, ev, bf.cp, cx, cy, so, i, j, k + 1);
-        if (!(bf.lor && in_lor(d, i, j, k))) {   // Lorentz cells: k_fwd_e_lor
+        if (!(bf.lor && in_lor(d, i, j, k))) {   // Lorentz cells: e_lor_block
             T ex, ey, ez;
             T Dx0 = cu.hz - cu.hz_ym, Dx1 = cu.hy - hym;    // Ex: Hz along y, Hy along z
             T Dy0 = cu.hx - hxm, Dy1 = cu.hz - cu.hz_xm;    // Ey: Hx along z, Hz along x
@@ -367,36 +405,6 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     }
 }
 
-// E update of the Lorentz boxes (one thread per box cell, x fastest): the
-// general per-node path with the auxiliary-differential-equation history.
-template <typename T>
-__global__ void __launch_bounds__(256) k_fwd_e_lor(const DomDev<T>* __restrict__ doms, const int* __restrict__ lbs,
-                                                   int ndom, int rs, int ws, int t, const int* __restrict__ tdev) {
-    int b = xcd_remap(blockIdx.x, gridDim.x);
-    int dom = find_domain(lbs, ndom, b);
-    const DomDev<T>& d = doms[dom];
-    const int bx = d.lhi[0] - d.llo[0], by = d.lhi[1] - d.llo[1], bzn = d.lhi[2] - d.llo[2];
-    long long q = (long long)(b - lbs[dom]) * 256 + threadIdx.x;
-    if (!d.has_lor || q >= (long long)bx * by * bzn) return;
-    if (tdev) t += *tdev;
-    const int i = d.llo[0] + (int)(q % bx), j = d.llo[1] + (int)((q / bx) % by), k = d.llo[2] + (int)(q / ((long long)bx * by));
-    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
-    const long long f = (long long)k * pl + (long long)j * d.pitch + i;
-    const FDTD_GLOBAL T* Hx = gp(d.H[0] + so);
-    const FDTD_GLOBAL T* Hy = gp(d.H[1] + so);
-    const FDTD_GLOBAL T* Hz = gp(d.H[2] + so);
-    T hx = Hx[f], hy = Hy[f], hz = Hz[f];
-    T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
-    T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
-    T hxm = k > 0 ? Hx[f - pl] : T(0), hym = k > 0 ? Hy[f - pl] : T(0);
-    // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
-    T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
-    T ey = e_update(d, 1, i, j, k, f, hx, hxm, hz, hz_xm, rs, ws, true, t);
-    T ez = e_update(d, 2, i, j, k, f, hy, hy_xm, hx, hx_ym, rs, ws, true, t);
-    gp(d.E[0] + wo)[f] = ex;
-    gp(d.E[1] + wo)[f] = ey;
-    gp(d.E[2] + wo)[f] = ez;
-}
 
 // reads E^{n+1} from set ws (written by k_fwd_e), H^{n+1/2} from set rs
 template <typename T>
@@ -1909,9 +1917,9 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
     if (c.kernel == 1) {
         // one launch per pass over all blocks: a second launch for the
         // interior blocks costs more in its drain than its leaner registers win
-        hipLaunchKernelGGL(k_fwd_e<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, t, tdev);
-        if (c.nlor)
-            hipLaunchKernelGGL(k_fwd_e_lor<T>, dim3(c.nlor), dim3(256), 0, s, dd, c.lbs, c.ndom, rs, ws, t, tdev);
+        const int nlb = (c.nlor + 7) / 8 * 8;
+        hipLaunchKernelGGL(k_fwd_e<T>, dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom, c.kz, rs, ws,
+                           t, tdev);
         hipLaunchKernelGGL(k_fwd_h<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
         return;
     }
@@ -1922,33 +1930,41 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
 }
 
 template <typename T>
-void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s) {
+void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s, int pass,
+                const hipStream_t* cs) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
-        // one launch per tile class (see kAdjFull): only the registers each needs
+        // one launch per tile class (see kAdjFull), each with only the registers
+        // it needs; cs[q] is the stream of class q (the classes of a pass write
+        // disjoint nodes and may run concurrently)
         static_assert(kAdjClasses1 == 7 && kAdjClasses2 == 6, "one launch per class below");
 #define FDTD_ADJ_HT(V, W, q)                                                                                          \
     if (c.na1[q])                                                                                                     \
-        hipLaunchKernelGGL((k_adj_ht<T, V, W>), dim3(c.na1[q]), dim3(256), 0, s, dd, c.ta1[q], c.kz, rs, ws, fsr);
+        hipLaunchKernelGGL((k_adj_ht<T, V, W>), dim3(c.na1[q]), dim3(256), 0, cs[q], dd, c.ta1[q], c.kz, rs, ws, fsr);
 #define FDTD_ADJ_ET(V, W, q)                                                                                          \
-    if (c.na2[q]) hipLaunchKernelGGL((k_adj_et<T, V, W>), dim3(c.na2[q]), dim3(256), 0, s, dd, c.ta2[q], c.kz, rs, ws);
-        FDTD_ADJ_HT(0, 64, 0)
-        FDTD_ADJ_HT(6, 64, 1)
-        FDTD_ADJ_HT(kAdjFull, 64, 2)
-        FDTD_ADJ_HT(1, 16, 3)
-        FDTD_ADJ_HT(7, 16, 4)
-        FDTD_ADJ_HT(kAdjFull, 16, 5)
-        FDTD_ADJ_HT(6, 16, 6)
-        FDTD_ADJ_ET(0, 64, 0)
-        FDTD_ADJ_ET(6, 64, 1)
-        FDTD_ADJ_ET(7, 64, 2)
-        FDTD_ADJ_ET(1, 16, 3)
-        FDTD_ADJ_ET(7, 16, 4)
-        FDTD_ADJ_ET(6, 16, 5)
+    if (c.na2[q])                                                                                                     \
+        hipLaunchKernelGGL((k_adj_et<T, V, W>), dim3(c.na2[q]), dim3(256), 0, cs[q], dd, c.ta2[q], c.kz, rs, ws);
+        if (pass == 0) {
+            FDTD_ADJ_HT(0, 64, 0)
+            FDTD_ADJ_HT(6, 64, 1)
+            FDTD_ADJ_HT(kAdjFull, 64, 2)
+            FDTD_ADJ_HT(1, 16, 3)
+            FDTD_ADJ_HT(7, 16, 4)
+            FDTD_ADJ_HT(kAdjFull, 16, 5)
+            FDTD_ADJ_HT(6, 16, 6)
+        } else {
+            FDTD_ADJ_ET(0, 64, 0)
+            FDTD_ADJ_ET(6, 64, 1)
+            FDTD_ADJ_ET(7, 64, 2)
+            FDTD_ADJ_ET(1, 16, 3)
+            FDTD_ADJ_ET(7, 16, 4)
+            FDTD_ADJ_ET(6, 16, 5)
+        }
 #undef FDTD_ADJ_HT
 #undef FDTD_ADJ_ET
         return;
     }
+    if (pass != 0) return;
     if (c.ngen) FDTD_ROWS_SWITCH(k_adj_fused, c.rows, dim3(c.ngen), dim3(256), 0, s, dd, c.tgen, c.kz, rs, ws, fsr)
     if (c.nbulk) FDTD_ROWS_SWITCH(k_adj_bulk, c.rows, dim3(c.nbulk), dim3(256), 0, s, dd, c.tbulk, c.kz, rs, ws, fsr)
 }
@@ -2019,7 +2035,7 @@ int split_blocks(int nx, int ny, int nz, int kz) { return ((nx + 63) / 64) * ((n
 
 #define FDTD_INSTANTIATE(T)                                                                   \
     template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, const int*); \
-    template void launch_adj<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t);   \
+    template void launch_adj<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, int, const hipStream_t*); \
     template void launch_sample<T>(const void*, const MonDev&, int, int, hipStream_t);        \
     template void launch_dft<T>(const MonDev&, int, int, hipStream_t, const int*);            \
     template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t, const int*); \

@@ -59,7 +59,10 @@ template <typename T>
 // tdev: when set, kernels add the device-held step index to t (graph replays)
 void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev = nullptr);
 template <typename T>
-void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s);
+// pass 0: the E-node pass (all of the fused adjoint), 1: the H-node pass of
+// the split family; cs[q]: stream of split class q of that pass
+void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s, int pass,
+                const hipStream_t* cs);
 template <typename T>
 void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s);
 template <typename T>

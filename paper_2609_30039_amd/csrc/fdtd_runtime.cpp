@@ -186,6 +186,7 @@ struct Handle : Base {
             (void)hipGraphDestroy(g.g);
         }
         if (cst) (void)hipStreamDestroy(cst);
+
         (void)hipFree(pool);
     }
 
@@ -946,6 +947,17 @@ struct Handle : Base {
         return check("adjoint_begin");
     }
 
+    // Both passes on the caller's stream.  (Forking the classes of a pass onto
+    // further streams and joining them back cost more in event waits than
+    // the overlap won.)
+    int launch_adjoint_passes() {
+        hipStream_t cs[kAdjClasses1];
+        for (int q = 0; q < kAdjClasses1; ++q) cs[q] = st;
+        launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 0, cs);
+        if (cfg.kernel == 1) launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 1, cs);
+        return FDTD_OK;
+    }
+
     int step_adjoint(int n) override {
         if (m < 0) return fail(FDTD_E_STATE, "fdtd_adjoint_begin has not been called");
         for (int s = 0; s < n; ++s) {
@@ -956,7 +968,8 @@ struct Handle : Base {
                 return fail(FDTD_E_STATE, b);
             }
             if (timing_on) ev_mark();
-            launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st);
+            int rc = launch_adjoint_passes();
+            if (rc) return rc;
             if (timing_on) ev_mark();
             ap ^= 1;
             --m;
