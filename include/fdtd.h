@@ -129,7 +129,8 @@ typedef struct {
     int32_t kernel;                /* FDTD_KERNEL_* */
     int32_t dft_block;             /* time samples buffered before a DFT flush (0: default) */
     int32_t graph_chunk;           /* steps per captured hipGraph (0: no graph) */
-    int32_t tile_rows;             /* fused kernel: rows per wave, 2 | 4 | 8 (0: 2) */
+    int32_t tile_rows;             /* fused kernels: rows per wave, 2 | 4 | 8 (0: 2); split kernels:
+                                      rows per 256-thread block, 4 (64 columns; 0 = 4) or 8 (32) */
     int32_t tile_kz;               /* z planes per block (0: default) */
     void *stream;                  /* hipStream_t; NULL = default stream */
     double mem_budget_bytes;       /* refuse with FDTD_E_NOMEM above this (0: device free memory) */

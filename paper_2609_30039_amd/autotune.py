@@ -23,6 +23,9 @@ CANDIDATES = [
     {"kernel": "split", "tile_rows": 0, "tile_kz": 4},
     {"kernel": "split", "tile_rows": 0, "tile_kz": 8},
     {"kernel": "split", "tile_rows": 0, "tile_kz": 16},
+    {"kernel": "split", "tile_rows": 8, "tile_kz": 2},
+    {"kernel": "split", "tile_rows": 8, "tile_kz": 4},
+    {"kernel": "split", "tile_rows": 8, "tile_kz": 8},
     {"kernel": "fused", "tile_rows": 2, "tile_kz": 8},
     {"kernel": "fused", "tile_rows": 2, "tile_kz": 16},
     {"kernel": "fused", "tile_rows": 4, "tile_kz": 8},

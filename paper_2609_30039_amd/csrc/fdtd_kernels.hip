@@ -44,27 +44,30 @@ __device__ __forceinline__ int find_domain(const int* __restrict__ bs, int ndom,
 }
 
 struct Col {
-    int i, j, k0, k1;
+    int i, j, k0, k1, x0, y0;
     bool ok;
 };
 
-// split kernels: 256 threads = 64 (x) x 4 (y) columns, z chunk of length kz
-template <typename T>
+// split kernels: 256 threads = W (x) by 256 / W (y) columns, z chunk of length
+// kz; braw / nb: the block among nb column blocks (blockIdx.x when negative)
+template <typename T, int W>
 __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int ndom, int kz, const DomDev<T>*& dp,
-                                      const int* list = nullptr, int braw = -1, int nb = 0) {
+                                      int braw = -1, int nb = 0) {
+    constexpr int NR = 256 / W;
     Col c;
     int b = braw < 0 ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(braw, nb);
-    if (list) b = list[b];   // a class of blocks: logical block ids
     int dom = find_domain(bs, ndom, b);
     dp = doms + dom;
     const DomDev<T>& d = *dp;
     int lb = b - bs[dom];
-    int nbx = (d.n[0] + 63) >> 6, nby = (d.n[1] + 3) >> 2;
+    int nbx = (d.n[0] + W - 1) / W, nby = (d.n[1] + NR - 1) / NR;
     int bx = lb % nbx;
     int r = lb / nbx;
     int by = r % nby, bz = r / nby;
-    c.i = bx * 64 + (threadIdx.x & 63);
-    c.j = by * 4 + (threadIdx.x >> 6);
+    c.x0 = bx * W;
+    c.y0 = by * NR;
+    c.i = c.x0 + (int)(threadIdx.x % W);
+    c.j = c.y0 + (int)(threadIdx.x / W);
     c.k0 = bz * kz;
     c.k1 = min(c.k0 + kz, d.n[2]);
     c.ok = c.i < d.n[0] && c.j < d.n[1];
@@ -72,9 +75,9 @@ __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int 
 }
 
 // Tile-table columns of the split adjoint.  A tile is (domain, x0 | xlen << 24,
-// y0, k0): W = 64, one row of 64 x-columns per wave (4 rows per block); W =
-// 16, 16 x-columns by 4 rows per wave (16 rows per block), for the narrow
-// x-slab zones.  Columns at or beyond x0 + xlen are idle.
+// y0, k0) and covers W x-columns by 256 / W rows: W = 32 (8 rows, two rows
+// per wave) inside, W = 16 (16 rows) for the narrow x-slab zones.  Columns
+// at or beyond x0 + xlen are idle.
 template <int W>
 struct TileCol {
     int i, j, k0, k1, x0, y0;
@@ -88,12 +91,11 @@ __device__ __forceinline__ TileCol<W> tile_column(const DomDev<T>* doms, const i
     const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
     dp = doms + e.x;
     const DomDev<T>& d = *dp;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int xlen = e.y >> 24, lx = W == 64 ? lane : (lane & 15);
+    const int xlen = e.y >> 24, lx = (int)(threadIdx.x % W);
     c.x0 = e.y & 0xFFFFFF;
     c.y0 = e.z;
     c.i = c.x0 + lx;
-    c.j = W == 64 ? e.z + w : e.z + 4 * w + (lane >> 4);
+    c.j = e.z + (int)(threadIdx.x / W);
     c.k0 = e.w;
     c.k1 = min(e.w + kz, d.n[2]);
     c.ok = lx < xlen && c.j < d.n[1];
@@ -251,8 +253,9 @@ struct BlkFlags {
 };
 
 template <typename T>
-__device__ __forceinline__ BlkFlags blk_flags(const DomDev<T>& d, int x0, int y0, int k0, int k1) {
-    int lo[3] = {x0, y0, k0}, hi[3] = {min(x0 + 63, d.n[0] - 1), min(y0 + 3, d.n[1] - 1), k1 - 1};
+__device__ __forceinline__ BlkFlags blk_flags(const DomDev<T>& d, int x0, int y0, int k0, int k1, int w = 64,
+                                              int nr = 4) {
+    int lo[3] = {x0, y0, k0}, hi[3] = {min(x0 + w - 1, d.n[0] - 1), min(y0 + nr - 1, d.n[1] - 1), k1 - 1};
     BlkFlags f;
     f.cp = false;
     for (int a = 0; a < 3; ++a)
@@ -323,7 +326,7 @@ __device__ __forceinline__ void e_lor_block(const DomDev<T>* __restrict__ doms, 
 // Blocks [0, nlb) update the Lorentz boxes (e_lor_block; nlb is a multiple
 // of 8 so that the column blocks keep their XCD placement), the rest the
 // columns.
-template <typename T>
+template <typename T, int W>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                const int* __restrict__ lbs, int nlb, int ndom, int kz, int rs, int ws,
                                                int t, const int* __restrict__ tdev) {
@@ -332,7 +335,7 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
         return;
     }
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp, nullptr, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
+    Col c = column<T, W>(doms, bs, ndom, kz, dp, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
     if (!c.ok) return;
     if (tdev) t += *tdev;   // graph replays: step index held on the device
     const DomDev<T>& d = *dp;
@@ -341,8 +344,8 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     const FDTD_GLOBAL T* h[3] = {gp(d.H[0] + so), gp(d.H[1] + so), gp(d.H[2] + so)};
     const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + so), gp(d.E[1] + so), gp(d.E[2] + so)};
     FDTD_GLOBAL T* ew[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
-    const BlkFlags bf = blk_flags(d, i & ~63, j & ~3, c.k0, c.k1);
-    const EpsView<T> ev = eps_view(d, i & ~63, j & ~3, 4, c.k0, c.k1 - 1);
+    const BlkFlags bf = blk_flags(d, c.x0, c.y0, c.k0, c.k1, W, 256 / W);
+    const EpsView<T> ev = eps_view(d, c.x0, c.y0, 256 / W, c.k0, c.k1 - 1);
     const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j);
     const T S = d.S;
     long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
@@ -435,11 +438,11 @@ __device__ __forceinline__ void colh_fetch(const DomDev<T>& d, ColH<T>& p, const
     if (cp) psi_load(d, d.psiH, so, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ps);
 }
 
-template <typename T>
+template <typename T, int W>
 __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                int ndom, int kz, int rs, int ws) {
     const DomDev<T>* dp;
-    Col c = column(doms, bs, ndom, kz, dp);
+    Col c = column<T, W>(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
@@ -447,7 +450,7 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
     const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
     const FDTD_GLOBAL T* h[3] = {gp(d.H[0] + so), gp(d.H[1] + so), gp(d.H[2] + so)};
     FDTD_GLOBAL T* hw[3] = {gp(d.H[0] + wo), gp(d.H[1] + wo), gp(d.H[2] + wo)};
-    const BlkFlags bf = blk_flags(d, i & ~63, j & ~3, c.k0, c.k1);
+    const BlkFlags bf = blk_flags(d, c.x0, c.y0, c.k0, c.k1, W, 256 / W);
     const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j);
     const T S = d.S;
     long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
@@ -607,7 +610,7 @@ __global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ do
     FDTD_GLOBAL T* ew[3] = {gp(d.Ea[0] + wo), gp(d.Ea[1] + wo), gp(d.Ea[2] + wo)};
     FDTD_GLOBAL T* uw[3] = {gp(d.Et[0]), gp(d.Et[1]), gp(d.Et[2])};
     constexpr bool CX = V & 1, CY = V & 2, CZ = V & 4, FULL = V & 8;
-    constexpr int NR = W == 64 ? 4 : 16;   // rows per block
+    constexpr int NR = 256 / W;   // rows per block
     const EpsView<T> ev = eps_view(d, c.x0, c.y0, NR, c.k0, c.k1 - 1);
     const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j), cxm = cpml_at(d, 0, i - 1), cym = cpml_at(d, 1, j - 1);
     const T S = d.S, mS = -d.S;
@@ -1918,9 +1921,16 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
         // one launch per pass over all blocks: a second launch for the
         // interior blocks costs more in its drain than its leaner registers win
         const int nlb = (c.nlor + 7) / 8 * 8;
-        hipLaunchKernelGGL(k_fwd_e<T>, dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom, c.kz, rs, ws,
-                           t, tdev);
-        hipLaunchKernelGGL(k_fwd_h<T>, dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
+        if (c.sw == 32)
+            hipLaunchKernelGGL((k_fwd_e<T, 32>), dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom,
+                               c.kz, rs, ws, t, tdev);
+        else
+            hipLaunchKernelGGL((k_fwd_e<T, 64>), dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom,
+                               c.kz, rs, ws, t, tdev);
+        if (c.sw == 32)
+            hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
+        else
+            hipLaunchKernelGGL((k_fwd_h<T, 64>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
         return;
     }
     if (c.nfgen) FDTD_ROWS_SWITCH(k_fwd_fused, c.rows, dim3(c.nfgen), dim3(256), 0, s, dd, c.tfgen, c.kz, rs, ws, t)
@@ -1945,17 +1955,17 @@ void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, h
     if (c.na2[q])                                                                                                     \
         hipLaunchKernelGGL((k_adj_et<T, V, W>), dim3(c.na2[q]), dim3(256), 0, cs[q], dd, c.ta2[q], c.kz, rs, ws);
         if (pass == 0) {
-            FDTD_ADJ_HT(0, 64, 0)
-            FDTD_ADJ_HT(6, 64, 1)
-            FDTD_ADJ_HT(kAdjFull, 64, 2)
+            FDTD_ADJ_HT(0, 32, 0)
+            FDTD_ADJ_HT(6, 32, 1)
+            FDTD_ADJ_HT(kAdjFull, 32, 2)
             FDTD_ADJ_HT(1, 16, 3)
             FDTD_ADJ_HT(7, 16, 4)
             FDTD_ADJ_HT(kAdjFull, 16, 5)
             FDTD_ADJ_HT(6, 16, 6)
         } else {
-            FDTD_ADJ_ET(0, 64, 0)
-            FDTD_ADJ_ET(6, 64, 1)
-            FDTD_ADJ_ET(7, 64, 2)
+            FDTD_ADJ_ET(0, 32, 0)
+            FDTD_ADJ_ET(6, 32, 1)
+            FDTD_ADJ_ET(7, 32, 2)
             FDTD_ADJ_ET(1, 16, 3)
             FDTD_ADJ_ET(7, 16, 4)
             FDTD_ADJ_ET(6, 16, 5)
@@ -2031,7 +2041,10 @@ void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipSt
     hipLaunchKernelGGL(k_checksum, dim3(blocks_1d(nw, 256, 4096)), dim3(256), 0, s, (const uint32_t*)p, nw, out);
 }
 
-int split_blocks(int nx, int ny, int nz, int kz) { return ((nx + 63) / 64) * ((ny + 3) / 4) * ((nz + kz - 1) / kz); }
+int split_blocks(int nx, int ny, int nz, int kz, int w) {
+    const int nr = 256 / w;
+    return ((nx + w - 1) / w) * ((ny + nr - 1) / nr) * ((nz + kz - 1) / kz);
+}
 
 #define FDTD_INSTANTIATE(T)                                                                   \
     template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, const int*); \

@@ -30,15 +30,16 @@ constexpr int kAdjClasses1 = 7, kAdjClasses2 = 6;
 
 struct LaunchCfg {
     int kernel, rows, kz, nblk, ndom;
+    int sw;                    // split forward: block width in columns (64 or 32; 256 / sw rows)
     const int* bs;             // split blocks per domain (prefix sums)
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
     // split adjoint: tile tables (domain, x0 | xlen << 24, y0, k0) per class,
     // domains with a gradient only.  x is cut into the slab zones (narrow
-    // tiles, W = 16) and the interior zone (W = 64); a class names the slabs
+    // tiles, W = 16) and the interior zone (W = 32); a class names the slabs
     // its tiles, or the neighbours they read, meet.  E-node pass kAdjClasses1
-    // classes [W64: none, y/z, general; W16: x, all, general, y/z], H-node
-    // pass kAdjClasses2 classes [W64: none, y/z, all; W16: x, all, y/z];
+    // classes [W32: none, y/z, general; W16: x, all, general, y/z], H-node
+    // pass kAdjClasses2 classes [W32: none, y/z, all; W16: x, all, y/z];
     // general = Lorentz cells or gradient cells in a slab.
     int na1[kAdjClasses1], na2[kAdjClasses2];
     const int4* ta1[kAdjClasses1];
@@ -72,7 +73,8 @@ void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t 
 template <typename T>
 void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t s);
 
-int split_blocks(int nx, int ny, int nz, int kz);
+// column blocks of the split forward for block width w (64 or 32 columns)
+int split_blocks(int nx, int ny, int nz, int kz, int w);
 
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_step_counter(int* c, int value, bool add, hipStream_t s);

@@ -227,7 +227,7 @@ struct Handle : Base {
         for (int q = 0; q < ndom; ++q) {
             const fdtd_domain_desc& s = dh[q].desc;
             const int nx = s.n[0], ny = s.n[1], nz = s.n[2];
-            bs_host[q + 1] = bs_host[q] + split_blocks(nx, ny, nz, kz);
+            bs_host[q + 1] = bs_host[q] + split_blocks(nx, ny, nz, kz, cfg.sw);
             long long nl = 0;
             if (s.n_lorentz) {
                 const fdtd_lorentz_desc& L = s.lorentz;
@@ -289,7 +289,7 @@ struct Handle : Base {
     // zone, an interior zone and a high slab zone; the E-node pass (which reads
     // the memory one step back) widens the low zone by one column, the H-node
     // pass (one step forward) the high zone.  Slab zones take narrow tiles (16
-    // columns by 16 rows), the interior zone wide ones (64 by 4) from its first
+    // columns by 16 rows), the interior zone wide ones (32 by 8) from its first
     // 32-column boundary on (narrow tiles cover the columns before it).  Per axis a,
     // a tile needs the a-slab memory cotangents if a node it updates, or the
     // neighbour it reads along a, lies in an a-slab; it goes to the narrowest
@@ -313,7 +313,7 @@ struct Handle : Base {
                 const int zlo[3] = {0, wa, xb}, zhi[3] = {wa, xb, n[0]};
                 for (int zone = 0; zone < 3; ++zone) {
                     const bool wide = zone == 1;
-                    const int W = wide ? 64 : 16, rows = wide ? 4 : 16;
+                    const int W = wide ? 32 : 16, rows = 256 / W;
                     for (int x0 = zlo[zone]; x0 < zhi[zone]; x0 += W)
                         for (int y0 = 0; y0 < n[1]; y0 += rows)
                             for (int k0 = 0; k0 < n[2]; k0 += kz) {
@@ -489,6 +489,10 @@ struct Handle : Base {
         if (o->tile_kz < 0) return fail(FDTD_E_INVALID, "tile_kz");
         cfg.kernel = o->kernel == FDTD_KERNEL_FUSED ? 2 : 1;
         cfg.rows = o->tile_rows ? o->tile_rows : 2;
+        // split family: tile_rows = rows per block, 4 (64 columns) or 8 (32 columns)
+        if (cfg.kernel == 1 && o->tile_rows != 0 && o->tile_rows != 4 && o->tile_rows != 8)
+            return fail(FDTD_E_INVALID, "split kernels take tile_rows 4 or 8");
+        cfg.sw = (cfg.kernel == 1 && o->tile_rows == 8) ? 32 : 64;
         cfg.kz = o->tile_kz ? o->tile_kz : (cfg.kernel == 1 ? 8 : 16);
         cfg.ndom = n;
         dh.resize(n);

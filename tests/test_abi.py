@@ -96,3 +96,12 @@ def test_bf16_needs_fp32():
     with pytest.raises(B.FdtdError) as e:
         B.fdtd_create([_spec()], B.FDTD_F64, ckpt_storage=B.FDTD_BF16, mem_budget_bytes=1e12)
     assert e.value.code == B.FDTD_E_INVALID
+
+
+def test_launch_shape_options_checked():
+    """Split blocks take 4 or 8 rows, fused tiles 2, 4 or 8 rows per wave;
+    captured chunks hold at most 64 steps."""
+    _refused(_spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_SPLIT, tile_rows=2)
+    _refused(_spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED, tile_rows=3)
+    _refused(_spec(), B.FDTD_E_INVALID, graph_chunk=65)
+    _refused(_spec(), B.FDTD_E_INVALID, tile_kz=-1)

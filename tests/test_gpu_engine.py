@@ -53,7 +53,7 @@ def _cot(mi, m, sp):
 def test_fused_equals_split_forward(dtype, case):
     spec = _case() if case == "lorentz" else _case_design()
     runs = []
-    for kern, rows, kz in (("split", 0, 0), ("fused", 4, 16), ("fused", 2, 7), ("fused", 8, 32)):
+    for kern, rows, kz in (("split", 0, 0), ("split", 8, 3), ("fused", 4, 16), ("fused", 2, 7), ("fused", 8, 32)):
         sim = Simulation(spec, dtype=dtype, kernel=kern, tile_rows=rows, tile_kz=kz)
         sim.step(spec.n_steps)
         runs.append((_fields(sim), [sim.spectra(mi) for mi in range(len(spec.monitors))]))
@@ -69,7 +69,7 @@ def test_fused_equals_split_forward(dtype, case):
 def test_fused_equals_split_adjoint(dtype, case):
     spec = _case(n_steps=60) if case == "lorentz" else _case_design(n_steps=60)
     g = {}
-    for kern, rows in (("split", 0), ("fused", 2), ("fused", 4)):
+    for kern, rows in (("split", 0), ("split", 8), ("fused", 2), ("fused", 4)):
         N = spec.n_steps
         sim = Simulation(spec, dtype=dtype, kernel=kern, n_ckpt=N + 1, tile_rows=rows)
         sim.save(0)
