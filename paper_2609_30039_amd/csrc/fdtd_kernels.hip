@@ -74,8 +74,8 @@ __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int 
     return c;
 }
 
-// Tile-table columns of the split adjoint.  A tile is (domain, x0 | xlen << 24,
-// y0, k0) and covers W x-columns by 256 / W rows: W = 32 (8 rows, two rows
+// Tile-table columns of the split adjoint.  A tile is (domain | class << 24,
+// x0 | xlen << 24, y0, k0) and covers W x-columns by 256 / W rows: W = 32 (8 rows, two rows
 // per wave) inside, W = 16 (16 rows) for the narrow x-slab zones.  Columns
 // at or beyond x0 + xlen are idle.
 template <int W>
@@ -85,11 +85,9 @@ struct TileCol {
 };
 
 template <typename T, int W>
-__device__ __forceinline__ TileCol<W> tile_column(const DomDev<T>* doms, const int4* tiles, int kz,
-                                                  const DomDev<T>*& dp) {
+__device__ __forceinline__ TileCol<W> tile_column(const DomDev<T>* doms, const int4 e, int kz, const DomDev<T>*& dp) {
     TileCol<W> c;
-    const int4 e = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-    dp = doms + e.x;
+    dp = doms + (e.x & 0xFFFFFF);
     const DomDev<T>& d = *dp;
     const int xlen = e.y >> 24, lx = (int)(threadIdx.x % W);
     c.x0 = e.y & 0xFFFFFF;
@@ -596,10 +594,10 @@ __device__ __forceinline__ void adje_fetch(const DomDev<T>& d, AdjColE<T>& p, co
 }
 
 template <typename T, int V, int W>
-__global__ void __launch_bounds__(256) k_adj_ht(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
-                                                int kz, int rs, int ws, int fsr) {
+__device__ __forceinline__ void adj_ht_tile(const DomDev<T>* __restrict__ doms, const int4 tile, int kz, int rs,
+                                            int ws, int fsr) {
     const DomDev<T>* dp;
-    const TileCol<W> c = tile_column<T, W>(doms, tiles, kz, dp);
+    const TileCol<W> c = tile_column<T, W>(doms, tile, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
@@ -863,10 +861,10 @@ __device__ __forceinline__ Dbar6<T> dbar6(int i, int j, int k, T ux, T uy, T uz,
 }
 
 template <typename T, int V, int W>
-__global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
-                                                int kz, int rs, int ws) {
+__device__ __forceinline__ void adj_et_tile(const DomDev<T>* __restrict__ doms, const int4 tile, int kz, int rs,
+                                            int ws) {
     const DomDev<T>* dp;
-    const TileCol<W> c = tile_column<T, W>(doms, tiles, kz, dp);
+    const TileCol<W> c = tile_column<T, W>(doms, tile, kz, dp);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     if (!d.grad) return;
@@ -936,6 +934,51 @@ __global__ void __launch_bounds__(256) k_adj_et(const DomDev<T>* __restrict__ do
         hw[2][f] = hbz;
         cur = up;
         cu = nx_;
+    }
+}
+
+// One launch per adjoint pass over every tile class: the class of a tile
+// selects the variant.  The host orders the table with the slab classes
+// first, so their slower waves start early and overlap the interior ones.
+// The general class (Lorentz cells, gradient cells in a slab; rare) has a
+// launch of its own, which keeps its registers out of the others.  Both
+// passes are held to 4 waves per SIMD (128 VGPRs, a few spills in the slab
+// variants): measured faster than 3 waves without spills.
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_adj_ht(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+                                                int kz, int rs, int ws, int fsr) {
+    const int4 e = tiles[blockIdx.x];
+    static_assert(kAdjClasses1 == 7, "one case per class");
+    switch (e.x >> 24) {
+    case 0: adj_ht_tile<T, 0, 32>(doms, e, kz, rs, ws, fsr); break;
+    case 1: adj_ht_tile<T, 6, 32>(doms, e, kz, rs, ws, fsr); break;
+    case 3: adj_ht_tile<T, 1, 16>(doms, e, kz, rs, ws, fsr); break;
+    case 4: adj_ht_tile<T, 7, 16>(doms, e, kz, rs, ws, fsr); break;
+    case 6: adj_ht_tile<T, 6, 16>(doms, e, kz, rs, ws, fsr); break;
+    default: break;   // general classes 2 and 5: k_adj_ht_full
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_ht_full(const DomDev<T>* __restrict__ doms,
+                                                     const int4* __restrict__ tiles, int kz, int rs, int ws, int fsr) {
+    const int4 e = tiles[blockIdx.x];
+    if ((e.x >> 24) == 2) adj_ht_tile<T, kAdjFull, 32>(doms, e, kz, rs, ws, fsr);
+    else adj_ht_tile<T, kAdjFull, 16>(doms, e, kz, rs, ws, fsr);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_adj_et(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles, int kz, int rs, int ws) {
+    const int4 e = tiles[blockIdx.x];
+    static_assert(kAdjClasses2 == 6, "one case per class");
+    switch (e.x >> 24) {
+    case 0: adj_et_tile<T, 0, 32>(doms, e, kz, rs, ws); break;
+    case 1: adj_et_tile<T, 6, 32>(doms, e, kz, rs, ws); break;
+    case 2: adj_et_tile<T, 7, 32>(doms, e, kz, rs, ws); break;
+    case 3: adj_et_tile<T, 1, 16>(doms, e, kz, rs, ws); break;
+    case 4: adj_et_tile<T, 7, 16>(doms, e, kz, rs, ws); break;
+    default: adj_et_tile<T, 6, 16>(doms, e, kz, rs, ws); break;
     }
 }
 
@@ -1944,34 +1987,13 @@ void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, h
                 const hipStream_t* cs) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
-        // one launch per tile class (see kAdjFull), each with only the registers
-        // it needs; cs[q] is the stream of class q (the classes of a pass write
-        // disjoint nodes and may run concurrently)
-        static_assert(kAdjClasses1 == 7 && kAdjClasses2 == 6, "one launch per class below");
-#define FDTD_ADJ_HT(V, W, q)                                                                                          \
-    if (c.na1[q])                                                                                                     \
-        hipLaunchKernelGGL((k_adj_ht<T, V, W>), dim3(c.na1[q]), dim3(256), 0, cs[q], dd, c.ta1[q], c.kz, rs, ws, fsr);
-#define FDTD_ADJ_ET(V, W, q)                                                                                          \
-    if (c.na2[q])                                                                                                     \
-        hipLaunchKernelGGL((k_adj_et<T, V, W>), dim3(c.na2[q]), dim3(256), 0, cs[q], dd, c.ta2[q], c.kz, rs, ws);
-        if (pass == 0) {
-            FDTD_ADJ_HT(0, 32, 0)
-            FDTD_ADJ_HT(6, 32, 1)
-            FDTD_ADJ_HT(kAdjFull, 32, 2)
-            FDTD_ADJ_HT(1, 16, 3)
-            FDTD_ADJ_HT(7, 16, 4)
-            FDTD_ADJ_HT(kAdjFull, 16, 5)
-            FDTD_ADJ_HT(6, 16, 6)
-        } else {
-            FDTD_ADJ_ET(0, 32, 0)
-            FDTD_ADJ_ET(6, 32, 1)
-            FDTD_ADJ_ET(7, 32, 2)
-            FDTD_ADJ_ET(1, 16, 3)
-            FDTD_ADJ_ET(7, 16, 4)
-            FDTD_ADJ_ET(6, 16, 5)
-        }
-#undef FDTD_ADJ_HT
-#undef FDTD_ADJ_ET
+        // ta1: [general tiles (na1g)][the other classes]
+        if (pass == 0 && c.na1g)
+            hipLaunchKernelGGL(k_adj_ht_full<T>, dim3(c.na1g), dim3(256), 0, s, dd, c.ta1, c.kz, rs, ws, fsr);
+        if (pass == 0 && c.na1 > c.na1g)
+            hipLaunchKernelGGL(k_adj_ht<T>, dim3(c.na1 - c.na1g), dim3(256), 0, s, dd, c.ta1 + c.na1g, c.kz, rs, ws,
+                               fsr);
+        if (pass == 1 && c.na2) hipLaunchKernelGGL(k_adj_et<T>, dim3(c.na2), dim3(256), 0, s, dd, c.ta2, c.kz, rs, ws);
         return;
     }
     if (pass != 0) return;

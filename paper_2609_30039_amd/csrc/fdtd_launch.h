@@ -34,16 +34,16 @@ struct LaunchCfg {
     const int* bs;             // split blocks per domain (prefix sums)
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
-    // split adjoint: tile tables (domain, x0 | xlen << 24, y0, k0) per class,
-    // domains with a gradient only.  x is cut into the slab zones (narrow
-    // tiles, W = 16) and the interior zone (W = 32); a class names the slabs
-    // its tiles, or the neighbours they read, meet.  E-node pass kAdjClasses1
-    // classes [W32: none, y/z, general; W16: x, all, general, y/z], H-node
-    // pass kAdjClasses2 classes [W32: none, y/z, all; W16: x, all, y/z];
-    // general = Lorentz cells or gradient cells in a slab.
-    int na1[kAdjClasses1], na2[kAdjClasses2];
-    const int4* ta1[kAdjClasses1];
-    const int4* ta2[kAdjClasses2];
+    // split adjoint: one tile table per pass, (domain | class << 24,
+    // x0 | xlen << 24, y0, k0), domains with a gradient only.  x is cut into
+    // the slab zones (narrow tiles, W = 16) and the interior zone (W = 32); a
+    // class names the slabs its tiles, or the neighbours they read, meet.
+    // E-node pass kAdjClasses1 classes [W32: none, y/z, general; W16: x, all,
+    // general, y/z], H-node pass kAdjClasses2 classes [W32: none, y/z, all;
+    // W16: x, all, y/z]; general = Lorentz cells or gradient cells in a slab.
+    int na1, na2, na1g;        // tiles per pass; general tiles leading the E-node table
+    const int4* ta1;
+    const int4* ta2;
 
     int ngen, nbulk;           // adjoint: general tiles, interior (bulk) tiles
     const int4* tgen;

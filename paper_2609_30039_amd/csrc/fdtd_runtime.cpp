@@ -142,6 +142,7 @@ struct Handle : Base {
     // tile tables of the split adjoint: E-node pass 6 classes, H-node pass 5
     // classes (LaunchCfg::ta1, ta2)
     std::vector<int4> atiles[kAdjClasses1 + kAdjClasses2];
+    std::vector<int4> atab1, atab2;   // the tables uploaded: E-node pass, H-node pass
     int4* d_atiles = nullptr;
     // pool: [misc][forward sets x nsets][adjoint sets x 2][split scratch][bf16 slots]
     char* pool = nullptr;
@@ -356,13 +357,23 @@ struct Handle : Base {
                                     else cls = !(mask & 1) ? 5 : (mask & ~1) ? 4 : 3;
                                     cls += kAdjClasses1;
                                 }
-                                atiles[cls].push_back(make_int4(q, x0 | (xlen << 24), y0, k0));
+                                const int c = pass == 0 ? cls : cls - kAdjClasses1;
+                                atiles[cls].push_back(make_int4(q | (c << 24), x0 | (xlen << 24), y0, k0));
                             }
                 }
             }
         }
-        for (int c = 0; c < kAdjClasses1; ++c) cfg.na1[c] = (int)atiles[c].size();
-        for (int c = 0; c < kAdjClasses2; ++c) cfg.na2[c] = (int)atiles[kAdjClasses1 + c].size();
+        // one table per pass, slab classes first (they start early and overlap
+        // the interior tiles)
+        static const int order1[kAdjClasses1] = {5, 2, 4, 3, 6, 1, 0};
+        static const int order2[kAdjClasses2] = {4, 3, 2, 5, 1, 0};
+        atab1.clear();
+        atab2.clear();
+        for (int c : order1) atab1.insert(atab1.end(), atiles[c].begin(), atiles[c].end());
+        for (int c : order2) atab2.insert(atab2.end(), atiles[kAdjClasses1 + c].begin(), atiles[kAdjClasses1 + c].end());
+        cfg.na1 = (int)atab1.size();
+        cfg.na1g = (int)(atiles[5].size() + atiles[2].size());   // order1 starts with the general classes
+        cfg.na2 = (int)atab2.size();
     }
 
     // ------------------------------------------------------------ layout
@@ -461,9 +472,7 @@ struct Handle : Base {
         M.take(d_doms, sizeof(DomDev<T>) * ndom);
         M.take(d_bs, sizeof(int) * 2 * (ndom + 1));
         M.take(d_tstep, sizeof(int));
-        size_t nat = 0;
-        for (auto& l : atiles) nat += l.size();
-        M.take(d_atiles, sizeof(int4) * std::max<size_t>(1, nat));
+        M.take(d_atiles, sizeof(int4) * std::max<size_t>(1, atab1.size() + atab2.size()));
         M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
                                                                tiles_fcp.size() + tiles_fplain.size()));
         M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
@@ -557,13 +566,8 @@ struct Handle : Base {
         cfg.tfgen = cfg.tbulk + tiles_bulk.size();
         cfg.tfcp = cfg.tfgen + tiles_fgen.size();
         cfg.tfplain = cfg.tfcp + tiles_fcp.size();
-        {
-            const int4* p = d_atiles;
-            for (int c = 0; c < kAdjClasses1 + kAdjClasses2; ++c) {
-                (c < kAdjClasses1 ? cfg.ta1[c] : cfg.ta2[c - kAdjClasses1]) = p;
-                p += atiles[c].size();
-            }
-        }
+        cfg.ta1 = d_atiles;
+        cfg.ta2 = d_atiles + atab1.size();
         // ---- initialise: zero everything, upload tables and inputs
         launch_zero(pool, pool_bytes, st);
         int rc = check("zero pool");
@@ -607,8 +611,8 @@ struct Handle : Base {
             if (!all.empty() && hipMemcpyAsync(d_tiles, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice,
                                                st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "upload tile tables failed");
-            std::vector<int4> at;
-            for (auto& l : atiles) at.insert(at.end(), l.begin(), l.end());
+            std::vector<int4> at(atab1);
+            at.insert(at.end(), atab2.begin(), atab2.end());
             if (!at.empty() && hipMemcpyAsync(d_atiles, at.data(), sizeof(int4) * at.size(), hipMemcpyHostToDevice,
                                               st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "upload adjoint tiles failed");
