@@ -80,6 +80,57 @@ def run_forward(spec, dtype, stream, K, Wm, tile=None, graph_chunk=32):
     return sim, el, kms, nl
 
 
+def large_adjoint(stream, log):
+    """512^3 + 12-cell CPML, diagonal eps, 128^3 Lorentz box, |DFT Ex|^2 on a
+    64x64 patch, 4000 steps: binomial replay with 32 FP32 slots and with 32 BF16
+    slots (per-array max-abs scale), and an FP64 reference (20 slots, to fit in
+    memory); gradients compared on a 64^3 subsample of the gradient box."""
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import adjoint as A
+    from paper_2609_30039_amd import autotune as AT
+    from paper_2609_30039_amd.sim import Simulation
+    spec = W.anisotropic_lorentz()
+    N = spec.n_steps
+    out = {"workload": "536^3 (512^3 + 12-cell CPML), diagonal eps in [1,5], 128^3 Lorentz box, Ex sheet, |DFT Ex|^2 "
+                       "on a 64x64 patch (8 frequencies), 4000 steps", "cells": spec.ncells}
+    grads = {}
+    for tag, dtype, slots, storage in (("fp32_slots", "f32", 32, None), ("bf16_slots", "f32", 32, "bf16"),
+                                       ("fp64", "f64", 20, None)):
+        tile = AT.tune(spec, dtype, adjoint=True, stream=stream, log=log, steps=3)
+        kw = dict(tile)
+        if storage:
+            kw["ckpt_storage"] = storage
+        sim = Simulation(spec, dtype=dtype, n_ckpt=slots, stream=stream, graph_chunk=32 if tile["kernel"] == "split"
+                         else 0, **kw)
+        plan = A.RevolvePlan(N, slots)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = A.forward_record(sim, plan)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.set_cotangent(0, 2.0 * sim.spectra(0))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        A.reverse_sweep(sim, plan, *last, progress=lambda m: log(f"  {tag}: adjoint at step {m}"))
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        g = sim.grad(0)
+        grads[tag] = g[:, ::8, ::8, ::8].astype(np.float64)   # 64^3 subsample per component
+        out[tag] = {"slots": slots, "launch_shape": tile, "forward_s": round(t1 - t0, 3),
+                    "reverse_s": round(t3 - t2, 3), "reverse_over_forward": round((t3 - t2) / (t1 - t0), 3),
+                    "forward_evaluations": plan.forward_evals + 1, "device_bytes": sim.memory_bytes()}
+        log(f"large adjoint {tag}: forward {t1 - t0:.2f} s, reverse {t3 - t2:.2f} s")
+        sim.close()
+        del sim
+    ref = grads["fp64"]
+    for tag in ("fp32_slots", "bf16_slots"):
+        out[tag]["grad_rel_l2_vs_fp64_64cube"] = float(f"{np.linalg.norm(grads[tag] - ref) / np.linalg.norm(ref):.3e}")
+    out["bf16_vs_fp32_slots_grad_rel_l2"] = float(
+        f"{np.linalg.norm(grads['bf16_slots'] - grads['fp32_slots']) / np.linalg.norm(grads['fp32_slots']):.3e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +139,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--large-adjoint", action="store_true",
+                    help="run only the 512^3 + CPML adjoint study (FP32 vs BF16 checkpoints vs FP64) and print its JSON")
     ap.add_argument("--shape", default=None,
                     help="launch shape KERNEL,ROWS,KZ for the headline (skips the autotuner), e.g. split,0,8")
     args = ap.parse_args()
@@ -110,6 +163,10 @@ def main():
     khash = kernel_source_hash()
 
     from paper_2609_30039_amd import autotune as AT
+
+    if args.large_adjoint:
+        print(json.dumps(large_adjoint(stream, log)), flush=True)
+        return
 
     # ---------------------------------------------------------------- headline
     spec = W.lorentz_flux()

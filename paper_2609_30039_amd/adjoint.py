@@ -52,8 +52,9 @@ def forward_record(sim: Simulation, plan: RevolvePlan):
     return last_slot, last_pos
 
 
-def reverse_sweep(sim: Simulation, plan: RevolvePlan, last_slot: int, last_pos: int):
-    """Reverse phase: ubar^N -> ubar^0, accumulating dJ/deps in the library."""
+def reverse_sweep(sim: Simulation, plan: RevolvePlan, last_slot: int, last_pos: int, progress=None):
+    """Reverse phase: ubar^N -> ubar^0, accumulating dJ/deps in the library.
+    progress(m), if given, is called after every 500th adjoint step."""
     N = plan.n_steps
     sim.adjoint_begin(N)
     if N == 0:
@@ -71,6 +72,8 @@ def reverse_sweep(sim: Simulation, plan: RevolvePlan, last_slot: int, last_pos: 
             sim.restore(a[1])
         elif a[0] == "adjoint":
             sim.step_adjoint(1)
+            if progress is not None and sim.steps[1] % 500 == 0:
+                progress(sim.steps[1])
 
 
 def gradient(sim: Simulation, n_steps: int, n_slots: int,
