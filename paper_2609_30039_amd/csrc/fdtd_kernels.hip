@@ -16,6 +16,7 @@
 //          neighbours travel by lane shuffles, y neighbours across waves by a
 //          double-buffered LDS row, z neighbours stay in registers.
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <stdint.h>
 
 #include "fdtd_dev.h"
@@ -1897,11 +1898,13 @@ __global__ void k_maxabs_f32(const float* __restrict__ x, long long n, unsigned 
     if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
-// x / scale rounded to bfloat16 (round to nearest even)
+// x / scale rounded to bfloat16 (round to nearest even).  An array whose
+// largest magnitude is below the smallest normal float (a slab the wave has not
+// reached yet) is stored as zeros: 1/scale would overflow and 0 * inf is NaN.
 __global__ void k_pack_bf16(const float* __restrict__ x, long long n, const unsigned int* scale_bits,
                             uint16_t* __restrict__ y) {
     float s = __uint_as_float(*scale_bits);
-    float inv = s > 0.f ? 1.f / s : 0.f;
+    float inv = s >= FLT_MIN ? 1.f / s : 0.f;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         uint32_t u = __float_as_uint(x[q] * inv);
@@ -1913,6 +1916,7 @@ __global__ void k_pack_bf16(const float* __restrict__ x, long long n, const unsi
 __global__ void k_unpack_bf16(const uint16_t* __restrict__ y, long long n, const unsigned int* scale_bits,
                               float* __restrict__ x) {
     float s = __uint_as_float(*scale_bits);
+    if (!(s >= FLT_MIN)) s = 0.f;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x)
         x[q] = __uint_as_float(((uint32_t)y[q]) << 16) * s;

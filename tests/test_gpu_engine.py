@@ -132,6 +132,33 @@ def test_bf16_checkpoints_report_error():
     assert 0 < err < 5e-2, err
 
 
+def test_bf16_slot_of_denormal_array_restores_finite():
+    """An array whose largest magnitude is below the smallest normal float (a
+    slab or Lorentz box the wave has not reached when a slot is saved) must
+    restore as zeros, not as NaN from 0 * (1 / scale)."""
+    spec = _case(n_steps=8)
+    sim = Simulation(spec, dtype="f32", n_ckpt=2, ckpt_storage="bf16")
+    nx, ny, nz = spec.shape
+    ex = np.zeros((nz, ny, nx), np.float32)     # fields are stored z-major, x fastest
+    ex[20, 30, 40] = np.float32(3e-39)          # denormal maximum
+    ex[20, 30, 41] = np.float32(-1e-40)
+    hz = np.zeros((nz, ny, nx), np.float32)
+    hz[10, 20, 50] = np.float32(0.75)           # an ordinary array beside it
+    sim.set_field(0, ex)
+    sim.set_field(5, hz)
+    sim.save(1)
+    sim.step(3, record=False)
+    sim.restore(1)
+    back = _fields(sim)
+    for f in back:
+        assert np.isfinite(f).all()
+    assert not back[0].any()
+    assert abs(back[5][10, 20, 50] - 0.75) <= 0.75 * 2.0 ** -8
+    sim.step(5, record=False)
+    for f in _fields(sim):
+        assert np.isfinite(f).all()
+
+
 def test_checksum_detects_corruption_and_empty_slot():
     spec = _case(n_steps=20)
     sim = Simulation(spec, dtype="f32", n_ckpt=3, ckpt_checksum=True)
