@@ -1890,36 +1890,117 @@ __global__ void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restr
 }
 
 // max |x| of an FP32 array into *out (as ordered bits; out pre-zeroed)
-__global__ void k_maxabs_f32(const float* __restrict__ x, long long n, unsigned int* out) {
-    float m = 0.f;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf(x[q]));
+// ---- BF16 checkpoint slots.  The forward state arrays of all domains are
+// listed in one table (BfArr); every array is cut into chunks of kBfChunk
+// elements and each block takes one chunk, so a save is three launches
+// (partial maxima, per-array scale, pack) and a restore one, whatever the
+// number of arrays.  Array starts and slot offsets are 256-byte aligned, so a
+// thread moves 8 elements as two float4 loads and one 16-byte bf16 store.
+
+// array whose chunk block b belongs to (largest q with blk0 <= b)
+__device__ inline int bf_array(const BfArr* __restrict__ a, int narr, int b) {
+    int lo = 0, hi = narr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid].blk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline float block_max(float m) {
+    __shared__ float red[4];
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_down(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// part[b] = max |x| over chunk b (no atomics; deterministic)
+__global__ void __launch_bounds__(256) k_bf16_partmax(const BfArr* __restrict__ arr, int narr, long long shift,
+                                                      float* __restrict__ part) {
+    const int q = bf_array(arr, narr, blockIdx.x);
+    const BfArr& A = arr[q];
+    const float* x = (const float*)((const char*)A.p + shift);
+    const long long e0 = (long long)(blockIdx.x - A.blk0) * kBfChunk;
+    const long long e1 = min(e0 + kBfChunk, A.n);
+    const long long v1 = e0 + ((e1 - e0) & ~7LL);
+    float m = 0.f;
+    for (long long v = e0 + 8 * threadIdx.x; v < v1; v += 8 * 256) {
+        const float4 u = *(const float4*)(x + v);
+        const float4 w = *(const float4*)(x + v + 4);
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(u.x), fabsf(u.y)), fmaxf(fabsf(u.z), fabsf(u.w))));
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(w.x), fabsf(w.y)), fmaxf(fabsf(w.z), fabsf(w.w))));
+    }
+    if (v1 + threadIdx.x < e1) m = fmaxf(m, fabsf(x[v1 + threadIdx.x]));
+    m = block_max(m);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// scale[q] = max over the chunks of array q (one block per array)
+__global__ void __launch_bounds__(256) k_bf16_scale(const BfArr* __restrict__ arr, const float* __restrict__ part,
+                                                    unsigned int* __restrict__ scale) {
+    const BfArr& A = arr[blockIdx.x];
+    float m = 0.f;
+    for (int b = threadIdx.x; b < A.nblk; b += 256) m = fmaxf(m, part[A.blk0 + b]);
+    m = block_max(m);
+    if (threadIdx.x == 0) scale[blockIdx.x] = __float_as_uint(m);
 }
 
 // x / scale rounded to bfloat16 (round to nearest even).  An array whose
 // largest magnitude is below the smallest normal float (a slab the wave has not
 // reached yet) is stored as zeros: 1/scale would overflow and 0 * inf is NaN.
-__global__ void k_pack_bf16(const float* __restrict__ x, long long n, const unsigned int* scale_bits,
-                            uint16_t* __restrict__ y) {
-    float s = __uint_as_float(*scale_bits);
-    float inv = s >= FLT_MIN ? 1.f / s : 0.f;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x) {
-        uint32_t u = __float_as_uint(x[q] * inv);
-        uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
-        y[q] = (uint16_t)(r >> 16);
-    }
+__device__ inline uint32_t bf16_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
-__global__ void k_unpack_bf16(const uint16_t* __restrict__ y, long long n, const unsigned int* scale_bits,
-                              float* __restrict__ x) {
-    float s = __uint_as_float(*scale_bits);
+__global__ void __launch_bounds__(256) k_bf16_pack(const BfArr* __restrict__ arr, int narr, long long shift,
+                                                   const unsigned int* __restrict__ scale, char* __restrict__ slot) {
+    const int q = bf_array(arr, narr, blockIdx.x);
+    const BfArr& A = arr[q];
+    const float* x = (const float*)((const char*)A.p + shift);
+    uint16_t* y = (uint16_t*)(slot + A.boff);
+    const float s = __uint_as_float(scale[q]);
+    const float inv = s >= FLT_MIN ? 1.f / s : 0.f;
+    const long long e0 = (long long)(blockIdx.x - A.blk0) * kBfChunk;
+    const long long e1 = min(e0 + kBfChunk, A.n);
+    const long long v1 = e0 + ((e1 - e0) & ~7LL);
+    for (long long v = e0 + 8 * threadIdx.x; v < v1; v += 8 * 256) {
+        const float4 u = *(const float4*)(x + v);
+        const float4 w = *(const float4*)(x + v + 4);
+        uint4 o;
+        o.x = bf16_bits(u.x * inv) | (bf16_bits(u.y * inv) << 16);
+        o.y = bf16_bits(u.z * inv) | (bf16_bits(u.w * inv) << 16);
+        o.z = bf16_bits(w.x * inv) | (bf16_bits(w.y * inv) << 16);
+        o.w = bf16_bits(w.z * inv) | (bf16_bits(w.w * inv) << 16);
+        *(uint4*)(y + v) = o;
+    }
+    if (v1 + threadIdx.x < e1) y[v1 + threadIdx.x] = (uint16_t)bf16_bits(x[v1 + threadIdx.x] * inv);
+}
+
+__device__ inline float bf16_float(uint32_t h) { return __uint_as_float(h << 16); }
+
+__global__ void __launch_bounds__(256) k_bf16_unpack(const BfArr* __restrict__ arr, int narr, long long shift,
+                                                     const unsigned int* __restrict__ scale,
+                                                     const char* __restrict__ slot) {
+    const int q = bf_array(arr, narr, blockIdx.x);
+    const BfArr& A = arr[q];
+    float* x = (float*)((char*)A.p + shift);
+    const uint16_t* y = (const uint16_t*)(slot + A.boff);
+    float s = __uint_as_float(scale[q]);
     if (!(s >= FLT_MIN)) s = 0.f;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x)
-        x[q] = __uint_as_float(((uint32_t)y[q]) << 16) * s;
+    const long long e0 = (long long)(blockIdx.x - A.blk0) * kBfChunk;
+    const long long e1 = min(e0 + kBfChunk, A.n);
+    const long long v1 = e0 + ((e1 - e0) & ~7LL);
+    for (long long v = e0 + 8 * threadIdx.x; v < v1; v += 8 * 256) {
+        const uint4 h = *(const uint4*)(y + v);
+        *(float4*)(x + v) = make_float4(bf16_float(h.x & 0xffffu) * s, bf16_float(h.x >> 16) * s,
+                                        bf16_float(h.y & 0xffffu) * s, bf16_float(h.y >> 16) * s);
+        *(float4*)(x + v + 4) = make_float4(bf16_float(h.z & 0xffffu) * s, bf16_float(h.z >> 16) * s,
+                                            bf16_float(h.w & 0xffffu) * s, bf16_float(h.w >> 16) * s);
+    }
+    if (v1 + threadIdx.x < e1) x[v1 + threadIdx.x] = bf16_float(y[v1 + threadIdx.x]) * s;
 }
 
 // 64-bit wrap-around weighted sum of 32-bit words (slot checksum)
@@ -2049,16 +2130,18 @@ void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
                        (uint32_t*)dst, nw);
 }
 
-void launch_maxabs_f32(const float* x, long long n, unsigned int* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_maxabs_f32, dim3(blocks_1d(n, 256, 4096)), dim3(256), 0, s, x, n, out);
+void launch_bf16_save(const BfArr* arr, int narr, int nblk, long long shift, float* part, unsigned int* scale,
+                      char* slot, hipStream_t s) {
+    if (narr == 0 || nblk == 0) return;
+    hipLaunchKernelGGL(k_bf16_partmax, dim3(nblk), dim3(256), 0, s, arr, narr, shift, part);
+    hipLaunchKernelGGL(k_bf16_scale, dim3(narr), dim3(256), 0, s, arr, (const float*)part, scale);
+    hipLaunchKernelGGL(k_bf16_pack, dim3(nblk), dim3(256), 0, s, arr, narr, shift, (const unsigned int*)scale, slot);
 }
 
-void launch_pack_bf16(const float* x, long long n, const unsigned int* scale, uint16_t* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_bf16, dim3(blocks_1d(n, 256, 8192)), dim3(256), 0, s, x, n, scale, y);
-}
-
-void launch_unpack_bf16(const uint16_t* y, long long n, const unsigned int* scale, float* x, hipStream_t s) {
-    hipLaunchKernelGGL(k_unpack_bf16, dim3(blocks_1d(n, 256, 8192)), dim3(256), 0, s, y, n, scale, x);
+void launch_bf16_restore(const BfArr* arr, int narr, int nblk, long long shift, const unsigned int* scale,
+                         const char* slot, hipStream_t s) {
+    if (narr == 0 || nblk == 0) return;
+    hipLaunchKernelGGL(k_bf16_unpack, dim3(nblk), dim3(256), 0, s, arr, narr, shift, scale, slot);
 }
 
 void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s) {

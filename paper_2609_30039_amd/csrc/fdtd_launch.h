@@ -79,9 +79,20 @@ int split_blocks(int nx, int ny, int nz, int kz, int w);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_step_counter(int* c, int value, bool add, hipStream_t s);
 void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
-void launch_maxabs_f32(const float* x, long long n, unsigned int* out, hipStream_t s);
-void launch_pack_bf16(const float* x, long long n, const unsigned int* scale, uint16_t* y, hipStream_t s);
-void launch_unpack_bf16(const uint16_t* y, long long n, const unsigned int* scale, float* x, hipStream_t s);
+// BF16 checkpoint slots: one table entry per forward state array (FP32)
+constexpr int kBfChunk = 32768;              // elements per block
+struct BfArr {
+    const void* p;                           // set-0 address of the array
+    long long n;                             // elements
+    long long boff;                          // byte offset of its bf16 copy in a slot (256-aligned)
+    int blk0, nblk;                          // its chunk blocks [blk0, blk0 + nblk)
+};
+// save: scale[q] = max |array q| over set (shift bytes from set 0); slot gets x / scale[q] in bf16
+void launch_bf16_save(const BfArr* arr, int narr, int nblk, long long shift, float* part, unsigned int* scale,
+                      char* slot, hipStream_t s);
+// restore: array q of the set at shift = slot value * scale[q]
+void launch_bf16_restore(const BfArr* arr, int narr, int nblk, long long shift, const unsigned int* scale,
+                         const char* slot, hipStream_t s);
 void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s);
 
 }  // namespace fdtd

@@ -151,6 +151,10 @@ struct Handle : Base {
     char *fbase = nullptr, *abase = nullptr, *etbase = nullptr, *bfbase = nullptr;
     std::vector<Slot> slots;
     unsigned int* d_scales = nullptr;         // [n_ckpt][n_state] BF16 scales
+    std::vector<BfArr> bfarr;                 // BF16 table: one entry per forward state array
+    BfArr* d_bfarr = nullptr;
+    float* d_bfpart = nullptr;                // per-chunk maxima of a save
+    int bfblocks = 0;
     unsigned long long* d_sum = nullptr;      // checksum scratch
     std::vector<StateArr> fwd, adj;           // state arrays (set-0 addresses)
     std::vector<std::pair<void*, size_t>> adj_flat;   // gradient accumulators, for zeroing
@@ -387,6 +391,8 @@ struct Handle : Base {
             adj_flat.clear();
         }
         bfslot = 0;
+        bfblocks = 0;
+        if (asg) bfarr.clear();
         size_t nstate = 0;
         const size_t ts = sizeof(T);
         for (int q = 0; q < ndom; ++q) {
@@ -397,9 +403,14 @@ struct Handle : Base {
             const bool g = s.grad != 0;
             auto fst = [&](T*& p, size_t n) {
                 F.take(p, n * ts);
+                const int nb = (int)((n + kBfChunk - 1) / kBfChunk);
+                if (asg) {
+                    fwd.push_back(StateArr{p, n});
+                    bfarr.push_back(BfArr{p, (long long)n, (long long)bfslot, bfblocks, nb});
+                }
                 bfslot += align256(n * 2);
+                bfblocks += nb;
                 nstate++;
-                if (asg) fwd.push_back(StateArr{p, n});
             };
             auto ast = [&](T*& p, size_t n) {
                 A.take(p, n * ts);
@@ -476,6 +487,8 @@ struct Handle : Base {
         M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
                                                                tiles_fcp.size() + tiles_fplain.size()));
         M.take(d_scales, std::max<size_t>(1, (size_t)opt.n_ckpt * nstate) * 4);
+        M.take(d_bfarr, std::max<size_t>(1, nstate) * sizeof(BfArr));
+        M.take(d_bfpart, std::max<size_t>(1, (size_t)bfblocks) * 4);
         M.take(d_sum, 8);
     }
 
@@ -616,6 +629,9 @@ struct Handle : Base {
             if (!at.empty() && hipMemcpyAsync(d_atiles, at.data(), sizeof(int4) * at.size(), hipMemcpyHostToDevice,
                                               st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "upload adjoint tiles failed");
+            if (!bfarr.empty() && hipMemcpyAsync(d_bfarr, bfarr.data(), sizeof(BfArr) * bfarr.size(),
+                                                 hipMemcpyHostToDevice, st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "upload checkpoint table failed");
         }
         return sync("create");
     }
@@ -1020,17 +1036,8 @@ struct Handle : Base {
     int ckpt_save(int slot) override {
         if (slot < 0 || slot >= (int)slots.size()) return fail(FDTD_E_RANGE, "checkpoint slot");
         if (bf16) {
-            char* base = bfbase + (size_t)slot * align256(bfslot);
-            size_t off = 0;
-            for (size_t q = 0; q < fwd.size(); ++q) {
-                StateArr& a = fwd[q];
-                const float* src = (const float*)((char*)a.p + (size_t)cur * fstride);
-                unsigned int* sc = d_scales + (size_t)slot * fwd.size() + q;
-                launch_zero(sc, 4, st);
-                launch_maxabs_f32(src, (long long)a.n, sc, st);
-                launch_pack_bf16(src, (long long)a.n, sc, (uint16_t*)(base + off), st);
-                off += align256(a.n * 2);
-            }
+            launch_bf16_save(d_bfarr, (int)bfarr.size(), bfblocks, (long long)cur * (long long)fstride, d_bfpart,
+                             d_scales + (size_t)slot * bfarr.size(), bfbase + (size_t)slot * align256(bfslot), st);
         } else if (cur == wset[0] || cur == wset[1]) {
             int wi = cur == wset[0] ? 0 : 1;
             int old = slotset[slot];
@@ -1068,15 +1075,8 @@ struct Handle : Base {
         }
         if (bf16) {
             int ws = write_set();
-            char* base = bfbase + (size_t)slot * align256(bfslot);
-            size_t off = 0;
-            for (size_t q = 0; q < fwd.size(); ++q) {
-                StateArr& a = fwd[q];
-                const unsigned int* sc = d_scales + (size_t)slot * fwd.size() + q;
-                launch_unpack_bf16((const uint16_t*)(base + off), (long long)a.n, sc,
-                                   (float*)((char*)a.p + (size_t)ws * fstride), st);
-                off += align256(a.n * 2);
-            }
+            launch_bf16_restore(d_bfarr, (int)bfarr.size(), bfblocks, (long long)ws * (long long)fstride,
+                                d_scales + (size_t)slot * bfarr.size(), bfbase + (size_t)slot * align256(bfslot), st);
             cur = ws;
         } else {
             cur = slotset[slot];
