@@ -204,8 +204,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
-                     "kernel": ("split E and H kernels (k_fwd_e, k_fwd_e_lor, k_fwd_h; lean and general block "
-                                "classes)" if tile["kernel"] == "split" else "fused single-pass tile kernels")
+                     "kernel": ("split E and H kernels (k_fwd_e with the Lorentz-box blocks leading, then k_fwd_h)"
+                                if tile["kernel"] == "split" else "fused single-pass tile kernels")
                                + ": all stepping launches of one time step",
                      "launch_shape": tile,
                      "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_launch,
