@@ -22,6 +22,19 @@
 namespace fdtd {
 
 constexpr int kMaxSrc = 4;
+constexpr int kMaxSmp = 8;   // plane monitors per domain (the descriptor limit)
+
+// A plane monitor as the split H kernel samples it: the threads whose column
+// lies in the rectangle write their node's values into slot `slot` of the ring
+// [block][rcomp][npts].  Flux rings hold Ex, Ey (plane k), Hx at k and k-1, Hy
+// at k and k-1; the spectrum update averages the two H planes.
+struct SmpDev {
+    int kind;                  // 1 flux, 2 patch
+    int comp;                  // patch component 0..5
+    int i0, i1, j0, j1, k;
+    int npts, rcomp;
+    void* ring;
+};
 
 // Global-address-space views of device pointers.  Pointers read out of a
 // descriptor are generic to the compiler, which would emit flat memory
@@ -73,6 +86,8 @@ struct DomDev {
     T* lor[3][3];              // [0 Eold | 1 W | 2 Wold][component] over the Lorentz box
     int nsrc;
     SrcDev<T> src[kMaxSrc];
+    int nsmp;                  // plane monitors sampled inside the split H kernel
+    SmpDev smp[kMaxSmp];
     // ---- adjoint state (set 0) ----
     int grad;                  // domain takes part in the adjoint
     T* Ea[3];

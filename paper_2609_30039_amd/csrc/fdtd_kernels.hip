@@ -437,9 +437,40 @@ __device__ __forceinline__ void colh_fetch(const DomDev<T>& d, ColH<T>& p, const
     if (cp) psi_load(d, d.psiH, so, true, cx, cy, cpml_at(d, 2, k), i, j, k, p.ps);
 }
 
+// In-kernel sampling (slot >= 0): a thread whose column lies in a plane
+// monitor's rectangle writes, on the monitor plane, E^{n+1} and the new H,
+// and on the plane below (flux) the new Hx, Hy, into the ring slot.
+template <typename T>
+__device__ __forceinline__ void sample_node(const DomDev<T>& d, int slot, int i, int j, int k, T ex, T ey, T ez,
+                                            T hx, T hy, T hz) {
+    for (int q = 0; q < d.nsmp; ++q) {
+        const SmpDev& m = d.smp[q];
+        if (i < m.i0 || i >= m.i1 || j < m.j0 || j >= m.j1) continue;
+        const bool on = k == m.k, below = m.kind == 1 && k + 1 == m.k;
+        if (!on && !below) continue;
+        const long long np = m.npts;
+        FDTD_GLOBAL T* buf = gp((T*)m.ring) + (long long)slot * m.rcomp * np + (j - m.j0) * (m.i1 - m.i0) + (i - m.i0);
+        if (m.kind == 1) {
+            if (on) {
+                buf[0] = ex;
+                buf[np] = ey;
+                buf[2 * np] = hx;
+                buf[4 * np] = hy;
+                if (k == 0) buf[3 * np] = buf[5 * np] = T(0);   // no plane below
+            } else {
+                buf[3 * np] = hx;
+                buf[5 * np] = hy;
+            }
+        } else {
+            const int c = m.comp;
+            buf[0] = c == 0 ? ex : c == 1 ? ey : c == 2 ? ez : c == 3 ? hx : c == 4 ? hy : hz;
+        }
+    }
+}
+
 template <typename T, int W>
 __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               int ndom, int kz, int rs, int ws) {
+                                               int ndom, int kz, int rs, int ws, int slot) {
     const DomDev<T>* dp;
     Col c = column<T, W>(doms, bs, ndom, kz, dp);
     if (!c.ok) return;
@@ -481,9 +512,13 @@ __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ dom
                 Dy1 = st_pref(d.psiH[0][cx.side][1], wo, q, true, cx.bH, cx.cH, cx.kH, ph[5], Dy1);
             }
         }
-        hw[0][f] = fma(-S, Dx0 - Dx1, cu.h[0]);
-        hw[1][f] = fma(-S, Dy0 - Dy1, cu.h[1]);
-        hw[2][f] = fma(-S, Dz0 - Dz1, cu.h[2]);
+        const T hx = fma(-S, Dx0 - Dx1, cu.h[0]);
+        const T hy = fma(-S, Dy0 - Dy1, cu.h[1]);
+        const T hz = fma(-S, Dz0 - Dz1, cu.h[2]);
+        hw[0][f] = hx;
+        hw[1][f] = hy;
+        hw[2][f] = hz;
+        if (slot >= 0) sample_node(d, slot, i, j, k, ex, ey, ez, hx, hy, hz);
         ex = cu.e1[0];
         ey = cu.e1[1];
         ez = cu.e1[2];
@@ -1751,8 +1786,9 @@ __global__ void __launch_bounds__(256) k_adj_bulk(const DomDev<T>* __restrict__ 
 
 // ============================================================ monitors
 // Sample one plane monitor (state set cs) into slot `slot` of its ring buffer
-// [block][ncomp][npts] (E at time n, H at n + 1/2; flux H averaged over
-// planes k and k-1).
+// [block][rcomp][npts] (E at time n, H at n + 1/2; flux: H at planes k and
+// k-1, averaged by the spectrum update).  The split H kernel writes the same
+// layout when it samples in-kernel.
 template <typename T>
 __global__ void k_sample(const DomDev<T>* __restrict__ doms, MonDev m, int cs, int slot) {
     const DomDev<T>& d = doms[m.dom];
@@ -1761,16 +1797,16 @@ __global__ void k_sample(const DomDev<T>* __restrict__ doms, MonDev m, int cs, i
     if (q >= npts) return;
     int i = m.i0 + q % ni, j = m.j0 + q / ni, k = m.k;
     long long f = fidx(d, i, j, k) + cs * d.fs;
-    FDTD_GLOBAL T* buf = gp((T*)m.samples) + (long long)slot * m.ncomp * npts;
+    FDTD_GLOBAL T* buf = gp((T*)m.samples) + (long long)slot * m.rcomp * npts;
     const FDTD_GLOBAL T* Hx = gp(d.H[0]);
     const FDTD_GLOBAL T* Hy = gp(d.H[1]);
     if (m.kind == 1) {
-        T hxm = k > 0 ? Hx[f - d.plane] : T(0);
-        T hym = k > 0 ? Hy[f - d.plane] : T(0);
         buf[q] = gp(d.E[0])[f];
         buf[npts + q] = gp(d.E[1])[f];
-        buf[2 * npts + q] = T(0.5) * (Hx[f] + hxm);
-        buf[3 * npts + q] = T(0.5) * (Hy[f] + hym);
+        buf[2 * npts + q] = Hx[f];
+        buf[3 * npts + q] = k > 0 ? Hx[f - d.plane] : T(0);
+        buf[4 * npts + q] = Hy[f];
+        buf[5 * npts + q] = k > 0 ? Hy[f - d.plane] : T(0);
     } else {
         buf[q] = m.comp < 3 ? gp(d.E[m.comp])[f] : gp(d.H[m.comp - 3])[f];
     }
@@ -1802,9 +1838,13 @@ __global__ void k_dft(MonDev m, int n0, int count, const int* __restrict__ tdev)
     const T* buf = (const T*)m.samples;
     for (int cq = 0; cq < m.ncomp; ++cq) {
         int ish = (m.kind == 1) ? (cq >= 2) : (m.comp >= 3);
+        // ring component(s) of spectrum component cq: flux <Hx>, <Hy> average planes k and k-1
+        const int r0 = (m.kind == 1 && cq >= 2) ? 2 * cq - 2 : cq;
         double re = 0, im = 0;
         for (int s = 0; s < count; ++s) {
-            double x = (double)buf[((long long)s * m.ncomp + cq) * npts + q];
+            const T* b = buf + (long long)s * m.rcomp * npts + q;
+            const T v = (m.kind == 1 && cq >= 2) ? T(0.5) * (b[r0 * npts] + b[(r0 + 1) * npts]) : b[r0 * npts];
+            double x = (double)v;
             re = fma(x, tw[ish][0][s], re);
             im = fma(-x, tw[ish][1][s], im);
         }
@@ -2043,7 +2083,8 @@ __global__ void __launch_bounds__(256) k_fwd_plain_nc(const DomDev<T>* __restric
     }
 
 template <typename T>
-void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev) {
+void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev,
+                int slot) {
     const DomDev<T>* dd = (const DomDev<T>*)doms;
     if (c.kernel == 1) {
         // one launch per pass over all blocks: a second launch for the
@@ -2056,9 +2097,9 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
             hipLaunchKernelGGL((k_fwd_e<T, 64>), dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom,
                                c.kz, rs, ws, t, tdev);
         if (c.sw == 32)
-            hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
+            hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, slot);
         else
-            hipLaunchKernelGGL((k_fwd_h<T, 64>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws);
+            hipLaunchKernelGGL((k_fwd_h<T, 64>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, slot);
         return;
     }
     if (c.nfgen) FDTD_ROWS_SWITCH(k_fwd_fused, c.rows, dim3(c.nfgen), dim3(256), 0, s, dd, c.tfgen, c.kz, rs, ws, t)
@@ -2156,7 +2197,7 @@ int split_blocks(int nx, int ny, int nz, int kz, int w) {
 }
 
 #define FDTD_INSTANTIATE(T)                                                                   \
-    template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, const int*); \
+    template void launch_fwd<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, const int*, int); \
     template void launch_adj<T>(const LaunchCfg&, const void*, int, int, int, hipStream_t, int, const hipStream_t*); \
     template void launch_sample<T>(const void*, const MonDev&, int, int, hipStream_t);        \
     template void launch_dft<T>(const MonDev&, int, int, hipStream_t, const int*);            \

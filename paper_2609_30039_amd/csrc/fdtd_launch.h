@@ -12,10 +12,11 @@ constexpr int kMaxDftBlock = 64;   // buffered time samples per DFT flush
 // One monitor as the kernels see it.
 struct MonDev {
     int dom, kind, comp, ncomp, nf;   // kind 0 probe, 1 flux (Ex, Ey, <Hx>, <Hy>), 2 patch
+    int rcomp;                        // ring components: flux 6 (Ex, Ey, Hx(k), Hx(k-1), Hy(k), Hy(k-1)), else 1
     int i0, i1, j0, j1, k;            // plane rectangle and plane index
     int pi, pj;                       // probe (pi, pj, k)
     const double* omega;              // [nf] omega * dt
-    void* samples;                    // ring buffer [block][ncomp][npts] of the field type
+    void* samples;                    // ring buffer [block][rcomp][npts] of the field type
     double* acc;                      // spectra [nf][ncomp][npts] (re, im)
     double* cot;                      // cotangents, same layout (probe: [max_steps])
     double* trace;                    // probe samples [ntrace]
@@ -58,7 +59,10 @@ constexpr int kFusedWaves = 4;
 
 template <typename T>
 // tdev: when set, kernels add the device-held step index to t (graph replays)
-void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev = nullptr);
+// slot >= 0: the split H kernel also writes every plane monitor's samples of
+// the new state into that ring slot (the fused family ignores it)
+void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hipStream_t s, const int* tdev = nullptr,
+                int slot = -1);
 template <typename T>
 // pass 0: the E-node pass (all of the fused adjoint), 1: the H-node pass of
 // the split family; cs[q]: stream of split class q of that pass

@@ -474,9 +474,27 @@ struct Handle : Base {
                     md.ntrace = std::max(1, opt.max_steps);
                     M.take(md.cot, std::max(1, opt.max_steps) * 8);
                 } else {
-                    M.take(md.samples, (size_t)dft_block * md.ncomp * mh.npts * ts);
+                    M.take(md.samples, (size_t)dft_block * md.rcomp * mh.npts * ts);
                     M.take(md.acc, mh.acc_elems * 8);
                     M.take(md.cot, mh.acc_elems * 8);
+                }
+            }
+            if (asg) {   // plane monitors as the split H kernel samples them
+                d.nsmp = 0;
+                for (auto& mh : h.mons) {
+                    const MonDev& md = mh.dev;
+                    if (md.kind == 0) continue;
+                    SmpDev& sm = d.smp[d.nsmp++];
+                    sm.kind = md.kind;
+                    sm.comp = md.comp;
+                    sm.i0 = md.i0;
+                    sm.i1 = md.i1;
+                    sm.j0 = md.j0;
+                    sm.j1 = md.j1;
+                    sm.k = md.k;
+                    sm.npts = mh.npts;
+                    sm.rcomp = md.rcomp;
+                    sm.ring = md.samples;
                 }
             }
         }
@@ -823,6 +841,7 @@ struct Handle : Base {
             if (md.n_freq < 1 || md.n_freq > 4096 || !md.omega_dt) return fail(FDTD_E_INVALID, "monitor frequencies");
             m.nf = md.n_freq;
             m.ncomp = md.kind == FDTD_MON_FLUX_Z ? 4 : 1;
+            m.rcomp = md.kind == FDTD_MON_FLUX_Z ? 6 : 1;
             mh.npts = (m.i1 - m.i0) * (m.j1 - m.j0);
             mh.omega.assign(md.omega_dt, md.omega_dt + md.n_freq);
         }
@@ -841,7 +860,24 @@ struct Handle : Base {
         mh.pending = 0;
     }
 
-    void record() {
+    // Ring slot in which the split H kernel can sample every plane monitor
+    // during the next step: all plane monitors must be at the same slot (a
+    // monitor reset puts one back to 0).  -1: sample with k_sample.
+    int insample_slot() const {
+        if (cfg.kernel != 1) return -1;
+        int slot = -1;
+        for (auto& h : dh)
+            for (auto& mh : h.mons) {
+                if (mh.dev.kind == 0) continue;
+                if (slot >= 0 && mh.pending != slot) return -1;
+                slot = mh.pending;
+            }
+        return slot;
+    }
+
+    // After a recorded step: probes, and the plane monitors' slot bookkeeping
+    // (their samples were written by the H kernel when sampled is set).
+    void record(bool sampled) {
         int n = t;   // the current set holds E^n, H^{n+1/2}
         for (auto& h : dh)
             for (auto& mh : h.mons) {
@@ -850,7 +886,7 @@ struct Handle : Base {
                     continue;
                 }
                 if (mh.pending == 0) mh.n0 = n;
-                launch_sample<T>(d_doms, mh.dev, cur, mh.pending, st);
+                if (!sampled) launch_sample<T>(d_doms, mh.dev, cur, mh.pending, st);
                 if (++mh.pending == dft_block) flush(mh);
             }
     }
@@ -890,14 +926,13 @@ struct Handle : Base {
             return fail(FDTD_E_DEVICE, "capture stream");
         if (hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(FDTD_E_DEVICE, "hipStreamBeginCapture failed");
+        // recording chunks start with every ring empty: step s samples into slot s
         for (int s = 0; s < G; ++s) {
-            launch_fwd<T>(cfg, d_doms, cur, cur, s, cst, d_tstep);
+            launch_fwd<T>(cfg, d_doms, cur, cur, s, cst, d_tstep, rec ? s : -1);
             if (!rec) continue;
             for (auto& h : dh)
-                for (auto& mh : h.mons) {
+                for (auto& mh : h.mons)
                     if (mh.dev.kind == 0) launch_probe<T>(d_doms, mh.dev, cur, s, cst, d_tstep);
-                    else launch_sample<T>(d_doms, mh.dev, cur, s, cst);
-                }
         }
         if (rec)
             for (auto& h : dh)
@@ -938,12 +973,13 @@ struct Handle : Base {
                 continue;
             }
             int ws = inplace && working ? cur : write_set();
+            const int slot = rec ? insample_slot() : -1;
             if (timing_on) ev_mark();
-            launch_fwd<T>(cfg, d_doms, cur, ws, t, st);
+            launch_fwd<T>(cfg, d_doms, cur, ws, t, st, nullptr, slot);
             if (timing_on) ev_mark();
             cur = ws;
             ++t;
-            if (rec) record();
+            if (rec) record(slot >= 0);
             ++s;
         }
         return check("step_forward");

@@ -267,6 +267,24 @@ def test_graph_chunks_equal_eager_steps(dtype):
     same("after reset")
 
 
+def test_monitor_reset_mid_block_matches_fused():
+    """The split H kernel samples the plane monitors itself while they all sit
+    at the same ring slot; after one monitor is reset mid-block the slots
+    differ and the separate sampling kernel takes over.  Spectra of both
+    monitors must equal the fused family's (which always samples separately)
+    bitwise, before and after the reset."""
+    spec = _case(n_steps=90)
+    out = {}
+    for kern in ("split", "fused"):
+        sim = Simulation(spec, dtype="f32", kernel=kern, dft_block=16)
+        sim.step(21)
+        sim.reset_monitor(1)
+        sim.step(30)
+        out[kern] = [sim.spectra(mi) for mi in range(len(spec.monitors))]
+    for a, b in zip(out["split"], out["fused"]):
+        assert np.array_equal(a, b)
+
+
 def test_split_block_classes_at_slab_edges():
     """Absorber depth 8 with 4-row blocks and 4-plane chunks puts block edges
     exactly on slab faces, so blocks whose neighbour one step back or forward
