@@ -37,10 +37,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_hash):
+def traffic_from_profiles(kernel_hash, name="fwd_lorentz_flux_f32_pmc.json"):
     """HBM bytes per launch of the dominant kernel from committed PMC summaries,
     only if they were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "fwd_lorentz_flux_f32_pmc.json")
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -358,13 +358,16 @@ def main():
         log(f"anisotropic_lorentz forward: {spec5.shape} x 200 steps, launch shape {tile5}")
         sim5, el5, kms5, nl5 = run_forward(spec5, "f32", stream, 1, 1, tile5)
         b5 = RL.forward_bytes(spec5, 4)
+        t5 = traffic_from_profiles(khash, "fwd_anisotropic_lorentz_f32_pmc.json")
         out["large_forward"] = {
             "workload": "536^3 (512^3 + 12-cell CPML), diagonal eps, 128^3 Lorentz box, Ex sheet, Ex patch "
                         "monitor, 200 steps FP32",
             "mcups": round(spec5.ncells * 200 / el5 / 1e6, 1),
             "avg_launch_us": round(kms5 / nl5 * 1e3, 1),
             "achieved_GBs": round(b5 / (kms5 / nl5 * 1e-3) / 1e9, 1),
-            "frac_hbm": round(b5 / (kms5 / nl5 * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4), "launch_shape": tile5}
+            "frac_hbm": round(b5 / (kms5 / nl5 * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4),
+            "traffic_GBs": None if t5 is None else round(t5 / (kms5 / nl5 * 1e-3) / 1e9, 1),
+            "launch_shape": tile5}
         del sim5
 
     print(json.dumps(out), flush=True)
