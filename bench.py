@@ -37,9 +37,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_hash, name="fwd_lorentz_flux_f32_pmc.json"):
-    """HBM bytes per launch of the dominant kernel from committed PMC summaries,
-    only if they were taken on the current kernel source."""
+def traffic_from_profiles(kernel_hash, tile, name="fwd_lorentz_flux_f32_pmc.json"):
+    """HBM bytes per step of the stepping kernels from a committed PMC summary,
+    only if it was taken on the current kernel source and the launch shape
+    that was timed."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
@@ -47,7 +48,9 @@ def traffic_from_profiles(kernel_hash, name="fwd_lorentz_flux_f32_pmc.json"):
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    key = f"{tile.get('kernel')},{tile.get('tile_rows', 0)},{tile.get('tile_kz', 0)}"
+    e = d.get("per_launch_shape", {}).get(key)
+    return None if e is None else e.get("hbm_bytes_per_launch")
 
 
 def run_forward(spec, dtype, stream, K, Wm, tile=None, graph_chunk=32):
@@ -184,7 +187,7 @@ def main():
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     log(f"lorentz_flux FP32: {el / K * 1e3:.2f} ms/solve, {mcups:.0f} Mcell-upd/s, kernel {avg_ms * 1e3:.1f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic")
-    traffic = traffic_from_profiles(khash)
+    traffic = traffic_from_profiles(khash, tile)
     out = {
         "metric": "Mcell-updates/s fwd & adjoint (FP32 vs FP64), % HBM roofline, grad rel. err",
         "value": round(mcups, 1),
@@ -253,6 +256,20 @@ def main():
             f32e[W.COMP_NAMES[q]] = float(f"{np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300):.3e}")
         fl32, fl64 = sim32.flux(0), sim64.flux(0)
         f32e["flux_max_rel"] = float(f"{np.max(np.abs(fl32 - fl64) / np.abs(fl64)):.3e}")
+        # By step 1000 most of the pulse has left through the absorbers, so the
+        # figures above are relative to late-time residual fields.  Diagnostic:
+        # the same differences over each field's largest norm in time (FP64 run
+        # sampled every 50 steps).
+        tsim = Simulation(spec, dtype="f64", stream=stream, **tile64)
+        peak = np.zeros(6)
+        for _ in range(spec.n_steps // 50):
+            tsim.step(50, record=False)
+            for q in range(6):
+                peak[q] = max(peak[q], float(np.linalg.norm(tsim.field(q))))
+        tsim.close()
+        f32e["rel_to_time_max_norm"] = {
+            W.COMP_NAMES[q]: float(f"{np.linalg.norm(sim32.field(q).astype(np.float64) - sim64.field(q)) / max(peak[q], 1e-300):.3e}")
+            for q in range(6)}
         out["fp32_vs_fp64_gpu_at_1000"] = f32e
         del sim64
 
@@ -358,7 +375,7 @@ def main():
         log(f"anisotropic_lorentz forward: {spec5.shape} x 200 steps, launch shape {tile5}")
         sim5, el5, kms5, nl5 = run_forward(spec5, "f32", stream, 1, 1, tile5)
         b5 = RL.forward_bytes(spec5, 4)
-        t5 = traffic_from_profiles(khash, "fwd_anisotropic_lorentz_f32_pmc.json")
+        t5 = traffic_from_profiles(khash, tile5, "fwd_anisotropic_lorentz_f32_pmc.json")
         out["large_forward"] = {
             "workload": "536^3 (512^3 + 12-cell CPML), diagonal eps, 128^3 Lorentz box, Ex sheet, Ex patch "
                         "monitor, 200 steps FP32",
