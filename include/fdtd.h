@@ -167,7 +167,9 @@ int fdtd_step_adjoint(fdtd_t h, int32_t n_steps);
 
 /* Copy the full forward state u^n (fields, absorber memories, Lorentz
    history) and n into slot (Section 3.2).  BF16 storage scales each array by
-   its max-abs value. */
+   its max-abs value and rounds to nearest even; an array whose max-abs value
+   is below the smallest normal float is stored as zeros.  FP32/FP64 slots
+   swap buffers with the working set, so a save copies nothing. */
 int fdtd_checkpoint_save(fdtd_t h, int32_t slot);
 
 /* Make the slot's state current: u := slot, forward step := slot's n.
