@@ -1,0 +1,145 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch shapes
+the autotuner picks there (split kernels, 8-row blocks, z chunks of 2, 4 or
+8 planes) and with captured step chunks where the benchmark uses them.
+
+The oracle is too slow for whole full-size runs, so these tests take few steps
+from a seeded random state in all six fields: every node then carries data,
+every absorber memory and Lorentz history becomes nonzero after the first
+step, and each output is compared element by element with the oracle started
+from the same state.  The adjoint is checked at full size through a property
+that holds at any size: the dot-product identity <A x, y> = <x, A^T y> for the
+linear step A (sources removed) and random x, y.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_30039_amd import workloads as W
+from paper_2609_30039_amd.sim import Simulation
+from tests.gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_fields(shape, seed):
+    """Six seeded N(0,1) fields [nz][ny][nx]; E_c is zero where the index along
+    c+1 or c+2 is 0 (the PEC nodes, which are not degrees of freedom)."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    k, j, i = np.ogrid[:nz, :ny, :nx]
+    idx = (i, j, k)
+    out = []
+    for q in range(6):
+        f = rng.standard_normal((nz, ny, nx))
+        if q < 3:
+            f[np.broadcast_to((idx[(q + 1) % 3] == 0) | (idx[(q + 2) % 3] == 0), f.shape)] = 0.0
+        out.append(f)
+    return out
+
+
+def _start(spec, fields, dtype, **kw):
+    sim = Simulation(spec, dtype=dtype, **kw)
+    for q in range(6):
+        sim.set_field(q, fields[q])
+    return sim
+
+
+def _oracle(spec, fields, n, record):
+    o = O.OracleSim(spec)
+    for q in range(6):
+        o.field(q)[...] = fields[q]
+    o.step(n, record=record)
+    return o
+
+
+@pytest.fixture(scope="module")
+def flux148():
+    spec = W.lorentz_flux()
+    fields = _random_fields(spec.shape, 7001)
+    o = _oracle(spec, fields, 64, True)
+    return spec, fields, o
+
+
+@pytest.mark.parametrize("shape", [(8, 2), (8, 4), (8, 8)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_headline_148_fields_and_spectra(flux148, shape, dtype, tol):
+    """148^3 + Lorentz box + sheet source + 16-frequency flux plane, 64 steps in
+    two captured chunks of 32: six fields and the flux spectra."""
+    spec, fields, o = flux148
+    sim = _start(spec, fields, dtype, kernel="split", tile_rows=shape[0], tile_kz=shape[1], graph_chunk=32)
+    sim.step(64, record=True)
+    for q in range(6):
+        r = rel(sim.field(q), o.field(q))
+        assert r < tol, (W.COMP_NAMES[q], r)
+    assert rel(sim.spectra(0), o.spectra(0)) < tol
+    sim.close()
+
+
+def test_anisotropic_536_fields():
+    """536^3 (512^3 + 12-cell CPML, diagonal eps, 128^3 Lorentz box), 3 steps
+    from a random state, FP64 and FP32 at the tuned shape, every node."""
+    spec = W.anisotropic_lorentz()
+    fields = _random_fields(spec.shape, 7002)
+    o = _oracle(spec, fields, 3, False)
+    for dtype, tol in (("f64", 1e-12), ("f32", 3e-6)):
+        sim = _start(spec, fields, dtype, kernel="split", tile_rows=8, tile_kz=2)
+        sim.step(3, record=False)
+        for q in range(6):
+            r = rel(sim.field(q), o.field(q))
+            assert r < tol, (dtype, W.COMP_NAMES[q], r)
+        sim.close()
+        del sim
+    del o
+
+
+def _inner(a, b):
+    return sum(float(np.dot(a[q].ravel().astype(np.float64), b[q].ravel().astype(np.float64))) for q in range(6))
+
+
+def _norm(a):
+    return np.sqrt(sum(float(np.sum(np.square(a[q].astype(np.float64)))) for q in range(6)))
+
+
+@pytest.mark.parametrize("shape", [(8, 4), (8, 8)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-5)])
+def test_design_patch_212_adjoint_dot_product(shape, dtype, tol):
+    """212^3 + CPML with the 64^3 random-eps design box, gradient box on: one
+    adjoint step (every tile class of both passes) is the transpose of one
+    forward step, <A x, y> = <x, A^T y>, relative to |A x| |y|."""
+    spec, _ = W.design_patch()
+    spec.sources = []
+    x = _random_fields(spec.shape, 7003)
+    y = _random_fields(spec.shape, 7004)
+    sim = _start(spec, x, dtype, kernel="split", tile_rows=shape[0], tile_kz=shape[1], n_ckpt=1)
+    sim.save(0)
+    sim.step(1, record=False)
+    ax = [sim.field(q) for q in range(6)]
+    sim.restore(0)
+    sim.adjoint_begin(1)
+    for q in range(6):
+        sim.set_field(q, y[q], adjoint=True)
+    sim.step_adjoint(1)
+    aty = [sim.field(q, adjoint=True) for q in range(6)]
+    lhs, rhs = _inner(ax, y), _inner(x, aty)
+    scale = _norm(ax) * _norm(y)
+    assert abs(lhs - rhs) <= tol * scale, (lhs, rhs, scale)
+    sim.close()
+
+
+def test_batch_48_domains_sampled():
+    """The 48 ragged domains in one launch (tuned shape, captured chunks),
+    32 steps from rest: the smallest, the largest and a middle domain against
+    the oracle, fields and flux spectra."""
+    specs = W.batch_domains()
+    cells = [s.ncells for s in specs]
+    pick = sorted({int(np.argmin(cells)), int(np.argmax(cells)), len(specs) // 2})
+    sim = Simulation(specs, dtype="f64", kernel="split", tile_rows=8, tile_kz=2, graph_chunk=32)
+    sim.step(32, record=True)
+    for d in pick:
+        o = O.OracleSim(specs[d])
+        o.step(32, record=True)
+        for q in range(6):
+            r = rel(sim.field(q, domain=d), o.field(q))
+            assert r < 1e-12, (d, W.COMP_NAMES[q], r)
+        assert rel(sim.spectra(0, domain=d), o.spectra(0)) < 1e-12
+    sim.close()
