@@ -974,8 +974,9 @@ __device__ __forceinline__ void adj_et_tile(const DomDev<T>* __restrict__ doms, 
 }
 
 // One launch per adjoint pass over every tile class: the class of a tile
-// selects the variant.  The host orders the table with the slab classes
-// first, so their slower waves start early and overlap the interior ones.
+// selects the variant.  The host lays the table out so that the tiles each
+// XCD receives form a contiguous spatial run of balanced cost (tiles of value
+// (domain, xlen 0) are padding and return at once).
 // The general class (Lorentz cells, gradient cells in a slab; rare) has a
 // launch of its own, which keeps its registers out of the others.  Both
 // passes are held to 4 waves per SIMD (128 VGPRs, a few spills in the slab

@@ -367,14 +367,61 @@ struct Handle : Base {
                 }
             }
         }
-        // one table per pass, slab classes first (they start early and overlap
-        // the interior tiles)
-        static const int order1[kAdjClasses1] = {5, 2, 4, 3, 6, 1, 0};
-        static const int order2[kAdjClasses2] = {4, 3, 2, 5, 1, 0};
+        // One table per pass.  The general classes of the E-node pass lead (a
+        // launch of their own).  Every other tile goes, in spatial order
+        // (domain, z chunk, 16-row band, x, y), to one of the 8 XCDs: the
+        // order is cut into 8 contiguous runs of equal estimated cost (slab
+        // tiles count 2.5 times an interior tile), and the runs are
+        // interleaved so that workgroup b, which the dispatcher sends to XCD
+        // b % 8, takes the next tile of run b % 8 (short runs are padded with
+        // empty tiles).  Tiles that share cache lines (a narrow tile and its x
+        // neighbour cover the two halves of a 128 B line) and halo rows and
+        // planes then run on one XCD, close in time, sharing its L2, and no
+        // XCD is left with the slab-heavy ends of the domain alone.
+        auto xcd_runs = [&](std::vector<int4>& v) {
+            std::stable_sort(v.begin(), v.end(), [](const int4& a, const int4& b) {
+                const long long ka[5] = {a.x & 0xFFFFFF, a.w, a.z >> 4, a.y & 0xFFFFFF, a.z};
+                const long long kb[5] = {b.x & 0xFFFFFF, b.w, b.z >> 4, b.y & 0xFFFFFF, b.z};
+                return std::lexicographical_compare(ka, ka + 5, kb, kb + 5);
+            });
+            constexpr int X = 8;
+            std::vector<double> cost(v.size());
+            double total = 0;
+            for (size_t t = 0; t < v.size(); ++t) {
+                const int4 e = v[t];
+                const fdtd_domain_desc& s = dh[e.x & 0xFFFFFF].desc;
+                const int cls = e.x >> 24, rows = cls < 3 ? 8 : 16;   // classes 0-2: 32 x 8 tiles, others 16 x 16
+                const double cells = (double)(e.y >> 24) * std::min(rows, s.n[1] - e.z) * std::min(kz, s.n[2] - e.w);
+                cost[t] = cells * (cls == 0 ? 1.0 : 2.5);
+                total += cost[t];
+            }
+            std::vector<int4> run[X];
+            double acc = 0;
+            for (size_t t = 0; t < v.size(); ++t) {
+                const int x = std::min(X - 1, (int)((acc + 0.5 * cost[t]) / std::max(total, 1e-30) * X));
+                run[x].push_back(v[t]);
+                acc += cost[t];
+            }
+            size_t len = 0;
+            for (auto& r : run) len = std::max(len, r.size());
+            std::vector<int4> out(len * X);
+            for (size_t m = 0; m < len; ++m)
+                for (int x = 0; x < X; ++x)
+                    out[m * X + x] = m < run[x].size() ? run[x][m]
+                                                       : make_int4(v.empty() ? 0 : (v[0].x & 0xFFFFFF), 0, 0, 0);
+            v.swap(out);
+        };
         atab1.clear();
         atab2.clear();
-        for (int c : order1) atab1.insert(atab1.end(), atiles[c].begin(), atiles[c].end());
-        for (int c : order2) atab2.insert(atab2.end(), atiles[kAdjClasses1 + c].begin(), atiles[kAdjClasses1 + c].end());
+        for (int c : {5, 2}) atab1.insert(atab1.end(), atiles[c].begin(), atiles[c].end());
+        std::vector<int4> rest;
+        for (int c : {0, 1, 3, 4, 6}) rest.insert(rest.end(), atiles[c].begin(), atiles[c].end());
+        xcd_runs(rest);
+        atab1.insert(atab1.end(), rest.begin(), rest.end());
+        for (int c = 0; c < kAdjClasses2; ++c)
+            atab2.insert(atab2.end(), atiles[kAdjClasses1 + c].begin(), atiles[kAdjClasses1 + c].end());
+        xcd_runs(atab2);
+        static_assert(kAdjClasses1 == 7, "the general classes 2 and 5 lead the E-node table");
         cfg.na1 = (int)atab1.size();
         cfg.na1g = (int)(atiles[5].size() + atiles[2].size());   // order1 starts with the general classes
         cfg.na2 = (int)atab2.size();
