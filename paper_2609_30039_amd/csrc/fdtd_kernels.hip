@@ -50,13 +50,23 @@ struct Col {
 };
 
 // split kernels: 256 threads = W (x) by 256 / W (y) columns, z chunk of length
-// kz; braw / nb: the block among nb column blocks (blockIdx.x when negative)
+// kz.  Column blocks are numbered domain by domain, x fastest, then rows,
+// then z chunks; xr[0..7] / xr[8..15] are the start and length of the run of
+// them that XCD x takes (the dispatcher sends workgroup b to XCD b % 8), cut
+// by the host into runs of equal estimated cost.  braw: the workgroup among
+// the column blocks (blockIdx.x when negative); beyond its run's end it idles.
 template <typename T, int W>
 __device__ __forceinline__ Col column(const DomDev<T>* doms, const int* bs, int ndom, int kz, const DomDev<T>*& dp,
-                                      int braw = -1, int nb = 0) {
+                                      const int* __restrict__ xr, int braw = -1) {
     constexpr int NR = 256 / W;
     Col c;
-    int b = braw < 0 ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(braw, nb);
+    const int raw = braw < 0 ? (int)blockIdx.x : braw, xcd = raw & 7, m = raw >> 3;
+    if (m >= xr[8 + xcd]) {
+        dp = doms;
+        c.ok = false;
+        return c;
+    }
+    int b = xr[xcd] + m;
     int dom = find_domain(bs, ndom, b);
     dp = doms + dom;
     const DomDev<T>& d = *dp;
@@ -327,14 +337,14 @@ __device__ __forceinline__ void e_lor_block(const DomDev<T>* __restrict__ doms, 
 // columns.
 template <typename T, int W>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               const int* __restrict__ lbs, int nlb, int ndom, int kz, int rs, int ws,
-                                               int t, const int* __restrict__ tdev) {
+                                               const int* __restrict__ xr, const int* __restrict__ lbs, int nlb,
+                                               int ndom, int kz, int rs, int ws, int t, const int* __restrict__ tdev) {
     if ((int)blockIdx.x < nlb) {
         e_lor_block(doms, lbs, ndom, xcd_remap(blockIdx.x, nlb), rs, ws, t, tdev);
         return;
     }
     const DomDev<T>* dp;
-    Col c = column<T, W>(doms, bs, ndom, kz, dp, (int)blockIdx.x - nlb, (int)gridDim.x - nlb);
+    Col c = column<T, W>(doms, bs, ndom, kz, dp, xr, (int)blockIdx.x - nlb);
     if (!c.ok) return;
     if (tdev) t += *tdev;   // graph replays: step index held on the device
     const DomDev<T>& d = *dp;
@@ -470,9 +480,9 @@ __device__ __forceinline__ void sample_node(const DomDev<T>& d, int slot, int i,
 
 template <typename T, int W>
 __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               int ndom, int kz, int rs, int ws, int slot) {
+                                               const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int slot) {
     const DomDev<T>* dp;
-    Col c = column<T, W>(doms, bs, ndom, kz, dp);
+    Col c = column<T, W>(doms, bs, ndom, kz, dp, xr);
     if (!c.ok) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
@@ -2092,15 +2102,17 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
         // interior blocks costs more in its drain than its leaner registers win
         const int nlb = (c.nlor + 7) / 8 * 8;
         if (c.sw == 32)
-            hipLaunchKernelGGL((k_fwd_e<T, 32>), dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom,
-                               c.kz, rs, ws, t, tdev);
+            hipLaunchKernelGGL((k_fwd_e<T, 32>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, nlb,
+                               c.ndom, c.kz, rs, ws, t, tdev);
         else
-            hipLaunchKernelGGL((k_fwd_e<T, 64>), dim3(nlb + c.nblk), dim3(256), 0, s, dd, c.bs, c.lbs, nlb, c.ndom,
-                               c.kz, rs, ws, t, tdev);
+            hipLaunchKernelGGL((k_fwd_e<T, 64>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, nlb,
+                               c.ndom, c.kz, rs, ws, t, tdev);
         if (c.sw == 32)
-            hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, slot);
+            hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz, rs, ws,
+                               slot);
         else
-            hipLaunchKernelGGL((k_fwd_h<T, 64>), dim3(c.nblk), dim3(256), 0, s, dd, c.bs, c.ndom, c.kz, rs, ws, slot);
+            hipLaunchKernelGGL((k_fwd_h<T, 64>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz, rs, ws,
+                               slot);
         return;
     }
     if (c.nfgen) FDTD_ROWS_SWITCH(k_fwd_fused, c.rows, dim3(c.nfgen), dim3(256), 0, s, dd, c.tfgen, c.kz, rs, ws, t)

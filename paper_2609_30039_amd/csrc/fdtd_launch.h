@@ -33,6 +33,8 @@ struct LaunchCfg {
     int kernel, rows, kz, nblk, ndom;
     int sw;                    // split forward: block width in columns (64 or 32; 256 / sw rows)
     const int* bs;             // split blocks per domain (prefix sums)
+    const int* xr;             // split: per-XCD runs of column blocks, 8 starts then 8 lengths
+    int ngrid;                 // split: column workgroups per launch (8 x the longest run)
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
     // split adjoint: one tile table per pass, (domain | class << 24,

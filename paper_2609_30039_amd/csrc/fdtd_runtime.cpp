@@ -221,7 +221,7 @@ struct Handle : Base {
     // kz planes, listed as bulk when they lie inside the domain away from
     // PEC nodes, absorbers, the Lorentz box and sources, general otherwise.
     void build_tiles() {
-        bs_host.assign(2 * (ndom + 1), 0);
+        bs_host.assign(2 * (ndom + 1) + 16, 0);   // [bs][lbs][per-XCD run starts, lengths]
         int* lbs = bs_host.data() + ndom + 1;
         tiles_gen.clear();
         tiles_bulk.clear();
@@ -282,6 +282,7 @@ struct Handle : Base {
         }
         cfg.nblk = bs_host[ndom];
         cfg.nlor = lbs[ndom];
+        if (cfg.kernel == 1) split_runs();
         build_adjoint_tiles();
         cfg.ngen = (int)tiles_gen.size();
         cfg.nbulk = (int)tiles_bulk.size();
@@ -427,6 +428,53 @@ struct Handle : Base {
         cfg.na2 = (int)atab2.size();
     }
 
+    // Split column blocks in their numbering (domain by domain, x fastest, then
+    // rows, then z chunks) cut into 8 contiguous runs of equal estimated cost,
+    // one per XCD: a block meeting an absorbing slab counts twice its cells
+    // (it also moves the memories).  Contiguous runs keep neighbouring
+    // columns and planes on one L2; equal cost keeps the XCDs holding the
+    // slab-heavy ends of the domain from finishing last.
+    void split_runs() {
+        const int W = cfg.sw, NR = 256 / W, kz = cfg.kz, nb = cfg.nblk;
+        std::vector<double> cost(nb);
+        double total = 0;
+        int b = 0;
+        for (int q = 0; q < ndom; ++q) {
+            const fdtd_domain_desc& s = dh[q].desc;
+            const int nbx = (s.n[0] + W - 1) / W, nby = (s.n[1] + NR - 1) / NR, nbz = (s.n[2] + kz - 1) / kz;
+            for (int bz = 0; bz < nbz; ++bz)
+                for (int by = 0; by < nby; ++by)
+                    for (int bx = 0; bx < nbx; ++bx, ++b) {
+                        const int lo[3] = {bx * W, by * NR, bz * kz};
+                        const int hi[3] = {std::min(lo[0] + W, s.n[0]) - 1, std::min(lo[1] + NR, s.n[1]) - 1,
+                                           std::min(lo[2] + kz, s.n[2]) - 1};
+                        bool cp = false;
+                        for (int a = 0; a < 3; ++a)
+                            if (lo[a] < s.pml[2 * a] || hi[a] >= s.n[a] - s.pml[2 * a + 1]) cp = true;
+                        const double cells = (double)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+                        cost[b] = cells * (cp ? 2.0 : 1.0);
+                        total += cost[b];
+                    }
+        }
+        int* xs = bs_host.data() + 2 * (ndom + 1);
+        int* xl = xs + 8;
+        for (int x = 0; x < 8; ++x) xs[x] = xl[x] = 0;
+        double acc = 0;
+        int prev = -1;
+        for (int t = 0; t < nb; ++t) {
+            const int x = std::min(7, (int)((acc + 0.5 * cost[t]) / std::max(total, 1e-30) * 8));
+            if (x != prev) {
+                xs[x] = t;
+                prev = x;
+            }
+            xl[x]++;
+            acc += cost[t];
+        }
+        int len = 0;
+        for (int x = 0; x < 8; ++x) len = std::max(len, xl[x]);
+        cfg.ngrid = 8 * len;
+    }
+
     // ------------------------------------------------------------ layout
     // Places every array in its arena.  Forward state arrays of all domains form
     // one set (stride fstride), adjoint arrays one adjoint set (astride).
@@ -546,7 +594,7 @@ struct Handle : Base {
             }
         }
         M.take(d_doms, sizeof(DomDev<T>) * ndom);
-        M.take(d_bs, sizeof(int) * 2 * (ndom + 1));
+        M.take(d_bs, sizeof(int) * (2 * (ndom + 1) + 16));
         M.take(d_tstep, sizeof(int));
         M.take(d_atiles, sizeof(int4) * std::max<size_t>(1, atab1.size() + atab2.size()));
         M.take(d_tiles, sizeof(int4) * std::max<size_t>(1, tiles_gen.size() + tiles_bulk.size() + tiles_fgen.size() +
@@ -639,6 +687,7 @@ struct Handle : Base {
         cur = 0;
         cfg.bs = d_bs;
         cfg.lbs = d_bs + ndom + 1;
+        cfg.xr = d_bs + 2 * (ndom + 1);
         cfg.tgen = d_tiles;
         cfg.tbulk = cfg.tgen + tiles_gen.size();
         cfg.tfgen = cfg.tbulk + tiles_bulk.size();
@@ -678,7 +727,8 @@ struct Handle : Base {
             }
         }
         if (hipMemcpyAsync(d_doms, dd.data(), sizeof(DomDev<T>) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(d_bs, bs_host.data(), sizeof(int) * 2 * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+            hipMemcpyAsync(d_bs, bs_host.data(), sizeof(int) * (2 * (n + 1) + 16), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
             return fail(FDTD_E_DEVICE, "upload descriptors failed");
         {
             std::vector<int4> all(tiles_gen);
