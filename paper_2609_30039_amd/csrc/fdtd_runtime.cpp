@@ -372,7 +372,7 @@ struct Handle : Base {
         // launch of their own).  Every other tile goes, in spatial order
         // (domain, z chunk, 16-row band, x, y), to one of the 8 XCDs: the
         // order is cut into 8 contiguous runs of equal estimated cost (slab
-        // tiles count 2.5 times an interior tile), and the runs are
+        // tiles count 1.75 times an interior tile), and the runs are
         // interleaved so that workgroup b, which the dispatcher sends to XCD
         // b % 8, takes the next tile of run b % 8 (short runs are padded with
         // empty tiles).  Tiles that share cache lines (a narrow tile and its x
@@ -393,7 +393,7 @@ struct Handle : Base {
                 const fdtd_domain_desc& s = dh[e.x & 0xFFFFFF].desc;
                 const int cls = e.x >> 24, rows = cls < 3 ? 8 : 16;   // classes 0-2: 32 x 8 tiles, others 16 x 16
                 const double cells = (double)(e.y >> 24) * std::min(rows, s.n[1] - e.z) * std::min(kz, s.n[2] - e.w);
-                cost[t] = cells * (cls == 0 ? 1.0 : 2.5);
+                cost[t] = cells * (cls == 0 ? 1.0 : 1.75);
                 total += cost[t];
             }
             std::vector<int4> run[X];
