@@ -24,6 +24,7 @@ CANDIDATES = [
     {"kernel": "split", "tile_rows": 0, "tile_kz": 8},
     {"kernel": "split", "tile_rows": 0, "tile_kz": 16},
     {"kernel": "split", "tile_rows": 8, "tile_kz": 2},
+    {"kernel": "split", "tile_rows": 8, "tile_kz": 3},
     {"kernel": "split", "tile_rows": 8, "tile_kz": 4},
     {"kernel": "split", "tile_rows": 8, "tile_kz": 8},
     {"kernel": "fused", "tile_rows": 2, "tile_kz": 8},
@@ -100,7 +101,9 @@ def tune(specs, dtype: str = "f32", adjoint: bool = False, steps: int = 6, strea
     """Best launch shape {kernel, tile_rows, tile_kz} for this workload."""
     if not isinstance(specs, (list, tuple)):
         specs = [specs]
-    key = signature(specs, dtype, adjoint)
+    cands = candidates or CANDIDATES
+    # the key also names the candidate list, so a changed list is measured afresh
+    key = signature(specs, dtype, adjoint) + "|" + hashlib.sha256(repr(cands).encode()).hexdigest()[:8]
     path = _cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -112,7 +115,7 @@ def tune(specs, dtype: str = "f32", adjoint: bool = False, steps: int = 6, strea
     if use_cache and key in cache:
         return dict(cache[key]["best"])
     results = []
-    for cand in (candidates or CANDIDATES):
+    for cand in cands:
         ms = _time(specs, dtype, cand, steps, adjoint, stream, min_ms)
         results.append((ms, cand))
         if log:

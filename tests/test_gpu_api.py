@@ -53,3 +53,6 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     # a second call is served from the cache (the recorded timings are kept)
     assert AT.tune(spec, "f32", candidates=cands, min_ms=2.0) == best
     assert json.loads(cache.read_text()) == stored
+    # a different candidate list is measured afresh under its own key
+    assert AT.tune(spec, "f32", candidates=cands[:1], min_ms=2.0) == cands[0]
+    assert len(json.loads(cache.read_text())) == 2

@@ -1,6 +1,6 @@
 """Parity at the full sizes of the benchmark workloads, in the launch shapes
-the autotuner picks there (split kernels, 8-row blocks, z chunks of 2, 4 or
-8 planes) and with captured step chunks where the benchmark uses them.
+the autotuner picks there (split kernels, 8-row blocks, z chunks of 2, 3, 4
+or 8 planes) and with captured step chunks where the benchmark uses them.
 
 The oracle is too slow for whole full-size runs, so these tests take few steps
 from a seeded random state in all six fields: every node then carries data,
@@ -60,7 +60,7 @@ def flux148():
     return spec, fields, o
 
 
-@pytest.mark.parametrize("shape", [(8, 2), (8, 4), (8, 8)])
+@pytest.mark.parametrize("shape", [(8, 2), (8, 3), (8, 4), (8, 8)])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 2e-5)])
 def test_headline_148_fields_and_spectra(flux148, shape, dtype, tol):
     """148^3 + Lorentz box + sheet source + 16-frequency flux plane, 64 steps in
@@ -100,7 +100,7 @@ def _norm(a):
     return np.sqrt(sum(float(np.sum(np.square(a[q].astype(np.float64)))) for q in range(6)))
 
 
-@pytest.mark.parametrize("shape", [(8, 4), (8, 8)])
+@pytest.mark.parametrize("shape", [(8, 2), (8, 3), (8, 8)])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-5)])
 def test_design_patch_212_adjoint_dot_product(shape, dtype, tol):
     """212^3 + CPML with the 64^3 random-eps design box, gradient box on: one
