@@ -58,7 +58,10 @@ def _cot(mi, m, sp):
     return 2.0 * np.asarray(sp)          # probe: J = sum of squared samples
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-4)])
+# Gradient bars: the target is 1e-4 (whole-vector rel. L2 against the oracle
+# adjoint); measured 1.3e-7 to 4.7e-7 in FP32 and ~1e-15 in FP64, so the bars
+# sit well inside it and still leave room for rounding-order changes.
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_adjoint_gradient_design_patch(dtype, tol):
     """|DFT Ez|^2 on a patch, random eps design box, CPML: dJ/deps over the design box."""
     spec, _ = W.design_patch(pml=6, design=12, patch=8, n_steps=150, n_f=4, shape=(46, 27, 39))
@@ -70,7 +73,7 @@ def test_adjoint_gradient_design_patch(dtype, tol):
     assert r < tol, r
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-4)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_adjoint_gradient_diag_lorentz(dtype, tol):
     """Diagonal eps with a Lorentz box inside the gradient box (per-component gradient)."""
     spec = W.anisotropic_lorentz(pml=5, lorentz=8, patch=10, n_steps=120, n_f=4, shape=(38, 26, 34))
