@@ -15,6 +15,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2609_30039_amd import workloads as W
+from paper_2609_30039_amd import adjoint as A
 from paper_2609_30039_amd.sim import Simulation
 from tests.gpu_util import rel
 
@@ -143,3 +144,41 @@ def test_batch_48_domains_sampled():
             assert r < 1e-12, (d, W.COMP_NAMES[q], r)
         assert rel(sim.spectra(0, domain=d), o.spectra(0)) < 1e-12
     sim.close()
+
+
+def test_design_patch_212_gradient_vs_central_differences():
+    """The full design workload (212^3, 2000 steps, 24 binomial slots): the FP32
+    adjoint gradient at the generator's 20 seeded design cells against central
+    differences of J = sum |DFT Ez|^2 from FP64 solves, eps -> eps (1 +- 1e-3)
+    at one cell.  Cells whose gradient is below 1e-3 of the largest among them
+    are compared in absolute terms."""
+    spec, cells = W.design_patch()
+    N = spec.n_steps
+    shape = dict(kernel="split", tile_rows=8, tile_kz=3)
+    sim32 = Simulation(spec, dtype="f32", n_ckpt=24, graph_chunk=32, **shape)
+    g = A.gradient(sim32, N, 24, lambda s_: {(0, 0): 2.0 * s_.spectra(0)})[0][0]
+    sim32.close()
+    lo, _ = spec.eps_box
+    sim64 = Simulation(spec, dtype="f64", graph_chunk=32, **shape)
+
+    def J(eps):
+        sim64.reset()
+        sim64.set_eps(eps)
+        sim64.step(N, record=True)
+        return float(np.sum(np.abs(sim64.spectra(0)) ** 2))
+
+    fd, ad = [], []
+    for (i, j, k) in cells:
+        c = (k - lo[2], j - lo[1], i - lo[0])
+        e0 = spec.eps[(0,) + c]
+        d = 1e-3 * e0
+        ep, em = spec.eps.copy(), spec.eps.copy()
+        ep[(0,) + c] = e0 + d
+        em[(0,) + c] = e0 - d
+        fd.append((J(ep) - J(em)) / (2 * d))
+        ad.append(g[c])
+    sim64.close()
+    fd, ad = np.array(fd), np.array(ad)
+    big = np.abs(fd).max()
+    err = np.abs(ad - fd) / np.maximum(np.abs(fd), 1e-3 * big)
+    assert err.max() < 1e-3, (err, fd, ad)
