@@ -13,9 +13,12 @@
  *     Dt = D / kappa + psi (the form whose transpose Section 3.1 prints).
  *   - PEC faces (Section 2.2): tangential E held at zero on the low boundary
  *     node; the high boundary node is not stored (ghost zero).
- *   - One-pole Lorentz medium by the trapezoidal auxiliary differential
- *     equation (Section 2.3): Ampere at n+1/2 with the trapezoidal average of
- *     the polarisation current, the pole ODE by central differences at n.
+ *   - Dispersive cells with up to 16 Lorentz or Drude poles by the
+ *     trapezoidal auxiliary differential equation (Section 2.3): Ampere at
+ *     n+1/2 with the trapezoidal average of the polarisation currents, each
+ *     pole's ODE by central differences at n; the poles' currents add.  A
+ *     Drude pole is the Lorentz recursion with omega_0 -> 0 and
+ *     delta_eps omega_0^2 -> omega_p^2.
  *   - Discrete adjoint, Eq. (3) of Section 3.1, with the transposes of
  *     Section 3.1 (opposite-direction differences, the absorber transpose,
  *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl).
@@ -39,15 +42,22 @@ typedef struct {
     const double *bH[3], *cH[3], *kiH[3];
     const unsigned char *slab[3];
     const double *eps[3];        /* permittivity at each E node, per component */
-    const unsigned char *lor;    /* 1 where the cell is a Lorentz cell, or NULL */
-    double lor_deps, lor_w0dt, lor_gdt;   /* delta eps, omega0 dt, gamma dt */
+    const unsigned char *lor;    /* 1 where the cell is a dispersive cell, or NULL */
+    int npole;                   /* poles of the dispersive cells, 1..ORC_MAXP */
+    int pkind[16];               /* 0 Lorentz, 1 Drude */
+    double pdeps[16];            /* Lorentz: delta eps (Drude: unused) */
+    double pwdt[16];             /* Lorentz: omega_0 dt; Drude: omega_p dt */
+    double pgdt[16];             /* gamma dt */
 } orc_params;
+
+#define ORC_MAXP 16
 
 typedef struct {
     double *F[6];                /* Ex Ey Ez Hx Hy Hz */
     double *psiE[3][3];          /* [E component][derivative axis], diagonal unused */
     double *psiH[3][3];          /* [H component][derivative axis] */
-    double *Eold[3], *W[3], *Wold[3];   /* Lorentz history: E^{n-1}, W^n, W^{n-1} */
+    double *Eold[3];             /* dispersive history: E^{n-1} */
+    double *W[3][16], *Wold[3][16];     /* per pole: W^n, W^{n-1} */
 } orc_state;
 
 #define IDX(P, i, j, k) (((size_t)(k) * (size_t)(P)->n[1] + (size_t)(j)) * (size_t)(P)->n[0] + (size_t)(i))
@@ -64,13 +74,27 @@ static int e_masked(int c, const int x[3]) {
 
 static int is_lorentz(const orc_params *P, size_t p) { return P->lor && P->lor[p]; }
 
-/* Pole recursion constants of the trapezoidal ADE with W = dt J:
-   W^{n+1} = al W^n + xi W^{n-1} + (g/2)(E^{n+1} - E^{n-1}). */
-static void lorentz_consts(const orc_params *P, double *al, double *xi, double *g) {
-    double q = 1.0 + 0.5 * P->lor_gdt;
-    *al = (2.0 - P->lor_w0dt * P->lor_w0dt) / q;
-    *xi = (0.5 * P->lor_gdt - 1.0) / q;
-    *g = P->lor_deps * P->lor_w0dt * P->lor_w0dt / q;
+/* Recursion constants of pole p of the trapezoidal ADE with W = dt J:
+   W^{n+1} = al W^n + xi W^{n-1} + (g/2)(E^{n+1} - E^{n-1}).
+   Lorentz: al = (2 - (w0 dt)^2)/q, g = deps (w0 dt)^2/q; Drude: al = 2/q,
+   g = (wp dt)^2/q; both xi = (gamma dt/2 - 1)/q, q = 1 + gamma dt/2. */
+static void pole_consts(const orc_params *P, int p, double *al, double *xi, double *g) {
+    double q = 1.0 + 0.5 * P->pgdt[p];
+    double w2 = P->pwdt[p] * P->pwdt[p];
+    *al = P->pkind[p] ? 2.0 / q : (2.0 - w2) / q;
+    *xi = (0.5 * P->pgdt[p] - 1.0) / q;
+    *g = P->pkind[p] ? w2 / q : P->pdeps[p] * w2 / q;
+}
+
+/* sum of the poles' g: the E^{n-1} weight and the denominator eps + gsum/4 */
+static double pole_gsum(const orc_params *P) {
+    double s = 0.0;
+    for (int q = 0; q < P->npole; ++q) {
+        double al, xi, g;
+        pole_consts(P, q, &al, &xi, &g);
+        s += g;
+    }
+    return s;
 }
 
 /* Stretched backward-difference curl of H at E node p (component c):
@@ -123,11 +147,15 @@ static double curl_plus(const orc_params *P, orc_state *U, int c, const int x[3]
 static double e_pre(const orc_params *P, const orc_state *U, int c, size_t p, double curl) {
     double ep = P->eps[c][p];
     if (is_lorentz(P, p)) {
-        double al, xi, g;
-        lorentz_consts(P, &al, &xi, &g);
-        double den = ep + 0.25 * g;
-        return (ep * U->F[c][p] + 0.25 * g * U->Eold[c][p] + P->S * curl
-                - 0.5 * ((1.0 + al) * U->W[c][p] + xi * U->Wold[c][p])) / den;
+        double gsum = pole_gsum(P);
+        double den = ep + 0.25 * gsum;
+        double num = ep * U->F[c][p] + 0.25 * gsum * U->Eold[c][p] + P->S * curl;
+        for (int q = 0; q < P->npole; ++q) {
+            double al, xi, g;
+            pole_consts(P, q, &al, &xi, &g);
+            num -= 0.5 * ((1.0 + al) * U->W[c][q][p] + xi * U->Wold[c][q][p]);
+        }
+        return num / den;
     }
     return U->F[c][p] + P->S * curl / ep;
 }
@@ -167,8 +195,6 @@ void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, 
         U->F[c][p] += src_amp[s];
     }
     if (P->lor) {
-        double al, xi, g;
-        lorentz_consts(P, &al, &xi, &g);
         for (int c = 0; c < 3; ++c) {
             const double *En = work + (size_t)c * N;
 #pragma omp parallel for schedule(static)
@@ -178,10 +204,14 @@ void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, 
                         int x[3] = {i, j, k};
                         size_t p = IDX(P, i, j, k);
                         if (!P->lor[p] || e_masked(c, x)) continue;
-                        double wn1 = al * U->W[c][p] + xi * U->Wold[c][p]
-                                     + 0.5 * g * (U->F[c][p] - U->Eold[c][p]);
-                        U->Wold[c][p] = U->W[c][p];
-                        U->W[c][p] = wn1;
+                        for (int q = 0; q < P->npole; ++q) {
+                            double al, xi, g;
+                            pole_consts(P, q, &al, &xi, &g);
+                            double wn1 = al * U->W[c][q][p] + xi * U->Wold[c][q][p]
+                                         + 0.5 * g * (U->F[c][p] - U->Eold[c][p]);
+                            U->Wold[c][q][p] = U->W[c][q][p];
+                            U->W[c][q][p] = wn1;
+                        }
                         U->Eold[c][p] = En[p];
                     }
         }
@@ -252,9 +282,8 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                     }
         }
 
-    /* ---- Lorentz history and E-update transposes, pointwise ---- */
-    double al = 0, xi = 0, gg = 0;
-    if (P->lor) lorentz_consts(P, &al, &xi, &gg);
+    /* ---- dispersive history and E-update transposes, pointwise ---- */
+    const double gg = P->lor ? pole_gsum(P) : 0.0;
     for (int c = 0; c < 3; ++c) {
 #pragma omp parallel for schedule(static)
         for (int k = 0; k < nz; ++k)
@@ -270,25 +299,35 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                     if (is_lorentz(P, p)) {
                         double ep = P->eps[c][p];
                         double den = ep + 0.25 * gg;
-                        /* roll: W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1}),
-                           Wold <- W^n, Eold <- E^n */
-                        double Wb = A->W[c][p], Wob = A->Wold[c][p], Eob = A->Eold[c][p];
-                        double Et = A->F[c][p] + 0.5 * gg * Wb;      /* cotangent of E^{n+1} */
-                        double Wn = al * Wb + Wob;                    /* cotangent of W^n */
-                        double Wnm1 = xi * Wb;                        /* cotangent of W^{n-1} */
-                        double Enm1 = -0.5 * gg * Wb;                 /* cotangent of E^{n-1} */
-                        double En = Eob;                              /* cotangent of E^n */
-                        /* E^{n+1}_pre = [eps E^n + g/4 E^{n-1} + S curl - ((1+al) W^n + xi W^{n-1})/2] / den */
+                        /* roll of each pole q: W_q^{n+1} = al_q W_q^n + xi_q W_q^{n-1}
+                           + g_q/2 (E^{n+1} - E^{n-1}), Wold_q <- W_q^n; Eold <- E^n */
+                        double Et = A->F[c][p];                       /* cotangent of E^{n+1} */
+                        double Enm1 = 0.0;                            /* cotangent of E^{n-1} */
+                        double Wn[ORC_MAXP], Wnm1[ORC_MAXP];           /* cotangents of W_q^n, W_q^{n-1} */
+                        for (int q = 0; q < P->npole; ++q) {
+                            double al, xi, g;
+                            pole_consts(P, q, &al, &xi, &g);
+                            double Wb = A->W[c][q][p];
+                            Et += 0.5 * g * Wb;
+                            Enm1 += -0.5 * g * Wb;
+                            Wn[q] = al * Wb + A->Wold[c][q][p];
+                            Wnm1[q] = xi * Wb;
+                        }
+                        double En = A->Eold[c][p];                    /* cotangent of E^n */
+                        /* E^{n+1}_pre = [eps E^n + gsum/4 E^{n-1} + S curl
+                                          - sum_q ((1+al_q) W_q^n + xi_q W_q^{n-1})/2] / den */
                         double Ep = Et;
                         En += ep / den * Ep;
                         Enm1 += 0.25 * gg / den * Ep;
-                        Wn += -0.5 * (1.0 + al) / den * Ep;
-                        Wnm1 += -0.5 * xi / den * Ep;
+                        for (int q = 0; q < P->npole; ++q) {
+                            double al, xi, g;
+                            pole_consts(P, q, &al, &xi, &g);
+                            A->W[c][q][p] = Wn[q] + -0.5 * (1.0 + al) / den * Ep;
+                            A->Wold[c][q][p] = Wnm1[q] + -0.5 * xi / den * Ep;
+                        }
                         Epb[c][p] = Ep;
                         A->F[c][p] = En;
                         A->Eold[c][p] = Enm1;
-                        A->W[c][p] = Wn;
-                        A->Wold[c][p] = Wnm1;
                     } else {
                         Epb[c][p] = A->F[c][p];   /* E^{n+1} = E^n + ... : identity on E^n */
                     }

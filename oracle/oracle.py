@@ -29,13 +29,23 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fdtd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-# state layout: 27 full-grid arrays
+# state layout: 21 + 6 P full-grid arrays for P dispersive poles (27 for one):
+# fields, E- and H-side absorber memories, E^{n-1}, then W^n of each pole
+# (3 components each) and W^{n-1} of each pole
 F0 = 0                      # Ex Ey Ez Hx Hy Hz
 PSI_PAIRS = [(0, 1), (0, 2), (1, 0), (1, 2), (2, 0), (2, 1)]   # (component, derivative axis)
 PSIE0 = 6
 PSIH0 = 12
-EOLD0, W0, WOLD0 = 18, 21, 24
-NSTATE = 27
+EOLD0, W0, WOLD0 = 18, 21, 24   # one pole
+NSTATE = 27                     # one pole
+MAXP = 16
+
+
+def state_layout(npole: int):
+    """(index of W^n of pole 0, index of W^{n-1} of pole 0, state arrays) for
+    npole poles; pole p, component c sit at base + 3 p + c."""
+    w0 = 21
+    return w0, w0 + 3 * npole, w0 + 6 * npole
 
 
 def build(force: bool = False) -> str:
@@ -53,12 +63,13 @@ class _Params(C.Structure):
                 ("bE", C.c_void_p * 3), ("cE", C.c_void_p * 3), ("kiE", C.c_void_p * 3),
                 ("bH", C.c_void_p * 3), ("cH", C.c_void_p * 3), ("kiH", C.c_void_p * 3),
                 ("slab", C.c_void_p * 3), ("eps", C.c_void_p * 3), ("lor", C.c_void_p),
-                ("lor_deps", C.c_double), ("lor_w0dt", C.c_double), ("lor_gdt", C.c_double)]
+                ("npole", C.c_int), ("pkind", C.c_int * MAXP), ("pdeps", C.c_double * MAXP),
+                ("pwdt", C.c_double * MAXP), ("pgdt", C.c_double * MAXP)]
 
 
 class _State(C.Structure):
     _fields_ = [("F", C.c_void_p * 6), ("psiE", C.c_void_p * 9), ("psiH", C.c_void_p * 9),
-                ("Eold", C.c_void_p * 3), ("W", C.c_void_p * 3), ("Wold", C.c_void_p * 3)]
+                ("Eold", C.c_void_p * 3), ("W", C.c_void_p * (3 * MAXP)), ("Wold", C.c_void_p * (3 * MAXP))]
 
 
 _lib = None
@@ -148,6 +159,7 @@ class OracleSim:
         for c in range(3):
             P.eps[c] = _ptr(self.eps[c])
         self.lor = None
+        self.npole = 1
         if spec.lorentz:
             assert len(spec.lorentz) == 1
             L = spec.lorentz[0]
@@ -155,11 +167,21 @@ class OracleSim:
             (i0, j0, k0), (i1, j1, k1) = L.lo, L.hi
             self.lor[k0:k1, j0:j1, i0:i1] = 1
             P.lor = _ptr(self.lor)
-            P.lor_deps, P.lor_w0dt, P.lor_gdt = L.delta_eps, L.omega0_dt, L.gamma_dt
+            poles = L.pole_list()
+            assert 1 <= len(poles) <= MAXP
+            self.npole = len(poles)
+            P.npole = len(poles)
+            for q, pl in enumerate(poles):
+                P.pkind[q] = {"lorentz": 0, "drude": 1}[pl.kind]
+                P.pdeps[q], P.pwdt[q], P.pgdt[q] = pl.delta_eps, pl.omega_dt, pl.gamma_dt
         else:
             P.lor = None
+            P.npole = 0
+            self.npole = 0
+        # (a domain without dispersive cells keeps the one-pole layout, unused)
+        self.W0, self.WOLD0, self.NSTATE = state_layout(max(self.npole, 1))
         self.P = P
-        self.u = np.zeros((NSTATE, self.N))
+        self.u = np.zeros((self.NSTATE, self.N))
         self.work = np.zeros((4, self.N))
         self.t = 0
         # sources: flattened node lists
@@ -193,8 +215,9 @@ class OracleSim:
             st.psiH[3 * c + a] = base + 8 * N * (PSIH0 + r)
         for c in range(3):
             st.Eold[c] = base + 8 * N * (EOLD0 + c)
-            st.W[c] = base + 8 * N * (W0 + c)
-            st.Wold[c] = base + 8 * N * (WOLD0 + c)
+            for q in range(self.npole):
+                st.W[MAXP * c + q] = base + 8 * N * (self.W0 + 3 * q + c)
+                st.Wold[MAXP * c + q] = base + 8 * N * (self.WOLD0 + 3 * q + c)
         return st
 
     def field(self, q: int, u: Optional[np.ndarray] = None) -> np.ndarray:
@@ -202,11 +225,11 @@ class OracleSim:
         return u[F0 + q].reshape(self.shape3)
 
     def dof_mask(self) -> np.ndarray:
-        """Boolean [27][N]: entries of the state that are degrees of freedom."""
+        """Boolean [NSTATE][N]: entries of the state that are degrees of freedom."""
         nz, ny, nx = self.shape3
         k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
         x = (i, j, k)
-        m = np.zeros((NSTATE,) + self.shape3, dtype=bool)
+        m = np.zeros((self.NSTATE,) + self.shape3, dtype=bool)
         for c in range(3):
             m[F0 + c] = ~((x[(c + 1) % 3] == 0) | (x[(c + 2) % 3] == 0))
             m[F0 + 3 + c] = True
@@ -216,9 +239,11 @@ class OracleSim:
             m[PSIH0 + r] = sl
         if self.lor is not None:
             for c in range(3):
-                for base in (EOLD0, W0, WOLD0):
+                bases = [EOLD0] + [self.W0 + 3 * q for q in range(self.npole)] + \
+                        [self.WOLD0 + 3 * q for q in range(self.npole)]
+                for base in bases:
                     m[base + c] = self.lor.astype(bool) & m[F0 + c]
-        return m.reshape(NSTATE, self.N)
+        return m.reshape(self.NSTATE, self.N)
 
     # ---------------- stepping ----------------
     def _src_amps(self, t: int) -> np.ndarray:

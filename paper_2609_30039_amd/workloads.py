@@ -31,13 +31,32 @@ COMP_NAMES = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
 
 
 @dataclass
+class PoleSpec:
+    """One pole of a dispersive medium.  kind 'lorentz': strength delta_eps,
+    resonance omega_dt = omega_0 dt; kind 'drude': plasma omega_dt = omega_p dt
+    (delta_eps unused).  gamma_dt = damping gamma dt."""
+    kind: str
+    delta_eps: float
+    omega_dt: float
+    gamma_dt: float
+
+
+@dataclass
 class LorentzSpec:
-    """One-pole Lorentz medium on a box; eps_inf is the cell's permittivity."""
+    """Dispersive medium on a box; eps_inf is the cell's permittivity.  One
+    Lorentz pole (delta_eps, omega0_dt, gamma_dt), or, when ``poles`` is given,
+    those poles (up to 16) instead."""
     lo: Tuple[int, int, int]
     hi: Tuple[int, int, int]
     delta_eps: float
     omega0_dt: float
     gamma_dt: float
+    poles: Optional[List[PoleSpec]] = None
+
+    def pole_list(self) -> List[PoleSpec]:
+        if self.poles:
+            return list(self.poles)
+        return [PoleSpec("lorentz", self.delta_eps, self.omega0_dt, self.gamma_dt)]
 
 
 @dataclass

@@ -563,3 +563,91 @@ def test_gradient_taylor_remainder():
     rem = np.asarray(rem)
     r = rem[:-1] / rem[1:]
     assert np.all(r > 3.5) and np.all(r < 4.5), (rem, r)
+
+
+# ---------------------------------------------------------------- several poles
+def _with_poles(spec, poles):
+    """The spec with its dispersive box carrying ``poles`` instead of its pole."""
+    L = spec.lorentz[0]
+    return W.DomainSpec(**{**spec.__dict__, "lorentz": [W.LorentzSpec(L.lo, L.hi, 0.0, 0.0, 0.0, poles=poles)]})
+
+
+def _fields_after(spec, n):
+    sim = O.OracleSim(spec)
+    sim.step(n)
+    return np.stack([sim.field(q) for q in range(6)])
+
+
+def test_two_equal_poles_equal_one_pole():
+    """The poles' currents add: two Lorentz poles with one resonance and one
+    damping and strengths 0.6 and 0.9 evolve as the single pole of strength
+    1.5 (each pole's recursion is linear with the same constants)."""
+    spec = _fd_problem("iso")
+    two = _with_poles(spec, [W.PoleSpec("lorentz", 0.6, 0.45, 0.05), W.PoleSpec("lorentz", 0.9, 0.45, 0.05)])
+    a, b = _fields_after(spec, 60), _fields_after(two, 60)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
+def test_drude_pole_is_the_zero_resonance_limit():
+    """A Drude pole of plasma frequency wp is the Lorentz pole with omega_0 -> 0
+    and delta_eps omega_0^2 = wp^2; the difference falls as omega_0^2."""
+    spec = _fd_problem("iso")
+    wp, g = 0.35, 0.08
+    drude = _fields_after(_with_poles(spec, [W.PoleSpec("drude", 0.0, wp, g)]), 60)
+    d = []
+    for w0 in (0.02, 0.01):
+        lor = _fields_after(_with_poles(spec, [W.PoleSpec("lorentz", (wp / w0) ** 2, w0, g)]), 60)
+        d.append(np.linalg.norm(lor - drude) / np.linalg.norm(drude))
+    assert d[0] < 1e-2 and 3.5 < d[0] / d[1] < 4.5, d
+
+
+MIXED_POLES = [W.PoleSpec("lorentz", 1.0, 0.3, 0.04), W.PoleSpec("lorentz", 0.5, 0.6, 0.1),
+               W.PoleSpec("drude", 0.0, 0.4, 0.07)]
+
+
+@pytest.mark.parametrize("nsteps", [1, 20])
+def test_adjoint_dot_product_several_poles(nsteps):
+    """<A x, y> = <x, A^T y> with two Lorentz poles and a Drude pole in the box
+    (every pole's history in x and y), to round-off."""
+    rng = np.random.Generator(np.random.PCG64(23))
+    shape = (9, 8, 10)
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), pml=(2, 3, 2, 2, 3, 2), eps_kind="diag",
+                        eps_box=((2, 2, 2), (7, 6, 8)), eps=1.0 + 3.0 * rng.random((3, 6, 4, 5)),
+                        lorentz=[W.LorentzSpec((3, 2, 3), (6, 5, 7), 0.0, 0.0, 0.0, poles=MIXED_POLES)])
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    assert sim.NSTATE == 21 + 6 * len(MIXED_POLES)
+    x = rng.standard_normal(sim.u.shape) * dof
+    y = rng.standard_normal(sim.u.shape) * dof
+    ax = x.copy()
+    for t in range(nsteps):
+        sim.step_state(ax, t, sources=False)
+    aty = y.copy()
+    for t in range(nsteps):
+        sim.adjoint_step_state(aty, x, None)
+    lhs, rhs = np.sum(ax * y * dof), np.sum(x * aty * dof)
+    scale = np.linalg.norm(ax * dof) * np.linalg.norm(y)
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+
+
+def test_gradient_central_differences_several_poles():
+    """dJ/deps at a dielectric and a dispersive cell with two Lorentz poles and
+    a Drude pole, against fourth-order central differences."""
+    spec = _with_poles(_fd_problem("iso"), MIXED_POLES)
+    sim = O.OracleSim(spec)
+    sim.step(spec.n_steps)
+    J, cot = _objective(sim)
+    g = sim.gradient(cot, spec.n_steps)
+    (i0, j0, k0), _ = spec.eps_box
+    lor = spec.lorentz[0]
+    for (i, j, k) in [(i0 + 1, j0 + 3, k0 + 2), (lor.lo[0] + 1, lor.lo[1] + 2, lor.lo[2] + 1)]:
+        li, lj, lk = i - i0, j - j0, k - k0
+        h = 1e-3 * spec.eps[0, lk, lj, li]
+        vals = {}
+        for m in (-2, -1, 1, 2):
+            e = spec.eps.copy()
+            e[0, lk, lj, li] += m * h
+            vals[m] = _run_J(W.DomainSpec(**{**spec.__dict__, "eps": e}))
+        fd = (8.0 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12.0 * h)
+        ad = g[:, k, j, i].sum()
+        assert abs(ad - fd) <= 1e-7 * abs(fd) + 1e-8, (i, j, k, ad, fd)
