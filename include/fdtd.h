@@ -76,12 +76,27 @@ enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
 
 #define FDTD_MAX_SOURCES 4
 #define FDTD_MAX_MONITORS 8
+#define FDTD_MAX_POLES 16
+
+/* One pole of a dispersive medium (Section 2.3: up to sixteen Drude or
+   Lorentz poles, trapezoidal auxiliary differential equation).  A Lorentz
+   pole has strength delta_eps, resonance omega_dt = omega_0 dt and damping
+   gamma_dt; a Drude pole has plasma frequency omega_dt = omega_p dt and
+   damping gamma_dt (delta_eps unused): the Lorentz recursion with omega_0 -> 0
+   and delta_eps omega_0^2 -> omega_p^2. */
+enum { FDTD_POLE_LORENTZ = 0, FDTD_POLE_DRUDE = 1 };
+
+typedef struct {
+    int32_t kind;                  /* FDTD_POLE_LORENTZ | FDTD_POLE_DRUDE */
+    double delta_eps;              /* Lorentz pole strength */
+    double omega_dt;               /* Lorentz omega_0 dt | Drude omega_p dt, > 0 */
+    double gamma_dt;               /* damping gamma * dt (full rate), >= 0 */
+} fdtd_pole_desc;
 
 typedef struct {
     int32_t lo[3], hi[3];          /* cell box; eps_inf of each cell is its permittivity */
-    double delta_eps;              /* pole strength */
-    double omega0_dt;              /* resonance omega_0 * dt */
-    double gamma_dt;               /* damping gamma * dt (full rate) */
+    int32_t n_poles;               /* 1..FDTD_MAX_POLES; the poles' polarisation currents add */
+    fdtd_pole_desc poles[FDTD_MAX_POLES];
 } fdtd_lorentz_desc;
 
 typedef struct {

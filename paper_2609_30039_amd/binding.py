@@ -42,9 +42,18 @@ class FdtdError(RuntimeError):
         self.code = code
 
 
+FDTD_MAX_POLES = 16
+FDTD_POLE_LORENTZ, FDTD_POLE_DRUDE = 0, 1
+
+
+class PoleDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("delta_eps", C.c_double), ("omega_dt", C.c_double),
+                ("gamma_dt", C.c_double)]
+
+
 class LorentzDesc(C.Structure):
-    _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("delta_eps", C.c_double),
-                ("omega0_dt", C.c_double), ("gamma_dt", C.c_double)]
+    _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("n_poles", C.c_int32),
+                ("poles", PoleDesc * FDTD_MAX_POLES)]
 
 
 class SourceDesc(C.Structure):
@@ -149,7 +158,14 @@ def domain_desc(spec, keep: list) -> DomainDesc:
         L = spec.lorentz[0]
         for a in range(3):
             d.lorentz.lo[a], d.lorentz.hi[a] = L.lo[a], L.hi[a]
-        d.lorentz.delta_eps, d.lorentz.omega0_dt, d.lorentz.gamma_dt = L.delta_eps, L.omega0_dt, L.gamma_dt
+        poles = L.pole_list()
+        if len(poles) > FDTD_MAX_POLES:
+            raise ValueError(f"at most {FDTD_MAX_POLES} poles")
+        d.lorentz.n_poles = len(poles)
+        for q, pl in enumerate(poles):
+            pd = d.lorentz.poles[q]
+            pd.kind = {"lorentz": FDTD_POLE_LORENTZ, "drude": FDTD_POLE_DRUDE}[pl.kind]
+            pd.delta_eps, pd.omega_dt, pd.gamma_dt = pl.delta_eps, pl.omega_dt, pl.gamma_dt
     d.n_sources = len(spec.sources)
     for q, s in enumerate(spec.sources):
         w = np.ascontiguousarray(s.waveform, dtype=np.float64)

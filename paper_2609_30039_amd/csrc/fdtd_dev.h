@@ -22,6 +22,7 @@
 namespace fdtd {
 
 constexpr int kMaxSrc = 4;
+constexpr int kMaxPole = 16;
 constexpr int kMaxSmp = 8;   // plane monitors per domain (the descriptor limit)
 
 // A plane monitor as the split H kernel samples it: the threads whose column
@@ -82,7 +83,10 @@ struct DomDev {
     const T* epsinv[3];        // over the eps box; isotropic: the same array thrice
     int has_lor;
     int llo[3], lhi[3];
-    T lal, lxi, lg;            // pole recursion constants
+    int npole;                 // poles of the dispersive box (1..kMaxPole)
+    T lal[kMaxPole], lxi[kMaxPole], lg[kMaxPole];   // per-pole recursion constants
+    T lgs;                     // sum of lg: the E^{n-1} weight, denominator eps + lgs/4
+    long long lbox;            // cells of the box: pole p of W and Wold at + p * lbox
     T* lor[3][3];              // [0 Eold | 1 W | 2 Wold][component] over the Lorentz box
     int nsrc;
     SrcDev<T> src[kMaxSrc];
@@ -197,8 +201,10 @@ __device__ __forceinline__ T e_update_v(const DomDev<T>& d, int c, int i, int j,
         if (own && lorc) {
             long long q = lidx(d, i, j, k) + ws * fs;
             gp(d.lor[0][c])[q] = T(0);
-            gp(d.lor[1][c])[q] = T(0);
-            gp(d.lor[2][c])[q] = T(0);
+            for (int p = 0; p < d.npole; ++p) {
+                gp(d.lor[1][c])[q + p * d.lbox] = T(0);
+                gp(d.lor[2][c])[q + p * d.lbox] = T(0);
+            }
         }
         return T(0);
     }
@@ -208,17 +214,20 @@ __device__ __forceinline__ T e_update_v(const DomDev<T>& d, int c, int i, int j,
     T curl = D0 - D1;
     T en;
     long long q = 0;
-    T eold = 0, w = 0, wold = 0;
+    T eold = 0;
     if (lorc) {
+        // poles' currents add: num = eps E^n + lgs/4 E^{n-1} + S curl - sum_p ((1+al_p) W_p^n + xi_p W_p^{n-1})/2
         q = lidx(d, i, j, k);
         eold = gp(d.lor[0][c])[q + rs * fs];
-        w = gp(d.lor[1][c])[q + rs * fs];
-        wold = gp(d.lor[2][c])[q + rs * fs];
         T einf = T(1) / einv;
-        T invden = T(1) / (einf + T(0.25) * d.lg);
-        T num = fma(einf, e, T(0.25) * d.lg * eold);
+        T invden = T(1) / (einf + T(0.25) * d.lgs);
+        T num = fma(einf, e, T(0.25) * d.lgs * eold);
         num = fma(d.S, curl, num);
-        num -= T(0.5) * fma(T(1) + d.lal, w, d.lxi * wold);
+        for (int p = 0; p < d.npole; ++p) {
+            const long long o = q + p * d.lbox + rs * fs;
+            const T w = gp(d.lor[1][c])[o], wold = gp(d.lor[2][c])[o];
+            num -= T(0.5) * fma(T(1) + d.lal[p], w, d.lxi[p] * wold);
+        }
         en = num * invden;
     } else {
         en = fma(d.S * einv, curl, e);
@@ -228,11 +237,15 @@ __device__ __forceinline__ T e_update_v(const DomDev<T>& d, int c, int i, int j,
         if (sr.comp == c && t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) en += gp(sr.wave)[t];
     }
     if (own && lorc) {
-        T wn = fma(d.lal, w, d.lxi * wold);
-        wn = fma(T(0.5) * d.lg, en - eold, wn);
+        for (int p = 0; p < d.npole; ++p) {   // each pole's roll reads its own entries before writing them
+            const long long o = q + p * d.lbox;
+            const T w = gp(d.lor[1][c])[o + rs * fs], wold = gp(d.lor[2][c])[o + rs * fs];
+            T wn = fma(d.lal[p], w, d.lxi[p] * wold);
+            wn = fma(T(0.5) * d.lg[p], en - eold, wn);
+            gp(d.lor[1][c])[o + ws * fs] = wn;
+            gp(d.lor[2][c])[o + ws * fs] = w;
+        }
         gp(d.lor[0][c])[q + ws * fs] = e;
-        gp(d.lor[1][c])[q + ws * fs] = wn;
-        gp(d.lor[2][c])[q + ws * fs] = w;
     }
     return en;
 }
@@ -330,33 +343,41 @@ __device__ __forceinline__ AdjE<T> et_node(const DomDev<T>& d, int c, int i, int
         if (own && in_lor(d, i, j, k)) {
             long long q = lidx(d, i, j, k) + ws * as;
             gp(d.lora[0][c])[q] = T(0);
-            gp(d.lora[1][c])[q] = T(0);
-            gp(d.lora[2][c])[q] = T(0);
+            for (int p = 0; p < d.npole; ++p) {
+                gp(d.lora[1][c])[q + p * d.lbox] = T(0);
+                gp(d.lora[2][c])[q + p * d.lbox] = T(0);
+            }
         }
         return r;
     }
     T einv = epsinv_at(d, c, i, j, k);
     if (in_lor(d, i, j, k)) {
         long long q = lidx(d, i, j, k);
-        T wb = gp(d.lora[1][c])[q + rs * as];
         T einf = T(1) / einv;
-        T invden = T(1) / (einf + T(0.25) * d.lg);
-        T ep = fma(T(0.5) * d.lg, wb, etot);      // W^{n+1} roll feeds E^{n+1}
+        T invden = T(1) / (einf + T(0.25) * d.lgs);
+        T ep = etot;
+        for (int p = 0; p < d.npole; ++p)        // each pole's W^{n+1} roll feeds E^{n+1}
+            ep = fma(T(0.5) * d.lg[p], gp(d.lora[1][c])[q + p * d.lbox + rs * as], ep);
         r.epre = ep;
         r.coef = invden;
         if (own) {
-            T wob = gp(d.lora[2][c])[q + rs * as], eob = gp(d.lora[0][c])[q + rs * as];
-            T wn = fma(d.lal, wb, wob);
-            T wnm1 = d.lxi * wb;
-            T enm1 = -T(0.5) * d.lg * wb;
+            T eob = gp(d.lora[0][c])[q + rs * as];
             T s = ep * invden;
             r.en = fma(einf, s, eob);
-            enm1 = fma(T(0.25) * d.lg, s, enm1);
-            wn = fma(-T(0.5) * (T(1) + d.lal), s, wn);
-            wnm1 = fma(-T(0.5) * d.lxi, s, wnm1);
+            T enm1 = T(0);
+            for (int p = 0; p < d.npole; ++p) {
+                const long long o = q + p * d.lbox;
+                const T wb = gp(d.lora[1][c])[o + rs * as], wob = gp(d.lora[2][c])[o + rs * as];
+                T wn = fma(d.lal[p], wb, wob);
+                T wnm1 = d.lxi[p] * wb;
+                enm1 = p == 0 ? -T(0.5) * d.lg[0] * wb : fma(-T(0.5) * d.lg[p], wb, enm1);
+                wn = fma(-T(0.5) * (T(1) + d.lal[p]), s, wn);
+                wnm1 = fma(-T(0.5) * d.lxi[p], s, wnm1);
+                gp(d.lora[1][c])[o + ws * as] = wn;
+                gp(d.lora[2][c])[o + ws * as] = wnm1;
+            }
+            enm1 = fma(T(0.25) * d.lgs, s, enm1);
             gp(d.lora[0][c])[q + ws * as] = enm1;
-            gp(d.lora[1][c])[q + ws * as] = wn;
-            gp(d.lora[2][c])[q + ws * as] = wnm1;
         }
     } else {
         r.epre = etot;
@@ -384,12 +405,15 @@ __device__ __forceinline__ double grad_term(const DomDev<T>& d, int c, int i, in
     if (in_lor(d, i, j, k)) {
         long long q = lidx(d, i, j, k) + fsr * d.fs;
         T e = gp(d.E[c])[f + fsr * d.fs];
-        T eold = gp(d.lor[0][c])[q], w = gp(d.lor[1][c])[q], wold = gp(d.lor[2][c])[q];
+        T eold = gp(d.lor[0][c])[q];
         T einf = T(1) / einv;
-        T invden = T(1) / (einf + T(0.25) * d.lg);
-        T num = fma(einf, e, T(0.25) * d.lg * eold);
+        T invden = T(1) / (einf + T(0.25) * d.lgs);
+        T num = fma(einf, e, T(0.25) * d.lgs * eold);
         num = fma(d.S, curl, num);
-        num -= T(0.5) * fma(T(1) + d.lal, w, d.lxi * wold);
+        for (int p = 0; p < d.npole; ++p) {
+            const T w = gp(d.lor[1][c])[q + p * d.lbox], wold = gp(d.lor[2][c])[q + p * d.lbox];
+            num -= T(0.5) * fma(T(1) + d.lal[p], w, d.lxi[p] * wold);
+        }
         T epre_f = num * invden;
         return (double)epre * (double)((e - epre_f) * invden);
     }

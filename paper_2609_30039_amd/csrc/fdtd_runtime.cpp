@@ -540,10 +540,12 @@ struct Handle : Base {
             if (d.has_lor) {
                 size_t lbox = 1;
                 for (int a = 0; a < 3; ++a) lbox *= (size_t)(d.lhi[a] - d.llo[a]);
+                // [0] E^{n-1}; [1] W^n and [2] W^{n-1} of every pole, pole p at + p * lbox
                 for (int w = 0; w < 3; ++w)
                     for (int c = 0; c < 3; ++c) {
-                        fst(d.lor[w][c], lbox);
-                        if (g) ast(d.lora[w][c], lbox);
+                        const size_t n = lbox * (w == 0 ? 1 : (size_t)d.npole);
+                        fst(d.lor[w][c], n);
+                        if (g) ast(d.lora[w][c], n);
                     }
             }
             for (int k = 0; k < s.n_sources; ++k)
@@ -783,11 +785,25 @@ struct Handle : Base {
                 d.llo[a] = L.lo[a];
                 d.lhi[a] = L.hi[a];
             }
-            // trapezoidal ADE with W = dt J: W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1})
-            double qq = 1.0 + 0.5 * L.gamma_dt;
-            d.lal = (T)((2.0 - L.omega0_dt * L.omega0_dt) / qq);
-            d.lxi = (T)((0.5 * L.gamma_dt - 1.0) / qq);
-            d.lg = (T)(L.delta_eps * L.omega0_dt * L.omega0_dt / qq);
+            // trapezoidal ADE per pole with W = dt J:
+            // W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1}), q = 1 + gamma dt/2,
+            // Lorentz: al = (2 - (w0 dt)^2)/q, g = deps (w0 dt)^2/q; Drude: al = 2/q, g = (wp dt)^2/q;
+            // xi = (gamma dt/2 - 1)/q
+            d.npole = L.n_poles;
+            double gsum = 0.0;
+            for (int p = 0; p < L.n_poles; ++p) {
+                const fdtd_pole_desc& pd = L.poles[p];
+                const double qq = 1.0 + 0.5 * pd.gamma_dt, w2 = pd.omega_dt * pd.omega_dt;
+                const bool drude = pd.kind == FDTD_POLE_DRUDE;
+                const double g = drude ? w2 / qq : pd.delta_eps * w2 / qq;
+                d.lal[p] = (T)(drude ? 2.0 / qq : (2.0 - w2) / qq);
+                d.lxi[p] = (T)((0.5 * pd.gamma_dt - 1.0) / qq);
+                d.lg[p] = (T)g;
+                gsum += g;
+            }
+            d.lgs = (T)gsum;
+            d.lbox = 1;
+            for (int a = 0; a < 3; ++a) d.lbox *= (long long)(L.hi[a] - L.lo[a]);
         }
         d.nsrc = s.n_sources;
         for (int k = 0; k < s.n_sources; ++k) {
@@ -884,9 +900,17 @@ struct Handle : Base {
             const fdtd_lorentz_desc& L = s.lorentz;
             for (int a = 0; a < 3; ++a)
                 if (L.lo[a] < 0 || L.hi[a] > s.n[a] || L.lo[a] >= L.hi[a]) return fail(FDTD_E_INVALID, "Lorentz box");
-            if (!(L.delta_eps >= 0) || !(L.omega0_dt > 0) || !(L.gamma_dt >= 0) || !std::isfinite(L.delta_eps) ||
-                !std::isfinite(L.omega0_dt) || !std::isfinite(L.gamma_dt))
-                return fail(FDTD_E_UNSTABLE, "Lorentz parameters must be finite with delta_eps >= 0, omega0 > 0, gamma >= 0");
+            if (L.n_poles < 1 || L.n_poles > FDTD_MAX_POLES) return fail(FDTD_E_INVALID, "1 to 16 poles per box");
+            for (int p = 0; p < L.n_poles; ++p) {
+                const fdtd_pole_desc& pd = L.poles[p];
+                if (pd.kind != FDTD_POLE_LORENTZ && pd.kind != FDTD_POLE_DRUDE)
+                    return fail(FDTD_E_INVALID, "pole kind");
+                if (!(pd.omega_dt > 0) || !(pd.gamma_dt >= 0) || !std::isfinite(pd.omega_dt) ||
+                    !std::isfinite(pd.gamma_dt) ||
+                    (pd.kind == FDTD_POLE_LORENTZ && (!(pd.delta_eps >= 0) || !std::isfinite(pd.delta_eps))))
+                    return fail(FDTD_E_UNSTABLE, "pole parameters must be finite with omega > 0, gamma >= 0, "
+                                                 "delta_eps >= 0");
+            }
         }
         if (s.n_sources < 0 || s.n_sources > FDTD_MAX_SOURCES) return fail(FDTD_E_INVALID, "too many sources");
         h.waves.resize(s.n_sources);

@@ -34,8 +34,10 @@ def face_cells(spec) -> int:
 def forward_bytes(spec, word: int) -> int:
     n = spec.ncells
     neps = _box_cells(spec.eps_box) * (3 if spec.eps_kind == "diag" else 1) if spec.eps is not None else 0
-    nlor = sum(_box_cells((L.lo, L.hi)) for L in spec.lorentz)
-    return word * (12 * n + neps + 8 * face_cells(spec) + 15 * nlor)
+    # dispersive cells, per component: read E^{n-1} and each pole's W^n, W^{n-1};
+    # write E^{n-1} and each pole's W^{n+1} (2 + 3 P words; 5 for one pole)
+    lor_words = sum(_box_cells((L.lo, L.hi)) * 3 * (2 + 3 * len(L.pole_list())) for L in spec.lorentz)
+    return word * (12 * n + neps + 8 * face_cells(spec) + lor_words)
 
 
 def adjoint_bytes(spec, word: int) -> int:

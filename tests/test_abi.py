@@ -105,3 +105,22 @@ def test_launch_shape_options_checked():
     _refused(_spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED, tile_rows=3)
     _refused(_spec(), B.FDTD_E_INVALID, graph_chunk=65)
     _refused(_spec(), B.FDTD_E_INVALID, tile_kz=-1)
+
+
+def test_pole_descriptors_checked():
+    """1 to 16 poles of a known kind, omega > 0, gamma >= 0, Lorentz delta_eps >= 0."""
+    def with_poles(poles):
+        return _spec(lorentz=[W.LorentzSpec((2, 2, 2), (5, 5, 5), 0.0, 0.0, 0.0, poles=poles)])
+    ok = W.PoleSpec("lorentz", 1.0, 0.3, 0.05)
+    with pytest.raises(ValueError):
+        B.fdtd_create([with_poles([ok] * 17)], B.FDTD_F32, mem_budget_bytes=1e12)
+    _refused(with_poles([W.PoleSpec("drude", 0.0, 0.0, 0.05)]), B.FDTD_E_UNSTABLE)
+    _refused(with_poles([ok, W.PoleSpec("lorentz", -1.0, 0.3, 0.05)]), B.FDTD_E_UNSTABLE)
+    _refused(with_poles([W.PoleSpec("lorentz", 1.0, 0.3, -0.1)]), B.FDTD_E_UNSTABLE)
+
+
+    class NoPoles(W.LorentzSpec):
+        def pole_list(self):
+            return []
+
+    _refused(_spec(lorentz=[NoPoles((2, 2, 2), (5, 5, 5), 0.0, 0.0, 0.0)]), B.FDTD_E_INVALID)

@@ -317,3 +317,39 @@ def test_split_block_classes_at_slab_edges():
             assert np.array_equal(ref[0][q], val[0][q]), (key, "fwd", q)
             assert np.array_equal(ref[2][q], val[2][q]), (key, "adj", q)
         assert np.array_equal(ref[1], val[1]), (key, "grad")
+
+
+def test_several_poles_split_equals_fused():
+    """Two Lorentz poles and a Drude pole: both kernel families give the same
+    fields, gradient and adjoint fields bitwise, and BF16 slots stay finite."""
+    spec = _case(n_steps=60)
+    L = spec.lorentz[0]
+    spec.lorentz = [W.LorentzSpec(L.lo, L.hi, 0.0, 0.0, 0.0, poles=[
+        W.PoleSpec("lorentz", 0.9, 0.45, 0.05), W.PoleSpec("lorentz", 0.6, 0.7, 0.1),
+        W.PoleSpec("drude", 0.0, 0.35, 0.08)])]
+    N = spec.n_steps
+    out = {}
+    for kern, rows in (("split", 0), ("split", 8), ("fused", 2)):
+        sim = Simulation(spec, dtype="f32", kernel=kern, n_ckpt=N + 1, tile_rows=rows)
+        sim.save(0)
+        for t in range(N):
+            sim.step(1)
+            sim.save(t + 1)
+        fields = _fields(sim)
+        for mi, m in enumerate(spec.monitors):
+            sim.set_cotangent(mi, _cot(mi, m, sim.spectra(mi)))
+        sim.adjoint_begin(N)
+        for m_ in range(N, 0, -1):
+            sim.restore(m_ - 1)
+            sim.step_adjoint(1)
+        out[(kern, rows)] = (fields, sim.grad(), [sim.field(q, adjoint=True) for q in range(6)])
+    ref = out[("split", 0)]
+    for key, val in out.items():
+        for q in range(6):
+            assert np.array_equal(ref[0][q], val[0][q]), (key, "fwd", q)
+            assert np.array_equal(ref[2][q], val[2][q]), (key, "adj", q)
+        assert np.array_equal(ref[1], val[1]), (key, "grad")
+    cot = lambda s: {(0, mi): _cot(mi, m, s.spectra(mi)) for mi, m in enumerate(spec.monitors)}
+    g16 = A.gradient(Simulation(spec, dtype="f32", n_ckpt=6, ckpt_storage="bf16"), N, 6, cot)[0]
+    assert np.isfinite(g16).all()
+    assert np.linalg.norm(g16 - ref[1]) / np.linalg.norm(ref[1]) < 5e-2
