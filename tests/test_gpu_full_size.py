@@ -182,3 +182,74 @@ def test_design_patch_212_gradient_vs_central_differences():
     big = np.abs(fd).max()
     err = np.abs(ad - fd) / np.maximum(np.abs(fd), 1e-3 * big)
     assert err.max() < 1e-3, (err, fd, ad)
+
+
+# two Lorentz poles and a Drude pole
+POLES = [W.PoleSpec("lorentz", 0.9, 0.45, 0.05), W.PoleSpec("lorentz", 0.6, 0.7, 0.1),
+         W.PoleSpec("drude", 0.0, 0.35, 0.08)]
+
+
+def _float32_storage_error(spec, fields, n):
+    """Per-field relative error of the FP64 oracle whose whole state is rounded
+    to float32 after every step, against the plain FP64 oracle: what storing
+    the state in FP32 costs by itself."""
+    a, b = _oracle(spec, fields, 0, False), _oracle(spec, fields, 0, False)
+    b.u[...] = b.u.astype(np.float32)
+    for _ in range(n):
+        a.step(1, record=False)
+        b.step(1, record=False)
+        b.u[...] = b.u.astype(np.float32)
+    return [rel(b.field(q), a.field(q)) for q in range(6)], a
+
+
+def test_headline_148_several_poles():
+    """148^3 with the 48^3 dispersive box holding two Lorentz poles and a Drude
+    pole (its cells updated by the leading blocks of the E launch), 32 steps
+    from a random state in one captured chunk, tuned shape, every node.  FP64
+    to 1e-11; FP32 to 3x the float32 storage error, never below 2e-5."""
+    spec = W.lorentz_flux()
+    L = spec.lorentz[0]
+    spec.lorentz = [W.LorentzSpec(L.lo, L.hi, 0.0, 0.0, 0.0, poles=POLES)]
+    fields = _random_fields(spec.shape, 7005)
+    store_err, o = _float32_storage_error(spec, fields, 32)
+    for dtype in ("f64", "f32"):
+        sim = _start(spec, fields, dtype, kernel="split", tile_rows=8, tile_kz=3, graph_chunk=32)
+        sim.step(32, record=False)
+        for q in range(6):
+            tol = 1e-11 if dtype == "f64" else max(2e-5, 3.0 * store_err[q])
+            r = rel(sim.field(q), o.field(q))
+            assert r < tol, (dtype, W.COMP_NAMES[q], r, tol)
+        sim.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-5)])
+def test_design_patch_212_several_poles_adjoint_dot_product(dtype, tol):
+    """212^3 with a 24^3 box of two Lorentz poles and a Drude pole across a
+    corner of the gradient box (dielectric, dispersive, in-box and out-of-box
+    gradient cells): three adjoint steps are the transpose of three forward
+    steps, <A^3 x, y> = <x, (A^T)^3 y>.  x and y live in the six fields; the
+    first step fills every pole's history, so the later steps carry all the
+    pole terms both ways."""
+    spec, _ = W.design_patch()
+    spec.sources = []
+    lo, _ = spec.grad_box
+    blo = tuple(c - 12 for c in lo)
+    spec.lorentz = [W.LorentzSpec(blo, tuple(c + 24 for c in blo), 0.0, 0.0, 0.0, poles=POLES)]
+    x = _random_fields(spec.shape, 7006)
+    y = _random_fields(spec.shape, 7007)
+    sim = _start(spec, x, dtype, kernel="split", tile_rows=8, tile_kz=3, n_ckpt=3)
+    for t in range(3):
+        sim.save(t)
+        sim.step(1, record=False)
+    ax = [sim.field(q) for q in range(6)]
+    sim.adjoint_begin(3)
+    for q in range(6):
+        sim.set_field(q, y[q], adjoint=True)
+    for m in range(3, 0, -1):
+        sim.restore(m - 1)
+        sim.step_adjoint(1)
+    aty = [sim.field(q, adjoint=True) for q in range(6)]
+    lhs, rhs = _inner(ax, y), _inner(x, aty)
+    scale = _norm(ax) * _norm(y)
+    assert abs(lhs - rhs) <= tol * scale, (lhs, rhs, scale)
+    sim.close()
