@@ -6,11 +6,11 @@
  *   E^{n+1} = E^n + S eps^-1 C^-(H^{n+1/2}) + s^{n+1},
  *   H^{n+3/2} = H^{n+1/2} - S C^+(E^{n+1})            (Section 2.1, Eq. 1)
  * with convolutional PML memories in absorbing faces and PEC outer walls
- * (Section 2.2), per-node real or diagonal permittivity and a one-pole
- * Lorentz box integrated by the trapezoidal ADE (Section 2.3), soft electric
- * sources and point / plane-spectrum monitors (Section 2.4), and runs the
- * discrete adjoint of that step (Section 3.1, Eq. 3) with accumulation of
- * dJ/deps.  Checkpoint slots serve the binomial replay of Section 3.2.
+ * (Section 2.2), per-node real or diagonal permittivity and a dispersive
+ * box of 1 to 16 Lorentz or Drude poles integrated by the trapezoidal ADE
+ * (Section 2.3), soft electric sources and point / plane-spectrum monitors
+ * (Section 2.4), and runs the discrete adjoint of that step (Section 3.1,
+ * Eq. 3) with accumulation of dJ/deps.  Checkpoint slots serve the binomial replay of Section 3.2.
  *
  * Conventions shared by every call:
  *   - unit mesh (h = 1), c = 1: dt = S, frequencies are given as omega*dt;
