@@ -988,11 +988,17 @@ __device__ __forceinline__ void adj_et_tile(const DomDev<T>* __restrict__ doms, 
 // XCD receives form a contiguous spatial run of balanced cost (tiles of value
 // (domain, xlen 0) are padding and return at once).
 // The general class (Lorentz cells, gradient cells in a slab; rare) has a
-// launch of its own, which keeps its registers out of the others.  Both
-// passes are held to 4 waves per SIMD (128 VGPRs, a few spills in the slab
-// variants): measured faster than 3 waves without spills.
+// launch of its own, which keeps its registers out of the others.  In FP32
+// both passes are held to 4 waves per SIMD (128 VGPRs, a few spills in the
+// slab variants): measured faster than 3 waves without spills.  FP64 needs
+// about twice the registers: at 4 waves it spilled over 300 VGPRs per lane;
+// 3 waves (168 VGPRs, about 90 spills) measured fastest over the 212^3 and
+// 536^3 workloads, 2 waves (no spills) gained less at 536^3.
+template <typename T> constexpr int kAdjHtWaves = sizeof(T) == 8 ? 3 : 4;
+template <typename T> constexpr int kAdjEtWaves = sizeof(T) == 8 ? 3 : 4;
+
 template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_adj_ht(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdjHtWaves<T>, 8))) k_adj_ht(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles,
                                                 int kz, int rs, int ws, int fsr) {
     const int4 e = tiles[blockIdx.x];
     static_assert(kAdjClasses1 == 7, "one case per class");
@@ -1015,7 +1021,7 @@ __global__ void __launch_bounds__(256) k_adj_ht_full(const DomDev<T>* __restrict
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdjEtWaves<T>, 8)))
 k_adj_et(const DomDev<T>* __restrict__ doms, const int4* __restrict__ tiles, int kz, int rs, int ws) {
     const int4 e = tiles[blockIdx.x];
     static_assert(kAdjClasses2 == 6, "one case per class");
