@@ -1012,8 +1012,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdjHt
     }
 }
 
+// The general class in FP32 just exceeds 128 VGPRs with the loop over poles;
+// held to 4 waves (2 spills) it measured 269 us against 318 us at 3 waves on
+// the 536^3 workload's dispersive box.
+template <typename T> constexpr int kAdjFullWaves = sizeof(T) == 8 ? 2 : 4;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_ht_full(const DomDev<T>* __restrict__ doms,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAdjFullWaves<T>, 8))) k_adj_ht_full(const DomDev<T>* __restrict__ doms,
                                                      const int4* __restrict__ tiles, int kz, int rs, int ws, int fsr) {
     const int4 e = tiles[blockIdx.x];
     if ((e.x >> 24) == 2) adj_ht_tile<T, kAdjFull, 32>(doms, e, kz, rs, ws, fsr);
