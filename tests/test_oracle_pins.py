@@ -651,3 +651,23 @@ def test_gradient_central_differences_several_poles():
         fd = (8.0 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12.0 * h)
         ad = g[:, k, j, i].sum()
         assert abs(ad - fd) <= 1e-7 * abs(fd) + 1e-8, (i, j, k, ad, fd)
+
+
+def test_spectral_radius_several_poles():
+    """The absorbing domain of the one-pole radius pin with two Lorentz poles
+    and a Drude pole in the dispersive box: the one-step operator stays
+    contractive (spectral radius <= 1), the lossless interior modes on the unit
+    circle.  A Drude pole's own recursion has an eigenvalue 1 (alpha + xi = 1),
+    so a wrong constant or a pole's history read in place of another pushes
+    the radius above 1."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    shape = (7, 6, 8)
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(0.99), pml=(2, 2, 2, 2, 2, 2),
+                        eps_kind="iso", eps_box=((2, 2, 2), (5, 4, 6)),
+                        eps=1.0 + 3.0 * rng.random((1, 4, 2, 3)),
+                        lorentz=[W.LorentzSpec((2, 2, 3), (5, 4, 5), 0.0, 0.0, 0.0, poles=MIXED_POLES)])
+    sim = O.OracleSim(spec)
+    M = _one_step_matrix(sim)
+    lam = np.abs(np.linalg.eigvals(M))
+    assert lam.max() <= 1.0 + 1e-9
+    assert lam.max() > 0.99
