@@ -6,9 +6,9 @@ candidate is timed through the C-ABI on a handle of the real workload (HIP
 events around the stepping launches only, monitors off), forward steps and
 optionally adjoint steps, and the fastest is kept.  Results are cached in a
 JSON file keyed by the dtype, the device name and a signature of the domain
-geometry (shapes, absorber depths, Lorentz and eps boxes, sources), because
-the best shape depends on how the tiles fall onto absorbers and dispersive
-regions as much as on the size.
+geometry (shapes, absorber depths, dispersive boxes with their pole kinds, eps
+boxes, sources), because the best shape depends on how the tiles fall onto
+absorbers and dispersive regions as much as on the size.
 """
 from __future__ import annotations
 
@@ -41,7 +41,7 @@ def _cache_path() -> str:
 def signature(specs: Sequence, dtype: str, adjoint: bool) -> str:
     h = hashlib.sha256()
     for s in specs:
-        lor = [(L.lo, L.hi) for L in s.lorentz]
+        lor = [(L.lo, L.hi, [p.kind for p in L.pole_list()]) for L in s.lorentz]
         src = [(x.kind, x.comp, tuple(x.pos)) for x in s.sources]
         h.update(repr((s.shape, tuple(s.pml), s.eps_kind, s.eps_box, lor, src, s.grad_box)).encode())
     dev = "unknown"
