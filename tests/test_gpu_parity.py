@@ -155,3 +155,33 @@ def test_adjoint_gradient_several_poles(dtype, tol):
     for c in range(3):
         r = rel(g_gpu[c], g_orc[c, k0:k1, j0:j1, i0:i1])
         assert r < tol, (c, r)
+
+
+def _sixteen_poles():
+    """The largest pole count a box takes: ten Lorentz poles spread over
+    resonance and damping and six Drude poles."""
+    poles = [W.PoleSpec("lorentz", 0.05 + 0.03 * p, 0.2 + 0.05 * p, 0.01 + 0.01 * p) for p in range(10)]
+    poles += [W.PoleSpec("drude", 0.0, 0.05 + 0.02 * p, 0.02 + 0.02 * p) for p in range(6)]
+    return poles
+
+
+def test_sixteen_poles_fields_spectra_and_gradient_f64():
+    """A box at the maximum of 16 poles: fields and flux spectra after 150
+    steps, then dJ/deps per component of the diagonal-eps gradient case,
+    FP64 against the oracle (every pole's history at its own offset)."""
+    poles = _sixteen_poles()
+    spec = _with_poles(_lorentz_flux_small(n_steps=150), poles)
+    o = oracle_forward(spec)
+    g = gpu_forward(spec, "f64")
+    for q in range(6):
+        r = rel(g.field(q), o.field(q))
+        assert r < 1e-10, (W.COMP_NAMES[q], r)
+    assert rel(g.spectra(0), o.spectra(0)) < 1e-10
+    spec = _with_poles(W.anisotropic_lorentz(pml=5, lorentz=8, patch=10, n_steps=80, n_f=4, shape=(38, 26, 34)),
+                       poles)
+    _, g_gpu, _ = gpu_gradient_store_all(spec, "f64", _cot)
+    _, g_orc = oracle_gradient(spec, _cot)
+    (i0, j0, k0), (i1, j1, k1) = spec.grad_box
+    for c in range(3):
+        r = rel(g_gpu[c], g_orc[c, k0:k1, j0:j1, i0:i1])
+        assert r < 1e-12, (c, r)
