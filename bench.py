@@ -394,6 +394,27 @@ def main():
             "launch_shape": tile5}
         del sim5
 
+        # ------------------------------------------------------------ dispersive box with several poles
+        # the headline domain and launch shape, its 48^3 box holding two Lorentz
+        # poles and a Drude pole, then the maximum of 16 poles
+        poles_out = {"workload": "148^3 headline domain, flux plane recorded, its 48^3 box with 3 poles (2 Lorentz, "
+                                 "1 Drude) or 16 poles (10 Lorentz, 6 Drude), 1000 steps FP32",
+                     "launch_shape": tile}
+        for key in (3, 16):
+            specp = W.with_poles(W.lorentz_flux(), W.pole_set(key))
+            simp, elp, kmsp, nlp = run_forward(specp, "f32", stream, 1, 1, tile)
+            bp = RL.forward_bytes(specp, 4)
+            poles_out[f"poles_{key}"] = {
+                "mcups": round(specp.ncells * specp.n_steps / elp / 1e6, 1),
+                "avg_launch_us": round(kmsp / nlp * 1e3, 2),
+                "algorithmic_bytes_per_launch": bp,
+                "achieved_GBs": round(bp / (kmsp / nlp * 1e-3) / 1e9, 1)}
+            log(f"lorentz_flux with {key} poles: {specp.ncells * specp.n_steps / elp / 1e6:.0f} Mcell/s, "
+                f"{kmsp / nlp * 1e3:.1f} us/launch")
+            simp.close()
+            del simp
+        out["several_poles"] = poles_out
+
     print(json.dumps(out), flush=True)
 
 

@@ -23,6 +23,7 @@ def main(argv=None):
     ap.add_argument("--adjoint", action="store_true", help="time adjoint steps instead of forward steps")
     ap.add_argument("--copy-bytes", type=int, default=0, help="also run the device copy kernel on this many bytes")
     ap.add_argument("--monitors", action="store_true", help="record monitors while stepping")
+    ap.add_argument("--poles", type=int, default=0, help="put this pole set (3 or 16) in every dispersive box")
     args = ap.parse_args(argv)
 
     import torch
@@ -31,6 +32,8 @@ def main(argv=None):
     from . import binding as B
 
     spec = W.WORKLOADS[args.workload]()
+    if args.poles:
+        spec = W.with_poles(spec, W.pole_set(args.poles))
     kk, rr, zz = args.shape.split(",")
     stream = torch.cuda.current_stream().cuda_stream
     cap = max(args.steps + args.warmup + 2, spec.n_steps)

@@ -172,6 +172,25 @@ def pec_cavity(n: int = 32, n_steps: int = 200, seed: int = 1001, src=None, prob
     )
 
 
+def pole_set(n: int) -> List[PoleSpec]:
+    """Pole lists for a dispersive box: 3 = two Lorentz poles and a Drude pole;
+    16 (the maximum a box takes) = ten Lorentz poles spread over resonance and
+    damping and six Drude poles."""
+    if n == 3:
+        return [PoleSpec("lorentz", 0.9, 0.45, 0.05), PoleSpec("lorentz", 0.6, 0.7, 0.1),
+                PoleSpec("drude", 0.0, 0.35, 0.08)]
+    if n == 16:
+        return ([PoleSpec("lorentz", 0.05 + 0.03 * p, 0.2 + 0.05 * p, 0.01 + 0.01 * p) for p in range(10)] +
+                [PoleSpec("drude", 0.0, 0.05 + 0.02 * p, 0.02 + 0.02 * p) for p in range(6)])
+    raise ValueError("pole sets: 3 or 16")
+
+
+def with_poles(spec: "DomainSpec", poles: List[PoleSpec]) -> "DomainSpec":
+    """The same domain with every dispersive box holding ``poles``."""
+    spec.lorentz = [LorentzSpec(L.lo, L.hi, 0.0, 0.0, 0.0, poles=list(poles)) for L in spec.lorentz]
+    return spec
+
+
 def lorentz_flux(interior: int = 128, pml: int = 10, lorentz: int = 48, n_steps: int = 1000,
                  n_f: int = 16, shape: Optional[Tuple[int, int, int]] = None) -> DomainSpec:
     """FP32 forward: interior^3 + CPML, central Lorentz block, z-sheet source, far flux plane."""
