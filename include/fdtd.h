@@ -50,7 +50,9 @@ enum {
     FDTD_E_INVALID = -1,   /* bad argument or descriptor */
     FDTD_E_UNSTABLE = -2,  /* CFL eta > 0.99 (Eq. 2), non-finite or non-positive eps,
                               anisotropic eps inside an absorbing face violating the
-                              principal-axis rule of Section 2.3 */
+                              principal-axis rule of Section 2.3, a pole with
+                              omega_dt <= 0, gamma_dt < 0, a negative Lorentz strength
+                              or a non-finite parameter */
     FDTD_E_NOMEM = -3,     /* device memory request above budget, refused before allocating */
     FDTD_E_DEVICE = -4,    /* HIP runtime error; handle poisoned */
     FDTD_E_STATE = -5,     /* wrong step index for an adjoint step, empty or corrupt slot */
@@ -83,7 +85,11 @@ enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
    pole has strength delta_eps, resonance omega_dt = omega_0 dt and damping
    gamma_dt; a Drude pole has plasma frequency omega_dt = omega_p dt and
    damping gamma_dt (delta_eps unused): the Lorentz recursion with omega_0 -> 0
-   and delta_eps omega_0^2 -> omega_p^2. */
+   and delta_eps omega_0^2 -> omega_p^2.  fdtd_create returns FDTD_E_INVALID
+   for n_poles outside 1..FDTD_MAX_POLES or an unknown kind, and
+   FDTD_E_UNSTABLE for omega_dt <= 0, gamma_dt < 0, a negative Lorentz
+   delta_eps or a non-finite parameter.  Each pole's two history arrays cost
+   6 words per box cell. */
 enum { FDTD_POLE_LORENTZ = 0, FDTD_POLE_DRUDE = 1 };
 
 typedef struct {
