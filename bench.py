@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--large-adjoint", action="store_true",
                     help="run only the 512^3 + CPML adjoint study (FP32 vs BF16 checkpoints vs FP64) and print its JSON")
     ap.add_argument("--shape", default=None,
@@ -220,20 +220,21 @@ def main():
         from oracle import oracle as O
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         osim = O.OracleSim(spec)
+        osim.step(2)                       # first steps: page faults and thread start-up
         t0 = time.perf_counter()
-        osim.step(2)
-        per = (time.perf_counter() - t0) / 2
-        nsteps = int(max(2, min(spec.n_steps - 2, args.cpu_seconds / max(per, 1e-6))))
+        osim.step(3)
+        per = (time.perf_counter() - t0) / 3
+        nsteps = int(max(2, min(spec.n_steps - 5, args.cpu_seconds / max(per, 1e-6))))
         log(f"oracle: {per * 1e3:.0f} ms/step on {cores} threads, running {nsteps} more steps")
         t0 = time.perf_counter()
         osim.step(nsteps)
         cel = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(ncell * nsteps / cel / 1e6, 2), "unit": "Mcell-updates/s",
                                "cores": cores, "kind": "oracle",
-                               "sample": f"FP64 C oracle, same workload, time steps 3..{nsteps + 2} of 1000 "
+                               "sample": f"FP64 C oracle, same workload, time steps 6..{nsteps + 5} of 1000 "
                                          f"({cel:.1f} s), monitors recorded"}
         # FP32 GPU fields against the oracle at the same step
-        n_cmp = nsteps + 2
+        n_cmp = nsteps + 5
         cmp_sim = Simulation(spec, dtype="f32", stream=stream)
         cmp_sim.step(n_cmp)
         errs = {W.COMP_NAMES[q]: float(np.linalg.norm(cmp_sim.field(q) - osim.field(q)) /
