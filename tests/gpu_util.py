@@ -40,10 +40,11 @@ def flux_objective(sp):
     return J, g
 
 
-def gpu_gradient_store_all(spec, dtype, cot_fn, n=None):
-    """Adjoint on the HIP path with every forward state kept in a slot."""
+def gpu_gradient_store_all(spec, dtype, cot_fn, n=None, **kw):
+    """Adjoint on the HIP path with every forward state kept in a slot (kw:
+    launch options such as the kernel family)."""
     N = spec.n_steps if n is None else n
-    sim = Simulation(spec, dtype=dtype, n_ckpt=N + 1, max_steps=N)
+    sim = Simulation(spec, dtype=dtype, n_ckpt=N + 1, max_steps=N, **kw)
     sim.save(0)
     for t in range(N):
         sim.step(1)
