@@ -152,9 +152,9 @@ def test_spectral_radius_cpml_lorentz():
 
 
 # ---------------------------------------------------------------- P5
-def _lorentz_modal_matrix(S, w0, gam, deps, einf, shape=(12, 12, 3)):
+def _lorentz_modal_matrix(S, w0, gam, deps, einf, shape=(12, 12, 3), poles=None):
     spec = _blank(shape, S=S, eps=einf,
-                  lorentz=W.LorentzSpec((0, 0, 0), shape, deps, w0 * S, gam * S))
+                  lorentz=W.LorentzSpec((0, 0, 0), shape, deps, w0 * S, gam * S, poles=poles))
     sim = O.OracleSim(spec)
     phi, dx, dy, lam = _mode(shape, 2, 1, 1)
     # H shape of an Ez mode: Hx = d+_y phi, Hy = -d+_x phi
@@ -208,6 +208,28 @@ def test_lorentz_ade_second_order():
         wc = np.roots(coeffs)
         e = max(np.min(np.abs(wd - r)) for r in wc)
         errs.append(e)
+    errs = np.asarray(errs)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(ratios > 3.6) and np.all(ratios < 4.4), (errs, ratios)
+    assert errs[-1] < 1e-4
+
+
+def test_drude_ade_second_order():
+    """A box filled with one Drude pole: the modal recursion's frequencies
+    converge at second order in dt to the roots of w^2 eps(w) = lambda with
+    eps(w) = eps_inf - wp^2/(w^2 + i g w), i.e. the static root w = 0 and the
+    cubic eps_inf w^3 + i g eps_inf w^2 - (wp^2 + lambda) w - i g lambda = 0
+    (one relaxing and two propagating roots)."""
+    wp, gam, einf = 0.45, 0.03, 2.0
+    errs = []
+    for S in (0.2, 0.1, 0.05):
+        M, lam = _lorentz_modal_matrix(S, 0.0, gam, 0.0, einf,
+                                       poles=[W.PoleSpec("drude", 0.0, wp * S, gam * S)])
+        z = np.linalg.eigvals(M)
+        z = z[np.abs(z) > 1e-8]
+        wd = 1j * np.log(z) / S
+        wc = np.concatenate([[0.0], np.roots([einf, 1j * gam * einf, -(wp ** 2 + lam), -1j * gam * lam])])
+        errs.append(max(np.min(np.abs(wd - r)) for r in wc))
     errs = np.asarray(errs)
     ratios = errs[:-1] / errs[1:]
     assert np.all(ratios > 3.6) and np.all(ratios < 4.4), (errs, ratios)
