@@ -48,10 +48,13 @@ extern "C" {
 enum {
     FDTD_OK = 0,
     FDTD_E_INVALID = -1,   /* bad argument or descriptor */
-    FDTD_E_UNSTABLE = -2,  /* CFL eta > 0.99 (Eq. 2), non-finite or non-positive eps,
-                              anisotropic eps inside an absorbing face violating the
-                              principal-axis rule of Section 2.3, a pole with
-                              omega_dt <= 0, gamma_dt < 0, a negative Lorentz strength
+    FDTD_E_UNSTABLE = -2,  /* CFL eta > 0.99 (Eq. 2), non-finite eps or eps below 1
+                              (the step bound of Eq. 2 is the vacuum one; Section 2.3
+                              admits eigenvalues >= 1), anisotropic eps inside an
+                              absorbing face violating the principal-axis rule of
+                              Section 2.3, a pole with omega_dt <= 0, gamma_dt < 0, a
+                              negative Lorentz strength, a Lorentz omega_0 dt >= 2
+                              (its recursion then has a root outside the unit disc)
                               or a non-finite parameter */
     FDTD_E_NOMEM = -3,     /* device memory request above budget, refused before allocating */
     FDTD_E_DEVICE = -4,    /* HIP runtime error; handle poisoned */
@@ -88,8 +91,8 @@ enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
    and delta_eps omega_0^2 -> omega_p^2.  fdtd_create returns FDTD_E_INVALID
    for n_poles outside 1..FDTD_MAX_POLES or an unknown kind, and
    FDTD_E_UNSTABLE for omega_dt <= 0, gamma_dt < 0, a negative Lorentz
-   delta_eps or a non-finite parameter.  Each pole's two history arrays cost
-   6 words per box cell. */
+   delta_eps, a Lorentz omega_dt >= 2 or a non-finite parameter.  Each
+   pole's two history arrays cost 6 words per box cell. */
 enum { FDTD_POLE_LORENTZ = 0, FDTD_POLE_DRUDE = 1 };
 
 typedef struct {
@@ -129,8 +132,8 @@ typedef struct {
     double pml_m, pml_kappa_max, pml_sigma_max, pml_alpha_max;   /* grading */
     int32_t eps_kind;              /* FDTD_EPS_ISO | FDTD_EPS_DIAG */
     int32_t eps_lo[3], eps_hi[3];  /* box where eps is given */
-    const double *eps;             /* host [ncomp][bz][by][bx], ncomp 1 (ISO) or 3 (DIAG) */
-    double eps_bg;                 /* permittivity outside the box */
+    const double *eps;             /* host [ncomp][bz][by][bx], ncomp 1 (ISO) or 3 (DIAG), >= 1 */
+    double eps_bg;                 /* permittivity outside the box, >= 1 */
     int32_t n_lorentz;             /* 0 or 1 */
     fdtd_lorentz_desc lorentz;
     int32_t n_sources;             /* <= FDTD_MAX_SOURCES */
@@ -243,8 +246,34 @@ int fdtd_copy_probe(size_t bytes, int32_t reps, double *ms_per_copy);
    `word` of checkpoint slot `slot` with `value`. */
 int fdtd_checkpoint_corrupt(fdtd_t h, int32_t slot, size_t word, uint32_t value);
 
-/* Message of the last failing call on this handle (or of the last failing
-   create when h is NULL); valid until the next call. */
+/* Poynting flux through a z-plane from its spectra (Section 2.4), reduced
+   on the device: flux[f] = Re sum_p (Ex Hy* - Ey Hx*) over the n_pts plane
+   points, for spectra laid out as fdtd_monitor_dft GET returns those of a
+   flux monitor: complex128 [n_freq][4][n_pts], components Ex, Ey, Hx, Hy (H
+   already averaged over planes k and k-1).  `spectra` (read) and `flux`
+   (double [n_freq], written) are device pointers owned by the caller.  The
+   sums run in a fixed order with no atomics, so the result depends only on
+   the inputs.  Work is enqueued on `stream` (a hipStream_t, NULL = the
+   default stream); the call does not synchronise unless it allocates.
+   Partial sums need FDTD_FLUX_WORKSPACE_BYTES(n_freq, n_pts) bytes of
+   device memory: pass a caller-owned `workspace` of `workspace_bytes` >=
+   that, or NULL, and the call then takes them with hipMalloc and frees them
+   after synchronising the stream.  Returns FDTD_E_INVALID for a null
+   spectra/flux pointer, n_freq < 1 or n_pts < 1, FDTD_E_RANGE for a
+   workspace below the size, FDTD_E_NOMEM if the allocation fails and
+   FDTD_E_DEVICE for a launch error; fdtd_last_error(NULL) holds the message.
+   fdtd_monitor_dft FLUX uses the same reduction. */
+#define FDTD_FLUX_POINTS_PER_BLOCK 4096
+#define FDTD_FLUX_MAX_BLOCKS 256
+#define FDTD_FLUX_BLOCKS(n_pts) \
+    ((n_pts) >= (int64_t)FDTD_FLUX_POINTS_PER_BLOCK * FDTD_FLUX_MAX_BLOCKS ? FDTD_FLUX_MAX_BLOCKS \
+     : (int)(((n_pts) + FDTD_FLUX_POINTS_PER_BLOCK - 1) / FDTD_FLUX_POINTS_PER_BLOCK))
+#define FDTD_FLUX_WORKSPACE_BYTES(n_freq, n_pts) ((size_t)(n_freq) * (size_t)FDTD_FLUX_BLOCKS(n_pts) * 8u)
+int fdtd_flux_reduce(const double *spectra, int32_t n_freq, int64_t n_pts, double *flux, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* Message of the last failing call on this handle (or, when h is NULL, of
+   the last failing create or handle-free call); valid until the next call. */
 const char *fdtd_last_error(fdtd_t h);
 
 #ifdef __cplusplus

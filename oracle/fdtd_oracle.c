@@ -8,8 +8,8 @@
  * It is written for a reader holding the paper (TorchFDTD, arXiv 2609.30039):
  *   - Yee leapfrog, Eq. (1) of Section 2.1: E += S eps^-1 C^-(H) + s,
  *     then H -= S C^+(E).  Unit mesh, c = 1, so dt = S.
- *   - Convolutional PML (Section 2.2): one memory variable per transverse
- *     derivative inside each absorbing face; forward form psi <- b psi + c D,
+ *   - Convolutional PML (Section 2.2): a psi memory for each tangential
+ *     difference taken inside an absorbing slab; forward form psi <- b psi + c D,
  *     Dt = D / kappa + psi (the form whose transpose Section 3.1 prints).
  *   - PEC faces (Section 2.2): tangential E held at zero on the low boundary
  *     node; the high boundary node is not stored (ghost zero).

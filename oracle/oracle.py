@@ -262,9 +262,18 @@ class OracleSim:
         else:
             _lib.orc_step(C.byref(self.P), C.byref(st), 0, None, None, None, _ptr(self.work))
 
-    def step(self, n: int = 1, record: bool = True):
+    def step(self, n: int = 1, record: bool = True, store_f32: bool = False):
+        """Advance n steps.  store_f32 rounds the whole state to float32 after
+        every step while the arithmetic stays FP64: a model of float32 state
+        storage alone, used to measure the error floor any float32-state
+        solver carries (it is not part of the method)."""
         for _ in range(n):
             self.step_state(self.u, self.t)
+            if store_f32:
+                if getattr(self, "_u32", None) is None:
+                    self._u32 = np.zeros(self.u.shape, dtype=np.float32)
+                np.copyto(self._u32, self.u, casting="same_kind")   # round to nearest
+                np.copyto(self.u, self._u32)
             self.t += 1
             if record:
                 self._record(self.u, self.t)
@@ -369,22 +378,31 @@ class OracleSim:
         a = np.zeros_like(self.u)
         g = np.zeros((3, self.N))
         self._add_seeds(a, n_steps, cot)
+        # one state buffer per recursion depth, reused: a fresh copy per
+        # bisection would page in a whole new state every time
+        bufs: List[np.ndarray] = []
 
-        def reverse(lo: int, hi: int, ulo: np.ndarray):
+        def buffer(depth: int) -> np.ndarray:
+            while len(bufs) <= depth:
+                bufs.append(np.zeros_like(self.u))
+            return bufs[depth]
+
+        def reverse(lo: int, hi: int, ulo: np.ndarray, depth: int):
             if hi - lo == 1:
                 self.adjoint_step_state(a, ulo, g)
                 self._add_seeds(a, lo, cot)
                 return
             mid = (lo + hi) // 2
-            um = ulo.copy()
+            um = buffer(depth)
+            np.copyto(um, ulo)
             for t in range(lo, mid):
                 self.step_state(um, t)
-            reverse(mid, hi, um)
-            del um
-            reverse(lo, mid, ulo)
+            reverse(mid, hi, um, depth + 1)
+            # um is no longer needed: the lower half may reuse its buffer
+            reverse(lo, mid, ulo, depth)
 
         if n_steps > 0:
-            reverse(0, n_steps, u_start)
+            reverse(0, n_steps, u_start, 0)
         g = g.reshape((3,) + self.shape3)
         return (g, a) if return_adjoint else g
 

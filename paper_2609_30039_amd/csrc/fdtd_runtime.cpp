@@ -574,6 +574,10 @@ struct Handle : Base {
                     M.take(md.samples, (size_t)dft_block * md.rcomp * mh.npts * ts);
                     M.take(md.acc, mh.acc_elems * 8);
                     M.take(md.cot, mh.acc_elems * 8);
+                    if (md.kind == 1) {
+                        M.take(md.fpart, (size_t)md.nf * flux_blocks(mh.npts) * 8);
+                        M.take(md.fout, (size_t)md.nf * 8);
+                    }
                 }
             }
             if (asg) {   // plane monitors as the split H kernel samples them
@@ -861,8 +865,10 @@ struct Handle : Base {
             int l0 = s.pml[2 * a], l1 = s.pml[2 * a + 1];
             if (l0 < 0 || l1 < 0 || l0 + l1 > s.n[a]) return fail(FDTD_E_INVALID, "absorbing depth out of range");
         }
-        if (!(s.eps_bg > 0) || !std::isfinite(s.eps_bg))
-            return fail(FDTD_E_UNSTABLE, "background permittivity must be positive and finite");
+        // Eq. 2 bounds the step by the vacuum speed, so a permittivity below 1
+        // (a faster medium) breaks it; Section 2.3 admits eigenvalues >= 1 only
+        if (!(s.eps_bg >= 1.0) || !std::isfinite(s.eps_bg))
+            return fail(FDTD_E_UNSTABLE, "background permittivity must be finite and at least 1");
         if (s.eps_kind != FDTD_EPS_ISO && s.eps_kind != FDTD_EPS_DIAG) return fail(FDTD_E_INVALID, "eps_kind");
         h.ncomp_eps = s.eps_kind == FDTD_EPS_DIAG ? 3 : 1;
         size_t ebox = 1;
@@ -875,7 +881,7 @@ struct Handle : Base {
         if (ebox) {
             h.eps.assign(s.eps, s.eps + ebox * h.ncomp_eps);
             for (double e : h.eps)
-                if (!(e > 0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be positive and finite");
+                if (!(e >= 1.0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be finite and at least 1");
             if (h.ncomp_eps == 3) {
                 // Section 2.3: a tensor inside an absorbing face needs the face normal to be a
                 // principal axis whose eigenvalue is not the intermediate one.
@@ -910,6 +916,10 @@ struct Handle : Base {
                     (pd.kind == FDTD_POLE_LORENTZ && (!(pd.delta_eps >= 0) || !std::isfinite(pd.delta_eps))))
                     return fail(FDTD_E_UNSTABLE, "pole parameters must be finite with omega > 0, gamma >= 0, "
                                                  "delta_eps >= 0");
+                // a Lorentz pole's recursion z^2 - alpha z - xi keeps its roots in the unit
+                // disc only for (omega_0 dt)^2 < 4, at any damping
+                if (pd.kind == FDTD_POLE_LORENTZ && !(pd.omega_dt < 2.0))
+                    return fail(FDTD_E_UNSTABLE, "Lorentz omega_0 dt must be below 2");
             }
         }
         if (s.n_sources < 0 || s.n_sources > FDTD_MAX_SOURCES) return fail(FDTD_E_INVALID, "too many sources");
@@ -1276,34 +1286,19 @@ struct Handle : Base {
                     return fail(FDTD_E_DEVICE, "probe copy failed");
                 return sync("probe get");
             }
-            std::vector<double> acc(mh.acc_elems);
-            if (hipMemcpyAsync(acc.data(), m.acc, mh.acc_elems * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
-                return fail(FDTD_E_DEVICE, "spectra copy failed");
-            int rc = sync("spectra get");
-            if (rc) return rc;
             if (op == FDTD_MON_GET) {
                 if (bytes < mh.acc_elems * 8) return fail(FDTD_E_RANGE, "buffer too small for spectra");
-                std::memcpy(buf, acc.data(), mh.acc_elems * 8);
-                return FDTD_OK;
+                if (hipMemcpyAsync(buf, m.acc, mh.acc_elems * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "spectra copy failed");
+                return sync("spectra get");
             }
             if (m.kind != 1) return fail(FDTD_E_INVALID, "flux needs a flux monitor");
             if (bytes < (size_t)m.nf * 8) return fail(FDTD_E_RANGE, "buffer too small for flux");
-            // F(w) = Re sum (Ex Hy* - Ey Hx*), components (Ex, Ey, Hx, Hy)
-            double* out = (double*)buf;
-            size_t np = mh.npts;
-            for (int f = 0; f < m.nf; ++f) {
-                const double* a = acc.data() + (size_t)f * 4 * np * 2;
-                double s = 0;
-                for (size_t q = 0; q < np; ++q) {
-                    double exr = a[(0 * np + q) * 2], exi = a[(0 * np + q) * 2 + 1];
-                    double eyr = a[(1 * np + q) * 2], eyi = a[(1 * np + q) * 2 + 1];
-                    double hxr = a[(2 * np + q) * 2], hxi = a[(2 * np + q) * 2 + 1];
-                    double hyr = a[(3 * np + q) * 2], hyi = a[(3 * np + q) * 2 + 1];
-                    s += (exr * hyr + exi * hyi) - (eyr * hxr + eyi * hxi);
-                }
-                out[f] = s;
-            }
-            return FDTD_OK;
+            // F(w) = Re sum (Ex Hy* - Ey Hx*) over the plane, reduced on the device
+            launch_flux(m.acc, m.nf, mh.npts, m.fpart, m.fout, st);
+            if (hipMemcpyAsync(buf, m.fout, (size_t)m.nf * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "flux copy failed");
+            return sync("flux");
         }
         if (op == FDTD_MON_SET_COTANGENT) {
             if (m.kind == 0) {
@@ -1375,7 +1370,7 @@ struct Handle : Base {
     int validate_eps_only(const fdtd_domain_desc& s, DomHost& h, const double* eps) {
         std::vector<double> v(eps, eps + h.eps.size());
         for (double e : v)
-            if (!(e > 0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be positive and finite");
+            if (!(e >= 1.0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be finite and at least 1");
         if (h.ncomp_eps == 3) {
             size_t ebox = h.eps.size() / 3;
             int bx = s.eps_hi[0] - s.eps_lo[0], by = s.eps_hi[1] - s.eps_lo[1];
@@ -1595,8 +1590,38 @@ int fdtd_copy_probe(size_t bytes, int32_t reps, double* ms_per_copy) {
     return rc;
 }
 
+int fdtd_flux_reduce(const double* spectra, int32_t n_freq, int64_t n_pts, double* flux, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+    if (!spectra || !flux || n_freq < 1 || n_pts < 1) {
+        g_create_error = "fdtd_flux_reduce: null pointer, n_freq < 1 or n_pts < 1";
+        return FDTD_E_INVALID;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = (size_t)n_freq * flux_blocks(n_pts) * 8;
+    void* part = workspace;
+    const bool own = !workspace;
+    if (own) {
+        if (hipMalloc(&part, need) != hipSuccess) {
+            (void)hipGetLastError();
+            g_create_error = "fdtd_flux_reduce: workspace allocation failed";
+            return FDTD_E_NOMEM;
+        }
+    } else if (workspace_bytes < need) {
+        g_create_error = "fdtd_flux_reduce: workspace smaller than FDTD_FLUX_WORKSPACE_BYTES";
+        return FDTD_E_RANGE;
+    }
+    launch_flux(spectra, n_freq, n_pts, (double*)part, flux, st);
+    int rc = hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_E_DEVICE;
+    if (own) {
+        if (hipStreamSynchronize(st) != hipSuccess) rc = FDTD_E_DEVICE;
+        (void)hipFree(part);
+    }
+    if (rc) g_create_error = "fdtd_flux_reduce: HIP launch failed";
+    return rc;
+}
+
 const char* fdtd_last_error(fdtd_t h) {
-    if (!h || !h->impl) return g_create_error.c_str();
+    if (!h || !h->impl) return g_create_error.c_str();   // failing create or handle-free call
     return h->impl->err.c_str();
 }
 

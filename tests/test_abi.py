@@ -53,6 +53,35 @@ def test_nonpositive_eps_refused():
     _refused(s, B.FDTD_E_UNSTABLE)
 
 
+def test_eps_below_one_refused():
+    """Eq. 2's step bound is the vacuum one: a permittivity below 1 in the
+    box or in the background is refused (the oracle's one-step operator grows
+    at 0.9), and 1 itself passes validation (then the tiny budget refuses)."""
+    s = _spec()
+    s.eps = s.eps.copy()
+    s.eps[0, 1, 2, 3] = 0.99
+    _refused(s, B.FDTD_E_UNSTABLE)
+    _refused(_spec(eps_bg=0.5), B.FDTD_E_UNSTABLE)
+    s.eps[0, 1, 2, 3] = 1.0
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([s], B.FDTD_F32, mem_budget_bytes=1.0)
+    assert e.value.code == B.FDTD_E_NOMEM
+
+
+def test_lorentz_resonance_bound_refused():
+    """A Lorentz pole with omega_0 dt >= 2 is refused (its recursion has a
+    root outside the unit disc; the oracle's operator grows at 2.01 and keeps
+    radius 1 at 1.99); a Drude pole has no such bound."""
+    def with_pole(p):
+        return _spec(lorentz=[W.LorentzSpec((2, 2, 2), (5, 5, 5), 0.0, 0.0, 0.0, poles=[p])])
+    _refused(with_pole(W.PoleSpec("lorentz", 1.0, 2.0, 0.05)), B.FDTD_E_UNSTABLE)
+    _refused(with_pole(W.PoleSpec("lorentz", 1.0, 3.0, 0.0)), B.FDTD_E_UNSTABLE)
+    for p in (W.PoleSpec("lorentz", 1.0, 1.99, 0.0), W.PoleSpec("drude", 0.0, 3.0, 0.05)):
+        with pytest.raises(B.FdtdError) as e:
+            B.fdtd_create([with_pole(p)], B.FDTD_F32, mem_budget_bytes=1.0)
+        assert e.value.code == B.FDTD_E_NOMEM
+
+
 def test_tensor_rule_in_absorbing_face():
     """Diagonal eps inside an absorbing face whose normal eigenvalue is the
     intermediate one is refused (Section 2.3); a non-intermediate one passes
