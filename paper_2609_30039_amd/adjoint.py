@@ -101,7 +101,9 @@ class FDTDFunction:
     forward(eps) uploads eps, runs the recording sweep and returns one complex
     tensor per plane monitor; backward(grad spectra) sets the cotangents
     (torch's dJ/dRe + i dJ/dIm convention), runs the reverse sweep and
-    returns dJ/deps (zero outside the gradient box)."""
+    returns dJ/deps (zero outside the gradient box).  The checkpoints live in
+    the Simulation, so backward raises if another forward sweep ran on it in
+    between."""
 
     @staticmethod
     def build():
@@ -115,6 +117,7 @@ class FDTDFunction:
                 plan = RevolvePlan(spec.n_steps, n_slots)
                 ctx.sim, ctx.plan = sim, plan
                 ctx.last = forward_record(sim, plan)
+                ctx.generation = sim.generation
                 ctx.eps_shape = tuple(eps.shape)
                 ctx.device, ctx.dtype = eps.device, eps.dtype
                 outs = []
@@ -129,6 +132,11 @@ class FDTDFunction:
             @staticmethod
             def backward(ctx, *grads):
                 sim, plan = ctx.sim, ctx.plan
+                if sim.generation != ctx.generation:
+                    # another forward (or a new eps) replaced the checkpoints and
+                    # the permittivity this backward pass would replay
+                    raise RuntimeError("the Simulation ran another forward sweep since this output was computed; "
+                                       "use one Simulation per pending backward pass")
                 spec = sim.specs[0]
                 for mi, g in zip(ctx.mons, grads):
                     if g is None:

@@ -25,6 +25,9 @@ class Simulation:
         if max_steps is None:
             max_steps = max(max(s.n_steps for s in self.specs), 1)
         self.max_steps = max_steps
+        # bumped by every reset and permittivity upload: a recorded forward
+        # sweep is valid for a backward pass only while it is unchanged
+        self.generation = 0
         self.h = B.fdtd_create(self.specs, dt, n_ckpt, storage, ckpt_checksum, max_steps, kern, dft_block,
                                graph_chunk, stream, mem_budget_bytes, tile_rows, tile_kz)
 
@@ -56,6 +59,7 @@ class Simulation:
         B.fdtd_checkpoint_restore(self.h, slot)
 
     def reset(self):
+        self.generation += 1
         B.fdtd_reset(self.h)
 
     @property
@@ -122,6 +126,7 @@ class Simulation:
         return out
 
     def set_eps(self, eps: np.ndarray, domain: int = 0):
+        self.generation += 1
         B.fdtd_set_eps(self.h, domain, eps)
 
     def timing(self, op: int):

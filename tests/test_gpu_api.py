@@ -40,6 +40,29 @@ def test_autograd_bridge_equals_direct_gradient():
     assert np.isclose(J.item(), float(np.sum(np.abs(ref.spectra(0)) ** 2)), rtol=1e-13)
 
 
+def test_autograd_backward_refuses_a_replaced_forward():
+    """Two differentiable forwards on one Simulation: the second replaces the
+    checkpoints and eps that the first output's backward would replay, so that
+    backward raises instead of returning the second run's gradient; the
+    second output's backward still equals the direct gradient at its eps."""
+    import torch
+    spec = _spec()
+    N, slots = spec.n_steps, 7
+    sim = Simulation(spec, dtype="f64", n_ckpt=slots)
+    eps1 = torch.tensor(spec.eps, dtype=torch.float64, requires_grad=True)
+    eps2 = torch.tensor(spec.eps * 1.1, dtype=torch.float64, requires_grad=True)
+    (X1,) = A.differentiable_spectra(eps1, sim, slots)
+    (X2,) = A.differentiable_spectra(eps2, sim, slots)
+    with pytest.raises(RuntimeError, match="another forward"):
+        (X1.real ** 2 + X1.imag ** 2).sum().backward()
+    (X2.real ** 2 + X2.imag ** 2).sum().backward()
+    spec2 = _spec()
+    spec2.eps = spec.eps * 1.1
+    direct = A.gradient(Simulation(spec2, dtype="f64", n_ckpt=slots), N, slots,
+                        lambda s: {(0, 0): 2.0 * s.spectra(0)})[0]
+    assert np.array_equal(eps2.grad.numpy(), direct)
+
+
 def test_autotune_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     cache = tmp_path / "tune.json"
     monkeypatch.setenv("FDTD_TUNE_CACHE", str(cache))
