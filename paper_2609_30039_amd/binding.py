@@ -33,7 +33,15 @@ EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_be
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
-            "fdtd_last_error"]
+            "fdtd_flux_reduce", "fdtd_last_error"]
+
+FDTD_FLUX_POINTS_PER_BLOCK, FDTD_FLUX_MAX_BLOCKS = 4096, 256
+
+
+def flux_workspace_bytes(n_freq: int, n_pts: int) -> int:
+    """FDTD_FLUX_WORKSPACE_BYTES of the header."""
+    nb = min(FDTD_FLUX_MAX_BLOCKS, max(1, -(-n_pts // FDTD_FLUX_POINTS_PER_BLOCK)))
+    return n_freq * nb * 8
 
 
 class FdtdError(RuntimeError):
@@ -114,6 +122,7 @@ def lib():
         L.fdtd_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.fdtd_checkpoint_corrupt.argtypes = [vp, i32, sz, u32]
         L.fdtd_copy_probe.argtypes = [sz, i32, C.POINTER(C.c_double)]
+        L.fdtd_flux_reduce.argtypes = [vp, i32, C.c_int64, vp, vp, sz, vp]
         L.fdtd_last_error.argtypes = [vp]
         L.fdtd_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -299,6 +308,13 @@ def fdtd_copy_probe(nbytes: int, reps: int) -> float:
     ms = C.c_double()
     _chk(lib().fdtd_copy_probe(nbytes, reps, C.byref(ms)), None)
     return ms.value
+
+
+def fdtd_flux_reduce(spectra_ptr: int, n_freq: int, n_pts: int, flux_ptr: int, workspace_ptr=None,
+                     workspace_bytes: int = 0, stream=None):
+    """Device pointers in, device pointer out (see include/fdtd.h)."""
+    return _chk(lib().fdtd_flux_reduce(spectra_ptr, n_freq, n_pts, flux_ptr, workspace_ptr, workspace_bytes,
+                                       stream), None)
 
 
 def fdtd_checkpoint_corrupt(h, slot: int, word: int, value: int):

@@ -19,6 +19,8 @@
 #include <float.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "fdtd_dev.h"
 #include "fdtd_launch.h"
 
@@ -1951,6 +1953,44 @@ __global__ void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restr
     for (; q < n_words; q += stride) dst[q] = src[q];
 }
 
+// ---- Poynting flux of a plane spectrum (Section 2.4):
+//   F(w_f) = Re sum_p (Ex Hy* - Ey Hx*),  spectra [nf][4][np] complex128.
+// Two launches, no atomics, a fixed summation order: block (b, f) sums its
+// contiguous run of points (each thread a strided subset), reduces across
+// its wave with xor shuffles and across its 4 waves through LDS, and writes
+// one partial; the second launch reduces the nblk partials of frequency f
+// the same way.  The result depends only on (nf, np), never on timing.
+__device__ __forceinline__ double block_sum(double s) {
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void __launch_bounds__(256) k_flux_partial(const double2* __restrict__ sp, long long np, int nblk,
+                                                      double* __restrict__ part) {
+    const int f = blockIdx.y, b = blockIdx.x;
+    const double2* a = sp + (long long)f * 4 * np;
+    const long long chunk = (np + nblk - 1) / nblk, p0 = (long long)b * chunk, p1 = min(np, p0 + chunk);
+    double s = 0.0;
+    for (long long q = p0 + threadIdx.x; q < p1; q += 256) {
+        const double2 ex = a[q], ey = a[np + q], hx = a[2 * np + q], hy = a[3 * np + q];
+        s += (ex.x * hy.x + ex.y * hy.y) - (ey.x * hx.x + ey.y * hx.y);
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[(long long)f * nblk + b] = s;
+}
+
+__global__ void __launch_bounds__(256) k_flux_final(const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ out) {
+    const int f = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += part[(long long)f * nblk + b];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[f] = s;
+}
+
 // max |x| of an FP32 array into *out (as ordered bits; out pre-zeroed)
 // ---- BF16 checkpoint slots.  The forward state arrays of all domains are
 // listed in one table (BfArr); every array is cut into chunks of kBfChunk
@@ -2207,6 +2247,17 @@ void launch_bf16_restore(const BfArr* arr, int narr, int nblk, long long shift, 
                          const char* slot, hipStream_t s) {
     if (narr == 0 || nblk == 0) return;
     hipLaunchKernelGGL(k_bf16_unpack, dim3(nblk), dim3(256), 0, s, arr, narr, shift, scale, slot);
+}
+
+int flux_blocks(long long npts) {
+    const long long b = (npts + kFluxPoints - 1) / kFluxPoints;
+    return (int)std::max(1LL, std::min((long long)kFluxMaxBlocks, b));
+}
+
+void launch_flux(const double* spectra, int nf, long long npts, double* part, double* out, hipStream_t s) {
+    const int nblk = flux_blocks(npts);
+    k_flux_partial<<<dim3(nblk, nf), 256, 0, s>>>((const double2*)spectra, npts, nblk, part);
+    k_flux_final<<<nf, 256, 0, s>>>(part, nblk, out);
 }
 
 void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s) {

@@ -21,6 +21,8 @@ struct MonDev {
     double* cot;                      // cotangents, same layout (probe: [max_steps])
     double* trace;                    // probe samples [ntrace]
     int ntrace;
+    double* fpart;                    // flux: partial sums [nf][flux_blocks(npts)]
+    double* fout;                     // flux: F(w) [nf]
 };
 
 // One stepping launch over all domains: kernel 1 = split, 2 = fused; rows =
@@ -100,5 +102,12 @@ void launch_bf16_save(const BfArr* arr, int narr, int nblk, long long shift, flo
 void launch_bf16_restore(const BfArr* arr, int narr, int nblk, long long shift, const unsigned int* scale,
                          const char* slot, hipStream_t s);
 void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s);
+// Poynting flux per frequency of spectra [nf][4][npts] complex128 (device):
+// flux_blocks(npts) partial sums per frequency in part (nf * flux_blocks
+// doubles), the result in out[nf]
+constexpr int kFluxPoints = 4096;      // plane points per block of the first pass
+constexpr int kFluxMaxBlocks = 256;
+int flux_blocks(long long npts);
+void launch_flux(const double* spectra, int nf, long long npts, double* part, double* out, hipStream_t s);
 
 }  // namespace fdtd
