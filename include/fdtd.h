@@ -272,6 +272,20 @@ int fdtd_checkpoint_corrupt(fdtd_t h, int32_t slot, size_t word, uint32_t value)
 int fdtd_flux_reduce(const double *spectra, int32_t n_freq, int64_t n_pts, double *flux, void *workspace,
                      size_t workspace_bytes, void *stream);
 
+/* fdtd_flux_reduce for callers that cannot allocate device memory: code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc.  Same arguments and results as fdtd_flux_reduce (bitwise), but
+   the partial sums live in a file-scope device array of
+   FDTD_FLUX_SCRATCH_BYTES that every GPU the library runs on holds until the
+   process ends, so the call allocates nothing and never synchronises.  It
+   returns FDTD_E_RANGE when FDTD_FLUX_WORKSPACE_BYTES(n_freq, n_pts) exceeds
+   that size (n_freq * blocks <= 8192), FDTD_E_INVALID for a null pointer,
+   n_freq < 1 or n_pts < 1, FDTD_E_DEVICE for a HIP error.  All calls on one
+   GPU share its array: calls that overlap on one GPU (other streams or
+   threads) race and must be serialised by the caller. */
+#define FDTD_FLUX_SCRATCH_BYTES 65536
+int fdtd_flux_reduce_noalloc(const double *spectra, int32_t n_freq, int64_t n_pts, double *flux, void *stream);
+
 /* Message of the last failing call on this handle (or, when h is NULL, of
    the last failing create or handle-free call); valid until the next call. */
 const char *fdtd_last_error(fdtd_t h);

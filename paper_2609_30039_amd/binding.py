@@ -33,9 +33,10 @@ EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_be
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
-            "fdtd_flux_reduce", "fdtd_last_error"]
+            "fdtd_flux_reduce", "fdtd_flux_reduce_noalloc", "fdtd_last_error"]
 
 FDTD_FLUX_POINTS_PER_BLOCK, FDTD_FLUX_MAX_BLOCKS = 4096, 256
+FDTD_FLUX_SCRATCH_BYTES = 65536
 
 
 def flux_workspace_bytes(n_freq: int, n_pts: int) -> int:
@@ -102,6 +103,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libfdtd.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one libfdtd links against; whichever loads first serves the process.
+        # Load torch's first, so that torch's device memory and streams and
+        # this library share one runtime whatever the import order.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, u32, sz = C.c_void_p, C.c_int32, C.c_uint32, C.c_size_t
         L.fdtd_create.argtypes = [C.POINTER(DomainDesc), i32, C.POINTER(Options), C.POINTER(vp)]
@@ -123,6 +129,7 @@ def lib():
         L.fdtd_checkpoint_corrupt.argtypes = [vp, i32, sz, u32]
         L.fdtd_copy_probe.argtypes = [sz, i32, C.POINTER(C.c_double)]
         L.fdtd_flux_reduce.argtypes = [vp, i32, C.c_int64, vp, vp, sz, vp]
+        L.fdtd_flux_reduce_noalloc.argtypes = [vp, i32, C.c_int64, vp, vp]
         L.fdtd_last_error.argtypes = [vp]
         L.fdtd_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -315,6 +322,11 @@ def fdtd_flux_reduce(spectra_ptr: int, n_freq: int, n_pts: int, flux_ptr: int, w
     """Device pointers in, device pointer out (see include/fdtd.h)."""
     return _chk(lib().fdtd_flux_reduce(spectra_ptr, n_freq, n_pts, flux_ptr, workspace_ptr, workspace_bytes,
                                        stream), None)
+
+
+def fdtd_flux_reduce_noalloc(spectra_ptr: int, n_freq: int, n_pts: int, flux_ptr: int, stream=None):
+    """fdtd_flux_reduce with the library's fixed device scratch (no allocation)."""
+    return _chk(lib().fdtd_flux_reduce_noalloc(spectra_ptr, n_freq, n_pts, flux_ptr, stream), None)
 
 
 def fdtd_checkpoint_corrupt(h, slot: int, word: int, value: int):

@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "fdtd_dev.h"
 #include "fdtd_launch.h"
@@ -2247,6 +2248,34 @@ void launch_bf16_restore(const BfArr* arr, int narr, int nblk, long long shift, 
                          const char* slot, hipStream_t s) {
     if (narr == 0 || nblk == 0) return;
     hipLaunchKernelGGL(k_bf16_unpack, dim3(nblk), dim3(256), 0, s, arr, narr, shift, scale, slot);
+}
+
+// Partial sums of the allocation-free flux entry point.  Every GPU the
+// library runs on holds its own copy until the process ends; calls on one GPU
+// share it (each call rewrites every partial it reads, so nothing has to be
+// cleared between calls; calls that overlap on one GPU race).  Host code
+// never passes this name to a kernel: it is a host-side stand-in, and the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[kFluxScratchBytes / 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+double* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+}  // namespace
+
+int flux_scratch(double** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+    std::call_once(g_scratch_once[dev], [dev] {   // with that device current
+        void* p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = (double*)p;
+    });
+    if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev]) return -1;
+    *out = g_scratch_ptr[dev];
+    return 0;
 }
 
 int flux_blocks(long long npts) {

@@ -109,5 +109,9 @@ constexpr int kFluxPoints = 4096;      // plane points per block of the first pa
 constexpr int kFluxMaxBlocks = 256;
 int flux_blocks(long long npts);
 void launch_flux(const double* spectra, int nf, long long npts, double* part, double* out, hipStream_t s);
+// device address (on the current device) of the file-scope scratch array of
+// kFluxScratchBytes that the allocation-free flux entry point uses; 0 on success
+constexpr size_t kFluxScratchBytes = 65536;
+int flux_scratch(double** out);
 
 }  // namespace fdtd

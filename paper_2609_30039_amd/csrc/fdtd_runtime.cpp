@@ -1620,6 +1620,28 @@ int fdtd_flux_reduce(const double* spectra, int32_t n_freq, int64_t n_pts, doubl
     return rc;
 }
 
+int fdtd_flux_reduce_noalloc(const double* spectra, int32_t n_freq, int64_t n_pts, double* flux, void* stream) {
+    if (!spectra || !flux || n_freq < 1 || n_pts < 1) {
+        g_create_error = "fdtd_flux_reduce_noalloc: null pointer, n_freq < 1 or n_pts < 1";
+        return FDTD_E_INVALID;
+    }
+    if ((size_t)n_freq * flux_blocks(n_pts) * 8 > kFluxScratchBytes) {
+        g_create_error = "fdtd_flux_reduce_noalloc: n_freq x blocks exceeds FDTD_FLUX_SCRATCH_BYTES";
+        return FDTD_E_RANGE;
+    }
+    double* part = nullptr;
+    if (flux_scratch(&part)) {
+        g_create_error = "fdtd_flux_reduce_noalloc: no device address for the scratch array";
+        return FDTD_E_DEVICE;
+    }
+    launch_flux(spectra, n_freq, n_pts, part, flux, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess) {
+        g_create_error = "fdtd_flux_reduce_noalloc: HIP launch failed";
+        return FDTD_E_DEVICE;
+    }
+    return FDTD_OK;
+}
+
 const char* fdtd_last_error(fdtd_t h) {
     if (!h || !h->impl) return g_create_error.c_str();   // failing create or handle-free call
     return h->impl->err.c_str();
