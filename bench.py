@@ -1,21 +1,39 @@
 #!/usr/bin/env python
 """Benchmark of the FDTD hot path on one MI355X.
 
-Headline (value): FP32 forward throughput in Mcell-updates/s on the 128^3 +
-10-cell CPML workload with a 48^3 Lorentz block, a z-sheet source and a
-16-frequency flux plane, 1000 time steps (one "step" of this benchmark = one
-complete 1000-time-step solve from rest, monitors included).  Alongside: the
-dominant kernel against the HBM roofline (HIP events on the library stream),
-the FP64 oracle on the host cores, the FP64 GPU path, the adjoint sweep with
-binomial replay on the 192^3 + CPML design-patch workload, and a 512^3 + CPML
-forward whose working set is far beyond the on-die cache.
+Headline (value): FP32 forward throughput in Mcell-updates/s on the largest
+workload: 536^3 = 512^3 + 12-cell CPML, diagonal eps with each component in
+[1,5], a central 128^3 one-pole Lorentz box, an Ex sheet source and an Ex
+64x64 patch monitor over 8 frequencies, 4000 time steps per solve.  One
+"step" of this benchmark is 100 time steps of that solve with the monitor
+recording (two captured 50-step chunks); the solve restarts from rest after
+its 4000 steps.  Inputs are resident in HBM before the timed region.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--shape K,R,Z]
+Alongside, on the same JSON line:
+  * roofline: the stepping kernels of one time step against the HBM peak,
+    timed live with HIP events on the library stream, and the HBM traffic of
+    the same launch shape from the committed counter summary in profiles/;
+  * cpu_baseline: the FP64 C oracle on the host, on all cores and on one
+    core, forward and adjoint steps of the same workload (a bounded sample);
+  * adjoint_536: the same workload's reverse sweep over 4000 steps with
+    binomial replay in 32 FP32 slots and in 32 BF16 slots, gradient against
+    an FP64 reference (20 slots) on a 64^3 subsample of the gradient box;
+  * cache_resident_148: the 148^3 one-pole Lorentz workload (its working set
+    fits the 256 MB Infinity Cache), its FP32 fields and flux after 1000
+    steps against the oracle's stored record, the FP64 GPU path, and the
+    full-solve time from construction to the final transfer (median of 3);
+  * adjoint_212: the 212^3 design workload's reverse sweep (24 slots) and its
+    gradient against the oracle's stored record; the 48-domain ragged batch;
+    the 148^3 workload with 3 and 16 poles.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--no-adjoint] [--shape K,R,Z]
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -23,6 +41,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 import numpy as np
+
+BENCH_CHUNK = 50           # captured time steps per graph
+BENCH_STEP = 100           # time steps per benchmark step
 
 
 def log(msg):
@@ -37,10 +58,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_hash, tile, name="fwd_lorentz_flux_f32_pmc.json"):
-    """HBM bytes per step of the stepping kernels from a committed PMC summary,
-    only if it was taken on the current kernel source and the launch shape
-    that was timed."""
+def traffic_from_profiles(kernel_hash, tile, name):
+    """HBM bytes per time step of the stepping kernels from a committed counter
+    summary, only if it was taken on the current kernel source and the launch
+    shape that was timed."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
@@ -51,6 +72,17 @@ def traffic_from_profiles(kernel_hash, tile, name="fwd_lorentz_flux_f32_pmc.json
     key = f"{tile.get('kernel')},{tile.get('tile_rows', 0)},{tile.get('tile_kz', 0)}"
     e = d.get("per_launch_shape", {}).get(key)
     return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def run_forward(spec, dtype, stream, K, Wm, tile=None, graph_chunk=32):
@@ -83,11 +115,150 @@ def run_forward(spec, dtype, stream, K, Wm, tile=None, graph_chunk=32):
     return sim, el, kms, nl
 
 
-def large_adjoint(stream, log):
-    """512^3 + 12-cell CPML, diagonal eps, 128^3 Lorentz box, |DFT Ex|^2 on a
-    64x64 patch, 4000 steps: binomial replay with 32 FP32 slots and with 32 BF16
-    slots (per-array max-abs scale), and an FP64 reference (20 slots, to fit in
-    memory); gradients compared on a 64^3 subsample of the gradient box."""
+SPLIT_SHAPES = [{"kernel": "split", "tile_rows": r, "tile_kz": z} for (r, z) in ((8, 2), (8, 3), (8, 4), (8, 8), (0, 8))]
+
+
+# ------------------------------------------------------------------ headline
+def headline(args, stream, khash):
+    """The 536^3 workload: K benchmark steps of 100 time steps each after W
+    warm-up steps, then 100 eagerly launched time steps with HIP events
+    around each step's stepping launches."""
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import roofline as RL
+    from paper_2609_30039_amd import autotune as AT
+    from paper_2609_30039_amd.sim import Simulation
+    spec = W.anisotropic_lorentz()
+    if args.shape:
+        kk, rr, zz = args.shape.split(",")
+        tile = {"kernel": kk, "tile_rows": int(rr), "tile_kz": int(zz)}
+    else:
+        tile = AT.tune(spec, "f32", stream=stream, log=log, steps=3, candidates=SPLIT_SHAPES)
+    K, Wm = args.steps, args.warmup
+    log(f"headline: anisotropic_lorentz {spec.shape} FP32, {BENCH_STEP} time steps per step, warmup {Wm}, "
+        f"timed {K}, launch shape {tile}")
+    sim = Simulation(spec, dtype="f32", stream=stream, graph_chunk=BENCH_CHUNK if tile["kernel"] == "split" else 0,
+                     **tile)
+    N = spec.n_steps
+    done = [0]
+
+    def bench_step():
+        if done[0] + BENCH_STEP > N:
+            sim.reset()
+            done[0] = 0
+        sim.step(BENCH_STEP, record=True)
+        done[0] += BENCH_STEP
+
+    for _ in range(Wm):
+        bench_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        bench_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.timing(1)
+    bench_step()
+    kms, nl = sim.timing(2)
+    sim.timing(0)
+    sim.close()
+    ncell = spec.ncells
+    mcups = ncell * BENCH_STEP * K / el / 1e6
+    avg_ms = kms / nl
+    bytes_step = RL.forward_bytes(spec, 4)
+    achieved = bytes_step / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(khash, tile, "fwd_anisotropic_lorentz_f32_pmc.json")
+    log(f"headline: {el / K * 1e3:.1f} ms per step, {mcups:.0f} Mcell-upd/s, stepping kernels {avg_ms * 1e3:.1f} us "
+        f"per time step, {achieved:.0f} GB/s algorithmic")
+    out = {
+        "metric": "Mcell-updates/s fwd & adjoint (FP32 vs FP64), % HBM roofline, grad rel. err",
+        "value": round(mcups, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(el / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "536^3 cells (512^3 + 12-cell CPML, m=3, kappa_max=5), diagonal eps in [1,5] "
+                               "(seed 1005), 128^3 one-pole Lorentz box, Ex sheet source, Ex 64x64 patch monitor "
+                               "(8 frequencies); one step = 100 of the solve's 4000 time steps",
+                   "cells": ncell, "time_steps_per_step": BENCH_STEP, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
+                     "kernel": ("split E and H kernels (k_fwd_e with the Lorentz-box blocks leading, then k_fwd_h)"
+                                if tile["kernel"] == "split" else "fused single-pass tile kernels")
+                               + ": all stepping launches of one time step",
+                     "launch_shape": tile,
+                     "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_step,
+                     "kernel_source_hash": khash},
+    }
+    return spec, tile, out
+
+
+# ------------------------------------------------------------------ CPU oracle
+def cpu_baseline(spec, budget_s=30.0):
+    """The FP64 oracle as it stands on the host's cores: forward steps with
+    every core and with one, and adjoint steps with every core, of the same
+    536^3 workload (a bounded sample of its 4000 steps)."""
+    import ctypes
+    from oracle import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    gomp = None
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        pass
+    t0 = time.perf_counter()
+    osim = O.OracleSim(spec)
+    osim.step(2)                       # first steps: page faults and thread start-up
+    log(f"oracle: set-up and 2 steps {time.perf_counter() - t0:.1f} s")
+    n_all = 6
+    t0 = time.perf_counter()
+    osim.step(n_all)
+    el_all = time.perf_counter() - t0
+    one = None
+    if gomp is not None:
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        osim.step(1)
+        one = time.perf_counter() - t0
+        gomp.omp_set_num_threads(cores)
+    # adjoint steps against the current forward state
+    a = np.zeros_like(osim.u)
+    g = np.zeros((3, osim.N))
+    osim.adjoint_step_state(a, osim.u, g)      # page faults
+    n_adj = 3
+    t0 = time.perf_counter()
+    for _ in range(n_adj):
+        osim.adjoint_step_state(a, osim.u, g)
+    el_adj = time.perf_counter() - t0
+    del osim, a, g
+    ncell = spec.ncells
+    out = {"value": round(ncell * n_all / el_all / 1e6, 2), "unit": "Mcell-updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"FP64 C oracle on the same 536^3 workload: forward time steps 3..{2 + n_all} of 4000 with the "
+                     f"monitor recorded ({el_all:.1f} s on {cores} threads); one thread: 1 step; adjoint: {n_adj} "
+                     f"steps on {cores} threads",
+           "cpu_model": cpu_model(),
+           "adjoint_value": round(ncell * n_adj / el_adj / 1e6, 2)}
+    if one is not None:
+        out["one_core_value"] = round(ncell / one / 1e6, 2)
+    log(f"oracle: {out['value']} Mcell-upd/s forward on {cores} threads, {out.get('one_core_value')} on one, "
+        f"adjoint {out['adjoint_value']}")
+    return out
+
+
+# ------------------------------------------------------------------ 536^3 adjoint
+def adjoint_536(stream):
+    """4000 steps, |DFT Ex|^2 on the 64x64 patch: binomial replay with 32 FP32
+    slots and with 32 BF16 slots (per-array max-abs scale), and an FP64
+    reference (20 slots, to fit in memory); gradients compared on a 64^3
+    subsample of the gradient box (every 8th cell per axis)."""
     import torch
     from paper_2609_30039_amd import workloads as W
     from paper_2609_30039_amd import adjoint as A
@@ -100,7 +271,7 @@ def large_adjoint(stream, log):
     grads = {}
     for tag, dtype, slots, storage in (("fp32_slots", "f32", 32, None), ("bf16_slots", "f32", 32, "bf16"),
                                        ("fp64", "f64", 20, None)):
-        tile = AT.tune(spec, dtype, adjoint=True, stream=stream, log=log, steps=3)
+        tile = AT.tune(spec, dtype, adjoint=True, stream=stream, log=log, steps=3, candidates=SPLIT_SHAPES[2:4])
         kw = dict(tile)
         if storage:
             kw["ckpt_storage"] = storage
@@ -115,15 +286,16 @@ def large_adjoint(stream, log):
         sim.set_cotangent(0, 2.0 * sim.spectra(0))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        A.reverse_sweep(sim, plan, *last, progress=lambda m: log(f"  {tag}: adjoint at step {m}"))
+        A.reverse_sweep(sim, plan, *last, progress=lambda m: log(f"  536^3 {tag}: adjoint at step {m}"))
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         g = sim.grad(0)
         grads[tag] = g[:, ::8, ::8, ::8].astype(np.float64)   # 64^3 subsample per component
         out[tag] = {"slots": slots, "launch_shape": tile, "forward_s": round(t1 - t0, 3),
                     "reverse_s": round(t3 - t2, 3), "reverse_over_forward": round((t3 - t2) / (t1 - t0), 3),
-                    "forward_evaluations": plan.forward_evals + 1, "device_bytes": sim.memory_bytes()}
-        log(f"large adjoint {tag}: forward {t1 - t0:.2f} s, reverse {t3 - t2:.2f} s")
+                    "forward_evaluations": plan.forward_evals + 1, "device_bytes": sim.memory_bytes(),
+                    "adjoint_mcups": round(spec.ncells * N / (t3 - t2) / 1e6, 1)}
+        log(f"536^3 adjoint {tag}: forward {t1 - t0:.2f} s, reverse {t3 - t2:.2f} s")
         sim.close()
         del sim
     ref = grads["fp64"]
@@ -134,18 +306,197 @@ def large_adjoint(stream, log):
     return out
 
 
+# ------------------------------------------------------------------ 148^3
+def cache_resident_148(stream, khash):
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import roofline as RL
+    from paper_2609_30039_amd import autotune as AT
+    from paper_2609_30039_amd.sim import Simulation
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_golden_full as G
+    spec = W.lorentz_flux()
+    ncell = spec.ncells
+    tile = AT.tune(spec, "f32", stream=stream, log=log)
+    sim32, el, kms, nl = run_forward(spec, "f32", stream, 3, 1, tile)
+    bytes_step = RL.forward_bytes(spec, 4)
+    avg_ms = kms / nl
+    traffic = traffic_from_profiles(khash, tile, "fwd_lorentz_flux_f32_pmc.json")
+    out = {"workload": "148^3 (128^3 + 10-cell CPML), 48^3 one-pole Lorentz block, Ex sheet, 16-frequency flux "
+                       "plane, 1000 steps FP32; working set inside the 256 MB Infinity Cache",
+           "mcups": round(ncell * spec.n_steps * 3 / el / 1e6, 1), "launch_shape": tile,
+           "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_step,
+           "achieved_GBs": round(bytes_step / (avg_ms * 1e-3) / 1e9, 1),
+           "frac_hbm": round(bytes_step / (avg_ms * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4),
+           "traffic_GBs": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1)}
+    # FP32 after 1000 steps against the oracle's record (strided node sample, flux)
+    rec = G.read("lorentz_flux_1000")
+    a, s_ = (int(v) for v in rec["field_sample_spec"])
+    errs = {}
+    for q in range(6):
+        f = sim32.field(q)[a::s_, a::s_, a::s_].astype(np.float64)
+        r = rec["fields_sample"][q]
+        errs[W.COMP_NAMES[q]] = float(f"{np.linalg.norm(f - r) / np.linalg.norm(r):.3e}")
+    fl = sim32.flux(0)
+    out["fp32_vs_oracle_at_1000"] = {
+        **errs, "flux_max_rel": float(f"{np.max(np.abs(fl - rec['flux']) / np.abs(rec['flux'])):.3e}"),
+        "float32_storage_floor": {W.COMP_NAMES[q]: float(f"{rec['f32store_rel_sample'][q]:.3e}") for q in range(6)},
+        "note": "rel. L2 on every 6th node per axis; the floor is the oracle with its state rounded to float32 each step"}
+    sim32.close()
+    # FP64 GPU path
+    tile64 = AT.tune(spec, "f64", stream=stream, log=log)
+    sim64, el64, kms64, nl64 = run_forward(spec, "f64", stream, 1, 1, tile64)
+    errs64 = max(np.linalg.norm(sim64.field(q)[a::s_, a::s_, a::s_] - rec["fields_sample"][q]) /
+                 np.linalg.norm(rec["fields_sample"][q]) for q in range(6))
+    out["fp64"] = {"mcups": round(ncell * spec.n_steps / el64 / 1e6, 1), "launch_shape": tile64,
+                   "achieved_GBs": round(RL.forward_bytes(spec, 8) / (kms64 / nl64 * 1e-3) / 1e9, 1),
+                   "max_field_rel_l2_vs_oracle_at_1000": float(f"{errs64:.3e}")}
+    sim64.close()
+    # full solve: construction, 1000 steps with the monitor, final transfer of
+    # the six fields and the flux; median of 3 after one warm repetition
+    reps = []
+    for r in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim = Simulation(spec, dtype="f32", stream=stream, graph_chunk=32 if tile["kernel"] == "split" else 0, **tile)
+        sim.step(spec.n_steps, record=True)
+        _ = [sim.field(q) for q in range(6)]
+        _ = sim.flux(0)
+        torch.cuda.synchronize()
+        sim.close()
+        if r:
+            reps.append(time.perf_counter() - t0)
+    out["full_solve_s_median_of_3"] = round(statistics.median(reps), 4)
+    out["full_solve_mcups"] = round(ncell * spec.n_steps / statistics.median(reps) / 1e6, 1)
+    log(f"148^3: {out['mcups']} Mcell/s stepping, full solve {out['full_solve_s_median_of_3']} s")
+    return out
+
+
+# ------------------------------------------------------------------ 212^3 adjoint
+def adjoint_212(stream):
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import adjoint as A
+    from paper_2609_30039_amd import autotune as AT
+    from paper_2609_30039_amd.sim import Simulation
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_golden_full as G
+    spec3, _ = W.design_patch()
+    log(f"design_patch adjoint: {spec3.shape} x {spec3.n_steps}, 24 checkpoint slots")
+    rec = G.read("design_patch_full") if os.path.exists(G.path("design_patch_full")) else None
+    out = {"workload": "212^3 (192^3 + 10-cell CPML), 64^3 design box eps in [1,6], |DFT Ez|^2 on a 32x32 patch, "
+                       "8 frequencies, 2000 steps, 24 checkpoints (binomial)"}
+    grads = {}
+    for dt in ("f32", "f64"):
+        tile3 = AT.tune(spec3, dt, adjoint=True, stream=stream, log=log)
+        sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream,
+                          graph_chunk=32 if tile3["kernel"] == "split" else 0, **tile3)
+        plan = A.RevolvePlan(spec3.n_steps, 24)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = A.forward_record(sim3, plan)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim3.set_cotangent(0, 2.0 * sim3.spectra(0))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        A.reverse_sweep(sim3, plan, *last)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        grads[dt] = sim3.grad(0)[0]
+        tf, tr = t1 - t0, t3 - t2
+        n3 = spec3.ncells
+        out[dt] = {"forward_s": round(tf, 4), "reverse_s": round(tr, 4), "reverse_over_forward": round(tr / tf, 3),
+                   "adjoint_mcups": round(n3 * spec3.n_steps / tr / 1e6, 1),
+                   "forward_mcups": round(n3 * spec3.n_steps / tf / 1e6, 1),
+                   "forward_evaluations": plan.forward_evals + 1, "launch_shape": tile3}
+        if rec is not None:
+            out[dt]["grad_rel_l2_vs_oracle"] = float(
+                f"{np.linalg.norm(grads[dt] - rec['grad']) / np.linalg.norm(rec['grad']):.3e}")
+        log(f"design_patch {dt}: forward {tf:.3f} s, reverse {tr:.3f} s")
+        sim3.close()
+        del sim3
+    out["grad_rel_l2_fp32_vs_fp64"] = float(
+        f"{np.linalg.norm(grads['f32'] - grads['f64']) / np.linalg.norm(grads['f64']):.3e}")
+    return out
+
+
+# ------------------------------------------------------------------ ragged batch
+def batch_48(stream):
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import adjoint as A
+    from paper_2609_30039_amd import autotune as AT
+    from paper_2609_30039_amd.sim import Simulation
+    specs4 = W.batch_domains()
+    cells4 = sum(s_.ncells for s_ in specs4)
+    n4 = specs4[0].n_steps
+    tile4 = AT.tune(specs4, "f32", stream=stream, log=log, steps=3)
+    log(f"batch_domains: {len(specs4)} domains, {cells4} cells, {n4} steps, launch shape {tile4}")
+    sim4 = Simulation(specs4, dtype="f32", n_ckpt=16, stream=stream,
+                      graph_chunk=32 if tile4["kernel"] == "split" else 0, **tile4)
+    sim4.step(4, record=False)
+    sim4.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim4.step(n4, record=True)
+    torch.cuda.synchronize()
+    el4 = time.perf_counter() - t0
+    plan4 = A.RevolvePlan(n4, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last4 = A.forward_record(sim4, plan4)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for d_, s_ in enumerate(specs4):
+        if s_.grad_box is None:
+            continue
+        sp = sim4.spectra(0, domain=d_)
+        g = np.zeros_like(sp)     # J = sum_f Re sum (Ex Hy* - Ey Hx*)
+        g[:, 0], g[:, 3], g[:, 1], g[:, 2] = sp[:, 3], sp[:, 0], -sp[:, 2], -sp[:, 1]
+        sim4.set_cotangent(0, g, domain=d_)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    A.reverse_sweep(sim4, plan4, *last4)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sim4.close()
+    return {"workload": f"{len(specs4)} ragged domains (per-axis interior from {{48,64,96,128,160}} + 10-cell CPML), "
+                        f"eps in [1,4], Ez dipole, {n4} steps FP32; even domains forward+adjoint of a flux objective, "
+                        f"16 checkpoints",
+            "cells": cells4, "forward_mcups": round(cells4 * n4 / el4 / 1e6, 1),
+            "record_s": round(t1 - t0, 4), "reverse_s": round(t3 - t2, 4),
+            "reverse_over_forward": round((t3 - t2) / (t1 - t0), 3),
+            "forward_evaluations": plan4.forward_evals + 1, "launch_shape": tile4}
+
+
+def several_poles(stream, tile):
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import roofline as RL
+    out = {"workload": "148^3 headline-sized domain, flux plane recorded, its 48^3 box with 3 poles (2 Lorentz, "
+                       "1 Drude) or 16 poles (10 Lorentz, 6 Drude), 1000 steps FP32", "launch_shape": tile}
+    for key in (3, 16):
+        specp = W.with_poles(W.lorentz_flux(), W.pole_set(key))
+        simp, elp, kmsp, nlp = run_forward(specp, "f32", stream, 1, 1, tile)
+        bp = RL.forward_bytes(specp, 4)
+        out[f"poles_{key}"] = {"mcups": round(specp.ncells * specp.n_steps / elp / 1e6, 1),
+                               "avg_launch_us": round(kmsp / nlp * 1e3, 2),
+                               "algorithmic_bytes_per_launch": bp,
+                               "achieved_GBs": round(bp / (kmsp / nlp * 1e-3) / 1e9, 1)}
+        simp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--large-adjoint", action="store_true",
-                    help="run only the 512^3 + CPML adjoint study (FP32 vs BF16 checkpoints vs FP64) and print its JSON")
+    ap.add_argument("--no-extra", action="store_true", help="headline only (with the CPU baseline)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 536^3 adjoint study")
     ap.add_argument("--shape", default=None,
-                    help="launch shape KERNEL,ROWS,KZ for the headline (skips the autotuner), e.g. split,0,8")
+                    help="launch shape KERNEL,ROWS,KZ for the headline (skips the autotuner), e.g. split,8,8")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the path is single-GPU (no collectives); --gpus {args.gpus} is not "
@@ -156,266 +507,21 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs the GPU", file=sys.stderr)
         sys.exit(1)
-    from paper_2609_30039_amd import workloads as W
-    from paper_2609_30039_amd import roofline as RL
-    from paper_2609_30039_amd.sim import Simulation
-    from paper_2609_30039_amd import adjoint as A
-
     stream = torch.cuda.current_stream().cuda_stream
-    K, Wm = args.steps, args.warmup
     khash = kernel_source_hash()
+    t_start = time.perf_counter()
 
-    from paper_2609_30039_amd import autotune as AT
-
-    if args.large_adjoint:
-        print(json.dumps(large_adjoint(stream, log)), flush=True)
-        return
-
-    # ---------------------------------------------------------------- headline
-    spec = W.lorentz_flux()
-    ncell = spec.ncells
-    if args.shape:
-        kk, rr, zz = args.shape.split(",")
-        tile = {"kernel": kk, "tile_rows": int(rr), "tile_kz": int(zz)}
-    else:
-        tile = AT.tune(spec, "f32", stream=stream, log=log)
-    log(f"lorentz_flux FP32 forward: {spec.shape} x {spec.n_steps} steps, warmup {Wm}, timed {K}, launch shape {tile}")
-    sim32, el, kms, nl = run_forward(spec, "f32", stream, K, Wm, tile)
-    mcups = ncell * spec.n_steps * K / el / 1e6
-    avg_ms = kms / nl
-    bytes_launch = RL.forward_bytes(spec, 4)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    log(f"lorentz_flux FP32: {el / K * 1e3:.2f} ms/solve, {mcups:.0f} Mcell-upd/s, kernel {avg_ms * 1e3:.1f} us/launch, "
-        f"{achieved:.0f} GB/s algorithmic")
-    traffic = traffic_from_profiles(khash, tile)
-    out = {
-        "metric": "Mcell-updates/s fwd & adjoint (FP32 vs FP64), % HBM roofline, grad rel. err",
-        "value": round(mcups, 1),
-        "unit": "Mcell-updates/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": Wm,
-        "ms_per_step": round(el / K * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "148^3 cells (128^3 + 10-cell CPML, m=3, kappa_max=5), 48^3 one-pole Lorentz "
-                               "block, Ex sheet source, 16-frequency flux plane, 1000 time steps per step",
-                   "cells": ncell, "time_steps_per_step": spec.n_steps, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
-                     "kernel": ("split E and H kernels (k_fwd_e with the Lorentz-box blocks leading, then k_fwd_h)"
-                                if tile["kernel"] == "split" else "fused single-pass tile kernels")
-                               + ": all stepping launches of one time step",
-                     "launch_shape": tile,
-                     "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_launch,
-                     "kernel_source_hash": khash},
-    }
-
-    # ---------------------------------------------------------------- CPU oracle
+    spec5, tile5, out = headline(args, stream, khash)
     if not args.no_cpu:
-        from oracle import oracle as O
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        osim = O.OracleSim(spec)
-        osim.step(2)                       # first steps: page faults and thread start-up
-        t0 = time.perf_counter()
-        osim.step(3)
-        per = (time.perf_counter() - t0) / 3
-        nsteps = int(max(2, min(spec.n_steps - 5, args.cpu_seconds / max(per, 1e-6))))
-        log(f"oracle: {per * 1e3:.0f} ms/step on {cores} threads, running {nsteps} more steps")
-        t0 = time.perf_counter()
-        osim.step(nsteps)
-        cel = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(ncell * nsteps / cel / 1e6, 2), "unit": "Mcell-updates/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": f"FP64 C oracle, same workload, time steps 6..{nsteps + 5} of 1000 "
-                                         f"({cel:.1f} s), monitors recorded"}
-        # FP32 GPU fields against the oracle at the same step
-        n_cmp = nsteps + 5
-        cmp_sim = Simulation(spec, dtype="f32", stream=stream)
-        cmp_sim.step(n_cmp)
-        errs = {W.COMP_NAMES[q]: float(np.linalg.norm(cmp_sim.field(q) - osim.field(q)) /
-                                       max(np.linalg.norm(osim.field(q)), 1e-300)) for q in range(6)}
-        out["accuracy_vs_oracle"] = {"fp32_field_rel_l2_at_step": n_cmp, **{k: float(f"{v:.3e}") for k, v in
-                                                                           errs.items()}}
-        del cmp_sim, osim
-
+        out["cpu_baseline"] = cpu_baseline(spec5)
     if not args.no_extra:
-        # ------------------------------------------------------------ FP64 path and FP32 accuracy at 1000 steps
-        tile64 = AT.tune(spec, "f64", stream=stream, log=log)
-        log(f"lorentz_flux FP64 forward, launch shape {tile64}")
-        sim64, el64, kms64, nl64 = run_forward(spec, "f64", stream, 1, 1, tile64)
-        out["fp64"] = {"value": round(ncell * spec.n_steps / el64 / 1e6, 1), "unit": "Mcell-updates/s",
-                       "ms_per_solve": round(el64 * 1e3, 2),
-                       "achieved_GBs": round(RL.forward_bytes(spec, 8) / (kms64 / nl64 * 1e-3) / 1e9, 1)}
-        f32e = {}
-        for q in range(6):
-            a, b = sim32.field(q).astype(np.float64), sim64.field(q)
-            f32e[W.COMP_NAMES[q]] = float(f"{np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300):.3e}")
-        fl32, fl64 = sim32.flux(0), sim64.flux(0)
-        f32e["flux_max_rel"] = float(f"{np.max(np.abs(fl32 - fl64) / np.abs(fl64)):.3e}")
-        # By step 1000 most of the pulse has left through the absorbers, so the
-        # figures above are relative to late-time residual fields.  Diagnostic:
-        # the same differences over each field's largest norm in time (FP64 run
-        # sampled every 50 steps).
-        tsim = Simulation(spec, dtype="f64", stream=stream, **tile64)
-        peak = np.zeros(6)
-        for _ in range(spec.n_steps // 50):
-            tsim.step(50, record=False)
-            for q in range(6):
-                peak[q] = max(peak[q], float(np.linalg.norm(tsim.field(q))))
-        tsim.close()
-        f32e["rel_to_time_max_norm"] = {
-            W.COMP_NAMES[q]: float(f"{np.linalg.norm(sim32.field(q).astype(np.float64) - sim64.field(q)) / max(peak[q], 1e-300):.3e}")
-            for q in range(6)}
-        out["fp32_vs_fp64_gpu_at_1000"] = f32e
-        del sim64
-
-        # ------------------------------------------------------------ adjoint (192^3 + CPML, 2000 steps, 24 slots)
-        spec3, fd_cells = W.design_patch()
-        log(f"design_patch adjoint: {spec3.shape} x {spec3.n_steps}, 24 checkpoint slots")
-
-        def cot(s):
-            sp = s.spectra(0)
-            return {(0, 0): 2.0 * sp}
-
-        grads = {}
-        for dt in ("f32", "f64"):
-            tile3 = AT.tune(spec3, dt, adjoint=True, stream=stream, log=log)
-            sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream,
-                              graph_chunk=32 if tile3["kernel"] == "split" else 0, **tile3)
-            plan = A.RevolvePlan(spec3.n_steps, 24)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            last = A.forward_record(sim3, plan)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sim3.set_cotangent(0, 2.0 * sim3.spectra(0))
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            A.reverse_sweep(sim3, plan, *last)
-            torch.cuda.synchronize()
-            t3 = time.perf_counter()
-            grads[dt] = sim3.grad(0)[0]
-            if dt == "f32":
-                # kernel time of the reverse sweep, from a second, untimed pass with
-                # per-launch events (which also keep the replays out of captured chunks)
-                last = A.forward_record(sim3, plan)
-                sim3.set_cotangent(0, 2.0 * sim3.spectra(0))
-                sim3.timing(1)
-                A.reverse_sweep(sim3, plan, *last)
-                akms, anl = sim3.timing(2)
-                sim3.timing(0)
-            tf, tr = t1 - t0, t3 - t2
-            n3 = spec3.ncells
-            if dt == "f32":
-                out["adjoint"] = {
-                    "workload": "212^3 (192^3 + 10-cell CPML), 64^3 design box eps in [1,6], |DFT Ez|^2 on a "
-                                "32x32 patch, 8 frequencies, 2000 steps, 24 checkpoints (binomial)",
-                    "forward_s": round(tf, 4), "reverse_s": round(tr, 4),
-                    "reverse_over_forward": round(tr / tf, 3),
-                    "adjoint_mcups": round(n3 * spec3.n_steps / tr / 1e6, 1),
-                    "forward_mcups": round(n3 * spec3.n_steps / tf / 1e6, 1),
-                    "forward_evaluations": plan.forward_evals + 1, "launch_shape": tile3,
-                    "reverse_stepping_kernel_ms": round(akms, 2), "reverse_stepping_launches": anl}
-            else:
-                out["adjoint"]["fp64_reverse_s"] = round(tr, 4)
-                out["adjoint"]["fp64_forward_s"] = round(tf, 4)
-            log(f"design_patch {dt}: forward {tf:.3f} s, reverse {tr:.3f} s")
-            del sim3
-        g32, g64 = grads["f32"], grads["f64"]
-        out["adjoint"]["grad_rel_l2_fp32_vs_fp64"] = float(f"{np.linalg.norm(g32 - g64) / np.linalg.norm(g64):.3e}")
-
-        # ------------------------------------------------------------ ragged batch: 48 domains in every launch
-        specs4 = W.batch_domains()
-        cells4 = sum(s_.ncells for s_ in specs4)
-        n4 = specs4[0].n_steps
-        tile4 = AT.tune(specs4, "f32", stream=stream, log=log, steps=3)
-        log(f"batch_domains: {len(specs4)} domains, {cells4} cells, {n4} steps, launch shape {tile4}")
-        sim4 = Simulation(specs4, dtype="f32", n_ckpt=16, stream=stream,
-                          graph_chunk=32 if tile4["kernel"] == "split" else 0, **tile4)
-        sim4.step(4, record=False)
-        sim4.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sim4.step(n4, record=True)
-        torch.cuda.synchronize()
-        el4 = time.perf_counter() - t0
-        # forward + adjoint of the flux objective on the even domains (binomial, 16 slots)
-        plan4 = A.RevolvePlan(n4, 16)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        last4 = A.forward_record(sim4, plan4)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for d_, s_ in enumerate(specs4):
-            if s_.grad_box is None:
-                continue
-            sp = sim4.spectra(0, domain=d_)
-            g = np.zeros_like(sp)     # J = sum_f Re sum (Ex Hy* - Ey Hx*)
-            g[:, 0], g[:, 3], g[:, 1], g[:, 2] = sp[:, 3], sp[:, 0], -sp[:, 2], -sp[:, 1]
-            sim4.set_cotangent(0, g, domain=d_)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        A.reverse_sweep(sim4, plan4, *last4)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        out["batch"] = {
-            "workload": f"{len(specs4)} ragged domains (per-axis interior from {{48,64,96,128,160}} + 10-cell CPML), "
-                        f"eps in [1,4], Ez dipole, {n4} steps FP32; even domains forward+adjoint of a flux objective, "
-                        f"16 checkpoints",
-            "cells": cells4, "forward_mcups": round(cells4 * n4 / el4 / 1e6, 1),
-            "record_s": round(t1 - t0, 4), "reverse_s": round(t3 - t2, 4),
-            "reverse_over_forward": round((t3 - t2) / (t1 - t0), 3),
-            "forward_evaluations": plan4.forward_evals + 1, "launch_shape": tile4}
-        log(f"batch: forward {cells4 * n4 / el4 / 1e6:.0f} Mcell/s, reverse/forward {(t3 - t2) / (t1 - t0):.2f}")
-        del sim4
-
-        # ------------------------------------------------------------ large forward (cache-free roofline)
-        spec5 = W.anisotropic_lorentz()
-        spec5.n_steps = 200
-        for s_ in spec5.sources:
-            s_.waveform = s_.waveform[:200]
-        tile5 = AT.tune(spec5, "f32", stream=stream, log=log, steps=3)
-        log(f"anisotropic_lorentz forward: {spec5.shape} x 200 steps, launch shape {tile5}")
-        sim5, el5, kms5, nl5 = run_forward(spec5, "f32", stream, 1, 1, tile5)
-        b5 = RL.forward_bytes(spec5, 4)
-        t5 = traffic_from_profiles(khash, tile5, "fwd_anisotropic_lorentz_f32_pmc.json")
-        out["large_forward"] = {
-            "workload": "536^3 (512^3 + 12-cell CPML), diagonal eps, 128^3 Lorentz box, Ex sheet, Ex patch "
-                        "monitor, 200 steps FP32",
-            "mcups": round(spec5.ncells * 200 / el5 / 1e6, 1),
-            "avg_launch_us": round(kms5 / nl5 * 1e3, 1),
-            "achieved_GBs": round(b5 / (kms5 / nl5 * 1e-3) / 1e9, 1),
-            "frac_hbm": round(b5 / (kms5 / nl5 * 1e-3) / 1e9 / RL.HBM_PEAK_GBS, 4),
-            "traffic_GBs": None if t5 is None else round(t5 / (kms5 / nl5 * 1e-3) / 1e9, 1),
-            "launch_shape": tile5}
-        del sim5
-
-        # ------------------------------------------------------------ dispersive box with several poles
-        # the headline domain and launch shape, its 48^3 box holding two Lorentz
-        # poles and a Drude pole, then the maximum of 16 poles
-        poles_out = {"workload": "148^3 headline domain, flux plane recorded, its 48^3 box with 3 poles (2 Lorentz, "
-                                 "1 Drude) or 16 poles (10 Lorentz, 6 Drude), 1000 steps FP32",
-                     "launch_shape": tile}
-        for key in (3, 16):
-            specp = W.with_poles(W.lorentz_flux(), W.pole_set(key))
-            simp, elp, kmsp, nlp = run_forward(specp, "f32", stream, 1, 1, tile)
-            bp = RL.forward_bytes(specp, 4)
-            poles_out[f"poles_{key}"] = {
-                "mcups": round(specp.ncells * specp.n_steps / elp / 1e6, 1),
-                "avg_launch_us": round(kmsp / nlp * 1e3, 2),
-                "algorithmic_bytes_per_launch": bp,
-                "achieved_GBs": round(bp / (kmsp / nlp * 1e-3) / 1e9, 1)}
-            log(f"lorentz_flux with {key} poles: {specp.ncells * specp.n_steps / elp / 1e6:.0f} Mcell/s, "
-                f"{kmsp / nlp * 1e3:.1f} us/launch")
-            simp.close()
-            del simp
-        out["several_poles"] = poles_out
-
+        if not args.no_adjoint:
+            out["adjoint_536"] = adjoint_536(stream)
+        out["cache_resident_148"] = cache_resident_148(stream, khash)
+        out["adjoint_212"] = adjoint_212(stream)
+        out["batch_48"] = batch_48(stream)
+        out["several_poles"] = several_poles(stream, out["cache_resident_148"]["launch_shape"])
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 
