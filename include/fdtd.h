@@ -158,6 +158,11 @@ typedef struct {
     int32_t tile_kz;               /* z planes per block (0: default) */
     void *stream;                  /* hipStream_t; NULL = default stream */
     double mem_budget_bytes;       /* refuse with FDTD_E_NOMEM above this (0: device free memory) */
+    int32_t reversible;            /* 1: reversible mode (see fdtd_step_reverse); admissible only when
+                                      every domain with a gradient has no dispersive box and its gradient
+                                      box lies between the absorbing slabs, one cell clear of a low slab
+                                      (else FDTD_E_INVALID); needs max_steps >= 1 and keeps
+                                      (max_steps + 1) x 4 x (the box's face areas) interface values */
 } fdtd_options;
 
 typedef struct fdtd_s *fdtd_t;
@@ -188,6 +193,23 @@ int fdtd_adjoint_begin(fdtd_t h, int32_t n_total);
    Section 3.1 in reverse order, accumulates dJ/deps from u^{m-1} inside the
    gradient box, and adds dJ/du^{m-1}. */
 int fdtd_step_adjoint(fdtd_t h, int32_t n_steps);
+
+/* Reversible mode (Section 3.2, the absorbing-face variant).  The box R of
+   each domain with a gradient, between its absorbing slabs, is lossless and
+   nondispersive, so Eq. 1 can be stepped backward there:
+     H^{m-1/2} = H^{m+1/2} + S C^+(E^m),  E^{m-1} = (E^m - s^m) - S eps^-1 C^-(H^{m-1/2}).
+   Every forward step records, on the device, the fields just outside R that
+   these backward steps read (H on R's low faces, E on its high faces), so the
+   interior reconstruction needs nothing from the absorbers.  fdtd_step_reverse
+   takes n_steps such backward steps: the forward step index goes from m to
+   m - n_steps and the forward state inside R becomes u^{m-n_steps} up to
+   round-off; outside R it is left undefined (the adjoint reads the forward
+   state only inside the gradient box).  The reverse sweep then alternates
+   fdtd_step_reverse(h, 1) and fdtd_step_adjoint(h, 1) without checkpoints.
+   Forward steps are launched one by one in this mode (no captured chunks).
+   FDTD_E_STATE without reversible mode, or when the interface of a step was
+   not recorded since the last reset, set_field or set_eps. */
+int fdtd_step_reverse(fdtd_t h, int32_t n_steps);
 
 /* Copy the full forward state u^n (fields, absorber memories, Lorentz
    history) and n into slot (Section 3.2).  BF16 storage scales each array by

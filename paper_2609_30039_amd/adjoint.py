@@ -89,6 +89,73 @@ def gradient(sim: Simulation, n_steps: int, n_slots: int,
     return [sim.grad(d) if s.grad_box is not None else None for d, s in enumerate(sim.specs)]
 
 
+# ---------------------------------------------------------------- reversible mode
+def reversible_admissible(specs) -> bool:
+    """Whether the reversible mode applies (Section 3.2: it follows from the
+    content of the problem): every domain with a gradient has no dispersive
+    box, and its gradient box lies between the absorbing slabs, one cell clear
+    of a low slab (the curl at the gradient box reads H one cell back)."""
+    if not isinstance(specs, (list, tuple)):
+        specs = [specs]
+    any_grad = False
+    for s in specs:
+        if s.grad_box is None:
+            continue
+        any_grad = True
+        if s.lorentz:
+            return False
+        (glo, ghi) = s.grad_box
+        for a in range(3):
+            lo, hi = s.pml[2 * a], s.shape[a] - s.pml[2 * a + 1]
+            if glo[a] < lo + (1 if lo > 0 else 0) or ghi[a] > hi:
+                return False
+    return any_grad
+
+
+def reversible_sweep(sim: Simulation, n_steps: int, progress=None):
+    """Reverse sweep of a handle created with reversible=True whose forward
+    state is u^N: each adjoint step m -> m-1 is preceded by one backward step
+    of the lossless box (u^m -> u^{m-1}); no checkpoint is read."""
+    sim.adjoint_begin(n_steps)
+    for m in range(n_steps, 0, -1):
+        sim.step_reverse(1)
+        sim.step_adjoint(1)
+        if progress is not None and (m - 1) % 500 == 0:
+            progress(m - 1)
+
+
+def reversible_gradient(sim: Simulation, n_steps: int,
+                        cotangent_fn: Callable[[Simulation], Dict[int, np.ndarray]]):
+    """Forward from rest with the interface recorded, cotangents from the
+    monitors, reversible reverse sweep.  Returns the per-domain gradients."""
+    sim.reset()
+    sim.step(n_steps, record=True)
+    for (dom, mon), g in cotangent_fn(sim).items():
+        sim.set_cotangent(mon, g, domain=dom)
+    reversible_sweep(sim, n_steps)
+    return [sim.grad(d) if s.grad_box is not None else None for d, s in enumerate(sim.specs)]
+
+
+def retained_gradients(sim: Simulation, n_steps: int, objectives, slot: int = 0):
+    """Several objectives from one forward run (the retained backward pass of
+    Section 3.2): the forward sweep runs once and its final state u^N is kept
+    in checkpoint slot `slot`; each objective's cotangents (a function of the
+    recorded spectra) then get their own reverse sweep from that state, in the
+    reversible mode.  Returns one gradient list per objective."""
+    sim.reset()
+    sim.step(n_steps, record=True)
+    sim.save(slot)
+    cots = [fn(sim) for fn in objectives]          # every objective sees the same forward run
+    out = []
+    for c in cots:
+        sim.restore(slot)
+        for (dom, mon), g in c.items():
+            sim.set_cotangent(mon, g, domain=dom)
+        reversible_sweep(sim, n_steps)
+        out.append([sim.grad(d) if s.grad_box is not None else None for d, s in enumerate(sim.specs)])
+    return out
+
+
 # ---------------------------------------------------------------- torch bridge
 def _torch():
     import torch

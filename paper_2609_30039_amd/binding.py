@@ -30,6 +30,7 @@ ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_E_INVALID", -2: "FDTD_E_UNSTABLE", -3: "F
                -4: "FDTD_E_DEVICE", -5: "FDTD_E_STATE", -6: "FDTD_E_RANGE"}
 
 EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_begin", "fdtd_step_adjoint",
+            "fdtd_step_reverse",
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
@@ -91,7 +92,7 @@ class Options(C.Structure):
                 ("ckpt_checksum", C.c_int32), ("max_steps", C.c_int32), ("kernel", C.c_int32),
                 ("dft_block", C.c_int32), ("graph_chunk", C.c_int32), ("tile_rows", C.c_int32),
                 ("tile_kz", C.c_int32), ("stream", C.c_void_p),
-                ("mem_budget_bytes", C.c_double)]
+                ("mem_budget_bytes", C.c_double), ("reversible", C.c_int32)]
 
 
 _lib = None
@@ -115,6 +116,7 @@ def lib():
         L.fdtd_step_forward.argtypes = [vp, i32, u32]
         L.fdtd_adjoint_begin.argtypes = [vp, i32]
         L.fdtd_step_adjoint.argtypes = [vp, i32]
+        L.fdtd_step_reverse.argtypes = [vp, i32]
         L.fdtd_checkpoint_save.argtypes = [vp, i32]
         L.fdtd_checkpoint_restore.argtypes = [vp, i32]
         L.fdtd_monitor_dft.argtypes = [vp, i32, i32, i32, vp, sz]
@@ -218,7 +220,7 @@ def domain_desc(spec, keep: list) -> DomainDesc:
 def fdtd_create(specs: Sequence, dtype: int = FDTD_F32, n_ckpt: int = 0, ckpt_storage: Optional[int] = None,
                 ckpt_checksum: bool = False, max_steps: int = 0, kernel: int = FDTD_KERNEL_AUTO,
                 dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
-                mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0):
+                mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0, reversible: bool = False):
     keep: list = []
     arr = (DomainDesc * len(specs))()
     for q, s in enumerate(specs):
@@ -229,6 +231,7 @@ def fdtd_create(specs: Sequence, dtype: int = FDTD_F32, n_ckpt: int = 0, ckpt_st
     o.ckpt_storage = dtype if ckpt_storage is None else ckpt_storage
     o.ckpt_checksum = int(bool(ckpt_checksum))
     o.max_steps = max_steps
+    o.reversible = int(bool(reversible))
     o.kernel = kernel
     o.dft_block = dft_block
     o.graph_chunk = graph_chunk
@@ -255,6 +258,10 @@ def fdtd_adjoint_begin(h, n_total: int):
 
 def fdtd_step_adjoint(h, n_steps: int = 1):
     return _chk(lib().fdtd_step_adjoint(h, n_steps), h)
+
+
+def fdtd_step_reverse(h, n_steps: int = 1):
+    return _chk(lib().fdtd_step_reverse(h, n_steps), h)
 
 
 def fdtd_checkpoint_save(h, slot: int):

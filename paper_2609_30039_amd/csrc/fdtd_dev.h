@@ -102,6 +102,17 @@ struct DomDev {
     T* lora[3][3];
     int glo[3], ghi[3];
     double* gacc[3];           // dJ/deps accumulators over the gradient box (isotropic: [0] only)
+    // ---- reversible mode: the lossless box R = [rlo, rhi) (the cells outside
+    // every absorbing slab) is stepped backward; rec holds, per forward step
+    // index, the fields just outside R that its backward steps need: H on the
+    // three low faces (index rlo_a - 1) and E on the three high faces (rhi_a),
+    // the two components tangential to the face, [face][comp][cells]
+    int rev;
+    int rlo[3], rhi[3];
+    T* rec;
+    long long rec_stride;      // elements per recorded step
+    long long rface[6];        // offset of face f (0..2 low x,y,z; 3..5 high x,y,z) in a step, 0 if absent
+    int rfcnt[3];              // cells of an x, y, z face: the product of R's other two extents
 };
 
 // ------------------------------------------------------------------ indexing

@@ -1954,6 +1954,151 @@ __global__ void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restr
     for (; q < n_words; q += stride) dst[q] = src[q];
 }
 
+// ---- Reversible mode (Section 3.2): the forward fields of the lossless box R
+// are rebuilt by stepping Eq. 1 backward, H first (from E^{m}), then E (from
+// the rebuilt H^{m-1/2}); the values just outside R come from the per-step
+// record of the interface.  Every cell of R runs the transposed order of its
+// forward update with the opposite sign: H^{m-1/2} = H^{m+1/2} + S C^+ E^m,
+// E^{m-1} = (E^m - s^m) - S eps^-1 C^- H^{m-1/2}.  Cells outside R are left
+// stale: the adjoint reads the forward state only inside the gradient box.
+
+// face f of domain d: axis a = f % 3, high = f >= 3; cell q -> (u, v) along
+// the two other axes b = a+1, c = a+2 (u fastest)
+template <typename T>
+__device__ __forceinline__ void rev_face_cell(const DomDev<T>& d, int f, long long q, int& i, int& j, int& k) {
+    const int a = f % 3, b = (a + 1) % 3, c = (a + 2) % 3;
+    const int nb = d.rhi[b] - d.rlo[b];
+    int x[3];
+    x[a] = f >= 3 ? d.rhi[a] : d.rlo[a] - 1;
+    x[b] = d.rlo[b] + (int)(q % nb);
+    x[c] = d.rlo[c] + (int)(q / nb);
+    i = x[0];
+    j = x[1];
+    k = x[2];
+}
+
+// copy the interface of the current state (set cs) into record slot `slot`:
+// low faces H_{a+1}, H_{a+2} at index rlo_a - 1, high faces E_{a+1}, E_{a+2}
+// at index rhi_a; grid y = domain
+template <typename T>
+__global__ void __launch_bounds__(256) k_rev_record(const DomDev<T>* __restrict__ doms, int cs, int slot) {
+    const DomDev<T>& d = doms[blockIdx.y];
+    if (!d.rev) return;
+    const long long so = (long long)cs * d.fs;
+    T* rec = d.rec + (long long)slot * d.rec_stride;
+    for (int f = 0; f < 6; ++f) {
+        if (d.rface[f] < 0) continue;
+        const int a = f % 3;
+        const long long cnt = d.rfcnt[a];
+        for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < cnt; q += (long long)gridDim.x * 256) {
+            int i, j, k;
+            rev_face_cell(d, f, q, i, j, k);
+            const long long fi = fidx(d, i, j, k) + so;
+            T* const* src = f >= 3 ? d.E : d.H;
+            gp(rec)[d.rface[f] + q] = gp(src[(a + 1) % 3])[fi];
+            gp(rec)[d.rface[f] + cnt + q] = gp(src[(a + 2) % 3])[fi];
+        }
+    }
+}
+
+// a recorded value: component r (0 -> a+1, 1 -> a+2) of face f at (i, j, k)
+template <typename T>
+__device__ __forceinline__ T rev_rec(const DomDev<T>& d, const T* rec, int f, int r, int i, int j, int k) {
+    if (d.rface[f] < 0) return T(0);    // no absorbing slab there: the ghost zero
+    const int a = f % 3, b = (a + 1) % 3;
+    const int x[3] = {i, j, k};
+    const long long q = (long long)(x[(a + 2) % 3] - d.rlo[(a + 2) % 3]) * (d.rhi[b] - d.rlo[b]) + (x[b] - d.rlo[b]);
+    return gp(rec)[d.rface[f] + r * d.rfcnt[a] + q];
+}
+
+// E^m one step forward along axis a from a node of R: inside R from the field,
+// on R's high face from the record (component c of E)
+template <typename T>
+__device__ __forceinline__ T rev_e_up(const DomDev<T>& d, const T* rec, const FDTD_GLOBAL T* e, long long f, int c,
+                                      int a, int i, int j, int k) {
+    const int x[3] = {i, j, k};
+    if (x[a] + 1 < d.rhi[a]) return e[f + (a == 0 ? 1 : (a == 1 ? (long long)d.pitch : d.plane))];
+    if (x[a] + 1 >= d.n[a]) return T(0);   // ghost
+    int y[3] = {i, j, k};
+    y[a] += 1;
+    return rev_rec(d, rec, 3 + a, c == (a + 1) % 3 ? 0 : 1, y[0], y[1], y[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ T rev_h_down(const DomDev<T>& d, const T* rec, const FDTD_GLOBAL T* h, long long f, int c,
+                                        int a, int i, int j, int k) {
+    const int x[3] = {i, j, k};
+    if (x[a] - 1 >= d.rlo[a]) return h[f - (a == 0 ? 1 : (a == 1 ? (long long)d.pitch : d.plane))];
+    if (x[a] == 0) return T(0);             // ghost
+    int y[3] = {i, j, k};
+    y[a] -= 1;
+    return rev_rec(d, rec, a, c == (a + 1) % 3 ? 0 : 1, y[0], y[1], y[2]);
+}
+
+// H^{m-1/2} over R from E^m (set rs) and H^{m+1/2} (set rs) into set ws,
+// with the interface E^m of record slot m; grid y = domain, x over R's cells
+template <typename T>
+__global__ void __launch_bounds__(256) k_rev_h(const DomDev<T>* __restrict__ doms, int rs, int ws, int slot) {
+    const DomDev<T>& d = doms[blockIdx.y];
+    if (!d.rev) return;
+    const int rx = d.rhi[0] - d.rlo[0], ry = d.rhi[1] - d.rlo[1], rz = d.rhi[2] - d.rlo[2];
+    const long long ncell = (long long)rx * ry * rz;
+    const T* rec = d.rec + (long long)slot * d.rec_stride;
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs;
+    const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + so), gp(d.E[1] + so), gp(d.E[2] + so)};
+    const T S = d.S;
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < ncell; q += (long long)gridDim.x * 256) {
+        const int i = d.rlo[0] + (int)(q % rx), j = d.rlo[1] + (int)((q / rx) % ry), k = d.rlo[2] + (int)(q / ((long long)rx * ry));
+        const long long f = fidx(d, i, j, k);
+        const T ex = e[0][f], ey = e[1][f], ez = e[2][f];
+        // Hx: d+_y Ez - d+_z Ey ; Hy: d+_z Ex - d+_x Ez ; Hz: d+_x Ey - d+_y Ex
+        const T Dx0 = rev_e_up(d, rec, e[2], f, 2, 1, i, j, k) - ez, Dx1 = rev_e_up(d, rec, e[1], f, 1, 2, i, j, k) - ey;
+        const T Dy0 = rev_e_up(d, rec, e[0], f, 0, 2, i, j, k) - ex, Dy1 = rev_e_up(d, rec, e[2], f, 2, 0, i, j, k) - ez;
+        const T Dz0 = rev_e_up(d, rec, e[1], f, 1, 0, i, j, k) - ey, Dz1 = rev_e_up(d, rec, e[0], f, 0, 1, i, j, k) - ex;
+        gp(d.H[0] + wo)[f] = fma(S, Dx0 - Dx1, gp(d.H[0] + so)[f]);
+        gp(d.H[1] + wo)[f] = fma(S, Dy0 - Dy1, gp(d.H[1] + so)[f]);
+        gp(d.H[2] + wo)[f] = fma(S, Dz0 - Dz1, gp(d.H[2] + so)[f]);
+    }
+}
+
+// E^{m-1} over R from E^m (set rs) and H^{m-1/2} (set ws, written by k_rev_h)
+// into set ws, with the interface H^{m-1/2} of record slot m - 1; the source
+// value of forward step t = m - 1 is taken off before the curl term
+template <typename T>
+__global__ void __launch_bounds__(256) k_rev_e(const DomDev<T>* __restrict__ doms, int rs, int ws, int slot, int t) {
+    const DomDev<T>& d = doms[blockIdx.y];
+    if (!d.rev) return;
+    const int rx = d.rhi[0] - d.rlo[0], ry = d.rhi[1] - d.rlo[1], rz = d.rhi[2] - d.rlo[2];
+    const long long ncell = (long long)rx * ry * rz;
+    const T* rec = d.rec + (long long)slot * d.rec_stride;
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs;
+    const FDTD_GLOBAL T* h[3] = {gp(d.H[0] + wo), gp(d.H[1] + wo), gp(d.H[2] + wo)};
+    const T S = d.S;
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < ncell; q += (long long)gridDim.x * 256) {
+        const int i = d.rlo[0] + (int)(q % rx), j = d.rlo[1] + (int)((q / rx) % ry), k = d.rlo[2] + (int)(q / ((long long)rx * ry));
+        const long long f = fidx(d, i, j, k);
+        const T hx = h[0][f], hy = h[1][f], hz = h[2][f];
+        // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
+        const T Dx0 = hz - rev_h_down(d, rec, h[2], f, 2, 1, i, j, k), Dx1 = hy - rev_h_down(d, rec, h[1], f, 1, 2, i, j, k);
+        const T Dy0 = hx - rev_h_down(d, rec, h[0], f, 0, 2, i, j, k), Dy1 = hz - rev_h_down(d, rec, h[2], f, 2, 0, i, j, k);
+        const T Dz0 = hy - rev_h_down(d, rec, h[1], f, 1, 0, i, j, k), Dz1 = hx - rev_h_down(d, rec, h[0], f, 0, 1, i, j, k);
+        const T D[3] = {Dx0 - Dx1, Dy0 - Dy1, Dz0 - Dz1};
+        for (int c = 0; c < 3; ++c) {
+            if (e_masked(c, i, j, k)) {
+                gp(d.E[c] + wo)[f] = T(0);
+                continue;
+            }
+            T v = gp(d.E[c] + so)[f];
+            for (int q2 = 0; q2 < d.nsrc; ++q2) {
+                const SrcDev<T>& sr = d.src[q2];
+                if (sr.comp == c && t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j)))
+                    v -= gp(sr.wave)[t];
+            }
+            gp(d.E[c] + wo)[f] = fma(-S * epsinv_at(d, c, i, j, k), D[c], v);
+        }
+    }
+}
+
 // ---- Poynting flux of a plane spectrum (Section 2.4):
 //   F(w_f) = Re sum_p (Ex Hy* - Ey Hx*),  spectra [nf][4][np] complex128.
 // Two launches, no atomics, a fixed summation order: block (b, f) sums its
@@ -2278,6 +2423,18 @@ int flux_scratch(double** out) {
     return 0;
 }
 
+template <typename T>
+void launch_rev_record(const void* doms, int ndom, int cs, int slot, int maxcnt, hipStream_t s) {
+    k_rev_record<T><<<dim3(blocks_1d(maxcnt, 256, 4096), ndom), 256, 0, s>>>((const DomDev<T>*)doms, cs, slot);
+}
+
+template <typename T>
+void launch_rev_step(const void* doms, int ndom, int rs, int ws, int m, long long maxcells, hipStream_t s) {
+    const dim3 g(blocks_1d(maxcells, 256, 16384), ndom);
+    k_rev_h<T><<<g, 256, 0, s>>>((const DomDev<T>*)doms, rs, ws, m);
+    k_rev_e<T><<<g, 256, 0, s>>>((const DomDev<T>*)doms, rs, ws, m - 1, m - 1);
+}
+
 int flux_blocks(long long npts) {
     const long long b = (npts + kFluxPoints - 1) / kFluxPoints;
     return (int)std::max(1LL, std::min((long long)kFluxMaxBlocks, b));
@@ -2306,7 +2463,9 @@ int split_blocks(int nx, int ny, int nz, int kz, int w) {
     template void launch_sample<T>(const void*, const MonDev&, int, int, hipStream_t);        \
     template void launch_dft<T>(const MonDev&, int, int, hipStream_t, const int*);            \
     template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t, const int*); \
-    template void launch_seed<T>(const void*, const MonDev&, int, int, hipStream_t);
+    template void launch_seed<T>(const void*, const MonDev&, int, int, hipStream_t);            \
+    template void launch_rev_record<T>(const void*, int, int, int, int, hipStream_t);          \
+    template void launch_rev_step<T>(const void*, int, int, int, int, long long, hipStream_t);
 FDTD_INSTANTIATE(float)
 FDTD_INSTANTIATE(double)
 

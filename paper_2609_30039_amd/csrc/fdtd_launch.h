@@ -81,6 +81,15 @@ void launch_probe(const void* doms, const MonDev& m, int cs, int n, hipStream_t 
 template <typename T>
 void launch_seed(const void* doms, const MonDev& m, int as_, int n, hipStream_t s);
 
+// reversible mode: record the interface of the current set cs into record
+// slot `slot` (maxcnt: the largest face of any domain); one backward step
+// u^m -> u^{m-1} over every domain's lossless box from set rs into set ws
+// (maxcells: the largest box)
+template <typename T>
+void launch_rev_record(const void* doms, int ndom, int cs, int slot, int maxcnt, hipStream_t s);
+template <typename T>
+void launch_rev_step(const void* doms, int ndom, int rs, int ws, int m, long long maxcells, hipStream_t s);
+
 // column blocks of the split forward for block width w (64 or 32 columns)
 int split_blocks(int nx, int ny, int nz, int kz, int w);
 

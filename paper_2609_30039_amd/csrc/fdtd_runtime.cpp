@@ -80,6 +80,7 @@ struct DomHost {
     size_t nfield = 0;                       // elements per field array (pitch*ny*nz)
     int gncomp = 0;
     size_t gelems = 0;                       // per component
+    size_t rec_step = 0;                     // reversible mode: recorded interface elements per step
 };
 
 struct StateArr {
@@ -100,6 +101,7 @@ struct Base {
     virtual int step_forward(int n, unsigned flags) = 0;
     virtual int adjoint_begin(int n) = 0;
     virtual int step_adjoint(int n) = 0;
+    virtual int step_reverse(int n) = 0;
     virtual int ckpt_save(int slot) = 0;
     virtual int ckpt_restore(int slot) = 0;
     virtual int monitor(int dom, int mon, int op, void* buf, size_t bytes) = 0;
@@ -176,6 +178,10 @@ struct Handle : Base {
         hipGraphExec_t ex;
     };
     std::vector<GraphEx> graphs;
+    // reversible mode: record slots [rec_lo, rec_hi] hold the interface of the
+    // current trajectory (-1: none)
+    int rec_lo = -1, rec_hi = -1, rev_maxcnt = 0;
+    long long rev_maxcells = 0;
     // kernel timing
     bool timing_on = false;
     std::vector<hipEvent_t> evs;
@@ -550,6 +556,7 @@ struct Handle : Base {
             }
             for (int k = 0; k < s.n_sources; ++k)
                 M.take(d.src[k].wave, (size_t)std::max(1, s.sources[k].n_waveform) * ts);
+            if (d.rev) M.take(d.rec, h.rec_step * ((size_t)opt.max_steps + 1) * ts);
             if (g) {
                 for (int c = 0; c < 3; ++c) {
                     ast(d.Ea[c], h.nfield);
@@ -642,6 +649,31 @@ struct Handle : Base {
             int rc = validate(doms[q], dh[q], q);
             if (rc) return rc;
             init_scalars(q);
+        }
+        if (o->reversible) {
+            // Section 3.2: the reversible mode needs a lossless, nondispersive box
+            // between the absorbing slabs that holds the gradient box with the H
+            // neighbours its curl reads
+            if (o->max_steps < 1) return fail(FDTD_E_INVALID, "reversible mode needs max_steps >= 1");
+            bool any = false;
+            for (int q = 0; q < n; ++q) {
+                const fdtd_domain_desc& s = dh[q].desc;
+                if (!s.grad) continue;
+                any = true;
+                if (s.n_lorentz) return fail(FDTD_E_INVALID, "reversible mode: a dispersive box is not lossless");
+                for (int a = 0; a < 3; ++a) {
+                    const int lo = s.pml[2 * a], hi = s.n[a] - s.pml[2 * a + 1];
+                    if (s.grad_lo[a] < lo + (lo > 0 ? 1 : 0) || s.grad_hi[a] > hi)
+                        return fail(FDTD_E_INVALID, "reversible mode: the gradient box reaches an absorbing slab");
+                }
+            }
+            if (!any) return fail(FDTD_E_INVALID, "reversible mode needs a domain with a gradient");
+            for (int q = 0; q < n; ++q) {
+                rev_maxcnt = std::max(rev_maxcnt, std::max(dd[q].rfcnt[0], std::max(dd[q].rfcnt[1], dd[q].rfcnt[2])));
+                if (dd[q].rev)
+                    rev_maxcells = std::max(rev_maxcells, (long long)(dd[q].rhi[0] - dd[q].rlo[0]) *
+                                                              (dd[q].rhi[1] - dd[q].rlo[1]) * (dd[q].rhi[2] - dd[q].rlo[2]));
+            }
         }
         nsets = 2 + (bf16 ? 0 : o->n_ckpt);
         build_tiles();
@@ -829,6 +861,27 @@ struct Handle : Base {
                 h.gelems *= (size_t)(s.grad_hi[a] - s.grad_lo[a]);
             }
             h.gncomp = d.eps_diag ? 3 : 1;
+        }
+        d.rev = opt.reversible && s.grad ? 1 : 0;
+        h.rec_step = 0;
+        for (int f = 0; f < 6; ++f) d.rface[f] = -1;
+        if (d.rev) {
+            for (int a = 0; a < 3; ++a) {
+                d.rlo[a] = s.pml[2 * a];
+                d.rhi[a] = s.n[a] - s.pml[2 * a + 1];
+            }
+            for (int a = 0; a < 3; ++a)
+                d.rfcnt[a] = (d.rhi[(a + 1) % 3] - d.rlo[(a + 1) % 3]) * (d.rhi[(a + 2) % 3] - d.rlo[(a + 2) % 3]);
+            long long off = 0;
+            for (int f = 0; f < 6; ++f) {
+                const int a = f % 3;
+                const bool present = f < 3 ? d.rlo[a] > 0 : d.rhi[a] < s.n[a];
+                if (!present) continue;
+                d.rface[f] = off;
+                off += 2LL * d.rfcnt[a];
+            }
+            d.rec_stride = off;
+            h.rec_step = (size_t)off;
         }
         for (auto& mh : h.mons) {
             if (mh.dev.kind != 0) mh.acc_elems = (size_t)mh.dev.nf * mh.dev.ncomp * mh.npts * 2;
@@ -1082,8 +1135,50 @@ struct Handle : Base {
         return FDTD_OK;
     }
 
+    // reversible mode: interface of the current state into record slot t
+    void rev_record() {
+        if (!opt.reversible || t > opt.max_steps) return;
+        launch_rev_record<T>(d_doms, ndom, cur, t, rev_maxcnt, st);
+        if (rec_hi < 0 || t < rec_lo || t > rec_hi + 1) rec_lo = rec_hi = t;
+        else if (t == rec_hi + 1) rec_hi = t;
+    }
+
     int step_forward(int n, unsigned flags) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
+        if (opt.reversible) {   // eager steps, the interface recorded before each and after the last
+            for (int s = 0; s < n; ++s) {
+                int rc = step_forward_eager(1, flags);
+                if (rc) return rc;
+            }
+            rev_record();
+            return check("step_forward");
+        }
+        return step_forward_eager(n, flags);
+    }
+
+    int step_reverse(int n) override {
+        if (!opt.reversible) return fail(FDTD_E_STATE, "the handle was not created in reversible mode");
+        if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
+        for (int s = 0; s < n; ++s) {
+            if (t < 1 || rec_hi < 0 || t - 1 < rec_lo || t > rec_hi) {
+                char b[160];
+                snprintf(b, sizeof b, "no recorded interface for the backward step from %d (recorded %d..%d)", t,
+                         rec_lo, rec_hi);
+                return fail(FDTD_E_STATE, b);
+            }
+            const bool working = cur == wset[0] || cur == wset[1];
+            const int ws = working ? cur : write_set();
+            if (timing_on) ev_mark();
+            launch_rev_step<T>(d_doms, ndom, cur, ws, t, rev_maxcells, st);
+            if (timing_on) ev_mark();
+            cur = ws;
+            --t;
+        }
+        return check("step_reverse");
+    }
+
+    int step_forward_eager(int n, unsigned flags) {
+        if (opt.reversible) rev_record();
         bool rec = (flags & FDTD_RECORD) && !(flags & FDTD_REPLAY);
         // The split kernels update a working set in place; the fused pass
         // reads neighbours' old values after they are overwritten, so it
@@ -1092,7 +1187,8 @@ struct Handle : Base {
         const int G = opt.graph_chunk;
         for (int s = 0; s < n;) {
             const bool working = cur == wset[0] || cur == wset[1];
-            if (G > 0 && inplace && working && !timing_on && n - s >= G && (!rec || monitors_flushed())) {
+            if (G > 0 && inplace && working && !timing_on && !opt.reversible && n - s >= G &&
+                (!rec || monitors_flushed())) {
                 GraphEx* g = nullptr;
                 int rc = graph_for(rec, g);
                 if (rc) return rc;
@@ -1331,6 +1427,7 @@ struct Handle : Base {
             launch_copy(set_ptr(cur), set_ptr(ws), fstride, st);
             cur = ws;
         }
+        if (set && !adjc) rec_lo = rec_hi = -1;   // the recorded interface belongs to another trajectory
         T* p = adjc ? (c < 3 ? d.Ea[c] : d.Ha[c - 3]) + (size_t)ap * d.as
                     : (c < 3 ? d.E[c] : d.H[c - 3]) + (size_t)cur * d.fs;
         size_t nx = d.n[0], ny = d.n[1], nz = d.n[2];
@@ -1364,6 +1461,7 @@ struct Handle : Base {
         if (bytes < h.eps.size() * 8) return fail(FDTD_E_RANGE, "buffer too small for eps");
         int rc = validate_eps_only(h.desc, h, eps);
         if (rc) return rc;
+        rec_lo = rec_hi = -1;   // another trajectory
         return upload_eps(dom);
     }
 
@@ -1403,6 +1501,7 @@ struct Handle : Base {
             }
         t = 0;
         m = -1;
+        rec_lo = rec_hi = -1;
         return sync("reset");
     }
 
@@ -1482,6 +1581,11 @@ int fdtd_adjoint_begin(fdtd_t h, int32_t n_total) {
 int fdtd_step_adjoint(fdtd_t h, int32_t n_steps) {
     GUARD(h);
     return h->impl->step_adjoint(n_steps);
+}
+
+int fdtd_step_reverse(fdtd_t h, int32_t n_steps) {
+    GUARD(h);
+    return h->impl->step_reverse(n_steps);
 }
 
 int fdtd_checkpoint_save(fdtd_t h, int32_t slot) {

@@ -14,7 +14,7 @@ class Simulation:
     def __init__(self, specs, dtype: str = "f32", n_ckpt: int = 0, ckpt_storage: Optional[str] = None,
                  ckpt_checksum: bool = False, max_steps: Optional[int] = None, kernel: str = "auto",
                  dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
-                 mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0):
+                 mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0, reversible: bool = False):
         if not isinstance(specs, (list, tuple)):
             specs = [specs]
         self.specs = list(specs)
@@ -29,7 +29,7 @@ class Simulation:
         # sweep is valid for a backward pass only while it is unchanged
         self.generation = 0
         self.h = B.fdtd_create(self.specs, dt, n_ckpt, storage, ckpt_checksum, max_steps, kern, dft_block,
-                               graph_chunk, stream, mem_budget_bytes, tile_rows, tile_kz)
+                               graph_chunk, stream, mem_budget_bytes, tile_rows, tile_kz, reversible)
 
     def close(self):
         if self.h is not None:
@@ -51,6 +51,11 @@ class Simulation:
 
     def step_adjoint(self, n: int = 1):
         B.fdtd_step_adjoint(self.h, n)
+
+    def step_reverse(self, n: int = 1):
+        """Reversible mode: n backward steps of the lossless box (the forward
+        state there goes from u^m to u^{m-n})."""
+        B.fdtd_step_reverse(self.h, n)
 
     def save(self, slot: int):
         B.fdtd_checkpoint_save(self.h, slot)

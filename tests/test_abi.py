@@ -153,3 +153,23 @@ def test_pole_descriptors_checked():
             return []
 
     _refused(_spec(lorentz=[NoPoles((2, 2, 2), (5, 5, 5), 0.0, 0.0, 0.0)]), B.FDTD_E_INVALID)
+
+
+def test_reversible_mode_admissibility():
+    """The reversible mode needs a lossless interior around the gradient box
+    (Section 3.2): a dispersive box, a gradient box inside an absorbing slab
+    or max_steps 0 are refused before any allocation; an admissible domain
+    passes validation (then the tiny budget refuses)."""
+    spec, _ = W.design_patch(pml=6, design=12, patch=10, n_steps=20, n_f=2, shape=(40, 34, 38))
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([spec], B.FDTD_F32, max_steps=20, reversible=True, mem_budget_bytes=1.0)
+    assert e.value.code == B.FDTD_E_NOMEM
+    _refused(spec, B.FDTD_E_INVALID, max_steps=0, reversible=True)
+    bad, _ = W.design_patch(pml=6, design=12, patch=10, n_steps=20, n_f=2, shape=(40, 34, 38))
+    bad.grad_box = ((6, 14, 14), (20, 26, 26))      # touches the low x slab's neighbour row
+    _refused(bad, B.FDTD_E_INVALID, max_steps=20, reversible=True)
+    lor = W.lorentz_flux(pml=6, lorentz=8, n_steps=20, n_f=2, shape=(40, 30, 36))
+    lor.grad_box = ((10, 10, 10), (30, 20, 26))
+    _refused(lor, B.FDTD_E_INVALID, max_steps=20, reversible=True)
+    from paper_2609_30039_amd import adjoint as A
+    assert A.reversible_admissible(spec) and not A.reversible_admissible(bad) and not A.reversible_admissible(lor)

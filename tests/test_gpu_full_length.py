@@ -124,3 +124,22 @@ def test_design_patch_full_gradient(dtype):
     assert eJ < (1e-10 if dtype == "f64" else 1e-5)
     assert eg < (1e-10 if dtype == "f64" else 1e-4)
     sim.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_design_patch_full_gradient_reversible(dtype, tol):
+    """The same 212^3 x 2000 gradient by the reversible mode: the design box
+    lies in the lossless interior, so the reverse sweep steps the interior
+    backward with the recorded interface instead of replaying checkpoints."""
+    import time
+    rec = G.read("design_patch_full")
+    spec, _ = W.design_patch()
+    N = spec.n_steps
+    sim = Simulation(spec, dtype=dtype, reversible=True, max_steps=N, kernel="split", tile_rows=8, tile_kz=3)
+    t0 = time.perf_counter()
+    g = A.reversible_gradient(sim, N, lambda s_: {(0, 0): 2.0 * s_.spectra(0)})[0][0]
+    el = time.perf_counter() - t0
+    eg = rel(g, rec["grad"])
+    print(f"design {dtype} reversible: gradient rel L2 vs oracle {eg:.3e} ({el:.2f} s forward + reverse)", flush=True)
+    assert eg < tol
+    sim.close()
