@@ -21,6 +21,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--shape", default="auto,0,0", help="KERNEL,ROWS,KZ (kernel auto|split|fused)")
     ap.add_argument("--adjoint", action="store_true", help="time adjoint steps instead of forward steps")
+    ap.add_argument("--reverse", action="store_true",
+                    help="reversible mode: after the forward steps, time as many backward steps")
     ap.add_argument("--copy-bytes", type=int, default=0, help="also run the device copy kernel on this many bytes")
     ap.add_argument("--monitors", action="store_true", help="record monitors while stepping")
     ap.add_argument("--poles", type=int, default=0, help="put this pole set (3 or 16) in every dispersive box")
@@ -38,14 +40,22 @@ def main(argv=None):
     stream = torch.cuda.current_stream().cuda_stream
     cap = max(args.steps + args.warmup + 2, spec.n_steps)
     sim = Simulation(spec, dtype=args.dtype, stream=stream, max_steps=cap, kernel=kk, tile_rows=int(rr),
-                     tile_kz=int(zz))
+                     tile_kz=int(zz), reversible=args.reverse)
     print(f"[run_workload] {args.workload} {spec.shape} {args.dtype} shape={args.shape} "
-          f"{'adjoint' if args.adjoint else 'forward'} steps={args.steps}", flush=True)
+          f"{'reverse' if args.reverse else ('adjoint' if args.adjoint else 'forward')} steps={args.steps}",
+          flush=True)
     sim.step(args.warmup, record=args.monitors)
     torch.cuda.synchronize()
     sim.timing(1)
     t0 = time.perf_counter()
-    if args.adjoint:
+    if args.reverse:
+        sim.timing(0)
+        sim.step(args.steps, record=args.monitors)
+        torch.cuda.synchronize()
+        sim.timing(1)
+        t0 = time.perf_counter()
+        sim.step_reverse(args.steps)
+    elif args.adjoint:
         t = sim.steps[0]
         for _ in range(args.steps):
             sim.adjoint_begin(t + 1)
