@@ -48,6 +48,9 @@ typedef struct {
     double pdeps[16];            /* Lorentz: delta eps (Drude: unused) */
     double pwdt[16];             /* Lorentz: omega_0 dt; Drude: omega_p dt */
     double pgdt[16];             /* gamma dt */
+    int per[3];                  /* 1: the axis is periodic (Bloch, Section 2.2): no PEC wall, the
+                                    neighbour past the last node is the first one times bsign */
+    double bsign[3];             /* real Bloch factor exp(i k L) = +1 or -1 of a periodic axis */
 } orc_params;
 
 #define ORC_MAXP 16
@@ -67,9 +70,27 @@ static size_t stride_of(const orc_params *P, int a) {
 }
 
 /* PEC: E component c is tangential to the low faces normal to the other two
-   axes; those boundary nodes are held at zero and are not degrees of freedom. */
-static int e_masked(int c, const int x[3]) {
-    return x[(c + 1) % 3] == 0 || x[(c + 2) % 3] == 0;
+   axes; those boundary nodes are held at zero and are not degrees of freedom.
+   A periodic axis has no wall. */
+static int e_masked(const orc_params *P, int c, const int x[3]) {
+    int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    return (x[a1] == 0 && !P->per[a1]) || (x[a2] == 0 && !P->per[a2]);
+}
+
+/* Field value one node back / forward along axis a from node p.  Past the
+   domain: zero (the wall's ghost), or on a periodic axis the node at the other
+   end times the Bloch factor: F(N) = bsign F(0) and F(-1) = bsign^-1 F(N-1),
+   where bsign^-1 = bsign for the real factors +1 and -1. */
+static double back(const orc_params *P, const double *F, const int x[3], size_t p, int a) {
+    size_t s = stride_of(P, a);
+    if (x[a] > 0) return F[p - s];
+    return P->per[a] ? P->bsign[a] * F[p + (size_t)(P->n[a] - 1) * s] : 0.0;
+}
+
+static double fwd(const orc_params *P, const double *F, const int x[3], size_t p, int a) {
+    size_t s = stride_of(P, a);
+    if (x[a] < P->n[a] - 1) return F[p + s];
+    return P->per[a] ? P->bsign[a] * F[p - (size_t)(P->n[a] - 1) * s] : 0.0;
 }
 
 static int is_lorentz(const orc_params *P, size_t p) { return P->lor && P->lor[p]; }
@@ -109,7 +130,7 @@ static double curl_minus(const orc_params *P, const orc_state *U, int c, const i
         int h = t == 0 ? (c + 2) % 3 : (c + 1) % 3;
         double sgn = t == 0 ? 1.0 : -1.0;
         const double *H = U->F[3 + h];
-        double D = H[p] - (x[a] > 0 ? H[p - stride_of(P, a)] : 0.0);
+        double D = H[p] - back(P, H, x, p, a);
         double Dt = D;
         if (P->slab[a][x[a]]) {
             double *psi = U->psiE[c][a];
@@ -131,7 +152,7 @@ static double curl_plus(const orc_params *P, orc_state *U, int c, const int x[3]
         int e = t == 0 ? (c + 2) % 3 : (c + 1) % 3;
         double sgn = t == 0 ? 1.0 : -1.0;
         const double *E = U->F[e];
-        double D = (x[a] < P->n[a] - 1 ? E[p + stride_of(P, a)] : 0.0) - E[p];
+        double D = fwd(P, E, x, p, a) - E[p];
         double Dt = D;
         if (P->slab[a][x[a]]) {
             double *psi = U->psiH[c][a];
@@ -179,7 +200,7 @@ void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, 
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
                     int x[3] = {i, j, k};
-                    if (e_masked(c, x)) continue;
+                    if (e_masked(P, c, x)) continue;
                     size_t p = IDX(P, i, j, k);
                     double curl = curl_minus(P, U, c, x, p, 1);
                     double en1 = e_pre(P, U, c, p, curl);
@@ -191,7 +212,7 @@ void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, 
         size_t p = (size_t)src_idx[s];
         int c = src_comp[s];
         int x[3] = {(int)(p % nx), (int)((p / nx) % ny), (int)(p / ((size_t)nx * ny))};
-        if (e_masked(c, x)) continue;
+        if (e_masked(P, c, x)) continue;
         U->F[c][p] += src_amp[s];
     }
     if (P->lor) {
@@ -203,7 +224,7 @@ void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, 
                     for (int i = 0; i < nx; ++i) {
                         int x[3] = {i, j, k};
                         size_t p = IDX(P, i, j, k);
-                        if (!P->lor[p] || e_masked(c, x)) continue;
+                        if (!P->lor[p] || e_masked(P, c, x)) continue;
                         for (int q = 0; q < P->npole; ++q) {
                             double al, xi, g;
                             pole_consts(P, q, &al, &xi, &g);
@@ -291,7 +312,7 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                 for (int i = 0; i < nx; ++i) {
                     int x[3] = {i, j, k};
                     size_t p = IDX(P, i, j, k);
-                    if (e_masked(c, x)) {
+                    if (e_masked(P, c, x)) {
                         A->F[c][p] = 0.0;
                         Epb[c][p] = 0.0;
                         continue;
@@ -343,7 +364,7 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {
                         int x[3] = {i, j, k};
-                        if (e_masked(c, x)) continue;
+                        if (e_masked(P, c, x)) continue;
                         size_t p = IDX(P, i, j, k);
                         double curl = curl_minus(P, U, c, x, p, 0);
                         double ep = P->eps[c][p];
@@ -371,7 +392,7 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                     for (int i = 0; i < nx; ++i) {
                         int x[3] = {i, j, k};
                         size_t p = IDX(P, i, j, k);
-                        if (e_masked(c, x)) {
+                        if (e_masked(P, c, x)) {
                             Dbar[p] = 0.0;
                             continue;
                         }

@@ -64,7 +64,8 @@ class _Params(C.Structure):
                 ("bH", C.c_void_p * 3), ("cH", C.c_void_p * 3), ("kiH", C.c_void_p * 3),
                 ("slab", C.c_void_p * 3), ("eps", C.c_void_p * 3), ("lor", C.c_void_p),
                 ("npole", C.c_int), ("pkind", C.c_int * MAXP), ("pdeps", C.c_double * MAXP),
-                ("pwdt", C.c_double * MAXP), ("pgdt", C.c_double * MAXP)]
+                ("pwdt", C.c_double * MAXP), ("pgdt", C.c_double * MAXP),
+                ("per", C.c_int * 3), ("bsign", C.c_double * 3)]
 
 
 class _State(C.Structure):
@@ -140,6 +141,10 @@ class OracleSim:
         P = _Params()
         P.n[0], P.n[1], P.n[2] = nx, ny, nz
         P.S = S
+        self.per = tuple(int(v) for v in getattr(spec, "periodic", (0, 0, 0)))
+        for a in range(3):
+            P.per[a] = self.per[a]
+            P.bsign[a] = float(getattr(spec, "bloch_sign", (1, 1, 1))[a])
         self.tabE, self.tabH = [], []
         for a in range(3):
             n = spec.shape[a]
@@ -231,7 +236,8 @@ class OracleSim:
         x = (i, j, k)
         m = np.zeros((self.NSTATE,) + self.shape3, dtype=bool)
         for c in range(3):
-            m[F0 + c] = ~((x[(c + 1) % 3] == 0) | (x[(c + 2) % 3] == 0))
+            a1, a2 = (c + 1) % 3, (c + 2) % 3
+            m[F0 + c] = ~(((x[a1] == 0) & (not self.per[a1])) | ((x[a2] == 0) & (not self.per[a2])))
             m[F0 + 3 + c] = True
         for r, (c, a) in enumerate(PSI_PAIRS):
             sl = self.tabE[a][3][x[a]].astype(bool)
@@ -374,6 +380,9 @@ class OracleSim:
         Forward states are regenerated by recursive bisection: to reverse
         steps [lo, hi) from u^lo, advance a copy to the midpoint, reverse the
         upper half, then the lower half from u^lo."""
+        if any(self.per):
+            raise ValueError("periodic domains: this oracle has no adjoint across periodic seams (the library "
+                             "refuses gradients there too)")
         u_start = np.zeros_like(self.u) if u0 is None else u0.copy()
         a = np.zeros_like(self.u)
         g = np.zeros((3, self.N))

@@ -17,6 +17,7 @@ import json
 import os
 from typing import Dict, List, Optional, Sequence
 
+from . import binding as B
 from .sim import Simulation
 
 CANDIDATES = [
@@ -43,7 +44,8 @@ def signature(specs: Sequence, dtype: str, adjoint: bool) -> str:
     for s in specs:
         lor = [(L.lo, L.hi, [p.kind for p in L.pole_list()]) for L in s.lorentz]
         src = [(x.kind, x.comp, tuple(x.pos)) for x in s.sources]
-        h.update(repr((s.shape, tuple(s.pml), s.eps_kind, s.eps_box, lor, src, s.grad_box)).encode())
+        h.update(repr((s.shape, tuple(s.pml), s.eps_kind, s.eps_box, lor, src, s.grad_box,
+                       tuple(getattr(s, "periodic", (0, 0, 0))))).encode())
     dev = "unknown"
     try:
         import torch
@@ -70,7 +72,12 @@ def _time(specs, dtype, cand, steps, adjoint, stream, min_ms) -> float:
     that at least min_ms of kernel time is measured (clocks need a sustained
     load before they settle; a handful of launches under-reports)."""
     cap = max(steps + 4, 64)
-    sim = Simulation(specs, dtype=dtype, stream=stream, max_steps=cap, **cand)
+    try:
+        sim = Simulation(specs, dtype=dtype, stream=stream, max_steps=cap, **cand)
+    except B.FdtdError as e:
+        if e.code != B.FDTD_E_INVALID:
+            raise
+        return float("inf")                 # a shape this workload does not admit (e.g. periodic + fused)
     try:
         sim.step(2, record=False)
         sim.timing(1)

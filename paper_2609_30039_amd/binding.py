@@ -84,7 +84,8 @@ class DomainDesc(C.Structure):
                 ("n_lorentz", C.c_int32), ("lorentz", LorentzDesc), ("n_sources", C.c_int32),
                 ("sources", SourceDesc * FDTD_MAX_SOURCES), ("n_monitors", C.c_int32),
                 ("monitors", MonitorDesc * FDTD_MAX_MONITORS), ("grad", C.c_int32),
-                ("grad_lo", C.c_int32 * 3), ("grad_hi", C.c_int32 * 3)]
+                ("grad_lo", C.c_int32 * 3), ("grad_hi", C.c_int32 * 3),
+                ("periodic", C.c_int32 * 3), ("bloch_sign", C.c_int32 * 3)]
 
 
 class Options(C.Structure):
@@ -157,6 +158,9 @@ def domain_desc(spec, keep: list) -> DomainDesc:
     d = DomainDesc()
     for a in range(3):
         d.n[a] = spec.shape[a]
+    for a in range(3):
+        d.periodic[a] = int(getattr(spec, "periodic", (0, 0, 0))[a])
+        d.bloch_sign[a] = int(getattr(spec, "bloch_sign", (1, 1, 1))[a])
     d.courant = spec.courant
     for q in range(6):
         d.pml[q] = spec.pml[q]

@@ -88,6 +88,10 @@ struct DomDev {
     T lgs;                     // sum of lg: the E^{n-1} weight, denominator eps + lgs/4
     long long lbox;            // cells of the box: pole p of W and Wold at + p * lbox
     T* lor[3][3];              // [0 Eold | 1 W | 2 Wold][component] over the Lorentz box
+    // Bloch-periodic axes (Section 2.2; x and y only): no wall, and the
+    // neighbour past the last node is the first one times bsign (+1 or -1)
+    int per[3];
+    T bsign[3];
     int nsrc;
     SrcDev<T> src[kMaxSrc];
     int nsmp;                  // plane monitors sampled inside the split H kernel
@@ -177,6 +181,30 @@ __device__ __forceinline__ bool e_masked(int c, int i, int j, int k) {
     return coord((c + 1) % 3, i, j, k) == 0 || coord((c + 2) % 3, i, j, k) == 0;
 }
 
+// the same with the domain's periodic axes, which have no wall (forward paths)
+template <typename T>
+__device__ __forceinline__ bool e_masked_d(const DomDev<T>& d, int c, int i, int j, int k) {
+    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+    return (coord(a1, i, j, k) == 0 && !d.per[a1]) || (coord(a2, i, j, k) == 0 && !d.per[a2]);
+}
+
+// a field one node back (x[a] - 1) / forward (x[a] + 1) along axis a = 0, 1
+// from flat index f: the ghost zero past a wall, across a periodic seam the
+// node at the other end times the real Bloch factor
+template <typename T>
+__device__ __forceinline__ T nb_back(const DomDev<T>& d, const FDTD_GLOBAL T* F, long long f, int a, int x) {
+    const long long s = a == 0 ? 1 : (long long)d.pitch;
+    if (x > 0) return F[f - s];
+    return d.per[a] ? d.bsign[a] * F[f + (long long)(d.n[a] - 1) * s] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_fwd(const DomDev<T>& d, const FDTD_GLOBAL T* F, long long f, int a, int x) {
+    const long long s = a == 0 ? 1 : (long long)d.pitch;
+    if (x + 1 < d.n[a]) return F[f + s];
+    return d.per[a] ? d.bsign[a] * F[f - (long long)(d.n[a] - 1) * s] : T(0);
+}
+
 // ---------------------------------------------------------- forward pieces
 // Stretched difference of one curl term: D is the raw difference along axis
 // a at node (i,j,k), r the slab slot, toff 0 (E side) or 3 (H side) in the
@@ -208,7 +236,7 @@ __device__ __forceinline__ T e_update_v(const DomDev<T>& d, int c, int i, int j,
                                         T h1, T h1m, T e, T einv, int rs, int ws, bool own, int t) {
     const bool lorc = in_lor(d, i, j, k);
     const long long fs = d.fs;
-    if (e_masked(c, i, j, k)) {
+    if (e_masked_d(d, c, i, j, k)) {
         if (own && lorc) {
             long long q = lidx(d, i, j, k) + ws * fs;
             gp(d.lor[0][c])[q] = T(0);
@@ -264,8 +292,8 @@ __device__ __forceinline__ T e_update_v(const DomDev<T>& d, int c, int i, int j,
 template <typename T>
 __device__ __forceinline__ T e_update(const DomDev<T>& d, int c, int i, int j, int k, long long f, T h0, T h0m,
                                       T h1, T h1m, int rs, int ws, bool own, int t) {
-    T e = e_masked(c, i, j, k) ? T(0) : gp(d.E[c])[f + rs * d.fs];
-    T einv = e_masked(c, i, j, k) ? T(0) : epsinv_at(d, c, i, j, k);
+    T e = e_masked_d(d, c, i, j, k) ? T(0) : gp(d.E[c])[f + rs * d.fs];
+    T einv = e_masked_d(d, c, i, j, k) ? T(0) : epsinv_at(d, c, i, j, k);
     return e_update_v(d, c, i, j, k, f, h0, h0m, h1, h1m, e, einv, rs, ws, own, t);
 }
 

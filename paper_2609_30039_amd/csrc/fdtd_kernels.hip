@@ -293,10 +293,10 @@ __device__ __forceinline__ void cole_fetch(const DomDev<T>& d, ColE<T>& p, const
     p.hx = h[0][f];
     p.hy = h[1][f];
     p.hz = h[2][f];
-    p.hy_xm = i > 0 ? h[1][f - 1] : T(0);
-    p.hz_xm = i > 0 ? h[2][f - 1] : T(0);
-    p.hx_ym = j > 0 ? h[0][f - d.pitch] : T(0);
-    p.hz_ym = j > 0 ? h[2][f - d.pitch] : T(0);
+    p.hy_xm = nb_back(d, h[1], f, 0, i);
+    p.hz_xm = nb_back(d, h[2], f, 0, i);
+    p.hx_ym = nb_back(d, h[0], f, 1, j);
+    p.hz_ym = nb_back(d, h[2], f, 1, j);
     p.e[0] = e[0][f];
     p.e[1] = e[1][f];
     p.e[2] = e[2][f];
@@ -323,8 +323,8 @@ __device__ __forceinline__ void e_lor_block(const DomDev<T>* __restrict__ doms, 
     const FDTD_GLOBAL T* Hy = gp(d.H[1] + so);
     const FDTD_GLOBAL T* Hz = gp(d.H[2] + so);
     T hx = Hx[f], hy = Hy[f], hz = Hz[f];
-    T hy_xm = i > 0 ? Hy[f - 1] : T(0), hz_xm = i > 0 ? Hz[f - 1] : T(0);
-    T hx_ym = j > 0 ? Hx[f - d.pitch] : T(0), hz_ym = j > 0 ? Hz[f - d.pitch] : T(0);
+    T hy_xm = nb_back(d, Hy, f, 0, i), hz_xm = nb_back(d, Hz, f, 0, i);
+    T hx_ym = nb_back(d, Hx, f, 1, j), hz_ym = nb_back(d, Hz, f, 1, j);
     T hxm = k > 0 ? Hx[f - pl] : T(0), hym = k > 0 ? Hy[f - pl] : T(0);
     // Ex: d-_y Hz - d-_z Hy ; Ey: d-_z Hx - d-_x Hz ; Ez: d-_x Hy - d-_y Hx
     T ex = e_update(d, 0, i, j, k, f, hz, hz_ym, hy, hym, rs, ws, true, t);
@@ -375,23 +375,26 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
             T Dx0 = cu.hz - cu.hz_ym, Dx1 = cu.hy - hym;    // Ex: Hz along y, Hy along z
             T Dy0 = cu.hx - hxm, Dy1 = cu.hz - cu.hz_xm;    // Ey: Hx along z, Hz along x
             T Dz0 = cu.hy - cu.hy_xm, Dz1 = cu.hx - cu.hx_ym;   // Ez: Hy along x, Hx along y
+            // unmasked nodes (E tangential to a wall is held at 0; periodic axes have none)
+            const bool fx = !e_masked_d(d, 0, i, j, k), fy = !e_masked_d(d, 1, i, j, k),
+                       fz = !e_masked_d(d, 2, i, j, k);
             if (bf.cp) {
                 const Cpml1<T> cz = cpml_at(d, 2, k);
                 const T* pe = cu.ps;
                 if (cy.side >= 0) {
                     int q = poff(d, 1, cy.side, i, j, k);
-                    Dx0 = st_pref(d.psiE[1][cy.side][0], wo, q, j > 0 && k > 0, cy.bE, cy.cE, cy.kE, pe[0], Dx0);
-                    Dz1 = st_pref(d.psiE[1][cy.side][1], wo, q, i > 0 && j > 0, cy.bE, cy.cE, cy.kE, pe[1], Dz1);
+                    Dx0 = st_pref(d.psiE[1][cy.side][0], wo, q, fx, cy.bE, cy.cE, cy.kE, pe[0], Dx0);
+                    Dz1 = st_pref(d.psiE[1][cy.side][1], wo, q, fz, cy.bE, cy.cE, cy.kE, pe[1], Dz1);
                 }
                 if (cz.side >= 0) {
                     int q = poff(d, 2, cz.side, i, j, k);
-                    Dy0 = st_pref(d.psiE[2][cz.side][0], wo, q, i > 0 && k > 0, cz.bE, cz.cE, cz.kE, pe[2], Dy0);
-                    Dx1 = st_pref(d.psiE[2][cz.side][1], wo, q, j > 0 && k > 0, cz.bE, cz.cE, cz.kE, pe[3], Dx1);
+                    Dy0 = st_pref(d.psiE[2][cz.side][0], wo, q, fy, cz.bE, cz.cE, cz.kE, pe[2], Dy0);
+                    Dx1 = st_pref(d.psiE[2][cz.side][1], wo, q, fx, cz.bE, cz.cE, cz.kE, pe[3], Dx1);
                 }
                 if (cx.side >= 0) {
                     int q = poff(d, 0, cx.side, i, j, k);
-                    Dz0 = st_pref(d.psiE[0][cx.side][0], wo, q, i > 0 && j > 0, cx.bE, cx.cE, cx.kE, pe[4], Dz0);
-                    Dy1 = st_pref(d.psiE[0][cx.side][1], wo, q, i > 0 && k > 0, cx.bE, cx.cE, cx.kE, pe[5], Dy1);
+                    Dz0 = st_pref(d.psiE[0][cx.side][0], wo, q, fz, cx.bE, cx.cE, cx.kE, pe[4], Dz0);
+                    Dy1 = st_pref(d.psiE[0][cx.side][1], wo, q, fy, cx.bE, cx.cE, cx.kE, pe[5], Dy1);
                 }
             }
             ex = fma(S * cu.ei[0], Dx0 - Dx1, cu.e[0]);
@@ -406,10 +409,10 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
                     else ez += v;
                 }
             }
-            // PEC: E_c is zero where the index along c+1 or c+2 is 0
-            if (j == 0 || k == 0) ex = T(0);
-            if (i == 0 || k == 0) ey = T(0);
-            if (i == 0 || j == 0) ez = T(0);
+            // PEC: E_c is zero where the index along c+1 or c+2 is 0 (not on a periodic axis)
+            if (!fx) ex = T(0);
+            if (!fy) ey = T(0);
+            if (!fz) ez = T(0);
             ew[0][f] = ex;
             ew[1][f] = ey;
             ew[2][f] = ez;
@@ -440,10 +443,10 @@ __device__ __forceinline__ void colh_fetch(const DomDev<T>& d, ColH<T>& p, const
     p.e1[0] = up ? e[0][f + pl] : T(0);
     p.e1[1] = up ? e[1][f + pl] : T(0);
     p.e1[2] = up ? e[2][f + pl] : T(0);
-    p.ey_xp = i + 1 < d.n[0] ? e[1][f + 1] : T(0);
-    p.ez_xp = i + 1 < d.n[0] ? e[2][f + 1] : T(0);
-    p.ex_yp = j + 1 < d.n[1] ? e[0][f + d.pitch] : T(0);
-    p.ez_yp = j + 1 < d.n[1] ? e[2][f + d.pitch] : T(0);
+    p.ey_xp = nb_fwd(d, e[1], f, 0, i);
+    p.ez_xp = nb_fwd(d, e[2], f, 0, i);
+    p.ex_yp = nb_fwd(d, e[0], f, 1, j);
+    p.ez_yp = nb_fwd(d, e[2], f, 1, j);
     p.h[0] = h[0][f];
     p.h[1] = h[1][f];
     p.h[2] = h[2][f];

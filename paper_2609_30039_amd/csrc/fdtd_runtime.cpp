@@ -852,6 +852,10 @@ struct Handle : Base {
             sd.k = sr.pos[2];
             sd.nwave = sr.n_waveform;
         }
+        for (int a = 0; a < 3; ++a) {
+            d.per[a] = s.periodic[a] ? 1 : 0;
+            d.bsign[a] = (T)(s.periodic[a] ? s.bloch_sign[a] : 1);
+        }
         d.grad = s.grad ? 1 : 0;
         if (s.grad) {
             h.gelems = 1;
@@ -953,6 +957,17 @@ struct Handle : Base {
                     }
                 }
             }
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (s.periodic[a] != 0 && s.periodic[a] != 1) return fail(FDTD_E_INVALID, "periodic flag must be 0 or 1");
+            if (!s.periodic[a]) continue;
+            if (a == 2) return fail(FDTD_E_INVALID, "periodic z is not supported (x and y only)");
+            if (s.pml[2 * a] || s.pml[2 * a + 1])
+                return fail(FDTD_E_INVALID, "a periodic axis takes no absorbing cells");
+            if (s.bloch_sign[a] != 1 && s.bloch_sign[a] != -1)
+                return fail(FDTD_E_INVALID, "bloch_sign of a periodic axis must be +1 or -1");
+            if (s.grad) return fail(FDTD_E_INVALID, "periodic domains take no gradient (no adjoint across the seam)");
+            if (opt.kernel == FDTD_KERNEL_FUSED) return fail(FDTD_E_INVALID, "periodic domains need the split kernels");
         }
         if (s.n_lorentz < 0 || s.n_lorentz > 1) return fail(FDTD_E_INVALID, "at most one Lorentz box per domain");
         if (s.n_lorentz) {

@@ -106,6 +106,8 @@ class DomainSpec:
     monitors: List[MonitorSpec] = field(default_factory=list)
     grad_box: Optional[Box] = None
     n_steps: int = 0
+    periodic: Tuple[int, int, int] = (0, 0, 0)  # 1: Bloch-periodic axis (x or y), no absorber on it
+    bloch_sign: Tuple[int, int, int] = (1, 1, 1)  # real Bloch factor exp(i k L) of each periodic axis: +1 or -1
 
     @property
     def ncells(self) -> int:

@@ -173,3 +173,23 @@ def test_reversible_mode_admissibility():
     _refused(lor, B.FDTD_E_INVALID, max_steps=20, reversible=True)
     from paper_2609_30039_amd import adjoint as A
     assert A.reversible_admissible(spec) and not A.reversible_admissible(bad) and not A.reversible_admissible(lor)
+
+
+def test_periodic_descriptor_checked():
+    """Periodic axes: x and y only, no absorbing cells on them, a Bloch sign of
+    +1 or -1, split kernels and no gradient; an admissible one passes
+    validation (the tiny budget then refuses)."""
+    def spec(**kw):
+        s = W.DomainSpec(shape=(8, 8, 12), courant=W.courant_3d(), pml=(0, 0, 0, 0, 3, 3), eps_kind="iso",
+                         eps_box=((0, 0, 0), (8, 8, 12)), eps=np.ones((1, 12, 8, 8)), periodic=(1, 1, 0))
+        for k, v in kw.items():
+            setattr(s, k, v)
+        return s
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([spec()], B.FDTD_F32, mem_budget_bytes=1.0)
+    assert e.value.code == B.FDTD_E_NOMEM
+    _refused(spec(periodic=(1, 1, 1)), B.FDTD_E_INVALID)
+    _refused(spec(pml=(2, 2, 0, 0, 3, 3)), B.FDTD_E_INVALID)
+    _refused(spec(bloch_sign=(2, 1, 1)), B.FDTD_E_INVALID)
+    _refused(spec(grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID)
+    _refused(spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)

@@ -75,6 +75,131 @@ def test_pec_mode_closed_form(c):
             assert np.abs(sim.field(3 + c)).max() < 1e-13
 
 
+@pytest.mark.parametrize("sx,sy", [(1, 1), (-1, 1), (1, -1), (-1, -1)])
+def test_bloch_periodic_mode_closed_form(sx, sy):
+    """x and y Bloch-periodic with real factors exp(i k L) = sx, sy (Section
+    2.2), z between PEC walls: Ez = cos(tx i) cos(ty j), uniform in z, with
+    tx = (2 pi m + beta_x)/Nx (beta = 0 for +1, pi for -1), is a discrete
+    eigenmode.  Its field values across the seam are those of the
+    continuation, so it evolves by the Yee dispersion relation with
+    lambda = 4 (sin^2(tx/2) + sin^2(ty/2)), exactly as the PEC-box mode."""
+    shape = (10, 12, 5)
+    nx, ny, nz = shape
+    eps = 2.3
+    spec = _blank(shape, eps=eps)
+    spec.periodic = (1, 1, 0)
+    spec.bloch_sign = (sx, sy, 1)
+    sim = O.OracleSim(spec)
+    tx = (2 * math.pi * 2 + (0 if sx > 0 else math.pi)) / nx
+    ty = (2 * math.pi * 1 + (0 if sy > 0 else math.pi)) / ny
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = np.cos(tx * i) * np.cos(ty * j)
+    # closed-form forward differences, valid across the seam by the Bloch factor
+    d1 = -2.0 * math.sin(tx / 2) * np.sin(tx * (i + 0.5)) * np.cos(ty * j)
+    d2 = -2.0 * math.sin(ty / 2) * np.sin(ty * (j + 0.5)) * np.cos(tx * i)
+    lam = 4.0 * (math.sin(tx / 2) ** 2 + math.sin(ty / 2) ** 2)
+    sim.field(2)[:] = phi
+    S = spec.courant
+    w = 2.0 * math.asin(0.5 * S * math.sqrt(lam / eps))
+    for n in range(1, 101):
+        sim.step(1, record=False)
+        e = math.cos((n - 0.5) * w) / math.cos(w / 2)
+        e1 = math.cos((n + 0.5) * w) / math.cos(w / 2)
+        h = eps * (e1 - e) / (S * lam)
+        if n % 25 == 0 or n < 3:
+            np.testing.assert_allclose(sim.field(2), e * phi, atol=1e-12, rtol=0)
+            np.testing.assert_allclose(sim.field(3), h * d2, atol=1e-12, rtol=0)
+            np.testing.assert_allclose(sim.field(4), -h * d1, atol=1e-12, rtol=0)
+            for q in (0, 1, 5):
+                assert np.abs(sim.field(q)).max() < 1e-13
+
+
+@pytest.mark.parametrize("signs", [(1, 1), (-1, 1)])
+def test_discrete_energy_invariant_bloch_periodic(signs):
+    """With real Bloch factors the seam keeps C^- = (C^+)^T, so the discrete
+    energy of a lossless box, periodic in x and y, stays constant; the E nodes
+    on a periodic axis's first plane are degrees of freedom (no wall)."""
+    shape = (9, 8, 10)
+    nx, ny, nz = shape
+    rng = np.random.Generator(np.random.PCG64(17))
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), eps_kind="diag", eps_box=((0, 0, 0), shape),
+                        eps=1.0 + 3.0 * rng.random((3, nz, ny, nx)), periodic=(1, 1, 0),
+                        bloch_sign=(signs[0], signs[1], 1))
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    assert dof.reshape(sim.NSTATE, nz, ny, nx)[O.F0 + 2, 3, 0, 0]       # Ez on the x = y = 0 edge: free
+    sim.u[:] = rng.standard_normal(sim.u.shape) * dof
+    sim.u[O.PSIE0:] = 0.0
+    eps = sim.eps
+    hist = []
+    for n in range(400):
+        h_prev = [sim.field(3 + c).copy() for c in range(3)]
+        sim.step(1, record=False)
+        hist.append(sum(np.sum(eps[c] * sim.field(c) ** 2) for c in range(3)) +
+                    sum(np.sum(h_prev[c] * sim.field(3 + c)) for c in range(3)))
+    hist = np.asarray(hist)
+    assert np.max(np.abs(hist - hist[0])) / abs(hist[0]) < 1e-12
+
+
+def slab_spec(slab_eps, n_steps=3000, nf=31, nxy=4):
+    """The slab check of Section 6.1 on the unit mesh: a cell periodic in x
+    and y, 16 absorbing cells at each z end, an Ex sheet, a front flux plane
+    between the sheet and the slab, an 8-cell slab of permittivity slab_eps
+    (index 1.5 for 2.25) and a back flux plane; 31 wavelengths of 52 to 72
+    cells (the paper's 1.3 to 1.8 um on a 0.025 um mesh, slab 0.2 um)."""
+    nz = 132
+    shape = (nxy, nxy, nz)
+    S = W.courant_3d()
+    lam = np.linspace(52.0, 72.0, nf)
+    w = 2.0 * math.pi * S / lam                      # omega dt with dt = S (h = c = 1)
+    eps = np.ones((1, nz, nxy, nxy))
+    eps[0, 60:68] = slab_eps
+    wc = 2.0 * math.pi * S / 62.0
+    spec = W.DomainSpec(
+        shape=shape, courant=S, pml=(0, 0, 0, 0, 16, 16), eps_kind="iso", eps_box=((0, 0, 0), shape), eps=eps,
+        sources=[W.SourceSpec("plane_z", 0, (0, 0, 22), W.gaussian_sine(n_steps, wc, 60.0, 240.0))],
+        monitors=[W.MonitorSpec("flux_z", pos=(0, 0, 40), rect=(0, nxy, 0, nxy), omega_dt=w),
+                  W.MonitorSpec("flux_z", pos=(0, 0, 100), rect=(0, nxy, 0, nxy), omega_dt=w)],
+        n_steps=n_steps, periodic=(1, 1, 0))
+    return spec, lam
+
+
+def slab_TR(sp_empty, sp_slab):
+    """T and R from the flux-plane spectra of the empty cell and of the slab:
+    T = transmitted / incident flux at the back plane, R = the flux of the
+    reflected field (slab minus empty) at the front plane, -z taken positive."""
+    F = O.OracleSim.flux_from_spectra
+    T = F(sp_slab[1]) / F(sp_empty[1])
+    R = -F(sp_slab[0] - sp_empty[0]) / F(sp_empty[0])
+    return T, R
+
+
+def eq5_T(lam, n=1.5, d=8.0):
+    return 1.0 / (1.0 + ((n * n - 1.0) / (2.0 * n)) ** 2 * np.sin(2.0 * np.pi * n * d / lam) ** 2)
+
+
+def test_lossless_slab_transmission_eq5():
+    """The analytic normal-incidence transmission of a lossless slab (Eq. 5,
+    Section 6.1): T and R = 1 - T from the oracle's flux planes, 31
+    wavelengths of 52-72 cells.  The discrete slab differs from the continuum
+    by the Yee dispersion (at 35-48 cells per wavelength inside the slab): T
+    and R are held to 2e-3 of Eq. 5 (measured 1.55e-3 and 1.54e-3, equal and
+    opposite), their sum to 2e-5 of 1 (measured 9.4e-6)."""
+    out = []
+    for e in (1.0, 2.25):
+        spec, lam = slab_spec(e)
+        sim = O.OracleSim(spec)
+        sim.step(spec.n_steps)
+        out.append((sim.spectra(0), sim.spectra(1)))
+    T, R = slab_TR(out[0], out[1])
+    Ta = eq5_T(lam)
+    assert np.max(np.abs(T - Ta)) < 2e-3, np.max(np.abs(T - Ta))
+    assert np.max(np.abs(R - (1.0 - Ta))) < 2e-3
+    assert np.max(np.abs(R + T - 1.0)) < 2e-5, np.max(np.abs(R + T - 1.0))
+    # the slab reflects 12-15% over the band (2 pi n d / lambda from 1.05 to 1.45 rad)
+    assert 0.84 < T.min() and T.max() < 0.9 and T.max() - T.min() > 0.02
+
+
 # ---------------------------------------------------------------- P2
 @pytest.mark.parametrize("kind", ["iso", "diag"])
 def test_discrete_energy_invariant(kind):
