@@ -19,6 +19,9 @@
  *     pole's ODE by central differences at n; the poles' currents add.  A
  *     Drude pole is the Lorentz recursion with omega_0 -> 0 and
  *     delta_eps omega_0^2 -> omega_p^2.
+ *   - Symmetric tensor media (Section 2.3): eps at the grid nodes, inverted
+ *     there, and applied to the curl through the node assembly
+ *     (1/8) sum over the eight octants of R^T eps^-1 R (forward only).
  *   - Discrete adjoint, Eq. (3) of Section 3.1, with the transposes of
  *     Section 3.1 (opposite-direction differences, the absorber transpose,
  *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl).
@@ -51,6 +54,11 @@ typedef struct {
     int per[3];                  /* 1: the axis is periodic (Bloch, Section 2.2): no PEC wall, the
                                     neighbour past the last node is the first one times bsign */
     double bsign[3];             /* real Bloch factor exp(i k L) = +1 or -1 of a periodic axis */
+    /* symmetric tensor media (Section 2.3): eps^-1 at the grid nodes, components
+       xx, yy, zz, xy, xz, yz, one full-grid array each (node (i,j,k) is the corner
+       where the edges Ex, Ey, Ez of index (i,j,k) start); NULL: eps per E node */
+    const double *einvT[6];
+    double einv_bg;              /* eps^-1 of the nodes past the arrays' high end */
 } orc_params;
 
 #define ORC_MAXP 16
@@ -189,10 +197,74 @@ static double e_pre(const orc_params *P, const orc_state *U, int c, size_t p, do
  *   4. H update with its absorber memories.
  * src_*: the increments of this step.  work: three full-grid scratch arrays.
  */
+/* eps^-1 component (a, b) at node v (entries beyond the arrays: the background) */
+static double node_einv(const orc_params *P, const int v[3], int a, int b) {
+    if (v[0] >= P->n[0] || v[1] >= P->n[1] || v[2] >= P->n[2]) return a == b ? P->einv_bg : 0.0;
+    static const int comp[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    return P->einvT[comp[a][b]][IDX(P, v[0], v[1], v[2])];
+}
+
+/* curl value of the E edge of component b starting at node v (zero past the
+   domain; the caller zeroes masked edges) */
+static double edge_curl(const orc_params *P, double *const Cc[3], int b, const int v[3]) {
+    for (int a = 0; a < 3; ++a)
+        if (v[a] < 0 || v[a] >= P->n[a]) return 0.0;
+    return Cc[b][IDX(P, v[0], v[1], v[2])];
+}
+
+/* The node-assembled tensor applied to the curl, at the E edge of component c
+   starting at node x (Section 2.3, S = D^-1/2 (1/8 sum_s R_s^T eps^-1 R_s)
+   D^-1/2 with D the identity on the unit mesh).  The edge belongs to its two end
+   nodes; at each, the eight octants pick one x, one y and one z edge incident
+   to the node, and the four octants holding this edge contribute
+   eps^-1_cc c_c + eps^-1_cb c_b(octant's b edge) for b != c, each times 1/8. */
+static double tensor_apply(const orc_params *P, double *const Cc[3], int c, const int x[3]) {
+    double acc = 0.0;
+    for (int end = 0; end < 2; ++end) {
+        int v[3] = {x[0], x[1], x[2]};
+        v[c] += end;
+        acc += 0.5 * node_einv(P, v, c, c) * Cc[c][IDX(P, x[0], x[1], x[2])];
+        for (int t = 1; t < 3; ++t) {
+            int b = (c + t) % 3;
+            int w[3] = {v[0], v[1], v[2]};
+            double s = edge_curl(P, Cc, b, w);        /* the b edge leaving the node */
+            w[b] -= 1;
+            s += edge_curl(P, Cc, b, w);              /* the b edge arriving at it */
+            acc += 0.25 * node_einv(P, v, c, b) * s;
+        }
+    }
+    return acc;
+}
+
 void orc_step(const orc_params *P, orc_state *U, int nsrc, const int *src_comp, const long long *src_idx,
               const double *src_amp, double *work) {
     const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
     const size_t N = (size_t)nx * ny * nz;
+    if (P->einvT[0]) {
+        /* tensor media: the stretched curl of every E edge first (absorber
+           memories updated, masked edges zero), then E += S (assembled eps^-1) curl */
+        double *Cc[3] = {work, work + N, work + 2 * N};
+        for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        Cc[c][p] = e_masked(P, c, x) ? 0.0 : curl_minus(P, U, c, x, p, 1);
+                    }
+        }
+        for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        if (e_masked(P, c, x)) continue;
+                        U->F[c][IDX(P, i, j, k)] += P->S * tensor_apply(P, Cc, c, x);
+                    }
+        }
+    } else
     for (int c = 0; c < 3; ++c) {
         double *En = work + (size_t)c * N;      /* E^n of Lorentz nodes, for the roll */
 #pragma omp parallel for schedule(static)

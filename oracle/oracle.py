@@ -65,7 +65,8 @@ class _Params(C.Structure):
                 ("slab", C.c_void_p * 3), ("eps", C.c_void_p * 3), ("lor", C.c_void_p),
                 ("npole", C.c_int), ("pkind", C.c_int * MAXP), ("pdeps", C.c_double * MAXP),
                 ("pwdt", C.c_double * MAXP), ("pgdt", C.c_double * MAXP),
-                ("per", C.c_int * 3), ("bsign", C.c_double * 3)]
+                ("per", C.c_int * 3), ("bsign", C.c_double * 3),
+                ("einvT", C.c_void_p * 6), ("einv_bg", C.c_double)]
 
 
 class _State(C.Structure):
@@ -163,6 +164,20 @@ class OracleSim:
         self.eps = np.ascontiguousarray(spec.eps_full())
         for c in range(3):
             P.eps[c] = _ptr(self.eps[c])
+        self.tensor = spec.eps_kind == "tensor"
+        if self.tensor:
+            # Section 2.3: the symmetric tensor at each node, inverted there
+            assert not spec.lorentz and not any(spec.periodic), "tensor media: no dispersion, no Bloch axes"
+            en = spec.eps_nodes()
+            m = np.empty(en.shape[1:] + (3, 3))
+            for q, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+                m[..., a, b] = m[..., b, a] = en[q]
+            inv = np.linalg.inv(m)
+            self.einvT = np.ascontiguousarray(
+                np.stack([inv[..., a, b] for (a, b) in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))]))
+            for q in range(6):
+                P.einvT[q] = _ptr(self.einvT[q])
+            P.einv_bg = 1.0 / float(spec.eps_bg)
         self.lor = None
         self.npole = 1
         if spec.lorentz:
@@ -382,6 +397,9 @@ class OracleSim:
         upper half, then the lower half from u^lo."""
         if any(self.per):
             raise ValueError("periodic domains: this oracle has no adjoint across periodic seams (the library "
+                             "refuses gradients there too)")
+        if self.tensor:
+            raise ValueError("tensor media: this oracle has no adjoint for node-assembled tensors (the library "
                              "refuses gradients there too)")
         u_start = np.zeros_like(self.u) if u0 is None else u0.copy()
         a = np.zeros_like(self.u)

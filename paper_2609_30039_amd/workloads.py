@@ -97,9 +97,10 @@ class DomainSpec:
     pml_kappa_max: float = 5.0
     pml_sigma_max: float = 3.2
     pml_alpha_max: float = 0.05
-    eps_kind: str = "iso"                       # 'iso' or 'diag'
+    eps_kind: str = "iso"                       # 'iso', 'diag' or 'tensor'
     eps_box: Optional[Box] = None               # where ``eps`` is given; eps_bg outside
-    eps: Optional[np.ndarray] = None            # [ncomp][bz][by][bx]
+    eps: Optional[np.ndarray] = None            # [ncomp][bz][by][bx]; tensor: 6 components
+    #                                             xx, yy, zz, xy, xz, yz at the grid nodes
     eps_bg: float = 1.0
     lorentz: List[LorentzSpec] = field(default_factory=list)
     sources: List[SourceSpec] = field(default_factory=list)
@@ -114,9 +115,24 @@ class DomainSpec:
         nx, ny, nz = self.shape
         return nx * ny * nz
 
-    def eps_full(self) -> np.ndarray:
-        """Dense per-component permittivity [3][nz][ny][nx] (float64)."""
+    def eps_nodes(self) -> np.ndarray:
+        """Tensor media: the dense node tensor [6][nz][ny][nx] (xx, yy, zz, xy,
+        xz, yz), eps_bg times the identity outside the box."""
+        assert self.eps_kind == "tensor"
         nx, ny, nz = self.shape
+        out = np.zeros((6, nz, ny, nx))
+        out[:3] = float(self.eps_bg)
+        if self.eps is not None:
+            (i0, j0, k0), (i1, j1, k1) = self.eps_box
+            out[:, k0:k1, j0:j1, i0:i1] = self.eps
+        return out
+
+    def eps_full(self) -> np.ndarray:
+        """Dense per-component permittivity [3][nz][ny][nx] (float64); tensor
+        media have none per E node (eps_bg throughout)."""
+        nx, ny, nz = self.shape
+        if self.eps_kind == "tensor":
+            return np.full((3, nz, ny, nx), float(self.eps_bg))
         out = np.full((3, nz, ny, nx), float(self.eps_bg))
         if self.eps is not None:
             (i0, j0, k0), (i1, j1, k1) = self.eps_box
