@@ -63,7 +63,21 @@ enum {
 };
 
 enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_BF16 = 2 };
-enum { FDTD_EPS_ISO = 0, FDTD_EPS_DIAG = 1 };
+/* permittivity kinds.  ISO: one value per cell (each E edge takes its
+   cell's value); DIAG: three values per cell, one per E component; TENSOR
+   (Section 2.3): a symmetric tensor at each grid node (the corner where the
+   edges Ex, Ey, Ez of index (i,j,k) start), six values xx, yy, zz, xy, xz, yz,
+   applied to the curl through the node assembly S = (1/8) sum over the eight
+   octants of R^T eps^-1 R (an edge takes half of each end node's diagonal
+   entry and a quarter of each off-diagonal entry times the sum of the two
+   edges of that axis meeting it there).  Every node's tensor must have all
+   eigenvalues >= 1; inside an absorbing face (node index along the normal in
+   the slab) the normal must be a principal axis (zero off-diagonal entries
+   with it) whose eigenvalue is the largest or the smallest: else
+   FDTD_E_UNSTABLE, checked node by node.  TENSOR domains take no dispersive
+   box, no periodic axis, no gradient, no reversible mode and no fused
+   kernels (FDTD_E_INVALID), and one scratch curl of 3 field arrays each. */
+enum { FDTD_EPS_ISO = 0, FDTD_EPS_DIAG = 1, FDTD_EPS_TENSOR = 2 };
 enum { FDTD_SRC_POINT = 0, FDTD_SRC_PLANE_Z = 1 };
 enum { FDTD_MON_PROBE = 0, FDTD_MON_FLUX_Z = 1, FDTD_MON_PATCH_Z = 2 };
 /* field components for get/set: 0..5 = Ex..Hz of the forward state,
@@ -130,9 +144,10 @@ typedef struct {
     double courant;                /* S = c dt / h; S*sqrt(3) must be <= 0.99 */
     int32_t pml[6];                /* absorbing cells at xlo, xhi, ylo, yhi, zlo, zhi */
     double pml_m, pml_kappa_max, pml_sigma_max, pml_alpha_max;   /* grading */
-    int32_t eps_kind;              /* FDTD_EPS_ISO | FDTD_EPS_DIAG */
-    int32_t eps_lo[3], eps_hi[3];  /* box where eps is given */
-    const double *eps;             /* host [ncomp][bz][by][bx], ncomp 1 (ISO) or 3 (DIAG), >= 1 */
+    int32_t eps_kind;              /* FDTD_EPS_ISO | FDTD_EPS_DIAG | FDTD_EPS_TENSOR */
+    int32_t eps_lo[3], eps_hi[3];  /* box where eps is given (TENSOR: a box of nodes) */
+    const double *eps;             /* host [ncomp][bz][by][bx], ncomp 1 (ISO), 3 (DIAG) or 6 (TENSOR:
+                                      xx, yy, zz, xy, xz, yz); values (eigenvalues) >= 1 */
     double eps_bg;                 /* permittivity outside the box, >= 1 */
     int32_t n_lorentz;             /* 0 or 1 */
     fdtd_lorentz_desc lorentz;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfdtd.so")
 FDTD_OK, FDTD_E_INVALID, FDTD_E_UNSTABLE, FDTD_E_NOMEM, FDTD_E_DEVICE, FDTD_E_STATE, FDTD_E_RANGE = \
     0, -1, -2, -3, -4, -5, -6
 FDTD_F32, FDTD_F64, FDTD_BF16 = 0, 1, 2
-FDTD_EPS_ISO, FDTD_EPS_DIAG = 0, 1
+FDTD_EPS_ISO, FDTD_EPS_DIAG, FDTD_EPS_TENSOR = 0, 1, 2
 FDTD_SRC_POINT, FDTD_SRC_PLANE_Z = 0, 1
 FDTD_MON_PROBE, FDTD_MON_FLUX_Z, FDTD_MON_PATCH_Z = 0, 1, 2
 FDTD_ADJ = 6
@@ -166,7 +166,7 @@ def domain_desc(spec, keep: list) -> DomainDesc:
         d.pml[q] = spec.pml[q]
     d.pml_m, d.pml_kappa_max = spec.pml_m, spec.pml_kappa_max
     d.pml_sigma_max, d.pml_alpha_max = spec.pml_sigma_max, spec.pml_alpha_max
-    d.eps_kind = FDTD_EPS_DIAG if spec.eps_kind == "diag" else FDTD_EPS_ISO
+    d.eps_kind = {"iso": FDTD_EPS_ISO, "diag": FDTD_EPS_DIAG, "tensor": FDTD_EPS_TENSOR}[spec.eps_kind]
     d.eps_bg = spec.eps_bg
     if spec.eps is not None:
         (lo, hi) = spec.eps_box

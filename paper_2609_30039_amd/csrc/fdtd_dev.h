@@ -81,6 +81,13 @@ struct DomDev {
     int elo[3], ehi[3];
     T epsinv_bg;
     const T* epsinv[3];        // over the eps box; isotropic: the same array thrice
+    // symmetric tensor media (Section 2.3): eps^-1 at the grid nodes of the
+    // eps box, six arrays xx yy zz xy xz yz over [elo, ehi) (the background
+    // times the identity elsewhere); curl: the stretched curl of every E edge
+    // of the current step, written by the first E pass, read by the assembly
+    int tens;
+    const T* tinv[6];
+    T* curl[3];
     int has_lor;
     int llo[3], lhi[3];
     int npole;                 // poles of the dispersive box (1..kMaxPole)

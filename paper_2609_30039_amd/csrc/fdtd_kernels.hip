@@ -337,8 +337,11 @@ __device__ __forceinline__ void e_lor_block(const DomDev<T>* __restrict__ doms, 
 
 // Blocks [0, nlb) update the Lorentz boxes (e_lor_block; nlb is a multiple
 // of 8 so that the column blocks keep their XCD placement), the rest the
-// columns.
-template <typename T, int W>
+// columns.  TENS = false serves the domains with a scalar or diagonal
+// permittivity; TENS = true the tensor domains, whose E update takes two
+// passes: this one writes the stretched curl of every edge (absorber memories
+// updated, zero on walls) into d.curl, k_tens_e applies the node assembly.
+template <typename T, int W, bool TENS>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                const int* __restrict__ xr, const int* __restrict__ lbs, int nlb,
                                                int ndom, int kz, int rs, int ws, int t, const int* __restrict__ tdev) {
@@ -348,7 +351,7 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     }
     const DomDev<T>* dp;
     Col c = column<T, W>(doms, bs, ndom, kz, dp, xr, (int)blockIdx.x - nlb);
-    if (!c.ok) return;
+    if (!c.ok || dp->tens != (int)TENS) return;
     if (tdev) t += *tdev;   // graph replays: step index held on the device
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
@@ -357,7 +360,8 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + so), gp(d.E[1] + so), gp(d.E[2] + so)};
     FDTD_GLOBAL T* ew[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
     const BlkFlags bf = blk_flags(d, c.x0, c.y0, c.k0, c.k1, W, 256 / W);
-    const EpsView<T> ev = eps_view(d, c.x0, c.y0, 256 / W, c.k0, c.k1 - 1);
+    EpsView<T> ev = eps_view(d, c.x0, c.y0, 256 / W, c.k0, c.k1 - 1);
+    if (TENS) ev.mode = 0;   // eps^-1 is applied by the assembly pass
     const Cpml1<T> cx = cpml_at(d, 0, i), cy = cpml_at(d, 1, j);
     const T S = d.S;
     long long f = (long long)c.k0 * pl + (long long)j * d.pitch + i;
@@ -397,6 +401,15 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
                     Dy1 = st_pref(d.psiE[0][cx.side][1], wo, q, fy, cx.bE, cx.cE, cx.kE, pe[5], Dy1);
                 }
             }
+            if constexpr (TENS) {
+                gp(d.curl[0])[f] = fx ? Dx0 - Dx1 : T(0);
+                gp(d.curl[1])[f] = fy ? Dy0 - Dy1 : T(0);
+                gp(d.curl[2])[f] = fz ? Dz0 - Dz1 : T(0);
+                hxm = cu.hx;
+                hym = cu.hy;
+                cu = nx;
+                continue;
+            }
             ex = fma(S * cu.ei[0], Dx0 - Dx1, cu.e[0]);
             ey = fma(S * cu.ei[1], Dy0 - Dy1, cu.e[1]);
             ez = fma(S * cu.ei[2], Dz0 - Dz1, cu.e[2]);
@@ -423,6 +436,87 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     }
 }
 
+
+// ------------------------------------------------ tensor media, assembly pass
+// eps^-1 component q (xx yy zz xy xz yz) at node (i,j,k): the node arrays
+// over the eps box, the background times the identity elsewhere (nodes on
+// the high walls included)
+template <typename T>
+__device__ __forceinline__ T tnode(const DomDev<T>& d, int q, int i, int j, int k) {
+    if (i >= d.elo[0] && i < d.ehi[0] && j >= d.elo[1] && j < d.ehi[1] && k >= d.elo[2] && k < d.ehi[2]) {
+        const long long e = ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) *
+                                (d.ehi[0] - d.elo[0]) + (i - d.elo[0]);
+        return gp(d.tinv[q])[e];
+    }
+    return q < 3 ? d.epsinv_bg : T(0);
+}
+
+// stretched curl of the b edge starting at node (i,j,k); zero off the grid
+template <typename T>
+__device__ __forceinline__ T tcurl(const DomDev<T>& d, int b, int i, int j, int k) {
+    if (i < 0 || j < 0 || k < 0 || i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) return T(0);
+    return gp(d.curl[b])[fidx(d, i, j, k)];
+}
+
+// E^{n+1} = E^n + S (node assembly of eps^-1) curl, plus the sources, for the
+// tensor domains, one thread per (i, j) column of a z chunk.  The edge of
+// component c from node v0 to v1 = v0 + e_c takes, at each end v,
+// eps^-1_cc(v)/2 times its own curl and eps^-1_cb(v)/4 times the sum of the
+// curls of the two b edges meeting at v (leaving and arriving), b != c.
+// Edges tangential to a wall keep E = 0.  Reads and writes only its own E
+// nodes, so it runs in place like the other split kernels.
+template <typename T, int W>
+__global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
+                                                const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int t,
+                                                const int* __restrict__ tdev) {
+    const DomDev<T>* dp;
+    Col c = column<T, W>(doms, bs, ndom, kz, dp, xr);
+    if (!c.ok || !dp->tens) return;
+    if (tdev) t += *tdev;
+    const DomDev<T>& d = *dp;
+    const int i = c.i, j = c.j;
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs;
+    const T S = d.S, h = T(0.5), q4 = T(0.25);
+    for (int k = c.k0; k < c.k1; ++k) {
+        const long long f = fidx(d, i, j, k);
+        T a0[6];
+        for (int q = 0; q < 6; ++q) a0[q] = tnode(d, q, i, j, k);
+        const T cx = tcurl(d, 0, i, j, k), cy = tcurl(d, 1, i, j, k), cz = tcurl(d, 2, i, j, k);
+        const T sxm = cx + tcurl(d, 0, i - 1, j, k);    // the two x edges at v0
+        const T sym = cy + tcurl(d, 1, i, j - 1, k);    // the two y edges at v0
+        const T szm = cz + tcurl(d, 2, i, j, k - 1);    // the two z edges at v0
+        // Ex: far node (i+1, j, k)
+        T mx = h * (a0[0] + tnode(d, 0, i + 1, j, k)) * cx;
+        mx += q4 * (a0[3] * sym + tnode(d, 3, i + 1, j, k) * (tcurl(d, 1, i + 1, j, k) + tcurl(d, 1, i + 1, j - 1, k)));
+        mx += q4 * (a0[4] * szm + tnode(d, 4, i + 1, j, k) * (tcurl(d, 2, i + 1, j, k) + tcurl(d, 2, i + 1, j, k - 1)));
+        // Ey: far node (i, j+1, k)
+        T my = h * (a0[1] + tnode(d, 1, i, j + 1, k)) * cy;
+        my += q4 * (a0[3] * sxm + tnode(d, 3, i, j + 1, k) * (tcurl(d, 0, i, j + 1, k) + tcurl(d, 0, i - 1, j + 1, k)));
+        my += q4 * (a0[5] * szm + tnode(d, 5, i, j + 1, k) * (tcurl(d, 2, i, j + 1, k) + tcurl(d, 2, i, j + 1, k - 1)));
+        // Ez: far node (i, j, k+1)
+        T mz = h * (a0[2] + tnode(d, 2, i, j, k + 1)) * cz;
+        mz += q4 * (a0[4] * sxm + tnode(d, 4, i, j, k + 1) * (tcurl(d, 0, i, j, k + 1) + tcurl(d, 0, i - 1, j, k + 1)));
+        mz += q4 * (a0[5] * sym + tnode(d, 5, i, j, k + 1) * (tcurl(d, 1, i, j, k + 1) + tcurl(d, 1, i, j - 1, k + 1)));
+        T ex = fma(S, mx, gp(d.E[0] + so)[f]);
+        T ey = fma(S, my, gp(d.E[1] + so)[f]);
+        T ez = fma(S, mz, gp(d.E[2] + so)[f]);
+        for (int q = 0; q < d.nsrc; ++q) {
+            const SrcDev<T>& sr = d.src[q];
+            if (t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) {
+                T v = gp(sr.wave)[t];
+                if (sr.comp == 0) ex += v;
+                else if (sr.comp == 1) ey += v;
+                else ez += v;
+            }
+        }
+        if (e_masked_d(d, 0, i, j, k)) ex = T(0);
+        if (e_masked_d(d, 1, i, j, k)) ey = T(0);
+        if (e_masked_d(d, 2, i, j, k)) ez = T(0);
+        gp(d.E[0] + wo)[f] = ex;
+        gp(d.E[1] + wo)[f] = ey;
+        gp(d.E[2] + wo)[f] = ez;
+    }
+}
 
 // reads E^{n+1} from set ws (written by k_fwd_e), H^{n+1/2} from set rs
 template <typename T>
@@ -2301,12 +2395,27 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
         // one launch per pass over all blocks: a second launch for the
         // interior blocks costs more in its drain than its leaner registers win
         const int nlb = (c.nlor + 7) / 8 * 8;
-        if (c.sw == 32)
-            hipLaunchKernelGGL((k_fwd_e<T, 32>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, nlb,
-                               c.ndom, c.kz, rs, ws, t, tdev);
-        else
-            hipLaunchKernelGGL((k_fwd_e<T, 64>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, nlb,
-                               c.ndom, c.kz, rs, ws, t, tdev);
+        if (c.ntens < c.ndom) {
+            if (c.sw == 32)
+                hipLaunchKernelGGL((k_fwd_e<T, 32, false>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
+                                   c.lbs, nlb, c.ndom, c.kz, rs, ws, t, tdev);
+            else
+                hipLaunchKernelGGL((k_fwd_e<T, 64, false>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
+                                   c.lbs, nlb, c.ndom, c.kz, rs, ws, t, tdev);
+        }
+        if (c.ntens) {   // tensor domains: curl pass, then the assembly pass
+            if (c.sw == 32) {
+                hipLaunchKernelGGL((k_fwd_e<T, 32, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, 0,
+                                   c.ndom, c.kz, rs, ws, t, tdev);
+                hipLaunchKernelGGL((k_tens_e<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
+                                   rs, ws, t, tdev);
+            } else {
+                hipLaunchKernelGGL((k_fwd_e<T, 64, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, 0,
+                                   c.ndom, c.kz, rs, ws, t, tdev);
+                hipLaunchKernelGGL((k_tens_e<T, 64>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
+                                   rs, ws, t, tdev);
+            }
+        }
         if (c.sw == 32)
             hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz, rs, ws,
                                slot);

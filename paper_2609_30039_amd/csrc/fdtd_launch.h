@@ -39,6 +39,7 @@ struct LaunchCfg {
     int ngrid;                 // split: column workgroups per launch (8 x the longest run)
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
+    int ntens;                 // split: domains with tensor media (two E passes)
     // split adjoint: one tile table per pass, (domain | class << 24,
     // x0 | xlen << 24, y0, k0), domains with a gradient only.  x is cut into
     // the slab zones (narrow tiles, W = 16) and the interior zone (W = 32); a

@@ -128,6 +128,83 @@ struct Arena {
     }
 };
 
+// ------------------------------------------------------------ tensor media
+// Entries of a symmetric 3x3 tensor in the descriptor's order: xx yy zz xy xz yz.
+static inline int sym_idx(int a, int b) {
+    if (a == b) return a;
+    const int lo = std::min(a, b), hi = std::max(a, b);
+    return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
+}
+
+// Eigenvalues (ascending) of a symmetric 3x3 tensor by the trigonometric
+// solution of its characteristic cubic (O. K. Smith, Commun. ACM 4(4), 1961).
+static void sym3_eigenvalues(const double m[6], double w[3]) {
+    const double off = m[3] * m[3] + m[4] * m[4] + m[5] * m[5];
+    const double q = (m[0] + m[1] + m[2]) / 3.0;
+    if (off == 0.0) {
+        w[0] = m[0];
+        w[1] = m[1];
+        w[2] = m[2];
+        std::sort(w, w + 3);
+        return;
+    }
+    const double p2 = (m[0] - q) * (m[0] - q) + (m[1] - q) * (m[1] - q) + (m[2] - q) * (m[2] - q) + 2.0 * off;
+    const double p = std::sqrt(p2 / 6.0);
+    // B = (A - q I) / p; r = det(B) / 2 in [-1, 1]
+    const double b0 = (m[0] - q) / p, b1 = (m[1] - q) / p, b2 = (m[2] - q) / p;
+    const double b3 = m[3] / p, b4 = m[4] / p, b5 = m[5] / p;
+    double r = 0.5 * (b0 * (b1 * b2 - b5 * b5) - b3 * (b3 * b2 - b5 * b4) + b4 * (b3 * b5 - b1 * b4));
+    r = std::min(1.0, std::max(-1.0, r));
+    const double phi = std::acos(r) / 3.0;
+    const double hi = q + 2.0 * p * std::cos(phi);
+    const double lo = q + 2.0 * p * std::cos(phi + 2.0 * std::acos(-1.0) / 3.0);
+    w[0] = lo;
+    w[2] = hi;
+    w[1] = 3.0 * q - lo - hi;
+}
+
+// Section 2.3 admission of one node's tensor: finite, every eigenvalue >= 1
+// (the vacuum step bound of Eq. 2 holds), and inside the absorbing face of
+// normal a the normal is a principal axis whose eigenvalue is the largest or
+// the smallest.  Returns nullptr when admitted.
+static const char* tensor_node_check(const double m[6], const bool inface[3]) {
+    double scale = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        if (!std::isfinite(m[q])) return "tensor permittivity must be finite";
+        scale = std::max(scale, std::fabs(m[q]));
+    }
+    const double tol = 1e-12 * std::max(1.0, scale);
+    double w[3];
+    sym3_eigenvalues(m, w);
+    if (!(w[0] >= 1.0 - tol)) return "tensor permittivity needs every eigenvalue at least 1";
+    for (int a = 0; a < 3; ++a) {
+        if (!inface[a]) continue;
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        if (std::fabs(m[sym_idx(a, b)]) > tol || std::fabs(m[sym_idx(a, c)]) > tol)
+            return "tensor in an absorbing face with principal axes rotated against the face normal";
+        // eigenvalues of the transverse block
+        const double p = m[b], r = m[c], o = m[sym_idx(b, c)];
+        const double mid = 0.5 * (p + r), rad = std::sqrt(0.25 * (p - r) * (p - r) + o * o);
+        if (m[a] > mid - rad + tol && m[a] < mid + rad - tol)
+            return "tensor in an absorbing face with intermediate normal eigenvalue";
+    }
+    return nullptr;
+}
+
+// inverse of a symmetric positive-definite 3x3 tensor (cofactors over the determinant)
+static void sym3_inverse(const double m[6], double out[6]) {
+    const double xx = m[0], yy = m[1], zz = m[2], xy = m[3], xz = m[4], yz = m[5];
+    const double cxx = yy * zz - yz * yz, cyy = xx * zz - xz * xz, czz = xx * yy - xy * xy;
+    const double cxy = xz * yz - xy * zz, cxz = xy * yz - xz * yy, cyz = xy * xz - xx * yz;
+    const double det = xx * cxx + xy * cxy + xz * cxz;
+    out[0] = cxx / det;
+    out[1] = cyy / det;
+    out[2] = czz / det;
+    out[3] = cxy / det;
+    out[4] = cxz / det;
+    out[5] = cyz / det;
+}
+
 template <typename T>
 struct Handle : Base {
     hipStream_t st = nullptr;
@@ -288,6 +365,8 @@ struct Handle : Base {
         }
         cfg.nblk = bs_host[ndom];
         cfg.nlor = lbs[ndom];
+        cfg.ntens = 0;
+        for (int q = 0; q < ndom; ++q) cfg.ntens += dd[q].tens;
         if (cfg.kernel == 1) split_runs();
         build_adjoint_tiles();
         cfg.ngen = (int)tiles_gen.size();
@@ -538,7 +617,11 @@ struct Handle : Base {
                 }
             size_t ebox = 1;
             for (int a = 0; a < 3; ++a) ebox *= (size_t)(d.ehi[a] - d.elo[a]);
-            if (ebox && s.eps) {
+            if (d.tens) {
+                if (ebox && s.eps)
+                    for (int q6 = 0; q6 < 6; ++q6) M.take(d.tinv[q6], ebox * ts);
+                for (int c = 0; c < 3; ++c) X.take(d.curl[c], h.nfield * ts);
+            } else if (ebox && s.eps) {
                 for (int c = 0; c < h.ncomp_eps; ++c) M.take(d.epsinv[c], ebox * ts);
                 if (asg)
                     for (int c = h.ncomp_eps; c < 3; ++c) d.epsinv[c] = d.epsinv[0];
@@ -805,6 +888,7 @@ struct Handle : Base {
             d.L[a][1] = s.pml[2 * a + 1];
         }
         d.eps_diag = s.eps_kind == FDTD_EPS_DIAG;
+        d.tens = s.eps_kind == FDTD_EPS_TENSOR;
         size_t ebox = 1;
         for (int a = 0; a < 3; ++a) {
             d.elo[a] = s.eps_lo[a];
@@ -895,9 +979,25 @@ struct Handle : Base {
     int upload_eps(int q) {
         DomHost& h = dh[q];
         DomDev<T>& d = dd[q];
-        if (!d.epsinv[0]) return FDTD_OK;
         size_t ebox = 1;
         for (int a = 0; a < 3; ++a) ebox *= (size_t)(d.ehi[a] - d.elo[a]);
+        if (d.tens) {   // eps^-1 of each node's tensor, six arrays
+            if (!d.tinv[0]) return FDTD_OK;
+            std::vector<T> v(6 * ebox);
+            for (size_t e = 0; e < ebox; ++e) {
+                double m[6], r[6];
+                for (int c = 0; c < 6; ++c) m[c] = h.eps[c * ebox + e];
+                sym3_inverse(m, r);
+                for (int c = 0; c < 6; ++c) v[c * ebox + e] = (T)r[c];
+            }
+            for (int c = 0; c < 6; ++c)
+                if (hipMemcpyAsync((void*)d.tinv[c], v.data() + c * ebox, ebox * sizeof(T), hipMemcpyHostToDevice,
+                                   st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "upload eps failed");
+            if (hipStreamSynchronize(st) != hipSuccess) return fail(FDTD_E_DEVICE, "upload eps sync failed");
+            return FDTD_OK;
+        }
+        if (!d.epsinv[0]) return FDTD_OK;
         std::vector<T> v(ebox);
         for (int c = 0; c < h.ncomp_eps; ++c) {
             for (size_t e = 0; e < ebox; ++e) v[e] = (T)(1.0 / h.eps[c * ebox + e]);
@@ -926,8 +1026,9 @@ struct Handle : Base {
         // (a faster medium) breaks it; Section 2.3 admits eigenvalues >= 1 only
         if (!(s.eps_bg >= 1.0) || !std::isfinite(s.eps_bg))
             return fail(FDTD_E_UNSTABLE, "background permittivity must be finite and at least 1");
-        if (s.eps_kind != FDTD_EPS_ISO && s.eps_kind != FDTD_EPS_DIAG) return fail(FDTD_E_INVALID, "eps_kind");
-        h.ncomp_eps = s.eps_kind == FDTD_EPS_DIAG ? 3 : 1;
+        if (s.eps_kind != FDTD_EPS_ISO && s.eps_kind != FDTD_EPS_DIAG && s.eps_kind != FDTD_EPS_TENSOR)
+            return fail(FDTD_E_INVALID, "eps_kind");
+        h.ncomp_eps = s.eps_kind == FDTD_EPS_DIAG ? 3 : (s.eps_kind == FDTD_EPS_TENSOR ? 6 : 1);
         size_t ebox = 1;
         for (int a = 0; a < 3; ++a) {
             if (s.eps_lo[a] < 0 || s.eps_hi[a] > s.n[a] || s.eps_lo[a] > s.eps_hi[a])
@@ -935,28 +1036,19 @@ struct Handle : Base {
             ebox *= (size_t)(s.eps_hi[a] - s.eps_lo[a]);
         }
         if (ebox && !s.eps) return fail(FDTD_E_INVALID, "eps array missing");
+        h.eps.assign(ebox * h.ncomp_eps, 1.0);
         if (ebox) {
-            h.eps.assign(s.eps, s.eps + ebox * h.ncomp_eps);
-            for (double e : h.eps)
-                if (!(e >= 1.0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be finite and at least 1");
-            if (h.ncomp_eps == 3) {
-                // Section 2.3: a tensor inside an absorbing face needs the face normal to be a
-                // principal axis whose eigenvalue is not the intermediate one.
-                int bx = s.eps_hi[0] - s.eps_lo[0], by = s.eps_hi[1] - s.eps_lo[1];
-                for (size_t e = 0; e < ebox; ++e) {
-                    int i = s.eps_lo[0] + (int)(e % bx), j = s.eps_lo[1] + (int)((e / bx) % by),
-                        k = s.eps_lo[2] + (int)(e / ((size_t)bx * by));
-                    int x[3] = {i, j, k};
-                    double v[3] = {h.eps[e], h.eps[ebox + e], h.eps[2 * ebox + e]};
-                    for (int a = 0; a < 3; ++a) {
-                        bool inface = x[a] < s.pml[2 * a] || x[a] >= s.n[a] - s.pml[2 * a + 1];
-                        if (!inface) continue;
-                        double o1 = v[(a + 1) % 3], o2 = v[(a + 2) % 3];
-                        bool mid = (v[a] > std::min(o1, o2) && v[a] < std::max(o1, o2));
-                        if (mid) return fail(FDTD_E_UNSTABLE, "anisotropic eps with intermediate normal eigenvalue in an absorbing face");
-                    }
-                }
-            }
+            int rc = validate_eps_only(s, h, s.eps);
+            if (rc) return rc;
+        }
+        if (s.eps_kind == FDTD_EPS_TENSOR) {
+            // the tensor path is forward-only, nondispersive and walled
+            if (s.n_lorentz) return fail(FDTD_E_INVALID, "tensor media take no dispersive box");
+            if (s.grad) return fail(FDTD_E_INVALID, "tensor media take no gradient");
+            if (s.periodic[0] || s.periodic[1] || s.periodic[2])
+                return fail(FDTD_E_INVALID, "tensor media take no periodic axis");
+            if (opt.kernel == FDTD_KERNEL_FUSED) return fail(FDTD_E_INVALID, "tensor media need the split kernels");
+            if (opt.reversible) return fail(FDTD_E_INVALID, "tensor media take no reversible mode");
         }
         for (int a = 0; a < 3; ++a) {
             if (s.periodic[a] != 0 && s.periodic[a] != 1) return fail(FDTD_E_INVALID, "periodic flag must be 0 or 1");
@@ -1480,27 +1572,44 @@ struct Handle : Base {
         return upload_eps(dom);
     }
 
+    // Checks a permittivity array of the domain's layout (h.eps.size()
+    // values) and keeps it as the host copy.  Every value (every eigenvalue of
+    // a tensor) must be finite and at least 1: Eq. 2 bounds the step by the
+    // vacuum speed.  Section 2.3: inside an absorbing face (index along the
+    // normal in the slab: the E position of a diagonal entry, the node of a
+    // tensor) the normal must be a principal axis whose eigenvalue is not the
+    // intermediate one.
     int validate_eps_only(const fdtd_domain_desc& s, DomHost& h, const double* eps) {
         std::vector<double> v(eps, eps + h.eps.size());
-        for (double e : v)
-            if (!(e >= 1.0) || !std::isfinite(e)) return fail(FDTD_E_UNSTABLE, "permittivity must be finite and at least 1");
-        if (h.ncomp_eps == 3) {
-            size_t ebox = h.eps.size() / 3;
-            int bx = s.eps_hi[0] - s.eps_lo[0], by = s.eps_hi[1] - s.eps_lo[1];
-            for (size_t e = 0; e < ebox; ++e) {
-                int x[3] = {s.eps_lo[0] + (int)(e % bx), s.eps_lo[1] + (int)((e / bx) % by),
-                            s.eps_lo[2] + (int)(e / ((size_t)bx * by))};
-                double w[3] = {v[e], v[ebox + e], v[2 * ebox + e]};
+        const int nc = h.ncomp_eps;
+        const size_t ebox = h.eps.size() / nc;
+        const int bx = s.eps_hi[0] - s.eps_lo[0], by = s.eps_hi[1] - s.eps_lo[1];
+        for (size_t e = 0; e < ebox; ++e) {
+            const int x[3] = {s.eps_lo[0] + (int)(e % bx), s.eps_lo[1] + (int)((e / bx) % by),
+                              s.eps_lo[2] + (int)(e / ((size_t)bx * by))};
+            bool inface[3];
+            for (int a = 0; a < 3; ++a) inface[a] = x[a] < s.pml[2 * a] || x[a] >= s.n[a] - s.pml[2 * a + 1];
+            if (nc == 6) {
+                double m[6];
+                for (int q = 0; q < 6; ++q) m[q] = v[q * ebox + e];
+                const char* why = tensor_node_check(m, inface);
+                if (why) return fail(FDTD_E_UNSTABLE, why);
+                continue;
+            }
+            for (int c = 0; c < nc; ++c)
+                if (!(v[c * ebox + e] >= 1.0) || !std::isfinite(v[c * ebox + e]))
+                    return fail(FDTD_E_UNSTABLE, "permittivity must be finite and at least 1");
+            if (nc == 3) {
+                const double w[3] = {v[e], v[ebox + e], v[2 * ebox + e]};
                 for (int a = 0; a < 3; ++a) {
-                    bool inface = x[a] < s.pml[2 * a] || x[a] >= s.n[a] - s.pml[2 * a + 1];
-                    if (!inface) continue;
-                    double o1 = w[(a + 1) % 3], o2 = w[(a + 2) % 3];
+                    if (!inface[a]) continue;
+                    const double o1 = w[(a + 1) % 3], o2 = w[(a + 2) % 3];
                     if (w[a] > std::min(o1, o2) && w[a] < std::max(o1, o2))
                         return fail(FDTD_E_UNSTABLE, "anisotropic eps with intermediate normal eigenvalue in an absorbing face");
                 }
             }
         }
-        h.eps = v;
+        h.eps = std::move(v);
         return FDTD_OK;
     }
 

@@ -310,6 +310,63 @@ def anisotropic_lorentz(interior: int = 512, pml: int = 12, lorentz: int = 128, 
     )
 
 
+def random_spd_tensors(rng: np.random.Generator, n: int, lo: float = 1.0, hi: float = 5.0,
+                       chunk: int = 1 << 22) -> np.ndarray:
+    """[6][n] symmetric tensors R diag(l) R^T (xx, yy, zz, xy, xz, yz) with
+    eigenvalues l uniform in [lo, hi] and R a uniformly random rotation (a
+    normalised Gaussian quaternion), drawn chunk by chunk."""
+    out = np.empty((6, n))
+    pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    for s0 in range(0, n, chunk):
+        m = min(chunk, n - s0)
+        w, x, y, z = rng.standard_normal((4, m))
+        r = np.sqrt(w * w + x * x + y * y + z * z)
+        w, x, y, z = w / r, x / r, y / r, z / r
+        R = ((1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)),
+             (2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)),
+             (2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)))
+        lam = lo + (hi - lo) * rng.random((3, m))
+        for q, (a, b) in enumerate(pairs):
+            out[q, s0:s0 + m] = R[a][0] * R[b][0] * lam[0] + R[a][1] * R[b][1] * lam[1] + R[a][2] * R[b][2] * lam[2]
+    return out
+
+
+def anisotropic_tensor(interior: int = 512, pml: int = 12, patch: int = 64, n_steps: int = 4000, n_f: int = 8,
+                       seed: int = 1006, shape: Optional[Tuple[int, int, int]] = None,
+                       block: int = 64) -> DomainSpec:
+    """Full symmetric tensor media (Section 2.3): a randomly rotated tensor
+    with eigenvalues in [1, 5] at every node between the absorbing slabs,
+    vacuum in the slabs; the x-polarised plane source and Ex patch monitor of
+    the diagonal anisotropic workload; forward only.  A block of block^3
+    independent node tensors repeats across the interior (drawing 1.3e8
+    rotations one by one would dominate the set-up)."""
+    if shape is None:
+        shape = (interior + 2 * pml,) * 3
+    nx, ny, nz = shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = (pml, pml, pml)
+    hi = (nx - pml, ny - pml, nz - pml)
+    bx, by, bz = hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]
+    cb = (min(block, bz), min(block, by), min(block, bx))
+    cell = random_spd_tensors(rng, cb[0] * cb[1] * cb[2]).reshape((6,) + cb)
+    eps = np.empty((6, bz, by, bx))
+    for z0 in range(0, bz, cb[0]):
+        for y0 in range(0, by, cb[1]):
+            for x0 in range(0, bx, cb[2]):
+                dz, dy, dx = min(cb[0], bz - z0), min(cb[1], by - y0), min(cb[2], bx - x0)
+                eps[:, z0:z0 + dz, y0:y0 + dy, x0:x0 + dx] = cell[:, :dz, :dy, :dx]
+    kp = nz - pml - 5
+    p0 = ((nx - patch) // 2, (ny - patch) // 2)
+    return DomainSpec(
+        shape=shape, courant=courant_3d(), pml=(pml,) * 6, eps_kind="tensor",
+        eps_box=(lo, hi), eps=eps, eps_bg=1.0,
+        sources=[SourceSpec("plane_z", EX, (0, 0, pml + 5), gaussian_sine(n_steps, 0.15, 30.0, 120.0))],
+        monitors=[MonitorSpec("patch_z", comp=EX, pos=(0, 0, kp),
+                              rect=(p0[0], p0[0] + patch, p0[1], p0[1] + patch), omega_dt=freq_grid(n_f))],
+        n_steps=n_steps,
+    )
+
+
 def random_state_like(spec: DomainSpec, seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
@@ -322,4 +379,5 @@ WORKLOADS = {
     "design_patch": lambda: design_patch()[0],
     "batch_domains": lambda: batch_domains(),
     "anisotropic_lorentz": lambda: anisotropic_lorentz(),
+    "anisotropic_tensor": lambda: anisotropic_tensor(),
 }

@@ -193,3 +193,55 @@ def test_periodic_descriptor_checked():
     _refused(spec(bloch_sign=(2, 1, 1)), B.FDTD_E_INVALID)
     _refused(spec(grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID)
     _refused(spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
+
+
+def _tensor_spec(m_node, n=10, pml=(0, 0, 0, 0, 3, 3), **kw):
+    """A tensor domain whose node (5, 5, 1) (inside the low z face) holds m_node."""
+    from tests.test_oracle_tensor import uniform_tensor
+    eps = uniform_tensor((n, n, n), 2.0 * np.eye(3))
+    eps[:, 1, 5, 5] = [m_node[0, 0], m_node[1, 1], m_node[2, 2], m_node[0, 1], m_node[0, 2], m_node[1, 2]]
+    s = W.DomainSpec(shape=(n, n, n), courant=W.courant_3d(), pml=pml, eps_kind="tensor",
+                     eps_box=((0, 0, 0), (n, n, n)), eps=eps)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _passes_validation(spec, **kw):
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_create([spec], B.FDTD_F32, mem_budget_bytes=1.0, **kw)
+    assert e.value.code == B.FDTD_E_NOMEM, str(e.value)
+
+
+def test_tensor_admission_node_by_node():
+    """Section 2.3's rule for tensor media, checked at every node: eigenvalues
+    of at least 1; inside an absorbing face the normal is a principal axis
+    with the largest or smallest eigenvalue.  The refused cases are those whose
+    one-step operator grows in the oracle (tests/test_oracle_tensor.py)."""
+    import math
+    c, s_ = math.cos(0.6), math.sin(0.6)
+    rz = np.array([[c, -s_, 0.0], [s_, c, 0.0], [0.0, 0.0, 1.0]])
+    cx, sx = math.cos(math.pi / 4), math.sin(math.pi / 4)
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, cx, -sx], [0.0, sx, cx]])
+    # admitted in the z face: normal eigenvalue largest / smallest with the transverse block rotated
+    _passes_validation(_tensor_spec(rz @ np.diag([1.5, 4.0, 6.0]) @ rz.T))
+    _passes_validation(_tensor_spec(rz @ np.diag([1.5, 4.0, 1.0]) @ rz.T))
+    # refused in the face: intermediate normal eigenvalue, axes rotated against the normal
+    _refused(_tensor_spec(np.diag([1.0, 4.0, 2.0])), B.FDTD_E_UNSTABLE)
+    _refused(_tensor_spec(rx @ np.diag([1.0, 16.0, 1.0]) @ rx.T), B.FDTD_E_UNSTABLE)
+    # the same rotated tensor outside every face is admitted
+    _passes_validation(_tensor_spec(rx @ np.diag([1.0, 16.0, 1.0]) @ rx.T, pml=(0,) * 6))
+    # an eigenvalue below one anywhere, or a non-finite entry
+    r = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))[0]
+    _refused(_tensor_spec(r @ np.diag([0.95, 2.0, 3.0]) @ r.T, pml=(0,) * 6), B.FDTD_E_UNSTABLE)
+    bad = np.diag([2.0, 2.0, np.nan])
+    _refused(_tensor_spec(bad, pml=(0,) * 6), B.FDTD_E_UNSTABLE)
+
+
+def test_tensor_media_combinations_refused():
+    """The tensor path is forward-only, nondispersive, walled and split."""
+    m = 2.0 * np.eye(3)
+    _refused(_tensor_spec(m, lorentz=[W.LorentzSpec((2, 2, 2), (5, 5, 5), 1.0, 0.3, 0.01)]), B.FDTD_E_INVALID)
+    _refused(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID)
+    _refused(_tensor_spec(m, pml=(0, 0, 0, 0, 3, 3), periodic=(1, 0, 0)), B.FDTD_E_INVALID)
+    _refused(_tensor_spec(m), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
