@@ -438,24 +438,83 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
 
 
 // ------------------------------------------------ tensor media, assembly pass
-// eps^-1 component q (xx yy zz xy xz yz) at node (i,j,k): the node arrays
-// over the eps box, the background times the identity elsewhere (nodes on
-// the high walls included)
+// Operands of plane k of the assembly pass that are not carried over from
+// plane k-1 (c: curl, a: node eps^-1; suffixes name the offset from (i,j,k))
 template <typename T>
-__device__ __forceinline__ T tnode(const DomDev<T>& d, int q, int i, int j, int k) {
-    if (i >= d.elo[0] && i < d.ehi[0] && j >= d.elo[1] && j < d.ehi[1] && k >= d.elo[2] && k < d.ehi[2]) {
-        const long long e = ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) *
-                                (d.ehi[0] - d.elo[0]) + (i - d.elo[0]);
-        return gp(d.tinv[q])[e];
-    }
-    return q < 3 ? d.epsinv_bg : T(0);
+struct TensPlane {
+    T cz, cz_xp, cz_yp;                 // Cz at (i,j,k), (i+1,j,k), (i,j+1,k)
+    T cy_xp, cy_xpym;                   // Cy at (i+1,j,k), (i+1,j-1,k)
+    T cx_yp, cx_xmyp;                   // Cx at (i,j+1,k), (i-1,j+1,k)
+    T cx_zp, cx_xmzp, cy_zp, cy_ymzp;   // plane k+1: Cx at (i,j,k+1), (i-1,j,k+1); Cy at (i,j,k+1), (i,j-1,k+1)
+    T a_xx, a_yy, a_xy;                 // node (i,j,k)
+    T axp_xx, axp_xy, axp_xz;           // node (i+1,j,k)
+    T ayp_yy, ayp_xy, ayp_yz;           // node (i,j+1,k)
+    T azp_zz, azp_xz, azp_yz;           // node (i,j,k+1)
+    T e[3];
+};
+
+// Per-column addressing of the assembly pass: curl and node-tensor offsets
+// of (i,j) with the in-grid and in-box tests of the x and y neighbours
+// evaluated once per column; the per-plane tests are on k alone.
+template <typename T>
+struct TensCol {
+    const FDTD_GLOBAL T* c[3];           // curl arrays
+    const FDTD_GLOBAL T* a[6];           // node eps^-1 arrays over the box
+    long long fc;                        // field offset of (i, j, 0)
+    long long qc;                        // box offset of (i, j, elo_z) (valid when the column is in the box)
+    long long pl, bpl;                   // field plane, box plane
+    int pitch, bx;
+    bool xm, xp, ym, yp;                 // i-1 >= 0, i+1 < nx, j-1 >= 0, j+1 < ny
+    bool bxy, bxpy, bxyp;                // (i,j), (i+1,j), (i,j+1) inside the box's x-y extent
+    int nz, ez0, ez1;
+    T bg;
+};
+
+template <typename T>
+__device__ __forceinline__ T tc(const TensCol<T>& m, int b, long long off, bool ok) {
+    return ok ? m.c[b][m.fc + off] : T(0);
 }
 
-// stretched curl of the b edge starting at node (i,j,k); zero off the grid
+// component q (xx yy zz xy xz yz) of the node tensor at column offset off
+// (in-box flag inb) and plane k; outside the box (the nodes on the high walls
+// included) the background eps^-1 times the identity
 template <typename T>
-__device__ __forceinline__ T tcurl(const DomDev<T>& d, int b, int i, int j, int k) {
-    if (i < 0 || j < 0 || k < 0 || i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) return T(0);
-    return gp(d.curl[b])[fidx(d, i, j, k)];
+__device__ __forceinline__ T ta(const TensCol<T>& m, int q, long long off, bool inb, int k) {
+    return (inb && k >= m.ez0 && k < m.ez1) ? m.a[q][m.qc + (long long)(k - m.ez0) * m.bpl + off]
+                                            : (q < 3 ? m.bg : T(0));
+}
+
+template <typename T>
+__device__ __forceinline__ void tens_fetch(const TensCol<T>& m, TensPlane<T>& p, const FDTD_GLOBAL T* const (&e)[3],
+                                           int k, long long f) {
+    const long long o = (long long)k * m.pl, P = m.pitch, X = m.bx;
+    const bool up = k + 1 < m.nz;
+    p.cz = tc(m, 2, o, true);
+    p.cz_xp = tc(m, 2, o + 1, m.xp);
+    p.cz_yp = tc(m, 2, o + P, m.yp);
+    p.cy_xp = tc(m, 1, o + 1, m.xp);
+    p.cy_xpym = tc(m, 1, o + 1 - P, m.xp && m.ym);
+    p.cx_yp = tc(m, 0, o + P, m.yp);
+    p.cx_xmyp = tc(m, 0, o - 1 + P, m.xm && m.yp);
+    p.cx_zp = tc(m, 0, o + m.pl, up);
+    p.cx_xmzp = tc(m, 0, o + m.pl - 1, up && m.xm);
+    p.cy_zp = tc(m, 1, o + m.pl, up);
+    p.cy_ymzp = tc(m, 1, o + m.pl - P, up && m.ym);
+    p.a_xx = ta(m, 0, 0, m.bxy, k);
+    p.a_yy = ta(m, 1, 0, m.bxy, k);
+    p.a_xy = ta(m, 3, 0, m.bxy, k);
+    p.axp_xx = ta(m, 0, 1, m.bxpy, k);
+    p.axp_xy = ta(m, 3, 1, m.bxpy, k);
+    p.axp_xz = ta(m, 4, 1, m.bxpy, k);
+    p.ayp_yy = ta(m, 1, X, m.bxyp, k);
+    p.ayp_xy = ta(m, 3, X, m.bxyp, k);
+    p.ayp_yz = ta(m, 5, X, m.bxyp, k);
+    p.azp_zz = ta(m, 2, 0, m.bxy, k + 1);
+    p.azp_xz = ta(m, 4, 0, m.bxy, k + 1);
+    p.azp_yz = ta(m, 5, 0, m.bxy, k + 1);
+    p.e[0] = e[0][f];
+    p.e[1] = e[1][f];
+    p.e[2] = e[2][f];
 }
 
 // E^{n+1} = E^n + S (node assembly of eps^-1) curl, plus the sources, for the
@@ -464,7 +523,10 @@ __device__ __forceinline__ T tcurl(const DomDev<T>& d, int b, int i, int j, int 
 // eps^-1_cc(v)/2 times its own curl and eps^-1_cb(v)/4 times the sum of the
 // curls of the two b edges meeting at v (leaving and arriving), b != c.
 // Edges tangential to a wall keep E = 0.  Reads and writes only its own E
-// nodes, so it runs in place like the other split kernels.
+// nodes, so it runs in place like the other split kernels.  Along z the
+// column keeps what plane k+1 shares with plane k (the Cz below, the Cx and
+// Cy above, the node above) in registers, and fetches plane k+1's other
+// operands before it computes and stores plane k.
 template <typename T, int W>
 __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                 const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int t,
@@ -476,30 +538,57 @@ __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ do
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
     const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs;
+    const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + so), gp(d.E[1] + so), gp(d.E[2] + so)};
+    FDTD_GLOBAL T* ew[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
     const T S = d.S, h = T(0.5), q4 = T(0.25);
-    for (int k = c.k0; k < c.k1; ++k) {
-        const long long f = fidx(d, i, j, k);
-        T a0[6];
-        for (int q = 0; q < 6; ++q) a0[q] = tnode(d, q, i, j, k);
-        const T cx = tcurl(d, 0, i, j, k), cy = tcurl(d, 1, i, j, k), cz = tcurl(d, 2, i, j, k);
-        const T sxm = cx + tcurl(d, 0, i - 1, j, k);    // the two x edges at v0
-        const T sym = cy + tcurl(d, 1, i, j - 1, k);    // the two y edges at v0
-        const T szm = cz + tcurl(d, 2, i, j, k - 1);    // the two z edges at v0
-        // Ex: far node (i+1, j, k)
-        T mx = h * (a0[0] + tnode(d, 0, i + 1, j, k)) * cx;
-        mx += q4 * (a0[3] * sym + tnode(d, 3, i + 1, j, k) * (tcurl(d, 1, i + 1, j, k) + tcurl(d, 1, i + 1, j - 1, k)));
-        mx += q4 * (a0[4] * szm + tnode(d, 4, i + 1, j, k) * (tcurl(d, 2, i + 1, j, k) + tcurl(d, 2, i + 1, j, k - 1)));
-        // Ey: far node (i, j+1, k)
-        T my = h * (a0[1] + tnode(d, 1, i, j + 1, k)) * cy;
-        my += q4 * (a0[3] * sxm + tnode(d, 3, i, j + 1, k) * (tcurl(d, 0, i, j + 1, k) + tcurl(d, 0, i - 1, j + 1, k)));
-        my += q4 * (a0[5] * szm + tnode(d, 5, i, j + 1, k) * (tcurl(d, 2, i, j + 1, k) + tcurl(d, 2, i, j + 1, k - 1)));
-        // Ez: far node (i, j, k+1)
-        T mz = h * (a0[2] + tnode(d, 2, i, j, k + 1)) * cz;
-        mz += q4 * (a0[4] * sxm + tnode(d, 4, i, j, k + 1) * (tcurl(d, 0, i, j, k + 1) + tcurl(d, 0, i - 1, j, k + 1)));
-        mz += q4 * (a0[5] * sym + tnode(d, 5, i, j, k + 1) * (tcurl(d, 1, i, j, k + 1) + tcurl(d, 1, i, j - 1, k + 1)));
-        T ex = fma(S, mx, gp(d.E[0] + so)[f]);
-        T ey = fma(S, my, gp(d.E[1] + so)[f]);
-        T ez = fma(S, mz, gp(d.E[2] + so)[f]);
+    const int k0 = c.k0;
+    TensCol<T> m;
+    for (int b = 0; b < 3; ++b) m.c[b] = gp((const T*)d.curl[b]);
+    for (int q = 0; q < 6; ++q) m.a[q] = gp(d.tinv[q]);
+    m.pitch = d.pitch;
+    m.pl = d.plane;
+    m.fc = (long long)j * d.pitch + i;
+    m.bx = d.ehi[0] - d.elo[0];
+    m.bpl = (long long)m.bx * (d.ehi[1] - d.elo[1]);
+    m.qc = (long long)(j - d.elo[1]) * m.bx + (i - d.elo[0]);
+    m.xm = i > 0;
+    m.xp = i + 1 < d.n[0];
+    m.ym = j > 0;
+    m.yp = j + 1 < d.n[1];
+    const bool inx = i >= d.elo[0] && i < d.ehi[0], inx1 = i + 1 >= d.elo[0] && i + 1 < d.ehi[0];
+    const bool iny = j >= d.elo[1] && j < d.ehi[1], iny1 = j + 1 >= d.elo[1] && j + 1 < d.ehi[1];
+    m.bxy = inx && iny;
+    m.bxpy = inx1 && iny;
+    m.bxyp = inx && iny1;
+    m.nz = d.n[2];
+    m.ez0 = d.elo[2];
+    m.ez1 = d.ehi[2];
+    m.bg = d.epsinv_bg;
+    // carried into plane k0: Cz below it, Cx and Cy on it, the z-related node entries
+    const long long o0 = (long long)k0 * m.pl;
+    T czm = tc(m, 2, o0 - m.pl, k0 > 0), czm_xp = tc(m, 2, o0 - m.pl + 1, k0 > 0 && m.xp),
+      czm_yp = tc(m, 2, o0 - m.pl + m.pitch, k0 > 0 && m.yp);
+    T cx = tc(m, 0, o0, true), cx_xm = tc(m, 0, o0 - 1, m.xm);
+    T cy = tc(m, 1, o0, true), cy_ym = tc(m, 1, o0 - m.pitch, m.ym);
+    T a_zz = ta(m, 2, 0, m.bxy, k0), a_xz = ta(m, 4, 0, m.bxy, k0), a_yz = ta(m, 5, 0, m.bxy, k0);
+    long long f = fidx(d, i, j, k0);
+    TensPlane<T> cu, nx;
+    tens_fetch(m, cu, e, k0, f);
+    for (int k = k0; k < c.k1; ++k, f += d.plane) {
+        if (k + 1 < c.k1) tens_fetch(m, nx, e, k + 1, f + d.plane);
+        const T sx = cx + cx_xm, sy = cy + cy_ym, sz = cu.cz + czm;   // the two edges of each axis at v0
+        T mx = h * (cu.a_xx + cu.axp_xx) * cx;
+        mx += q4 * (cu.a_xy * sy + cu.axp_xy * (cu.cy_xp + cu.cy_xpym));
+        mx += q4 * (a_xz * sz + cu.axp_xz * (cu.cz_xp + czm_xp));
+        T my = h * (cu.a_yy + cu.ayp_yy) * cy;
+        my += q4 * (cu.a_xy * sx + cu.ayp_xy * (cu.cx_yp + cu.cx_xmyp));
+        my += q4 * (a_yz * sz + cu.ayp_yz * (cu.cz_yp + czm_yp));
+        T mz = h * (a_zz + cu.azp_zz) * cu.cz;
+        mz += q4 * (a_xz * sx + cu.azp_xz * (cu.cx_zp + cu.cx_xmzp));
+        mz += q4 * (a_yz * sy + cu.azp_yz * (cu.cy_zp + cu.cy_ymzp));
+        T ex = fma(S, mx, cu.e[0]);
+        T ey = fma(S, my, cu.e[1]);
+        T ez = fma(S, mz, cu.e[2]);
         for (int q = 0; q < d.nsrc; ++q) {
             const SrcDev<T>& sr = d.src[q];
             if (t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j))) {
@@ -512,9 +601,21 @@ __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ do
         if (e_masked_d(d, 0, i, j, k)) ex = T(0);
         if (e_masked_d(d, 1, i, j, k)) ey = T(0);
         if (e_masked_d(d, 2, i, j, k)) ez = T(0);
-        gp(d.E[0] + wo)[f] = ex;
-        gp(d.E[1] + wo)[f] = ey;
-        gp(d.E[2] + wo)[f] = ez;
+        ew[0][f] = ex;
+        ew[1][f] = ey;
+        ew[2][f] = ez;
+        // plane k+1 inherits
+        czm = cu.cz;
+        czm_xp = cu.cz_xp;
+        czm_yp = cu.cz_yp;
+        cx = cu.cx_zp;
+        cx_xm = cu.cx_xmzp;
+        cy = cu.cy_zp;
+        cy_ym = cu.cy_ymzp;
+        a_zz = cu.azp_zz;
+        a_xz = cu.azp_xz;
+        a_yz = cu.azp_yz;
+        cu = nx;
     }
 }
 

@@ -2,7 +2,9 @@
 
 Per cell and step the Yee update reads and writes the six field components
 once (12 words).  Add eps^-1 where it is stored (1 word per cell of the eps
-box, 3 for a diagonal tensor), 8 words per absorbing-face cell (two E and two
+box, 3 for a diagonal tensor, 6 per node of a symmetric tensor's box; the
+tensor path's curl scratch, written and read once per step, is an
+implementation cost and not counted), 8 words per absorbing-face cell (two E and two
 H memories read and written), 15 words per Lorentz cell (per component read
 E^{n-1}, W^n, W^{n-1}; write E^{n-1}, W^{n+1}).  Halo re-reads, the second
 copy of W^{n-1} that ping-ponged state writes, and padding are not counted.
@@ -33,7 +35,8 @@ def face_cells(spec) -> int:
 
 def forward_bytes(spec, word: int) -> int:
     n = spec.ncells
-    neps = _box_cells(spec.eps_box) * (3 if spec.eps_kind == "diag" else 1) if spec.eps is not None else 0
+    per = {"iso": 1, "diag": 3, "tensor": 6}[spec.eps_kind]
+    neps = _box_cells(spec.eps_box) * per if spec.eps is not None else 0
     # dispersive cells, per component: read E^{n-1} and each pole's W^n, W^{n-1};
     # write E^{n-1} and each pole's W^{n+1} (2 + 3 P words; 5 for one pole)
     lor_words = sum(_box_cells((L.lo, L.hi)) * 3 * (2 + 3 * len(L.pole_list())) for L in spec.lorentz)
