@@ -333,6 +333,76 @@ int fdtd_flux_reduce_noalloc(const double *spectra, int32_t n_freq, int64_t n_pt
    the last failing create or handle-free call); valid until the next call. */
 const char *fdtd_last_error(fdtd_t h);
 
+/* ---------------------------------------------------------------------------
+   Host-streamed causal slabs (Section 4.2): one domain whose state lives in
+   host memory, advanced slab by slab in a device workspace of a few slabs'
+   planes, for domains beyond the device's memory.
+
+   The domain is cut along z (the slowest axis of the field layout, so every
+   host<->device transfer is one contiguous copy per state array) into
+   ceil(nz / slab_planes) slabs whose cores split nz as evenly as possible.
+   One pass advances the domain by K = steps_per_pass steps: each slab in turn
+   is copied from host bank A (time t) over its core and K + 1 halo planes per
+   cut side, stepped K times with the resident kernels, and its core is copied
+   to host bank B (time t + K); the banks then swap.  A cut face acts as a
+   wall, and a wrong value moves at most one plane per step, so every core
+   plane equals the resident solution bit for bit (same kernels, same
+   operands).  Device memory scales with (W + 2K + 2) nx ny, host memory with
+   the two banks (2 x the resident state) plus eps^-1 in the field type.
+
+   Supported: everything the resident forward path supports on the domain
+   (scalar, diagonal or tensor eps, a dispersive box, absorbing faces on every
+   side, periodic x/y, sources, probe and plane monitors), forward only: a
+   descriptor with grad set is refused (FDTD_E_INVALID).  An absorbing z face
+   must lie wholly inside or wholly outside each slab's extent: a slab that
+   would cut one is refused (FDTD_E_INVALID; raise slab_planes).  Monitors
+   belong to the slab whose core holds their plane; their spectra and probe
+   traces accumulate on the device across slabs and passes.  The device
+   workspace and monitor accumulators are admitted against mem_budget_bytes
+   (0: the device's free memory) and the host banks against
+   host_budget_bytes (0: no limit besides the pinned allocation itself), both
+   before anything is allocated (FDTD_E_NOMEM). */
+typedef struct {
+    int32_t dtype;                 /* FDTD_F32 | FDTD_F64 */
+    int32_t slab_planes;           /* W: most core planes of one slab, >= 1 */
+    int32_t steps_per_pass;        /* K: steps a slab advances per visit, >= 1 (halo K + 1 per cut side) */
+    int32_t max_steps;             /* probe trace length */
+    int32_t tile_rows, tile_kz;    /* split-kernel launch shape of the slab steps (0: defaults) */
+    void *stream;                  /* hipStream_t; NULL = default stream */
+    double mem_budget_bytes;       /* device budget (0: free memory) */
+    double host_budget_bytes;      /* pinned host budget for the banks and eps^-1 (0: unchecked) */
+} fdtd_stream_options;
+
+typedef struct {
+    int32_t n_slabs;
+    int32_t halo;                  /* planes per cut side */
+    int32_t max_extent;            /* planes of the largest slab, halos included */
+    int32_t step;                  /* steps advanced so far */
+    double device_bytes;           /* workspace + monitor accumulators */
+    double host_bytes;             /* pinned: two state banks + eps^-1 */
+    double resident_bytes;         /* what the resident handle of the same domain would allocate */
+} fdtd_stream_info;
+
+typedef struct fdtd_stream_s *fdtd_stream_t;
+
+/* Validates the domain as fdtd_create would (same error codes), plans and
+   admits the slabs, allocates, and zeroes the state (time 0).  The
+   descriptor's arrays are copied; the caller may free them afterwards. */
+int fdtd_stream_create(const fdtd_domain_desc *domain, const fdtd_stream_options *opt, fdtd_stream_t *out);
+int fdtd_stream_destroy(fdtd_stream_t h);
+/* Advances n_steps (passes of steps_per_pass steps, the last one shorter). */
+int fdtd_stream_step(fdtd_stream_t h, int32_t n_steps);
+/* Field comp 0..5 (Ex..Hz) of the current state, [nz][ny][nx] of the dtype. */
+int fdtd_stream_get_field(fdtd_stream_t h, int32_t comp, void *host_buf, size_t bytes);
+/* op FDTD_MON_GET: spectra (layout of fdtd_monitor_dft) or the probe trace;
+   FDTD_MON_FLUX: flux per frequency of a flux monitor, reduced on the device. */
+int fdtd_stream_monitor(fdtd_stream_t h, int32_t monitor, int32_t op, double *host_buf, size_t bytes);
+/* Back to time 0: state and monitors zeroed. */
+int fdtd_stream_reset(fdtd_stream_t h);
+int fdtd_stream_get_info(fdtd_stream_t h, fdtd_stream_info *out);
+/* Message of the last failing call on h (NULL: of a failing create). */
+const char *fdtd_stream_last_error(fdtd_stream_t h);
+
 #ifdef __cplusplus
 }
 #endif

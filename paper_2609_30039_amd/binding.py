@@ -34,7 +34,9 @@ EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_be
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
-            "fdtd_flux_reduce", "fdtd_flux_reduce_noalloc", "fdtd_last_error"]
+            "fdtd_flux_reduce", "fdtd_flux_reduce_noalloc", "fdtd_last_error",
+            "fdtd_stream_create", "fdtd_stream_destroy", "fdtd_stream_step", "fdtd_stream_get_field",
+            "fdtd_stream_monitor", "fdtd_stream_reset", "fdtd_stream_get_info", "fdtd_stream_last_error"]
 
 FDTD_FLUX_POINTS_PER_BLOCK, FDTD_FLUX_MAX_BLOCKS = 4096, 256
 FDTD_FLUX_SCRATCH_BYTES = 65536
@@ -96,6 +98,17 @@ class Options(C.Structure):
                 ("mem_budget_bytes", C.c_double), ("reversible", C.c_int32)]
 
 
+class StreamOptions(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("slab_planes", C.c_int32), ("steps_per_pass", C.c_int32),
+                ("max_steps", C.c_int32), ("tile_rows", C.c_int32), ("tile_kz", C.c_int32),
+                ("stream", C.c_void_p), ("mem_budget_bytes", C.c_double), ("host_budget_bytes", C.c_double)]
+
+
+class StreamInfo(C.Structure):
+    _fields_ = [("n_slabs", C.c_int32), ("halo", C.c_int32), ("max_extent", C.c_int32), ("step", C.c_int32),
+                ("device_bytes", C.c_double), ("host_bytes", C.c_double), ("resident_bytes", C.c_double)]
+
+
 _lib = None
 
 
@@ -135,8 +148,17 @@ def lib():
         L.fdtd_flux_reduce_noalloc.argtypes = [vp, i32, C.c_int64, vp, vp]
         L.fdtd_last_error.argtypes = [vp]
         L.fdtd_last_error.restype = C.c_char_p
+        L.fdtd_stream_create.argtypes = [C.POINTER(DomainDesc), C.POINTER(StreamOptions), C.POINTER(vp)]
+        L.fdtd_stream_destroy.argtypes = [vp]
+        L.fdtd_stream_step.argtypes = [vp, i32]
+        L.fdtd_stream_get_field.argtypes = [vp, i32, vp, sz]
+        L.fdtd_stream_monitor.argtypes = [vp, i32, i32, vp, sz]
+        L.fdtd_stream_reset.argtypes = [vp]
+        L.fdtd_stream_get_info.argtypes = [vp, C.POINTER(StreamInfo)]
+        L.fdtd_stream_last_error.argtypes = [vp]
+        L.fdtd_stream_last_error.restype = C.c_char_p
         for name in EXPORTED:
-            if name != "fdtd_last_error":
+            if not name.endswith("last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -347,3 +369,52 @@ def fdtd_checkpoint_corrupt(h, slot: int, word: int, value: int):
 def fdtd_last_error(h=None) -> str:
     s = lib().fdtd_last_error(h)
     return s.decode() if s else ""
+
+
+# ---------------------------------------------------------------- streamed slabs
+def _schk(rc: int, h=None):
+    if rc != FDTD_OK:
+        msg = lib().fdtd_stream_last_error(h)
+        raise FdtdError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def fdtd_stream_create(spec, dtype: int, slab_planes: int, steps_per_pass: int, max_steps: int = 0,
+                       tile_rows: int = 0, tile_kz: int = 0, stream: Optional[int] = None,
+                       mem_budget_bytes: float = 0.0, host_budget_bytes: float = 0.0):
+    keep: list = []
+    d = domain_desc(spec, keep)
+    o = StreamOptions()
+    o.dtype, o.slab_planes, o.steps_per_pass, o.max_steps = dtype, slab_planes, steps_per_pass, max_steps
+    o.tile_rows, o.tile_kz = tile_rows, tile_kz
+    o.stream = stream
+    o.mem_budget_bytes, o.host_budget_bytes = mem_budget_bytes, host_budget_bytes
+    h = C.c_void_p()
+    _schk(lib().fdtd_stream_create(C.byref(d), C.byref(o), C.byref(h)), None)
+    return h
+
+
+def fdtd_stream_destroy(h):
+    return _schk(lib().fdtd_stream_destroy(h), None)
+
+
+def fdtd_stream_step(h, n_steps: int):
+    return _schk(lib().fdtd_stream_step(h, n_steps), h)
+
+
+def fdtd_stream_get_field(h, comp: int, out: np.ndarray):
+    return _schk(lib().fdtd_stream_get_field(h, comp, out.ctypes.data, out.nbytes), h)
+
+
+def fdtd_stream_monitor(h, monitor: int, op: int, out: np.ndarray):
+    return _schk(lib().fdtd_stream_monitor(h, monitor, op, out.ctypes.data, out.nbytes), h)
+
+
+def fdtd_stream_reset(h):
+    return _schk(lib().fdtd_stream_reset(h), h)
+
+
+def fdtd_stream_get_info(h) -> dict:
+    i = StreamInfo()
+    _schk(lib().fdtd_stream_get_info(h, C.byref(i)), h)
+    return {k: getattr(i, k) for k, _ in StreamInfo._fields_}

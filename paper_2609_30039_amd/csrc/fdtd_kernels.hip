@@ -2140,6 +2140,10 @@ __global__ void k_step_counter(int* __restrict__ c, int value, int add) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = add ? *c + value : value;
 }
 
+__global__ void __launch_bounds__(256) k_add_f64(double* __restrict__ y, const double* __restrict__ x, long long n) {
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < n; q += (long long)gridDim.x * 256) y[q] += x[q];
+}
+
 __global__ void k_fill_zero(uint32_t* __restrict__ p, long long n_words) {
     long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long stride = (long long)gridDim.x * blockDim.x;
@@ -2585,6 +2589,11 @@ void launch_zero(void* p, size_t bytes, hipStream_t s) {
     long long nw = (long long)(bytes / 4);
     if (nw == 0) return;
     hipLaunchKernelGGL(k_fill_zero, dim3(blocks_1d(nw, 256, 8192)), dim3(256), 0, s, (uint32_t*)p, nw);
+}
+
+void launch_add_f64(double* y, const double* x, size_t n, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_add_f64, dim3(blocks_1d((long long)n, 256, 4096)), dim3(256), 0, s, y, x, (long long)n);
 }
 
 void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {

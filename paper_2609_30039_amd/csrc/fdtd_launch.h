@@ -97,6 +97,8 @@ int split_blocks(int nx, int ny, int nz, int kz, int w);
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 void launch_step_counter(int* c, int value, bool add, hipStream_t s);
 void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// y[0..n) += x[0..n) (monitor accumulators of a slab into the domain's)
+void launch_add_f64(double* y, const double* x, size_t n, hipStream_t s);
 // BF16 checkpoint slots: one table entry per forward state array (FP32)
 constexpr int kBfChunk = 32768;              // elements per block
 struct BfArr {

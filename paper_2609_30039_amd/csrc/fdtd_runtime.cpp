@@ -263,6 +263,13 @@ struct Handle : Base {
     bool timing_on = false;
     std::vector<hipEvent_t> evs;
     size_t nev = 0;
+    // use by the streamed executor: size_only stops create() once the pool
+    // size is known; ext_pool (ext_cap bytes) replaces the allocation and is
+    // not freed; external_eps: the caller uploads eps^-1 itself (a slab cut
+    // from an admitted domain), so create() neither checks nor keeps eps
+    bool size_only = false, external_eps = false;
+    char* ext_pool = nullptr;
+    size_t ext_cap = 0;
 
     ~Handle() override {
         if (!pool) return;   // nothing was allocated (e.g. refused at admission)
@@ -274,8 +281,7 @@ struct Handle : Base {
             (void)hipGraphDestroy(g.g);
         }
         if (cst) (void)hipStreamDestroy(cst);
-
-        (void)hipFree(pool);
+        if (!ext_pool) (void)hipFree(pool);
     }
 
     int fail(int code, const std::string& msg) {
@@ -769,21 +775,29 @@ struct Handle : Base {
         et_bytes = align256(X.off);
         size_t bf_total = bf16 ? align256(bfslot) * o->n_ckpt : 0;
         pool_bytes = misc_bytes + fstride * nsets + astride * 2 + et_bytes + bf_total;
-        double budget = o->mem_budget_bytes;
-        if (budget <= 0) {
-            size_t fr = 0, tot = 0;
-            if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(FDTD_E_DEVICE, "hipMemGetInfo failed");
-            budget = (double)fr - 256.0 * 1024 * 1024;
+        if (size_only) return FDTD_OK;
+        if (ext_pool) {
+            if (pool_bytes > ext_cap) return fail(FDTD_E_NOMEM, "slab workspace larger than its pool");
+            pool = ext_pool;
         }
-        if ((double)pool_bytes > budget) {
-            char b[160];
-            snprintf(b, sizeof b, "device memory request %.3e B exceeds budget %.3e B", (double)pool_bytes, budget);
-            return fail(FDTD_E_NOMEM, b);
-        }
-        if (hipMalloc((void**)&pool, pool_bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            pool = nullptr;
-            return fail(FDTD_E_NOMEM, "hipMalloc of the device pool failed");
+        if (!ext_pool) {
+            double budget = o->mem_budget_bytes;
+            if (budget <= 0) {
+                size_t fr = 0, tot = 0;
+                if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(FDTD_E_DEVICE, "hipMemGetInfo failed");
+                budget = (double)fr - 256.0 * 1024 * 1024;
+            }
+            if ((double)pool_bytes > budget) {
+                char b[160];
+                snprintf(b, sizeof b, "device memory request %.3e B exceeds budget %.3e B", (double)pool_bytes,
+                         budget);
+                return fail(FDTD_E_NOMEM, b);
+            }
+            if (hipMalloc((void**)&pool, pool_bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                pool = nullptr;
+                return fail(FDTD_E_NOMEM, "hipMalloc of the device pool failed");
+            }
         }
         fbase = pool + misc_bytes;
         abase = fbase + fstride * nsets;
@@ -977,6 +991,7 @@ struct Handle : Base {
     }
 
     int upload_eps(int q) {
+        if (external_eps) return FDTD_OK;
         DomHost& h = dh[q];
         DomDev<T>& d = dd[q];
         size_t ebox = 1;
@@ -1035,11 +1050,15 @@ struct Handle : Base {
                 return fail(FDTD_E_INVALID, "eps box out of range");
             ebox *= (size_t)(s.eps_hi[a] - s.eps_lo[a]);
         }
-        if (ebox && !s.eps) return fail(FDTD_E_INVALID, "eps array missing");
-        h.eps.assign(ebox * h.ncomp_eps, 1.0);
-        if (ebox) {
-            int rc = validate_eps_only(s, h, s.eps);
-            if (rc) return rc;
+        if (ebox && !s.eps && !external_eps) return fail(FDTD_E_INVALID, "eps array missing");
+        if (external_eps) {
+            h.eps.clear();
+        } else {
+            h.eps.assign(ebox * h.ncomp_eps, 1.0);
+            if (ebox) {
+                int rc = validate_eps_only(s, h, s.eps);
+                if (rc) return rc;
+            }
         }
         if (s.eps_kind == FDTD_EPS_TENSOR) {
             // the tensor path is forward-only, nondispersive and walled
@@ -1641,6 +1660,501 @@ int guard(fdtd_t h);
 
 }  // namespace
 
+namespace {
+// ------------------------------------------------------------ streamed slabs
+// Host-streamed causal slabs (Section 4.2).  The domain is cut along z, the
+// slowest axis of the x-fastest layout, so that every transfer between the
+// host banks and the device is one contiguous copy per state array.  Each
+// slab owns a core of at most W planes; the cores tile [0, nz).  One pass
+// advances the whole domain by K steps: every slab in turn is loaded from
+// bank A (time t) over its core plus K + 1 halo planes on each cut side, is
+// stepped K times in a device workspace, and writes its core to bank B
+// (time t + K); then the banks swap.  A cut face acts as a wall with ghost
+// zeros, and a wrong value moves at most one plane per step (the E update
+// reads H one plane back, the H update E one plane forward), so after K
+// steps the wrong planes are the K nearest each cut: the core and the
+// halo plane next to it are exact, the latter for the flux planes' H below.
+// An absorbing z face is either wholly inside a slab's extent (with its
+// memories) or outside it, so every slab's absorber tables are the domain's.
+struct StreamBase {
+    virtual ~StreamBase() = default;
+    std::string err;
+    bool poisoned = false;
+    virtual int step(int n) = 0;
+    virtual int get_field(int comp, void* buf, size_t bytes) = 0;
+    virtual int monitor(int mon, int op, double* buf, size_t bytes) = 0;
+    virtual int reset() = 0;
+    virtual void info(fdtd_stream_info* o) = 0;
+};
+
+template <typename T>
+struct Streamer : StreamBase {
+    fdtd_domain_desc g{};                       // the domain (pointers into the copies below)
+    fdtd_stream_options so{};
+    std::vector<std::vector<double>> waves, omegas;
+    hipStream_t st = nullptr;
+    int nx = 0, ny = 0, nz = 0, pitch = 0, K = 0, halo = 0, t = 0, npole = 0, ncomp_eps = 1;
+    std::vector<int> core;                      // core start plane of each slab; core[ns] = nz
+    // One global state array: planes [z0, z1) of `per` elements each, at
+    // element offset `off` of a bank.  kind: 0 field E/H c, 1 psi_E, 2 psi_H
+    // (a, side, r), 3 dispersive history (w, c, pole p).
+    struct GArr {
+        int kind, c, a, side, r, w, p;
+        int z0, z1;
+        size_t per, off;
+    };
+    std::vector<GArr> ga;
+    size_t bank_elems = 0;
+    T* bank[2] = {nullptr, nullptr};
+    int cb = 0;                                 // bank holding the state at time t
+    // eps^-1 of the domain in the field type over its eps box, per component
+    // (tensor: six), pinned, uploaded plane-range by plane-range per slab
+    T* einv = nullptr;
+    size_t ebox = 0;
+    int ez0 = 0, ez1 = 0;
+    size_t eplane = 0;
+    char* pool = nullptr;
+    size_t pool_cap = 0;
+    // monitor accumulators of the domain on the device: spectra or the probe trace
+    struct GMon {
+        int kind, nf, k, slab;
+        long long npts;
+        size_t elems;
+        double *acc = nullptr, *fpart = nullptr, *fout = nullptr;
+    };
+    std::vector<GMon> gm;
+    char* dmon = nullptr;
+    size_t dmon_bytes = 0;
+    double resident_bytes = 0;
+    static inline double dummy_eps = 1.0;
+
+    ~Streamer() override {
+        if (st) (void)hipStreamSynchronize(st);
+        if (pool) (void)hipFree(pool);
+        if (dmon) (void)hipFree(dmon);
+        for (int b = 0; b < 2; ++b)
+            if (bank[b]) (void)hipHostFree(bank[b]);
+        if (einv) (void)hipHostFree(einv);
+    }
+
+    int fail(int code, const std::string& m) {
+        err = m;
+        if (code == FDTD_E_DEVICE) poisoned = true;
+        return code;
+    }
+
+    int ns() const { return (int)core.size() - 1; }
+    int ext_lo(int s) const { return std::max(0, core[s] - (s > 0 ? halo : 0)); }
+    int ext_hi(int s) const { return std::min(nz, core[s + 1] + (s + 1 < ns() ? halo : 0)); }
+
+    fdtd_options slab_options() const {
+        fdtd_options o{};
+        o.dtype = so.dtype;
+        o.max_steps = so.max_steps;
+        o.kernel = FDTD_KERNEL_SPLIT;
+        o.tile_rows = so.tile_rows;
+        o.tile_kz = so.tile_kz;
+        o.stream = so.stream;
+        o.ckpt_storage = so.dtype;
+        return o;
+    }
+
+    // The descriptor of slab s: the domain's planes [o, e) with the absorbing
+    // z faces it contains, the eps and dispersive boxes clipped to it, the
+    // sources in it and the monitors whose plane lies in its core (lmon:
+    // their indices in the domain's list).
+    fdtd_domain_desc slab_desc(int s, std::vector<int>& lmon) const {
+        const int o = ext_lo(s), e = ext_hi(s);
+        fdtd_domain_desc d = g;
+        d.n[2] = e - o;
+        d.pml[4] = o == 0 ? g.pml[4] : 0;
+        d.pml[5] = e == nz ? g.pml[5] : 0;
+        d.eps_lo[2] = std::max(g.eps_lo[2], o) - o;
+        d.eps_hi[2] = std::max(std::min(g.eps_hi[2], e) - o, d.eps_lo[2]);
+        d.eps = ebox ? &dummy_eps : nullptr;
+        if (d.eps_hi[2] == d.eps_lo[2]) {
+            for (int a = 0; a < 3; ++a) d.eps_lo[a] = d.eps_hi[a] = 0;
+            d.eps = nullptr;
+        }
+        d.n_lorentz = 0;
+        if (g.n_lorentz) {
+            const int l0 = std::max(g.lorentz.lo[2], o), l1 = std::min(g.lorentz.hi[2], e);
+            if (l1 > l0) {
+                d.n_lorentz = 1;
+                d.lorentz.lo[2] = l0 - o;
+                d.lorentz.hi[2] = l1 - o;
+            }
+        }
+        d.n_sources = 0;
+        for (int q = 0; q < g.n_sources; ++q) {
+            const fdtd_source_desc& sr = g.sources[q];
+            if (sr.pos[2] < o || sr.pos[2] >= e) continue;
+            fdtd_source_desc& x = d.sources[d.n_sources++];
+            x = sr;
+            x.pos[2] = sr.pos[2] - o;
+        }
+        d.n_monitors = 0;
+        lmon.clear();
+        for (int q = 0; q < g.n_monitors; ++q) {
+            if (gm[q].slab != s) continue;
+            fdtd_monitor_desc& x = d.monitors[d.n_monitors++];
+            x = g.monitors[q];
+            x.pos[2] = g.monitors[q].pos[2] - o;
+            lmon.push_back(q);
+        }
+        d.grad = 0;
+        return d;
+    }
+
+    // device address of the slab handle's copy of global array q and the
+    // first global plane it holds (nullptr: the slab does not hold it)
+    T* slab_array(Handle<T>& hd, const GArr& q, int o, int e, int& sz0, int& sz1) const {
+        const DomDev<T>& d = hd.dd[0];
+        sz0 = std::max(q.z0, o);
+        sz1 = std::min(q.z1, e);
+        if (sz1 <= sz0) return nullptr;
+        switch (q.kind) {
+            case 0:
+                return q.c < 3 ? d.E[q.c] : d.H[q.c - 3];
+            case 1:
+            case 2: {
+                if (q.a == 2 && ((q.side == 0 && o != 0) || (q.side == 1 && e != nz))) return nullptr;
+                T* p = q.kind == 1 ? d.psiE[q.a][q.side][q.r] : d.psiH[q.a][q.side][q.r];
+                return p;
+            }
+            default: {
+                if (!d.has_lor) return nullptr;
+                const long long lbox = d.lbox;
+                return d.lor[q.w][q.c] + (long long)q.p * lbox;
+            }
+        }
+    }
+
+    // the plane of the slab array holding global plane z
+    static int slab_plane(const GArr& q, int z, int o, int sz0) {
+        if (q.kind == 0) return z - o;
+        if ((q.kind == 1 || q.kind == 2) && q.a < 2) return z - o;
+        return z - sz0;   // z faces and the dispersive box: arrays start at their own first plane
+    }
+
+    int create(const fdtd_domain_desc* dom, const fdtd_stream_options* o) {
+        so = *o;
+        g = *dom;
+        st = (hipStream_t)o->stream;
+        if (o->slab_planes < 1 || o->steps_per_pass < 1 || o->max_steps < 0)
+            return fail(FDTD_E_INVALID, "slab_planes and steps_per_pass must be >= 1, max_steps >= 0");
+        if (g.grad) return fail(FDTD_E_INVALID, "the streamed path is forward only: no gradient");
+        // admission of the domain itself: validate it as a resident handle would, without allocating
+        {
+            Handle<T> gh;
+            gh.size_only = true;
+            fdtd_options go = slab_options();
+            int rc = gh.create(dom, 1, &go);
+            if (rc) return fail(rc, gh.err);
+            resident_bytes = (double)gh.pool_bytes;
+            pitch = gh.dd[0].pitch;
+            ncomp_eps = gh.dh[0].ncomp_eps;
+            npole = gh.dd[0].has_lor ? gh.dd[0].npole : 0;
+            // keep the waveforms and frequencies: the descriptor's pointers are the caller's
+            waves.resize(g.n_sources);
+            for (int q = 0; q < g.n_sources; ++q) {
+                waves[q] = gh.dh[0].waves[q];
+                g.sources[q].waveform = waves[q].data();
+            }
+            omegas.resize(g.n_monitors);
+            for (int q = 0; q < g.n_monitors; ++q) {
+                omegas[q] = gh.dh[0].mons[q].omega;
+                g.monitors[q].omega_dt = omegas[q].empty() ? nullptr : omegas[q].data();
+            }
+            ebox = 1;
+            for (int a = 0; a < 3; ++a) ebox *= (size_t)(g.eps_hi[a] - g.eps_lo[a]);
+            if (!g.eps) ebox = 0;
+            if (ebox) {
+                ez0 = g.eps_lo[2];
+                ez1 = g.eps_hi[2];
+                eplane = ebox / (size_t)(ez1 - ez0);
+            }
+        }
+        const double* eps_in = g.eps;   // read once below, after admission; not kept
+        g.eps = nullptr;
+        nx = g.n[0];
+        ny = g.n[1];
+        nz = g.n[2];
+        K = o->steps_per_pass;
+        halo = K + 1;
+        // cores: nz split into ceil(nz / W) near-equal parts
+        const int nsl = (nz + o->slab_planes - 1) / o->slab_planes;
+        core.assign(nsl + 1, 0);
+        for (int s = 0; s < nsl; ++s) core[s + 1] = core[s] + nz / nsl + (s < nz % nsl ? 1 : 0);
+        const int lz0 = g.pml[4], lz1 = g.pml[5];
+        for (int s = 0; s < nsl; ++s) {
+            const int lo = ext_lo(s), hi = ext_hi(s);
+            if ((lo > 0 && lo < lz0) || (hi < nz && hi > nz - lz1)) {
+                char b[200];
+                snprintf(b, sizeof b, "slab %d spans planes [%d, %d), cutting an absorbing z face: slab_planes must "
+                                      "exceed the face depth plus steps_per_pass + 1", s, lo, hi);
+                return fail(FDTD_E_INVALID, b);
+            }
+        }
+        // monitors: each belongs to the slab whose core holds its plane
+        gm.assign(g.n_monitors, GMon{});
+        size_t moff = 0;
+        for (int q = 0; q < g.n_monitors; ++q) {
+            const fdtd_monitor_desc& md = g.monitors[q];
+            GMon& m = gm[q];
+            m.kind = md.kind == FDTD_MON_PROBE ? 0 : (md.kind == FDTD_MON_FLUX_Z ? 1 : 2);
+            m.k = md.pos[2];
+            m.slab = 0;
+            while (m.k >= core[m.slab + 1]) ++m.slab;
+            m.nf = m.kind ? md.n_freq : 0;
+            m.npts = m.kind ? (long long)(md.rect[1] - md.rect[0]) * (md.rect[3] - md.rect[2]) : 0;
+            m.elems = m.kind ? (size_t)m.nf * (m.kind == 1 ? 4 : 1) * m.npts * 2 : (size_t)std::max(1, so.max_steps);
+            moff = align256(moff) + m.elems * 8;
+            if (m.kind == 1) moff = align256(moff) + (size_t)m.nf * flux_blocks(m.npts) * 8 + 256 + (size_t)m.nf * 8;
+        }
+        dmon_bytes = align256(moff) + 256;
+        // global state arrays, in the slab handles' order
+        size_t off = 0;
+        auto add = [&](int kind, int c, int a, int side, int r, int w, int p, int z0, int z1, size_t per) {
+            GArr q{kind, c, a, side, r, w, p, z0, z1, per, off};
+            off += (size_t)(z1 - z0) * per;
+            ga.push_back(q);
+        };
+        for (int c = 0; c < 6; ++c) add(0, c, 0, 0, 0, 0, 0, 0, nz, (size_t)ny * pitch);
+        for (int a = 0; a < 3; ++a)
+            for (int side = 0; side < 2; ++side) {
+                const int L = g.pml[2 * a + side];
+                if (!L) continue;
+                for (int r = 0; r < 2; ++r)
+                    for (int kind = 1; kind <= 2; ++kind) {
+                        if (a == 0) add(kind, 0, a, side, r, 0, 0, 0, nz, (size_t)ny * L);
+                        else if (a == 1) add(kind, 0, a, side, r, 0, 0, 0, nz, (size_t)L * nx);
+                        else add(kind, 0, a, side, r, 0, 0, side ? nz - L : 0, side ? nz : L, (size_t)ny * nx);
+                    }
+            }
+        if (g.n_lorentz) {
+            const fdtd_lorentz_desc& L = g.lorentz;
+            const size_t per = (size_t)(L.hi[0] - L.lo[0]) * (L.hi[1] - L.lo[1]);
+            for (int w = 0; w < 3; ++w)
+                for (int c = 0; c < 3; ++c)
+                    for (int p = 0; p < (w == 0 ? 1 : npole); ++p) add(3, c, 0, 0, 0, w, p, L.lo[2], L.hi[2], per);
+        }
+        bank_elems = off;
+        // the workspace: the largest slab's pool
+        for (int s = 0; s < nsl; ++s) {
+            std::vector<int> lm;
+            fdtd_domain_desc d = slab_desc(s, lm);
+            Handle<T> sh;
+            sh.size_only = true;
+            sh.external_eps = true;
+            fdtd_options so2 = slab_options();
+            int rc = sh.create(&d, 1, &so2);
+            if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + sh.err);
+            pool_cap = std::max(pool_cap, sh.pool_bytes);
+        }
+        // admission: device workspace + accumulators, host banks
+        const double dev = (double)(pool_cap + dmon_bytes),
+                     host = 2.0 * bank_elems * sizeof(T) + (double)ebox * ncomp_eps * sizeof(T);
+        double budget = o->mem_budget_bytes;
+        if (budget <= 0) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(FDTD_E_DEVICE, "hipMemGetInfo failed");
+            budget = (double)fr - 256.0 * 1024 * 1024;
+        }
+        char b[240];
+        if (dev > budget) {
+            snprintf(b, sizeof b, "streamed workspace %.3e B exceeds the device budget %.3e B", dev, budget);
+            return fail(FDTD_E_NOMEM, b);
+        }
+        if (o->host_budget_bytes > 0 && host > o->host_budget_bytes) {
+            snprintf(b, sizeof b, "host state banks and eps^-1 %.3e B exceed the host budget %.3e B", host,
+                     o->host_budget_bytes);
+            return fail(FDTD_E_NOMEM, b);
+        }
+        if (ebox) {
+            // eps^-1 in the field type, as the resident upload computes it
+            if (hipHostMalloc((void**)&einv, ebox * ncomp_eps * sizeof(T), 0) != hipSuccess) {
+                (void)hipGetLastError();
+                einv = nullptr;
+                return fail(FDTD_E_NOMEM, "pinned host allocation of the material arrays failed");
+            }
+            if (ncomp_eps == 6) {
+                for (size_t q = 0; q < ebox; ++q) {
+                    double m[6], r[6];
+                    for (int c = 0; c < 6; ++c) m[c] = eps_in[c * ebox + q];
+                    sym3_inverse(m, r);
+                    for (int c = 0; c < 6; ++c) einv[c * ebox + q] = (T)r[c];
+                }
+            } else {
+                for (size_t q = 0; q < ebox * ncomp_eps; ++q) einv[q] = (T)(1.0 / eps_in[q]);
+            }
+        }
+        if (hipMalloc((void**)&pool, pool_cap) != hipSuccess || hipMalloc((void**)&dmon, dmon_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FDTD_E_NOMEM, "device allocation of the streamed workspace failed");
+        }
+        for (int k = 0; k < 2; ++k)
+            if (hipHostMalloc((void**)&bank[k], std::max<size_t>(bank_elems, 1) * sizeof(T), 0) != hipSuccess) {
+                (void)hipGetLastError();
+                bank[k] = nullptr;
+                return fail(FDTD_E_NOMEM, "pinned host allocation of the state banks failed");
+            }
+        moff = 0;
+        for (auto& m : gm) {
+            moff = align256(moff);
+            m.acc = (double*)(dmon + moff);
+            moff += m.elems * 8;
+            if (m.kind == 1) {
+                moff = align256(moff);
+                m.fpart = (double*)(dmon + moff);
+                moff += (size_t)m.nf * flux_blocks(m.npts) * 8;
+                moff = align256(moff);
+                m.fout = (double*)(dmon + moff);
+                moff += (size_t)m.nf * 8;
+            }
+        }
+        return reset();
+    }
+
+    int reset() override {
+        std::memset(bank[0], 0, bank_elems * sizeof(T));
+        std::memset(bank[1], 0, bank_elems * sizeof(T));
+        cb = 0;
+        t = 0;
+        launch_zero(dmon, dmon_bytes, st);
+        if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
+            return fail(FDTD_E_DEVICE, "stream reset failed");
+        return FDTD_OK;
+    }
+
+    // One slab's visit: load its extent at time t from bank cb, step n, store
+    // its core to the other bank, fold its monitors into the domain's.
+    int run_slab(int s, int n) {
+        const int o = ext_lo(s), e = ext_hi(s), c0 = core[s], c1 = core[s + 1];
+        std::vector<int> lm;
+        fdtd_domain_desc d = slab_desc(s, lm);
+        Handle<T> hd;
+        hd.external_eps = true;
+        hd.ext_pool = pool;
+        hd.ext_cap = pool_cap;
+        fdtd_options so2 = slab_options();
+        int rc = hd.create(&d, 1, &so2);
+        if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + hd.err);
+        hd.t = t;
+        const DomDev<T>& dv = hd.dd[0];
+        // eps^-1 of the slab's share of the eps box
+        if (ebox && dv.elo[2] < dv.ehi[2]) {
+            const int z0 = dv.elo[2] + o, z1 = dv.ehi[2] + o;
+            for (int c = 0; c < ncomp_eps; ++c) {
+                T* dst = ncomp_eps == 6 ? const_cast<T*>(dv.tinv[c]) : const_cast<T*>(dv.epsinv[c]);
+                const T* src = einv + c * ebox + (size_t)(z0 - ez0) * eplane;
+                if (hipMemcpyAsync(dst, src, (size_t)(z1 - z0) * eplane * sizeof(T), hipMemcpyHostToDevice, st) !=
+                    hipSuccess)
+                    return fail(FDTD_E_DEVICE, "slab eps upload failed");
+            }
+        }
+        // state at time t over the extent
+        for (const GArr& q : ga) {
+            int sz0, sz1;
+            T* p = slab_array(hd, q, o, e, sz0, sz1);
+            if (!p) continue;
+            T* dst = p + (size_t)slab_plane(q, sz0, o, sz0) * q.per;
+            const T* src = bank[cb] + q.off + (size_t)(sz0 - q.z0) * q.per;
+            if (hipMemcpyAsync(dst, src, (size_t)(sz1 - sz0) * q.per * sizeof(T), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return fail(FDTD_E_DEVICE, "slab state upload failed");
+        }
+        if ((rc = hd.step_forward(n, FDTD_RECORD))) return fail(rc, hd.err);
+        // the core at time t + n
+        for (const GArr& q : ga) {
+            int sz0, sz1;
+            T* p = slab_array(hd, q, o, e, sz0, sz1);
+            if (!p) continue;
+            const int z0 = std::max(sz0, c0), z1 = std::min(sz1, c1);
+            if (z1 <= z0) continue;
+            const T* src = p + (size_t)slab_plane(q, z0, o, sz0) * q.per;
+            T* dst = bank[cb ^ 1] + q.off + (size_t)(z0 - q.z0) * q.per;
+            if (hipMemcpyAsync(dst, src, (size_t)(z1 - z0) * q.per * sizeof(T), hipMemcpyDeviceToHost, st) !=
+                hipSuccess)
+                return fail(FDTD_E_DEVICE, "slab state download failed");
+        }
+        for (size_t li = 0; li < lm.size(); ++li) {
+            MonHost& mh = hd.dh[0].mons[li];
+            hd.flush(mh);
+            GMon& m = gm[lm[li]];
+            launch_add_f64(m.acc, m.kind ? mh.dev.acc : mh.dev.trace, m.elems, st);
+        }
+        if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
+            return fail(FDTD_E_DEVICE, "slab pass failed");
+        return FDTD_OK;
+    }
+
+    int step(int n) override {
+        if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
+        while (n > 0) {
+            const int kp = std::min(n, K);
+            for (int s = 0; s < ns(); ++s) {
+                int rc = run_slab(s, kp);
+                if (rc) return rc;
+            }
+            cb ^= 1;
+            t += kp;
+            n -= kp;
+        }
+        return FDTD_OK;
+    }
+
+    int get_field(int comp, void* buf, size_t bytes) override {
+        if (comp < 0 || comp > 5) return fail(FDTD_E_RANGE, "component");
+        if (bytes < (size_t)nx * ny * nz * sizeof(T)) return fail(FDTD_E_RANGE, "buffer too small for field");
+        const T* src = bank[cb] + ga[comp].off;
+        T* out = (T*)buf;
+        for (size_t r = 0; r < (size_t)ny * nz; ++r) std::memcpy(out + r * nx, src + r * pitch, nx * sizeof(T));
+        return FDTD_OK;
+    }
+
+    int monitor(int mon, int op, double* buf, size_t bytes) override {
+        if (mon < 0 || mon >= (int)gm.size()) return fail(FDTD_E_RANGE, "monitor index");
+        GMon& m = gm[mon];
+        if (op == FDTD_MON_GET) {
+            if (bytes < m.elems * 8 && m.kind) return fail(FDTD_E_RANGE, "buffer too small for spectra");
+            const size_t nb = std::min(bytes / 8, m.elems) * 8;
+            if (hipMemcpyAsync(buf, m.acc, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "monitor copy failed");
+            return FDTD_OK;
+        }
+        if (op == FDTD_MON_FLUX) {
+            if (m.kind != 1) return fail(FDTD_E_INVALID, "flux needs a flux monitor");
+            if (bytes < (size_t)m.nf * 8) return fail(FDTD_E_RANGE, "buffer too small for flux");
+            launch_flux(m.acc, m.nf, m.npts, m.fpart, m.fout, st);
+            if (hipMemcpyAsync(buf, m.fout, (size_t)m.nf * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, "flux failed");
+            return FDTD_OK;
+        }
+        return fail(FDTD_E_INVALID, "monitor op (GET or FLUX)");
+    }
+
+    void info(fdtd_stream_info* out) override {
+        out->n_slabs = ns();
+        out->halo = halo;
+        int mx = 0;
+        for (int s = 0; s < ns(); ++s) mx = std::max(mx, ext_hi(s) - ext_lo(s));
+        out->max_extent = mx;
+        out->step = t;
+        out->device_bytes = (double)(pool_cap + dmon_bytes);
+        out->host_bytes = 2.0 * bank_elems * sizeof(T) + (double)ebox * ncomp_eps * sizeof(T);
+        out->resident_bytes = resident_bytes;
+    }
+};
+
+}  // namespace
+
+struct fdtd_stream_s {
+    std::unique_ptr<StreamBase> impl;
+};
+
 struct fdtd_s {
     std::unique_ptr<Base> impl;
 };
@@ -1868,6 +2382,91 @@ int fdtd_flux_reduce_noalloc(const double* spectra, int32_t n_freq, int64_t n_pt
         return FDTD_E_DEVICE;
     }
     return FDTD_OK;
+}
+
+// ---------------------------------------------------------------- streamed
+namespace {
+int sguard(fdtd_stream_t h) {
+    if (!h || !h->impl) return FDTD_E_INVALID;
+    if (h->impl->poisoned) return FDTD_E_DEVICE;
+    return FDTD_OK;
+}
+}  // namespace
+
+#define SGUARD(h)               \
+    do {                        \
+        int _g = sguard(h);     \
+        if (_g) return _g;      \
+    } while (0)
+
+int fdtd_stream_create(const fdtd_domain_desc* domain, const fdtd_stream_options* opt, fdtd_stream_t* out) {
+    if (!out) return FDTD_E_INVALID;
+    *out = nullptr;
+    if (!domain || !opt) {
+        g_create_error = "null descriptor or options";
+        return FDTD_E_INVALID;
+    }
+    if (opt->dtype != FDTD_F32 && opt->dtype != FDTD_F64) {
+        g_create_error = "dtype must be FDTD_F32 or FDTD_F64";
+        return FDTD_E_INVALID;
+    }
+    std::unique_ptr<fdtd_stream_s> h(new fdtd_stream_s);
+    int rc;
+    if (opt->dtype == FDTD_F32) {
+        auto* p = new Streamer<float>();
+        h->impl.reset(p);
+        rc = p->create(domain, opt);
+    } else {
+        auto* p = new Streamer<double>();
+        h->impl.reset(p);
+        rc = p->create(domain, opt);
+    }
+    if (rc) {
+        g_create_error = h->impl->err;
+        return rc;
+    }
+    *out = h.release();
+    return FDTD_OK;
+}
+
+int fdtd_stream_destroy(fdtd_stream_t h) {
+    if (!h) return FDTD_E_INVALID;
+    delete h;
+    return FDTD_OK;
+}
+
+int fdtd_stream_step(fdtd_stream_t h, int32_t n_steps) {
+    SGUARD(h);
+    return h->impl->step(n_steps);
+}
+
+int fdtd_stream_get_field(fdtd_stream_t h, int32_t comp, void* host_buf, size_t bytes) {
+    SGUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->get_field(comp, host_buf, bytes);
+}
+
+int fdtd_stream_monitor(fdtd_stream_t h, int32_t monitor, int32_t op, double* host_buf, size_t bytes) {
+    SGUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->monitor(monitor, op, host_buf, bytes);
+}
+
+int fdtd_stream_reset(fdtd_stream_t h) {
+    SGUARD(h);
+    return h->impl->reset();
+}
+
+int fdtd_stream_get_info(fdtd_stream_t h, fdtd_stream_info* out) {
+    SGUARD(h);
+    if (!out) return FDTD_E_INVALID;
+    h->impl->info(out);
+    return FDTD_OK;
+}
+
+const char* fdtd_stream_last_error(fdtd_stream_t h) {
+    if (!h || !h->impl) return g_create_error.c_str();
+    return h->impl->err.c_str();
 }
 
 const char* fdtd_last_error(fdtd_t h) {

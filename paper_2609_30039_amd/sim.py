@@ -140,3 +140,62 @@ class Simulation:
 
     def memory_bytes(self) -> float:
         return B.fdtd_get_memory(self.h)
+
+
+class StreamedSimulation:
+    """One domain advanced by host-streamed causal slabs (the libfdtd
+    fdtd_stream_* calls): its state in pinned host banks, slabs of at most
+    ``slab_planes`` z planes stepped ``steps_per_pass`` steps per visit in a
+    device workspace."""
+
+    def __init__(self, spec, slab_planes: int, steps_per_pass: int, dtype: str = "f32",
+                 max_steps: Optional[int] = None, tile_rows: int = 0, tile_kz: int = 0,
+                 stream: Optional[int] = None, mem_budget_bytes: float = 0.0, host_budget_bytes: float = 0.0):
+        self.spec = spec
+        self.dtype = np.float32 if dtype == "f32" else np.float64
+        self.max_steps = max(spec.n_steps, 1) if max_steps is None else max_steps
+        self.h = B.fdtd_stream_create(spec, B.FDTD_F32 if dtype == "f32" else B.FDTD_F64, slab_planes,
+                                      steps_per_pass, self.max_steps, tile_rows, tile_kz, stream,
+                                      mem_budget_bytes, host_budget_bytes)
+
+    def close(self):
+        if self.h is not None:
+            B.fdtd_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        B.fdtd_stream_step(self.h, n)
+
+    def reset(self):
+        B.fdtd_stream_reset(self.h)
+
+    def info(self) -> dict:
+        return B.fdtd_stream_get_info(self.h)
+
+    def field(self, comp: int) -> np.ndarray:
+        nx, ny, nz = self.spec.shape
+        out = np.empty((nz, ny, nx), dtype=self.dtype)
+        B.fdtd_stream_get_field(self.h, comp, out)
+        return out
+
+    def spectra(self, monitor: int) -> np.ndarray:
+        m = self.spec.monitors[monitor]
+        if m.kind == "probe":
+            out = np.zeros(self.max_steps)
+            B.fdtd_stream_monitor(self.h, monitor, B.FDTD_MON_GET, out)
+            return out
+        i0, i1, j0, j1 = m.rect
+        buf = np.zeros((len(m.omega_dt), 4 if m.kind == "flux_z" else 1, j1 - j0, i1 - i0, 2))
+        B.fdtd_stream_monitor(self.h, monitor, B.FDTD_MON_GET, buf)
+        return buf[..., 0] + 1j * buf[..., 1]
+
+    def flux(self, monitor: int) -> np.ndarray:
+        out = np.zeros(len(self.spec.monitors[monitor].omega_dt))
+        B.fdtd_stream_monitor(self.h, monitor, B.FDTD_MON_FLUX, out)
+        return out

@@ -245,3 +245,36 @@ def test_tensor_media_combinations_refused():
     _refused(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID)
     _refused(_tensor_spec(m, pml=(0, 0, 0, 0, 3, 3), periodic=(1, 0, 0)), B.FDTD_E_INVALID)
     _refused(_tensor_spec(m), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
+
+
+def _stream_refused(spec, code, **kw):
+    args = dict(dtype=B.FDTD_F32, slab_planes=16, steps_per_pass=4, max_steps=10, mem_budget_bytes=1e12,
+                host_budget_bytes=1e12)
+    args.update(kw)
+    with pytest.raises(B.FdtdError) as e:
+        B.fdtd_stream_create(spec, **args)
+    assert e.value.code == code, str(e.value)
+    return str(e.value)
+
+
+def test_stream_admission():
+    """Host-streamed slabs: the domain is validated as a resident handle
+    would be, a gradient is refused (forward only), a slab whose extent would
+    cut an absorbing z face is refused, and the device workspace and the host
+    banks are admitted against their budgets before anything is allocated."""
+    spec = W.lorentz_flux(pml=6, lorentz=8, n_steps=10, n_f=2, shape=(24, 20, 60))
+    _stream_refused(spec, B.FDTD_E_INVALID, slab_planes=0)
+    _stream_refused(spec, B.FDTD_E_INVALID, steps_per_pass=0)
+    g = W.lorentz_flux(pml=6, lorentz=8, n_steps=10, n_f=2, shape=(24, 20, 60))
+    g.grad_box = ((8, 8, 8), (16, 12, 40))
+    _stream_refused(g, B.FDTD_E_INVALID)
+    # cores of 8 planes, halo 5: slab 1 starts at plane 3, cutting the low face
+    msg = _stream_refused(spec, B.FDTD_E_INVALID, slab_planes=8, steps_per_pass=4)
+    assert "absorbing z face" in msg
+    bad = W.lorentz_flux(pml=6, lorentz=8, n_steps=10, n_f=2, shape=(24, 20, 60))
+    bad.courant = 0.995 / np.sqrt(3.0)
+    _stream_refused(bad, B.FDTD_E_UNSTABLE)
+    msg = _stream_refused(spec, B.FDTD_E_NOMEM, mem_budget_bytes=1e5)
+    assert "device budget" in msg
+    msg = _stream_refused(spec, B.FDTD_E_NOMEM, host_budget_bytes=1e5)
+    assert "host budget" in msg

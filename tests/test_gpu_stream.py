@@ -1,0 +1,134 @@
+"""Host-streamed causal slabs (Section 4.2) on the GPU.
+
+The domain's state lives in host banks; slabs of z planes are stepped K
+steps at a time in a device workspace with K + 1 halo planes per cut side.
+Every core plane must equal the resident solution bit for bit (same kernels,
+same operands), in FP64 and FP32, and therefore the oracle's; so must the
+probe traces, and the spectra up to the order of their FP64 time sums, with
+monitor planes next to and on the cuts.  Covered: absorbing faces
+on every side, a diagonal eps box and a two-pole dispersive box across cuts,
+sources in halos, a flux plane on a core's first plane, a pass shorter than
+K, one slab, tensor media, Bloch-periodic x and y.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_30039_amd import workloads as W
+from paper_2609_30039_amd.sim import Simulation, StreamedSimulation
+from tests.gpu_util import rel
+from tests.test_gpu_periodic import _periodic_spec
+from tests.test_gpu_tensor import tensor_spec
+
+pytestmark = pytest.mark.gpu
+
+
+def stream_spec(n_steps=57):
+    """30 x 26 x 70, 6 absorbing cells on every face, diagonal eps over the
+    interior, a Lorentz + Drude box over z in [20, 45), an Ex sheet at k = 9
+    and an Ez point at k = 27, a flux plane at k = 42, an Ey patch at k = 30,
+    an Hx probe at k = 55."""
+    nx, ny, nz = 30, 26, 70
+    rng = np.random.Generator(np.random.PCG64(51))
+    lo, hi = (6, 6, 6), (nx - 6, ny - 6, nz - 6)
+    eps = 1.0 + 3.0 * rng.random((3, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]))
+    poles = [W.PoleSpec("lorentz", 1.2, 0.35, 0.02), W.PoleSpec("drude", 0.0, 0.2, 0.05)]
+    return W.DomainSpec(
+        shape=(nx, ny, nz), courant=W.courant_3d(), pml=(6,) * 6, eps_kind="diag", eps_box=(lo, hi), eps=eps,
+        lorentz=[W.LorentzSpec((8, 7, 20), (20, 18, 45), 0.0, 0.0, 0.0, poles=poles)],
+        sources=[W.SourceSpec("plane_z", 0, (0, 0, 9), W.gaussian_sine(n_steps, 0.3, 10.0, 30.0)),
+                 W.SourceSpec("point", 2, (15, 13, 27), W.gaussian_sine(n_steps, 0.5, 6.0, 20.0))],
+        monitors=[W.MonitorSpec("flux_z", pos=(0, 0, 42), rect=(6, 24, 6, 20), omega_dt=W.freq_grid(4, 0.2, 0.5)),
+                  W.MonitorSpec("patch_z", comp=1, pos=(0, 0, 30), rect=(3, 27, 2, 24),
+                                omega_dt=W.freq_grid(3, 0.2, 0.4)),
+                  W.MonitorSpec("probe", comp=3, pos=(12, 10, 55))],
+        n_steps=n_steps)
+
+
+def _resident(spec, dtype):
+    g = Simulation(spec, dtype=dtype, kernel="split")
+    g.step(spec.n_steps)
+    out = ([g.field(q) for q in range(6)], [g.spectra(m) for m in range(len(spec.monitors))])
+    fl = [g.flux(m) for m, mm in enumerate(spec.monitors) if mm.kind == "flux_z"]
+    g.close()
+    return out, fl
+
+
+def _streamed(spec, dtype, W_, K_):
+    s = StreamedSimulation(spec, W_, K_, dtype=dtype)
+    s.step(spec.n_steps)
+    out = ([s.field(q) for q in range(6)], [s.spectra(m) for m in range(len(spec.monitors))])
+    fl = [s.flux(m) for m, mm in enumerate(spec.monitors) if mm.kind == "flux_z"]
+    info = s.info()
+    s.close()
+    return out, fl, info
+
+
+def _equal(a, b, label):
+    """Fields and probe traces bit for bit.  Spectra and flux to 1e-14: their
+    FP64 time sums are folded per pass here and per 32-sample block in the
+    resident run, so the rounding order differs."""
+    (fa, sa), fla = a
+    (fb, sb), flb = b
+    for q in range(6):
+        assert np.array_equal(fa[q], fb[q]), (label, "field", q, rel(fa[q], fb[q]))
+    for m in range(len(sa)):
+        if sa[m].dtype == np.float64:
+            assert np.array_equal(sa[m], sb[m]), (label, "probe", m)
+        else:
+            assert rel(sa[m], sb[m]) < 1e-14, (label, "monitor", m, rel(sa[m], sb[m]))
+    for x, y in zip(fla, flb):
+        assert rel(x, y) < 1e-14, (label, "flux", rel(x, y))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("W_,K_", [(14, 5), (20, 3), (70, 8)])
+def test_streamed_equals_resident_bitwise(dtype, W_, K_):
+    spec = stream_spec()
+    res = _resident(spec, dtype)
+    out, fl, info = _streamed(spec, dtype, W_, K_)
+    print(f"streamed {dtype} W={W_} K={K_}: {info}", flush=True)
+    assert info["step"] == spec.n_steps and info["halo"] == K_ + 1
+    if W_ < 70:
+        assert info["n_slabs"] > 1 and info["device_bytes"] < info["resident_bytes"]
+    _equal((out, fl), res, f"{dtype} W={W_} K={K_}")
+
+
+def test_streamed_matches_oracle():
+    spec = stream_spec()
+    out, fl, _ = _streamed(spec, "f64", 14, 5)
+    o = O.OracleSim(spec)
+    o.step(spec.n_steps)
+    for q in range(6):
+        assert rel(out[0][q], o.field(q)) < 1e-11
+    for m in range(3):
+        assert rel(out[1][m], o.spectra(m)) < 1e-11
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_streamed_tensor_and_periodic_bitwise(dtype):
+    """Tensor media with admitted tensors in the absorbing faces, and a
+    Bloch-periodic cell, each streamed in three slabs."""
+    for spec, W_, K_ in ((tensor_spec(faces=True), 12, 3), (_periodic_spec((-1, 1)), 10, 2)):
+        res = _resident(spec, dtype)
+        out, fl, info = _streamed(spec, dtype, W_, K_)
+        assert info["n_slabs"] == 3
+        _equal((out, fl), res, f"{dtype} {spec.eps_kind} periodic={spec.periodic}")
+
+
+def test_streamed_reset_and_continue():
+    """Two calls of 30 and 27 steps, and a reset followed by the whole run,
+    give the single run's state."""
+    spec = stream_spec()
+    res = _resident(spec, "f64")
+    s = StreamedSimulation(spec, 14, 5, dtype="f64")
+    s.step(30)
+    s.step(27)
+    a = [s.field(q) for q in range(6)]
+    s.reset()
+    assert s.info()["step"] == 0 and not np.any(s.field(0))
+    s.step(spec.n_steps)
+    b = [s.field(q) for q in range(6)]
+    s.close()
+    for q in range(6):
+        assert np.array_equal(a[q], res[0][0][q]) and np.array_equal(b[q], res[0][0][q])
