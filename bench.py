@@ -26,7 +26,9 @@ Alongside, on the same JSON line:
     gradient against the oracle's stored record; the 48-domain ragged batch;
     the 148^3 workload with 3 and 16 poles;
   * tensor_536: the 536^3 domain with a rotated symmetric tensor at every
-    interior node (the two-pass tensor E update), FP32 forward.
+    interior node (the two-pass tensor E update), FP32 forward;
+  * streamed_536: the headline workload through host-streamed causal slabs
+    (state in host memory, 64-plane slabs, 32 steps per visit).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--no-adjoint] [--shape K,R,Z]
 """
@@ -566,6 +568,37 @@ def tensor_536(stream):
             "inputs_s": round(t1 - t0, 1), "create_s": round(t2 - t1, 1)}
 
 
+def streamed_536(stream):
+    """Host-streamed causal slabs on the 536^3 workload: slabs of 64 core
+    planes, K = 32 steps per visit (33 halo planes per cut), FP32 forward
+    over two passes (64 steps), against the resident stepping rate."""
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd.sim import StreamedSimulation
+    spec = W.anisotropic_lorentz()
+    spec.grad_box = None          # forward only
+    Wp, Kp, passes = 64, 32, 2
+    t0 = time.perf_counter()
+    s = StreamedSimulation(spec, Wp, Kp, dtype="f32", stream=stream, tile_rows=8, tile_kz=8)
+    t1 = time.perf_counter()
+    s.step(Kp)                    # warm-up pass
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.step(passes * Kp)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t2
+    info = s.info()
+    s.close()
+    mc = spec.ncells * passes * Kp / el / 1e6
+    log(f"streamed_536: {mc:.0f} Mcell-upd/s, {info}")
+    return {"workload": "536^3 anisotropic workload streamed: z slabs of <= 64 core planes, K = 32 steps per visit, "
+                        "33 halo planes per cut, FP32 forward, state in two pinned host banks",
+            "mcups": round(mc, 1), "s_per_pass": round(el / passes, 3), "create_s": round(t1 - t0, 2),
+            "n_slabs": info["n_slabs"], "max_extent_planes": info["max_extent"],
+            "device_bytes": info["device_bytes"], "host_bytes": info["host_bytes"],
+            "resident_bytes": info["resident_bytes"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -601,6 +634,7 @@ def main():
         out["batch_48"] = batch_48(stream)
         out["several_poles"] = several_poles(stream, out["cache_resident_148"]["launch_shape"])
         out["tensor_536"] = tensor_536(stream)
+        out["streamed_536"] = streamed_536(stream)
     out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 

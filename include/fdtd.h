@@ -371,6 +371,8 @@ typedef struct {
     void *stream;                  /* hipStream_t; NULL = default stream */
     double mem_budget_bytes;       /* device budget (0: free memory) */
     double host_budget_bytes;      /* pinned host budget for the banks and eps^-1 (0: unchecked) */
+    int32_t overlap;               /* 1: two workspaces on two streams, so that one slab's transfers run
+                                      beside the other slab's steps (twice the device workspace) */
 } fdtd_stream_options;
 
 typedef struct {
@@ -381,6 +383,8 @@ typedef struct {
     double device_bytes;           /* workspace + monitor accumulators */
     double host_bytes;             /* pinned: two state banks + eps^-1 */
     double resident_bytes;         /* what the resident handle of the same domain would allocate */
+    int32_t materials_resident;    /* 1: eps^-1 is kept on the device (the budget held it beside the
+                                      workspaces); 0: each visit uploads its planes from pinned memory */
 } fdtd_stream_info;
 
 typedef struct fdtd_stream_s *fdtd_stream_t;

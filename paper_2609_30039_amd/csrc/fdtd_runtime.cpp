@@ -1710,11 +1710,17 @@ struct Streamer : StreamBase {
     // eps^-1 of the domain in the field type over its eps box, per component
     // (tensor: six), pinned, uploaded plane-range by plane-range per slab
     T* einv = nullptr;
+    T* d_einv = nullptr;                        // a device copy of einv when the budget holds it
     size_t ebox = 0;
     int ez0 = 0, ez1 = 0;
     size_t eplane = 0;
-    char* pool = nullptr;
+    // workspaces: one, or two (overlap) so that one slab's transfers run
+    // beside the other's steps, each with its own stream and slab handle
+    int nws = 1;
+    char* pool[2] = {nullptr, nullptr};
     size_t pool_cap = 0;
+    hipStream_t wst[2] = {nullptr, nullptr};
+    std::unique_ptr<Handle<T>> hs[2];
     // monitor accumulators of the domain on the device: spectra or the probe trace
     struct GMon {
         int kind, nf, k, slab;
@@ -1729,9 +1735,14 @@ struct Streamer : StreamBase {
     static inline double dummy_eps = 1.0;
 
     ~Streamer() override {
+        for (int k = 0; k < 2; ++k) hs[k].reset();
         if (st) (void)hipStreamSynchronize(st);
-        if (pool) (void)hipFree(pool);
+        for (int k = 0; k < 2; ++k) {
+            if (wst[k]) (void)hipStreamDestroy(wst[k]);
+            if (pool[k]) (void)hipFree(pool[k]);
+        }
         if (dmon) (void)hipFree(dmon);
+        if (d_einv) (void)hipFree(d_einv);
         for (int b = 0; b < 2; ++b)
             if (bank[b]) (void)hipHostFree(bank[b]);
         if (einv) (void)hipHostFree(einv);
@@ -1952,8 +1963,9 @@ struct Streamer : StreamBase {
             if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + sh.err);
             pool_cap = std::max(pool_cap, sh.pool_bytes);
         }
-        // admission: device workspace + accumulators, host banks
-        const double dev = (double)(pool_cap + dmon_bytes),
+        // admission: device workspaces + accumulators, host banks
+        nws = o->overlap ? 2 : 1;
+        const double dev = (double)(nws * pool_cap + dmon_bytes),
                      host = 2.0 * bank_elems * sizeof(T) + (double)ebox * ncomp_eps * sizeof(T);
         double budget = o->mem_budget_bytes;
         if (budget <= 0) {
@@ -1989,9 +2001,26 @@ struct Streamer : StreamBase {
                 for (size_t q = 0; q < ebox * ncomp_eps; ++q) einv[q] = (T)(1.0 / eps_in[q]);
             }
         }
-        if (hipMalloc((void**)&pool, pool_cap) != hipSuccess || hipMalloc((void**)&dmon, dmon_bytes) != hipSuccess) {
+        for (int k = 0; k < nws; ++k)
+            if (hipMalloc((void**)&pool[k], pool_cap) != hipSuccess ||
+                hipStreamCreateWithFlags(&wst[k], hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(FDTD_E_NOMEM, "device allocation of the streamed workspace failed");
+            }
+        if (hipMalloc((void**)&dmon, dmon_bytes) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(FDTD_E_NOMEM, "device allocation of the streamed workspace failed");
+            return fail(FDTD_E_NOMEM, "device allocation of the monitor accumulators failed");
+        }
+        // eps^-1 stays on the device when the budget holds it beside the
+        // workspaces: each visit then copies its planes device to device
+        const size_t ebytes = ebox * ncomp_eps * sizeof(T);
+        if (ebox && dev + (double)ebytes <= budget) {
+            if (hipMalloc((void**)&d_einv, ebytes) != hipSuccess) {
+                (void)hipGetLastError();
+                d_einv = nullptr;
+            } else if (hipMemcpy(d_einv, einv, ebytes, hipMemcpyHostToDevice) != hipSuccess) {
+                return fail(FDTD_E_DEVICE, "eps^-1 upload failed");
+            }
         }
         for (int k = 0; k < 2; ++k)
             if (hipHostMalloc((void**)&bank[k], std::max<size_t>(bank_elems, 1) * sizeof(T), 0) != hipSuccess) {
@@ -2017,6 +2046,7 @@ struct Streamer : StreamBase {
     }
 
     int reset() override {
+        if (int rc = drain()) return rc;
         std::memset(bank[0], 0, bank_elems * sizeof(T));
         std::memset(bank[1], 0, bank_elems * sizeof(T));
         cb = 0;
@@ -2027,17 +2057,34 @@ struct Streamer : StreamBase {
         return FDTD_OK;
     }
 
-    // One slab's visit: load its extent at time t from bank cb, step n, store
-    // its core to the other bank, fold its monitors into the domain's.
+    // Waits for both workspaces and releases their slab handles.
+    int drain() {
+        for (int k = 0; k < 2; ++k) hs[k].reset();   // a handle's destructor waits for its stream
+        for (int k = 0; k < nws; ++k)
+            if (wst[k] && hipStreamSynchronize(wst[k]) != hipSuccess) return fail(FDTD_E_DEVICE, "slab stream failed");
+        if (hipGetLastError() != hipSuccess) return fail(FDTD_E_DEVICE, "slab pass failed");
+        return FDTD_OK;
+    }
+
+    // One slab's visit, queued on its workspace's stream: load its extent at
+    // time t from bank cb, step n, store its core to the other bank, fold its
+    // monitors into the domain's.  The previous slab of that workspace is
+    // waited for (its handle released) first; the other workspace's slab keeps
+    // running meanwhile.
     int run_slab(int s, int n) {
         const int o = ext_lo(s), e = ext_hi(s), c0 = core[s], c1 = core[s + 1];
+        const int w = s % nws;
+        hs[w].reset();
         std::vector<int> lm;
         fdtd_domain_desc d = slab_desc(s, lm);
-        Handle<T> hd;
+        hs[w].reset(new Handle<T>());
+        Handle<T>& hd = *hs[w];
         hd.external_eps = true;
-        hd.ext_pool = pool;
+        hd.ext_pool = pool[w];
         hd.ext_cap = pool_cap;
         fdtd_options so2 = slab_options();
+        so2.stream = wst[w];
+        hipStream_t st = wst[w];
         int rc = hd.create(&d, 1, &so2);
         if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + hd.err);
         hd.t = t;
@@ -2047,9 +2094,9 @@ struct Streamer : StreamBase {
             const int z0 = dv.elo[2] + o, z1 = dv.ehi[2] + o;
             for (int c = 0; c < ncomp_eps; ++c) {
                 T* dst = ncomp_eps == 6 ? const_cast<T*>(dv.tinv[c]) : const_cast<T*>(dv.epsinv[c]);
-                const T* src = einv + c * ebox + (size_t)(z0 - ez0) * eplane;
-                if (hipMemcpyAsync(dst, src, (size_t)(z1 - z0) * eplane * sizeof(T), hipMemcpyHostToDevice, st) !=
-                    hipSuccess)
+                const size_t q0 = c * ebox + (size_t)(z0 - ez0) * eplane;
+                if (hipMemcpyAsync(dst, d_einv ? d_einv + q0 : einv + q0, (size_t)(z1 - z0) * eplane * sizeof(T),
+                                   d_einv ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st) != hipSuccess)
                     return fail(FDTD_E_DEVICE, "slab eps upload failed");
             }
         }
@@ -2084,8 +2131,7 @@ struct Streamer : StreamBase {
             GMon& m = gm[lm[li]];
             launch_add_f64(m.acc, m.kind ? mh.dev.acc : mh.dev.trace, m.elems, st);
         }
-        if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
-            return fail(FDTD_E_DEVICE, "slab pass failed");
+        if (hipGetLastError() != hipSuccess) return fail(FDTD_E_DEVICE, "slab launch failed");
         return FDTD_OK;
     }
 
@@ -2095,8 +2141,12 @@ struct Streamer : StreamBase {
             const int kp = std::min(n, K);
             for (int s = 0; s < ns(); ++s) {
                 int rc = run_slab(s, kp);
-                if (rc) return rc;
+                if (rc) {
+                    drain();
+                    return rc;
+                }
             }
+            if (int rc = drain()) return rc;   // bank B complete before it is read
             cb ^= 1;
             t += kp;
             n -= kp;
@@ -2143,9 +2193,10 @@ struct Streamer : StreamBase {
         for (int s = 0; s < ns(); ++s) mx = std::max(mx, ext_hi(s) - ext_lo(s));
         out->max_extent = mx;
         out->step = t;
-        out->device_bytes = (double)(pool_cap + dmon_bytes);
+        out->device_bytes = (double)(nws * pool_cap + dmon_bytes) + (d_einv ? (double)ebox * ncomp_eps * sizeof(T) : 0.0);
         out->host_bytes = 2.0 * bank_elems * sizeof(T) + (double)ebox * ncomp_eps * sizeof(T);
         out->resident_bytes = resident_bytes;
+        out->materials_resident = d_einv ? 1 : 0;
     }
 };
 

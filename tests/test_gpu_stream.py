@@ -54,8 +54,8 @@ def _resident(spec, dtype):
     return out, fl
 
 
-def _streamed(spec, dtype, W_, K_):
-    s = StreamedSimulation(spec, W_, K_, dtype=dtype)
+def _streamed(spec, dtype, W_, K_, overlap=True, budget=0.0):
+    s = StreamedSimulation(spec, W_, K_, dtype=dtype, overlap=overlap, mem_budget_bytes=budget)
     s.step(spec.n_steps)
     out = ([s.field(q) for q in range(6)], [s.spectra(m) for m in range(len(spec.monitors))])
     fl = [s.flux(m) for m, mm in enumerate(spec.monitors) if mm.kind == "flux_z"]
@@ -92,6 +92,25 @@ def test_streamed_equals_resident_bitwise(dtype, W_, K_):
     if W_ < 70:
         assert info["n_slabs"] > 1 and info["device_bytes"] < info["resident_bytes"]
     _equal((out, fl), res, f"{dtype} W={W_} K={K_}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_streamed_one_workspace_bitwise(dtype):
+    """Without the second workspace (slabs strictly one after another) the
+    result is the same, in half the device workspace."""
+    spec = stream_spec()
+    res = _resident(spec, dtype)
+    out, fl, info = _streamed(spec, dtype, 14, 5, overlap=False)
+    _, _, info2 = _streamed(spec, dtype, 14, 5, overlap=True)
+    assert info["device_bytes"] < info2["device_bytes"]
+    _equal((out, fl), res, f"{dtype} one workspace")
+    # a budget that leaves no room for eps^-1 on the device: each visit uploads it
+    word = 8 if dtype == "f64" else 4
+    eps_bytes = spec.eps.size * word
+    assert info["materials_resident"] == 1
+    out, fl, info3 = _streamed(spec, dtype, 14, 5, overlap=False, budget=info["device_bytes"] - eps_bytes)
+    assert info3["materials_resident"] == 0
+    _equal((out, fl), res, f"{dtype} eps^-1 streamed")
 
 
 def test_streamed_matches_oracle():
