@@ -28,7 +28,9 @@ Alongside, on the same JSON line:
   * tensor_536: the 536^3 domain with a rotated symmetric tensor at every
     interior node (the two-pass tensor E update), FP32 forward;
   * streamed_536: the headline workload through host-streamed causal slabs
-    (state in host memory, 64-plane slabs, 32 steps per visit).
+    (state in host memory, 64-plane slabs, 32 steps per visit);
+  * streamed_adjoint_256: resident against streamed time to gradient and
+    device memory on a matched 256^3 adjoint of 128 steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--no-adjoint] [--shape K,R,Z]
 """
@@ -599,6 +601,53 @@ def streamed_536(stream):
             "resident_bytes": info["resident_bytes"]}
 
 
+def streamed_adjoint_256(stream):
+    """The memory-time trade-off of host streaming on a matched 256^3 adjoint
+    (the paper's protocol: 128 steps, two checkpoints for the resident run):
+    |DFT Ez|^2 of a patch, dJ/deps over a 128^3 design box.  Resident: two
+    binomial checkpoint slots; streamed: 64-plane slabs, K = 32 (a forward
+    bank per 32 steps in host memory).  Both FP32, from construction to the
+    gradient on the host."""
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import adjoint as A
+    from paper_2609_30039_amd.sim import Simulation, StreamedSimulation
+    spec, _ = W.design_patch(interior=236, pml=10, design=128, patch=32, n_steps=128, n_f=8)
+    N = spec.n_steps
+    tile = {"kernel": "split", "tile_rows": 8, "tile_kz": 8}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim = Simulation(spec, dtype="f32", n_ckpt=2, stream=stream, **tile)
+    plan = A.RevolvePlan(N, 2)
+    last = A.forward_record(sim, plan)
+    sim.set_cotangent(0, 2.0 * sim.spectra(0))
+    A.reverse_sweep(sim, plan, *last)
+    g_res = sim.grad(0)[0]
+    t1 = time.perf_counter()
+    dev_res = sim.memory_bytes()
+    sim.close()
+    t2 = time.perf_counter()
+    st_ = StreamedSimulation(spec, 64, 32, dtype="f32", stream=stream, **{k: v for k, v in tile.items() if k != "kernel"})
+    st_.step(N)
+    st_.set_cotangent(0, 2.0 * st_.spectra(0))
+    st_.reverse()
+    g_str = st_.grad()[0]
+    t3 = time.perf_counter()
+    info = st_.info()
+    st_.close()
+    r = float(np.linalg.norm(g_str - g_res) / np.linalg.norm(g_res))
+    log(f"streamed_adjoint_256: resident {t1 - t0:.2f} s ({dev_res / 1e9:.2f} GB), streamed {t3 - t2:.2f} s "
+        f"({info['device_bytes'] / 1e9:.2f} GB device, {info['host_bytes'] / 1e9:.2f} GB host), grad rel {r:.2e}")
+    return {"workload": "256^3 (236^3 + 10-cell CPML), 128^3 design box eps in [1,6], |DFT Ez|^2 on a 32x32 "
+                        "patch, 8 frequencies, 128 steps, FP32; resident with 2 binomial slots (forward "
+                        f"evaluations {plan.forward_evals + 1}), streamed with 64-plane slabs and K = 32",
+            "resident_s": round(t1 - t0, 3), "streamed_s": round(t3 - t2, 3),
+            "streamed_over_resident": round((t3 - t2) / (t1 - t0), 2),
+            "resident_device_bytes": dev_res, "streamed_device_bytes": info["device_bytes"],
+            "streamed_host_bytes": info["host_bytes"], "n_slabs": info["n_slabs"],
+            "grad_rel_l2_streamed_vs_resident": float(f"{r:.3e}")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -635,6 +684,7 @@ def main():
         out["several_poles"] = several_poles(stream, out["cache_resident_148"]["launch_shape"])
         out["tensor_536"] = tensor_536(stream)
         out["streamed_536"] = streamed_536(stream)
+        out["streamed_adjoint_256"] = streamed_adjoint_256(stream)
     out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 

@@ -352,8 +352,11 @@ const char *fdtd_last_error(fdtd_t h);
 
    Supported: everything the resident forward path supports on the domain
    (scalar, diagonal or tensor eps, a dispersive box, absorbing faces on every
-   side, periodic x/y, sources, probe and plane monitors), forward only: a
-   descriptor with grad set is refused (FDTD_E_INVALID).  An absorbing z face
+   side, periodic x/y, sources, probe and plane monitors), and with grad set
+   the reverse sweep (fdtd_stream_reverse) over the same slabs.  With a
+   gradient the host keeps one forward bank per pass boundary (bank j holds
+   time j K; ceil(max_steps / K) + 1 banks) and two cotangent banks, and
+   passes are exactly K steps except the last one.  An absorbing z face
    must lie wholly inside or wholly outside each slab's extent: a slab that
    would cut one is refused (FDTD_E_INVALID; raise slab_planes).  Monitors
    belong to the slab whose core holds their plane; their spectra and probe
@@ -403,6 +406,22 @@ int fdtd_stream_get_field(fdtd_stream_t h, int32_t comp, void *host_buf, size_t 
 int fdtd_stream_monitor(fdtd_stream_t h, int32_t monitor, int32_t op, double *host_buf, size_t bytes);
 /* Back to time 0: state and monitors zeroed. */
 int fdtd_stream_reset(fdtd_stream_t h);
+/* Cotangent dJ/d(observation) of monitor `monitor` (layout of
+   FDTD_MON_SET_COTANGENT), kept until replaced; FDTD_E_STATE without grad. */
+int fdtd_stream_set_cotangent(fdtd_stream_t h, int32_t monitor, const double *host_buf, size_t bytes);
+/* Reverse sweep (Eq. 3, Section 3.1) over the forward steps done since the
+   reset, block by block from the last: each slab replays its block from the
+   block's starting bank with every state kept in the workspace, runs the
+   transposed steps from the cotangent state at the block's end (loaded over
+   its extent, seeded by every monitor whose plane the extent holds), and
+   returns its core's cotangent state and dJ/deps.  The gradient equals the
+   resident sweep's up to the order of its FP64 sums.  FDTD_E_STATE without
+   grad or without forward steps. */
+int fdtd_stream_reverse(fdtd_stream_t h);
+/* dJ/deps of the last reverse sweep over the gradient box, double
+   [ncomp][gz][gy][gx] as fdtd_get_grad; FDTD_E_STATE if the forward has
+   moved since or no sweep ran. */
+int fdtd_stream_get_grad(fdtd_stream_t h, double *host_buf, size_t bytes);
 int fdtd_stream_get_info(fdtd_stream_t h, fdtd_stream_info *out);
 /* Message of the last failing call on h (NULL: of a failing create). */
 const char *fdtd_stream_last_error(fdtd_stream_t h);

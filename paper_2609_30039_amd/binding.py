@@ -36,7 +36,8 @@ EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_be
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
             "fdtd_flux_reduce", "fdtd_flux_reduce_noalloc", "fdtd_last_error",
             "fdtd_stream_create", "fdtd_stream_destroy", "fdtd_stream_step", "fdtd_stream_get_field",
-            "fdtd_stream_monitor", "fdtd_stream_reset", "fdtd_stream_get_info", "fdtd_stream_last_error"]
+            "fdtd_stream_monitor", "fdtd_stream_reset", "fdtd_stream_get_info", "fdtd_stream_last_error",
+            "fdtd_stream_set_cotangent", "fdtd_stream_reverse", "fdtd_stream_get_grad"]
 
 FDTD_FLUX_POINTS_PER_BLOCK, FDTD_FLUX_MAX_BLOCKS = 4096, 256
 FDTD_FLUX_SCRATCH_BYTES = 65536
@@ -157,6 +158,9 @@ def lib():
         L.fdtd_stream_monitor.argtypes = [vp, i32, i32, vp, sz]
         L.fdtd_stream_reset.argtypes = [vp]
         L.fdtd_stream_get_info.argtypes = [vp, C.POINTER(StreamInfo)]
+        L.fdtd_stream_set_cotangent.argtypes = [vp, i32, vp, sz]
+        L.fdtd_stream_reverse.argtypes = [vp]
+        L.fdtd_stream_get_grad.argtypes = [vp, vp, sz]
         L.fdtd_stream_last_error.argtypes = [vp]
         L.fdtd_stream_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -421,3 +425,16 @@ def fdtd_stream_get_info(h) -> dict:
     i = StreamInfo()
     _schk(lib().fdtd_stream_get_info(h, C.byref(i)), h)
     return {k: getattr(i, k) for k, _ in StreamInfo._fields_}
+
+
+def fdtd_stream_set_cotangent(h, monitor: int, buf: np.ndarray):
+    buf = np.ascontiguousarray(buf, dtype=np.float64)
+    return _schk(lib().fdtd_stream_set_cotangent(h, monitor, buf.ctypes.data, buf.nbytes), h)
+
+
+def fdtd_stream_reverse(h):
+    return _schk(lib().fdtd_stream_reverse(h), h)
+
+
+def fdtd_stream_get_grad(h, out: np.ndarray):
+    return _schk(lib().fdtd_stream_get_grad(h, out.ctypes.data, out.nbytes), h)

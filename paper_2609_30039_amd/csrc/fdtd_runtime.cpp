@@ -1685,6 +1685,9 @@ struct StreamBase {
     virtual int monitor(int mon, int op, double* buf, size_t bytes) = 0;
     virtual int reset() = 0;
     virtual void info(fdtd_stream_info* o) = 0;
+    virtual int set_cotangent(int mon, const double* buf, size_t bytes) = 0;
+    virtual int reverse() = 0;
+    virtual int get_grad(double* buf, size_t bytes) = 0;
 };
 
 template <typename T>
@@ -1705,8 +1708,20 @@ struct Streamer : StreamBase {
     };
     std::vector<GArr> ga;
     size_t bank_elems = 0;
-    T* bank[2] = {nullptr, nullptr};
-    int cb = 0;                                 // bank holding the state at time t
+    // Forward banks.  Forward only: two, ping-ponged (cb holds time t).  With
+    // a gradient: one per pass boundary, bank j holding time j K, so that the
+    // reverse sweep finds every block's starting state; passes are then K
+    // steps long except a last, shorter one.
+    bool adj = false;
+    std::vector<T*> bank;
+    int cb = 0;
+    T* abank[2] = {nullptr, nullptr};           // cotangent state banks of the reverse sweep
+    std::vector<double> grad;                   // dJ/deps over the gradient box [ncomp][gz][gy][gx]
+    int gncomp = 1;
+    size_t gelems = 0;
+    std::vector<std::vector<double>> cots;      // monitor cotangents (host copies)
+    std::vector<char> cot_set;
+    int grad_step = -1;                         // the forward length the gradient was taken over
     // eps^-1 of the domain in the field type over its eps box, per component
     // (tensor: six), pinned, uploaded plane-range by plane-range per slab
     T* einv = nullptr;
@@ -1743,8 +1758,10 @@ struct Streamer : StreamBase {
         }
         if (dmon) (void)hipFree(dmon);
         if (d_einv) (void)hipFree(d_einv);
+        for (T* b : bank)
+            if (b) (void)hipHostFree(b);
         for (int b = 0; b < 2; ++b)
-            if (bank[b]) (void)hipHostFree(bank[b]);
+            if (abank[b]) (void)hipHostFree(abank[b]);
         if (einv) (void)hipHostFree(einv);
     }
 
@@ -1758,8 +1775,9 @@ struct Streamer : StreamBase {
     int ext_lo(int s) const { return std::max(0, core[s] - (s > 0 ? halo : 0)); }
     int ext_hi(int s) const { return std::min(nz, core[s + 1] + (s + 1 < ns() ? halo : 0)); }
 
-    fdtd_options slab_options() const {
+    fdtd_options slab_options(int n_ckpt = 0) const {
         fdtd_options o{};
+        o.n_ckpt = n_ckpt;
         o.dtype = so.dtype;
         o.max_steps = so.max_steps;
         o.kernel = FDTD_KERNEL_SPLIT;
@@ -1774,7 +1792,7 @@ struct Streamer : StreamBase {
     // z faces it contains, the eps and dispersive boxes clipped to it, the
     // sources in it and the monitors whose plane lies in its core (lmon:
     // their indices in the domain's list).
-    fdtd_domain_desc slab_desc(int s, std::vector<int>& lmon) const {
+    fdtd_domain_desc slab_desc(int s, std::vector<int>& lmon, bool reverse = false) const {
         const int o = ext_lo(s), e = ext_hi(s);
         fdtd_domain_desc d = g;
         d.n[2] = e - o;
@@ -1804,41 +1822,72 @@ struct Streamer : StreamBase {
             x = sr;
             x.pos[2] = sr.pos[2] - o;
         }
+        // forward: the monitors whose plane lies in the core (they record);
+        // reverse: every monitor whose plane lies in the extent, since its
+        // seeds enter the cotangent state wherever the extent holds its plane
         d.n_monitors = 0;
         lmon.clear();
         for (int q = 0; q < g.n_monitors; ++q) {
-            if (gm[q].slab != s) continue;
+            const int k = g.monitors[q].pos[2];
+            if (reverse ? (k < o || k >= e) : gm[q].slab != s) continue;
             fdtd_monitor_desc& x = d.monitors[d.n_monitors++];
             x = g.monitors[q];
-            x.pos[2] = g.monitors[q].pos[2] - o;
+            x.pos[2] = k - o;
             lmon.push_back(q);
         }
-        d.grad = 0;
+        d.grad = reverse ? 1 : 0;
+        if (reverse) {   // the gradient box clipped to the extent (possibly empty)
+            d.grad_lo[2] = std::min(std::max(g.grad_lo[2], o), e) - o;
+            d.grad_hi[2] = std::max(std::min(g.grad_hi[2], e) - o, d.grad_lo[2]);
+        }
         return d;
     }
 
     // device address of the slab handle's copy of global array q and the
     // first global plane it holds (nullptr: the slab does not hold it)
-    T* slab_array(Handle<T>& hd, const GArr& q, int o, int e, int& sz0, int& sz1) const {
+    // (cot: the cotangent copy, in the handle's adjoint set aset)
+    T* slab_array(Handle<T>& hd, const GArr& q, int o, int e, int& sz0, int& sz1, bool cot = false,
+                  int aset = 0) const {
         const DomDev<T>& d = hd.dd[0];
         sz0 = std::max(q.z0, o);
         sz1 = std::min(q.z1, e);
         if (sz1 <= sz0) return nullptr;
+        const long long so = cot ? (long long)aset * d.as : 0;
         switch (q.kind) {
             case 0:
-                return q.c < 3 ? d.E[q.c] : d.H[q.c - 3];
+                return (cot ? (q.c < 3 ? d.Ea[q.c] : d.Ha[q.c - 3]) : (q.c < 3 ? d.E[q.c] : d.H[q.c - 3])) + so;
             case 1:
             case 2: {
                 if (q.a == 2 && ((q.side == 0 && o != 0) || (q.side == 1 && e != nz))) return nullptr;
-                T* p = q.kind == 1 ? d.psiE[q.a][q.side][q.r] : d.psiH[q.a][q.side][q.r];
-                return p;
+                if (cot) return (q.kind == 1 ? d.psiEa[q.a][q.side][q.r] : d.psiHa[q.a][q.side][q.r]) + so;
+                return q.kind == 1 ? d.psiE[q.a][q.side][q.r] : d.psiH[q.a][q.side][q.r];
             }
             default: {
                 if (!d.has_lor) return nullptr;
                 const long long lbox = d.lbox;
-                return d.lor[q.w][q.c] + (long long)q.p * lbox;
+                return (cot ? d.lora[q.w][q.c] + so : d.lor[q.w][q.c]) + (long long)q.p * lbox;
             }
         }
+    }
+
+    // copies of the state arrays between a host bank and the slab handle:
+    // up: the extent [o, e) into the handle; down: planes [c0, c1) to the bank
+    int xfer(Handle<T>& hd, T* hbank, bool up, int o, int e, int c0, int c1, hipStream_t st, bool cot = false,
+             int aset = 0) {
+        for (const GArr& q : ga) {
+            int sz0, sz1;
+            T* p = slab_array(hd, q, o, e, sz0, sz1, cot, aset);
+            if (!p) continue;
+            const int z0 = up ? sz0 : std::max(sz0, c0), z1 = up ? sz1 : std::min(sz1, c1);
+            if (z1 <= z0) continue;
+            T* dv = p + (size_t)slab_plane(q, z0, o, sz0) * q.per;
+            T* hv = hbank + q.off + (size_t)(z0 - q.z0) * q.per;
+            const size_t nb = (size_t)(z1 - z0) * q.per * sizeof(T);
+            if (hipMemcpyAsync(up ? (void*)dv : (void*)hv, up ? (const void*)hv : (const void*)dv, nb,
+                               up ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost, st) != hipSuccess)
+                return fail(FDTD_E_DEVICE, up ? "slab state upload failed" : "slab state download failed");
+        }
+        return FDTD_OK;
     }
 
     // the plane of the slab array holding global plane z
@@ -1854,7 +1903,8 @@ struct Streamer : StreamBase {
         st = (hipStream_t)o->stream;
         if (o->slab_planes < 1 || o->steps_per_pass < 1 || o->max_steps < 0)
             return fail(FDTD_E_INVALID, "slab_planes and steps_per_pass must be >= 1, max_steps >= 0");
-        if (g.grad) return fail(FDTD_E_INVALID, "the streamed path is forward only: no gradient");
+        adj = g.grad != 0;
+        if (adj && o->max_steps < 1) return fail(FDTD_E_INVALID, "a streamed gradient needs max_steps >= 1");
         // admission of the domain itself: validate it as a resident handle would, without allocating
         {
             Handle<T> gh;
@@ -1864,6 +1914,8 @@ struct Streamer : StreamBase {
             if (rc) return fail(rc, gh.err);
             resident_bytes = (double)gh.pool_bytes;
             pitch = gh.dd[0].pitch;
+            gncomp = gh.dh[0].gncomp;
+            gelems = gh.dh[0].gelems;
             ncomp_eps = gh.dh[0].ncomp_eps;
             npole = gh.dd[0].has_lor ? gh.dd[0].npole : 0;
             // keep the waveforms and frequencies: the descriptor's pointers are the caller's
@@ -1951,22 +2003,27 @@ struct Streamer : StreamBase {
                     for (int p = 0; p < (w == 0 ? 1 : npole); ++p) add(3, c, 0, 0, 0, w, p, L.lo[2], L.hi[2], per);
         }
         bank_elems = off;
-        // the workspace: the largest slab's pool
-        for (int s = 0; s < nsl; ++s) {
-            std::vector<int> lm;
-            fdtd_domain_desc d = slab_desc(s, lm);
-            Handle<T> sh;
-            sh.size_only = true;
-            sh.external_eps = true;
-            fdtd_options so2 = slab_options();
-            int rc = sh.create(&d, 1, &so2);
-            if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + sh.err);
-            pool_cap = std::max(pool_cap, sh.pool_bytes);
-        }
+        // the workspace: the largest slab's pool, forward or (with a gradient)
+        // reverse, where a block's K forward states are kept for its K
+        // transposed steps
+        for (int rev = 0; rev <= (adj ? 1 : 0); ++rev)
+            for (int s = 0; s < nsl; ++s) {
+                std::vector<int> lm;
+                fdtd_domain_desc d = slab_desc(s, lm, rev != 0);
+                Handle<T> sh;
+                sh.size_only = true;
+                sh.external_eps = true;
+                fdtd_options so2 = slab_options(rev ? K : 0);
+                int rc = sh.create(&d, 1, &so2);
+                if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + sh.err);
+                pool_cap = std::max(pool_cap, sh.pool_bytes);
+            }
+        const int nbank = adj ? (so.max_steps + K - 1) / K + 1 : 2;
         // admission: device workspaces + accumulators, host banks
         nws = o->overlap ? 2 : 1;
         const double dev = (double)(nws * pool_cap + dmon_bytes),
-                     host = 2.0 * bank_elems * sizeof(T) + (double)ebox * ncomp_eps * sizeof(T);
+                     host = (double)(nbank + (adj ? 2 : 0)) * bank_elems * sizeof(T) +
+                            (double)ebox * ncomp_eps * sizeof(T) + (adj ? 8.0 * gncomp * gelems : 0.0);
         double budget = o->mem_budget_bytes;
         if (budget <= 0) {
             size_t fr = 0, tot = 0;
@@ -2022,12 +2079,20 @@ struct Streamer : StreamBase {
                 return fail(FDTD_E_DEVICE, "eps^-1 upload failed");
             }
         }
-        for (int k = 0; k < 2; ++k)
-            if (hipHostMalloc((void**)&bank[k], std::max<size_t>(bank_elems, 1) * sizeof(T), 0) != hipSuccess) {
+        bank.assign(nbank, nullptr);
+        for (int k = 0; k < nbank + (adj ? 2 : 0); ++k) {
+            T*& b = k < nbank ? bank[k] : abank[k - nbank];
+            if (hipHostMalloc((void**)&b, std::max<size_t>(bank_elems, 1) * sizeof(T), 0) != hipSuccess) {
                 (void)hipGetLastError();
-                bank[k] = nullptr;
+                b = nullptr;
                 return fail(FDTD_E_NOMEM, "pinned host allocation of the state banks failed");
             }
+        }
+        if (adj) {
+            grad.assign((size_t)gncomp * gelems, 0.0);
+            cots.resize(g.n_monitors);
+            cot_set.assign(g.n_monitors, 0);
+        }
         moff = 0;
         for (auto& m : gm) {
             moff = align256(moff);
@@ -2047,10 +2112,10 @@ struct Streamer : StreamBase {
 
     int reset() override {
         if (int rc = drain()) return rc;
-        std::memset(bank[0], 0, bank_elems * sizeof(T));
-        std::memset(bank[1], 0, bank_elems * sizeof(T));
+        std::memset(bank[0], 0, bank_elems * sizeof(T));   // the state at time 0; later banks are written whole
         cb = 0;
         t = 0;
+        grad_step = -1;
         launch_zero(dmon, dmon_bytes, st);
         if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess)
             return fail(FDTD_E_DEVICE, "stream reset failed");
@@ -2071,7 +2136,7 @@ struct Streamer : StreamBase {
     // monitors into the domain's.  The previous slab of that workspace is
     // waited for (its handle released) first; the other workspace's slab keeps
     // running meanwhile.
-    int run_slab(int s, int n) {
+    int run_slab(int s, int n, T* src_bank, T* dst_bank) {
         const int o = ext_lo(s), e = ext_hi(s), c0 = core[s], c1 = core[s + 1];
         const int w = s % nws;
         hs[w].reset();
@@ -2100,31 +2165,10 @@ struct Streamer : StreamBase {
                     return fail(FDTD_E_DEVICE, "slab eps upload failed");
             }
         }
-        // state at time t over the extent
-        for (const GArr& q : ga) {
-            int sz0, sz1;
-            T* p = slab_array(hd, q, o, e, sz0, sz1);
-            if (!p) continue;
-            T* dst = p + (size_t)slab_plane(q, sz0, o, sz0) * q.per;
-            const T* src = bank[cb] + q.off + (size_t)(sz0 - q.z0) * q.per;
-            if (hipMemcpyAsync(dst, src, (size_t)(sz1 - sz0) * q.per * sizeof(T), hipMemcpyHostToDevice, st) !=
-                hipSuccess)
-                return fail(FDTD_E_DEVICE, "slab state upload failed");
-        }
+        // state at time t over the extent, n steps, the core at time t + n
+        if ((rc = xfer(hd, src_bank, true, o, e, c0, c1, st))) return rc;
         if ((rc = hd.step_forward(n, FDTD_RECORD))) return fail(rc, hd.err);
-        // the core at time t + n
-        for (const GArr& q : ga) {
-            int sz0, sz1;
-            T* p = slab_array(hd, q, o, e, sz0, sz1);
-            if (!p) continue;
-            const int z0 = std::max(sz0, c0), z1 = std::min(sz1, c1);
-            if (z1 <= z0) continue;
-            const T* src = p + (size_t)slab_plane(q, z0, o, sz0) * q.per;
-            T* dst = bank[cb ^ 1] + q.off + (size_t)(z0 - q.z0) * q.per;
-            if (hipMemcpyAsync(dst, src, (size_t)(z1 - z0) * q.per * sizeof(T), hipMemcpyDeviceToHost, st) !=
-                hipSuccess)
-                return fail(FDTD_E_DEVICE, "slab state download failed");
-        }
+        if ((rc = xfer(hd, dst_bank, false, o, e, c0, c1, st))) return rc;
         for (size_t li = 0; li < lm.size(); ++li) {
             MonHost& mh = hd.dh[0].mons[li];
             hd.flush(mh);
@@ -2135,29 +2179,160 @@ struct Streamer : StreamBase {
         return FDTD_OK;
     }
 
+    // bank holding the state at time t
+    int cur_bank() const { return adj ? (t + K - 1) / K : cb; }
+
     int step(int n) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
+        if (adj && n > 0 && (t % K != 0 || t + n > so.max_steps))
+            return fail(FDTD_E_STATE, "with a gradient, passes are K steps long except the last one, within "
+                                      "max_steps");
         while (n > 0) {
             const int kp = std::min(n, K);
+            T* src = bank[cur_bank()];
+            T* dst = bank[adj ? t / K + 1 : cb ^ 1];
             for (int s = 0; s < ns(); ++s) {
-                int rc = run_slab(s, kp);
+                int rc = run_slab(s, kp, src, dst);
                 if (rc) {
                     drain();
                     return rc;
                 }
             }
-            if (int rc = drain()) return rc;   // bank B complete before it is read
+            if (int rc = drain()) return rc;   // the next bank complete before it is read
             cb ^= 1;
             t += kp;
             n -= kp;
         }
+        grad_step = -1;
+        return FDTD_OK;
+    }
+
+    // ---------------------------------------------------------- reverse sweep
+    // The transposed steps are local like the forward ones (each reads its
+    // neighbours one plane away, in the other direction), so the same slabs
+    // and halos serve the reverse sweep, block by block from the last: for
+    // each slab, the block's starting state (bank j) is replayed forward K
+    // steps in the workspace with every state kept, the cotangent state at
+    // the block's end is loaded over the extent, and K transposed steps run
+    // with the monitor seeds of every monitor plane in the extent; the core's
+    // cotangent state goes to the other cotangent bank and the core's dJ/deps
+    // is added to the domain's.  The forward states and cotangents of the
+    // core are exact, so its gradient terms are those of the resident sweep.
+    int set_cotangent(int mon, const double* buf, size_t bytes) override {
+        if (!adj) return fail(FDTD_E_STATE, "the domain takes no gradient");
+        if (mon < 0 || mon >= (int)gm.size()) return fail(FDTD_E_RANGE, "monitor index");
+        const size_t ne = gm[mon].elems;
+        if (gm[mon].kind && bytes < ne * 8) return fail(FDTD_E_RANGE, "buffer too small for cotangents");
+        cots[mon].assign(ne, 0.0);
+        std::memcpy(cots[mon].data(), buf, std::min(bytes / 8, ne) * 8);
+        cot_set[mon] = 1;
+        return FDTD_OK;
+    }
+
+    int run_slab_reverse(int s, int t0, int kb, int N, T* fstart, T* cot_in, T* cot_out) {
+        const int o = ext_lo(s), e = ext_hi(s), c0 = core[s], c1 = core[s + 1];
+        const int w = s % nws;
+        hs[w].reset();
+        std::vector<int> lm;
+        fdtd_domain_desc d = slab_desc(s, lm, true);
+        hs[w].reset(new Handle<T>());
+        Handle<T>& hd = *hs[w];
+        hd.external_eps = true;
+        hd.ext_pool = pool[w];
+        hd.ext_cap = pool_cap;
+        fdtd_options so2 = slab_options(K);
+        so2.stream = wst[w];
+        hipStream_t st = wst[w];
+        int rc = hd.create(&d, 1, &so2);
+        if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + hd.err);
+        hd.t = t0;
+        const DomDev<T>& dv = hd.dd[0];
+        if (ebox && dv.elo[2] < dv.ehi[2]) {
+            const int z0 = dv.elo[2] + o, z1 = dv.ehi[2] + o;
+            for (int c = 0; c < ncomp_eps; ++c) {
+                T* dst = ncomp_eps == 6 ? const_cast<T*>(dv.tinv[c]) : const_cast<T*>(dv.epsinv[c]);
+                const size_t q0 = c * ebox + (size_t)(z0 - ez0) * eplane;
+                if (hipMemcpyAsync(dst, d_einv ? d_einv + q0 : einv + q0, (size_t)(z1 - z0) * eplane * sizeof(T),
+                                   d_einv ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "slab eps upload failed");
+            }
+        }
+        // the block's forward states u^t0 .. u^{t0+kb-1}, each kept in a slot
+        if ((rc = xfer(hd, fstart, true, o, e, c0, c1, st))) return rc;
+        for (int j = 0; j < kb; ++j) {
+            if ((rc = hd.ckpt_save(j))) return fail(rc, hd.err);
+            if ((rc = hd.step_forward(1, FDTD_REPLAY))) return fail(rc, hd.err);
+        }
+        // cotangent state at t0 + kb (its seeds included), then kb transposed steps
+        hd.ap = 0;
+        hd.m = t0 + kb;
+        if ((rc = xfer(hd, cot_in, true, o, e, c0, c1, st, true, 0))) return rc;
+        for (size_t li = 0; li < lm.size(); ++li) {
+            if (!cot_set[lm[li]]) continue;
+            std::vector<double>& cv = cots[lm[li]];
+            if ((rc = hd.monitor(0, (int)li, FDTD_MON_SET_COTANGENT, cv.data(), cv.size() * 8)))
+                return fail(rc, hd.err);
+        }
+        if (t0 + kb == N && (rc = hd.seed(N))) return fail(rc, hd.err);
+        for (int j = kb - 1; j >= 0; --j) {
+            if ((rc = hd.ckpt_restore(j))) return fail(rc, hd.err);
+            if ((rc = hd.step_adjoint(1))) return fail(rc, hd.err);
+        }
+        if ((rc = xfer(hd, cot_out, false, o, e, c0, c1, st, true, hd.ap))) return rc;
+        // dJ/deps of the core's gradient planes, added to the domain's on the host
+        const int gz0 = std::max(g.grad_lo[2], c0), gz1 = std::min(g.grad_hi[2], c1);
+        if (gz1 > gz0 && gelems) {
+            const size_t gpl = (size_t)(g.grad_hi[0] - g.grad_lo[0]) * (g.grad_hi[1] - g.grad_lo[1]);
+            std::vector<double> tmp((size_t)(gz1 - gz0) * gpl);
+            const int lz0 = dv.glo[2] + o;   // the slab's gradient box starts at this plane
+            for (int c = 0; c < gncomp; ++c) {
+                if (hipMemcpyAsync(tmp.data(), dv.gacc[c] + (size_t)(gz0 - lz0) * gpl, tmp.size() * 8,
+                                   hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    return fail(FDTD_E_DEVICE, "gradient download failed");
+                double* gg = grad.data() + c * gelems + (size_t)(gz0 - g.grad_lo[2]) * gpl;
+                for (size_t q = 0; q < tmp.size(); ++q) gg[q] += tmp[q];
+            }
+        }
+        if (hipGetLastError() != hipSuccess) return fail(FDTD_E_DEVICE, "slab launch failed");
+        return FDTD_OK;
+    }
+
+    int reverse() override {
+        if (!adj) return fail(FDTD_E_STATE, "the domain takes no gradient");
+        const int N = t;
+        if (N < 1) return fail(FDTD_E_STATE, "no forward steps to reverse");
+        std::fill(grad.begin(), grad.end(), 0.0);
+        std::memset(abank[0], 0, bank_elems * sizeof(T));
+        int ab = 0;
+        for (int j = (N - 1) / K; j >= 0; --j) {
+            const int t0 = j * K, kb = std::min(K, N - t0);
+            for (int s = 0; s < ns(); ++s) {
+                int rc = run_slab_reverse(s, t0, kb, N, bank[j], abank[ab], abank[ab ^ 1]);
+                if (rc) {
+                    drain();
+                    return rc;
+                }
+            }
+            if (int rc = drain()) return rc;
+            ab ^= 1;
+        }
+        grad_step = N;
+        return FDTD_OK;
+    }
+
+    int get_grad(double* buf, size_t bytes) override {
+        if (!adj) return fail(FDTD_E_STATE, "the domain takes no gradient");
+        if (grad_step < 0) return fail(FDTD_E_STATE, "no reverse sweep since the last forward steps");
+        if (bytes < grad.size() * 8) return fail(FDTD_E_RANGE, "buffer too small for the gradient");
+        std::memcpy(buf, grad.data(), grad.size() * 8);
         return FDTD_OK;
     }
 
     int get_field(int comp, void* buf, size_t bytes) override {
         if (comp < 0 || comp > 5) return fail(FDTD_E_RANGE, "component");
         if (bytes < (size_t)nx * ny * nz * sizeof(T)) return fail(FDTD_E_RANGE, "buffer too small for field");
-        const T* src = bank[cb] + ga[comp].off;
+        const T* src = bank[cur_bank()] + ga[comp].off;
         T* out = (T*)buf;
         for (size_t r = 0; r < (size_t)ny * nz; ++r) std::memcpy(out + r * nx, src + r * pitch, nx * sizeof(T));
         return FDTD_OK;
@@ -2501,6 +2676,23 @@ int fdtd_stream_monitor(fdtd_stream_t h, int32_t monitor, int32_t op, double* ho
     SGUARD(h);
     if (!host_buf) return FDTD_E_INVALID;
     return h->impl->monitor(monitor, op, host_buf, bytes);
+}
+
+int fdtd_stream_set_cotangent(fdtd_stream_t h, int32_t monitor, const double* host_buf, size_t bytes) {
+    SGUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->set_cotangent(monitor, host_buf, bytes);
+}
+
+int fdtd_stream_reverse(fdtd_stream_t h) {
+    SGUARD(h);
+    return h->impl->reverse();
+}
+
+int fdtd_stream_get_grad(fdtd_stream_t h, double* host_buf, size_t bytes) {
+    SGUARD(h);
+    if (!host_buf) return FDTD_E_INVALID;
+    return h->impl->get_grad(host_buf, bytes);
 }
 
 int fdtd_stream_reset(fdtd_stream_t h) {

@@ -200,3 +200,28 @@ class StreamedSimulation:
         out = np.zeros(len(self.spec.monitors[monitor].omega_dt))
         B.fdtd_stream_monitor(self.h, monitor, B.FDTD_MON_FLUX, out)
         return out
+
+    def set_cotangent(self, monitor: int, g: np.ndarray):
+        m = self.spec.monitors[monitor]
+        if m.kind == "probe":
+            buf = np.zeros(self.max_steps)
+            g = np.asarray(g, dtype=np.float64).ravel()
+            buf[:len(g)] = g[:self.max_steps]
+        else:
+            i0, i1, j0, j1 = m.rect
+            shape = (len(m.omega_dt), 4 if m.kind == "flux_z" else 1, j1 - j0, i1 - i0)
+            g = np.asarray(g, dtype=np.complex128).reshape(shape)
+            buf = np.ascontiguousarray(np.stack([g.real, g.imag], axis=-1))
+        B.fdtd_stream_set_cotangent(self.h, monitor, buf)
+
+    def reverse(self):
+        """The reverse sweep over the forward steps done since the reset."""
+        B.fdtd_stream_reverse(self.h)
+
+    def grad(self) -> np.ndarray:
+        s = self.spec
+        lo, hi = s.grad_box
+        nc = 3 if s.eps_kind == "diag" else 1
+        out = np.zeros((nc, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]))
+        B.fdtd_stream_get_grad(self.h, out)
+        return out

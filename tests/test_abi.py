@@ -259,7 +259,7 @@ def _stream_refused(spec, code, **kw):
 
 def test_stream_admission():
     """Host-streamed slabs: the domain is validated as a resident handle
-    would be, a gradient is refused (forward only), a slab whose extent would
+    would be, a gradient needs max_steps, a slab whose extent would
     cut an absorbing z face is refused, and the device workspace and the host
     banks are admitted against their budgets before anything is allocated."""
     spec = W.lorentz_flux(pml=6, lorentz=8, n_steps=10, n_f=2, shape=(24, 20, 60))
@@ -267,7 +267,10 @@ def test_stream_admission():
     _stream_refused(spec, B.FDTD_E_INVALID, steps_per_pass=0)
     g = W.lorentz_flux(pml=6, lorentz=8, n_steps=10, n_f=2, shape=(24, 20, 60))
     g.grad_box = ((8, 8, 8), (16, 12, 40))
-    _stream_refused(g, B.FDTD_E_INVALID)
+    _stream_refused(g, B.FDTD_E_INVALID, max_steps=0)          # a gradient needs the step count
+    # with a gradient the host keeps a bank per pass boundary: 10 steps of 4 -> 4 banks + 2 cotangent banks
+    msg = _stream_refused(g, B.FDTD_E_NOMEM, host_budget_bytes=5.5 * 24 * 20 * 60 * 4 * 6)
+    assert "host budget" in msg
     # cores of 8 planes, halo 5: slab 1 starts at plane 3, cutting the low face
     msg = _stream_refused(spec, B.FDTD_E_INVALID, slab_planes=8, steps_per_pass=4)
     assert "absorbing z face" in msg

@@ -151,3 +151,82 @@ def test_streamed_reset_and_continue():
     s.close()
     for q in range(6):
         assert np.array_equal(a[q], res[0][0][q]) and np.array_equal(b[q], res[0][0][q])
+
+
+def _cot(mi, m, sp):
+    """Cotangents of J = sum |patch|^2 + sum Re flux + 1/2 sum probe^2."""
+    if m.kind == "probe":
+        return sp
+    if m.kind == "flux_z":
+        g = np.zeros_like(sp)
+        g[:, 0], g[:, 3], g[:, 1], g[:, 2] = sp[:, 3], sp[:, 0], -sp[:, 2], -sp[:, 1]
+        return g
+    return 2.0 * sp
+
+
+def grad_spec():
+    spec = stream_spec()
+    spec.grad_box = ((6, 6, 6), (24, 20, 64))   # the interior, across every cut
+    return spec
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-9)])
+@pytest.mark.parametrize("W_,K_,overlap", [(14, 5, True), (20, 3, False)])
+def test_streamed_gradient_equals_resident(dtype, tol, W_, K_, overlap):
+    """dJ/deps by the streamed reverse sweep (blocks of K steps, slabs with
+    K + 1 halo planes, the seeds of a flux plane on a core's first plane, a
+    patch and a probe) against the resident sweep over stored states."""
+    from tests.gpu_util import gpu_gradient_store_all
+    spec = grad_spec()
+    N = spec.n_steps
+    _, g_res, _ = gpu_gradient_store_all(spec, dtype, _cot, kernel="split")
+    s = StreamedSimulation(spec, W_, K_, dtype=dtype, overlap=overlap)
+    s.step(N)
+    for mi, m in enumerate(spec.monitors):
+        s.set_cotangent(mi, _cot(mi, m, s.spectra(mi)[:N] if m.kind == "probe" else s.spectra(mi)))
+    s.reverse()
+    g = s.grad()
+    r = rel(g, g_res)
+    print(f"streamed gradient {dtype} W={W_} K={K_} overlap={overlap}: rel L2 vs resident {r:.3e}", flush=True)
+    assert r < tol
+    assert np.abs(g).max() > 0
+    s.close()
+
+
+def test_streamed_gradient_matches_oracle():
+    from tests.gpu_util import oracle_gradient
+    spec = grad_spec()
+    N = spec.n_steps
+    s = StreamedSimulation(spec, 14, 5, dtype="f64")
+    s.step(N)
+    for mi, m in enumerate(spec.monitors):
+        s.set_cotangent(mi, _cot(mi, m, s.spectra(mi)[:N] if m.kind == "probe" else s.spectra(mi)))
+    s.reverse()
+    g = s.grad()
+    _, g_orc = oracle_gradient(spec, _cot)
+    (i0, j0, k0), (i1, j1, k1) = spec.grad_box
+    r = rel(g, g_orc[:, k0:k1, j0:j1, i0:i1])
+    print(f"streamed gradient f64 vs oracle {r:.3e}", flush=True)
+    assert r < 1e-10
+
+
+def test_streamed_gradient_state_rules():
+    """Passes of K steps with a gradient; the gradient is gone once the
+    forward moves; no sweep without forward steps."""
+    from paper_2609_30039_amd import binding as B
+    spec = grad_spec()
+    s = StreamedSimulation(spec, 14, 5, dtype="f32")
+    with pytest.raises(B.FdtdError) as e:
+        s.reverse()
+    assert e.value.code == B.FDTD_E_STATE
+    s.step(7)                                   # 5 + 2: the last pass is the short one
+    with pytest.raises(B.FdtdError) as e:
+        s.step(3)
+    assert e.value.code == B.FDTD_E_STATE
+    s.reverse()
+    s.grad()
+    s.reset()
+    with pytest.raises(B.FdtdError) as e:
+        s.grad()
+    assert e.value.code == B.FDTD_E_STATE
+    s.close()
