@@ -605,14 +605,16 @@ def streamed_adjoint_256(stream):
     """The memory-time trade-off of host streaming on a matched 256^3 adjoint
     (the paper's protocol: 128 steps, two checkpoints for the resident run):
     |DFT Ez|^2 of a patch, dJ/deps over a 128^3 design box.  Resident: two
-    binomial checkpoint slots; streamed: 64-plane slabs, K = 32 (a forward
-    bank per 32 steps in host memory).  Both FP32, from construction to the
-    gradient on the host."""
+    binomial checkpoint slots; streamed: 64-plane slabs, K = 16 (a forward
+    bank per 16 steps in host memory), one workspace, 4 local slots per
+    block.  Both FP32, from construction to the gradient on the host."""
     import torch
     from paper_2609_30039_amd import workloads as W
     from paper_2609_30039_amd import adjoint as A
     from paper_2609_30039_amd.sim import Simulation, StreamedSimulation
     spec, _ = W.design_patch(interior=236, pml=10, design=128, patch=32, n_steps=128, n_f=8)
+    # the patch where the 128-step pulse has arrived: 60 planes past the sheet source
+    spec.monitors[0].pos = (0, 0, spec.sources[0].pos[2] + 60)
     N = spec.n_steps
     tile = {"kernel": "split", "tile_rows": 8, "tile_kz": 8}
     torch.cuda.synchronize()
@@ -627,7 +629,8 @@ def streamed_adjoint_256(stream):
     dev_res = sim.memory_bytes()
     sim.close()
     t2 = time.perf_counter()
-    st_ = StreamedSimulation(spec, 64, 32, dtype="f32", stream=stream, **{k: v for k, v in tile.items() if k != "kernel"})
+    st_ = StreamedSimulation(spec, 64, 16, dtype="f32", stream=stream, overlap=False, local_slots=4,
+                             **{k: v for k, v in tile.items() if k != "kernel"})
     st_.step(N)
     st_.set_cotangent(0, 2.0 * st_.spectra(0))
     st_.reverse()
@@ -640,7 +643,8 @@ def streamed_adjoint_256(stream):
         f"({info['device_bytes'] / 1e9:.2f} GB device, {info['host_bytes'] / 1e9:.2f} GB host), grad rel {r:.2e}")
     return {"workload": "256^3 (236^3 + 10-cell CPML), 128^3 design box eps in [1,6], |DFT Ez|^2 on a 32x32 "
                         "patch, 8 frequencies, 128 steps, FP32; resident with 2 binomial slots (forward "
-                        f"evaluations {plan.forward_evals + 1}), streamed with 64-plane slabs and K = 32",
+                        f"evaluations {plan.forward_evals + 1}), streamed with 64-plane slabs, K = 16, one "
+                        "workspace and 4 local slots",
             "resident_s": round(t1 - t0, 3), "streamed_s": round(t3 - t2, 3),
             "streamed_over_resident": round((t3 - t2) / (t1 - t0), 2),
             "resident_device_bytes": dev_res, "streamed_device_bytes": info["device_bytes"],

@@ -376,6 +376,8 @@ typedef struct {
     double host_budget_bytes;      /* pinned host budget for the banks and eps^-1 (0: unchecked) */
     int32_t overlap;               /* 1: two workspaces on two streams, so that one slab's transfers run
                                       beside the other slab's steps (twice the device workspace) */
+    int32_t local_slots;           /* reverse sweep: forward states a slab keeps on the device while it
+                                      reverses a block (binomial schedule); 0 or >= K: every state */
 } fdtd_stream_options;
 
 typedef struct {

@@ -2013,7 +2013,7 @@ struct Streamer : StreamBase {
                 Handle<T> sh;
                 sh.size_only = true;
                 sh.external_eps = true;
-                fdtd_options so2 = slab_options(rev ? K : 0);
+                fdtd_options so2 = slab_options(rev ? local_slots() : 0);
                 int rc = sh.create(&d, 1, &so2);
                 if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + sh.err);
                 pool_cap = std::max(pool_cap, sh.pool_bytes);
@@ -2182,6 +2182,58 @@ struct Streamer : StreamBase {
     // bank holding the state at time t
     int cur_bank() const { return adj ? (t + K - 1) / K : cb; }
 
+    // checkpoint slots a slab keeps while it reverses a block
+    int local_slots() const { return so.local_slots > 0 ? std::min(so.local_slots, K) : K; }
+
+    // Binomial checkpointing of one block (Griewank's rule, as in the
+    // package's revolve.py): beta(s, r) = C(s + r, s); to reverse [a, b)
+    // holding u^a in slot sa, advance m = max(1, l - beta(s-1, r),
+    // beta(s, r-2)) steps (r the fewest repetitions with beta(s, r) >= l),
+    // keep u^{a+m}, reverse [a+m, b) with one slot fewer, then [a, a+m).
+    static long long beta(int s_, int r) {
+        if (r < 0 || s_ < 0) return 0;
+        long long c = 1;
+        for (int q = 1; q <= s_; ++q) c = c * (r + q) / q;
+        return c;
+    }
+
+    int rev_block(Handle<T>& hd, int a, int b, int sa, std::vector<int>& free_slots, int& at) {
+        int rc;
+        auto go = [&](int pos) -> int {
+            if (at == pos) return FDTD_OK;
+            if ((rc = hd.ckpt_restore(sa))) return fail(rc, hd.err);
+            at = pos;
+            return FDTD_OK;
+        };
+        auto adv = [&](int k) -> int {
+            if (k <= 0) return FDTD_OK;
+            if ((rc = hd.step_forward(k, FDTD_REPLAY))) return fail(rc, hd.err);
+            at += k;
+            return FDTD_OK;
+        };
+        const int l = b - a;
+        if ((rc = go(a))) return rc;
+        if (l == 1) return (rc = hd.step_adjoint(1)) ? fail(rc, hd.err) : FDTD_OK;
+        const int s_ = (int)free_slots.size() + 1;
+        if (s_ == 1) {
+            for (int k = b - 1; k >= a; --k) {
+                if ((rc = go(a)) || (rc = adv(k - a))) return rc;
+                if ((rc = hd.step_adjoint(1))) return fail(rc, hd.err);
+            }
+            return FDTD_OK;
+        }
+        int r = 0;
+        while (beta(s_, r) < l) ++r;
+        const int m = (int)std::max<long long>(1, std::max<long long>(l - beta(s_ - 1, r), beta(s_, r - 2)));
+        if ((rc = adv(m))) return rc;
+        const int slot = free_slots.back();
+        free_slots.pop_back();
+        if ((rc = hd.ckpt_save(slot))) return fail(rc, hd.err);
+        if ((rc = rev_block(hd, a + m, b, slot, free_slots, at))) return rc;
+        free_slots.push_back(slot);
+        return rev_block(hd, a, a + m, sa, free_slots, at);
+    }
+
     int step(int n) override {
         if (n < 0) return fail(FDTD_E_INVALID, "negative step count");
         if (adj && n > 0 && (t % K != 0 || t + n > so.max_steps))
@@ -2240,7 +2292,8 @@ struct Streamer : StreamBase {
         hd.external_eps = true;
         hd.ext_pool = pool[w];
         hd.ext_cap = pool_cap;
-        fdtd_options so2 = slab_options(K);
+        const int L = std::min(local_slots(), kb);
+        fdtd_options so2 = slab_options(local_slots());
         so2.stream = wst[w];
         hipStream_t st = wst[w];
         int rc = hd.create(&d, 1, &so2);
@@ -2257,13 +2310,11 @@ struct Streamer : StreamBase {
                     return fail(FDTD_E_DEVICE, "slab eps upload failed");
             }
         }
-        // the block's forward states u^t0 .. u^{t0+kb-1}, each kept in a slot
+        // the block's starting state u^t0 in slot 0
         if ((rc = xfer(hd, fstart, true, o, e, c0, c1, st))) return rc;
-        for (int j = 0; j < kb; ++j) {
-            if ((rc = hd.ckpt_save(j))) return fail(rc, hd.err);
-            if ((rc = hd.step_forward(1, FDTD_REPLAY))) return fail(rc, hd.err);
-        }
-        // cotangent state at t0 + kb (its seeds included), then kb transposed steps
+        if ((rc = hd.ckpt_save(0))) return fail(rc, hd.err);
+        // cotangent state at t0 + kb (its seeds included), then kb transposed
+        // steps, the forward states regenerated from the block's slots
         hd.ap = 0;
         hd.m = t0 + kb;
         if ((rc = xfer(hd, cot_in, true, o, e, c0, c1, st, true, 0))) return rc;
@@ -2274,9 +2325,11 @@ struct Streamer : StreamBase {
                 return fail(rc, hd.err);
         }
         if (t0 + kb == N && (rc = hd.seed(N))) return fail(rc, hd.err);
-        for (int j = kb - 1; j >= 0; --j) {
-            if ((rc = hd.ckpt_restore(j))) return fail(rc, hd.err);
-            if ((rc = hd.step_adjoint(1))) return fail(rc, hd.err);
+        {
+            std::vector<int> free_slots;
+            for (int q = L - 1; q >= 1; --q) free_slots.push_back(q);
+            int at = t0;
+            if ((rc = rev_block(hd, t0, t0 + kb, 0, free_slots, at))) return rc;
         }
         if ((rc = xfer(hd, cot_out, false, o, e, c0, c1, st, true, hd.ap))) return rc;
         // dJ/deps of the core's gradient planes, added to the domain's on the host
@@ -2369,7 +2422,8 @@ struct Streamer : StreamBase {
         out->max_extent = mx;
         out->step = t;
         out->device_bytes = (double)(nws * pool_cap + dmon_bytes) + (d_einv ? (double)ebox * ncomp_eps * sizeof(T) : 0.0);
-        out->host_bytes = 2.0 * bank_elems * sizeof(T) + (double)ebox * ncomp_eps * sizeof(T);
+        out->host_bytes = (double)(bank.size() + (adj ? 2 : 0)) * bank_elems * sizeof(T) +
+                          (double)ebox * ncomp_eps * sizeof(T) + 8.0 * grad.size();
         out->resident_bytes = resident_bytes;
         out->materials_resident = d_einv ? 1 : 0;
     }

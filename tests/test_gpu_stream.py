@@ -171,23 +171,26 @@ def grad_spec():
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-9)])
-@pytest.mark.parametrize("W_,K_,overlap", [(14, 5, True), (20, 3, False)])
-def test_streamed_gradient_equals_resident(dtype, tol, W_, K_, overlap):
+@pytest.mark.parametrize("W_,K_,overlap,slots", [(14, 5, True, 0), (20, 3, False, 0), (14, 7, True, 2),
+                                                 (14, 6, False, 1)])
+def test_streamed_gradient_equals_resident(dtype, tol, W_, K_, overlap, slots):
     """dJ/deps by the streamed reverse sweep (blocks of K steps, slabs with
     K + 1 halo planes, the seeds of a flux plane on a core's first plane, a
-    patch and a probe) against the resident sweep over stored states."""
+    patch and a probe; every block state kept, or 2 or 1 local slots with the
+    binomial schedule) against the resident sweep over stored states."""
     from tests.gpu_util import gpu_gradient_store_all
     spec = grad_spec()
     N = spec.n_steps
     _, g_res, _ = gpu_gradient_store_all(spec, dtype, _cot, kernel="split")
-    s = StreamedSimulation(spec, W_, K_, dtype=dtype, overlap=overlap)
+    s = StreamedSimulation(spec, W_, K_, dtype=dtype, overlap=overlap, local_slots=slots)
     s.step(N)
     for mi, m in enumerate(spec.monitors):
         s.set_cotangent(mi, _cot(mi, m, s.spectra(mi)[:N] if m.kind == "probe" else s.spectra(mi)))
     s.reverse()
     g = s.grad()
     r = rel(g, g_res)
-    print(f"streamed gradient {dtype} W={W_} K={K_} overlap={overlap}: rel L2 vs resident {r:.3e}", flush=True)
+    print(f"streamed gradient {dtype} W={W_} K={K_} overlap={overlap} slots={slots}: rel L2 vs resident {r:.3e}",
+          flush=True)
     assert r < tol
     assert np.abs(g).max() > 0
     s.close()
