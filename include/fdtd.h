@@ -270,6 +270,14 @@ int fdtd_reset(fdtd_t h);
 /* Current forward step n and adjoint index m (-1 before fdtd_adjoint_begin). */
 int fdtd_get_step(fdtd_t h, int32_t *fwd_n, int32_t *adj_m);
 
+/* Watchdog: the sum of squares of domain `domain`'s six fields in the
+   current state, reduced on the device in FP64 in a fixed order, into
+   *energy.  Returns FDTD_E_UNSTABLE (after writing the sum) when it is not
+   finite: a NaN or an infinity somewhere in the fields, from a diverged run
+   or non-finite input.  The FDTD_MON_FLUX op of fdtd_monitor_dft returns
+   FDTD_E_UNSTABLE the same way when a flux value is not finite. */
+int fdtd_field_energy(fdtd_t h, int32_t domain, double *energy);
+
 /* Bytes of device memory held by the handle. */
 int fdtd_get_memory(fdtd_t h, double *bytes);
 

@@ -32,7 +32,7 @@ ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_E_INVALID", -2: "FDTD_E_UNSTABLE", -3: "F
 EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_begin", "fdtd_step_adjoint",
             "fdtd_step_reverse",
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
-            "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step",
+            "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step", "fdtd_field_energy",
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
             "fdtd_flux_reduce", "fdtd_flux_reduce_noalloc", "fdtd_last_error",
             "fdtd_stream_create", "fdtd_stream_destroy", "fdtd_stream_step", "fdtd_stream_get_field",
@@ -144,6 +144,7 @@ def lib():
         L.fdtd_reset.argtypes = [vp]
         L.fdtd_get_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.fdtd_get_memory.argtypes = [vp, C.POINTER(C.c_double)]
+        L.fdtd_field_energy.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.fdtd_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.fdtd_checkpoint_corrupt.argtypes = [vp, i32, sz, u32]
         L.fdtd_copy_probe.argtypes = [sz, i32, C.POINTER(C.c_double)]
@@ -440,3 +441,9 @@ def fdtd_stream_reverse(h):
 
 def fdtd_stream_get_grad(h, out: np.ndarray):
     return _schk(lib().fdtd_stream_get_grad(h, out.ctypes.data, out.nbytes), h)
+
+
+def fdtd_field_energy(h, domain: int) -> float:
+    e = C.c_double()
+    _chk(lib().fdtd_field_energy(h, domain, C.byref(e)), h)
+    return e.value

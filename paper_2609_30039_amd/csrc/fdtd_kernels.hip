@@ -2339,6 +2339,29 @@ __global__ void __launch_bounds__(256) k_flux_final(const double* __restrict__ p
     if (threadIdx.x == 0) out[f] = s;
 }
 
+// Field energy of one domain (the watchdog's reduction): the sum of squares
+// of its six fields over the grid (row padding skipped), FP64, as kEnergyBlocks
+// partial sums over contiguous runs of elements, then one block reduces them;
+// a fixed order, and a NaN or infinity anywhere makes the result non-finite.
+template <typename T>
+__global__ void __launch_bounds__(256) k_energy_partial(const DomDev<T>* __restrict__ doms, int dom, int cs,
+                                                        double* __restrict__ part) {
+    const DomDev<T>& d = doms[dom];
+    const long long nx = d.n[0], n = nx * d.n[1] * d.n[2];
+    const long long chunk = (n + kEnergyBlocks - 1) / kEnergyBlocks, q0 = (long long)blockIdx.x * chunk,
+                    q1 = min(n, q0 + chunk);
+    double s = 0.0;
+    for (int c = 0; c < 6; ++c) {
+        const FDTD_GLOBAL T* F = gp((c < 3 ? d.E[c] : d.H[c - 3]) + (long long)cs * d.fs);
+        for (long long q = q0 + threadIdx.x; q < q1; q += 256) {
+            const double v = (double)F[(q / nx) * d.pitch + q % nx];
+            s = fma(v, v, s);
+        }
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // max |x| of an FP32 array into *out (as ordered bits; out pre-zeroed)
 // ---- BF16 checkpoint slots.  The forward state arrays of all domains are
 // listed in one table (BfArr); every array is cut into chunks of kBfChunk
@@ -2668,6 +2691,13 @@ void launch_flux(const double* spectra, int nf, long long npts, double* part, do
     k_flux_final<<<nf, 256, 0, s>>>(part, nblk, out);
 }
 
+template <typename T>
+void launch_energy(const void* doms, int dom, int cs, double* part, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_partial<T>, dim3(kEnergyBlocks), dim3(256), 0, s, (const DomDev<T>*)doms, dom, cs,
+                       part);
+    hipLaunchKernelGGL(k_flux_final, dim3(1), dim3(256), 0, s, (const double*)part, kEnergyBlocks, out);
+}
+
 void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s) {
     long long nw = (long long)(bytes / 4);
     if (nw == 0) return;
@@ -2687,7 +2717,8 @@ int split_blocks(int nx, int ny, int nz, int kz, int w) {
     template void launch_probe<T>(const void*, const MonDev&, int, int, hipStream_t, const int*); \
     template void launch_seed<T>(const void*, const MonDev&, int, int, hipStream_t);            \
     template void launch_rev_record<T>(const void*, int, int, int, int, hipStream_t);          \
-    template void launch_rev_step<T>(const void*, int, int, int, int, long long, hipStream_t);
+    template void launch_rev_step<T>(const void*, int, int, int, int, long long, hipStream_t);        \
+    template void launch_energy<T>(const void*, int, int, double*, double*, hipStream_t);
 FDTD_INSTANTIATE(float)
 FDTD_INSTANTIATE(double)
 

@@ -114,6 +114,11 @@ void launch_bf16_save(const BfArr* arr, int narr, int nblk, long long shift, flo
 void launch_bf16_restore(const BfArr* arr, int narr, int nblk, long long shift, const unsigned int* scale,
                          const char* slot, hipStream_t s);
 void launch_checksum(const void* p, size_t bytes, unsigned long long* out, hipStream_t s);
+// sum of squares of domain dom's six fields of set cs into *out (FP64), through
+// kEnergyBlocks partial sums in part
+constexpr int kEnergyBlocks = 512;
+template <typename T>
+void launch_energy(const void* doms, int dom, int cs, double* part, double* out, hipStream_t s);
 // Poynting flux per frequency of spectra [nf][4][npts] complex128 (device):
 // flux_blocks(npts) partial sums per frequency in part (nf * flux_blocks
 // doubles), the result in out[nf]

@@ -113,6 +113,7 @@ struct Base {
     virtual double memory() = 0;
     virtual int timing(int op, double* ms, long long* n) = 0;
     virtual int poke_slot(int slot, size_t word, unsigned int value) = 0;
+    virtual int energy(int dom, double* out) = 0;
 };
 
 // Bump allocator over one arena of the pool; with assign=false it only sizes.
@@ -235,6 +236,7 @@ struct Handle : Base {
     float* d_bfpart = nullptr;                // per-chunk maxima of a save
     int bfblocks = 0;
     unsigned long long* d_sum = nullptr;      // checksum scratch
+    double* d_energy = nullptr;               // watchdog: kEnergyBlocks partial sums, then the sum
     std::vector<StateArr> fwd, adj;           // state arrays (set-0 addresses)
     std::vector<std::pair<void*, size_t>> adj_flat;   // gradient accumulators, for zeroing
     // physical forward sets: two working sets and one per full-precision slot
@@ -705,6 +707,7 @@ struct Handle : Base {
         M.take(d_bfarr, std::max<size_t>(1, nstate) * sizeof(BfArr));
         M.take(d_bfpart, std::max<size_t>(1, (size_t)bfblocks) * 4);
         M.take(d_sum, 8);
+        M.take(d_energy, (kEnergyBlocks + 1) * 8);
     }
 
     // ------------------------------------------------------------ create
@@ -1474,6 +1477,20 @@ struct Handle : Base {
         return check("checkpoint_restore");
     }
 
+    // Watchdog: the fields' sum of squares, reduced on the device; a
+    // non-finite sum means a NaN or an infinity somewhere in the state.
+    int energy(int dom, double* out) override {
+        if (dom < 0 || dom >= ndom) return fail(FDTD_E_RANGE, "domain index");
+        launch_energy<T>(d_doms, dom, cur, d_energy, d_energy + kEnergyBlocks, st);
+        if (hipMemcpyAsync(out, d_energy + kEnergyBlocks, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+            return fail(FDTD_E_DEVICE, "energy copy failed");
+        int rc = sync("energy");
+        if (rc) return rc;
+        if (!std::isfinite(*out)) return fail(FDTD_E_UNSTABLE, "non-finite field energy: the state holds a NaN or an "
+                                                                "infinity (diverged run or non-finite input)");
+        return FDTD_OK;
+    }
+
     // Corrupt one word of a slot (failure-path tests of checksum validation).
     int poke_slot(int slot, size_t word, unsigned int value) override {
         if (slot < 0 || slot >= (int)slots.size()) return fail(FDTD_E_RANGE, "checkpoint slot");
@@ -1520,7 +1537,12 @@ struct Handle : Base {
             launch_flux(m.acc, m.nf, mh.npts, m.fpart, m.fout, st);
             if (hipMemcpyAsync(buf, m.fout, (size_t)m.nf * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "flux copy failed");
-            return sync("flux");
+            int rc = sync("flux");
+            if (rc) return rc;
+            for (int f = 0; f < m.nf; ++f)   // watchdog: a diverged run shows in its flux
+                if (!std::isfinite(((const double*)buf)[f]))
+                    return fail(FDTD_E_UNSTABLE, "non-finite flux: the run diverged or was fed non-finite input");
+            return FDTD_OK;
         }
         if (op == FDTD_MON_SET_COTANGENT) {
             if (m.kind == 0) {
@@ -2558,6 +2580,12 @@ int fdtd_get_step(fdtd_t h, int32_t* fwd_n, int32_t* adj_m) {
     if (fwd_n) *fwd_n = n;
     if (adj_m) *adj_m = m;
     return FDTD_OK;
+}
+
+int fdtd_field_energy(fdtd_t h, int32_t domain, double* energy) {
+    GUARD(h);
+    if (!energy) return FDTD_E_INVALID;
+    return h->impl->energy(domain, energy);
 }
 
 int fdtd_get_memory(fdtd_t h, double* bytes) {

@@ -141,6 +141,11 @@ class Simulation:
     def memory_bytes(self) -> float:
         return B.fdtd_get_memory(self.h)
 
+    def field_energy(self, domain: int = 0) -> float:
+        """Sum of squares of the six fields (the watchdog: raises FdtdError
+        with FDTD_E_UNSTABLE when the state holds a NaN or an infinity)."""
+        return B.fdtd_field_energy(self.h, domain)
+
 
 class StreamedSimulation:
     """One domain advanced by host-streamed causal slabs (the libfdtd

@@ -79,3 +79,29 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path, monkeypatch):
     # a different candidate list is measured afresh under its own key
     assert AT.tune(spec, "f32", candidates=cands[:1], min_ms=2.0) == cands[0]
     assert len(json.loads(cache.read_text())) == 2
+
+
+def test_watchdog_energy_and_flux():
+    """The field-energy reduction equals the host's sum of squares; a NaN
+    planted from the host makes it, and the flux of a monitor plane the NaN
+    reaches, return FDTD_E_UNSTABLE instead of a number."""
+    from paper_2609_30039_amd import binding as B
+    spec = W.lorentz_flux(pml=6, lorentz=8, n_steps=60, n_f=4, shape=(40, 22, 36))
+    sim = Simulation(spec, dtype="f64", kernel="split")
+    sim.step(40)
+    e = sim.field_energy()
+    want = sum(float(np.sum(sim.field(q).astype(np.float64) ** 2)) for q in range(6))
+    assert want > 0 and abs(e - want) <= 1e-12 * want
+    assert np.all(np.isfinite(sim.flux(0)))
+    k = spec.monitors[0].pos[2]
+    f = sim.field(0)
+    f[k, 11, 20] = np.nan
+    sim.set_field(0, f)
+    with pytest.raises(B.FdtdError) as err:
+        sim.field_energy()
+    assert err.value.code == B.FDTD_E_UNSTABLE
+    sim.step(2)
+    with pytest.raises(B.FdtdError) as err:
+        sim.flux(0)
+    assert err.value.code == B.FDTD_E_UNSTABLE
+    sim.close()
