@@ -253,3 +253,40 @@ def test_design_patch_212_several_poles_adjoint_dot_product(dtype, tol):
     scale = _norm(ax) * _norm(y)
     assert abs(lhs - rhs) <= tol * scale, (lhs, rhs, scale)
     sim.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12)])
+def test_anisotropic_tensor_536_local_windows(dtype, tol):
+    """The 536^3 tensor workload (a rotated tensor at every interior node) at
+    full size, 3 steps from a random state in the tuned launch shape, checked
+    on three 20^3 windows spread over the interior (near the low corner, the
+    centre, near the high corner: different tiles, XCD runs and large
+    offsets).  The oracle steps each window with a margin of 5 planes: a
+    window's faces act as walls, whose error moves one plane per step, so the
+    inner 20^3 is exact after 3 steps."""
+    spec = W.anisotropic_tensor(n_steps=4)
+    spec.sources = []
+    fields = _random_fields(spec.shape, 7003)
+    sim = _start(spec, fields, dtype, kernel="split", tile_rows=8, tile_kz=8)
+    sim.step(3, record=False)
+    got = [sim.field(q) for q in range(6)]
+    sim.close()
+    del sim
+    (bx0, by0, bz0), _ = spec.eps_box
+    m, w, n = 5, 20, 3
+    for c in ((40, 45, 50), (268, 261, 270), (494, 500, 497)):
+        lo = [c[a] - w // 2 - m for a in range(3)]
+        hi = [c[a] + w // 2 + m for a in range(3)]
+        shape = tuple(hi[a] - lo[a] for a in range(3))
+        win = W.DomainSpec(shape=shape, courant=spec.courant, eps_kind="tensor", eps_box=((0, 0, 0), shape),
+                           eps=np.ascontiguousarray(spec.eps[:, lo[2] - bz0:hi[2] - bz0, lo[1] - by0:hi[1] - by0,
+                                                            lo[0] - bx0:hi[0] - bx0]), eps_bg=1.0)
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        o = O.OracleSim(win)
+        for q in range(6):
+            o.field(q)[...] = fields[q][sl]
+        o.step(n, record=False)
+        inner = (slice(m, m + w),) * 3
+        for q in range(6):
+            r = rel(got[q][sl][inner], o.field(q)[inner])
+            assert r < tol, (c, W.COMP_NAMES[q], r)
