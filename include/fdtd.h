@@ -184,6 +184,14 @@ typedef struct {
                                       box lies between the absorbing slabs, one cell clear of a low slab
                                       (else FDTD_E_INVALID); needs max_steps >= 1 and keeps
                                       (max_steps + 1) x 4 x (the box's face areas) interface values */
+    /* optional device allocator for the handle's one pool (e.g. the caching
+       allocator of the caller's framework, so that its memory accounting sees
+       the pool): alloc(ctx, bytes) returns device memory or NULL (then
+       FDTD_E_NOMEM), release(ctx, p) takes it back at fdtd_destroy; both NULL:
+       hipMalloc / hipFree.  Called on the handle's stream's device. */
+    void *(*alloc)(void *ctx, size_t bytes);
+    void (*release)(void *ctx, void *p);
+    void *alloc_ctx;
 } fdtd_options;
 
 typedef struct fdtd_s *fdtd_t;
@@ -269,6 +277,11 @@ int fdtd_reset(fdtd_t h);
 
 /* Current forward step n and adjoint index m (-1 before fdtd_adjoint_begin). */
 int fdtd_get_step(fdtd_t h, int32_t *fwd_n, int32_t *adj_m);
+
+/* The probe trace of monitor `probe` (a FDTD_MON_PROBE) of domain `domain`:
+   its first n samples (n <= max_steps), sample t taken after forward step t
+   + 1, as FDTD_MON_GET returns them. */
+int fdtd_probe_trace(fdtd_t h, int32_t domain, int32_t probe, double *host_buf, int32_t n);
 
 /* Watchdog: the sum of squares of domain `domain`'s six fields in the
    current state, reduced on the device in FP64 in a fixed order, into

@@ -33,6 +33,7 @@ EXPORTED = ["fdtd_create", "fdtd_destroy", "fdtd_step_forward", "fdtd_adjoint_be
             "fdtd_step_reverse",
             "fdtd_checkpoint_save", "fdtd_checkpoint_restore", "fdtd_monitor_dft", "fdtd_get_field",
             "fdtd_set_field", "fdtd_get_grad", "fdtd_set_eps", "fdtd_reset", "fdtd_get_step", "fdtd_field_energy",
+            "fdtd_probe_trace",
             "fdtd_get_memory", "fdtd_kernel_timing", "fdtd_copy_probe", "fdtd_checkpoint_corrupt",
             "fdtd_flux_reduce", "fdtd_flux_reduce_noalloc", "fdtd_last_error",
             "fdtd_stream_create", "fdtd_stream_destroy", "fdtd_stream_step", "fdtd_stream_get_field",
@@ -96,7 +97,31 @@ class Options(C.Structure):
                 ("ckpt_checksum", C.c_int32), ("max_steps", C.c_int32), ("kernel", C.c_int32),
                 ("dft_block", C.c_int32), ("graph_chunk", C.c_int32), ("tile_rows", C.c_int32),
                 ("tile_kz", C.c_int32), ("stream", C.c_void_p),
-                ("mem_budget_bytes", C.c_double), ("reversible", C.c_int32)]
+                ("mem_budget_bytes", C.c_double), ("reversible", C.c_int32),
+                ("alloc", C.c_void_p), ("release", C.c_void_p), ("alloc_ctx", C.c_void_p)]
+
+
+# the optional pool allocator of fdtd_options
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def torch_allocator(device: int = 0):
+    """(alloc, release) callbacks that take the pool from torch's caching
+    allocator on `device` (so torch.cuda.memory_allocated counts it).  Keep
+    the returned pair alive as long as the handle."""
+    import torch
+
+    def alloc(ctx, nbytes):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:
+            return None
+
+    def release(ctx, p):
+        torch.cuda.caching_allocator_delete(p)
+
+    return ALLOC_FN(alloc), RELEASE_FN(release)
 
 
 class StreamOptions(C.Structure):
@@ -145,6 +170,7 @@ def lib():
         L.fdtd_get_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.fdtd_get_memory.argtypes = [vp, C.POINTER(C.c_double)]
         L.fdtd_field_energy.argtypes = [vp, i32, C.POINTER(C.c_double)]
+        L.fdtd_probe_trace.argtypes = [vp, i32, i32, vp, i32]
         L.fdtd_kernel_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.fdtd_checkpoint_corrupt.argtypes = [vp, i32, sz, u32]
         L.fdtd_copy_probe.argtypes = [sz, i32, C.POINTER(C.c_double)]
@@ -253,7 +279,10 @@ def domain_desc(spec, keep: list) -> DomainDesc:
 def fdtd_create(specs: Sequence, dtype: int = FDTD_F32, n_ckpt: int = 0, ckpt_storage: Optional[int] = None,
                 ckpt_checksum: bool = False, max_steps: int = 0, kernel: int = FDTD_KERNEL_AUTO,
                 dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
-                mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0, reversible: bool = False):
+                mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0, reversible: bool = False,
+                allocator=None):
+    """allocator: None (hipMalloc) or an (alloc, release) pair of ctypes
+    callbacks (torch_allocator()) that the caller keeps alive."""
     keep: list = []
     arr = (DomainDesc * len(specs))()
     for q, s in enumerate(specs):
@@ -272,6 +301,9 @@ def fdtd_create(specs: Sequence, dtype: int = FDTD_F32, n_ckpt: int = 0, ckpt_st
     o.tile_kz = tile_kz
     o.stream = stream
     o.mem_budget_bytes = mem_budget_bytes
+    if allocator is not None:
+        o.alloc = C.cast(allocator[0], C.c_void_p)
+        o.release = C.cast(allocator[1], C.c_void_p)
     h = C.c_void_p()
     _chk(lib().fdtd_create(arr, len(specs), C.byref(o), C.byref(h)))
     return h
@@ -447,3 +479,9 @@ def fdtd_field_energy(h, domain: int) -> float:
     e = C.c_double()
     _chk(lib().fdtd_field_energy(h, domain, C.byref(e)), h)
     return e.value
+
+
+def fdtd_probe_trace(h, domain: int, probe: int, n: int) -> np.ndarray:
+    out = np.zeros(max(n, 1))
+    _chk(lib().fdtd_probe_trace(h, domain, probe, out.ctypes.data, n), h)
+    return out[:n]

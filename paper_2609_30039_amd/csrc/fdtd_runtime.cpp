@@ -114,6 +114,7 @@ struct Base {
     virtual int timing(int op, double* ms, long long* n) = 0;
     virtual int poke_slot(int slot, size_t word, unsigned int value) = 0;
     virtual int energy(int dom, double* out) = 0;
+    virtual int probe_trace(int dom, int mon, double* buf, int n) = 0;
 };
 
 // Bump allocator over one arena of the pool; with assign=false it only sizes.
@@ -283,7 +284,9 @@ struct Handle : Base {
             (void)hipGraphDestroy(g.g);
         }
         if (cst) (void)hipStreamDestroy(cst);
-        if (!ext_pool) (void)hipFree(pool);
+        if (ext_pool) return;
+        if (opt.alloc) opt.release(opt.alloc_ctx, pool);
+        else (void)hipFree(pool);
     }
 
     int fail(int code, const std::string& msg) {
@@ -783,7 +786,11 @@ struct Handle : Base {
             if (pool_bytes > ext_cap) return fail(FDTD_E_NOMEM, "slab workspace larger than its pool");
             pool = ext_pool;
         }
-        if (!ext_pool) {
+        if (!ext_pool && o->alloc) {
+            if (!o->release) return fail(FDTD_E_INVALID, "an allocator needs its release function");
+            pool = (char*)o->alloc(o->alloc_ctx, pool_bytes);
+            if (!pool) return fail(FDTD_E_NOMEM, "the caller's allocator returned no memory for the pool");
+        } else if (!ext_pool) {
             double budget = o->mem_budget_bytes;
             if (budget <= 0) {
                 size_t fr = 0, tot = 0;
@@ -1475,6 +1482,15 @@ struct Handle : Base {
         }
         t = slots[slot].step;
         return check("checkpoint_restore");
+    }
+
+    int probe_trace(int dom, int mon, double* buf, int n) override {
+        if (dom < 0 || dom >= ndom) return fail(FDTD_E_RANGE, "domain index");
+        if (mon < 0 || mon >= (int)dh[dom].mons.size()) return fail(FDTD_E_RANGE, "monitor index");
+        if (dh[dom].mons[mon].dev.kind != 0) return fail(FDTD_E_INVALID, "not a probe monitor");
+        if (n > std::max(1, opt.max_steps)) return fail(FDTD_E_RANGE, "more samples than max_steps");
+        if (n == 0) return FDTD_OK;
+        return monitor(dom, mon, FDTD_MON_GET, buf, (size_t)n * 8);
     }
 
     // Watchdog: the fields' sum of squares, reduced on the device; a
@@ -2580,6 +2596,12 @@ int fdtd_get_step(fdtd_t h, int32_t* fwd_n, int32_t* adj_m) {
     if (fwd_n) *fwd_n = n;
     if (adj_m) *adj_m = m;
     return FDTD_OK;
+}
+
+int fdtd_probe_trace(fdtd_t h, int32_t domain, int32_t probe, double* host_buf, int32_t n) {
+    GUARD(h);
+    if (!host_buf || n < 0) return FDTD_E_INVALID;
+    return h->impl->probe_trace(domain, probe, host_buf, n);
 }
 
 int fdtd_field_energy(fdtd_t h, int32_t domain, double* energy) {

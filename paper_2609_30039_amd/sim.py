@@ -14,7 +14,8 @@ class Simulation:
     def __init__(self, specs, dtype: str = "f32", n_ckpt: int = 0, ckpt_storage: Optional[str] = None,
                  ckpt_checksum: bool = False, max_steps: Optional[int] = None, kernel: str = "auto",
                  dft_block: int = 0, graph_chunk: int = 0, stream: Optional[int] = None,
-                 mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0, reversible: bool = False):
+                 mem_budget_bytes: float = 0.0, tile_rows: int = 0, tile_kz: int = 0, reversible: bool = False,
+                 torch_pool: bool = False):
         if not isinstance(specs, (list, tuple)):
             specs = [specs]
         self.specs = list(specs)
@@ -28,8 +29,10 @@ class Simulation:
         # bumped by every reset and permittivity upload: a recorded forward
         # sweep is valid for a backward pass only while it is unchanged
         self.generation = 0
+        # torch_pool: the device pool comes from torch's caching allocator
+        self._alloc = B.torch_allocator() if torch_pool else None
         self.h = B.fdtd_create(self.specs, dt, n_ckpt, storage, ckpt_checksum, max_steps, kern, dft_block,
-                               graph_chunk, stream, mem_budget_bytes, tile_rows, tile_kz, reversible)
+                               graph_chunk, stream, mem_budget_bytes, tile_rows, tile_kz, reversible, self._alloc)
 
     def close(self):
         if self.h is not None:

@@ -105,3 +105,30 @@ def test_watchdog_energy_and_flux():
         sim.flux(0)
     assert err.value.code == B.FDTD_E_UNSTABLE
     sim.close()
+
+
+def test_torch_pool_and_probe_trace():
+    """The pool taken from torch's caching allocator shows in torch's memory
+    accounting, gives the same run bit for bit, and returns to torch at
+    destroy; fdtd_probe_trace returns the probe's samples."""
+    import torch
+    from paper_2609_30039_amd import binding as B
+    spec = W.pec_cavity(24, 40)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    a = Simulation(spec, dtype="f64", torch_pool=True)
+    assert torch.cuda.memory_allocated() - before >= a.memory_bytes()
+    a.step(40)
+    b = Simulation(spec, dtype="f64")
+    b.step(40)
+    for q in range(6):
+        assert np.array_equal(a.field(q), b.field(q))
+    tr = B.fdtd_probe_trace(a.h, 0, 0, 40)
+    assert np.array_equal(tr, b.spectra(0)[:40]) and np.abs(tr).max() > 0
+    with pytest.raises(B.FdtdError) as err:
+        B.fdtd_probe_trace(a.h, 0, 0, 41)
+    assert err.value.code == B.FDTD_E_RANGE
+    a.close()
+    b.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
