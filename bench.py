@@ -98,7 +98,7 @@ def run_forward(spec, dtype, stream, K, Wm, tile=None, graph_chunk=32):
     from paper_2609_30039_amd.sim import Simulation
     import torch
     kw = dict(tile or {})
-    if kw.get("kernel") != "split":
+    if kw.get("kernel") not in ("split", "onepass"):
         graph_chunk = 0
     sim = Simulation(spec, dtype=dtype, stream=stream, graph_chunk=graph_chunk, **kw)
 
@@ -143,7 +143,7 @@ def headline(args, stream, khash):
     K, Wm = args.steps, args.warmup
     log(f"headline: anisotropic_lorentz {spec.shape} FP32, {BENCH_STEP} time steps per step, warmup {Wm}, "
         f"timed {K}, launch shape {tile}")
-    sim = Simulation(spec, dtype="f32", stream=stream, graph_chunk=BENCH_CHUNK if tile["kernel"] == "split" else 0,
+    sim = Simulation(spec, dtype="f32", stream=stream, graph_chunk=BENCH_CHUNK if tile["kernel"] in ("split", "onepass") else 0,
                      **tile)
     N = spec.n_steps
     done = [0]
@@ -196,8 +196,11 @@ def headline(args, stream, khash):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": RL.HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
-                     "kernel": ("split E and H kernels (k_fwd_e with the Lorentz-box blocks leading, then k_fwd_h)"
-                                if tile["kernel"] == "split" else "fused single-pass tile kernels")
+                     "kernel": {"split": "split E and H kernels (k_fwd_e with the Lorentz-box blocks leading, "
+                                         "then k_fwd_h)",
+                                "onepass": "single-pass interior kernel k_fwd_one beside the split E and H kernels "
+                                           "on the absorbing, wall and dispersive blocks",
+                                "fused": "fused single-pass tile kernels"}[tile["kernel"]]
                                + ": all stepping launches of one time step",
                      "launch_shape": tile,
                      "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_step,
@@ -281,7 +284,7 @@ def adjoint_536(stream):
         kw = dict(tile)
         if storage:
             kw["ckpt_storage"] = storage
-        sim = Simulation(spec, dtype=dtype, n_ckpt=slots, stream=stream, graph_chunk=32 if tile["kernel"] == "split"
+        sim = Simulation(spec, dtype=dtype, n_ckpt=slots, stream=stream, graph_chunk=32 if tile["kernel"] in ("split", "onepass")
                          else 0, **kw)
         plan = A.RevolvePlan(N, slots)
         torch.cuda.synchronize()
@@ -365,7 +368,7 @@ def cache_resident_148(stream, khash):
     for r in range(4):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim = Simulation(spec, dtype="f32", stream=stream, graph_chunk=32 if tile["kernel"] == "split" else 0, **tile)
+        sim = Simulation(spec, dtype="f32", stream=stream, graph_chunk=32 if tile["kernel"] in ("split", "onepass") else 0, **tile)
         sim.step(spec.n_steps, record=True)
         _ = [sim.field(q) for q in range(6)]
         _ = sim.flux(0)
@@ -397,7 +400,7 @@ def adjoint_212(stream):
     for dt in ("f32", "f64"):
         tile3 = AT.tune(spec3, dt, adjoint=True, stream=stream, log=log)
         sim3 = Simulation(spec3, dtype=dt, n_ckpt=24, stream=stream,
-                          graph_chunk=32 if tile3["kernel"] == "split" else 0, **tile3)
+                          graph_chunk=32 if tile3["kernel"] in ("split", "onepass") else 0, **tile3)
         plan = A.RevolvePlan(spec3.n_steps, 24)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -473,7 +476,7 @@ def batch_48(stream):
     tile4 = AT.tune(specs4, "f32", stream=stream, log=log, steps=3)
     log(f"batch_domains: {len(specs4)} domains, {cells4} cells, {n4} steps, launch shape {tile4}")
     sim4 = Simulation(specs4, dtype="f32", n_ckpt=16, stream=stream,
-                      graph_chunk=32 if tile4["kernel"] == "split" else 0, **tile4)
+                      graph_chunk=32 if tile4["kernel"] in ("split", "onepass") else 0, **tile4)
     sim4.step(4, record=False)
     sim4.reset()
     torch.cuda.synchronize()

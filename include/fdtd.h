@@ -89,9 +89,13 @@ enum { FDTD_RECORD = 1u, FDTD_REPLAY = 2u };
 enum { FDTD_MON_GET = 0, FDTD_MON_FLUX = 1, FDTD_MON_SET_COTANGENT = 2, FDTD_MON_RESET = 3 };
 /* kernel family.  AUTO and SPLIT: one E launch and one H launch per step,
    updating the state in place; FUSED: one pass per step over tiles, writing
+   the other state set; ONEPASS: the split kernels on the blocks that meet an
+   absorbing slab, a wall or a dispersive box, and one z-marching pass that
+   advances E and H together on every other block (interior blocks), writing
    the other state set.  Results are bitwise identical; the speed depends on
-   the geometry (the package's autotuner picks per workload). */
-enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2 };
+   the geometry (the package's autotuner picks per workload).  ONEPASS takes
+   the split launch shapes (tile_rows 4 or 8) and no reversible mode. */
+enum { FDTD_KERNEL_AUTO = 0, FDTD_KERNEL_SPLIT = 1, FDTD_KERNEL_FUSED = 2, FDTD_KERNEL_ONEPASS = 3 };
 
 #define FDTD_MAX_SOURCES 4
 #define FDTD_MAX_MONITORS 8

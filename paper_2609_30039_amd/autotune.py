@@ -28,6 +28,9 @@ CANDIDATES = [
     {"kernel": "split", "tile_rows": 8, "tile_kz": 3},
     {"kernel": "split", "tile_rows": 8, "tile_kz": 4},
     {"kernel": "split", "tile_rows": 8, "tile_kz": 8},
+    {"kernel": "onepass", "tile_rows": 8, "tile_kz": 8},
+    {"kernel": "onepass", "tile_rows": 8, "tile_kz": 16},
+    {"kernel": "onepass", "tile_rows": 0, "tile_kz": 16},
     {"kernel": "fused", "tile_rows": 2, "tile_kz": 8},
     {"kernel": "fused", "tile_rows": 2, "tile_kz": 16},
     {"kernel": "fused", "tile_rows": 4, "tile_kz": 8},

@@ -23,7 +23,7 @@ FDTD_MON_PROBE, FDTD_MON_FLUX_Z, FDTD_MON_PATCH_Z = 0, 1, 2
 FDTD_ADJ = 6
 FDTD_RECORD, FDTD_REPLAY = 1, 2
 FDTD_MON_GET, FDTD_MON_FLUX, FDTD_MON_SET_COTANGENT, FDTD_MON_RESET = 0, 1, 2, 3
-FDTD_KERNEL_AUTO, FDTD_KERNEL_SPLIT, FDTD_KERNEL_FUSED = 0, 1, 2
+FDTD_KERNEL_AUTO, FDTD_KERNEL_SPLIT, FDTD_KERNEL_FUSED, FDTD_KERNEL_ONEPASS = 0, 1, 2, 3
 FDTD_MAX_SOURCES, FDTD_MAX_MONITORS = 4, 8
 
 ERROR_NAMES = {0: "FDTD_OK", -1: "FDTD_E_INVALID", -2: "FDTD_E_UNSTABLE", -3: "FDTD_E_NOMEM",

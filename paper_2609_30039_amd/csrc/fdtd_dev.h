@@ -79,6 +79,10 @@ struct DomDev {
     T* psiH[3][2][2];
     int eps_diag;
     int elo[3], ehi[3];
+    // rows of the stored eps box: x from exa (elo[0] rounded down to a 128-byte
+    // boundary of the field rows) over exs elements (a multiple of 128 bytes), so
+    // that a wave's eps^-1 loads touch the cache lines its field loads do
+    int exa, exs;
     T epsinv_bg;
     const T* epsinv[3];        // over the eps box; isotropic: the same array thrice
     // symmetric tensor media (Section 2.3): eps^-1 at the grid nodes of the
@@ -88,6 +92,7 @@ struct DomDev {
     int tens;
     const T* tinv[6];
     T* curl[3];
+    int onep;                  // the domain's interior blocks may take the single-pass kernel
     int has_lor;
     int llo[3], lhi[3];
     int npole;                 // poles of the dispersive box (1..kMaxPole)
@@ -165,8 +170,7 @@ __device__ __forceinline__ bool in_box(const int lo[3], const int hi[3], int i, 
 template <typename T>
 __device__ __forceinline__ T epsinv_at(const DomDev<T>& d, int c, int i, int j, int k) {
     if (in_box<T>(d.elo, d.ehi, i, j, k)) {
-        long long q = ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) * (d.ehi[0] - d.elo[0]) +
-                      (i - d.elo[0]);
+        long long q = ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) * d.exs + (i - d.exa);
         return gp(d.epsinv[c])[q];
     }
     return d.epsinv_bg;

@@ -123,7 +123,8 @@ struct EpsView {
     int mode;                   // 0 background everywhere, 1 inside the eps box, 2 partial
     int diag;
     const FDTD_GLOBAL T* p[3];
-    int lo[3], hi[3], ex, ey;
+    int lo[3], hi[3], ex, ey;   // ex: the stored row length, ey: the box's rows per plane
+    int exa;                    // x of a stored row's first element
     T bg;
 };
 
@@ -137,7 +138,8 @@ __device__ __forceinline__ EpsView<T> eps_view(const DomDev<T>& d, int X0, int Y
         v.lo[a] = d.elo[a];
         v.hi[a] = d.ehi[a];
     }
-    v.ex = d.ehi[0] - d.elo[0];
+    v.ex = d.exs;
+    v.exa = d.exa;
     v.ey = d.ehi[1] - d.elo[1];
     int lo[3] = {X0, Y0, klo}, hi[3] = {X0 + 63, Y0 + NR - 1, khi};
     bool inside = true, outside = false;
@@ -158,7 +160,7 @@ __device__ __forceinline__ void eps_at(const EpsView<T>& v, int i, int j, int k,
         out[0] = out[1] = out[2] = v.bg;
         return;
     }
-    int q = ((k - v.lo[2]) * v.ey + (j - v.lo[1])) * v.ex + (i - v.lo[0]);
+    int q = ((k - v.lo[2]) * v.ey + (j - v.lo[1])) * v.ex + (i - v.exa);
     out[0] = v.p[0][q];
     if (v.diag) {
         out[1] = v.p[1][q];
@@ -264,6 +266,23 @@ struct BlkFlags {
     bool cp, lor;
 };
 
+// A block of the single-pass family: its cells, their +x, +y, +z neighbours
+// (whose E^{n+1} its H updates read, recomputed in the block) and their
+// -x, -y, -z neighbours (whose H its E updates read) lie off every absorbing
+// slab, wall node and dispersive box, so every update there is the plain
+// Yee one.  The split kernels skip exactly these blocks in that family.
+template <typename T>
+__device__ __forceinline__ bool blk_interior(const DomDev<T>& d, int x0, int y0, int k0, int k1, int w, int nr) {
+    if (!d.onep) return false;
+    const int lo[3] = {x0, y0, k0}, hi[3] = {x0 + w, y0 + nr, k1};   // hi: the +1 neighbours, inclusive
+    bool lor = d.has_lor;
+    for (int a = 0; a < 3; ++a) {
+        if (lo[a] < max(1, d.L[a][0]) || hi[a] >= d.n[a] - d.L[a][1]) return false;
+        if (hi[a] < d.llo[a] || lo[a] >= d.lhi[a]) lor = false;
+    }
+    return !lor;
+}
+
 template <typename T>
 __device__ __forceinline__ BlkFlags blk_flags(const DomDev<T>& d, int x0, int y0, int k0, int k1, int w = 64,
                                               int nr = 4) {
@@ -344,7 +363,8 @@ __device__ __forceinline__ void e_lor_block(const DomDev<T>* __restrict__ doms, 
 template <typename T, int W, bool TENS>
 __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                const int* __restrict__ xr, const int* __restrict__ lbs, int nlb,
-                                               int ndom, int kz, int rs, int ws, int t, const int* __restrict__ tdev) {
+                                               int ndom, int kz, int rs, int ws, int t, const int* __restrict__ tdev,
+                                               int skip_interior) {
     if ((int)blockIdx.x < nlb) {
         e_lor_block(doms, lbs, ndom, xcd_remap(blockIdx.x, nlb), rs, ws, t, tdev);
         return;
@@ -352,6 +372,7 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     const DomDev<T>* dp;
     Col c = column<T, W>(doms, bs, ndom, kz, dp, xr, (int)blockIdx.x - nlb);
     if (!c.ok || dp->tens != (int)TENS) return;
+    if (skip_interior && blk_interior(*dp, c.x0, c.y0, c.k0, c.k1, W, 256 / W)) return;   // the single pass takes it
     if (tdev) t += *tdev;   // graph replays: step index held on the device
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
@@ -436,6 +457,178 @@ __global__ void __launch_bounds__(256) k_fwd_e(const DomDev<T>* __restrict__ dom
     }
 }
 
+
+// ============================================================ forward, single pass
+// Interior blocks (blk_interior) advance E and H in one launch, z-marching a
+// column per thread like the split kernels, into the other state set.  At
+// plane k a thread computes E^{n+1} of its own column at plane k+1 and of
+// its +x and +y neighbour columns at plane k (the components its H update
+// reads: Ez, Ey at i+1; Ez, Ex at j+1), then H^{n+3/2} at plane k.  The
+// neighbours' E^{n+1} are recomputed rather than exchanged, so the block
+// needs no LDS and no barrier; their operands are the neighbours' own loads,
+// served by the caches.  Every update is the split kernels' arithmetic on
+// the same operands, so the result is bitwise the split family's.
+template <typename T>
+struct OneOwn {   // own column, plane p: H, H one back along x and y, E^n, eps^-1
+    T h[3], hy_xm, hz_xm, hx_ym, hz_ym, e[3], ep[3];
+};
+
+template <typename T>
+struct OneNb {    // the +x and +y columns' E-update operands at plane p
+    T hx_xp, hy_xp, hz_xp, hx_xpym, ey_xp, ez_xp, epy_xp, epz_xp;
+    T hx_yp, hy_yp, hz_yp, hy_xmyp, ex_yp, ez_yp, epx_yp, epz_yp;
+};
+
+// eps^-1 of component c at (i,j,k) from a view whose mode covers the cell
+template <typename T>
+__device__ __forceinline__ T eps1(const EpsView<T>& v, int c, int i, int j, int k) {
+    const bool in = v.mode == 1 || (v.mode == 2 && i >= v.lo[0] && i < v.hi[0] && j >= v.lo[1] && j < v.hi[1] &&
+                                    k >= v.lo[2] && k < v.hi[2]);
+    if (!in) return v.bg;
+    const int q = ((k - v.lo[2]) * v.ey + (j - v.lo[1])) * v.ex + (i - v.exa);
+    return v.p[v.diag ? c : 0][q];
+}
+
+template <typename T>
+__device__ __forceinline__ void one_own(const FDTD_GLOBAL T* const (&h)[3], const FDTD_GLOBAL T* const (&e)[3],
+                                        const EpsView<T>& ev, OneOwn<T>& o, long long f, long long P, int i, int j,
+                                        int k) {
+    o.h[0] = h[0][f];
+    o.h[1] = h[1][f];
+    o.h[2] = h[2][f];
+    o.hy_xm = h[1][f - 1];
+    o.hz_xm = h[2][f - 1];
+    o.hx_ym = h[0][f - P];
+    o.hz_ym = h[2][f - P];
+    o.e[0] = e[0][f];
+    o.e[1] = e[1][f];
+    o.e[2] = e[2][f];
+    eps_at(ev, i, j, k, o.ep);
+}
+
+template <typename T>
+__device__ __forceinline__ void one_nb(const FDTD_GLOBAL T* const (&h)[3], const FDTD_GLOBAL T* const (&e)[3],
+                                       const EpsView<T>& ev, OneNb<T>& n, long long f, long long P, int i, int j,
+                                       int k) {
+    n.hx_xp = h[0][f + 1];
+    n.hy_xp = h[1][f + 1];
+    n.hz_xp = h[2][f + 1];
+    n.hx_xpym = h[0][f + 1 - P];
+    n.ey_xp = e[1][f + 1];
+    n.ez_xp = e[2][f + 1];
+    n.epy_xp = eps1(ev, 1, i + 1, j, k);
+    n.epz_xp = eps1(ev, 2, i + 1, j, k);
+    n.hx_yp = h[0][f + P];
+    n.hy_yp = h[1][f + P];
+    n.hz_yp = h[2][f + P];
+    n.hy_xmyp = h[1][f - 1 + P];
+    n.ex_yp = e[0][f + P];
+    n.ez_yp = e[2][f + P];
+    n.epx_yp = eps1(ev, 0, i, j + 1, k);
+    n.epz_yp = eps1(ev, 2, i, j + 1, k);
+}
+
+// the sources of E_c at (i, j, k) for step t, added in the split kernel's order
+template <typename T>
+__device__ __forceinline__ T add_src(const DomDev<T>& d, int c, int i, int j, int k, int t, T v) {
+    for (int q = 0; q < d.nsrc; ++q) {
+        const SrcDev<T>& sr = d.src[q];
+        if (sr.comp == c && t < sr.nwave && k == sr.k && (sr.kind == 1 || (i == sr.i && j == sr.j)))
+            v += gp(sr.wave)[t];
+    }
+    return v;
+}
+
+template <typename T, int W>
+__global__ void __launch_bounds__(256) k_fwd_one(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
+                                                 const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int t,
+                                                 const int* __restrict__ tdev, int slot) {
+    constexpr int NR = 256 / W;
+    const DomDev<T>* dp;
+    Col c = column<T, W>(doms, bs, ndom, kz, dp, xr);
+    if (!c.ok || !blk_interior(*dp, c.x0, c.y0, c.k0, c.k1, W, NR)) return;
+    if (tdev) t += *tdev;
+    const DomDev<T>& d = *dp;
+    const int i = c.i, j = c.j, k0 = c.k0, k1 = c.k1;
+    const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane, P = d.pitch;
+    const FDTD_GLOBAL T* h[3] = {gp(d.H[0] + so), gp(d.H[1] + so), gp(d.H[2] + so)};
+    const FDTD_GLOBAL T* e[3] = {gp(d.E[0] + so), gp(d.E[1] + so), gp(d.E[2] + so)};
+    FDTD_GLOBAL T* ew[3] = {gp(d.E[0] + wo), gp(d.E[1] + wo), gp(d.E[2] + wo)};
+    FDTD_GLOBAL T* hw[3] = {gp(d.H[0] + wo), gp(d.H[1] + wo), gp(d.H[2] + wo)};
+    // the block's cells and their +1 neighbours, planes k0 .. k1
+    EpsView<T> ev = eps_view(d, c.x0, c.y0, NR + 1, k0, k1);
+    {
+        bool inside = true, outside = false;
+        const int lo[3] = {c.x0, c.y0, k0}, hi[3] = {c.x0 + W, c.y0 + NR, k1};
+        for (int a = 0; a < 3; ++a) {
+            if (lo[a] < d.elo[a] || hi[a] >= d.ehi[a]) inside = false;
+            if (hi[a] < d.elo[a] || lo[a] >= d.ehi[a]) outside = true;
+        }
+        ev.mode = outside ? 0 : (inside ? 1 : 2);
+    }
+    const T S = d.S;
+    long long f = (long long)k0 * pl + (long long)j * P + i;
+    // own E^{n+1} at plane k0, from H at k0 and k0 - 1
+    T hxm = h[0][f - pl], hym = h[1][f - pl];
+    T hx_xp_m = h[0][f - pl + 1], hy_yp_m = h[1][f - pl + P];   // the +x column's Hx, the +y column's Hy at k0 - 1
+    OneOwn<T> cu, no;
+    one_own(h, e, ev, cu, f, P, i, j, k0);
+    T ex = fma(S * cu.ep[0], (cu.h[2] - cu.hz_ym) - (cu.h[1] - hym), cu.e[0]);
+    T ey = fma(S * cu.ep[1], (cu.h[0] - hxm) - (cu.h[2] - cu.hz_xm), cu.e[1]);
+    T ez = fma(S * cu.ep[2], (cu.h[1] - cu.hy_xm) - (cu.h[0] - cu.hx_ym), cu.e[2]);
+    ex = add_src(d, 0, i, j, k0, t, ex);
+    ey = add_src(d, 1, i, j, k0, t, ey);
+    ez = add_src(d, 2, i, j, k0, t, ez);
+    T hc[3] = {cu.h[0], cu.h[1], cu.h[2]};   // own H^{n+1/2} at plane k
+    OneNb<T> nb;
+    one_own(h, e, ev, no, f + pl, P, i, j, k0 + 1);
+    one_nb(h, e, ev, nb, f, P, i, j, k0);
+    for (int k = k0; k < k1; ++k, f += pl) {
+        OneOwn<T> no2 = no;
+        OneNb<T> nn = nb;
+        if (k + 1 < k1) {   // fetch ahead: own plane k + 2, neighbour plane k + 1
+            one_own(h, e, ev, no2, f + 2 * pl, P, i, j, k + 2);
+            one_nb(h, e, ev, nn, f + pl, P, i, j, k + 1);
+        }
+        // own E^{n+1} at plane k + 1
+        T ex1 = fma(S * no.ep[0], (no.h[2] - no.hz_ym) - (no.h[1] - hc[1]), no.e[0]);
+        T ey1 = fma(S * no.ep[1], (no.h[0] - hc[0]) - (no.h[2] - no.hz_xm), no.e[1]);
+        T ez1 = fma(S * no.ep[2], (no.h[1] - no.hy_xm) - (no.h[0] - no.hx_ym), no.e[2]);
+        ex1 = add_src(d, 0, i, j, k + 1, t, ex1);
+        ey1 = add_src(d, 1, i, j, k + 1, t, ey1);
+        ez1 = add_src(d, 2, i, j, k + 1, t, ez1);
+        // the +x column's Ez, Ey and the +y column's Ez, Ex at plane k
+        T ez_xp = fma(S * nb.epz_xp, (nb.hy_xp - hc[1]) - (nb.hx_xp - nb.hx_xpym), nb.ez_xp);
+        T ey_xp = fma(S * nb.epy_xp, (nb.hx_xp - hx_xp_m) - (nb.hz_xp - hc[2]), nb.ey_xp);
+        T ez_yp = fma(S * nb.epz_yp, (nb.hy_yp - nb.hy_xmyp) - (nb.hx_yp - hc[0]), nb.ez_yp);
+        T ex_yp = fma(S * nb.epx_yp, (nb.hz_yp - hc[2]) - (nb.hy_yp - hy_yp_m), nb.ex_yp);
+        ez_xp = add_src(d, 2, i + 1, j, k, t, ez_xp);
+        ey_xp = add_src(d, 1, i + 1, j, k, t, ey_xp);
+        ez_yp = add_src(d, 2, i, j + 1, k, t, ez_yp);
+        ex_yp = add_src(d, 0, i, j + 1, k, t, ex_yp);
+        // H^{n+3/2} at plane k
+        const T hx = fma(-S, (ez_yp - ez) - (ey1 - ey), hc[0]);
+        const T hy = fma(-S, (ex1 - ex) - (ez_xp - ez), hc[1]);
+        const T hz = fma(-S, (ey_xp - ey) - (ex_yp - ex), hc[2]);
+        ew[0][f] = ex;
+        ew[1][f] = ey;
+        ew[2][f] = ez;
+        hw[0][f] = hx;
+        hw[1][f] = hy;
+        hw[2][f] = hz;
+        if (slot >= 0) sample_node(d, slot, i, j, k, ex, ey, ez, hx, hy, hz);
+        hx_xp_m = nb.hx_xp;
+        hy_yp_m = nb.hy_yp;
+        hc[0] = no.h[0];
+        hc[1] = no.h[1];
+        hc[2] = no.h[2];
+        ex = ex1;
+        ey = ey1;
+        ez = ez1;
+        no = no2;
+        nb = nn;
+    }
+}
 
 // ------------------------------------------------ tensor media, assembly pass
 // Operands of plane k of the assembly pass that are not carried over from
@@ -548,9 +741,9 @@ __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ do
     m.pitch = d.pitch;
     m.pl = d.plane;
     m.fc = (long long)j * d.pitch + i;
-    m.bx = d.ehi[0] - d.elo[0];
+    m.bx = d.exs;
     m.bpl = (long long)m.bx * (d.ehi[1] - d.elo[1]);
-    m.qc = (long long)(j - d.elo[1]) * m.bx + (i - d.elo[0]);
+    m.qc = (long long)(j - d.elo[1]) * m.bx + (i - d.exa);
     m.xm = i > 0;
     m.xp = i + 1 < d.n[0];
     m.ym = j > 0;
@@ -681,10 +874,12 @@ __device__ __forceinline__ void sample_node(const DomDev<T>& d, int slot, int i,
 
 template <typename T, int W>
 __global__ void __launch_bounds__(256) k_fwd_h(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
-                                               const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int slot) {
+                                               const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int slot,
+                                               int skip_interior) {
     const DomDev<T>* dp;
     Col c = column<T, W>(doms, bs, ndom, kz, dp, xr);
     if (!c.ok) return;
+    if (skip_interior && blk_interior(*dp, c.x0, c.y0, c.k0, c.k1, W, 256 / W)) return;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
     const long long so = (long long)rs * d.fs, wo = (long long)ws * d.fs, pl = d.plane;
@@ -2523,33 +2718,42 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
         // one launch per pass over all blocks: a second launch for the
         // interior blocks costs more in its drain than its leaner registers win
         const int nlb = (c.nlor + 7) / 8 * 8;
+        const int sk = c.onepass;
         if (c.ntens < c.ndom) {
             if (c.sw == 32)
                 hipLaunchKernelGGL((k_fwd_e<T, 32, false>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
-                                   c.lbs, nlb, c.ndom, c.kz, rs, ws, t, tdev);
+                                   c.lbs, nlb, c.ndom, c.kz, rs, ws, t, tdev, sk);
             else
                 hipLaunchKernelGGL((k_fwd_e<T, 64, false>), dim3(nlb + c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
-                                   c.lbs, nlb, c.ndom, c.kz, rs, ws, t, tdev);
+                                   c.lbs, nlb, c.ndom, c.kz, rs, ws, t, tdev, sk);
         }
         if (c.ntens) {   // tensor domains: curl pass, then the assembly pass
             if (c.sw == 32) {
                 hipLaunchKernelGGL((k_fwd_e<T, 32, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, 0,
-                                   c.ndom, c.kz, rs, ws, t, tdev);
+                                   c.ndom, c.kz, rs, ws, t, tdev, 0);
                 hipLaunchKernelGGL((k_tens_e<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
                                    rs, ws, t, tdev);
             } else {
                 hipLaunchKernelGGL((k_fwd_e<T, 64, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, 0,
-                                   c.ndom, c.kz, rs, ws, t, tdev);
+                                   c.ndom, c.kz, rs, ws, t, tdev, 0);
                 hipLaunchKernelGGL((k_tens_e<T, 64>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
                                    rs, ws, t, tdev);
             }
         }
+        if (sk) {   // interior blocks: one pass (reads set rs only, so it may run after the E pass)
+            if (c.sw == 32)
+                hipLaunchKernelGGL((k_fwd_one<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
+                                   rs, ws, t, tdev, slot);
+            else
+                hipLaunchKernelGGL((k_fwd_one<T, 64>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
+                                   rs, ws, t, tdev, slot);
+        }
         if (c.sw == 32)
             hipLaunchKernelGGL((k_fwd_h<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz, rs, ws,
-                               slot);
+                               slot, sk);
         else
             hipLaunchKernelGGL((k_fwd_h<T, 64>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz, rs, ws,
-                               slot);
+                               slot, sk);
         return;
     }
     if (c.nfgen) FDTD_ROWS_SWITCH(k_fwd_fused, c.rows, dim3(c.nfgen), dim3(256), 0, s, dd, c.tfgen, c.kz, rs, ws, t)

@@ -40,6 +40,7 @@ struct LaunchCfg {
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
     int ntens;                 // split: domains with tensor media (two E passes)
+    int onepass;               // split family with the single-pass kernel on interior blocks (ping-pong sets)
     // split adjoint: one tile table per pass, (domain | class << 24,
     // x0 | xlen << 24, y0, k0), domains with a gradient only.  x is cut into
     // the slab zones (narrow tiles, W = 16) and the interior zone (W = 32); a

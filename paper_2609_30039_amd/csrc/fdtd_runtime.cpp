@@ -628,12 +628,13 @@ struct Handle : Base {
                 }
             size_t ebox = 1;
             for (int a = 0; a < 3; ++a) ebox *= (size_t)(d.ehi[a] - d.elo[a]);
+            const size_t erows = ebox ? ebox / (size_t)(d.ehi[0] - d.elo[0]) * d.exs : 0;   // stored elements
             if (d.tens) {
                 if (ebox && s.eps)
-                    for (int q6 = 0; q6 < 6; ++q6) M.take(d.tinv[q6], ebox * ts);
+                    for (int q6 = 0; q6 < 6; ++q6) M.take(d.tinv[q6], erows * ts);
                 for (int c = 0; c < 3; ++c) X.take(d.curl[c], h.nfield * ts);
             } else if (ebox && s.eps) {
-                for (int c = 0; c < h.ncomp_eps; ++c) M.take(d.epsinv[c], ebox * ts);
+                for (int c = 0; c < h.ncomp_eps; ++c) M.take(d.epsinv[c], erows * ts);
                 if (asg)
                     for (int c = h.ncomp_eps; c < 3; ++c) d.epsinv[c] = d.epsinv[0];
             }
@@ -726,11 +727,14 @@ struct Handle : Base {
         bf16 = o->ckpt_storage == FDTD_BF16;
         if (bf16 && sizeof(T) != 4) return fail(FDTD_E_INVALID, "BF16 checkpoints need FP32 fields");
         if (o->n_ckpt < 0 || o->max_steps < 0) return fail(FDTD_E_INVALID, "negative n_ckpt or max_steps");
-        if (o->kernel < 0 || o->kernel > 2) return fail(FDTD_E_INVALID, "kernel selector");
+        if (o->kernel < 0 || o->kernel > 3) return fail(FDTD_E_INVALID, "kernel selector");
+        if (o->kernel == FDTD_KERNEL_ONEPASS && o->reversible)
+            return fail(FDTD_E_INVALID, "the single-pass family takes no reversible mode");
         if (o->tile_rows != 0 && o->tile_rows != 2 && o->tile_rows != 4 && o->tile_rows != 8)
             return fail(FDTD_E_INVALID, "tile_rows must be 2, 4 or 8");
         if (o->tile_kz < 0) return fail(FDTD_E_INVALID, "tile_kz");
         cfg.kernel = o->kernel == FDTD_KERNEL_FUSED ? 2 : 1;
+        cfg.onepass = o->kernel == FDTD_KERNEL_ONEPASS ? 1 : 0;
         cfg.rows = o->tile_rows ? o->tile_rows : 2;
         // split family: tile_rows = rows per block, 4 (64 columns) or 8 (32 columns)
         if (cfg.kernel == 1 && o->tile_rows != 0 && o->tile_rows != 4 && o->tile_rows != 8)
@@ -913,6 +917,8 @@ struct Handle : Base {
         }
         d.eps_diag = s.eps_kind == FDTD_EPS_DIAG;
         d.tens = s.eps_kind == FDTD_EPS_TENSOR;
+        // interior blocks take the single pass unless the domain has tensor media or a periodic axis
+        d.onep = opt.kernel == FDTD_KERNEL_ONEPASS && !d.tens && !s.periodic[0] && !s.periodic[1] && !s.periodic[2];
         size_t ebox = 1;
         for (int a = 0; a < 3; ++a) {
             d.elo[a] = s.eps_lo[a];
@@ -921,6 +927,8 @@ struct Handle : Base {
         }
         if (!(ebox && s.eps))
             for (int a = 0; a < 3; ++a) d.elo[a] = d.ehi[a] = 0;
+        d.exa = d.elo[0] / align * align;
+        d.exs = (d.ehi[0] - d.exa + align - 1) / align * align;
         d.epsinv_bg = (T)(1.0 / s.eps_bg);
         d.has_lor = s.n_lorentz > 0;
         if (d.has_lor) {
@@ -1000,37 +1008,47 @@ struct Handle : Base {
         }
     }
 
+    // eps^-1 of a domain's eps box in the stored row layout (rows of exs
+    // elements from x = exa; the row padding holds the background): ncomp
+    // arrays of (box rows) x exs, component c at c * (box rows) * exs.
+    // h_eps: [ncomp][bz][by][bx] as the descriptor gives it.
+    static void einv_rows(const DomDev<T>& d, int ncomp, const double* h_eps, double bg, std::vector<T>& v) {
+        const int bx = d.ehi[0] - d.elo[0], by = d.ehi[1] - d.elo[1], bz = d.ehi[2] - d.elo[2];
+        const size_t rows = (size_t)by * bz, ebox = rows * bx, nst = rows * d.exs;
+        v.assign(ncomp * nst, T(0));
+        const int ncm = ncomp == 6 ? 3 : ncomp;
+        for (int c = 0; c < ncm; ++c)
+            for (size_t r = 0; r < rows; ++r)
+                for (int x = 0; x < d.exs; ++x) v[c * nst + r * d.exs + x] = (T)(1.0 / bg);   // padding: the background
+        for (size_t r = 0; r < rows; ++r)
+            for (int x = 0; x < bx; ++x) {
+                const size_t e = r * bx + x, o = r * d.exs + (d.elo[0] - d.exa) + x;
+                if (ncomp == 6) {   // each node's tensor inverted
+                    double m[6], w[6];
+                    for (int c = 0; c < 6; ++c) m[c] = h_eps[c * ebox + e];
+                    sym3_inverse(m, w);
+                    for (int c = 0; c < 6; ++c) v[c * nst + o] = (T)w[c];
+                } else {
+                    for (int c = 0; c < ncomp; ++c) v[c * nst + o] = (T)(1.0 / h_eps[c * ebox + e]);
+                }
+            }
+    }
+
     int upload_eps(int q) {
         if (external_eps) return FDTD_OK;
         DomHost& h = dh[q];
         DomDev<T>& d = dd[q];
-        size_t ebox = 1;
-        for (int a = 0; a < 3; ++a) ebox *= (size_t)(d.ehi[a] - d.elo[a]);
-        if (d.tens) {   // eps^-1 of each node's tensor, six arrays
-            if (!d.tinv[0]) return FDTD_OK;
-            std::vector<T> v(6 * ebox);
-            for (size_t e = 0; e < ebox; ++e) {
-                double m[6], r[6];
-                for (int c = 0; c < 6; ++c) m[c] = h.eps[c * ebox + e];
-                sym3_inverse(m, r);
-                for (int c = 0; c < 6; ++c) v[c * ebox + e] = (T)r[c];
-            }
-            for (int c = 0; c < 6; ++c)
-                if (hipMemcpyAsync((void*)d.tinv[c], v.data() + c * ebox, ebox * sizeof(T), hipMemcpyHostToDevice,
-                                   st) != hipSuccess)
-                    return fail(FDTD_E_DEVICE, "upload eps failed");
-            if (hipStreamSynchronize(st) != hipSuccess) return fail(FDTD_E_DEVICE, "upload eps sync failed");
-            return FDTD_OK;
-        }
-        if (!d.epsinv[0]) return FDTD_OK;
-        std::vector<T> v(ebox);
-        for (int c = 0; c < h.ncomp_eps; ++c) {
-            for (size_t e = 0; e < ebox; ++e) v[e] = (T)(1.0 / h.eps[c * ebox + e]);
-            if (hipMemcpyAsync((void*)d.epsinv[c], v.data(), ebox * sizeof(T), hipMemcpyHostToDevice, st) !=
-                hipSuccess)
+        const int nc = d.tens ? 6 : h.ncomp_eps;
+        if (d.tens ? !d.tinv[0] : !d.epsinv[0]) return FDTD_OK;
+        std::vector<T> v;
+        einv_rows(d, nc, h.eps.data(), h.desc.eps_bg, v);
+        const size_t nst = v.size() / nc;
+        for (int c = 0; c < nc; ++c) {
+            T* dst = d.tens ? const_cast<T*>(d.tinv[c]) : const_cast<T*>(d.epsinv[c]);
+            if (hipMemcpyAsync(dst, v.data() + c * nst, nst * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
                 return fail(FDTD_E_DEVICE, "upload eps failed");
-            if (hipStreamSynchronize(st) != hipSuccess) return fail(FDTD_E_DEVICE, "upload eps sync failed");
         }
+        if (hipStreamSynchronize(st) != hipSuccess) return fail(FDTD_E_DEVICE, "upload eps sync failed");
         return FDTD_OK;
     }
 
@@ -1246,13 +1264,17 @@ struct Handle : Base {
             return fail(FDTD_E_DEVICE, "capture stream");
         if (hipStreamBeginCapture(cst, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail(FDTD_E_DEVICE, "hipStreamBeginCapture failed");
-        // recording chunks start with every ring empty: step s samples into slot s
+        // recording chunks start with every ring empty: step s samples into slot s.
+        // In place (split), or ping-pong between the two working sets (single pass)
+        int rset = cur;
         for (int s = 0; s < G; ++s) {
-            launch_fwd<T>(cfg, d_doms, cur, cur, s, cst, d_tstep, rec ? s : -1);
+            const int wset_ = cfg.onepass ? (wset[0] != rset ? wset[0] : wset[1]) : rset;
+            launch_fwd<T>(cfg, d_doms, rset, wset_, s, cst, d_tstep, rec ? s : -1);
+            rset = wset_;
             if (!rec) continue;
             for (auto& h : dh)
                 for (auto& mh : h.mons)
-                    if (mh.dev.kind == 0) launch_probe<T>(d_doms, mh.dev, cur, s, cst, d_tstep);
+                    if (mh.dev.kind == 0) launch_probe<T>(d_doms, mh.dev, rset, s, cst, d_tstep);
         }
         if (rec)
             for (auto& h : dh)
@@ -1319,12 +1341,14 @@ struct Handle : Base {
         // The split kernels update a working set in place; the fused pass
         // reads neighbours' old values after they are overwritten, so it
         // writes the other set.  A restored slot is never written.
-        const bool inplace = cfg.kernel == 1;
+        // (the single-pass family reads neighbours' old values across blocks:
+        // it and the split kernels beside it write the other working set)
+        const bool inplace = cfg.kernel == 1 && !cfg.onepass;
         const int G = opt.graph_chunk;
         for (int s = 0; s < n;) {
             const bool working = cur == wset[0] || cur == wset[1];
-            if (G > 0 && inplace && working && !timing_on && !opt.reversible && n - s >= G &&
-                (!rec || monitors_flushed())) {
+            if (G > 0 && cfg.kernel == 1 && (inplace || G % 2 == 0) && working && !timing_on && !opt.reversible &&
+                n - s >= G && (!rec || monitors_flushed())) {
                 GraphEx* g = nullptr;
                 int rc = graph_for(rec, g);
                 if (rc) return rc;
@@ -1333,7 +1357,7 @@ struct Handle : Base {
                 t += G;
                 tstep_val = t;
                 s += G;
-                continue;
+                continue;   // an even chunk of ping-pong steps ends in the set it started from
             }
             int ws = inplace && working ? cur : write_set();
             const int slot = rec ? insample_slot() : -1;
@@ -1764,6 +1788,7 @@ struct Streamer : StreamBase {
     // (tensor: six), pinned, uploaded plane-range by plane-range per slab
     T* einv = nullptr;
     T* d_einv = nullptr;                        // a device copy of einv when the budget holds it
+    DomDev<T> egeom{};                          // the domain's eps box geometry (elo, ehi, exa, exs)
     size_t ebox = 0;
     int ez0 = 0, ez1 = 0;
     size_t eplane = 0;
@@ -1973,7 +1998,9 @@ struct Streamer : StreamBase {
             if (ebox) {
                 ez0 = g.eps_lo[2];
                 ez1 = g.eps_hi[2];
-                eplane = ebox / (size_t)(ez1 - ez0);
+                // planes of the stored layout (rows of exs elements), the slabs' layout too
+                eplane = (size_t)(g.eps_hi[1] - g.eps_lo[1]) * gh.dd[0].exs;
+                egeom = gh.dd[0];
             }
         }
         const double* eps_in = g.eps;   // read once below, after admission; not kept
@@ -2059,9 +2086,10 @@ struct Streamer : StreamBase {
         const int nbank = adj ? (so.max_steps + K - 1) / K + 1 : 2;
         // admission: device workspaces + accumulators, host banks
         nws = o->overlap ? 2 : 1;
+        const size_t est = ebox ? eplane * (size_t)(ez1 - ez0) : 0;   // stored elements per component
         const double dev = (double)(nws * pool_cap + dmon_bytes),
                      host = (double)(nbank + (adj ? 2 : 0)) * bank_elems * sizeof(T) +
-                            (double)ebox * ncomp_eps * sizeof(T) + (adj ? 8.0 * gncomp * gelems : 0.0);
+                            (double)est * ncomp_eps * sizeof(T) + (adj ? 8.0 * gncomp * gelems : 0.0);
         double budget = o->mem_budget_bytes;
         if (budget <= 0) {
             size_t fr = 0, tot = 0;
@@ -2079,22 +2107,15 @@ struct Streamer : StreamBase {
             return fail(FDTD_E_NOMEM, b);
         }
         if (ebox) {
-            // eps^-1 in the field type, as the resident upload computes it
-            if (hipHostMalloc((void**)&einv, ebox * ncomp_eps * sizeof(T), 0) != hipSuccess) {
+            // eps^-1 in the field type and the stored row layout, as the resident upload computes it
+            std::vector<T> v;
+            Handle<T>::einv_rows(egeom, ncomp_eps, eps_in, g.eps_bg, v);
+            if (hipHostMalloc((void**)&einv, v.size() * sizeof(T), 0) != hipSuccess) {
                 (void)hipGetLastError();
                 einv = nullptr;
                 return fail(FDTD_E_NOMEM, "pinned host allocation of the material arrays failed");
             }
-            if (ncomp_eps == 6) {
-                for (size_t q = 0; q < ebox; ++q) {
-                    double m[6], r[6];
-                    for (int c = 0; c < 6; ++c) m[c] = eps_in[c * ebox + q];
-                    sym3_inverse(m, r);
-                    for (int c = 0; c < 6; ++c) einv[c * ebox + q] = (T)r[c];
-                }
-            } else {
-                for (size_t q = 0; q < ebox * ncomp_eps; ++q) einv[q] = (T)(1.0 / eps_in[q]);
-            }
+            std::memcpy(einv, v.data(), v.size() * sizeof(T));
         }
         for (int k = 0; k < nws; ++k)
             if (hipMalloc((void**)&pool[k], pool_cap) != hipSuccess ||
@@ -2108,7 +2129,7 @@ struct Streamer : StreamBase {
         }
         // eps^-1 stays on the device when the budget holds it beside the
         // workspaces: each visit then copies its planes device to device
-        const size_t ebytes = ebox * ncomp_eps * sizeof(T);
+        const size_t ebytes = est * ncomp_eps * sizeof(T);
         if (ebox && dev + (double)ebytes <= budget) {
             if (hipMalloc((void**)&d_einv, ebytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -2197,7 +2218,7 @@ struct Streamer : StreamBase {
             const int z0 = dv.elo[2] + o, z1 = dv.ehi[2] + o;
             for (int c = 0; c < ncomp_eps; ++c) {
                 T* dst = ncomp_eps == 6 ? const_cast<T*>(dv.tinv[c]) : const_cast<T*>(dv.epsinv[c]);
-                const size_t q0 = c * ebox + (size_t)(z0 - ez0) * eplane;
+                const size_t q0 = c * eplane * (size_t)(ez1 - ez0) + (size_t)(z0 - ez0) * eplane;
                 if (hipMemcpyAsync(dst, d_einv ? d_einv + q0 : einv + q0, (size_t)(z1 - z0) * eplane * sizeof(T),
                                    d_einv ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st) != hipSuccess)
                     return fail(FDTD_E_DEVICE, "slab eps upload failed");
@@ -2342,7 +2363,7 @@ struct Streamer : StreamBase {
             const int z0 = dv.elo[2] + o, z1 = dv.ehi[2] + o;
             for (int c = 0; c < ncomp_eps; ++c) {
                 T* dst = ncomp_eps == 6 ? const_cast<T*>(dv.tinv[c]) : const_cast<T*>(dv.epsinv[c]);
-                const size_t q0 = c * ebox + (size_t)(z0 - ez0) * eplane;
+                const size_t q0 = c * eplane * (size_t)(ez1 - ez0) + (size_t)(z0 - ez0) * eplane;
                 if (hipMemcpyAsync(dst, d_einv ? d_einv + q0 : einv + q0, (size_t)(z1 - z0) * eplane * sizeof(T),
                                    d_einv ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st) != hipSuccess)
                     return fail(FDTD_E_DEVICE, "slab eps upload failed");
@@ -2459,9 +2480,10 @@ struct Streamer : StreamBase {
         for (int s = 0; s < ns(); ++s) mx = std::max(mx, ext_hi(s) - ext_lo(s));
         out->max_extent = mx;
         out->step = t;
-        out->device_bytes = (double)(nws * pool_cap + dmon_bytes) + (d_einv ? (double)ebox * ncomp_eps * sizeof(T) : 0.0);
+        const double est = ebox ? (double)eplane * (ez1 - ez0) : 0.0;   // stored eps^-1 elements per component
+        out->device_bytes = (double)(nws * pool_cap + dmon_bytes) + (d_einv ? est * ncomp_eps * sizeof(T) : 0.0);
         out->host_bytes = (double)(bank.size() + (adj ? 2 : 0)) * bank_elems * sizeof(T) +
-                          (double)ebox * ncomp_eps * sizeof(T) + 8.0 * grad.size();
+                          est * ncomp_eps * sizeof(T) + 8.0 * grad.size();
         out->resident_bytes = resident_bytes;
         out->materials_resident = d_einv ? 1 : 0;
     }

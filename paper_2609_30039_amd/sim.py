@@ -22,7 +22,8 @@ class Simulation:
         self.dtype = np.float32 if dtype == "f32" else np.float64
         dt = B.FDTD_F32 if dtype == "f32" else B.FDTD_F64
         storage = {None: dt, "f32": B.FDTD_F32, "f64": B.FDTD_F64, "bf16": B.FDTD_BF16}[ckpt_storage]
-        kern = {"auto": B.FDTD_KERNEL_AUTO, "split": B.FDTD_KERNEL_SPLIT, "fused": B.FDTD_KERNEL_FUSED}[kernel]
+        kern = {"auto": B.FDTD_KERNEL_AUTO, "split": B.FDTD_KERNEL_SPLIT, "fused": B.FDTD_KERNEL_FUSED,
+                "onepass": B.FDTD_KERNEL_ONEPASS}[kernel]
         if max_steps is None:
             max_steps = max(max(s.n_steps for s in self.specs), 1)
         self.max_steps = max_steps
