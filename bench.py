@@ -567,7 +567,6 @@ def tensor_536(stream):
                         "every interior node (a 64^3 block of independent tensors repeated, seed 1006), Ex sheet, "
                         "Ex patch, FP32 forward",
             "mcups": round(mc, 1), "stepping_us_per_time_step": round(per_step_ms * 1e3, 2),
-            "launches_per_time_step": nl // BENCH_STEP,
             "algorithmic_bytes_per_time_step": bstep, "achieved_GBs": round(achieved, 1),
             "frac": round(achieved / RL.HBM_PEAK_GBS, 4), "launch_shape": tile,
             "inputs_s": round(t1 - t0, 1), "create_s": round(t2 - t1, 1)}

@@ -21,7 +21,7 @@ def test_pmc_summaries_match_the_bench_lookup():
         shapes = d["per_launch_shape"]
         assert shapes, p
         for key, e in shapes.items():
-            assert re.fullmatch(r"(split|fused),\d+,\d+", key), (p, key)
+            assert re.fullmatch(r"(split|fused|onepass),\d+,\d+", key), (p, key)
             kern, rows, kz = key.split(",")
             got = bench.traffic_from_profiles(d["kernel_source_hash"],
                                               {"kernel": kern, "tile_rows": int(rows), "tile_kz": int(kz)},
