@@ -21,7 +21,9 @@
  *     delta_eps omega_0^2 -> omega_p^2.
  *   - Symmetric tensor media (Section 2.3): eps at the grid nodes, inverted
  *     there, and applied to the curl through the node assembly
- *     (1/8) sum over the eight octants of R^T eps^-1 R (forward only).
+ *     (1/8) sum over the eight octants of R^T eps^-1 R; its transpose is
+ *     itself, and the gradient of a node's tensor collects, octant by octant,
+ *     the outer product of the E cotangent and the curl on the octant's edges.
  *   - Discrete adjoint, Eq. (3) of Section 3.1, with the transposes of
  *     Section 3.1 (opposite-direction differences, the absorber transpose,
  *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl).
@@ -336,7 +338,10 @@ static double cpml_T(double ybar, double *psibar, double b, double c, double ki)
  * accumulation of the permittivity gradient dJ/deps_c into g[c] (when g is
  * non-null) from the forward state U = u^n.  The seeds dJ/du^n are added by
  * the caller.  The order is the reverse of orc_step: H transpose, Lorentz
- * history transpose, E transpose.  work: four full-grid scratch arrays.
+ * history transpose, E transpose.  Tensor media: g holds six arrays, dJ/dp
+ * for the stored entries xx yy zz xy xz yz of eps^-1 at the nodes (an
+ * off-diagonal entry is one parameter for both of its matrix entries).
+ * work: four full-grid scratch arrays, seven for tensor media.
  */
 void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, double **g, double *work) {
     const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
@@ -427,8 +432,64 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                 }
     }
 
+    /* ---- tensor media: the node-tensor gradient, then the curl cotangent ---- */
+    double *Cb[3] = {work + 4 * N, work + 5 * N, work + 6 * N};
+    if (P->einvT[0]) {
+        /* the stretched curl of the forward step from u^n (memories read, not
+           written), zero on masked edges: the y of E += S (assembly) y */
+        for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        size_t p = IDX(P, i, j, k);
+                        Cb[c][p] = e_masked(P, c, x) ? 0.0 : curl_minus(P, U, c, x, p, 0);
+                    }
+        }
+        if (g) {
+            /* dJ/dp_q for the stored entry q = (a, b) of eps^-1 at node v (one
+               parameter for both A_ab and A_ba): with u = R_s (S Ebar) and
+               y = R_s curl the three edges of octant s,
+               dJ/dA_ab = 1/8 sum_s u_a y_b; p_ab collects A_ab and A_ba */
+            static const int qa[6] = {0, 1, 2, 0, 0, 1}, qb[6] = {0, 1, 2, 1, 2, 2};
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        const int v[3] = {i, j, k};
+                        const size_t pv = IDX(P, i, j, k);
+                        for (int s = 0; s < 8; ++s) {
+                            double u[3], y[3];
+                            for (int b = 0; b < 3; ++b) {
+                                int w[3] = {v[0], v[1], v[2]};
+                                w[b] -= (s >> b) & 1;        /* 1: the b edge arriving at v */
+                                u[b] = P->S * edge_curl(P, Epb, b, w);
+                                y[b] = edge_curl(P, Cb, b, w);
+                            }
+                            for (int q = 0; q < 6; ++q) {
+                                const int a = qa[q], b = qb[q];
+                                g[q][pv] += (a == b ? u[a] * y[a] : u[a] * y[b] + u[b] * y[a]) / 8.0;
+                            }
+                        }
+                    }
+        }
+        /* Cbar = S (assembly) Ebar on the unmasked edges.  The assembly is its
+           own transpose: each octant's R_s^T eps^-1 R_s is symmetric, and the
+           masked edges (zero in Ebar, no update) drop out of rows and columns */
+        for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    for (int i = 0; i < nx; ++i) {
+                        int x[3] = {i, j, k};
+                        Cb[c][IDX(P, i, j, k)] = e_masked(P, c, x) ? 0.0 : P->S * tensor_apply(P, Epb, c, x);
+                    }
+        }
+    }
+
     /* ---- gradient: dJ/deps_c accumulates dE_pre/deps_c * Ebar_pre ---- */
-    if (g) {
+    if (g && !P->einvT[0]) {
         for (int c = 0; c < 3; ++c) {
             if (!g[c]) continue;
 #pragma omp parallel for schedule(static)
@@ -468,9 +529,14 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                             Dbar[p] = 0.0;
                             continue;
                         }
-                        double ep = P->eps[c][p];
-                        double coef = is_lorentz(P, p) ? 1.0 / (ep + 0.25 * gg) : 1.0 / ep;
-                        double ybar = P->S * coef * sgn * Epb[c][p];
+                        double ybar;
+                        if (P->einvT[0]) {
+                            ybar = sgn * Cb[c][p];
+                        } else {
+                            double ep = P->eps[c][p];
+                            double coef = is_lorentz(P, p) ? 1.0 / (ep + 0.25 * gg) : 1.0 / ep;
+                            ybar = P->S * coef * sgn * Epb[c][p];
+                        }
                         if (P->slab[a][x[a]])
                             Dbar[p] = cpml_T(ybar, &A->psiE[c][a][p], P->bE[a][x[a]], P->cE[a][x[a]],
                                              P->kiE[a][x[a]]);

@@ -202,7 +202,7 @@ class OracleSim:
         self.W0, self.WOLD0, self.NSTATE = state_layout(max(self.npole, 1))
         self.P = P
         self.u = np.zeros((self.NSTATE, self.N))
-        self.work = np.zeros((4, self.N))
+        self.work = np.zeros((7 if self.tensor else 4, self.N))
         self.t = 0
         # sources: flattened node lists
         self.src_comp, self.src_idx, self.src_wave = [], [], []
@@ -303,7 +303,7 @@ class OracleSim:
         sa = self._state_struct(a)
         su = self._state_struct(u)
         if g is not None:
-            gp = (C.c_void_p * 3)(_ptr(g[0]), _ptr(g[1]), _ptr(g[2]))
+            gp = (C.c_void_p * len(g))(*[_ptr(g[q]) for q in range(len(g))])
             _lib.orc_adjoint_step(C.byref(self.P), C.byref(sa), C.byref(su), C.cast(gp, C.c_void_p),
                                   _ptr(self.work))
         else:
@@ -391,6 +391,9 @@ class OracleSim:
                  return_adjoint: bool = False):
         """dJ/deps per component [3][nz][ny][nx] for an objective whose
         cotangents w.r.t. the monitors are ``cot``, after n_steps from u0.
+        Tensor media: [6][nz][ny][nx], dJ/deps for the stored entries xx yy zz
+        xy xz yz of the node tensors, an off-diagonal entry being one
+        parameter for both of its matrix entries.
 
         Forward states are regenerated by recursive bisection: to reverse
         steps [lo, hi) from u^lo, advance a copy to the midpoint, reverse the
@@ -398,12 +401,9 @@ class OracleSim:
         if any(self.per):
             raise ValueError("periodic domains: this oracle has no adjoint across periodic seams (the library "
                              "refuses gradients there too)")
-        if self.tensor:
-            raise ValueError("tensor media: this oracle has no adjoint for node-assembled tensors (the library "
-                             "refuses gradients there too)")
         u_start = np.zeros_like(self.u) if u0 is None else u0.copy()
         a = np.zeros_like(self.u)
-        g = np.zeros((3, self.N))
+        g = np.zeros((6 if self.tensor else 3, self.N))
         self._add_seeds(a, n_steps, cot)
         # one state buffer per recursion depth, reused: a fresh copy per
         # bisection would page in a whole new state every time
@@ -430,8 +430,27 @@ class OracleSim:
 
         if n_steps > 0:
             reverse(0, n_steps, u_start, 0)
-        g = g.reshape((3,) + self.shape3)
+        if self.tensor:
+            g = self._tensor_eps_gradient(g)
+        g = g.reshape((len(g),) + self.shape3)
         return (g, a) if return_adjoint else g
+
+    def _tensor_eps_gradient(self, gp: np.ndarray) -> np.ndarray:
+        """From dJ/dp of the stored entries of A = eps^-1 to those of eps.
+        As symmetric matrices under <X, Y> = tr(XY), the gradient of A is G
+        with G_aa = dJ/dp_aa and G_ab = dJ/dp_ab / 2; dA = -A deps A gives
+        the gradient of eps Q = -A G A, whose stored entries are Q_aa and
+        2 Q_ab."""
+        N = self.N
+        G = np.zeros((N, 3, 3))
+        A = np.zeros((N, 3, 3))
+        for q, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+            w = 1.0 if a == b else 0.5
+            G[:, a, b] = G[:, b, a] = w * gp[q]
+            A[:, a, b] = A[:, b, a] = self.einvT[q].reshape(-1)
+        Q = -np.matmul(np.matmul(A, G), A)
+        return np.stack([(1.0 if a == b else 2.0) * Q[:, a, b]
+                         for (a, b) in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))])
 
 
 def run_forward(spec, n_steps: Optional[int] = None) -> OracleSim:

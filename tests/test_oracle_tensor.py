@@ -14,6 +14,13 @@ inside an absorbing face, unit spectral radius when the face normal is a
 principal axis with a non-intermediate eigenvalue and growth for the
 rejected cases (an intermediate normal eigenvalue, principal axes rotated
 against the normal).
+
+The adjoint (Section 3.1 with the tensor of Section 2.3): the dot-product
+identity of the step map with admitted tensors in absorbing faces; the
+one-step eps^-1 gradient against the derivative of the octant-built
+assembly; dJ/deps of the stored entries against fourth-order central
+differences of whole solves and a Taylor remainder falling as h^2; and an
+isotropic tensor's gradient against the scalar medium's.
 """
 import math
 
@@ -278,3 +285,257 @@ def test_discrete_energy_invariant_rotated_tensor():
         hist.append(energy(h_prev))
     hist = np.asarray(hist)
     assert np.max(np.abs(hist - hist[0])) / abs(hist[0]) < 1e-11
+
+
+# ------------------------------------------------------------ the adjoint
+def _tensor_adjoint_case(seed):
+    """Absorbing faces on every side holding admitted tensors (z faces: the
+    normal a principal axis with the largest eigenvalue; x and y faces: the
+    isotropic background), random rotated tensors inside, PEC walls."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (10, 9, 12)
+    nx, ny, nz = shape
+    pml = (2, 2, 2, 3, 3, 2)
+    box = ((2, 2, 0), (8, 6, 12))           # inside the x and y faces, through both z faces
+    bx, by, bz = 6, 4, 12
+    eps = random_tensors(rng, (bx, by, bz), 1.0, 3.0)
+    face = _pack(_rz(0.4) @ np.diag([1.5, 2.5, 4.0]) @ _rz(0.4).T)
+    eps[:, :3] = face[:, None, None, None]
+    eps[:, -2:] = face[:, None, None, None]
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), pml=pml, eps_kind="tensor", eps_box=box, eps=eps,
+                        eps_bg=1.2)
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    x = rng.standard_normal(sim.u.shape) * dof
+    y = rng.standard_normal(sim.u.shape) * dof
+    return sim, x, y
+
+
+@pytest.mark.parametrize("nsteps", [1, 40])
+def test_tensor_adjoint_dot_product(nsteps):
+    """<A x, y> = <x, A^T y> for the source-free step map of a tensor medium
+    with absorbing faces, to round-off: the transposed assembly, the curl
+    and absorber transposes around it (Section 3.1)."""
+    sim, x, y = _tensor_adjoint_case(31)
+    ax = x.copy()
+    for t in range(nsteps):
+        sim.step_state(ax, t, sources=False)
+    aty = y.copy()
+    for t in range(nsteps):
+        sim.adjoint_step_state(aty, x, None)
+    dof = sim.dof_mask()
+    lhs = np.sum(ax * y * dof)
+    rhs = np.sum(x * aty * dof)
+    scale = np.linalg.norm(ax * dof) * np.linalg.norm(y)
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    assert np.all(aty[~dof] == 0.0)
+
+
+def test_tensor_gradient_one_step_is_the_octant_outer_product():
+    """One step from a random state: the eps^-1 gradient the adjoint step
+    accumulates equals, at every node, 1/8 sum over its octants of the
+    outer product of S Ebar and the curl on the octant's edges, built here
+    from the assembled matrix's definition: d<Ebar, S M c>/dA_v with M
+    differentiated through the octant enumeration (finite differences of
+    the exactly linear map M(A) are exact up to rounding)."""
+    rng = np.random.Generator(np.random.PCG64(33))
+    shape = (5, 4, 6)
+    nx, ny, nz = shape
+    box = ((0, 0, 0), shape)
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), eps_kind="tensor", eps_box=box,
+                        eps=random_tensors(rng, shape), eps_bg=1.4)
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    u = np.zeros_like(sim.u)
+    u[O.F0 + 3:O.F0 + 6] = rng.standard_normal((3, sim.N))
+    a = rng.standard_normal(sim.u.shape) * dof
+    a[O.F0 + 3:] = 0.0                        # E cotangents only: the H transpose adds nothing
+    ebar = np.concatenate([a[O.F0 + c] for c in range(3)])
+    g = np.zeros((6, sim.N))
+    sim.adjoint_step_state(a.copy(), u, g)
+    H = np.stack([u[O.F0 + 3 + c].reshape(sim.shape3) for c in range(3)])
+    edof = dof[:3].reshape(-1)
+    curl = _curl_minus(H).reshape(-1) * edof
+    base = spec.eps_nodes()
+    S = spec.courant
+    for (i, j, k) in [(0, 0, 0), (2, 1, 3), (4, 3, 5), (3, 0, 2)]:
+        p = (k * ny + j) * nx + i
+        for q, (ca, cb) in enumerate(COMP):
+            # J(A) = <Ebar, S M(A) c> is linear in A_v: its derivative along the
+            # stored entry q (both matrix entries for q >= 3) is a difference
+            def J(delta):
+                inv = sim.einvT.copy()
+                inv[q].reshape(-1)[p] += delta
+                s2 = W.DomainSpec(**{**spec.__dict__})
+                M = _assembly_from_inverse(s2, inv)
+                return ebar @ (S * (M @ curl) * edof)
+            want = (J(0.5) - J(-0.5)) / 1.0
+            assert abs(g[q, p] - want) <= 1e-12 * (1.0 + abs(want)), (i, j, k, q, g[q, p], want)
+
+
+def _assembly_from_inverse(spec, inv):
+    """The octant assembly with eps^-1 at the in-grid nodes taken from inv
+    [6][N] (the background past the arrays)."""
+    nx, ny, nz = spec.shape
+    n = (nx, ny, nz)
+    N = nx * ny * nz
+    inv = inv.reshape(6, N)
+
+    def einv(v):
+        if any(v[a] >= n[a] for a in range(3)):
+            return np.eye(3) / spec.eps_bg
+        p = (v[2] * ny + v[1]) * nx + v[0]
+        m = np.zeros((3, 3))
+        for q, (a, b) in enumerate(COMP):
+            m[a, b] = m[b, a] = inv[q, p]
+        return m
+
+    def edge(b, start):
+        if any(start[a] < 0 or start[a] >= n[a] for a in range(3)):
+            return None
+        if start[(b + 1) % 3] == 0 or start[(b + 2) % 3] == 0:
+            return None
+        return b * N + (start[2] * ny + start[1]) * nx + start[0]
+
+    M = np.zeros((3 * N, 3 * N))
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            for i in range(nx + 1):
+                v = (i, j, k)
+                A = einv(v)
+                for s in range(8):
+                    rows = []
+                    for b in range(3):
+                        st = list(v)
+                        st[b] -= (s >> b) & 1
+                        rows.append(edge(b, st))
+                    for a in range(3):
+                        for b in range(3):
+                            if rows[a] is not None and rows[b] is not None:
+                                M[rows[a], rows[b]] += A[a, b] / 8.0
+    return M
+
+
+def _tensor_fd_problem():
+    """A tensor design box in a domain with absorbing faces, a sheet and a
+    point source, a patch spectrum, a flux plane and a probe."""
+    rng = np.random.Generator(np.random.PCG64(41))
+    pml = 4
+    shape = (10 + 2 * pml, 9 + 2 * pml, 12 + 2 * pml)
+    nx, ny, nz = shape
+    lo, hi = (pml + 1, pml + 1, pml + 3), (nx - pml - 1, ny - pml - 1, nz - pml - 3)
+    bx = [hi[a] - lo[a] for a in range(3)]
+    nsteps = 50
+    spec = W.DomainSpec(
+        shape=shape, courant=W.courant_3d(), pml=(pml,) * 6, eps_kind="tensor", eps_box=(lo, hi),
+        eps=random_tensors(rng, tuple(bx), 1.0, 3.0), eps_bg=1.0,
+        sources=[W.SourceSpec("plane_z", 0, (0, 0, pml + 1), W.gaussian_sine(nsteps, 0.6, 6.0, 18.0)),
+                 W.SourceSpec("point", 1, (nx // 2, ny // 2, pml + 2), W.gaussian_sine(nsteps, 0.5, 5.0, 15.0))],
+        monitors=[W.MonitorSpec("patch_z", comp=1, pos=(0, 0, nz - pml - 2), rect=(5, 13, 5, 12),
+                                omega_dt=np.array([0.4, 0.55, 0.7])),
+                  W.MonitorSpec("flux_z", pos=(0, 0, nz - pml - 3), rect=(0, nx, 0, ny),
+                                omega_dt=np.array([0.5, 0.6])),
+                  W.MonitorSpec("probe", comp=0, pos=(nx // 2, ny // 2 + 1, nz - pml - 4))],
+        n_steps=nsteps)
+    return spec
+
+
+def _objective(sim):
+    """J = sum |E_y patch|^2 + sum_f flux_f + sum probe^2 and its monitor cotangents."""
+    sp0, sp1, pr = sim.spectra(0), sim.spectra(1), sim.probe(2)
+    J = np.sum(np.abs(sp0) ** 2) + np.sum(O.OracleSim.flux_from_spectra(sp1)) + np.sum(pr ** 2)
+    g1 = np.zeros_like(sp1)
+    g1[:, 0], g1[:, 3], g1[:, 1], g1[:, 2] = sp1[:, 3], sp1[:, 0], -sp1[:, 2], -sp1[:, 1]
+    return J, {0: 2.0 * sp0, 1: g1, 2: 2.0 * pr}
+
+
+def _run_J(spec):
+    sim = O.OracleSim(spec)
+    sim.step(spec.n_steps)
+    return _objective(sim)[0]
+
+
+def test_tensor_gradient_central_differences():
+    """dJ/deps for the stored tensor entries (an off-diagonal entry moves both
+    matrix entries) from the transposed sweep equals fourth-order central
+    differences of the full solve, for every entry at three nodes."""
+    spec = _tensor_fd_problem()
+    sim = O.OracleSim(spec)
+    sim.step(spec.n_steps)
+    J, cot = _objective(sim)
+    g = sim.gradient(cot, spec.n_steps)
+    assert g.shape == (6,) + sim.shape3
+    (i0, j0, k0), _ = spec.eps_box
+    for (li, lj, lk) in [(1, 2, 1), (4, 5, 3), (7, 3, 5)]:
+        i, j, k = i0 + li, j0 + lj, k0 + lk
+        for q in range(6):
+            h = 2e-3
+            vals = {}
+            for m in (-2, -1, 1, 2):
+                e = spec.eps.copy()
+                e[q, lk, lj, li] += m * h
+                vals[m] = _run_J(W.DomainSpec(**{**spec.__dict__, "eps": e}))
+            fd = (8.0 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12.0 * h)
+            ad = g[q, k, j, i]
+            assert abs(ad - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(J), (i, j, k, q, ad, fd)
+
+
+def test_tensor_gradient_taylor_remainder():
+    """Along a random symmetric direction over the whole box the remainder
+    J(eps + h d) - J(eps) - h <g, d> falls as h^2."""
+    spec = _tensor_fd_problem()
+    sim = O.OracleSim(spec)
+    sim.step(spec.n_steps)
+    J0, cot = _objective(sim)
+    g = sim.gradient(cot, spec.n_steps)
+    (i0, j0, k0), (i1, j1, k1) = spec.eps_box
+    gb = g[:, k0:k1, j0:j1, i0:i1]
+    rng = np.random.Generator(np.random.PCG64(12))
+    d = rng.standard_normal(spec.eps.shape)
+    rem = []
+    for h in (1e-2, 5e-3, 2.5e-3):
+        s2 = W.DomainSpec(**{**spec.__dict__, "eps": spec.eps + h * d})
+        rem.append(abs(_run_J(s2) - J0 - h * np.sum(gb * d)))
+    rem = np.asarray(rem)
+    r = rem[:-1] / rem[1:]
+    assert np.all(r > 3.5) and np.all(r < 4.5), (rem, r)
+
+
+def test_isotropic_tensor_gradient_is_the_scalar_gradient():
+    """eps = e I over the whole grid with background e: the derivative of J
+    along a uniform change of e is the same whether e is the scalar medium's
+    (the sum of its edge gradient) or every node tensor's (the sum of the
+    diagonal node gradients, the high-wall background nodes moved too: their
+    share is the derivative with the background fixed subtracted, by central
+    differences of the background alone)."""
+    rng = np.random.Generator(np.random.PCG64(24))
+    shape = (7, 6, 8)
+    nx, ny, nz = shape
+    e = 2.0
+    nsteps = 30
+    common = dict(shape=shape, courant=W.courant_3d(), pml=(2,) * 6, eps_box=((0, 0, 0), shape), eps_bg=e,
+                  sources=[W.SourceSpec("point", 2, (3, 3, 3), W.gaussian_sine(nsteps, 0.6, 5.0, 12.0))],
+                  monitors=[W.MonitorSpec("probe", comp=1, pos=(4, 2, 5))], n_steps=nsteps)
+    t = W.DomainSpec(eps_kind="tensor", eps=uniform_tensor(shape, e * np.eye(3)), **common)
+    s = W.DomainSpec(eps_kind="iso", eps=np.full((1, nz, ny, nx), e), **common)
+    out = []
+    for spec in (t, s):
+        sim = O.OracleSim(spec)
+        sim.step(nsteps)
+        pr = sim.probe(0)
+        g = sim.gradient({0: 2.0 * pr}, nsteps)
+        out.append((np.sum(pr ** 2), g))
+    (Jt, gt), (Js, gs) = out
+    assert abs(Jt - Js) <= 1e-12 * abs(Js)
+    d_scalar = gs.sum()
+    h = 1e-4
+    jb = [_run_probe_J(W.DomainSpec(**{**t.__dict__, "eps_bg": e + m * h})) for m in (-1, 1)]
+    d_bg = (jb[1] - jb[0]) / (2 * h)
+    d_tensor = gt[:3].sum() + d_bg
+    assert abs(d_tensor - d_scalar) <= 1e-7 * abs(d_scalar), (d_tensor, d_scalar, d_bg)
+
+
+def _run_probe_J(spec):
+    sim = O.OracleSim(spec)
+    sim.step(spec.n_steps)
+    return np.sum(sim.probe(0) ** 2)
