@@ -75,8 +75,12 @@ enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_BF16 = 2 };
    the slab) the normal must be a principal axis (zero off-diagonal entries
    with it) whose eigenvalue is the largest or the smallest: else
    FDTD_E_UNSTABLE, checked node by node.  TENSOR domains take no dispersive
-   box, no periodic axis, no gradient, no reversible mode and no fused
-   kernels (FDTD_E_INVALID), and one scratch curl of 3 field arrays each. */
+   box, no periodic axis, no reversible mode and no fused kernels
+   (FDTD_E_INVALID), and one scratch curl of 3 field arrays each.  Their
+   gradient (Section 3.1 through the assembly, which is its own transpose)
+   is dJ/deps of the six stored entries of each node tensor in the gradient
+   box, an off-diagonal entry counting as one parameter for both of its
+   matrix entries. */
 enum { FDTD_EPS_ISO = 0, FDTD_EPS_DIAG = 1, FDTD_EPS_TENSOR = 2 };
 enum { FDTD_SRC_POINT = 0, FDTD_SRC_PLANE_Z = 1 };
 enum { FDTD_MON_PROBE = 0, FDTD_MON_FLUX_Z = 1, FDTD_MON_PATCH_Z = 2 };
@@ -270,7 +274,9 @@ int fdtd_monitor_dft(fdtd_t h, int32_t domain, int32_t monitor, int32_t op, void
 int fdtd_get_field(fdtd_t h, int32_t domain, int32_t comp, void *host_buf, size_t bytes);
 int fdtd_set_field(fdtd_t h, int32_t domain, int32_t comp, const void *host_buf, size_t bytes);
 
-/* dJ/deps over the gradient box: double [ncomp][gz][gy][gx]. */
+/* dJ/deps over the gradient box: double [ncomp][gz][gy][gx], ncomp 1 (ISO),
+   3 (DIAG: per E component) or 6 (TENSOR: xx, yy, zz, xy, xz, yz at the
+   nodes).  FDTD_E_RANGE if bytes is below ncomp * cells * 8. */
 int fdtd_get_grad(fdtd_t h, int32_t domain, double *host_buf, size_t bytes);
 
 /* Replace the permittivity of a domain (same layout as the descriptor). */

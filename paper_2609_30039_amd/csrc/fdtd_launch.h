@@ -74,6 +74,12 @@ template <typename T>
 // the split family; cs[q]: stream of split class q of that pass
 void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, hipStream_t s, int pass,
                 const hipStream_t* cs);
+// the E-node work of the split adjoint for tensor domain dom (n: its cells):
+// the H-update transpose into the new Ebar, then u = S M Ebar into the
+// scratch Et, the E-side memory cotangents and the node-tensor gradient;
+// launch_adj's H-node pass completes the step
+template <typename T>
+void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s);
 template <typename T>
 void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s);
 template <typename T>

@@ -406,6 +406,8 @@ struct Handle : Base {
             if (!s.grad) continue;
             const int n[3] = {s.n[0], s.n[1], s.n[2]};
             for (int pass = 0; pass < 2; ++pass) {
+                // a tensor domain's E-node work has launches of its own (launch_tens_adj)
+                if (pass == 0 && s.eps_kind == FDTD_EPS_TENSOR) continue;
                 const int L0 = s.pml[0], L1 = s.pml[1];
                 const int xa = L0 > 0 ? std::min(L0 + (pass == 0 ? 1 : 0), n[0]) : 0;
                 const int xb = L1 > 0 ? std::max(n[0] - L1 - (pass == 1 ? 1 : 0), xa) : n[0];
@@ -980,7 +982,7 @@ struct Handle : Base {
                 d.ghi[a] = s.grad_hi[a];
                 h.gelems *= (size_t)(s.grad_hi[a] - s.grad_lo[a]);
             }
-            h.gncomp = d.eps_diag ? 3 : 1;
+            h.gncomp = d.tens ? 6 : (d.eps_diag ? 3 : 1);
         }
         d.rev = opt.reversible && s.grad ? 1 : 0;
         h.rec_step = 0;
@@ -1089,9 +1091,8 @@ struct Handle : Base {
             }
         }
         if (s.eps_kind == FDTD_EPS_TENSOR) {
-            // the tensor path is forward-only, nondispersive and walled
+            // the tensor path is nondispersive and walled
             if (s.n_lorentz) return fail(FDTD_E_INVALID, "tensor media take no dispersive box");
-            if (s.grad) return fail(FDTD_E_INVALID, "tensor media take no gradient");
             if (s.periodic[0] || s.periodic[1] || s.periodic[2])
                 return fail(FDTD_E_INVALID, "tensor media take no periodic axis");
             if (opt.kernel == FDTD_KERNEL_FUSED) return fail(FDTD_E_INVALID, "tensor media need the split kernels");
@@ -1401,6 +1402,8 @@ struct Handle : Base {
         hipStream_t cs[kAdjClasses1];
         for (int q = 0; q < kAdjClasses1; ++q) cs[q] = st;
         launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 0, cs);
+        for (int q = 0; q < ndom; ++q)
+            if (dd[q].tens && dd[q].grad) launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
         if (cfg.kernel == 1) launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 1, cs);
         return FDTD_OK;
     }

@@ -45,5 +45,5 @@ def forward_bytes(spec, word: int) -> int:
 
 def adjoint_bytes(spec, word: int) -> int:
     gb = _box_cells(spec.grad_box) if spec.grad_box is not None else 0
-    nacc = 3 if spec.eps_kind == "diag" else 1
+    nacc = {"diag": 3, "tensor": 6}.get(spec.eps_kind, 1)
     return forward_bytes(spec, word) + gb * (3 * word + 16 * nacc)

@@ -129,7 +129,7 @@ class Simulation:
     def grad(self, domain: int = 0) -> np.ndarray:
         s = self.specs[domain]
         lo, hi = s.grad_box
-        nc = 3 if s.eps_kind == "diag" else 1
+        nc = {"diag": 3, "tensor": 6}.get(s.eps_kind, 1)
         out = np.zeros((nc, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]))
         B.fdtd_get_grad(self.h, domain, out)
         return out
@@ -230,7 +230,7 @@ class StreamedSimulation:
     def grad(self) -> np.ndarray:
         s = self.spec
         lo, hi = s.grad_box
-        nc = 3 if s.eps_kind == "diag" else 1
+        nc = {"diag": 3, "tensor": 6}.get(s.eps_kind, 1)
         out = np.zeros((nc, hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]))
         B.fdtd_stream_get_grad(self.h, out)
         return out

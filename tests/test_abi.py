@@ -239,12 +239,14 @@ def test_tensor_admission_node_by_node():
 
 
 def test_tensor_media_combinations_refused():
-    """The tensor path is forward-only, nondispersive, walled and split."""
+    """The tensor path is nondispersive, walled and split, and has no
+    reversible mode; a gradient over its node tensors is admitted."""
     m = 2.0 * np.eye(3)
     _refused(_tensor_spec(m, lorentz=[W.LorentzSpec((2, 2, 2), (5, 5, 5), 1.0, 0.3, 0.01)]), B.FDTD_E_INVALID)
-    _refused(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID)
     _refused(_tensor_spec(m, pml=(0, 0, 0, 0, 3, 3), periodic=(1, 0, 0)), B.FDTD_E_INVALID)
     _refused(_tensor_spec(m), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
+    _refused(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID, reversible=1)
+    _passes_validation(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))))
 
 
 def _stream_refused(spec, code, **kw):
