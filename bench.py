@@ -27,6 +27,9 @@ Alongside, on the same JSON line:
     the 148^3 workload with 3 and 16 poles;
   * tensor_536: the 536^3 domain with a rotated symmetric tensor at every
     interior node (the two-pass tensor E update), FP32 forward;
+  * tensor_adjoint_536: its reverse sweep with the gradient over every node
+    tensor (160 steps, 8 slots, FP32 and FP64) and the adjoint step's
+    kernel time against the forward step's;
   * streamed_536: the headline workload through host-streamed causal slabs
     (state in host memory, 64-plane slabs, 32 steps per visit);
   * streamed_adjoint_256: resident against streamed time to gradient and
@@ -572,6 +575,79 @@ def tensor_536(stream):
             "inputs_s": round(t1 - t0, 1), "create_s": round(t2 - t1, 1)}
 
 
+def tensor_adjoint_536(stream):
+    """The reverse sweep of tensor media at 536^3: dJ/deps of all six entries
+    of every interior node tensor (512^3 nodes), |DFT Ex|^2 on the 64x64
+    patch moved 60 planes past the source so that 160 steps reach it;
+    binomial replay in 8 slots, FP32 and FP64, the FP32 gradient against
+    FP64 on the 64^3 block of nodes between the source and the patch; and
+    the adjoint step's kernel time (HIP events on the library's stream,
+    one adjoint step at a time from a stored state) against the forward
+    step's."""
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import adjoint as A
+    from paper_2609_30039_amd.sim import Simulation
+    N, slots, R = 160, 8, 10
+    spec = W.anisotropic_tensor(n_steps=N)
+    pml = spec.pml[4]
+    spec.monitors[0].pos = (0, 0, pml + 65)
+    spec.grad_box = spec.eps_box
+    (gx0, gy0, gz0), _ = spec.grad_box
+    p0 = spec.monitors[0].rect
+    blk = (slice(0, 64), slice(p0[2] - gy0, p0[2] - gy0 + 64), slice(p0[0] - gx0, p0[0] - gx0 + 64))
+    out = {"workload": f"536^3 tensor workload with the gradient over every interior node tensor (6 entries), "
+                       f"|DFT Ex|^2 on the 64x64 patch 60 planes past the source, {N} steps, {slots} binomial slots",
+           "cells": spec.ncells}
+    grads = {}
+    for dtype, tile in (("f32", {"kernel": "split", "tile_rows": 8, "tile_kz": 8}),
+                        ("f64", {"kernel": "split", "tile_rows": 8, "tile_kz": 4})):
+        t0 = time.perf_counter()
+        sim = Simulation(spec, dtype=dtype, n_ckpt=slots, max_steps=N, stream=stream, graph_chunk=32, **tile)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # kernel time of single steps: forward, then the adjoint step from the stored u^0
+        sim.save(0)
+        sim.timing(1)
+        sim.step(R, record=False)
+        fms, _ = sim.timing(2)
+        sim.timing(0)
+        sim.restore(0)
+        sim.timing(1)
+        for _ in range(R):
+            sim.restore(0)
+            sim.adjoint_begin(1)
+            sim.step_adjoint(1)
+        ams, na = sim.timing(2)
+        sim.timing(0)
+        sim.reset()
+        plan = A.RevolvePlan(N, slots)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        last = A.forward_record(sim, plan)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        sim.set_cotangent(0, 2.0 * sim.spectra(0))
+        A.reverse_sweep(sim, plan, *last)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        g = sim.grad(0)
+        grads[dtype] = g[(slice(None),) + blk].astype(np.float64)
+        del g
+        out[dtype] = {"launch_shape": tile, "create_s": round(t1 - t0, 1), "forward_s": round(t3 - t2, 3),
+                      "reverse_s": round(t4 - t3, 3), "reverse_over_forward": round((t4 - t3) / (t3 - t2), 3),
+                      "forward_evaluations": plan.forward_evals + 1, "device_bytes": sim.memory_bytes(),
+                      "forward_step_ms_events": round(fms / R, 3), "adjoint_step_ms_events": round(ams / na, 3),
+                      "adjoint_over_forward_step": round((ams / na) / (fms / R), 3)}
+        log(f"tensor adjoint 536^3 {dtype}: {out[dtype]}")
+        sim.close()
+        del sim
+    ref = grads["f64"]
+    out["grad_rel_l2_fp32_vs_fp64_64cube"] = float(f"{np.linalg.norm(grads['f32'] - ref) / np.linalg.norm(ref):.3e}")
+    out["grad_offdiag_share"] = float(f"{np.linalg.norm(ref[3:]) / np.linalg.norm(ref):.3e}")
+    return out
+
+
 def streamed_536(stream):
     """Host-streamed causal slabs on the 536^3 workload: slabs of 64 core
     planes, K = 32 steps per visit (33 halo planes per cut), FP32 forward
@@ -689,6 +765,7 @@ def main():
         out["batch_48"] = batch_48(stream)
         out["several_poles"] = several_poles(stream, out["cache_resident_148"]["launch_shape"])
         out["tensor_536"] = tensor_536(stream)
+        out["tensor_adjoint_536"] = tensor_adjoint_536(stream)
         out["streamed_536"] = streamed_536(stream)
         out["streamed_adjoint_256"] = streamed_adjoint_256(stream)
     out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)

@@ -290,3 +290,69 @@ def test_anisotropic_tensor_536_local_windows(dtype, tol):
         for q in range(6):
             r = rel(got[q][sl][inner], o.field(q)[inner])
             assert r < tol, (c, W.COMP_NAMES[q], r)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-5)])
+def test_anisotropic_tensor_536_adjoint(dtype, tol):
+    """The 536^3 tensor workload with the gradient over its whole interior,
+    one step from random forward and cotangent states in the tuned launch
+    shape: the dot-product identity <A x, y> = <x, A^T y> over the whole
+    grid, and (FP64) the new cotangent fields and the node-tensor gradient
+    element by element on three 20^3 windows against the oracle's adjoint
+    step on the window with a 5-plane margin (a window's faces perturb one
+    plane per step, the tensor's assembly one more)."""
+    spec = W.anisotropic_tensor(n_steps=4)
+    spec.sources = []
+    spec.monitors = []
+    spec.grad_box = spec.eps_box
+    x = _random_fields(spec.shape, 7005)
+    y = _random_fields(spec.shape, 7006)
+    sim = _start(spec, x, dtype, kernel="split", tile_rows=8, tile_kz=8, n_ckpt=1, max_steps=1)
+    sim.save(0)
+    sim.step(1, record=False)
+    ax = [sim.field(q) for q in range(6)]
+    sim.restore(0)
+    sim.adjoint_begin(1)
+    for q in range(6):
+        sim.set_field(q, y[q], adjoint=True)
+    sim.step_adjoint(1)
+    aty = [sim.field(q, adjoint=True) for q in range(6)]
+    lhs, rhs = _inner(ax, y), _inner(x, aty)
+    scale = _norm(ax) * _norm(y)
+    print(f"tensor 536^3 {dtype}: dot-product defect {abs(lhs - rhs) / scale:.2e}", flush=True)
+    assert abs(lhs - rhs) <= tol * scale, (lhs, rhs, scale)
+    del ax
+    if dtype != "f64":
+        sim.close()
+        return
+    g = sim.grad()
+    sim.close()
+    del sim
+    (bx0, by0, bz0), _ = spec.eps_box
+    m, w = 5, 20
+    for c in ((40, 45, 50), (268, 261, 270), (494, 500, 497)):
+        lo = [c[a] - w // 2 - m for a in range(3)]
+        hi = [c[a] + w // 2 + m for a in range(3)]
+        shape = tuple(hi[a] - lo[a] for a in range(3))
+        win = W.DomainSpec(shape=shape, courant=spec.courant, eps_kind="tensor", eps_box=((0, 0, 0), shape),
+                           eps=np.ascontiguousarray(spec.eps[:, lo[2] - bz0:hi[2] - bz0, lo[1] - by0:hi[1] - by0,
+                                                            lo[0] - bx0:hi[0] - bx0]), eps_bg=1.0)
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        o = O.OracleSim(win)
+        u = np.zeros_like(o.u)
+        a = np.zeros_like(o.u)
+        for q in range(6):
+            u[O.F0 + q] = x[q][sl].reshape(-1)
+            a[O.F0 + q] = y[q][sl].reshape(-1)
+        gw = np.zeros((6, o.N))
+        o.adjoint_step_state(a, u, gw)
+        gw = o._tensor_eps_gradient(gw).reshape((6,) + o.shape3)
+        inner = (slice(m, m + w),) * 3
+        gsl = (slice(lo[2] - bz0 + m, lo[2] - bz0 + m + w), slice(lo[1] - by0 + m, lo[1] - by0 + m + w),
+               slice(lo[0] - bx0 + m, lo[0] - bx0 + m + w))
+        for q in range(6):
+            r = rel(aty[q][sl][inner], a[O.F0 + q].reshape(o.shape3)[inner])
+            assert r < 1e-12, (c, "cotangent", W.COMP_NAMES[q], r)
+            r = rel(g[(q,) + gsl], gw[q][inner])
+            assert r < 1e-12, (c, "gradient entry", q, r)
+        print(f"tensor 536^3 window at {c}: cotangents and gradient match the oracle", flush=True)
