@@ -26,7 +26,9 @@
  *     the outer product of the E cotangent and the curl on the octant's edges.
  *   - Discrete adjoint, Eq. (3) of Section 3.1, with the transposes of
  *     Section 3.1 (opposite-direction differences, the absorber transpose,
- *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl).
+ *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl, and
+ *     across a periodic seam the conjugate of the Bloch factor, which is the
+ *     factor itself for the real factors +1 and -1).
  *
  * Arrays are [nz][ny][nx], x fastest, one full-grid array per quantity.
  * Every loop is a plain loop over the grid; OpenMP splits the outer z loop
@@ -369,14 +371,19 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                         else
                             Dbar[p] = ybar;
                     }
-            /* D[i] = E[i+1] - E[i] (E beyond the grid is zero)  =>  Ebar[i] += Dbar[i-1] - Dbar[i] */
+            /* D[i] = E[i+1] - E[i] (E beyond the grid is zero, or on a periodic
+               axis E[N] = bsign E[0])  =>  Ebar[i] += Dbar[i-1] - Dbar[i], and
+               Ebar[0] takes bsign Dbar[N-1] across the seam (the transposed
+               factor: the conjugate, equal to bsign for the real factors) */
+            const double seam = P->per[a] ? P->bsign[a] : 0.0;
+            const size_t wrap = (size_t)(P->n[a] - 1) * sa;
 #pragma omp parallel for schedule(static)
             for (int k = 0; k < nz; ++k)
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {
                         int x[3] = {i, j, k};
                         size_t p = IDX(P, i, j, k);
-                        A->F[e][p] += (x[a] > 0 ? Dbar[p - sa] : 0.0) - Dbar[p];
+                        A->F[e][p] += (x[a] > 0 ? Dbar[p - sa] : seam * Dbar[p + wrap]) - Dbar[p];
                     }
         }
 
@@ -543,14 +550,18 @@ void orc_adjoint_step(const orc_params *P, orc_state *A, const orc_state *U, dou
                         else
                             Dbar[p] = ybar;
                     }
-            /* D[i] = H[i] - H[i-1] (H below the grid is zero)  =>  Hbar[i] += Dbar[i] - Dbar[i+1] */
+            /* D[i] = H[i] - H[i-1] (H below the grid is zero, or on a periodic
+               axis H[-1] = bsign H[N-1])  =>  Hbar[i] += Dbar[i] - Dbar[i+1],
+               and Hbar[N-1] gives up bsign Dbar[0] across the seam */
+            const double seam = P->per[a] ? P->bsign[a] : 0.0;
+            const size_t wrap = (size_t)(P->n[a] - 1) * sa;
 #pragma omp parallel for schedule(static)
             for (int k = 0; k < nz; ++k)
                 for (int j = 0; j < ny; ++j)
                     for (int i = 0; i < nx; ++i) {
                         int x[3] = {i, j, k};
                         size_t p = IDX(P, i, j, k);
-                        A->F[3 + h][p] += Dbar[p] - (x[a] < P->n[a] - 1 ? Dbar[p + sa] : 0.0);
+                        A->F[3 + h][p] += Dbar[p] - (x[a] < P->n[a] - 1 ? Dbar[p + sa] : seam * Dbar[p - wrap]);
                     }
         }
 }

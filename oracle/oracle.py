@@ -398,9 +398,6 @@ class OracleSim:
         Forward states are regenerated by recursive bisection: to reverse
         steps [lo, hi) from u^lo, advance a copy to the midpoint, reverse the
         upper half, then the lower half from u^lo."""
-        if any(self.per):
-            raise ValueError("periodic domains: this oracle has no adjoint across periodic seams (the library "
-                             "refuses gradients there too)")
         u_start = np.zeros_like(self.u) if u0 is None else u0.copy()
         a = np.zeros_like(self.u)
         g = np.zeros((6 if self.tensor else 3, self.N))

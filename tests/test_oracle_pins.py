@@ -200,6 +200,81 @@ def test_lossless_slab_transmission_eq5():
     assert 0.84 < T.min() and T.max() < 0.9 and T.max() - T.min() > 0.02
 
 
+@pytest.mark.parametrize("signs", [(1, 1), (-1, 1), (1, -1)])
+@pytest.mark.parametrize("nsteps", [1, 30])
+def test_periodic_adjoint_dot_product(signs, nsteps):
+    """<A x, y> = <x, A^T y> for the step map of a cell periodic in x and y
+    with real Bloch factors (Section 2.2: across the seam the transpose takes
+    the conjugate factor, the factor itself for +1 and -1), absorbing z
+    faces, diagonal eps and a Lorentz box touching both seams, to round-off;
+    cotangents stay off the non-degrees of freedom."""
+    rng = np.random.Generator(np.random.PCG64(61))
+    shape = (7, 6, 12)
+    nx, ny, nz = shape
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), pml=(0, 0, 0, 0, 2, 3), eps_kind="diag",
+                        eps_box=((0, 0, 0), shape), eps=1.0 + 3.0 * rng.random((3, nz, ny, nx)),
+                        lorentz=[W.LorentzSpec((0, 0, 4), (nx, 3, 8), 1.5, 0.3, 0.04)],
+                        periodic=(1, 1, 0), bloch_sign=(signs[0], signs[1], 1))
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    x = rng.standard_normal(sim.u.shape) * dof
+    y = rng.standard_normal(sim.u.shape) * dof
+    ax = x.copy()
+    for t in range(nsteps):
+        sim.step_state(ax, t, sources=False)
+    aty = y.copy()
+    for t in range(nsteps):
+        sim.adjoint_step_state(aty, x, None)
+    lhs = np.sum(ax * y * dof)
+    rhs = np.sum(x * aty * dof)
+    scale = np.linalg.norm(ax * dof) * np.linalg.norm(y)
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    assert np.all(aty[~dof] == 0.0)
+
+
+def test_periodic_gradient_central_differences():
+    """A Bloch cell (factor -1 along x, +1 along y) with a patterned slab
+    between absorbing z faces, an Ex sheet and a flux plane behind the slab:
+    dJ/deps of J = sum_f flux_f from the transposed sweep against
+    fourth-order central differences, at slab cells on the x and y seams and
+    inside (the paper checks a Bloch-periodic slab's index derivative by
+    central differences)."""
+    rng = np.random.Generator(np.random.PCG64(62))
+    nx, ny, nz = 6, 5, 40
+    shape = (nx, ny, nz)
+    n_steps = 140
+    eps = np.ones((1, nz, ny, nx))
+    eps[0, 18:24] = 1.5 + rng.random((6, ny, nx))
+    S = W.courant_3d()
+    spec = W.DomainSpec(
+        shape=shape, courant=S, pml=(0, 0, 0, 0, 8, 8), eps_kind="iso", eps_box=((0, 0, 0), shape), eps=eps,
+        sources=[W.SourceSpec("plane_z", 0, (0, 0, 11), W.gaussian_sine(n_steps, 0.5, 10.0, 30.0)),
+                 W.SourceSpec("point", 1, (2, 3, 12), W.gaussian_sine(n_steps, 0.6, 8.0, 24.0))],
+        monitors=[W.MonitorSpec("flux_z", pos=(0, 0, 28), rect=(0, nx, 0, ny), omega_dt=np.array([0.45, 0.6]))],
+        n_steps=n_steps, periodic=(1, 1, 0), bloch_sign=(-1, 1, 1))
+
+    def run(sp):
+        sim = O.OracleSim(sp)
+        sim.step(sp.n_steps)
+        f = sim.spectra(0)
+        J = float(np.sum(O.OracleSim.flux_from_spectra(f)))
+        g = np.zeros_like(f)
+        g[:, 0], g[:, 3], g[:, 1], g[:, 2] = f[:, 3], f[:, 0], -f[:, 2], -f[:, 1]
+        return sim, J, g
+
+    sim, J, cot = run(spec)
+    grad = sim.gradient({0: cot}, n_steps).sum(axis=0)
+    for (i, j, k) in [(0, 2, 19), (5, 0, 21), (3, 4, 23), (0, 0, 20)]:
+        h = 1e-3
+        vals = {}
+        for m in (-2, -1, 1, 2):
+            e = spec.eps.copy()
+            e[0, k, j, i] += m * h
+            vals[m] = run(W.DomainSpec(**{**spec.__dict__, "eps": e}))[1]
+        fd = (8.0 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12.0 * h)
+        assert abs(grad[k, j, i] - fd) <= 1e-7 * abs(fd) + 1e-10 * abs(J), (i, j, k, grad[k, j, i], fd)
+
+
 # ---------------------------------------------------------------- P2
 @pytest.mark.parametrize("kind", ["iso", "diag"])
 def test_discrete_energy_invariant(kind):
