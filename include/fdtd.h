@@ -167,8 +167,10 @@ typedef struct {
     int32_t grad_lo[3], grad_hi[3];/* box where dJ/deps accumulates */
     int32_t periodic[3];           /* 1: Bloch-periodic axis (Section 2.2): no PEC wall, and the node past
                                       the last one is the first one times bloch_sign.  x and y only, with no
-                                      absorbing cells on that axis, split kernels, no gradient (the adjoint
-                                      has no periodic seams): else FDTD_E_INVALID */
+                                      absorbing cells on that axis, split kernels; with a gradient (the
+                                      adjoint scatters across the seam with the same real factor, its own
+                                      conjugate) no dispersive box and no reversible mode: else
+                                      FDTD_E_INVALID */
     int32_t bloch_sign[3];         /* real Bloch factor exp(i k L) of a periodic axis: +1 (periodic) or -1
                                       (anti-periodic); ignored on other axes */
 } fdtd_domain_desc;

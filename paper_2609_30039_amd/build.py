@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfdtd.so")
-SOURCES = ["fdtd_kernels.hip", "fdtd_tens_adj.hip", "fdtd_runtime.cpp"]
+SOURCES = ["fdtd_kernels.hip", "fdtd_tens_adj.hip", "fdtd_per_adj.hip", "fdtd_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -80,6 +80,10 @@ void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, h
 // launch_adj's H-node pass completes the step
 template <typename T>
 void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s);
+// the whole adjoint step of Bloch-periodic domain dom (both passes, the seam
+// in their neighbour gathers)
+template <typename T>
+void launch_per_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s);
 template <typename T>
 void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s);
 template <typename T>

@@ -404,6 +404,8 @@ struct Handle : Base {
         for (int q = 0; q < ndom; ++q) {
             const fdtd_domain_desc& s = dh[q].desc;
             if (!s.grad) continue;
+            // a periodic domain's adjoint has launches of its own (launch_per_adj)
+            if (s.periodic[0] || s.periodic[1] || s.periodic[2]) continue;
             const int n[3] = {s.n[0], s.n[1], s.n[2]};
             for (int pass = 0; pass < 2; ++pass) {
                 // a tensor domain's E-node work has launches of its own (launch_tens_adj)
@@ -1106,7 +1108,10 @@ struct Handle : Base {
                 return fail(FDTD_E_INVALID, "a periodic axis takes no absorbing cells");
             if (s.bloch_sign[a] != 1 && s.bloch_sign[a] != -1)
                 return fail(FDTD_E_INVALID, "bloch_sign of a periodic axis must be +1 or -1");
-            if (s.grad) return fail(FDTD_E_INVALID, "periodic domains take no gradient (no adjoint across the seam)");
+            if (s.grad && s.n_lorentz)
+                return fail(FDTD_E_INVALID, "periodic domains with a gradient take no dispersive box");
+            if (opt.reversible && s.grad)
+                return fail(FDTD_E_INVALID, "periodic domains with a gradient take no reversible mode");
             if (opt.kernel == FDTD_KERNEL_FUSED) return fail(FDTD_E_INVALID, "periodic domains need the split kernels");
         }
         if (s.n_lorentz < 0 || s.n_lorentz > 1) return fail(FDTD_E_INVALID, "at most one Lorentz box per domain");
@@ -1402,8 +1407,11 @@ struct Handle : Base {
         hipStream_t cs[kAdjClasses1];
         for (int q = 0; q < kAdjClasses1; ++q) cs[q] = st;
         launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 0, cs);
-        for (int q = 0; q < ndom; ++q)
-            if (dd[q].tens && dd[q].grad) launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+        for (int q = 0; q < ndom; ++q) {
+            if (!dd[q].grad) continue;
+            if (dd[q].tens) launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+            else if (dd[q].per[0] || dd[q].per[1]) launch_per_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+        }
         if (cfg.kernel == 1) launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 1, cs);
         return FDTD_OK;
     }

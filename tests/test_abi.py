@@ -177,8 +177,9 @@ def test_reversible_mode_admissibility():
 
 def test_periodic_descriptor_checked():
     """Periodic axes: x and y only, no absorbing cells on them, a Bloch sign of
-    +1 or -1, split kernels and no gradient; an admissible one passes
-    validation (the tiny budget then refuses)."""
+    +1 or -1, split kernels; a gradient without a dispersive box or the
+    reversible mode; an admissible one passes validation (the tiny budget
+    then refuses)."""
     def spec(**kw):
         s = W.DomainSpec(shape=(8, 8, 12), courant=W.courant_3d(), pml=(0, 0, 0, 0, 3, 3), eps_kind="iso",
                          eps_box=((0, 0, 0), (8, 8, 12)), eps=np.ones((1, 12, 8, 8)), periodic=(1, 1, 0))
@@ -191,8 +192,11 @@ def test_periodic_descriptor_checked():
     _refused(spec(periodic=(1, 1, 1)), B.FDTD_E_INVALID)
     _refused(spec(pml=(2, 2, 0, 0, 3, 3)), B.FDTD_E_INVALID)
     _refused(spec(bloch_sign=(2, 1, 1)), B.FDTD_E_INVALID)
-    _refused(spec(grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID)
     _refused(spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
+    g = ((2, 2, 4), (6, 6, 8))
+    _passes_validation(spec(grad_box=g))
+    _refused(spec(grad_box=g, lorentz=[W.LorentzSpec((2, 2, 4), (5, 5, 7), 1.0, 0.3, 0.01)]), B.FDTD_E_INVALID)
+    _refused(spec(grad_box=g), B.FDTD_E_INVALID, reversible=True, max_steps=4)
 
 
 def _tensor_spec(m_node, n=10, pml=(0, 0, 0, 0, 3, 3), **kw):
