@@ -93,8 +93,9 @@ def gradient(sim: Simulation, n_steps: int, n_slots: int,
 def reversible_admissible(specs) -> bool:
     """Whether the reversible mode applies (Section 3.2: it follows from the
     content of the problem): every domain with a gradient has no dispersive
-    box, and its gradient box lies between the absorbing slabs, one cell clear
-    of a low slab (the curl at the gradient box reads H one cell back)."""
+    box, no tensor media and no periodic axis, and its gradient box lies
+    between the absorbing slabs, one cell clear of a low slab (the curl at
+    the gradient box reads H one cell back)."""
     if not isinstance(specs, (list, tuple)):
         specs = [specs]
     any_grad = False
@@ -102,7 +103,7 @@ def reversible_admissible(specs) -> bool:
         if s.grad_box is None:
             continue
         any_grad = True
-        if s.lorentz:
+        if s.lorentz or s.eps_kind == "tensor" or any(getattr(s, "periodic", (0, 0, 0))):
             return False
         (glo, ghi) = s.grad_box
         for a in range(3):
