@@ -30,6 +30,8 @@ Alongside, on the same JSON line:
   * tensor_adjoint_536: its reverse sweep with the gradient over every node
     tensor (160 steps, 8 slots, FP32 and FP64) and the adjoint step's
     kernel time against the forward step's;
+  * periodic_536: a 512 x 512 x 536 Bloch-periodic cell, forward rate and
+    roofline, and the adjoint step's kernel time against the forward step's;
   * streamed_536: the headline workload through host-streamed causal slabs
     (state in host memory, 64-plane slabs, 32 steps per visit);
   * streamed_adjoint_256: resident against streamed time to gradient and
@@ -648,6 +650,54 @@ def tensor_adjoint_536(stream):
     return out
 
 
+def periodic_536(stream):
+    """The Bloch-periodic cell at the headline's size (512 x 512 x 536, x and
+    y periodic with factors -1 and +1, absorbing z ends, a 64-plane
+    patterned layer): FP32 forward in captured 50-step chunks with the flux
+    plane recording, its stepping kernels' time per step (HIP events) and
+    roofline, and the adjoint step's kernel time with the gradient over the
+    layer (one adjoint step at a time from a stored state)."""
+    import torch
+    from paper_2609_30039_amd import workloads as W
+    from paper_2609_30039_amd import roofline as RL
+    from paper_2609_30039_amd.sim import Simulation
+    spec = W.bloch_cell()
+    tile = {"kernel": "split", "tile_rows": 8, "tile_kz": 8}
+    sim = Simulation(spec, dtype="f32", n_ckpt=1, stream=stream, graph_chunk=BENCH_CHUNK, **tile)
+    sim.step(BENCH_STEP)
+    torch.cuda.synchronize()
+    K, R = 3, 10
+    t0 = time.perf_counter()
+    sim.step(K * BENCH_STEP)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.timing(1)
+    sim.step(BENCH_STEP, record=False)
+    fms, _ = sim.timing(2)
+    sim.timing(0)
+    sim.save(0)
+    sim.timing(1)
+    for _ in range(R):
+        sim.restore(0)
+        sim.adjoint_begin(sim.steps[0] + 1)
+        sim.step_adjoint(1)
+    ams, na = sim.timing(2)
+    sim.timing(0)
+    sim.close()
+    fstep = fms / BENCH_STEP
+    astep = ams / na
+    bstep = RL.forward_bytes(spec, 4)
+    achieved = bstep / (fstep * 1e-3) / 1e9
+    mc = spec.ncells * K * BENCH_STEP / el / 1e6
+    log(f"periodic_536: {mc:.0f} Mcell-upd/s, forward step {fstep * 1e3:.0f} us, adjoint step {astep * 1e3:.0f} us")
+    return {"workload": "512 x 512 x 536 Bloch cell (x, y periodic, factors -1 and +1; 12-cell CPML at the z ends), "
+                        "64-plane diagonal-eps layer in [1,5] (seed 1007) as the gradient box, Ex sheet, flux plane, "
+                        "FP32", "cells": spec.ncells, "mcups": round(mc, 1), "launch_shape": tile,
+            "stepping_us_per_time_step": round(fstep * 1e3, 2), "algorithmic_bytes_per_time_step": bstep,
+            "achieved_GBs": round(achieved, 1), "frac": round(achieved / RL.HBM_PEAK_GBS, 4),
+            "adjoint_step_us_events": round(astep * 1e3, 2), "adjoint_over_forward_step": round(astep / fstep, 3)}
+
+
 def streamed_536(stream):
     """Host-streamed causal slabs on the 536^3 workload: slabs of 64 core
     planes, K = 32 steps per visit (33 halo planes per cut), FP32 forward
@@ -766,6 +816,7 @@ def main():
         out["several_poles"] = several_poles(stream, out["cache_resident_148"]["launch_shape"])
         out["tensor_536"] = tensor_536(stream)
         out["tensor_adjoint_536"] = tensor_adjoint_536(stream)
+        out["periodic_536"] = periodic_536(stream)
         out["streamed_536"] = streamed_536(stream)
         out["streamed_adjoint_256"] = streamed_adjoint_256(stream)
     out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)

@@ -10,8 +10,11 @@
 //              Ebar^{n+1} -> the new Ebar (no dispersion in tensor media,
 //              so the E-update transpose is the identity on E^n);
 //   k_tadj_e   per E node: u = S M Ebar (M is symmetric, so it is its own
-//              transpose), the E-side absorber memory cotangents, and the
-//              node tensor's gradient;
+//              transpose) from the cotangents of the 18 edges and the 15
+//              node-tensor entries the node's three edges meet, the E-side
+//              absorber memory cotangents, and the node tensor's gradient
+//              (the forward curls of the node's six edges from 12 H values
+//              away from the absorbing slabs);
 //   k_adj_et   u through the transposed absorber recursion and the curl into
 //              Hbar.
 // One thread per node, 64 x-nodes by 4 rows per block, one plane per block
@@ -39,39 +42,11 @@ __device__ __forceinline__ T tinv_at(const DomDev<T>& d, int q, int i, int j, in
     return q < 3 ? d.epsinv_bg : T(0);
 }
 
-__device__ __forceinline__ int tcomp(int a, int b) {
-    return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
-}
-
 // value of an edge array at the edge starting at (i,j,k); zero off the grid
 template <typename T>
 __device__ __forceinline__ T edge_at(const DomDev<T>& d, const FDTD_GLOBAL T* F, int i, int j, int k) {
     if (i < 0 || j < 0 || k < 0 || i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) return T(0);
     return F[fidx(d, i, j, k)];
-}
-
-// (M F)_c at the edge of component c starting at x: at each end node v the
-// edge takes eps^-1_cc(v)/2 times its own value and eps^-1_cb(v)/4 times the
-// sum over the two b edges meeting at v (leaving and arriving), b != c
-template <typename T>
-__device__ __forceinline__ T assemble(const DomDev<T>& d, const FDTD_GLOBAL T* const (&F)[3], int c, int i, int j,
-                                      int k) {
-    const T own = F[c][fidx(d, i, j, k)];
-    T acc = T(0);
-    for (int end = 0; end < 2; ++end) {
-        int v[3] = {i, j, k};
-        v[c] += end;
-        acc += T(0.5) * tinv_at(d, c, v[0], v[1], v[2]) * own;
-        for (int t = 1; t < 3; ++t) {
-            const int b = (c + t) % 3;
-            int w[3] = {v[0], v[1], v[2]};
-            T s = edge_at(d, F[b], w[0], w[1], w[2]);
-            w[b] -= 1;
-            s += edge_at(d, F[b], w[0], w[1], w[2]);
-            acc += T(0.25) * tinv_at(d, tcomp(c, b), v[0], v[1], v[2]) * s;
-        }
-    }
-    return acc;
 }
 
 // the forward stretched curl of edge (c, x) from u^n (set fsr), read only;
@@ -124,27 +99,67 @@ __global__ void __launch_bounds__(256) k_tadj_ht(const DomDev<T>* __restrict__ d
     }
 }
 
+// forward field value at (i,j,k) of array F, zero before the first node
+template <typename T>
+__device__ __forceinline__ T back_val(const DomDev<T>& d, const FDTD_GLOBAL T* F, int i, int j, int k) {
+    return (i < 0 || j < 0 || k < 0) ? T(0) : F[fidx(d, i, j, k)];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp, int rs, int ws, int fsr) {
     const DomDev<T>& d = *dp;
     const int i = blockIdx.x * kTx + threadIdx.x % kTx, j = blockIdx.y * kTy + threadIdx.x / kTx;
     if (i >= d.n[0] || j >= d.n[1]) return;
     const long long wo = (long long)ws * d.as;
-    const FDTD_GLOBAL T* eb[3] = {gp(d.Ea[0]) + wo, gp(d.Ea[1]) + wo, gp(d.Ea[2]) + wo};
-    const T S = d.S;
+    const FDTD_GLOBAL T* ex = gp(d.Ea[0]) + wo;
+    const FDTD_GLOBAL T* ey = gp(d.Ea[1]) + wo;
+    const FDTD_GLOBAL T* ez = gp(d.Ea[2]) + wo;
+    const T S = d.S, h = T(0.5), q4 = T(0.25);
     for (int k = blockIdx.z; k < d.n[2]; k += gridDim.z) {
         const long long f = fidx(d, i, j, k);
-        T u[3];
-        for (int c = 0; c < 3; ++c) {
-            u[c] = e_masked(c, i, j, k) ? T(0) : S * assemble(d, eb, c, i, j, k);
-            gp(d.Et[c])[f] = u[c];
-        }
+        // Ebar on the edges the three assembled edges of node v = (i,j,k) meet
+        // (suffixes: offsets from v; zero off the grid)
+        const T x0 = ex[f], x_xm = edge_at(d, ex, i - 1, j, k), x_yp = edge_at(d, ex, i, j + 1, k),
+                x_xmyp = edge_at(d, ex, i - 1, j + 1, k), x_zp = edge_at(d, ex, i, j, k + 1),
+                x_xmzp = edge_at(d, ex, i - 1, j, k + 1);
+        const T y0 = ey[f], y_ym = edge_at(d, ey, i, j - 1, k), y_xp = edge_at(d, ey, i + 1, j, k),
+                y_xpym = edge_at(d, ey, i + 1, j - 1, k), y_zp = edge_at(d, ey, i, j, k + 1),
+                y_ymzp = edge_at(d, ey, i, j - 1, k + 1);
+        const T z0 = ez[f], z_zm = edge_at(d, ez, i, j, k - 1), z_xp = edge_at(d, ez, i + 1, j, k),
+                z_xpzm = edge_at(d, ez, i + 1, j, k - 1), z_yp = edge_at(d, ez, i, j + 1, k),
+                z_ypzm = edge_at(d, ez, i, j + 1, k - 1);
+        // node tensors: v (all six), v+x (xx xy xz), v+y (yy xy yz), v+z (zz xz yz)
+        const T a_xx = tinv_at(d, 0, i, j, k), a_yy = tinv_at(d, 1, i, j, k), a_zz = tinv_at(d, 2, i, j, k),
+                a_xy = tinv_at(d, 3, i, j, k), a_xz = tinv_at(d, 4, i, j, k), a_yz = tinv_at(d, 5, i, j, k);
+        const T px_xx = tinv_at(d, 0, i + 1, j, k), px_xy = tinv_at(d, 3, i + 1, j, k),
+                px_xz = tinv_at(d, 4, i + 1, j, k);
+        const T py_yy = tinv_at(d, 1, i, j + 1, k), py_xy = tinv_at(d, 3, i, j + 1, k),
+                py_yz = tinv_at(d, 5, i, j + 1, k);
+        const T pz_zz = tinv_at(d, 2, i, j, k + 1), pz_xz = tinv_at(d, 4, i, j, k + 1),
+                pz_yz = tinv_at(d, 5, i, j, k + 1);
+        const T sx = x0 + x_xm, sy = y0 + y_ym, sz = z0 + z_zm;   // the two edges of each axis at v
+        T mx = h * (a_xx + px_xx) * x0;
+        mx += q4 * (a_xy * sy + px_xy * (y_xp + y_xpym));
+        mx += q4 * (a_xz * sz + px_xz * (z_xp + z_xpzm));
+        T my = h * (a_yy + py_yy) * y0;
+        my += q4 * (a_xy * sx + py_xy * (x_yp + x_xmyp));
+        my += q4 * (a_yz * sz + py_yz * (z_yp + z_ypzm));
+        T mz = h * (a_zz + pz_zz) * z0;
+        mz += q4 * (a_xz * sx + pz_xz * (x_zp + x_xmzp));
+        mz += q4 * (a_yz * sy + pz_yz * (y_zp + y_ymzp));
+        T u[3] = {e_masked(0, i, j, k) ? T(0) : S * mx, e_masked(1, i, j, k) ? T(0) : S * my,
+                  e_masked(2, i, j, k) ? T(0) : S * mz};
+        gp(d.Et[0])[f] = u[0];
+        gp(d.Et[1])[f] = u[1];
+        gp(d.Et[2])[f] = u[2];
+        const bool slab = slab_side(d, 0, i) >= 0 || slab_side(d, 1, j) >= 0 || slab_side(d, 2, k) >= 0;
         // E-side memory cotangents (owner): ybar = +u (term 0), -u (term 1)
-        for (int c = 0; c < 3; ++c) {
-            if (e_masked(c, i, j, k)) continue;
-            for (int t = 0; t < 2; ++t)
-                (void)stretch_T(d, d.psiEa, rs, ws, true, (c + 1 + t) % 3, t, 0, i, j, k, t == 0 ? u[c] : -u[c]);
-        }
+        if (slab)
+            for (int c = 0; c < 3; ++c) {
+                if (e_masked(c, i, j, k)) continue;
+                for (int t = 0; t < 2; ++t)
+                    (void)stretch_T(d, d.psiEa, rs, ws, true, (c + 1 + t) % 3, t, 0, i, j, k, t == 0 ? u[c] : -u[c]);
+            }
         if (!in_gbox(d, i, j, k)) continue;
         // node gradient.  U, Y: S Ebar and the forward curl on the two edges of
         // each axis b at the node (0: leaving, 1: arriving).  With eps^-1 = A,
@@ -153,14 +168,42 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         // (sums over the two edges); the gradient of eps is Q = -A G A, stored
         // as Q_aa and 2 Q_ab for the entries xx yy zz xy xz yz
         double U[3][2], Y[3][2];
-        for (int b = 0; b < 3; ++b)
-            for (int s = 0; s < 2; ++s) {
-                int w[3] = {i, j, k};
-                w[b] -= s;
-                U[b][s] = (double)(S * edge_at(d, eb[b], w[0], w[1], w[2]));
-                Y[b][s] = (double)fwd_curl(d, b, w, fsr);
-            }
-        double G[3][3], A[3][3];
+        U[0][0] = (double)(S * x0);
+        U[0][1] = (double)(S * x_xm);
+        U[1][0] = (double)(S * y0);
+        U[1][1] = (double)(S * y_ym);
+        U[2][0] = (double)(S * z0);
+        U[2][1] = (double)(S * z_zm);
+        if (slab) {   // stretched curls: the absorber memories of u^n take part
+            for (int b = 0; b < 3; ++b)
+                for (int s = 0; s < 2; ++s) {
+                    int w[3] = {i, j, k};
+                    w[b] -= s;
+                    Y[b][s] = (double)fwd_curl(d, b, w, fsr);
+                }
+        } else {      // plain backward-difference curls of the forward H
+            const long long fo = (long long)fsr * d.fs;
+            const FDTD_GLOBAL T* Hx = gp(d.H[0]) + fo;
+            const FDTD_GLOBAL T* Hy = gp(d.H[1]) + fo;
+            const FDTD_GLOBAL T* Hz = gp(d.H[2]) + fo;
+            const T hx = Hx[f], hx_ym = back_val(d, Hx, i, j - 1, k), hx_zm = back_val(d, Hx, i, j, k - 1),
+                    hx_ymzm = back_val(d, Hx, i, j - 1, k - 1);
+            const T hy = Hy[f], hy_xm = back_val(d, Hy, i - 1, j, k), hy_zm = back_val(d, Hy, i, j, k - 1),
+                    hy_xmzm = back_val(d, Hy, i - 1, j, k - 1);
+            const T hz = Hz[f], hz_xm = back_val(d, Hz, i - 1, j, k), hz_ym = back_val(d, Hz, i, j - 1, k),
+                    hz_xmym = back_val(d, Hz, i - 1, j - 1, k);
+            const bool mx_ = j == 0 || k == 0, my_ = i == 0 || k == 0, mz_ = i == 0 || j == 0;
+            Y[0][0] = mx_ ? 0.0 : (double)((hz - hz_ym) - (hy - hy_zm));
+            Y[0][1] = (mx_ || i == 0) ? 0.0 : (double)((hz_xm - hz_xmym) - (hy_xm - hy_xmzm));
+            Y[1][0] = my_ ? 0.0 : (double)((hx - hx_zm) - (hz - hz_xm));
+            Y[1][1] = (my_ || j == 0) ? 0.0 : (double)((hx_ym - hx_ymzm) - (hz_ym - hz_xmym));
+            Y[2][0] = mz_ ? 0.0 : (double)((hy - hy_xm) - (hx - hx_ym));
+            Y[2][1] = (mz_ || k == 0) ? 0.0 : (double)((hy_zm - hy_xmzm) - (hx_zm - hx_ymzm));
+        }
+        double G[3][3];
+        const double A[3][3] = {{(double)a_xx, (double)a_xy, (double)a_xz},
+                                {(double)a_xy, (double)a_yy, (double)a_yz},
+                                {(double)a_xz, (double)a_yz, (double)a_zz}};
         for (int a = 0; a < 3; ++a) {
             G[a][a] = 0.5 * (U[a][0] * Y[a][0] + U[a][1] * Y[a][1]);
             for (int b = a + 1; b < 3; ++b) {
@@ -168,7 +211,6 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
                                           (U[b][0] + U[b][1]) * (Y[a][0] + Y[a][1]));
                 G[a][b] = G[b][a] = g;
             }
-            for (int b = 0; b < 3; ++b) A[a][b] = (double)tinv_at(d, tcomp(a, b), i, j, k);
         }
         double B[3][3];   // G A
         for (int a = 0; a < 3; ++a)

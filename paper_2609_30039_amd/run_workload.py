@@ -34,6 +34,8 @@ def main(argv=None):
     from . import binding as B
 
     spec = W.WORKLOADS[args.workload]()
+    if (args.adjoint or args.reverse) and spec.grad_box is None:
+        spec.grad_box = spec.eps_box          # a forward-only workload: the gradient over its eps box
     if args.poles:
         spec = W.with_poles(spec, W.pole_set(args.poles))
     kk, rr, zz = args.shape.split(",")

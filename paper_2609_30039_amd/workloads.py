@@ -367,6 +367,27 @@ def anisotropic_tensor(interior: int = 512, pml: int = 12, patch: int = 64, n_st
     )
 
 
+def bloch_cell(nxy: int = 512, nz: int = 536, pml: int = 12, layer: int = 64, n_steps: int = 4000, n_f: int = 8,
+               seed: int = 1007, sign_x: int = -1) -> DomainSpec:
+    """A Bloch-periodic cell at the headline's size (Section 2.2; the slab
+    set-up of Section 6.1): x and y periodic with the real factors (sign_x,
+    +1), absorbing cells at the z ends only, a patterned layer of `layer`
+    planes with diagonal eps in [1, 5] over the whole cross-section (the
+    gradient box), an Ex sheet below it and a flux plane above it."""
+    shape = (nxy, nxy, nz)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z0 = (nz - layer) // 2
+    eps = 1.0 + 4.0 * rng.random((3, layer, nxy, nxy))
+    box = ((0, 0, z0), (nxy, nxy, z0 + layer))
+    return DomainSpec(
+        shape=shape, courant=courant_3d(), pml=(0, 0, 0, 0, pml, pml), eps_kind="diag", eps_box=box, eps=eps,
+        eps_bg=1.0,
+        sources=[SourceSpec("plane_z", EX, (0, 0, pml + 5), gaussian_sine(n_steps, 0.15, 30.0, 120.0))],
+        monitors=[MonitorSpec("flux_z", pos=(0, 0, nz - pml - 5), rect=(0, nxy, 0, nxy), omega_dt=freq_grid(n_f))],
+        grad_box=box, n_steps=n_steps, periodic=(1, 1, 0), bloch_sign=(sign_x, 1, 1),
+    )
+
+
 def random_state_like(spec: DomainSpec, seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
@@ -380,4 +401,5 @@ WORKLOADS = {
     "batch_domains": lambda: batch_domains(),
     "anisotropic_lorentz": lambda: anisotropic_lorentz(),
     "anisotropic_tensor": lambda: anisotropic_tensor(),
+    "bloch_cell": lambda: bloch_cell(),
 }
