@@ -1,0 +1,107 @@
+// fdtd_node_adj.h -- pieces shared by the per-node adjoint passes of tensor
+// media and Bloch-periodic domains (internal).
+//
+// These passes give each thread one (i, j) column of kNodeKz planes of a
+// domain, 64 x-columns by 4 rows per 256-thread block, and march it in z:
+// the z neighbour a node reads is the previous (or next) plane of the same
+// thread, carried in registers, so a plane's operands are fetched once.
+#pragma once
+#include "fdtd_dev.h"
+
+namespace fdtd {
+
+constexpr int kNodeTx = 64, kNodeTy = 4, kNodeKz = 8;
+
+// the node one step back along a from x, across a periodic seam when x[a] = 0
+// (fac: the Bloch factor there, else 1); false past a wall
+template <typename T>
+__device__ __forceinline__ bool back_node(const DomDev<T>& d, int a, const int x[3], int y[3], T& fac) {
+    y[0] = x[0];
+    y[1] = x[1];
+    y[2] = x[2];
+    fac = T(1);
+    if (x[a] > 0) {
+        y[a] -= 1;
+        return true;
+    }
+    if (!d.per[a]) return false;
+    y[a] = d.n[a] - 1;
+    fac = d.bsign[a];
+    return true;
+}
+
+// the node one step forward along a, across a periodic seam when x[a] = n - 1
+template <typename T>
+__device__ __forceinline__ bool fwd_node(const DomDev<T>& d, int a, const int x[3], int y[3], T& fac) {
+    y[0] = x[0];
+    y[1] = x[1];
+    y[2] = x[2];
+    fac = T(1);
+    if (x[a] + 1 < d.n[a]) {
+        y[a] += 1;
+        return true;
+    }
+    if (!d.per[a]) return false;
+    y[a] = 0;
+    fac = d.bsign[a];
+    return true;
+}
+
+// The H-update transpose gathered onto the E nodes of one column.  H_c's term
+// t (t = 0: difference along c+1 of E_{c+2}, sign +; t = 1: along c+2 of
+// E_{c+1}, sign -) has raw-difference cotangent Dbar_ct(p) (the transposed
+// absorber recursion of ybar = -S sign Hbar_c(p), memories of set rs read
+// only).  With D(p) = E(p + a) - E(p), E_e(x) collects Dbar(back node) - Dbar(x)
+// from (c, t) = (e+1, 0) along e+2 and (e+2, 1) along e+1.  Along z (no seam)
+// the back node's terms are the previous plane's own ones, carried.
+template <typename T>
+struct HtGather {
+    const DomDev<T>& d;
+    int i, j, rs, ws;
+    long long ro;
+    T dz_y0, dz_x1;   // own z-terms of the plane below: Dbar of (Hy, t=0) and (Hx, t=1)
+
+    __device__ __forceinline__ HtGather(const DomDev<T>& d_, int i_, int j_, int k0, int rs_, int ws_)
+        : d(d_), i(i_), j(j_), rs(rs_), ws(ws_), ro((long long)rs_ * d_.as), dz_y0(0), dz_x1(0) {
+        if (k0 > 0) {
+            const long long f = fidx(d, i, j, k0 - 1) + ro;
+            dz_y0 = hT_dbar(d, 2, 0, T(1), i, j, k0 - 1, gp(d.Ha[1])[f], rs, ws, false);
+            dz_x1 = hT_dbar(d, 2, 1, T(-1), i, j, k0 - 1, gp(d.Ha[0])[f], rs, ws, false);
+        }
+    }
+
+    // Dbar of (c, t) at the back node of x along a (x, y only), zero past a wall
+    __device__ __forceinline__ T back_term(int c, int t, int a, int k) {
+        const int x[3] = {i, j, k};
+        int y[3];
+        T fac;
+        if (!back_node(d, a, x, y, fac)) return T(0);
+        const T hb = gp(d.Ha[c])[fidx(d, y[0], y[1], y[2]) + ro];
+        return fac * hT_dbar(d, a, t, t == 0 ? T(1) : T(-1), y[0], y[1], y[2], hb, rs, ws, false);
+    }
+
+    // et[e]: Ebar^{n+1} of set rs plus the gathered terms at plane k (zero on
+    // a node a wall holds)
+    __device__ __forceinline__ void plane(int k, long long f, T et[3]) {
+        const long long fr = f + ro;
+        const T hx = gp(d.Ha[0])[fr], hy = gp(d.Ha[1])[fr], hz = gp(d.Ha[2])[fr];
+        // own terms: (Hx,0) along y, (Hx,1) along z, (Hy,0) along z, (Hy,1) along x, (Hz,0) along x, (Hz,1) along y
+        const T ox0 = hT_dbar(d, 1, 0, T(1), i, j, k, hx, rs, ws, false);
+        const T ox1 = hT_dbar(d, 2, 1, T(-1), i, j, k, hx, rs, ws, false);
+        const T oy0 = hT_dbar(d, 2, 0, T(1), i, j, k, hy, rs, ws, false);
+        const T oy1 = hT_dbar(d, 0, 1, T(-1), i, j, k, hy, rs, ws, false);
+        const T oz0 = hT_dbar(d, 0, 0, T(1), i, j, k, hz, rs, ws, false);
+        const T oz1 = hT_dbar(d, 1, 1, T(-1), i, j, k, hz, rs, ws, false);
+        // Ex: (Hy,0) along z, (Hz,1) along y; Ey: (Hz,0) along x, (Hx,1) along z; Ez: (Hx,0) along y, (Hy,1) along x
+        et[0] = e_masked_d(d, 0, i, j, k) ? T(0)
+                : gp(d.Ea[0])[fr] + (dz_y0 - oy0) + (back_term(2, 1, 1, k) - oz1);
+        et[1] = e_masked_d(d, 1, i, j, k) ? T(0)
+                : gp(d.Ea[1])[fr] + (back_term(2, 0, 0, k) - oz0) + (dz_x1 - ox1);
+        et[2] = e_masked_d(d, 2, i, j, k) ? T(0)
+                : gp(d.Ea[2])[fr] + (back_term(0, 0, 1, k) - ox0) + (back_term(1, 1, 0, k) - oy1);
+        dz_y0 = oy0;
+        dz_x1 = ox1;
+    }
+};
+
+}  // namespace fdtd

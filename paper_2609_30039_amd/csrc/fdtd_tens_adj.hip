@@ -17,13 +17,16 @@
 //              away from the absorbing slabs);
 //   k_adj_et   u through the transposed absorber recursion and the curl into
 //              Hbar.
-// One thread per node, 64 x-nodes by 4 rows per block, one plane per block
-// row of the grid (a z-stride loop beyond the grid's z extent).  The passes
-// read set rs of the adjoint state and write set ws, like the split adjoint.
+// k_tadj_ht marches (i, j) columns of kNodeKz planes (fdtd_node_adj.h);
+// k_tadj_e takes one node per thread, 64 x-nodes by 4 rows per block, one
+// plane per block row of the grid (a z-stride loop beyond the grid's z
+// extent).  The passes read set rs of the adjoint state and write set ws,
+// like the split adjoint.
 #include <hip/hip_runtime.h>
 
 #include "fdtd_dev.h"
 #include "fdtd_launch.h"
+#include "fdtd_node_adj.h"
 
 namespace fdtd {
 namespace {
@@ -67,35 +70,18 @@ __device__ __forceinline__ T fwd_curl(const DomDev<T>& d, int c, const int x[3],
 template <typename T>
 __global__ void __launch_bounds__(256) k_tadj_ht(const DomDev<T>* __restrict__ dp, int rs, int ws) {
     const DomDev<T>& d = *dp;
-    const int i = blockIdx.x * kTx + threadIdx.x % kTx, j = blockIdx.y * kTy + threadIdx.x / kTx;
+    const int i = blockIdx.x * kNodeTx + threadIdx.x % kNodeTx, j = blockIdx.y * kNodeTy + threadIdx.x / kNodeTx;
+    const int k0 = blockIdx.z * kNodeKz, k1 = min(k0 + kNodeKz, d.n[2]);
     if (i >= d.n[0] || j >= d.n[1]) return;
-    const long long ro = (long long)rs * d.as, wo = (long long)ws * d.as;
-    const long long st[3] = {1, d.pitch, d.plane};
-    for (int k = blockIdx.z; k < d.n[2]; k += gridDim.z) {
+    const long long wo = (long long)ws * d.as;
+    HtGather<T> hg(d, i, j, k0, rs, ws);
+    for (int k = k0; k < k1; ++k) {
         const long long f = fidx(d, i, j, k);
-        const int x[3] = {i, j, k};
-        for (int e = 0; e < 3; ++e) {
-            T acc = T(0);
-            if (!e_masked(e, i, j, k)) {
-                acc = gp(d.Ea[e])[f + ro];
-                // E_e enters H_c's update term t, differenced forward along a:
-                // t = 0: c = e+1, a = e+2, sign +; t = 1: c = e+2, a = e+1, sign -.
-                // D(p) = E_e(p + a) - E_e(p), so Ebar_e(x) gets Dbar(x - a) - Dbar(x)
-                for (int t = 0; t < 2; ++t) {
-                    const int c = t == 0 ? (e + 1) % 3 : (e + 2) % 3;
-                    const int a = t == 0 ? (e + 2) % 3 : (e + 1) % 3;
-                    const T sgn = t == 0 ? T(1) : T(-1);
-                    const FDTD_GLOBAL T* hb = gp(d.Ha[c]) + ro;
-                    acc -= hT_dbar(d, a, t, sgn, i, j, k, hb[f], rs, ws, false);
-                    if (x[a] > 0) {
-                        int y[3] = {i, j, k};
-                        y[a] -= 1;
-                        acc += hT_dbar(d, a, t, sgn, y[0], y[1], y[2], hb[f - st[a]], rs, ws, false);
-                    }
-                }
-            }
-            gp(d.Ea[e])[f + wo] = acc;
-        }
+        T et[3];
+        hg.plane(k, f, et);
+        gp(d.Ea[0])[f + wo] = et[0];
+        gp(d.Ea[1])[f + wo] = et[1];
+        gp(d.Ea[2])[f + wo] = et[2];
     }
 }
 
@@ -231,9 +217,10 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
 template <typename T>
 void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s) {
     const DomDev<T>* dp = (const DomDev<T>*)doms + dom;
-    const dim3 grid((n[0] + kTx - 1) / kTx, (n[1] + kTy - 1) / kTy, std::min(n[2], kMaxGridZ));
-    hipLaunchKernelGGL(k_tadj_ht<T>, grid, dim3(256), 0, s, dp, rs, ws);
-    hipLaunchKernelGGL(k_tadj_e<T>, grid, dim3(256), 0, s, dp, rs, ws, fsr);
+    const dim3 gcol((n[0] + kNodeTx - 1) / kNodeTx, (n[1] + kNodeTy - 1) / kNodeTy, (n[2] + kNodeKz - 1) / kNodeKz);
+    const dim3 gplane((n[0] + kTx - 1) / kTx, (n[1] + kTy - 1) / kTy, std::min(n[2], kMaxGridZ));
+    hipLaunchKernelGGL(k_tadj_ht<T>, gcol, dim3(256), 0, s, dp, rs, ws);
+    hipLaunchKernelGGL(k_tadj_e<T>, gplane, dim3(256), 0, s, dp, rs, ws, fsr);
 }
 
 template void launch_tens_adj<float>(const void*, int, const int*, int, int, int, hipStream_t);
