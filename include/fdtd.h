@@ -387,9 +387,14 @@ const char *fdtd_last_error(fdtd_t h);
    (scalar, diagonal or tensor eps, a dispersive box, absorbing faces on every
    side, periodic x/y, sources, probe and plane monitors), and with grad set
    the reverse sweep (fdtd_stream_reverse) over the same slabs.  With a
-   gradient the host keeps one forward bank per pass boundary (bank j holds
-   time j K; ceil(max_steps / K) + 1 banks) and two cotangent banks, and
-   passes are exactly K steps except the last one.  An absorbing z face
+   gradient the host keeps, by default, one forward bank per pass boundary
+   (bank j holds time j K; ceil(max_steps / K) + 1 banks), or with
+   host_banks = B >= 4 only B forward banks: the state at time t, time 0 and
+   the snapshots of a binomial schedule over passes (Section 3.2's
+   checkpointing applied to the block checkpoints); the reverse sweep then
+   regenerates the other block starts by streamed forward passes from the
+   nearest snapshot.  Two cotangent banks besides, and passes are exactly K
+   steps except the last one.  An absorbing z face
    must lie wholly inside or wholly outside each slab's extent: a slab that
    would cut one is refused (FDTD_E_INVALID; raise slab_planes).  Monitors
    belong to the slab whose core holds their plane; their spectra and probe
@@ -411,6 +416,8 @@ typedef struct {
                                       beside the other slab's steps (twice the device workspace) */
     int32_t local_slots;           /* reverse sweep: forward states a slab keeps on the device while it
                                       reverses a block (binomial schedule); 0 or >= K: every state */
+    int32_t host_banks;            /* with a gradient: forward banks on the host, 0 (one per pass
+                                      boundary) or >= 4 (binomial over passes); else FDTD_E_INVALID */
 } fdtd_stream_options;
 
 typedef struct {
@@ -423,6 +430,8 @@ typedef struct {
     double resident_bytes;         /* what the resident handle of the same domain would allocate */
     int32_t materials_resident;    /* 1: eps^-1 is kept on the device (the budget held it beside the
                                       workspaces); 0: each visit uploads its planes from pinned memory */
+    int32_t replay_passes;         /* streamed forward passes the last reverse sweep ran to regenerate
+                                      block starts (0 with one bank per pass boundary) */
 } fdtd_stream_info;
 
 typedef struct fdtd_stream_s *fdtd_stream_t;

@@ -128,13 +128,13 @@ class StreamOptions(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("slab_planes", C.c_int32), ("steps_per_pass", C.c_int32),
                 ("max_steps", C.c_int32), ("tile_rows", C.c_int32), ("tile_kz", C.c_int32),
                 ("stream", C.c_void_p), ("mem_budget_bytes", C.c_double), ("host_budget_bytes", C.c_double),
-                ("overlap", C.c_int32), ("local_slots", C.c_int32)]
+                ("overlap", C.c_int32), ("local_slots", C.c_int32), ("host_banks", C.c_int32)]
 
 
 class StreamInfo(C.Structure):
     _fields_ = [("n_slabs", C.c_int32), ("halo", C.c_int32), ("max_extent", C.c_int32), ("step", C.c_int32),
                 ("device_bytes", C.c_double), ("host_bytes", C.c_double), ("resident_bytes", C.c_double),
-                ("materials_resident", C.c_int32)]
+                ("materials_resident", C.c_int32), ("replay_passes", C.c_int32)]
 
 
 _lib = None
@@ -421,7 +421,7 @@ def _schk(rc: int, h=None):
 def fdtd_stream_create(spec, dtype: int, slab_planes: int, steps_per_pass: int, max_steps: int = 0,
                        tile_rows: int = 0, tile_kz: int = 0, stream: Optional[int] = None,
                        mem_budget_bytes: float = 0.0, host_budget_bytes: float = 0.0, overlap: bool = True,
-                       local_slots: int = 0):
+                       local_slots: int = 0, host_banks: int = 0):
     keep: list = []
     d = domain_desc(spec, keep)
     o = StreamOptions()
@@ -431,6 +431,7 @@ def fdtd_stream_create(spec, dtype: int, slab_planes: int, steps_per_pass: int, 
     o.mem_budget_bytes, o.host_budget_bytes = mem_budget_bytes, host_budget_bytes
     o.overlap = 1 if overlap else 0
     o.local_slots = local_slots
+    o.host_banks = host_banks
     h = C.c_void_p()
     _schk(lib().fdtd_stream_create(C.byref(d), C.byref(o), C.byref(h)), None)
     return h

@@ -1784,10 +1784,18 @@ struct Streamer : StreamBase {
     // Forward banks.  Forward only: two, ping-ponged (cb holds time t).  With
     // a gradient: one per pass boundary, bank j holding time j K, so that the
     // reverse sweep finds every block's starting state; passes are then K
-    // steps long except a last, shorter one.
+    // steps long except a last, shorter one.  With host_banks = B (bounded):
+    // B banks, one holding time t (cur_id), snap[p] the bank holding the
+    // state at pass boundary p (time 0 always; the forward keeps the
+    // positions `planned` of the binomial descent), the rest free.
     bool adj = false;
     std::vector<T*> bank;
     int cb = 0;
+    bool bounded = false;
+    int cur_id = 0;
+    std::vector<int> snap;                      // pass boundary -> bank, or -1
+    std::vector<char> planned;                  // pass boundary kept by the forward
+    int replay_passes = 0;
     T* abank[2] = {nullptr, nullptr};           // cotangent state banks of the reverse sweep
     std::vector<double> grad;                   // dJ/deps over the gradient box [ncomp][gz][gy][gx]
     int gncomp = 1;
@@ -2094,7 +2102,27 @@ struct Streamer : StreamBase {
                 if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + sh.err);
                 pool_cap = std::max(pool_cap, sh.pool_bytes);
             }
-        const int nbank = adj ? (so.max_steps + K - 1) / K + 1 : 2;
+        const int npass = (so.max_steps + K - 1) / K;
+        if (o->host_banks != 0 && o->host_banks < 4)
+            return fail(FDTD_E_INVALID, "host_banks must be 0 or at least 4");
+        bounded = adj && o->host_banks >= 4 && o->host_banks < npass + 1;
+        const int nbank = adj ? (bounded ? o->host_banks : npass + 1) : 2;
+        if (bounded) {
+            // the forward keeps the binomial descent over [0, npass): with s
+            // slots (the one at a included) advance m = max(1, l - beta(s-1, r),
+            // beta(s, r-2)) passes, keep that boundary, one slot fewer; B - 4 of
+            // them, so that the reverse always has two free banks to advance with
+            planned.assign(npass + 1, 0);
+            int a = 0, s_ = nbank - 3;
+            while (npass - a > 1 && s_ > 1) {
+                const int l = npass - a;
+                int r = 0;
+                while (beta(s_, r) < l) ++r;
+                a += (int)std::max<long long>(1, std::max<long long>(l - beta(s_ - 1, r), beta(s_, r - 2)));
+                planned[a] = 1;
+                --s_;
+            }
+        }
         // admission: device workspaces + accumulators, host banks
         nws = o->overlap ? 2 : 1;
         const size_t est = ebox ? eplane * (size_t)(ez1 - ez0) : 0;   // stored elements per component
@@ -2184,6 +2212,11 @@ struct Streamer : StreamBase {
         if (int rc = drain()) return rc;
         std::memset(bank[0], 0, bank_elems * sizeof(T));   // the state at time 0; later banks are written whole
         cb = 0;
+        cur_id = 0;
+        if (bounded) {
+            snap.assign(planned.size(), -1);
+            snap[0] = 0;
+        }
         t = 0;
         grad_step = -1;
         launch_zero(dmon, dmon_bytes, st);
@@ -2206,7 +2239,7 @@ struct Streamer : StreamBase {
     // monitors into the domain's.  The previous slab of that workspace is
     // waited for (its handle released) first; the other workspace's slab keeps
     // running meanwhile.
-    int run_slab(int s, int n, T* src_bank, T* dst_bank) {
+    int run_slab(int s, int n, T* src_bank, T* dst_bank, int t_start = -1, bool record = true) {
         const int o = ext_lo(s), e = ext_hi(s), c0 = core[s], c1 = core[s + 1];
         const int w = s % nws;
         hs[w].reset();
@@ -2222,7 +2255,7 @@ struct Streamer : StreamBase {
         hipStream_t st = wst[w];
         int rc = hd.create(&d, 1, &so2);
         if (rc) return fail(rc, "slab " + std::to_string(s) + ": " + hd.err);
-        hd.t = t;
+        hd.t = t_start < 0 ? t : t_start;
         const DomDev<T>& dv = hd.dd[0];
         // eps^-1 of the slab's share of the eps box
         if (ebox && dv.elo[2] < dv.ehi[2]) {
@@ -2237,9 +2270,9 @@ struct Streamer : StreamBase {
         }
         // state at time t over the extent, n steps, the core at time t + n
         if ((rc = xfer(hd, src_bank, true, o, e, c0, c1, st))) return rc;
-        if ((rc = hd.step_forward(n, FDTD_RECORD))) return fail(rc, hd.err);
+        if ((rc = hd.step_forward(n, record ? FDTD_RECORD : FDTD_REPLAY))) return fail(rc, hd.err);
         if ((rc = xfer(hd, dst_bank, false, o, e, c0, c1, st))) return rc;
-        for (size_t li = 0; li < lm.size(); ++li) {
+        for (size_t li = 0; record && li < lm.size(); ++li) {
             MonHost& mh = hd.dh[0].mons[li];
             hd.flush(mh);
             GMon& m = gm[lm[li]];
@@ -2250,7 +2283,19 @@ struct Streamer : StreamBase {
     }
 
     // bank holding the state at time t
-    int cur_bank() const { return adj ? (t + K - 1) / K : cb; }
+    int cur_bank() const { return bounded ? cur_id : (adj ? (t + K - 1) / K : cb); }
+
+    // banks holding neither the state at time t nor a snapshot (bounded mode)
+    std::vector<int> free_banks() const {
+        std::vector<char> used(bank.size(), 0);
+        used[cur_id] = 1;
+        for (int b : snap)
+            if (b >= 0) used[b] = 1;
+        std::vector<int> f;
+        for (int q = 0; q < (int)bank.size(); ++q)
+            if (!used[q]) f.push_back(q);
+        return f;
+    }
 
     // checkpoint slots a slab keeps while it reverses a block
     int local_slots() const { return so.local_slots > 0 ? std::min(so.local_slots, K) : K; }
@@ -2311,8 +2356,13 @@ struct Streamer : StreamBase {
                                       "max_steps");
         while (n > 0) {
             const int kp = std::min(n, K);
+            int did = -1;
+            if (bounded) {
+                const std::vector<int> f = free_banks();
+                did = f.front();   // two or more are free: B - 4 planned snapshots, time 0, time t
+            }
             T* src = bank[cur_bank()];
-            T* dst = bank[adj ? t / K + 1 : cb ^ 1];
+            T* dst = bank[bounded ? did : (adj ? t / K + 1 : cb ^ 1)];
             for (int s = 0; s < ns(); ++s) {
                 int rc = run_slab(s, kp, src, dst);
                 if (rc) {
@@ -2324,6 +2374,10 @@ struct Streamer : StreamBase {
             cb ^= 1;
             t += kp;
             n -= kp;
+            if (bounded) {
+                cur_id = did;
+                if (t % K == 0 && planned[t / K]) snap[t / K] = did;   // kept for the reverse sweep
+            }
         }
         grad_step = -1;
         return FDTD_OK;
@@ -2421,6 +2475,78 @@ struct Streamer : StreamBase {
         return FDTD_OK;
     }
 
+    // Reverse the block of pass p, whose starting state is in bank bid.
+    int run_block(int p, int bid, int N, int& ab) {
+        const int t0 = p * K, kb = std::min(K, N - t0);
+        for (int s = 0; s < ns(); ++s) {
+            int rc = run_slab_reverse(s, t0, kb, N, bank[bid], abank[ab], abank[ab ^ 1]);
+            if (rc) {
+                drain();
+                return rc;
+            }
+        }
+        if (int rc = drain()) return rc;
+        ab ^= 1;
+        return FDTD_OK;
+    }
+
+    // Streamed forward passes a -> m (full K-step passes, no monitors) from
+    // bank src; the state lands in bank x, y the other of the ping-pong pair.
+    int advance(int src, int a, int m, int x, int y) {
+        const int q = m - a;
+        int from = src, to = (q % 2) ? x : y;
+        for (int p = a; p < m; ++p) {
+            for (int s = 0; s < ns(); ++s) {
+                int rc = run_slab(s, K, bank[from], bank[to], p * K, false);
+                if (rc) {
+                    drain();
+                    return rc;
+                }
+            }
+            if (int rc = drain()) return rc;
+            ++replay_passes;
+            from = to;
+            to = to == x ? y : x;
+        }
+        return FDTD_OK;
+    }
+
+    // Bounded banks: reverse passes [a, b) holding u at boundary a in snap[a].
+    // A snapshot inside (a, b) splits the range (the largest first);
+    // otherwise, with s = free banks - 1 slots, the binomial rule picks the
+    // boundary m to regenerate and keep (s = 1: each block start regenerated
+    // from a in turn).
+    int rev_passes(int a, int b, int N, int& ab) {
+        int rc;
+        if (b - a == 1) return run_block(a, snap[a], N, ab);
+        int m = -1;
+        for (int p = b - 1; p > a; --p)
+            if (snap[p] >= 0) {
+                m = p;
+                break;
+            }
+        if (m < 0) {
+            const std::vector<int> f = free_banks();
+            const int s_ = (int)f.size() - 1;
+            if (s_ <= 1) {
+                for (int c = b - 1; c > a; --c) {
+                    if ((rc = advance(snap[a], a, c, f[0], f[1]))) return rc;
+                    if ((rc = run_block(c, f[0], N, ab))) return rc;
+                }
+                return run_block(a, snap[a], N, ab);
+            }
+            const int l = b - a;
+            int r = 0;
+            while (beta(s_, r) < l) ++r;
+            m = a + (int)std::max<long long>(1, std::max<long long>(l - beta(s_ - 1, r), beta(s_, r - 2)));
+            if ((rc = advance(snap[a], a, m, f[0], f[1]))) return rc;
+            snap[m] = f[0];
+        }
+        if ((rc = rev_passes(m, b, N, ab))) return rc;
+        snap[m] = -1;
+        return rev_passes(a, m, N, ab);
+    }
+
     int reverse() override {
         if (!adj) return fail(FDTD_E_STATE, "the domain takes no gradient");
         const int N = t;
@@ -2428,6 +2554,12 @@ struct Streamer : StreamBase {
         std::fill(grad.begin(), grad.end(), 0.0);
         std::memset(abank[0], 0, bank_elems * sizeof(T));
         int ab = 0;
+        replay_passes = 0;
+        if (bounded) {
+            if (int rc = rev_passes(0, (N + K - 1) / K, N, ab)) return rc;
+            grad_step = N;
+            return FDTD_OK;
+        }
         for (int j = (N - 1) / K; j >= 0; --j) {
             const int t0 = j * K, kb = std::min(K, N - t0);
             for (int s = 0; s < ns(); ++s) {
@@ -2497,6 +2629,7 @@ struct Streamer : StreamBase {
                           est * ncomp_eps * sizeof(T) + 8.0 * grad.size();
         out->resident_bytes = resident_bytes;
         out->materials_resident = d_einv ? 1 : 0;
+        out->replay_passes = replay_passes;
     }
 };
 

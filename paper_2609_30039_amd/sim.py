@@ -160,13 +160,13 @@ class StreamedSimulation:
     def __init__(self, spec, slab_planes: int, steps_per_pass: int, dtype: str = "f32",
                  max_steps: Optional[int] = None, tile_rows: int = 0, tile_kz: int = 0,
                  stream: Optional[int] = None, mem_budget_bytes: float = 0.0, host_budget_bytes: float = 0.0,
-                 overlap: bool = True, local_slots: int = 0):
+                 overlap: bool = True, local_slots: int = 0, host_banks: int = 0):
         self.spec = spec
         self.dtype = np.float32 if dtype == "f32" else np.float64
         self.max_steps = max(spec.n_steps, 1) if max_steps is None else max_steps
         self.h = B.fdtd_stream_create(spec, B.FDTD_F32 if dtype == "f32" else B.FDTD_F64, slab_planes,
                                       steps_per_pass, self.max_steps, tile_rows, tile_kz, stream,
-                                      mem_budget_bytes, host_budget_bytes, overlap, local_slots)
+                                      mem_budget_bytes, host_budget_bytes, overlap, local_slots, host_banks)
 
     def close(self):
         if self.h is not None:

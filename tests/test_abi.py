@@ -287,3 +287,14 @@ def test_stream_admission():
     assert "device budget" in msg
     msg = _stream_refused(spec, B.FDTD_E_NOMEM, host_budget_bytes=1e5)
     assert "host budget" in msg
+    # bounded forward banks: fewer than 4 refused; 4 banks pass a host budget that one bank per pass
+    # boundary (40 steps of 4 -> 11 banks) exceeds, and are then refused only by the device budget
+    g40 = W.lorentz_flux(pml=6, lorentz=8, n_steps=40, n_f=2, shape=(24, 20, 60))
+    g40.grad_box = ((8, 8, 8), (16, 12, 40))
+    bank = 24 * 20 * 60 * 4 * 6
+    _stream_refused(g40, B.FDTD_E_INVALID, max_steps=40, host_banks=3)
+    msg = _stream_refused(g40, B.FDTD_E_NOMEM, max_steps=40, host_budget_bytes=9 * bank)
+    assert "host budget" in msg
+    msg = _stream_refused(g40, B.FDTD_E_NOMEM, max_steps=40, host_budget_bytes=9 * bank, host_banks=4,
+                          mem_budget_bytes=1e5)
+    assert "device budget" in msg

@@ -233,3 +233,56 @@ def test_streamed_gradient_state_rules():
         s.grad()
     assert e.value.code == B.FDTD_E_STATE
     s.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-9)])
+@pytest.mark.parametrize("banks", [4, 5, 7])
+def test_streamed_gradient_bounded_host_banks(dtype, tol, banks):
+    """Only `banks` forward banks on the host for the 12 passes of 57 steps
+    with K = 5 (a binomial schedule over passes; the block starts that are
+    not kept are regenerated by streamed forward passes) against the
+    resident sweep.  With 4 banks (time t, time 0 and the two a
+    regeneration needs) each block start is regenerated from time 0: 1 + 2
+    + ... + 11 = 66 passes.  More banks, fewer passes; the state at the
+    final time survives the sweep, and a second sweep gives the same
+    gradient."""
+    from tests.gpu_util import gpu_gradient_store_all
+    spec = grad_spec()
+    N = spec.n_steps
+    res_sim, g_res, _ = gpu_gradient_store_all(spec, dtype, _cot, kernel="split")
+    s = StreamedSimulation(spec, 14, 5, dtype=dtype, host_banks=banks)
+    s.step(N)
+    for mi, m in enumerate(spec.monitors):
+        s.set_cotangent(mi, _cot(mi, m, s.spectra(mi)[:N] if m.kind == "probe" else s.spectra(mi)))
+    s.reverse()
+    g = s.grad()
+    info = s.info()
+    r = rel(g, g_res)
+    print(f"streamed gradient {dtype} with {banks} host banks: rel L2 vs resident {r:.3e}, "
+          f"{info['replay_passes']} replayed passes, host {info['host_bytes']:.3e} B", flush=True)
+    assert r < tol
+    if banks == 4:
+        assert info["replay_passes"] == 66
+    else:
+        assert 0 < info["replay_passes"] < 66
+    # the forward state at step N is intact
+    ref = Simulation(spec, dtype=dtype, kernel="split")
+    ref.step(N)
+    for q in range(6):
+        assert np.array_equal(s.field(q), ref.field(q))
+    ref.close()
+    s.reverse()
+    assert np.array_equal(s.grad(), g)
+    s.close()
+
+
+def test_streamed_bounded_banks_host_memory():
+    """Bounded banks hold the host state to the bank count: 4 banks against
+    one per pass boundary (13 for 12 passes)."""
+    spec = grad_spec()
+    a = StreamedSimulation(spec, 14, 5, dtype="f32")
+    b = StreamedSimulation(spec, 14, 5, dtype="f32", host_banks=4)
+    ha, hb = a.info()["host_bytes"], b.info()["host_bytes"]
+    a.close()
+    b.close()
+    assert hb < 0.6 * ha, (ha, hb)
