@@ -169,8 +169,7 @@ typedef struct {
                                       the last one is the first one times bloch_sign.  x and y only, with no
                                       absorbing cells on that axis, split kernels; with a gradient (the
                                       adjoint scatters across the seam with the same real factor, its own
-                                      conjugate) no dispersive box and no reversible mode: else
-                                      FDTD_E_INVALID */
+                                      conjugate) no reversible mode: else FDTD_E_INVALID */
     int32_t bloch_sign[3];         /* real Bloch factor exp(i k L) of a periodic axis: +1 (periodic) or -1
                                       (anti-periodic); ignored on other axes */
 } fdtd_domain_desc;

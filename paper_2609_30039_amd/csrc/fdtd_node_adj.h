@@ -104,4 +104,63 @@ struct HtGather {
     }
 };
 
+// E-update transpose at E node c of a domain that may have periodic axes
+// (the walls' masks from e_masked_d): from etot, the cotangent of E^{n+1}
+// after the H transpose, the cotangent of E^{n+1} before the source (epre),
+// the curl's coefficient (eps^-1, or 1/den in a dispersive cell) and, with
+// the pole histories' transposes stored into set ws, the new cotangent of
+// E^n.  The same recursion as the walled domains' et_node.
+template <typename T>
+__device__ __forceinline__ AdjE<T> et_node_d(const DomDev<T>& d, int c, int i, int j, int k, T etot, int rs, int ws) {
+    AdjE<T> r;
+    r.epre = T(0);
+    r.coef = T(0);
+    r.en = T(0);
+    const long long as = d.as;
+    if (e_masked_d(d, c, i, j, k)) {
+        if (in_lor(d, i, j, k)) {
+            const long long q = lidx(d, i, j, k) + ws * as;
+            gp(d.lora[0][c])[q] = T(0);
+            for (int p = 0; p < d.npole; ++p) {
+                gp(d.lora[1][c])[q + p * d.lbox] = T(0);
+                gp(d.lora[2][c])[q + p * d.lbox] = T(0);
+            }
+        }
+        return r;
+    }
+    const T einv = epsinv_at(d, c, i, j, k);
+    if (!in_lor(d, i, j, k)) {
+        r.epre = etot;
+        r.coef = einv;
+        r.en = etot;
+        return r;
+    }
+    // each pole's roll W^{n+1} = al W^n + xi W^{n-1} + g/2 (E^{n+1} - E^{n-1}) feeds E^{n+1};
+    // E^{n+1}_pre = [einf E^n + gsum/4 E^{n-1} + S curl - sum ((1 + al) W^n + xi W^{n-1}) / 2] / den
+    const long long q = lidx(d, i, j, k);
+    const T einf = T(1) / einv;
+    const T invden = T(1) / (einf + T(0.25) * d.lgs);
+    T ep = etot;
+    for (int p = 0; p < d.npole; ++p) ep = fma(T(0.5) * d.lg[p], gp(d.lora[1][c])[q + p * d.lbox + rs * as], ep);
+    r.epre = ep;
+    r.coef = invden;
+    const T s = ep * invden;
+    r.en = fma(einf, s, gp(d.lora[0][c])[q + rs * as]);
+    T enm1 = T(0);
+    for (int p = 0; p < d.npole; ++p) {
+        const long long o = q + p * d.lbox;
+        const T wb = gp(d.lora[1][c])[o + rs * as], wob = gp(d.lora[2][c])[o + rs * as];
+        T wn = fma(d.lal[p], wb, wob);
+        T wnm1 = d.lxi[p] * wb;
+        enm1 = p == 0 ? -T(0.5) * d.lg[0] * wb : fma(-T(0.5) * d.lg[p], wb, enm1);
+        wn = fma(-T(0.5) * (T(1) + d.lal[p]), s, wn);
+        wnm1 = fma(-T(0.5) * d.lxi[p], s, wnm1);
+        gp(d.lora[1][c])[o + ws * as] = wn;
+        gp(d.lora[2][c])[o + ws * as] = wnm1;
+    }
+    enm1 = fma(T(0.25) * d.lgs, s, enm1);
+    gp(d.lora[0][c])[q + ws * as] = enm1;
+    return r;
+}
+
 }  // namespace fdtd

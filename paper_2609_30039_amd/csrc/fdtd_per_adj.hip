@@ -9,11 +9,11 @@
 // split adjoint's two passes written per node with the seam in their
 // neighbour gathers:
 //   k_padj_e  per E node: the H-update transpose gathered onto the node, the
-//             new Ebar (no dispersion in a periodic domain with a gradient,
-//             so the E-update transpose is the identity on E^n), the scaled
-//             cotangent u = S eps^-1 Ebar into the scratch Et, the E-side
-//             memory cotangents (absorbing faces on the other axes) and
-//             dJ/deps from the forward state;
+//             E-update transpose (the identity on E^n, or in a dispersive
+//             cell the pole histories' transposes) into the new Ebar, the
+//             scaled cotangent u = S coef Ebar_pre into the scratch Et, the
+//             E-side memory cotangents (absorbing faces on the other axes)
+//             and dJ/deps from the forward state;
 //   k_padj_h  per H node: u through the transposed absorber recursion and
 //             the curl into the new Hbar, and the H-side memory cotangents.
 // Each thread marches one (i, j) column of kNodeKz planes (fdtd_node_adj.h),
@@ -40,11 +40,13 @@ __global__ void __launch_bounds__(256) k_padj_e(const DomDev<T>* __restrict__ dp
     for (int k = k0; k < k1; ++k) {
         const long long f = fidx(d, i, j, k);
         const int x[3] = {i, j, k};
-        T et[3], u[3];
+        T et[3], u[3], epre[3];
         hg.plane(k, f, et);
         for (int e = 0; e < 3; ++e) {
-            u[e] = e_masked_d(d, e, i, j, k) ? T(0) : S * epsinv_at(d, e, i, j, k) * et[e];
-            gp(d.Ea[e])[f + wo] = et[e];
+            const AdjE<T> r = et_node_d(d, e, i, j, k, et[e], rs, ws);
+            epre[e] = r.epre;
+            u[e] = e_masked_d(d, e, i, j, k) ? T(0) : S * r.coef * r.epre;
+            gp(d.Ea[e])[f + wo] = r.en;
             gp(d.Et[e])[f] = u[e];
         }
         // E-side memory cotangents (owner): ybar = +u (term 0), -u (term 1)
@@ -67,7 +69,7 @@ __global__ void __launch_bounds__(256) k_padj_e(const DomDev<T>* __restrict__ dp
             T fac;
             const T h0m = back_node(d, a0, x, y, fac) ? fac * H0[fidx(d, y[0], y[1], y[2])] : T(0);
             const T h1m = back_node(d, a1, x, y, fac) ? fac * H1[fidx(d, y[0], y[1], y[2])] : T(0);
-            g[c] = grad_term(d, c, i, j, k, f, et[c], H0[f], h0m, H1[f], h1m, fsr);
+            g[c] = grad_term(d, c, i, j, k, f, epre[c], H0[f], h0m, H1[f], h1m, fsr);
         }
         grad_store(d, i, j, k, g);
     }

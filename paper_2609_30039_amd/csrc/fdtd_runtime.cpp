@@ -1108,8 +1108,6 @@ struct Handle : Base {
                 return fail(FDTD_E_INVALID, "a periodic axis takes no absorbing cells");
             if (s.bloch_sign[a] != 1 && s.bloch_sign[a] != -1)
                 return fail(FDTD_E_INVALID, "bloch_sign of a periodic axis must be +1 or -1");
-            if (s.grad && s.n_lorentz)
-                return fail(FDTD_E_INVALID, "periodic domains with a gradient take no dispersive box");
             if (opt.reversible && s.grad)
                 return fail(FDTD_E_INVALID, "periodic domains with a gradient take no reversible mode");
             if (opt.kernel == FDTD_KERNEL_FUSED) return fail(FDTD_E_INVALID, "periodic domains need the split kernels");

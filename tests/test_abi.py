@@ -177,8 +177,8 @@ def test_reversible_mode_admissibility():
 
 def test_periodic_descriptor_checked():
     """Periodic axes: x and y only, no absorbing cells on them, a Bloch sign of
-    +1 or -1, split kernels; a gradient without a dispersive box or the
-    reversible mode; an admissible one passes validation (the tiny budget
+    +1 or -1, split kernels; a gradient (with a dispersive box too) but not
+    the reversible mode; an admissible one passes validation (the tiny budget
     then refuses)."""
     def spec(**kw):
         s = W.DomainSpec(shape=(8, 8, 12), courant=W.courant_3d(), pml=(0, 0, 0, 0, 3, 3), eps_kind="iso",
@@ -195,7 +195,7 @@ def test_periodic_descriptor_checked():
     _refused(spec(), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
     g = ((2, 2, 4), (6, 6, 8))
     _passes_validation(spec(grad_box=g))
-    _refused(spec(grad_box=g, lorentz=[W.LorentzSpec((2, 2, 4), (5, 5, 7), 1.0, 0.3, 0.01)]), B.FDTD_E_INVALID)
+    _passes_validation(spec(grad_box=g, lorentz=[W.LorentzSpec((2, 2, 4), (5, 5, 7), 1.0, 0.3, 0.01)]))
     _refused(spec(grad_box=g), B.FDTD_E_INVALID, reversible=True, max_steps=4)
 
 

@@ -70,13 +70,14 @@ def test_lossless_slab_eq5_on_the_gpu():
 
 
 def test_periodic_refusals():
+    """Periodic axes need the split kernels; with a gradient, no reversible mode."""
     from paper_2609_30039_amd import binding as B
     spec = _periodic_spec((1, 1))
     with pytest.raises(B.FdtdError):
         Simulation(spec, dtype="f32", kernel="fused")
     spec.grad_box = ((5, 5, 10), (20, 15, 20))
     with pytest.raises(B.FdtdError):
-        Simulation(spec, dtype="f32")
+        Simulation(spec, dtype="f32", reversible=True, max_steps=10)
 
 
 # ---------------------------------------------------------------- the adjoint
@@ -226,3 +227,25 @@ def test_eq5_slab_index_derivative_f64():
           f"rel {abs(dJ - fd) / abs(fd):.2e}", flush=True)
     assert abs(dJ - fd) <= 1e-6 * abs(fd)
     assert nz == 132
+
+
+@pytest.mark.parametrize("signs", [(1, 1), (-1, 1)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 2e-5)])
+def test_periodic_dispersive_gradient_matches_oracle(signs, dtype, tol):
+    """The periodic cell with its Lorentz box on the x seam (the pole
+    histories' transposes next to the seam) and the gradient box over the
+    box, across both seams and into the z faces: dJ/deps against the oracle."""
+    from tests.gpu_util import gpu_gradient_store_all, oracle_gradient
+    spec = _periodic_spec(signs, n_steps=100)
+    nx, ny, nz = spec.shape
+    spec.grad_box = ((0, 0, 3), (nx, ny, nz - 3))
+    _, g, _ = gpu_gradient_store_all(spec, dtype, _cot, kernel="split")
+    _, ref = oracle_gradient(spec, _cot)
+    (i0, j0, k0), (i1, j1, k1) = spec.grad_box
+    ref = ref[:, k0:k1, j0:j1, i0:i1].sum(axis=0)
+    r = rel(g[0], ref)
+    L = spec.lorentz[0]
+    rl = rel(g[0][L.lo[2] - k0:L.hi[2] - k0, L.lo[1]:L.hi[1], L.lo[0]:L.hi[0]],
+             ref[L.lo[2] - k0:L.hi[2] - k0, L.lo[1]:L.hi[1], L.lo[0]:L.hi[0]])
+    print(f"periodic dispersive gradient signs={signs} {dtype}: rel L2 {r:.2e} (dispersive box {rl:.2e})", flush=True)
+    assert r < tol and rl < 5 * tol
