@@ -117,7 +117,8 @@ struct DomDev {
     T* psiHa[3][2][2];
     T* lora[3][3];
     int glo[3], ghi[3];
-    double* gacc[3];           // dJ/deps accumulators over the gradient box (isotropic: [0] only)
+    double* gacc[6];           // dJ/deps accumulators over the gradient box: [0] isotropic, [0..2]
+                               // diagonal, [0..5] the stored entries of a node tensor
     // ---- reversible mode: the lossless box R = [rlo, rhi) (the cells outside
     // every absorbing slab) is stepped backward; rec holds, per forward step
     // index, the fields just outside R that its backward steps need: H on the
