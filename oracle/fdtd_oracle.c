@@ -21,9 +21,11 @@
  *     delta_eps omega_0^2 -> omega_p^2.
  *   - Symmetric tensor media (Section 2.3): eps at the grid nodes, inverted
  *     there, and applied to the curl through the node assembly
- *     (1/8) sum over the eight octants of R^T eps^-1 R; its transpose is
- *     itself, and the gradient of a node's tensor collects, octant by octant,
- *     the outer product of the E cotangent and the curl on the octant's edges.
+ *     (1/8) sum over the eight octants of R^T eps^-1 R (across a periodic
+ *     seam the node and edges at the other end, the edges times the Bloch
+ *     factor); its transpose is itself, and the gradient of a node's tensor
+ *     collects, octant by octant, the outer product of the E cotangent and
+ *     the curl on the octant's edges.
  *   - Discrete adjoint, Eq. (3) of Section 3.1, with the transposes of
  *     Section 3.1 (opposite-direction differences, the absorber transpose,
  *     the 2x2 dispersion transpose, eps cotangent = E cotangent x curl, and
@@ -201,19 +203,34 @@ static double e_pre(const orc_params *P, const orc_state *U, int c, size_t p, do
  *   4. H update with its absorber memories.
  * src_*: the increments of this step.  work: three full-grid scratch arrays.
  */
-/* eps^-1 component (a, b) at node v (entries beyond the arrays: the background) */
+/* eps^-1 component (a, b) at node v.  Nodes past the arrays' high end take
+   the background, or on a periodic axis are the node at the other end (the
+   medium repeats; the Bloch factor multiplies fields, not materials). */
 static double node_einv(const orc_params *P, const int v[3], int a, int b) {
-    if (v[0] >= P->n[0] || v[1] >= P->n[1] || v[2] >= P->n[2]) return a == b ? P->einv_bg : 0.0;
+    int w[3] = {v[0], v[1], v[2]};
+    for (int q = 0; q < 3; ++q)
+        if (w[q] >= P->n[q]) {
+            if (!P->per[q]) return a == b ? P->einv_bg : 0.0;
+            w[q] -= P->n[q];
+        }
     static const int comp[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    return P->einvT[comp[a][b]][IDX(P, v[0], v[1], v[2])];
+    return P->einvT[comp[a][b]][IDX(P, w[0], w[1], w[2])];
 }
 
-/* curl value of the E edge of component b starting at node v (zero past the
-   domain; the caller zeroes masked edges) */
+/* value of the E-edge array Cc of component b at the edge starting at node v:
+   zero past a wall; across a periodic seam the edge at the other end times
+   the Bloch factor (F(N) = bsign F(0), F(-1) = bsign F(N-1) for the real
+   factors).  The caller zeroes masked edges. */
 static double edge_curl(const orc_params *P, double *const Cc[3], int b, const int v[3]) {
-    for (int a = 0; a < 3; ++a)
-        if (v[a] < 0 || v[a] >= P->n[a]) return 0.0;
-    return Cc[b][IDX(P, v[0], v[1], v[2])];
+    int w[3] = {v[0], v[1], v[2]};
+    double fac = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (w[a] >= 0 && w[a] < P->n[a]) continue;
+        if (!P->per[a]) return 0.0;
+        w[a] += w[a] < 0 ? P->n[a] : -P->n[a];
+        fac *= P->bsign[a];
+    }
+    return fac * Cc[b][IDX(P, w[0], w[1], w[2])];
 }
 
 /* The node-assembled tensor applied to the curl, at the E edge of component c

@@ -167,7 +167,7 @@ class OracleSim:
         self.tensor = spec.eps_kind == "tensor"
         if self.tensor:
             # Section 2.3: the symmetric tensor at each node, inverted there
-            assert not spec.lorentz and not any(spec.periodic), "tensor media: no dispersion, no Bloch axes"
+            assert not spec.lorentz, "tensor media: no dispersive box"
             en = spec.eps_nodes()
             m = np.empty(en.shape[1:] + (3, 3))
             for q, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):

@@ -15,6 +15,11 @@ principal axis with a non-intermediate eigenvalue and growth for the
 rejected cases (an intermediate normal eigenvalue, principal axes rotated
 against the normal).
 
+On Bloch grids (x and y periodic with real factors): the octant assembly
+across the seams, unit radii for admitted tensors, growth for the rejected
+ones in absorbing z faces, the energy invariant, the adjoint's dot product
+and central differences at seam nodes.
+
 The adjoint (Section 3.1 with the tensor of Section 2.3): the dot-product
 identity of the step map with admitted tensors in absorbing faces; the
 one-step eps^-1 gradient against the derivative of the octant-built
@@ -539,3 +544,232 @@ def _run_probe_J(spec):
     sim = O.OracleSim(spec)
     sim.step(spec.n_steps)
     return np.sum(sim.probe(0) ** 2)
+
+
+# ------------------------------------------------------------ Bloch-periodic tensor media
+def _assembly_by_octants_bloch(spec):
+    """The assembled operator of a domain periodic in x and/or y: the node
+    set is 0..n-1 along a periodic axis (node n is node 0), the edges seen
+    from a node across the seam are the edges at the other end times the
+    Bloch factor, and both factors enter the node's 3x3 form."""
+    nx, ny, nz = spec.shape
+    n = (nx, ny, nz)
+    N = nx * ny * nz
+    per = tuple(int(p) for p in spec.periodic)
+    sign = tuple(float(s) for s in spec.bloch_sign)
+    en = spec.eps_nodes()
+
+    def einv(v):
+        w = list(v)
+        for a in range(3):
+            if w[a] >= n[a]:
+                if not per[a]:
+                    return np.eye(3) / spec.eps_bg
+                w[a] -= n[a]
+        m = np.zeros((3, 3))
+        for q, (a, b) in enumerate(COMP):
+            m[a, b] = m[b, a] = en[q, w[2], w[1], w[0]]
+        return np.linalg.inv(m)
+
+    def edge(b, start):
+        w = list(start)
+        f = 1.0
+        for a in range(3):
+            if 0 <= w[a] < n[a]:
+                continue
+            if not per[a]:
+                return None, 0.0
+            w[a] += n[a] if w[a] < 0 else -n[a]
+            f *= sign[a]
+        masked = any(w[(b + t) % 3] == 0 and not per[(b + t) % 3] for t in (1, 2))
+        if masked:
+            return None, 0.0
+        return b * N + (w[2] * ny + w[1]) * nx + w[0], f
+
+    M = np.zeros((3 * N, 3 * N))
+    ranges = [range(n[a]) if per[a] else range(n[a] + 1) for a in range(3)]
+    for k in ranges[2]:
+        for j in ranges[1]:
+            for i in ranges[0]:
+                v = (i, j, k)
+                A = einv(v)
+                for s in range(8):
+                    rows = []
+                    for b in range(3):
+                        st = list(v)
+                        st[b] -= (s >> b) & 1
+                        rows.append(edge(b, st))
+                    for a in range(3):
+                        for b in range(3):
+                            (ra, fa), (rb, fb) = rows[a], rows[b]
+                            if ra is not None and rb is not None:
+                                M[ra, rb] += A[a, b] * fa * fb / 8.0
+    return M
+
+
+@pytest.mark.parametrize("signs", [(1, 1), (-1, 1), (-1, -1)])
+def test_tensor_step_is_the_octant_assembly_bloch(signs):
+    """One step from E = 0 and a random H on a cell periodic in x and y: the
+    tensor update equals S M C^-(H) with M built octant by octant across the
+    seams (the curl's own seam taken from the oracle's scalar step, which the
+    scalar pins fix); M is symmetric with eigenvalues in (0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(25))
+    shape = (5, 4, 6)
+    nx, ny, nz = shape
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), eps_kind="tensor", eps_box=((0, 0, 0), shape),
+                        eps=random_tensors(rng, shape), eps_bg=1.0, periodic=(1, 1, 0),
+                        bloch_sign=(signs[0], signs[1], 1))
+    sim = O.OracleSim(spec)
+    H = rng.standard_normal((3, nz, ny, nx))
+    for c in range(3):
+        sim.u[O.F0 + 3 + c] = H[c].reshape(-1)
+    sim.step(1, record=False)
+    # the curl by the scalar oracle: eps = 1 everywhere, one step from the same H
+    iso = W.DomainSpec(shape=shape, courant=W.courant_3d(), eps_kind="iso", eps_box=((0, 0, 0), shape),
+                       eps=np.ones((1, nz, ny, nx)), periodic=(1, 1, 0), bloch_sign=(signs[0], signs[1], 1))
+    si = O.OracleSim(iso)
+    for c in range(3):
+        si.u[O.F0 + 3 + c] = H[c].reshape(-1)
+    si.step(1, record=False)
+    curl = np.concatenate([si.field(c).reshape(-1) for c in range(3)]) / spec.courant
+    M = _assembly_by_octants_bloch(spec)
+    dof = sim.dof_mask()[:3].reshape(-1)
+    want = spec.courant * (M @ (curl * dof)) * dof
+    got = np.concatenate([sim.field(q).reshape(-1) for q in range(3)])
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    Md = M[np.ix_(dof, dof)]
+    assert np.max(np.abs(Md - Md.T)) < 1e-15
+    w = np.linalg.eigvalsh(0.5 * (Md + Md.T))
+    assert w.min() > 0.0 and w.max() <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("signs", [(1, 1), (-1, 1), (-1, -1)])
+def test_spectral_radius_admitted_tensors_bloch_grid(signs):
+    """On small Bloch grids (x and y periodic, z walled) with random rotated
+    tensors at every node, every eigenvalue of the one-step operator lies on
+    the unit circle (Appendix A: one to nine decimals)."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    shape = (4, 4, 5)
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(0.99), eps_kind="tensor", eps_box=((0, 0, 0), shape),
+                        eps=random_tensors(rng, shape), periodic=(1, 1, 0), bloch_sign=(signs[0], signs[1], 1))
+    lam = np.abs(np.linalg.eigvals(_one_step_matrix(O.OracleSim(spec))))
+    assert np.max(np.abs(lam - 1.0)) < 1e-12
+
+
+def _face_spec_bloch(m, shape):
+    return W.DomainSpec(shape=shape, courant=W.courant_3d(0.99), pml=FACE_PML, eps_kind="tensor",
+                        eps_box=((0, 0, 0), shape), eps=uniform_tensor(shape, m), periodic=(1, 1, 0))
+
+
+@pytest.mark.parametrize("name", sorted(ADMITTED))
+def test_absorbing_face_admitted_tensor_bloch(name):
+    """A Bloch grid (x, y periodic) with absorbing z faces filled by an
+    admitted tensor: spectral radius 1 to round-off."""
+    assert _radius(_face_spec_bloch(ADMITTED[name], FACE_SHAPE)) <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(REJECTED))
+def test_absorbing_face_rejected_tensor_grows_bloch(name):
+    """The rejected tensors in the absorbing z faces of a Bloch grid grow
+    (measured 1.0028, 1.0132 and 1.0082 here; the paper's Bloch grids: radii
+    1.0049 to 1.0089)."""
+    m, shape, bar = REJECTED[name]
+    r = _radius(_face_spec_bloch(m, shape))
+    assert r > 1.0 + bar, r
+
+
+def test_tensor_energy_invariant_bloch():
+    """A lossless Bloch cell (x anti-periodic, y periodic, z walled) with
+    random rotated tensors: <E, M^-1 E> + <H^{n-1/2}, H^{n+1/2}> with M the
+    octant assembly across the seams is conserved over 300 steps."""
+    rng = np.random.Generator(np.random.PCG64(27))
+    shape = (5, 4, 6)
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(0.99), eps_kind="tensor", eps_box=((0, 0, 0), shape),
+                        eps=random_tensors(rng, shape), periodic=(1, 1, 0), bloch_sign=(-1, 1, 1))
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    sim.u[:] = rng.standard_normal(sim.u.shape) * dof
+    sim.u[O.PSIE0:] = 0.0
+    M = _assembly_by_octants_bloch(spec)
+    edof = dof[:3].reshape(-1)
+    Minv = np.linalg.inv(M[np.ix_(edof, edof)])
+
+    def energy(h_prev):
+        e = np.concatenate([sim.field(c).reshape(-1) for c in range(3)])[edof]
+        return e @ Minv @ e + sum(np.sum(h_prev[c] * sim.field(3 + c)) for c in range(3))
+
+    hist = []
+    for _ in range(300):
+        h_prev = [sim.field(3 + c).copy() for c in range(3)]
+        sim.step(1, record=False)
+        hist.append(energy(h_prev))
+    hist = np.asarray(hist)
+    assert np.max(np.abs(hist - hist[0])) / abs(hist[0]) < 1e-11
+
+
+@pytest.mark.parametrize("nsteps", [1, 30])
+def test_tensor_adjoint_dot_product_bloch(nsteps):
+    """The dot-product identity of the step map of a Bloch cell (x
+    anti-periodic, y periodic) with random tensors inside and admitted ones
+    in its absorbing z faces."""
+    rng = np.random.Generator(np.random.PCG64(35))
+    shape = (6, 5, 12)
+    nx, ny, nz = shape
+    eps = random_tensors(rng, shape, 1.0, 3.0)
+    face = _pack(_rz(0.4) @ np.diag([1.5, 2.5, 4.0]) @ _rz(0.4).T)
+    eps[:, :3] = face[:, None, None, None]
+    eps[:, -3:] = face[:, None, None, None]
+    spec = W.DomainSpec(shape=shape, courant=W.courant_3d(), pml=(0, 0, 0, 0, 3, 3), eps_kind="tensor",
+                        eps_box=((0, 0, 0), shape), eps=eps, periodic=(1, 1, 0), bloch_sign=(-1, 1, 1))
+    sim = O.OracleSim(spec)
+    dof = sim.dof_mask()
+    x = rng.standard_normal(sim.u.shape) * dof
+    y = rng.standard_normal(sim.u.shape) * dof
+    ax = x.copy()
+    for t in range(nsteps):
+        sim.step_state(ax, t, sources=False)
+    aty = y.copy()
+    for t in range(nsteps):
+        sim.adjoint_step_state(aty, x, None)
+    lhs, rhs = np.sum(ax * y * dof), np.sum(x * aty * dof)
+    scale = np.linalg.norm(ax * dof) * np.linalg.norm(y)
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    assert np.all(aty[~dof] == 0.0)
+
+
+def test_tensor_gradient_central_differences_bloch():
+    """dJ/deps of node tensors on both seams of a Bloch cell (x
+    anti-periodic) against fourth-order central differences."""
+    rng = np.random.Generator(np.random.PCG64(43))
+    nx, ny, nz = 6, 5, 30
+    shape = (nx, ny, nz)
+    n_steps = 60
+    lo, hi = (0, 0, 10), (nx, ny, 20)
+    spec = W.DomainSpec(
+        shape=shape, courant=W.courant_3d(), pml=(0, 0, 0, 0, 6, 6), eps_kind="tensor", eps_box=(lo, hi),
+        eps=random_tensors(rng, (nx, ny, 10), 1.0, 3.0), eps_bg=1.0, periodic=(1, 1, 0), bloch_sign=(-1, 1, 1),
+        sources=[W.SourceSpec("plane_z", 0, (0, 0, 7), W.gaussian_sine(n_steps, 0.5, 8.0, 24.0)),
+                 W.SourceSpec("point", 1, (0, 2, 8), W.gaussian_sine(n_steps, 0.6, 6.0, 18.0))],
+        monitors=[W.MonitorSpec("flux_z", pos=(0, 0, 22), rect=(0, nx, 0, ny), omega_dt=np.array([0.45, 0.6]))],
+        n_steps=n_steps)
+
+    def run(sp):
+        sim = O.OracleSim(sp)
+        sim.step(sp.n_steps)
+        f = sim.spectra(0)
+        g = np.zeros_like(f)
+        g[:, 0], g[:, 3], g[:, 1], g[:, 2] = f[:, 3], f[:, 0], -f[:, 2], -f[:, 1]
+        return sim, float(np.sum(O.OracleSim.flux_from_spectra(f))), g
+
+    sim, J, cot = run(spec)
+    g = sim.gradient({0: cot}, n_steps)
+    for (i, j, k) in [(0, 2, 12), (5, 0, 15), (3, 4, 18)]:
+        for q in range(6):
+            h = 2e-3
+            vals = {}
+            for m in (-2, -1, 1, 2):
+                e = spec.eps.copy()
+                e[q, k - lo[2], j, i] += m * h
+                vals[m] = run(W.DomainSpec(**{**spec.__dict__, "eps": e}))[1]
+            fd = (8.0 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12.0 * h)
+            assert abs(g[q, k, j, i] - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(J), (i, j, k, q, g[q, k, j, i], fd)
