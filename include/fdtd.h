@@ -74,9 +74,11 @@ enum { FDTD_F32 = 0, FDTD_F64 = 1, FDTD_BF16 = 2 };
    eigenvalues >= 1; inside an absorbing face (node index along the normal in
    the slab) the normal must be a principal axis (zero off-diagonal entries
    with it) whose eigenvalue is the largest or the smallest: else
-   FDTD_E_UNSTABLE, checked node by node.  TENSOR domains take no dispersive
-   box, no periodic axis, no reversible mode and no fused kernels
-   (FDTD_E_INVALID), and one scratch curl of 3 field arrays each.  Their
+   FDTD_E_UNSTABLE, checked node by node.  On a periodic axis the node
+   tensors repeat past the seam (the node past the last one is the first)
+   and the edges past it take the Bloch factor.  TENSOR domains take no
+   dispersive box, no reversible mode and no fused kernels (FDTD_E_INVALID),
+   and one scratch curl of 3 field arrays each.  Their
    gradient (Section 3.1 through the assembly, which is its own transpose)
    is dJ/deps of the six stored entries of each node tensor in the gradient
    box, an off-diagonal entry counting as one parameter for both of its

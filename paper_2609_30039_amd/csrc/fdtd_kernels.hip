@@ -648,7 +648,9 @@ struct TensPlane {
 
 // Per-column addressing of the assembly pass: curl and node-tensor offsets
 // of (i,j) with the in-grid and in-box tests of the x and y neighbours
-// evaluated once per column; the per-plane tests are on k alone.
+// evaluated once per column; the per-plane tests are on k alone.  Across a
+// periodic seam a neighbour column is the one at the other end: its edges
+// carry the real Bloch factor, its node tensors repeat unchanged.
 template <typename T>
 struct TensCol {
     const FDTD_GLOBAL T* c[3];           // curl arrays
@@ -656,8 +658,11 @@ struct TensCol {
     long long fc;                        // field offset of (i, j, 0)
     long long qc;                        // box offset of (i, j, elo_z) (valid when the column is in the box)
     long long pl, bpl;                   // field plane, box plane
+    long long oxm, oxp, oym, oyp;        // field offsets of the columns i-1, i+1, j-1, j+1 from (i, j)
+    long long qxp, qyp;                  // box offsets of the node columns i+1 and j+1 from (i, j)
+    T fxm, fxp, fym, fyp;                // their edges' Bloch factors (1 inside the grid)
     int pitch, bx;
-    bool xm, xp, ym, yp;                 // i-1 >= 0, i+1 < nx, j-1 >= 0, j+1 < ny
+    bool xm, xp, ym, yp;                 // the neighbour column exists (inside the grid or across a seam)
     bool bxy, bxpy, bxyp;                // (i,j), (i+1,j), (i,j+1) inside the box's x-y extent
     int nz, ez0, ez1;
     T bg;
@@ -680,28 +685,28 @@ __device__ __forceinline__ T ta(const TensCol<T>& m, int q, long long off, bool 
 template <typename T>
 __device__ __forceinline__ void tens_fetch(const TensCol<T>& m, TensPlane<T>& p, const FDTD_GLOBAL T* const (&e)[3],
                                            int k, long long f) {
-    const long long o = (long long)k * m.pl, P = m.pitch, X = m.bx;
+    const long long o = (long long)k * m.pl;
     const bool up = k + 1 < m.nz;
     p.cz = tc(m, 2, o, true);
-    p.cz_xp = tc(m, 2, o + 1, m.xp);
-    p.cz_yp = tc(m, 2, o + P, m.yp);
-    p.cy_xp = tc(m, 1, o + 1, m.xp);
-    p.cy_xpym = tc(m, 1, o + 1 - P, m.xp && m.ym);
-    p.cx_yp = tc(m, 0, o + P, m.yp);
-    p.cx_xmyp = tc(m, 0, o - 1 + P, m.xm && m.yp);
+    p.cz_xp = m.fxp * tc(m, 2, o + m.oxp, m.xp);
+    p.cz_yp = m.fyp * tc(m, 2, o + m.oyp, m.yp);
+    p.cy_xp = m.fxp * tc(m, 1, o + m.oxp, m.xp);
+    p.cy_xpym = (m.fxp * m.fym) * tc(m, 1, o + m.oxp + m.oym, m.xp && m.ym);
+    p.cx_yp = m.fyp * tc(m, 0, o + m.oyp, m.yp);
+    p.cx_xmyp = (m.fxm * m.fyp) * tc(m, 0, o + m.oxm + m.oyp, m.xm && m.yp);
     p.cx_zp = tc(m, 0, o + m.pl, up);
-    p.cx_xmzp = tc(m, 0, o + m.pl - 1, up && m.xm);
+    p.cx_xmzp = m.fxm * tc(m, 0, o + m.pl + m.oxm, up && m.xm);
     p.cy_zp = tc(m, 1, o + m.pl, up);
-    p.cy_ymzp = tc(m, 1, o + m.pl - P, up && m.ym);
+    p.cy_ymzp = m.fym * tc(m, 1, o + m.pl + m.oym, up && m.ym);
     p.a_xx = ta(m, 0, 0, m.bxy, k);
     p.a_yy = ta(m, 1, 0, m.bxy, k);
     p.a_xy = ta(m, 3, 0, m.bxy, k);
-    p.axp_xx = ta(m, 0, 1, m.bxpy, k);
-    p.axp_xy = ta(m, 3, 1, m.bxpy, k);
-    p.axp_xz = ta(m, 4, 1, m.bxpy, k);
-    p.ayp_yy = ta(m, 1, X, m.bxyp, k);
-    p.ayp_xy = ta(m, 3, X, m.bxyp, k);
-    p.ayp_yz = ta(m, 5, X, m.bxyp, k);
+    p.axp_xx = ta(m, 0, m.qxp, m.bxpy, k);
+    p.axp_xy = ta(m, 3, m.qxp, m.bxpy, k);
+    p.axp_xz = ta(m, 4, m.qxp, m.bxpy, k);
+    p.ayp_yy = ta(m, 1, m.qyp, m.bxyp, k);
+    p.ayp_xy = ta(m, 3, m.qyp, m.bxyp, k);
+    p.ayp_yz = ta(m, 5, m.qyp, m.bxyp, k);
     p.azp_zz = ta(m, 2, 0, m.bxy, k + 1);
     p.azp_xz = ta(m, 4, 0, m.bxy, k + 1);
     p.azp_yz = ta(m, 5, 0, m.bxy, k + 1);
@@ -715,7 +720,9 @@ __device__ __forceinline__ void tens_fetch(const TensCol<T>& m, TensPlane<T>& p,
 // component c from node v0 to v1 = v0 + e_c takes, at each end v,
 // eps^-1_cc(v)/2 times its own curl and eps^-1_cb(v)/4 times the sum of the
 // curls of the two b edges meeting at v (leaving and arriving), b != c.
-// Edges tangential to a wall keep E = 0.  Reads and writes only its own E
+// Edges tangential to a wall keep E = 0; on a periodic axis the edges and
+// nodes past the seam are those at the other end (Section 2.2), the edges
+// times the real Bloch factor.  Reads and writes only its own E
 // nodes, so it runs in place like the other split kernels.  Along z the
 // column keeps what plane k+1 shares with plane k (the Cz below, the Cx and
 // Cy above, the node above) in registers, and fetches plane k+1's other
@@ -744,12 +751,29 @@ __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ do
     m.bx = d.exs;
     m.bpl = (long long)m.bx * (d.ehi[1] - d.elo[1]);
     m.qc = (long long)(j - d.elo[1]) * m.bx + (i - d.exa);
-    m.xm = i > 0;
-    m.xp = i + 1 < d.n[0];
-    m.ym = j > 0;
-    m.yp = j + 1 < d.n[1];
-    const bool inx = i >= d.elo[0] && i < d.ehi[0], inx1 = i + 1 >= d.elo[0] && i + 1 < d.ehi[0];
-    const bool iny = j >= d.elo[1] && j < d.ehi[1], iny1 = j + 1 >= d.elo[1] && j + 1 < d.ehi[1];
+    // neighbour columns: inside the grid, else across a periodic seam (the
+    // column at the other end, the Bloch factor on its edges), else none
+    const long long P = d.pitch;
+    const int nx1 = d.n[0] - 1, ny1 = d.n[1] - 1;
+    m.xm = i > 0 || d.per[0];
+    m.xp = i < nx1 || d.per[0];
+    m.ym = j > 0 || d.per[1];
+    m.yp = j < ny1 || d.per[1];
+    m.oxm = i > 0 ? -1 : nx1;
+    m.oxp = i < nx1 ? 1 : -nx1;
+    m.oym = j > 0 ? -P : ny1 * P;
+    m.oyp = j < ny1 ? P : -ny1 * P;
+    m.fxm = i > 0 ? T(1) : d.bsign[0];
+    m.fxp = i < nx1 ? T(1) : d.bsign[0];
+    m.fym = j > 0 ? T(1) : d.bsign[1];
+    m.fyp = j < ny1 ? T(1) : d.bsign[1];
+    // the node columns i+1 and j+1 (the first ones past a seam; past a wall
+    // outside every box)
+    const int i1 = i < nx1 || !d.per[0] ? i + 1 : 0, j1 = j < ny1 || !d.per[1] ? j + 1 : 0;
+    m.qxp = i1 - i;
+    m.qyp = (long long)(j1 - j) * m.bx;
+    const bool inx = i >= d.elo[0] && i < d.ehi[0], inx1 = i1 >= d.elo[0] && i1 < d.ehi[0];
+    const bool iny = j >= d.elo[1] && j < d.ehi[1], iny1 = j1 >= d.elo[1] && j1 < d.ehi[1];
     m.bxy = inx && iny;
     m.bxpy = inx1 && iny;
     m.bxyp = inx && iny1;
@@ -759,10 +783,10 @@ __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ do
     m.bg = d.epsinv_bg;
     // carried into plane k0: Cz below it, Cx and Cy on it, the z-related node entries
     const long long o0 = (long long)k0 * m.pl;
-    T czm = tc(m, 2, o0 - m.pl, k0 > 0), czm_xp = tc(m, 2, o0 - m.pl + 1, k0 > 0 && m.xp),
-      czm_yp = tc(m, 2, o0 - m.pl + m.pitch, k0 > 0 && m.yp);
-    T cx = tc(m, 0, o0, true), cx_xm = tc(m, 0, o0 - 1, m.xm);
-    T cy = tc(m, 1, o0, true), cy_ym = tc(m, 1, o0 - m.pitch, m.ym);
+    T czm = tc(m, 2, o0 - m.pl, k0 > 0), czm_xp = m.fxp * tc(m, 2, o0 - m.pl + m.oxp, k0 > 0 && m.xp),
+      czm_yp = m.fyp * tc(m, 2, o0 - m.pl + m.oyp, k0 > 0 && m.yp);
+    T cx = tc(m, 0, o0, true), cx_xm = m.fxm * tc(m, 0, o0 + m.oxm, m.xm);
+    T cy = tc(m, 1, o0, true), cy_ym = m.fym * tc(m, 1, o0 + m.oym, m.ym);
     T a_zz = ta(m, 2, 0, m.bxy, k0), a_xz = ta(m, 4, 0, m.bxy, k0), a_yz = ta(m, 5, 0, m.bxy, k0);
     long long f = fidx(d, i, j, k0);
     TensPlane<T> cu, nx;

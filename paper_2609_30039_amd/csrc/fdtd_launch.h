@@ -77,13 +77,17 @@ void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, h
 // the E-node work of the split adjoint for tensor domain dom (n: its cells):
 // the H-update transpose into the new Ebar, then u = S M Ebar into the
 // scratch Et, the E-side memory cotangents and the node-tensor gradient;
-// launch_adj's H-node pass completes the step
+// launch_adj's H-node pass completes the step (launch_per_adj_h in a
+// periodic domain)
 template <typename T>
 void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s);
 // the whole adjoint step of Bloch-periodic domain dom (both passes, the seam
 // in their neighbour gathers)
 template <typename T>
 void launch_per_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s);
+// its H-node pass alone: u of the scratch Et into the new Hbar across the seams
+template <typename T>
+void launch_per_adj_h(const void* doms, int dom, const int n[3], int rs, int ws, hipStream_t s);
 template <typename T>
 void launch_sample(const void* doms, const MonDev& m, int cs, int slot, hipStream_t s);
 template <typename T>

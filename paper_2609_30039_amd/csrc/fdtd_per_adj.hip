@@ -144,7 +144,16 @@ void launch_per_adj(const void* doms, int dom, const int n[3], int rs, int ws, i
     hipLaunchKernelGGL(k_padj_h<T>, grid, dim3(256), 0, s, dp, rs, ws);
 }
 
+template <typename T>
+void launch_per_adj_h(const void* doms, int dom, const int n[3], int rs, int ws, hipStream_t s) {
+    const DomDev<T>* dp = (const DomDev<T>*)doms + dom;
+    const dim3 grid((n[0] + kNodeTx - 1) / kNodeTx, (n[1] + kNodeTy - 1) / kNodeTy, (n[2] + kNodeKz - 1) / kNodeKz);
+    hipLaunchKernelGGL(k_padj_h<T>, grid, dim3(256), 0, s, dp, rs, ws);
+}
+
 template void launch_per_adj<float>(const void*, int, const int*, int, int, int, hipStream_t);
 template void launch_per_adj<double>(const void*, int, const int*, int, int, int, hipStream_t);
+template void launch_per_adj_h<float>(const void*, int, const int*, int, int, hipStream_t);
+template void launch_per_adj_h<double>(const void*, int, const int*, int, int, hipStream_t);
 
 }  // namespace fdtd

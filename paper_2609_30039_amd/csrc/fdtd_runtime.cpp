@@ -1093,10 +1093,8 @@ struct Handle : Base {
             }
         }
         if (s.eps_kind == FDTD_EPS_TENSOR) {
-            // the tensor path is nondispersive and walled
+            // the tensor path is nondispersive
             if (s.n_lorentz) return fail(FDTD_E_INVALID, "tensor media take no dispersive box");
-            if (s.periodic[0] || s.periodic[1] || s.periodic[2])
-                return fail(FDTD_E_INVALID, "tensor media take no periodic axis");
             if (opt.kernel == FDTD_KERNEL_FUSED) return fail(FDTD_E_INVALID, "tensor media need the split kernels");
             if (opt.reversible) return fail(FDTD_E_INVALID, "tensor media take no reversible mode");
         }
@@ -1407,8 +1405,13 @@ struct Handle : Base {
         launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 0, cs);
         for (int q = 0; q < ndom; ++q) {
             if (!dd[q].grad) continue;
-            if (dd[q].tens) launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
-            else if (dd[q].per[0] || dd[q].per[1]) launch_per_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+            const bool per = dd[q].per[0] || dd[q].per[1];
+            if (dd[q].tens) {
+                launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+                if (per) launch_per_adj_h<T>(d_doms, q, dd[q].n, ap, ap ^ 1, st);
+            } else if (per) {
+                launch_per_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+            }
         }
         if (cfg.kernel == 1) launch_adj<T>(cfg, d_doms, ap, ap ^ 1, cur, st, 1, cs);
         return FDTD_OK;

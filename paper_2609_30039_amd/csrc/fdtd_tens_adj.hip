@@ -16,7 +16,10 @@
 //              (the forward curls of the node's six edges from 12 H values
 //              away from the absorbing slabs);
 //   k_adj_et   u through the transposed absorber recursion and the curl into
-//              Hbar.
+//              Hbar (in a Bloch-periodic domain the per-node k_padj_h, whose
+//              gathers cross the seams).
+// On a periodic axis (Section 2.2) the edges past a seam are those at the
+// other end times the real Bloch factor, the node tensors past it repeat.
 // k_tadj_ht marches (i, j) columns of kNodeKz planes (fdtd_node_adj.h);
 // k_tadj_e takes one node per thread, 64 x-nodes by 4 rows per block, one
 // plane per block row of the grid (a z-stride loop beyond the grid's z
@@ -33,10 +36,13 @@ namespace {
 
 constexpr int kTx = 64, kTy = 4, kMaxGridZ = 65535;
 
-// eps^-1 entry q (xx yy zz xy xz yz) at node (i,j,k): the box arrays, the
-// background times the identity outside the box (the high-wall nodes included)
+// eps^-1 entry q (xx yy zz xy xz yz) at node (i,j,k), i <= nx, j <= ny: the
+// box arrays, the background times the identity outside the box (the
+// high-wall nodes included); past a periodic seam the node at the other end
 template <typename T>
 __device__ __forceinline__ T tinv_at(const DomDev<T>& d, int q, int i, int j, int k) {
+    if (i >= d.n[0] && d.per[0]) i -= d.n[0];
+    if (j >= d.n[1] && d.per[1]) j -= d.n[1];
     if (in_box<T>(d.elo, d.ehi, i, j, k)) {
         const long long o =
             ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) * d.exs + (i - d.exa);
@@ -45,26 +51,49 @@ __device__ __forceinline__ T tinv_at(const DomDev<T>& d, int q, int i, int j, in
     return q < 3 ? d.epsinv_bg : T(0);
 }
 
+// (i, j) one step off the grid in x or y (at most): across a periodic seam
+// the node at the other end and the Bloch factor, else false
+template <typename T>
+__device__ __forceinline__ bool seam_wrap(const DomDev<T>& d, int& i, int& j, T& fac) {
+    fac = T(1);
+    if (i < 0 || i >= d.n[0]) {
+        if (!d.per[0]) return false;
+        i += i < 0 ? d.n[0] : -d.n[0];
+        fac = d.bsign[0];
+    }
+    if (j < 0 || j >= d.n[1]) {
+        if (!d.per[1]) return false;
+        j += j < 0 ? d.n[1] : -d.n[1];
+        fac *= d.bsign[1];
+    }
+    return true;
+}
+
 // value of an edge array at the edge starting at (i,j,k); zero off the grid
+// past a wall
 template <typename T>
 __device__ __forceinline__ T edge_at(const DomDev<T>& d, const FDTD_GLOBAL T* F, int i, int j, int k) {
-    if (i < 0 || j < 0 || k < 0 || i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) return T(0);
-    return F[fidx(d, i, j, k)];
+    T fac;
+    if (k < 0 || k >= d.n[2] || !seam_wrap(d, i, j, fac)) return T(0);
+    return fac * F[fidx(d, i, j, k)];
 }
 
 // the forward stretched curl of edge (c, x) from u^n (set fsr), read only;
 // zero on an edge a wall holds
 template <typename T>
 __device__ __forceinline__ T fwd_curl(const DomDev<T>& d, int c, const int x[3], int fsr) {
-    if (x[0] < 0 || x[1] < 0 || x[2] < 0 || e_masked(c, x[0], x[1], x[2])) return T(0);
-    const long long fo = (long long)fsr * d.fs, f = fidx(d, x[0], x[1], x[2]) + fo;
-    const long long st[3] = {1, d.pitch, d.plane};
+    int w[3] = {x[0], x[1], x[2]};
+    T fac;
+    if (w[2] < 0 || !seam_wrap(d, w[0], w[1], fac) || e_masked_d(d, c, w[0], w[1], w[2])) return T(0);
+    const long long fo = (long long)fsr * d.fs, f = fidx(d, w[0], w[1], w[2]);
     const int a0 = (c + 1) % 3, a1 = (c + 2) % 3;
-    const FDTD_GLOBAL T* H0 = gp(d.H[(c + 2) % 3]);   // differenced along a0
-    const FDTD_GLOBAL T* H1 = gp(d.H[(c + 1) % 3]);   // differenced along a1
-    const T h0 = H0[f], h0m = x[a0] > 0 ? H0[f - st[a0]] : T(0);
-    const T h1 = H1[f], h1m = x[a1] > 0 ? H1[f - st[a1]] : T(0);
-    return curl_minus_ro(d, c, x[0], x[1], x[2], h0, h0m, h1, h1m, fsr);
+    const FDTD_GLOBAL T* H0 = gp(d.H[(c + 2) % 3]) + fo;   // differenced along a0
+    const FDTD_GLOBAL T* H1 = gp(d.H[(c + 1) % 3]) + fo;   // differenced along a1
+    int y[3];
+    T fb;
+    const T h0m = back_node(d, a0, w, y, fb) ? fb * H0[fidx(d, y[0], y[1], y[2])] : T(0);
+    const T h1m = back_node(d, a1, w, y, fb) ? fb * H1[fidx(d, y[0], y[1], y[2])] : T(0);
+    return fac * curl_minus_ro(d, c, w[0], w[1], w[2], H0[f], h0m, H1[f], h1m, fsr);
 }
 
 template <typename T>
@@ -133,8 +162,8 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         T mz = h * (a_zz + pz_zz) * z0;
         mz += q4 * (a_xz * sx + pz_xz * (x_zp + x_xmzp));
         mz += q4 * (a_yz * sy + pz_yz * (y_zp + y_ymzp));
-        T u[3] = {e_masked(0, i, j, k) ? T(0) : S * mx, e_masked(1, i, j, k) ? T(0) : S * my,
-                  e_masked(2, i, j, k) ? T(0) : S * mz};
+        T u[3] = {e_masked_d(d, 0, i, j, k) ? T(0) : S * mx, e_masked_d(d, 1, i, j, k) ? T(0) : S * my,
+                  e_masked_d(d, 2, i, j, k) ? T(0) : S * mz};
         gp(d.Et[0])[f] = u[0];
         gp(d.Et[1])[f] = u[1];
         gp(d.Et[2])[f] = u[2];
@@ -142,7 +171,7 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         // E-side memory cotangents (owner): ybar = +u (term 0), -u (term 1)
         if (slab)
             for (int c = 0; c < 3; ++c) {
-                if (e_masked(c, i, j, k)) continue;
+                if (e_masked_d(d, c, i, j, k)) continue;
                 for (int t = 0; t < 2; ++t)
                     (void)stretch_T(d, d.psiEa, rs, ws, true, (c + 1 + t) % 3, t, 0, i, j, k, t == 0 ? u[c] : -u[c]);
             }
@@ -160,7 +189,9 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         U[1][1] = (double)(S * y_ym);
         U[2][0] = (double)(S * z0);
         U[2][1] = (double)(S * z_zm);
-        if (slab) {   // stretched curls: the absorber memories of u^n take part
+        // stretched curls where the absorber memories of u^n take part, and on
+        // a periodic axis's first plane (the back differences cross the seam)
+        if (slab || (d.per[0] && i == 0) || (d.per[1] && j == 0)) {
             for (int b = 0; b < 3; ++b)
                 for (int s = 0; s < 2; ++s) {
                     int w[3] = {i, j, k};

@@ -243,14 +243,19 @@ def test_tensor_admission_node_by_node():
 
 
 def test_tensor_media_combinations_refused():
-    """The tensor path is nondispersive, walled and split, and has no
-    reversible mode; a gradient over its node tensors is admitted."""
+    """The tensor path is nondispersive and split, and has no reversible
+    mode; a gradient over its node tensors is admitted, and so are
+    Bloch-periodic x and y axes (with a gradient too)."""
     m = 2.0 * np.eye(3)
     _refused(_tensor_spec(m, lorentz=[W.LorentzSpec((2, 2, 2), (5, 5, 5), 1.0, 0.3, 0.01)]), B.FDTD_E_INVALID)
-    _refused(_tensor_spec(m, pml=(0, 0, 0, 0, 3, 3), periodic=(1, 0, 0)), B.FDTD_E_INVALID)
     _refused(_tensor_spec(m), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
     _refused(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))), B.FDTD_E_INVALID, reversible=1)
     _passes_validation(_tensor_spec(m, grad_box=((2, 2, 4), (6, 6, 8))))
+    per = dict(pml=(0, 0, 0, 0, 3, 3), periodic=(1, 1, 0), bloch_sign=(-1, 1, 1))
+    _passes_validation(_tensor_spec(m, **per))
+    _passes_validation(_tensor_spec(m, grad_box=((0, 0, 4), (8, 8, 8)), **per))
+    _refused(_tensor_spec(m, pml=(3, 3, 0, 0, 3, 3), periodic=(1, 0, 0)), B.FDTD_E_INVALID)
+    _refused(_tensor_spec(m, **per), B.FDTD_E_INVALID, kernel=B.FDTD_KERNEL_FUSED)
 
 
 def _stream_refused(spec, code, **kw):
