@@ -682,31 +682,46 @@ __device__ __forceinline__ T ta(const TensCol<T>& m, int q, long long off, bool 
                                             : (q < 3 ? m.bg : T(0));
 }
 
-template <typename T>
+// PER: the domain has a periodic axis (neighbour offsets and Bloch factors
+// from the column's table); else the neighbours are the fixed offsets
+template <typename T, bool PER>
 __device__ __forceinline__ void tens_fetch(const TensCol<T>& m, TensPlane<T>& p, const FDTD_GLOBAL T* const (&e)[3],
                                            int k, long long f) {
     const long long o = (long long)k * m.pl;
     const bool up = k + 1 < m.nz;
     p.cz = tc(m, 2, o, true);
-    p.cz_xp = m.fxp * tc(m, 2, o + m.oxp, m.xp);
-    p.cz_yp = m.fyp * tc(m, 2, o + m.oyp, m.yp);
-    p.cy_xp = m.fxp * tc(m, 1, o + m.oxp, m.xp);
-    p.cy_xpym = (m.fxp * m.fym) * tc(m, 1, o + m.oxp + m.oym, m.xp && m.ym);
-    p.cx_yp = m.fyp * tc(m, 0, o + m.oyp, m.yp);
-    p.cx_xmyp = (m.fxm * m.fyp) * tc(m, 0, o + m.oxm + m.oyp, m.xm && m.yp);
+    if constexpr (PER) {
+        p.cz_xp = m.fxp * tc(m, 2, o + m.oxp, m.xp);
+        p.cz_yp = m.fyp * tc(m, 2, o + m.oyp, m.yp);
+        p.cy_xp = m.fxp * tc(m, 1, o + m.oxp, m.xp);
+        p.cy_xpym = (m.fxp * m.fym) * tc(m, 1, o + m.oxp + m.oym, m.xp && m.ym);
+        p.cx_yp = m.fyp * tc(m, 0, o + m.oyp, m.yp);
+        p.cx_xmyp = (m.fxm * m.fyp) * tc(m, 0, o + m.oxm + m.oyp, m.xm && m.yp);
+        p.cx_xmzp = m.fxm * tc(m, 0, o + m.pl + m.oxm, up && m.xm);
+        p.cy_ymzp = m.fym * tc(m, 1, o + m.pl + m.oym, up && m.ym);
+    } else {
+        const long long P = m.pitch;
+        p.cz_xp = tc(m, 2, o + 1, m.xp);
+        p.cz_yp = tc(m, 2, o + P, m.yp);
+        p.cy_xp = tc(m, 1, o + 1, m.xp);
+        p.cy_xpym = tc(m, 1, o + 1 - P, m.xp && m.ym);
+        p.cx_yp = tc(m, 0, o + P, m.yp);
+        p.cx_xmyp = tc(m, 0, o - 1 + P, m.xm && m.yp);
+        p.cx_xmzp = tc(m, 0, o + m.pl - 1, up && m.xm);
+        p.cy_ymzp = tc(m, 1, o + m.pl - P, up && m.ym);
+    }
     p.cx_zp = tc(m, 0, o + m.pl, up);
-    p.cx_xmzp = m.fxm * tc(m, 0, o + m.pl + m.oxm, up && m.xm);
     p.cy_zp = tc(m, 1, o + m.pl, up);
-    p.cy_ymzp = m.fym * tc(m, 1, o + m.pl + m.oym, up && m.ym);
+    const long long qx = PER ? m.qxp : 1, qy = PER ? m.qyp : (long long)m.bx;
     p.a_xx = ta(m, 0, 0, m.bxy, k);
     p.a_yy = ta(m, 1, 0, m.bxy, k);
     p.a_xy = ta(m, 3, 0, m.bxy, k);
-    p.axp_xx = ta(m, 0, m.qxp, m.bxpy, k);
-    p.axp_xy = ta(m, 3, m.qxp, m.bxpy, k);
-    p.axp_xz = ta(m, 4, m.qxp, m.bxpy, k);
-    p.ayp_yy = ta(m, 1, m.qyp, m.bxyp, k);
-    p.ayp_xy = ta(m, 3, m.qyp, m.bxyp, k);
-    p.ayp_yz = ta(m, 5, m.qyp, m.bxyp, k);
+    p.axp_xx = ta(m, 0, qx, m.bxpy, k);
+    p.axp_xy = ta(m, 3, qx, m.bxpy, k);
+    p.axp_xz = ta(m, 4, qx, m.bxpy, k);
+    p.ayp_yy = ta(m, 1, qy, m.bxyp, k);
+    p.ayp_xy = ta(m, 3, qy, m.bxyp, k);
+    p.ayp_yz = ta(m, 5, qy, m.bxyp, k);
     p.azp_zz = ta(m, 2, 0, m.bxy, k + 1);
     p.azp_xz = ta(m, 4, 0, m.bxy, k + 1);
     p.azp_yz = ta(m, 5, 0, m.bxy, k + 1);
@@ -726,14 +741,15 @@ __device__ __forceinline__ void tens_fetch(const TensCol<T>& m, TensPlane<T>& p,
 // nodes, so it runs in place like the other split kernels.  Along z the
 // column keeps what plane k+1 shares with plane k (the Cz below, the Cx and
 // Cy above, the node above) in registers, and fetches plane k+1's other
-// operands before it computes and stores plane k.
-template <typename T, int W>
+// operands before it computes and stores plane k.  PER = true serves the
+// tensor domains with a periodic axis, false the others.
+template <typename T, int W, bool PER>
 __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ doms, const int* __restrict__ bs,
                                                 const int* __restrict__ xr, int ndom, int kz, int rs, int ws, int t,
                                                 const int* __restrict__ tdev) {
     const DomDev<T>* dp;
     Col c = column<T, W>(doms, bs, ndom, kz, dp, xr);
-    if (!c.ok || !dp->tens) return;
+    if (!c.ok || !dp->tens || (dp->per[0] || dp->per[1]) != PER) return;
     if (tdev) t += *tdev;
     const DomDev<T>& d = *dp;
     const int i = c.i, j = c.j;
@@ -783,16 +799,25 @@ __global__ void __launch_bounds__(256) k_tens_e(const DomDev<T>* __restrict__ do
     m.bg = d.epsinv_bg;
     // carried into plane k0: Cz below it, Cx and Cy on it, the z-related node entries
     const long long o0 = (long long)k0 * m.pl;
-    T czm = tc(m, 2, o0 - m.pl, k0 > 0), czm_xp = m.fxp * tc(m, 2, o0 - m.pl + m.oxp, k0 > 0 && m.xp),
-      czm_yp = m.fyp * tc(m, 2, o0 - m.pl + m.oyp, k0 > 0 && m.yp);
-    T cx = tc(m, 0, o0, true), cx_xm = m.fxm * tc(m, 0, o0 + m.oxm, m.xm);
-    T cy = tc(m, 1, o0, true), cy_ym = m.fym * tc(m, 1, o0 + m.oym, m.ym);
+    T czm = tc(m, 2, o0 - m.pl, k0 > 0), cx = tc(m, 0, o0, true), cy = tc(m, 1, o0, true);
+    T czm_xp, czm_yp, cx_xm, cy_ym;
+    if constexpr (PER) {
+        czm_xp = m.fxp * tc(m, 2, o0 - m.pl + m.oxp, k0 > 0 && m.xp);
+        czm_yp = m.fyp * tc(m, 2, o0 - m.pl + m.oyp, k0 > 0 && m.yp);
+        cx_xm = m.fxm * tc(m, 0, o0 + m.oxm, m.xm);
+        cy_ym = m.fym * tc(m, 1, o0 + m.oym, m.ym);
+    } else {
+        czm_xp = tc(m, 2, o0 - m.pl + 1, k0 > 0 && m.xp);
+        czm_yp = tc(m, 2, o0 - m.pl + m.pitch, k0 > 0 && m.yp);
+        cx_xm = tc(m, 0, o0 - 1, m.xm);
+        cy_ym = tc(m, 1, o0 - m.pitch, m.ym);
+    }
     T a_zz = ta(m, 2, 0, m.bxy, k0), a_xz = ta(m, 4, 0, m.bxy, k0), a_yz = ta(m, 5, 0, m.bxy, k0);
     long long f = fidx(d, i, j, k0);
     TensPlane<T> cu, nx;
-    tens_fetch(m, cu, e, k0, f);
+    tens_fetch<T, PER>(m, cu, e, k0, f);
     for (int k = k0; k < c.k1; ++k, f += d.plane) {
-        if (k + 1 < c.k1) tens_fetch(m, nx, e, k + 1, f + d.plane);
+        if (k + 1 < c.k1) tens_fetch<T, PER>(m, nx, e, k + 1, f + d.plane);
         const T sx = cx + cx_xm, sy = cy + cy_ym, sz = cu.cz + czm;   // the two edges of each axis at v0
         T mx = h * (cu.a_xx + cu.axp_xx) * cx;
         mx += q4 * (cu.a_xy * sy + cu.axp_xy * (cu.cy_xp + cu.cy_xpym));
@@ -2755,13 +2780,21 @@ void launch_fwd(const LaunchCfg& c, const void* doms, int rs, int ws, int t, hip
             if (c.sw == 32) {
                 hipLaunchKernelGGL((k_fwd_e<T, 32, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, 0,
                                    c.ndom, c.kz, rs, ws, t, tdev, 0);
-                hipLaunchKernelGGL((k_tens_e<T, 32>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
-                                   rs, ws, t, tdev);
+                if (c.ntens > c.ntper)
+                    hipLaunchKernelGGL((k_tens_e<T, 32, false>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
+                                       c.ndom, c.kz, rs, ws, t, tdev);
+                if (c.ntper)
+                    hipLaunchKernelGGL((k_tens_e<T, 32, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
+                                       c.ndom, c.kz, rs, ws, t, tdev);
             } else {
                 hipLaunchKernelGGL((k_fwd_e<T, 64, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.lbs, 0,
                                    c.ndom, c.kz, rs, ws, t, tdev, 0);
-                hipLaunchKernelGGL((k_tens_e<T, 64>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr, c.ndom, c.kz,
-                                   rs, ws, t, tdev);
+                if (c.ntens > c.ntper)
+                    hipLaunchKernelGGL((k_tens_e<T, 64, false>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
+                                       c.ndom, c.kz, rs, ws, t, tdev);
+                if (c.ntper)
+                    hipLaunchKernelGGL((k_tens_e<T, 64, true>), dim3(c.ngrid), dim3(256), 0, s, dd, c.bs, c.xr,
+                                       c.ndom, c.kz, rs, ws, t, tdev);
             }
         }
         if (sk) {   // interior blocks: one pass (reads set rs only, so it may run after the E pass)

@@ -40,6 +40,7 @@ struct LaunchCfg {
     const int* lbs;            // blocks over each domain's Lorentz box (prefix sums)
     int nlor;
     int ntens;                 // split: domains with tensor media (two E passes)
+    int ntper;                 // split: those of them with a periodic axis
     int onepass;               // split family with the single-pass kernel on interior blocks (ping-pong sets)
     // split adjoint: one tile table per pass, (domain | class << 24,
     // x0 | xlen << 24, y0, k0), domains with a gradient only.  x is cut into
@@ -78,9 +79,9 @@ void launch_adj(const LaunchCfg& c, const void* doms, int rs, int ws, int fsr, h
 // the H-update transpose into the new Ebar, then u = S M Ebar into the
 // scratch Et, the E-side memory cotangents and the node-tensor gradient;
 // launch_adj's H-node pass completes the step (launch_per_adj_h in a
-// periodic domain)
+// periodic domain: per)
 template <typename T>
-void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s);
+void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, bool per, hipStream_t s);
 // the whole adjoint step of Bloch-periodic domain dom (both passes, the seam
 // in their neighbour gathers)
 template <typename T>

@@ -376,8 +376,11 @@ struct Handle : Base {
         }
         cfg.nblk = bs_host[ndom];
         cfg.nlor = lbs[ndom];
-        cfg.ntens = 0;
-        for (int q = 0; q < ndom; ++q) cfg.ntens += dd[q].tens;
+        cfg.ntens = cfg.ntper = 0;
+        for (int q = 0; q < ndom; ++q) {
+            cfg.ntens += dd[q].tens;
+            cfg.ntper += dd[q].tens && (dd[q].per[0] || dd[q].per[1]);
+        }
         if (cfg.kernel == 1) split_runs();
         build_adjoint_tiles();
         cfg.ngen = (int)tiles_gen.size();
@@ -1407,7 +1410,7 @@ struct Handle : Base {
             if (!dd[q].grad) continue;
             const bool per = dd[q].per[0] || dd[q].per[1];
             if (dd[q].tens) {
-                launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);
+                launch_tens_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, per, st);
                 if (per) launch_per_adj_h<T>(d_doms, q, dd[q].n, ap, ap ^ 1, st);
             } else if (per) {
                 launch_per_adj<T>(d_doms, q, dd[q].n, ap, ap ^ 1, cur, st);

@@ -38,11 +38,14 @@ constexpr int kTx = 64, kTy = 4, kMaxGridZ = 65535;
 
 // eps^-1 entry q (xx yy zz xy xz yz) at node (i,j,k), i <= nx, j <= ny: the
 // box arrays, the background times the identity outside the box (the
-// high-wall nodes included); past a periodic seam the node at the other end
-template <typename T>
+// high-wall nodes included); past a periodic seam (PER: the domain has a
+// periodic axis) the node at the other end
+template <typename T, bool PER>
 __device__ __forceinline__ T tinv_at(const DomDev<T>& d, int q, int i, int j, int k) {
-    if (i >= d.n[0] && d.per[0]) i -= d.n[0];
-    if (j >= d.n[1] && d.per[1]) j -= d.n[1];
+    if constexpr (PER) {
+        if (i >= d.n[0] && d.per[0]) i -= d.n[0];
+        if (j >= d.n[1] && d.per[1]) j -= d.n[1];
+    }
     if (in_box<T>(d.elo, d.ehi, i, j, k)) {
         const long long o =
             ((long long)(k - d.elo[2]) * (d.ehi[1] - d.elo[1]) + (j - d.elo[1])) * d.exs + (i - d.exa);
@@ -71,17 +74,39 @@ __device__ __forceinline__ bool seam_wrap(const DomDev<T>& d, int& i, int& j, T&
 
 // value of an edge array at the edge starting at (i,j,k); zero off the grid
 // past a wall
-template <typename T>
+template <typename T, bool PER>
 __device__ __forceinline__ T edge_at(const DomDev<T>& d, const FDTD_GLOBAL T* F, int i, int j, int k) {
-    T fac;
-    if (k < 0 || k >= d.n[2] || !seam_wrap(d, i, j, fac)) return T(0);
-    return fac * F[fidx(d, i, j, k)];
+    if constexpr (PER) {
+        T fac;
+        if (k < 0 || k >= d.n[2] || !seam_wrap(d, i, j, fac)) return T(0);
+        return fac * F[fidx(d, i, j, k)];
+    } else {
+        if (i < 0 || j < 0 || k < 0 || i >= d.n[0] || j >= d.n[1] || k >= d.n[2]) return T(0);
+        return F[fidx(d, i, j, k)];
+    }
+}
+
+template <bool PER, typename T>
+__device__ __forceinline__ bool emask(const DomDev<T>& d, int c, int i, int j, int k) {
+    if constexpr (PER) return e_masked_d(d, c, i, j, k);
+    else return e_masked(c, i, j, k);
 }
 
 // the forward stretched curl of edge (c, x) from u^n (set fsr), read only;
 // zero on an edge a wall holds
-template <typename T>
+template <typename T, bool PER>
 __device__ __forceinline__ T fwd_curl(const DomDev<T>& d, int c, const int x[3], int fsr) {
+    if constexpr (!PER) {
+        if (x[0] < 0 || x[1] < 0 || x[2] < 0 || e_masked(c, x[0], x[1], x[2])) return T(0);
+        const long long fo = (long long)fsr * d.fs, f = fidx(d, x[0], x[1], x[2]) + fo;
+        const long long st[3] = {1, d.pitch, d.plane};
+        const int a0 = (c + 1) % 3, a1 = (c + 2) % 3;
+        const FDTD_GLOBAL T* H0 = gp(d.H[(c + 2) % 3]);   // differenced along a0
+        const FDTD_GLOBAL T* H1 = gp(d.H[(c + 1) % 3]);   // differenced along a1
+        const T h0 = H0[f], h0m = x[a0] > 0 ? H0[f - st[a0]] : T(0);
+        const T h1 = H1[f], h1m = x[a1] > 0 ? H1[f - st[a1]] : T(0);
+        return curl_minus_ro(d, c, x[0], x[1], x[2], h0, h0m, h1, h1m, fsr);
+    }
     int w[3] = {x[0], x[1], x[2]};
     T fac;
     if (w[2] < 0 || !seam_wrap(d, w[0], w[1], fac) || e_masked_d(d, c, w[0], w[1], w[2])) return T(0);
@@ -120,7 +145,7 @@ __device__ __forceinline__ T back_val(const DomDev<T>& d, const FDTD_GLOBAL T* F
     return (i < 0 || j < 0 || k < 0) ? T(0) : F[fidx(d, i, j, k)];
 }
 
-template <typename T>
+template <typename T, bool PER>
 __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp, int rs, int ws, int fsr) {
     const DomDev<T>& d = *dp;
     const int i = blockIdx.x * kTx + threadIdx.x % kTx, j = blockIdx.y * kTy + threadIdx.x / kTx;
@@ -134,24 +159,25 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         const long long f = fidx(d, i, j, k);
         // Ebar on the edges the three assembled edges of node v = (i,j,k) meet
         // (suffixes: offsets from v; zero off the grid)
-        const T x0 = ex[f], x_xm = edge_at(d, ex, i - 1, j, k), x_yp = edge_at(d, ex, i, j + 1, k),
-                x_xmyp = edge_at(d, ex, i - 1, j + 1, k), x_zp = edge_at(d, ex, i, j, k + 1),
-                x_xmzp = edge_at(d, ex, i - 1, j, k + 1);
-        const T y0 = ey[f], y_ym = edge_at(d, ey, i, j - 1, k), y_xp = edge_at(d, ey, i + 1, j, k),
-                y_xpym = edge_at(d, ey, i + 1, j - 1, k), y_zp = edge_at(d, ey, i, j, k + 1),
-                y_ymzp = edge_at(d, ey, i, j - 1, k + 1);
-        const T z0 = ez[f], z_zm = edge_at(d, ez, i, j, k - 1), z_xp = edge_at(d, ez, i + 1, j, k),
-                z_xpzm = edge_at(d, ez, i + 1, j, k - 1), z_yp = edge_at(d, ez, i, j + 1, k),
-                z_ypzm = edge_at(d, ez, i, j + 1, k - 1);
+        const T x0 = ex[f], x_xm = edge_at<T, PER>(d, ex, i - 1, j, k), x_yp = edge_at<T, PER>(d, ex, i, j + 1, k),
+                x_xmyp = edge_at<T, PER>(d, ex, i - 1, j + 1, k), x_zp = edge_at<T, PER>(d, ex, i, j, k + 1),
+                x_xmzp = edge_at<T, PER>(d, ex, i - 1, j, k + 1);
+        const T y0 = ey[f], y_ym = edge_at<T, PER>(d, ey, i, j - 1, k), y_xp = edge_at<T, PER>(d, ey, i + 1, j, k),
+                y_xpym = edge_at<T, PER>(d, ey, i + 1, j - 1, k), y_zp = edge_at<T, PER>(d, ey, i, j, k + 1),
+                y_ymzp = edge_at<T, PER>(d, ey, i, j - 1, k + 1);
+        const T z0 = ez[f], z_zm = edge_at<T, PER>(d, ez, i, j, k - 1), z_xp = edge_at<T, PER>(d, ez, i + 1, j, k),
+                z_xpzm = edge_at<T, PER>(d, ez, i + 1, j, k - 1), z_yp = edge_at<T, PER>(d, ez, i, j + 1, k),
+                z_ypzm = edge_at<T, PER>(d, ez, i, j + 1, k - 1);
         // node tensors: v (all six), v+x (xx xy xz), v+y (yy xy yz), v+z (zz xz yz)
-        const T a_xx = tinv_at(d, 0, i, j, k), a_yy = tinv_at(d, 1, i, j, k), a_zz = tinv_at(d, 2, i, j, k),
-                a_xy = tinv_at(d, 3, i, j, k), a_xz = tinv_at(d, 4, i, j, k), a_yz = tinv_at(d, 5, i, j, k);
-        const T px_xx = tinv_at(d, 0, i + 1, j, k), px_xy = tinv_at(d, 3, i + 1, j, k),
-                px_xz = tinv_at(d, 4, i + 1, j, k);
-        const T py_yy = tinv_at(d, 1, i, j + 1, k), py_xy = tinv_at(d, 3, i, j + 1, k),
-                py_yz = tinv_at(d, 5, i, j + 1, k);
-        const T pz_zz = tinv_at(d, 2, i, j, k + 1), pz_xz = tinv_at(d, 4, i, j, k + 1),
-                pz_yz = tinv_at(d, 5, i, j, k + 1);
+        const T a_xx = tinv_at<T, PER>(d, 0, i, j, k), a_yy = tinv_at<T, PER>(d, 1, i, j, k),
+                a_zz = tinv_at<T, PER>(d, 2, i, j, k), a_xy = tinv_at<T, PER>(d, 3, i, j, k),
+                a_xz = tinv_at<T, PER>(d, 4, i, j, k), a_yz = tinv_at<T, PER>(d, 5, i, j, k);
+        const T px_xx = tinv_at<T, PER>(d, 0, i + 1, j, k), px_xy = tinv_at<T, PER>(d, 3, i + 1, j, k),
+                px_xz = tinv_at<T, PER>(d, 4, i + 1, j, k);
+        const T py_yy = tinv_at<T, PER>(d, 1, i, j + 1, k), py_xy = tinv_at<T, PER>(d, 3, i, j + 1, k),
+                py_yz = tinv_at<T, PER>(d, 5, i, j + 1, k);
+        const T pz_zz = tinv_at<T, PER>(d, 2, i, j, k + 1), pz_xz = tinv_at<T, PER>(d, 4, i, j, k + 1),
+                pz_yz = tinv_at<T, PER>(d, 5, i, j, k + 1);
         const T sx = x0 + x_xm, sy = y0 + y_ym, sz = z0 + z_zm;   // the two edges of each axis at v
         T mx = h * (a_xx + px_xx) * x0;
         mx += q4 * (a_xy * sy + px_xy * (y_xp + y_xpym));
@@ -162,8 +188,8 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         T mz = h * (a_zz + pz_zz) * z0;
         mz += q4 * (a_xz * sx + pz_xz * (x_zp + x_xmzp));
         mz += q4 * (a_yz * sy + pz_yz * (y_zp + y_ymzp));
-        T u[3] = {e_masked_d(d, 0, i, j, k) ? T(0) : S * mx, e_masked_d(d, 1, i, j, k) ? T(0) : S * my,
-                  e_masked_d(d, 2, i, j, k) ? T(0) : S * mz};
+        T u[3] = {emask<PER>(d, 0, i, j, k) ? T(0) : S * mx, emask<PER>(d, 1, i, j, k) ? T(0) : S * my,
+                  emask<PER>(d, 2, i, j, k) ? T(0) : S * mz};
         gp(d.Et[0])[f] = u[0];
         gp(d.Et[1])[f] = u[1];
         gp(d.Et[2])[f] = u[2];
@@ -171,7 +197,7 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         // E-side memory cotangents (owner): ybar = +u (term 0), -u (term 1)
         if (slab)
             for (int c = 0; c < 3; ++c) {
-                if (e_masked_d(d, c, i, j, k)) continue;
+                if (emask<PER>(d, c, i, j, k)) continue;
                 for (int t = 0; t < 2; ++t)
                     (void)stretch_T(d, d.psiEa, rs, ws, true, (c + 1 + t) % 3, t, 0, i, j, k, t == 0 ? u[c] : -u[c]);
             }
@@ -191,12 +217,12 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
         U[2][1] = (double)(S * z_zm);
         // stretched curls where the absorber memories of u^n take part, and on
         // a periodic axis's first plane (the back differences cross the seam)
-        if (slab || (d.per[0] && i == 0) || (d.per[1] && j == 0)) {
+        if (slab || (PER && ((d.per[0] && i == 0) || (d.per[1] && j == 0)))) {
             for (int b = 0; b < 3; ++b)
                 for (int s = 0; s < 2; ++s) {
                     int w[3] = {i, j, k};
                     w[b] -= s;
-                    Y[b][s] = (double)fwd_curl(d, b, w, fsr);
+                    Y[b][s] = (double)fwd_curl<T, PER>(d, b, w, fsr);
                 }
         } else {      // plain backward-difference curls of the forward H
             const long long fo = (long long)fsr * d.fs;
@@ -246,15 +272,16 @@ __global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp
 }  // namespace
 
 template <typename T>
-void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, hipStream_t s) {
+void launch_tens_adj(const void* doms, int dom, const int n[3], int rs, int ws, int fsr, bool per, hipStream_t s) {
     const DomDev<T>* dp = (const DomDev<T>*)doms + dom;
     const dim3 gcol((n[0] + kNodeTx - 1) / kNodeTx, (n[1] + kNodeTy - 1) / kNodeTy, (n[2] + kNodeKz - 1) / kNodeKz);
     const dim3 gplane((n[0] + kTx - 1) / kTx, (n[1] + kTy - 1) / kTy, std::min(n[2], kMaxGridZ));
     hipLaunchKernelGGL(k_tadj_ht<T>, gcol, dim3(256), 0, s, dp, rs, ws);
-    hipLaunchKernelGGL(k_tadj_e<T>, gplane, dim3(256), 0, s, dp, rs, ws, fsr);
+    if (per) hipLaunchKernelGGL((k_tadj_e<T, true>), gplane, dim3(256), 0, s, dp, rs, ws, fsr);
+    else hipLaunchKernelGGL((k_tadj_e<T, false>), gplane, dim3(256), 0, s, dp, rs, ws, fsr);
 }
 
-template void launch_tens_adj<float>(const void*, int, const int*, int, int, int, hipStream_t);
-template void launch_tens_adj<double>(const void*, int, const int*, int, int, int, hipStream_t);
+template void launch_tens_adj<float>(const void*, int, const int*, int, int, int, bool, hipStream_t);
+template void launch_tens_adj<double>(const void*, int, const int*, int, int, int, bool, hipStream_t);
 
 }  // namespace fdtd
