@@ -37,11 +37,14 @@ __global__ void __launch_bounds__(256) k_padj_e(const DomDev<T>* __restrict__ dp
     const long long wo = (long long)ws * d.as, fo = (long long)fsr * d.fs;
     const T S = d.S;
     HtGather<T> hg(d, i, j, k0, rs, ws);
+    HtPlane<T> cu = hg.fetch(fidx(d, i, j, k0)), nx;
     for (int k = k0; k < k1; ++k) {
         const long long f = fidx(d, i, j, k);
         const int x[3] = {i, j, k};
+        if (k + 1 < k1) nx = hg.fetch(f + d.plane);   // plane k+1's loads ahead of plane k's stores
         T et[3], u[3], epre[3];
-        hg.plane(k, f, et);
+        hg.gather(k, cu, et);
+        cu = nx;
         for (int e = 0; e < 3; ++e) {
             const AdjE<T> r = et_node_d(d, e, i, j, k, et[e], rs, ws);
             epre[e] = r.epre;
@@ -83,6 +86,33 @@ __device__ __forceinline__ T e_dbar(const DomDev<T>& d, int c, int t, int i, int
     return stretch_T(d, d.psiEa, rs, ws, false, (c + 1 + t) % 3, t, 0, i, j, k, t == 0 ? uc : -uc);
 }
 
+// Operands of one plane of k_padj_h: u (the scratch Et) at the node and at its
+// forward neighbours along y and x, Hbar (set rs) at the node
+template <typename T>
+struct HnPlane {
+    T ux, uy, uz;
+    T uz_yp, ux_yp;     // u_z, u_x at the forward node along y
+    T uz_xp, uy_xp;     // u_z, u_y at the forward node along x
+    T hbx, hby, hbz;
+};
+
+template <typename T>
+__device__ __forceinline__ HnPlane<T> hn_fetch(const FDTD_GLOBAL T* const (&u)[3], const DomDev<T>& d, long long f,
+                                               long long ro, bool okx, long long oxp, bool oky, long long oyp) {
+    HnPlane<T> p;
+    p.ux = u[0][f];
+    p.uy = u[1][f];
+    p.uz = u[2][f];
+    p.uz_yp = oky ? u[2][f + oyp] : T(0);
+    p.ux_yp = oky ? u[0][f + oyp] : T(0);
+    p.uz_xp = okx ? u[2][f + oxp] : T(0);
+    p.uy_xp = okx ? u[1][f + oxp] : T(0);
+    p.hbx = gp(d.Ha[0])[f + ro];
+    p.hby = gp(d.Ha[1])[f + ro];
+    p.hbz = gp(d.Ha[2])[f + ro];
+    return p;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_padj_h(const DomDev<T>* __restrict__ dp, int rs, int ws) {
     const DomDev<T>& d = *dp;
@@ -92,45 +122,52 @@ __global__ void __launch_bounds__(256) k_padj_h(const DomDev<T>* __restrict__ dp
     const long long ro = (long long)rs * d.as, wo = (long long)ws * d.as, pl = d.plane;
     const FDTD_GLOBAL T* u[3] = {gp(d.Et[0]), gp(d.Et[1]), gp(d.Et[2])};
     const T S = d.S;
-    // Dbar of E_c's term t at the forward node along a (x, y: across a seam), zero past a wall
-    auto fwd_term = [&](int c, int t, int a, int k) -> T {
-        const int x[3] = {i, j, k};
-        int y[3];
-        T fac;
-        if (!fwd_node(d, a, x, y, fac)) return T(0);
-        return fac * e_dbar(d, c, t, y[0], y[1], y[2], u[c][fidx(d, y[0], y[1], y[2])], rs, ws);
-    };
+    // the forward nodes along x and y (across a seam; none past a wall), fixed per column
+    const int x0[3] = {i, j, 0};
+    int nxn[3], nyn[3];
+    T fxp, fyp;
+    const bool okx = fwd_node(d, 0, x0, nxn, fxp), oky = fwd_node(d, 1, x0, nyn, fyp);
+    const long long oxp = nxn[0] - i, oyp = (long long)(nyn[1] - j) * d.pitch;
     long long f = fidx(d, i, j, k0);
-    T ux = u[0][f], uy = u[1][f], uz = u[2][f];
+    HnPlane<T> cu = hn_fetch(u, d, f, ro, okx, oxp, oky, oyp);
     // own z-terms of the current plane: (Ex, 1) and (Ey, 0), both along z
-    T ex1 = e_dbar(d, 0, 1, i, j, k0, ux, rs, ws), ey0 = e_dbar(d, 1, 0, i, j, k0, uy, rs, ws);
+    T ex1 = e_dbar(d, 0, 1, i, j, k0, cu.ux, rs, ws), ey0 = e_dbar(d, 1, 0, i, j, k0, cu.uy, rs, ws);
     for (int k = k0; k < k1; ++k, f += pl) {
         const bool up = k + 1 < d.n[2];
-        const T uxu = up ? u[0][f + pl] : T(0), uyu = up ? u[1][f + pl] : T(0), uzu = up ? u[2][f + pl] : T(0);
-        const T ex1u = up ? e_dbar(d, 0, 1, i, j, k + 1, uxu, rs, ws) : T(0);
-        const T ey0u = up ? e_dbar(d, 1, 0, i, j, k + 1, uyu, rs, ws) : T(0);
-        const T ex0 = e_dbar(d, 0, 0, i, j, k, ux, rs, ws), ey1 = e_dbar(d, 1, 1, i, j, k, uy, rs, ws);
-        const T ez0 = e_dbar(d, 2, 0, i, j, k, uz, rs, ws), ez1 = e_dbar(d, 2, 1, i, j, k, uz, rs, ws);
+        // plane k+1's loads ahead of plane k's stores (past the chunk, only the z neighbours)
+        HnPlane<T> nx;
+        if (k + 1 < k1) {
+            nx = hn_fetch(u, d, f + pl, ro, okx, oxp, oky, oyp);
+        } else {
+            nx.ux = up ? u[0][f + pl] : T(0);
+            nx.uy = up ? u[1][f + pl] : T(0);
+        }
+        const T ex1u = up ? e_dbar(d, 0, 1, i, j, k + 1, nx.ux, rs, ws) : T(0);
+        const T ey0u = up ? e_dbar(d, 1, 0, i, j, k + 1, nx.uy, rs, ws) : T(0);
+        const T ex0 = e_dbar(d, 0, 0, i, j, k, cu.ux, rs, ws), ey1 = e_dbar(d, 1, 1, i, j, k, cu.uy, rs, ws);
+        const T ez0 = e_dbar(d, 2, 0, i, j, k, cu.uz, rs, ws), ez1 = e_dbar(d, 2, 1, i, j, k, cu.uz, rs, ws);
+        // Dbar of E_c's term t at the forward node along x or y, zero past a wall
+        const T fz1 = oky ? fyp * e_dbar(d, 2, 1, nyn[0], nyn[1], k, cu.uz_yp, rs, ws) : T(0);
+        const T fx0 = oky ? fyp * e_dbar(d, 0, 0, nyn[0], nyn[1], k, cu.ux_yp, rs, ws) : T(0);
+        const T fz0 = okx ? fxp * e_dbar(d, 2, 0, nxn[0], nxn[1], k, cu.uz_xp, rs, ws) : T(0);
+        const T fy1 = okx ? fxp * e_dbar(d, 1, 1, nxn[0], nxn[1], k, cu.uy_xp, rs, ws) : T(0);
         // H_h(x) collects Dbar(x) - Dbar(forward node) from the terms it enters:
         // Hx: (Ey,0) along z, (Ez,1) along y; Hy: (Ez,0) along x, (Ex,1) along z;
         // Hz: (Ex,0) along y, (Ey,1) along x
-        const T hbx = gp(d.Ha[0])[f + ro], hby = gp(d.Ha[1])[f + ro], hbz = gp(d.Ha[2])[f + ro];
-        gp(d.Ha[0])[f + wo] = hbx + (ey0 - ey0u) + (ez1 - fwd_term(2, 1, 1, k));
-        gp(d.Ha[1])[f + wo] = hby + (ez0 - fwd_term(2, 0, 0, k)) + (ex1 - ex1u);
-        gp(d.Ha[2])[f + wo] = hbz + (ex0 - fwd_term(0, 0, 1, k)) + (ey1 - fwd_term(1, 1, 0, k));
+        gp(d.Ha[0])[f + wo] = cu.hbx + (ey0 - ey0u) + (ez1 - fz1);
+        gp(d.Ha[1])[f + wo] = cu.hby + (ez0 - fz0) + (ex1 - ex1u);
+        gp(d.Ha[2])[f + wo] = cu.hbz + (ex0 - fx0) + (ey1 - fy1);
         // H-side memory cotangents (owner): ybar = -S sign Hbar
         if (slab_side(d, 0, i) >= 0 || slab_side(d, 1, j) >= 0 || slab_side(d, 2, k) >= 0) {
-            const T hb[3] = {hbx, hby, hbz};
+            const T hb[3] = {cu.hbx, cu.hby, cu.hbz};
             for (int c = 0; c < 3; ++c)
                 for (int t = 0; t < 2; ++t)
                     (void)stretch_T(d, d.psiHa, rs, ws, true, (c + 1 + t) % 3, t, 3, i, j, k,
                                     -S * (t == 0 ? T(1) : T(-1)) * hb[c]);
         }
-        ux = uxu;
-        uy = uyu;
-        uz = uzu;
         ex1 = ex1u;
         ey0 = ey0u;
+        cu = nx;
     }
 }
 

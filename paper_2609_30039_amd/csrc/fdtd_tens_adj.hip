@@ -129,13 +129,16 @@ __global__ void __launch_bounds__(256) k_tadj_ht(const DomDev<T>* __restrict__ d
     if (i >= d.n[0] || j >= d.n[1]) return;
     const long long wo = (long long)ws * d.as;
     HtGather<T> hg(d, i, j, k0, rs, ws);
-    for (int k = k0; k < k1; ++k) {
-        const long long f = fidx(d, i, j, k);
+    long long f = fidx(d, i, j, k0);
+    HtPlane<T> cu = hg.fetch(f), nx;
+    for (int k = k0; k < k1; ++k, f += d.plane) {
+        if (k + 1 < k1) nx = hg.fetch(f + d.plane);   // plane k+1's loads ahead of plane k's stores
         T et[3];
-        hg.plane(k, f, et);
+        hg.gather(k, cu, et);
         gp(d.Ea[0])[f + wo] = et[0];
         gp(d.Ea[1])[f + wo] = et[1];
         gp(d.Ea[2])[f + wo] = et[2];
+        cu = nx;
     }
 }
 
