@@ -148,8 +148,13 @@ __device__ __forceinline__ T back_val(const DomDev<T>& d, const FDTD_GLOBAL T* F
     return (i < 0 || j < 0 || k < 0) ? T(0) : F[fidx(d, i, j, k)];
 }
 
+// k_tadj_e's wave target per SIMD.  FP32 at 5 (95 VGPRs, no spills; left
+// alone the compiler takes 103 and 4 waves): 5.67 against 6.58 ms at 536^3;
+// at 6 (80 VGPRs, 12 spills) 6.24 ms.  FP64 keeps 4 (125 VGPRs; 5 spills).
+template <typename T> constexpr int kTadjWaves = sizeof(T) == 8 ? 4 : 5;
+
 template <typename T, bool PER>
-__global__ void __launch_bounds__(256) k_tadj_e(const DomDev<T>* __restrict__ dp, int rs, int ws, int fsr) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kTadjWaves<T>, 8))) k_tadj_e(const DomDev<T>* __restrict__ dp, int rs, int ws, int fsr) {
     const DomDev<T>& d = *dp;
     const int i = blockIdx.x * kTx + threadIdx.x % kTx, j = blockIdx.y * kTy + threadIdx.x / kTx;
     if (i >= d.n[0] || j >= d.n[1]) return;
