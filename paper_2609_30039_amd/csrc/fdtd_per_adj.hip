@@ -28,8 +28,15 @@
 namespace fdtd {
 namespace {
 
+// k_padj_e's wave target per SIMD: FP32 at 8 (62 VGPRs, no spills; the
+// compiler alone takes 68 and 7 waves), 2.04 against 2.34 ms on the 512 x 512 x
+// 536 Bloch cell.  FP64 keeps its 5.  (One wave more cost k_tadj_ht and
+// k_tens_e their spills: 1.63 -> 2.43 and 2.08 -> 3.06 ms.)
+template <typename T> constexpr int kPadjEWaves = sizeof(T) == 8 ? 5 : 8;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_padj_e(const DomDev<T>* __restrict__ dp, int rs, int ws, int fsr) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPadjEWaves<T>, 8)))
+k_padj_e(const DomDev<T>* __restrict__ dp, int rs, int ws, int fsr) {
     const DomDev<T>& d = *dp;
     const int i = blockIdx.x * kNodeTx + threadIdx.x % kNodeTx, j = blockIdx.y * kNodeTy + threadIdx.x / kNodeTx;
     const int k0 = blockIdx.z * kNodeKz, k1 = min(k0 + kNodeKz, d.n[2]);
