@@ -150,7 +150,8 @@ __device__ __forceinline__ T back_val(const DomDev<T>& d, const FDTD_GLOBAL T* F
 
 // k_tadj_e's wave target per SIMD.  FP32 at 5 (95 VGPRs, no spills; left
 // alone the compiler takes 103 and 4 waves): 5.67 against 6.58 ms at 536^3;
-// at 6 (80 VGPRs, 12 spills) 6.24 ms.  FP64 keeps 4 (125 VGPRs; 5 spills).
+// at 6 (80 VGPRs, 12 spills) 6.24 ms.  FP64 keeps 4 (125 VGPRs; at 5 waves
+// it would spill 28).
 template <typename T> constexpr int kTadjWaves = sizeof(T) == 8 ? 4 : 5;
 
 template <typename T, bool PER>
